@@ -1,0 +1,17 @@
+"""Seeded synthetic inputs for the hyper-reduced RVE evaluation.
+
+This package draws random numbers and arranges them into arrays. It holds none
+of the method's arithmetic (no kinematics, no material law, no reduction), so
+both the FP64 oracle and the GPU path can consume its arrays without sharing
+any code of the method.
+"""
+from .generators import (  # noqa: F401
+    THETA_REF,
+    Cluster,
+    make_cluster,
+    make_macro_points,
+    make_increments,
+    zipf_counts,
+    perturbed_theta,
+    WORKLOADS,
+)

@@ -1,0 +1,140 @@
+"""Seeded generators for the synthetic RVE clusters and macro load states.
+
+Shapes and distributions follow the synthetic workloads of the hyper-reduced
+RVE evaluation (monolithic hyper ROM FE2, Sec. 3.2-3.3 of the paper): an RVE
+cluster is described by its ECM points (weights ``w``), the mode gradients
+``G`` of its ROM modes at those points and a phase label per point; every
+macro Gauss point carries a macro deformation gradient ``Fbar``.
+
+Readings of the workload text (all documented in the design doc):
+
+* ``N(0, 0.05)`` means standard deviation 0.05.
+* Draw order per cluster: weights, then mode gradients, then phases, all from
+  one ``numpy.random.default_rng(seed)`` (PCG64).
+* The weighted mean of each mode gradient is subtracted with the normalised
+  weights, so ``sum_q w_q G_qm = 0`` holds to rounding (zero-mean fluctuation
+  gradients, the periodic-fluctuation property of Sec. 2).
+* Macro loads ``Fbar = R (I + H)`` with ``H`` symmetric; draws are taken in
+  blocks: all six upper-triangle entries of every point, then every rotation
+  axis (normalised standard-normal 3-vector), then every angle.
+* Monolithic-iteration increments ``dFbar = R dH`` with symmetric ``dH`` keep
+  the polar split exact (``Ubar`` moves from ``I + H`` to ``I + H + dH``).
+
+Arrays use the natural numpy shapes: ``G[Q, 9, m]`` (3x3 tensors flattened
+row-major, index ``3 i + j``), ``Fbar[N, 3, 3]``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+# (mu_matrix, lambda_matrix, mu_inclusion, lambda_inclusion)
+THETA_REF = np.array([1.0, 1.5, 10.0, 15.0], dtype=np.float64)
+
+
+@dataclass
+class Cluster:
+    """One RVE cluster: ECM weights, mode gradients and phase labels."""
+
+    m: int
+    Q: int
+    G: np.ndarray      # [Q, 9, m] float64
+    w: np.ndarray      # [Q] float64, sums to 1 (the RVE measure V0)
+    phase: np.ndarray  # [Q] int32, 0 = matrix, 1 = inclusion
+    seed: int
+
+
+def make_cluster(m: int, Q: int, seed: int, g_std: float = 0.05,
+                 p_incl: float = 0.3) -> Cluster:
+    """Draw one RVE cluster (weights, mode gradients, phase map)."""
+    if m < 1 or Q < 1:
+        raise ValueError("m and Q must be positive")
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.5, 1.5, size=Q)
+    w = w / w.sum()
+    G = rng.normal(0.0, g_std, size=(Q, 9, m))
+    # remove the weighted mean of every (component, mode) over the ECM points
+    mean = np.tensordot(w, G, axes=(0, 0))          # [9, m]
+    G = G - mean[None, :, :]
+    phase = (rng.random(Q) < p_incl).astype(np.int32)
+    return Cluster(m=m, Q=Q, G=np.ascontiguousarray(G), w=w, phase=phase, seed=seed)
+
+
+def _rotations(rng: np.random.Generator, n: int, max_angle: float) -> np.ndarray:
+    axis = rng.standard_normal((n, 3))
+    axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+    ang = rng.uniform(-max_angle, max_angle, size=n)
+    K = np.zeros((n, 3, 3))
+    K[:, 0, 1], K[:, 0, 2] = -axis[:, 2], axis[:, 1]
+    K[:, 1, 0], K[:, 1, 2] = axis[:, 2], -axis[:, 0]
+    K[:, 2, 0], K[:, 2, 1] = -axis[:, 1], axis[:, 0]
+    s = np.sin(ang)[:, None, None]
+    c = np.cos(ang)[:, None, None]
+    return np.eye(3)[None] + s * K + (1.0 - c) * (K @ K)
+
+
+def _sym_from_upper(u6: np.ndarray) -> np.ndarray:
+    n = u6.shape[0]
+    H = np.zeros((n, 3, 3))
+    iu = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    for k, (i, j) in enumerate(iu):
+        H[:, i, j] = u6[:, k]
+        H[:, j, i] = u6[:, k]
+    return H
+
+
+def make_macro_points(N: int, seed: int, amp: float = 0.05,
+                      max_angle: float = 0.3):
+    """Draw ``N`` macro deformation gradients ``Fbar = R (I + H)``.
+
+    Returns ``(Fbar, R, H)``, each ``[N, 3, 3]``.
+    """
+    rng = np.random.default_rng(seed)
+    H = _sym_from_upper(rng.uniform(-amp, amp, size=(N, 6)))
+    R = _rotations(rng, N, max_angle)
+    Fbar = R @ (np.eye(3)[None] + H)
+    return np.ascontiguousarray(Fbar), R, H
+
+
+def make_increments(R: np.ndarray, n_iter: int, seed: int,
+                    amp: float = 0.005) -> np.ndarray:
+    """Monolithic-iteration increments ``dFbar_k = R dH_k``: ``[n_iter, N, 3, 3]``."""
+    rng = np.random.default_rng(seed)
+    N = R.shape[0]
+    out = np.empty((n_iter, N, 3, 3))
+    for k in range(n_iter):
+        dH = _sym_from_upper(rng.uniform(-amp, amp, size=(N, 6)))
+        out[k] = R @ dH
+    return out
+
+
+def zipf_counts(total: int, n: int, s: float) -> list[int]:
+    """Deterministic largest-remainder split of ``total`` in proportion k^-s."""
+    p = np.array([(k + 1) ** (-s) for k in range(n)])
+    p /= p.sum()
+    raw = p * total
+    base = np.floor(raw).astype(np.int64)
+    rem = total - int(base.sum())
+    order = np.argsort(-(raw - base), kind="stable")
+    base[order[:rem]] += 1
+    return [int(x) for x in base]
+
+
+def perturbed_theta(seed: int, rel: float = 0.1):
+    """Target parameters ``theta* = theta (1 + rel s)`` with seeded signs ``s``."""
+    rng = np.random.default_rng(seed)
+    s = np.where(rng.random(4) < 0.5, -1.0, 1.0)
+    return THETA_REF * (1.0 + rel * s), s
+
+
+# The five synthetic workloads: sizes, ROM mode count m and ECM point count Q.
+WORKLOADS = {
+    "fp64_small": dict(N=256, m=8, Q=32, amp=0.05, seed=1000),
+    "fp64_scale": dict(N=65536, m=32, Q=256, amp=0.05, seed=2000, iters=5,
+                       inc_amp=0.005),
+    "batched": dict(N=262144, ms=[8, 16, 24, 32, 48, 64, 80, 96], q_per_m=6,
+                    zipf_s=1.1, amp=0.05, seed=3000, iters=10, inc_amp=0.005),
+    "mixed": dict(N=131072, m=64, Q=512, amps=[0.01, 0.05, 0.2], seed=4000),
+    "adjoint": dict(N=65536, m=48, Q=384, amp=0.05, seed=5000, rel=0.1),
+}

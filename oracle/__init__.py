@@ -1,0 +1,201 @@
+"""FP64 CPU oracle of the hyper-reduced RVE evaluation (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product path
+(the HIP library and its binding) never imports, links or calls it.
+
+The arithmetic lives in ``hrom_oracle.c`` (plain C loops in double precision,
+one macro point at a time); this module only marshals numpy arrays into it.
+Every array is a row-major numpy array in its natural shape:
+``G[Q, 9, m]``, ``Fbar[N, 3, 3]`` (or ``[N, 9]``), ``a[N, m]``.
+
+Parity status of every function is documented in the design doc; every function
+here is pinned by a test in ``tests/test_oracle_pins.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hrom_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+PT_JNONPOS, PT_NOT_SPD, PT_NOCONV, PT_NONFINITE = 1, 2, 4, 8
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE double, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        i64, i32, d = C.c_int64, C.c_int, C.c_double
+        L.orc_neo_hooke.argtypes = [i64, P, d, d, P, P]
+        L.orc_neo_hooke_energy.argtypes = [i64, P, d, d, P]
+        L.orc_polar.argtypes = [i64, P, P, P, P, P]
+        L.orc_eval.argtypes = [i32, i32, P, P, P, P, i64, P, P, P, P, P, P, P, P]
+        L.orc_point_eval.argtypes = [i32, i32, P, P, P, P, i32, i64, P, P, P, P, P, P, P,
+                                     P, P, P]
+        L.orc_newton.argtypes = [i32, i32, P, P, P, P, i32, i64, P, P, d, i32, P, P, P, P, P]
+        L.orc_monolithic.argtypes = [i32, i32, P, P, P, P, i32, i64, P, P, i32, P, P, P, P, P]
+        L.orc_backward.argtypes = [i32, i32, P, P, P, P, i32, i64, P, P, P, P, P, P, P]
+        L.orc_stretch_increment.argtypes = [i64, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _f64(x, shape=None):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if shape is not None:
+        x = x.reshape(shape)
+    return x
+
+
+def _p(x):
+    return None if x is None else x.ctypes.data_as(C.c_void_p)
+
+
+def _cluster_args(cl, theta):
+    G = _f64(cl.G)
+    w = _f64(cl.w)
+    ph = np.ascontiguousarray(cl.phase, dtype=np.int32)
+    th = _f64(theta, (4,))
+    return (G, w, ph, th)
+
+
+def neo_hooke(F, mu, lam):
+    """Neo-Hooke first Piola stress P[N,9] and tangent A[N,9,9] = dP/dF."""
+    F = _f64(F)
+    N = F.size // 9
+    F = F.reshape(N, 9)
+    P = np.zeros((N, 9))
+    A = np.zeros((N, 9, 9))
+    bad = lib().orc_neo_hooke(N, _p(F), mu, lam, _p(P), _p(A))
+    if bad:
+        raise ValueError("det F <= 0 at %d points" % bad)
+    return P, A
+
+
+def neo_hooke_energy(F, mu, lam):
+    F = _f64(F)
+    N = F.size // 9
+    W = np.zeros(N)
+    lib().orc_neo_hooke_energy(N, _p(F.reshape(N, 9)), mu, lam, _p(W))
+    return W
+
+
+def polar(F):
+    """Polar split F = R U: returns (U, R, V, u) with U = V diag(u) V^T."""
+    F = _f64(F)
+    N = F.size // 9
+    U, R, V = (np.zeros((N, 3, 3)) for _ in range(3))
+    u = np.zeros((N, 3))
+    lib().orc_polar(N, _p(F.reshape(N, 9)), _p(U), _p(R), _p(V), _p(u))
+    return U, R, V, u
+
+
+def stretch_increment(F, dF):
+    F = _f64(F)
+    N = F.size // 9
+    dF = _f64(dF, (N, 9))
+    dU = np.zeros((N, 3, 3))
+    lib().orc_stretch_increment(N, _p(F.reshape(N, 9)), _p(dF), _p(dU))
+    return dU
+
+
+def eval_blocks(cl, theta, Fr, a):
+    """Raw RVE-frame blocks at given (Fr, a): dict of r, Pr, Kaa, KaF, KFF, status."""
+    G, w, ph, th = _cluster_args(cl, theta)
+    Fr = _f64(Fr)
+    N = Fr.size // 9
+    a = _f64(a, (N, cl.m))
+    m = cl.m
+    out = dict(r=np.zeros((N, m)), Pr=np.zeros((N, 9)), Kaa=np.zeros((N, m, m)),
+               KaF=np.zeros((N, m, 9)), KFF=np.zeros((N, 9, 9)),
+               status=np.zeros(N, dtype=np.int32))
+    lib().orc_eval(m, cl.Q, _p(G), _p(w), _p(ph), _p(th), N, _p(Fr.reshape(N, 9)), _p(a),
+                   _p(out["r"]), _p(out["Pr"]), _p(out["Kaa"]), _p(out["KaF"]),
+                   _p(out["KFF"]), _p(out["status"]))
+    return out
+
+
+def point_eval(cl, theta, Fbar, a, objective=True):
+    """One evaluate + condense (+ push-out) at given (Fbar, a)."""
+    G, w, ph, th = _cluster_args(cl, theta)
+    Fbar = _f64(Fbar)
+    N = Fbar.size // 9
+    a = _f64(a, (N, cl.m))
+    m = cl.m
+    o = dict(Pbar=np.zeros((N, 9)), Cbar=np.zeros((N, 9, 9)), rnorm=np.zeros(N),
+             y=np.zeros((N, m)), X=np.zeros((N, m, 9)), Palg_r=np.zeros((N, 9)),
+             Cr=np.zeros((N, 9, 9)), status=np.zeros(N, dtype=np.int32))
+    lib().orc_point_eval(m, cl.Q, _p(G), _p(w), _p(ph), _p(th), int(objective), N,
+                         _p(Fbar.reshape(N, 9)), _p(a), _p(o["Pbar"]), _p(o["Cbar"]),
+                         _p(o["rnorm"]), _p(o["y"]), _p(o["X"]), _p(o["Palg_r"]), _p(o["Cr"]),
+                         _p(o["status"]))
+    return o
+
+
+def newton(cl, theta, Fbar, a0=None, tol=1e-10, max_it=25, objective=True):
+    """Micro Newton to ||r||_2 < tol; returns dict with a, Pbar, Cbar, rnorm, iters, status."""
+    G, w, ph, th = _cluster_args(cl, theta)
+    Fbar = _f64(Fbar)
+    N = Fbar.size // 9
+    a = np.zeros((N, cl.m)) if a0 is None else _f64(a0, (N, cl.m)).copy()
+    o = dict(a=a, Pbar=np.zeros((N, 9)), Cbar=np.zeros((N, 9, 9)), rnorm=np.zeros(N),
+             iters=np.zeros(N, dtype=np.int32), status=np.zeros(N, dtype=np.int32))
+    lib().orc_newton(cl.m, cl.Q, _p(G), _p(w), _p(ph), _p(th), int(objective), N,
+                     _p(Fbar.reshape(N, 9)), _p(a), float(tol), int(max_it), _p(o["Pbar"]),
+                     _p(o["Cbar"]), _p(o["rnorm"]), _p(o["iters"]), _p(o["status"]))
+    return o
+
+
+def monolithic(cl, theta, Fbar0, dFbar, a0=None, objective=True):
+    """K monolithic iterations; dFbar[K, N, 3, 3].  Outputs Pbar[K,N,9], Cbar[K,N,9,9]."""
+    G, w, ph, th = _cluster_args(cl, theta)
+    Fbar0 = _f64(Fbar0)
+    N = Fbar0.size // 9
+    dF = _f64(dFbar)
+    K = dF.shape[0]
+    dF = dF.reshape(K, N, 9)
+    a = np.zeros((N, cl.m)) if a0 is None else _f64(a0, (N, cl.m)).copy()
+    o = dict(a=a, Pbar=np.zeros((K, N, 9)), Cbar=np.zeros((K, N, 9, 9)),
+             rnorm=np.zeros((K, N)), status=np.zeros(N, dtype=np.int32))
+    lib().orc_monolithic(cl.m, cl.Q, _p(G), _p(w), _p(ph), _p(th), int(objective), N,
+                         _p(Fbar0.reshape(N, 9)), _p(dF), K, _p(a), _p(o["Pbar"]),
+                         _p(o["Cbar"]), _p(o["rnorm"]), _p(o["status"]))
+    return o
+
+
+def backward(cl, theta, Fbar, a, g, objective=True):
+    """Adjoint gradients at a converged state: (dL/dFbar[N,9], dL/dtheta[4], per-point[N,4])."""
+    G, w, ph, th = _cluster_args(cl, theta)
+    Fbar = _f64(Fbar)
+    N = Fbar.size // 9
+    a = _f64(a, (N, cl.m))
+    g = _f64(g, (N, 9))
+    gF = np.zeros((N, 9))
+    gpt = np.zeros((N, 4))
+    gth = np.zeros(4)
+    st = np.zeros(N, dtype=np.int32)
+    lib().orc_backward(cl.m, cl.Q, _p(G), _p(w), _p(ph), _p(th), int(objective), N,
+                       _p(Fbar.reshape(N, 9)), _p(a), _p(g), _p(gF), _p(gpt), _p(gth), _p(st))
+    return dict(gF=gF, gtheta=gth, gtheta_pt=gpt, status=st)
