@@ -1,0 +1,152 @@
+/*
+ * hrom.h -- C ABI of the MI355X (gfx950) hyper-reduced RVE evaluation.
+ *
+ * The library evaluates the hyper-reduced RVE of the monolithic hyper ROM FE2
+ * method (Lange, Huetter, Kiefer, arXiv 2306.02687) at every macroscopic
+ * Gauss point ("macro point"), on one GPU.  At each ECM point q of the RVE
+ * cluster it forms the reduced kinematics F_q = Fr + sum_m a_m G_qm
+ * (Sec. 3.2.1, eq. ROM_assumption), evaluates the compressible Neo-Hooke
+ * stress P_q and tangent A_q, and accumulates with the ECM weights
+ * (Sec. 3.3):
+ *   r   = sum_q w_q G_q^T P_q           (eq. ROMintforce)
+ *   Kaa = sum_q G_q^T (w_q A_q) G_q     (eq. ROMstiffness)
+ *   KaF = sum_q w_q G_q^T A_q,  KFF = sum_q w_q A_q,  Pr = sum_q w_q P_q.
+ * It then condenses the ROM amplitudes statically (Sec. 3.2.3):
+ *   Palg = Pr - KaF^T Kaa^{-1} r,   Cr = KFF - KaF^T Kaa^{-1} KaF
+ * (eq. Biot_Tangent), applies the monolithic update
+ *   a <- a - Kaa^{-1} (r + KaF dFr)
+ * and differentiates the converged map by an adjoint solve.
+ *
+ * Frames.  With HROM_OBJECTIVE the RVE sees only the right stretch Ubar of
+ * the polar split Fbar = Rbar Ubar (Sec. 3.2.2, eq. ploar_decomp), so Fr =
+ * Ubar; the returned macro stress is Pbar = Fbar S with Ubar S + S Ubar =
+ * 2 sym(Palg) (the second-Piola form of eqs. workconjugacy / biotstress) and
+ * Cbar = dPbar/dFbar.  Without the flag Fr = Fbar and Pbar = Palg, Cbar = Cr.
+ *
+ * Conventions.
+ *  - 3x3 tensors are flattened row-major, I = 3 i + j; tangents are
+ *    C[I][J] = dP_I / dF_J.
+ *  - Per-point arrays are component-major ("SoA"): X[k * N + b] is component
+ *    k of macro point b, so consecutive points are contiguous.
+ *  - Mode-indexed per-point arrays (a, r, and the optional Kaa, KaF outputs)
+ *    hold one block per cluster, in cluster order; cluster c's block starts
+ *    at offset hrom_plan_offset(plan, c, kind) and is [k][count_c].
+ *  - All array arguments are DEVICE pointers owned by the caller, except the
+ *    cluster descriptor array of hrom_plan_create (host memory).
+ *  - Every compute call only enqueues work on `stream` (no host sync, no
+ *    allocation after plan creation).  Per-point results and status are
+ *    valid after the stream is synchronised.
+ *
+ * Return codes: HROM_OK, or a negative HROM_E_* (nothing was enqueued).
+ * Per-point failures do not fail the call; they set bits in status[N].
+ */
+#ifndef HROM_H
+#define HROM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HROM_OK 0
+#define HROM_E_INVALID (-1)   /* invalid argument (null pointer, bad size) */
+#define HROM_E_HIP (-2)       /* a HIP runtime call failed */
+#define HROM_E_ORDER (-3)     /* call sequence violated, e.g. condense before eval */
+#define HROM_E_NOMEM (-4)     /* device allocation failed at plan creation */
+#define HROM_E_UNSUPPORTED (-5) /* size outside the supported range (m > 96, ...) */
+
+/* per-point status bits */
+#define HROM_PT_JNONPOS 1    /* det F <= 0 at an ECM point (or det Fbar <= 0) */
+#define HROM_PT_NOT_SPD 2    /* Cholesky of Kaa hit a non-positive pivot; LU used */
+#define HROM_PT_NOCONV 4     /* Newton did not reach the tolerance */
+#define HROM_PT_NONFINITE 8  /* non-finite input or output, or singular Kaa */
+
+/* arithmetic of the evaluation (Sec. 3.2 blocks) */
+#define HROM_FP64 0          /* everything in double precision (FP64 MFMA) */
+#define HROM_MIXED_BF16 1    /* Kaa, KaF, KFF contraction on BF16 MFMA, FP32 accumulation */
+#define HROM_MIXED_FP16 2    /* same with FP16 MFMA */
+
+/* plan flags */
+#define HROM_OBJECTIVE 1u    /* RVE sees Ubar of Fbar = Rbar Ubar (Sec. 3.2.2) */
+#define HROM_SPLIT 2u        /* mixed modes: hi/lo split operands (3 MFMA terms) */
+
+/* offset kinds for hrom_plan_offset */
+#define HROM_OFF_A 0         /* a, r, y: [m_c][count_c] */
+#define HROM_OFF_KAA 1       /* Kaa output: [m_c * m_c][count_c] */
+#define HROM_OFF_KAF 2       /* KaF output: [m_c * 9][count_c] */
+
+/* One RVE cluster (Sec. 3.3, hyper integration points and weights; the
+ * element ROM modes of Sec. 4 enter as mode gradients at the ECM points). */
+typedef struct {
+    int32_t m;              /* ROM modes, 1 <= m <= 96 */
+    int32_t Q;              /* ECM points, Q >= 1 */
+    const double* G;        /* device [Q][9][m]: gradient of mode m at point q */
+    const double* w;        /* device [Q]: ECM weights (sum = RVE measure V0 = 1) */
+    const int32_t* phase;   /* device [Q]: 0 = matrix, 1 = inclusion */
+    int64_t first;          /* macro points [first, first + count) use this cluster */
+    int64_t count;
+} hrom_cluster;
+
+typedef struct hrom_plan_s* hrom_plan;
+
+/* Create a plan for N macro points partitioned into ncl clusters (contiguous,
+ * in order, covering [0, N)).  Reads G, w, phase once (synchronously) to build
+ * the device layouts the kernels use; allocates the per-point workspace.
+ * Ownership: the plan owns its workspace; the caller keeps G, w, phase. */
+int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, int64_t N,
+                     int32_t precision, uint32_t flags);
+int hrom_plan_destroy(hrom_plan plan);
+
+/* offset (in elements) of cluster c's block in mode-indexed arrays, and the
+ * total length of such an array (c = ncl) */
+int64_t hrom_plan_offset(hrom_plan plan, int32_t c, int32_t kind);
+
+/* Evaluate at (Fbar, a): theta = device [4] (mu_0, lam_0, mu_1, lam_1).
+ * Fbar [9][N], a (mode-indexed).  Writes status[N] (overwrites).  Optional
+ * test outputs (NULL = not written), all in the RVE frame: r (mode-indexed),
+ * Pr [9][N], Kaa [m*m][count] blocks, KaF [m*9][count] blocks, KFF [81][N]. */
+int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const double* a,
+              double* r, double* Pr, double* Kaa, double* KaF, double* KFF,
+              int32_t* status, hipStream_t stream);
+
+/* Condense the state left by the last hrom_eval: Pbar [9][N] (algorithmic
+ * stress, macro frame), Cbar [81][N], rnorm [N] = ||r||_2.  ORs status bits. */
+int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm,
+                  int32_t* status, hipStream_t stream);
+
+/* Monolithic update a <- a - (y + X dFr) with the y, X of the last condense
+ * (Sec. 3.2.3).  dFbar [9][N] macro-frame increment (linearised to the stretch
+ * increment in objective mode), or NULL for a pure micro Newton step; with
+ * dFbar == NULL, points whose last rnorm < tol are left unchanged (frozen).
+ * Points whose status (of the last eval/condense) has JNONPOS or NONFINITE
+ * are never changed.  After an update, the next call must be hrom_eval. */
+int hrom_update(hrom_plan plan, const double* dFbar, double tol, double* a,
+                const int32_t* status, hipStream_t stream);
+
+/* Micro Newton at fixed Fbar, max_it evaluations with no host sync (so it can
+ * be captured in a HIP graph): max_it - 1 times {eval, condense, update with
+ * converged points frozen}, then a final eval + condense.  Points still at
+ * rnorm >= tol get HROM_PT_NOCONV.  Pbar, Cbar, rnorm as in hrom_condense. */
+int hrom_newton(hrom_plan plan, const double* theta, const double* Fbar, double* a, double tol,
+                int32_t max_it, double* Pbar, double* Cbar, double* rnorm, int32_t* status,
+                hipStream_t stream);
+
+/* Adjoint backward of the converged map (Fbar, theta) -> Pbar at the state of
+ * the last eval + condense (which must have been at this a and theta, i.e.
+ * no update in between).  gPbar [9][N] = dL/dPbar.  Pull-back to the RVE
+ * frame g_r, adjoint solve lambda = Kaa^{-T} KaF g_r with the stored solve
+ * (mixed modes: plus one refinement step with the accurate operator),
+ * re-evaluation of F_q and A_q at every ECM point (nothing of size Q is
+ * stored), then dL/dFbar [9][N] and dL/dtheta [4] (sum over all points in a
+ * fixed order: bitwise reproducible). */
+int hrom_backward(hrom_plan plan, const double* theta, const double* a, const double* gPbar,
+                  double* gFbar, double* gtheta, int32_t* status, hipStream_t stream);
+
+const char* hrom_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HROM_H */

@@ -1,0 +1,186 @@
+"""Thin ctypes binding of ``libhrom.so`` (the C ABI declared in include/hrom.h).
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels of the library.  Tensors are torch CUDA tensors (device memory and
+streams are torch's), in the layouts of the C ABI: per-point arrays are
+component-major ``[k, N]`` float64, mode-indexed arrays are 1-D with one
+``[m_c, count_c]`` block per cluster.
+
+The library must have been built (``python -m paper_2306_02687_amd.build``);
+loading raises if it is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhrom.so")
+
+HROM_OK = 0
+PT_JNONPOS, PT_NOT_SPD, PT_NOCONV, PT_NONFINITE = 1, 2, 4, 8
+FP64, MIXED_BF16, MIXED_FP16 = 0, 1, 2
+OBJECTIVE, SPLIT = 1, 2
+OFF_A, OFF_KAA, OFF_KAF = 0, 1, 2
+
+EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_eval",
+            "hrom_condense", "hrom_update", "hrom_newton", "hrom_backward", "hrom_strerror")
+
+
+class HromError(RuntimeError):
+    pass
+
+
+class _Cluster(C.Structure):
+    _fields_ = [("m", C.c_int32), ("Q", C.c_int32), ("G", C.c_void_p), ("w", C.c_void_p),
+                ("phase", C.c_void_p), ("first", C.c_int64), ("count", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhrom.so and declare the C signatures (raises if not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise HromError(f"{path} not found: build it with `python -m paper_2306_02687_amd.build`")
+    L = C.CDLL(path)
+    P, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.hrom_plan_create.argtypes = [C.POINTER(P), C.POINTER(_Cluster), i32, i64, i32, C.c_uint32]
+    L.hrom_plan_create.restype = C.c_int
+    L.hrom_plan_destroy.argtypes = [P]
+    L.hrom_plan_offset.argtypes = [P, i32, i32]
+    L.hrom_plan_offset.restype = i64
+    L.hrom_eval.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+    L.hrom_condense.argtypes = [P, P, P, P, P, P]
+    L.hrom_update.argtypes = [P, P, d, P, P, P]
+    L.hrom_newton.argtypes = [P, P, P, P, d, i32, P, P, P, P, P]
+    L.hrom_backward.argtypes = [P, P, P, P, P, P, P, P]
+    L.hrom_strerror.argtypes = [C.c_int]
+    L.hrom_strerror.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != HROM_OK:
+        raise HromError(f"{what}: {load().hrom_strerror(rc).decode()} ({rc})")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise HromError("expected a contiguous CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class ClusterSpec:
+    """One RVE cluster on the device: G [Q,9,m], w [Q] float64, phase [Q] int32."""
+    G: torch.Tensor
+    w: torch.Tensor
+    phase: torch.Tensor
+    count: int
+
+    @property
+    def m(self):
+        return int(self.G.shape[2])
+
+    @property
+    def Q(self):
+        return int(self.G.shape[0])
+
+
+class Plan:
+    """A plan for N macro points partitioned into RVE clusters (in order)."""
+
+    def __init__(self, clusters, precision: int = FP64, objective: bool = True,
+                 split: bool = False):
+        L = load()
+        self.clusters = list(clusters)
+        self.N = sum(c.count for c in self.clusters)
+        arr = (_Cluster * len(self.clusters))()
+        first = 0
+        for i, c in enumerate(self.clusters):
+            for t, dt in ((c.G, torch.float64), (c.w, torch.float64), (c.phase, torch.int32)):
+                if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                    raise HromError("cluster arrays must be contiguous CUDA tensors "
+                                    "(G, w float64; phase int32)")
+            arr[i] = _Cluster(c.m, c.Q, c.G.data_ptr(), c.w.data_ptr(), c.phase.data_ptr(),
+                              first, c.count)
+            first += c.count
+        flags = (OBJECTIVE if objective else 0) | (SPLIT if split else 0)
+        h = C.c_void_p()
+        torch.cuda.synchronize()
+        _check(L.hrom_plan_create(C.byref(h), arr, len(self.clusters), self.N, precision, flags),
+               "hrom_plan_create")
+        self._h = h
+        self.precision = precision
+        self.objective = objective
+        self.split = split
+        self.a_len = int(L.hrom_plan_offset(h, len(self.clusters), OFF_A))
+        self.off_a = [int(L.hrom_plan_offset(h, i, OFF_A)) for i in range(len(self.clusters))]
+        self.off_kaa = [int(L.hrom_plan_offset(h, i, OFF_KAA)) for i in range(len(self.clusters))]
+        self.off_kaf = [int(L.hrom_plan_offset(h, i, OFF_KAF)) for i in range(len(self.clusters))]
+        self.kaa_len = int(L.hrom_plan_offset(h, len(self.clusters), OFF_KAA))
+        self.kaf_len = int(L.hrom_plan_offset(h, len(self.clusters), OFF_KAF))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().hrom_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ allocation helpers
+    def _dev(self):
+        return self.clusters[0].G.device
+
+    def zeros_points(self, k):
+        return torch.zeros((k, self.N), dtype=torch.float64, device=self._dev())
+
+    def zeros_modes(self):
+        return torch.zeros(self.a_len, dtype=torch.float64, device=self._dev())
+
+    def status(self):
+        return torch.zeros(self.N, dtype=torch.int32, device=self._dev())
+
+    # ------------------------------------------------------------ entry points
+    def eval(self, theta, Fbar, a, status, r=None, Pr=None, Kaa=None, KaF=None, KFF=None,
+             stream=None):
+        _check(load().hrom_eval(self._h, _ptr(theta), _ptr(Fbar), _ptr(a), _ptr(r), _ptr(Pr),
+                                _ptr(Kaa), _ptr(KaF), _ptr(KFF), _ptr(status), _stream(stream)),
+               "hrom_eval")
+
+    def condense(self, Pbar, Cbar, rnorm, status, stream=None):
+        _check(load().hrom_condense(self._h, _ptr(Pbar), _ptr(Cbar), _ptr(rnorm), _ptr(status),
+                                    _stream(stream)), "hrom_condense")
+
+    def update(self, dFbar, a, status, tol=0.0, stream=None):
+        _check(load().hrom_update(self._h, _ptr(dFbar), float(tol), _ptr(a), _ptr(status),
+                                  _stream(stream)), "hrom_update")
+
+    def newton(self, theta, Fbar, a, Pbar, Cbar, rnorm, status, tol=1e-10, max_it=6,
+               stream=None):
+        _check(load().hrom_newton(self._h, _ptr(theta), _ptr(Fbar), _ptr(a), float(tol),
+                                  int(max_it), _ptr(Pbar), _ptr(Cbar), _ptr(rnorm), _ptr(status),
+                                  _stream(stream)), "hrom_newton")
+
+    def backward(self, theta, a, gPbar, gFbar, gtheta, status, stream=None):
+        _check(load().hrom_backward(self._h, _ptr(theta), _ptr(a), _ptr(gPbar), _ptr(gFbar),
+                                    _ptr(gtheta), _ptr(status), _stream(stream)), "hrom_backward")

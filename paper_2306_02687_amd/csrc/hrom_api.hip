@@ -1,0 +1,363 @@
+// C ABI of the hyper-reduced RVE library: plan creation (device layouts and
+// workspace), and the evaluate / condense / update / backward entry points,
+// which only enqueue kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+
+#include "hrom_internal.h"
+
+using namespace hrom;
+
+struct hrom_plan_s {
+    Plan p;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(T** ptr, int64_t n) {
+    *ptr = nullptr;
+    if (n <= 0) n = 1;
+    if (hipMalloc((void**)ptr, sizeof(T) * (size_t)n) != hipSuccess) {
+        *ptr = nullptr;
+        return HROM_E_NOMEM;
+    }
+    return HROM_OK;
+}
+
+template <typename T>
+void dfree(T*& ptr) {
+    if (ptr) (void)hipFree((void*)ptr);
+    ptr = nullptr;
+}
+
+void free_plan(Plan& p) {
+    for (auto& c : p.cl) {
+        dfree(c.Ghat);
+        dfree(c.GT);
+        dfree(c.w);
+        dfree(c.phase);
+        dfree(c.Fhi);
+        dfree(c.Flo);
+    }
+    dfree(p.Fr); dfree(p.polar); dfree(p.Pr); dfree(p.r); dfree(p.Khat); dfree(p.L);
+    dfree(p.piv); dfree(p.y); dfree(p.X); dfree(p.Palg); dfree(p.Cr); dfree(p.S);
+    dfree(p.rnorm); dfree(p.dU); dfree(p.gr); dfree(p.Lam); dfree(p.lam); dfree(p.rho);
+    dfree(p.hr); dfree(p.gth);
+}
+
+int hip_status() { return hipGetLastError() == hipSuccess ? HROM_OK : HROM_E_HIP; }
+
+bool mixed(const Plan& p) { return p.prec != HROM_FP64; }
+
+// power-of-two scaling of w_q A_q for the low-precision operands (w ~ 1/Q)
+float wscale_for(int Q) { return std::ldexp(1.0f, (int)std::ceil(std::log2((double)Q))); }
+
+}  // namespace
+
+extern "C" {
+
+const char* hrom_strerror(int code) {
+    switch (code) {
+        case HROM_OK: return "ok";
+        case HROM_E_INVALID: return "invalid argument";
+        case HROM_E_HIP: return "HIP runtime error";
+        case HROM_E_ORDER: return "call order violated (evaluate before condense, condense before update/backward)";
+        case HROM_E_NOMEM: return "device allocation failed";
+        case HROM_E_UNSUPPORTED: return "size outside the supported range";
+        default: return "unknown error";
+    }
+}
+
+int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, int64_t N,
+                     int32_t precision, uint32_t flags) {
+    if (!out || !clusters || ncl < 1 || N < 1) return HROM_E_INVALID;
+    *out = nullptr;
+    if (precision != HROM_FP64 && precision != HROM_MIXED_BF16 && precision != HROM_MIXED_FP16)
+        return HROM_E_INVALID;
+    int64_t next = 0;
+    for (int c = 0; c < ncl; c++) {
+        const hrom_cluster& k = clusters[c];
+        if (!k.G || !k.w || !k.phase || k.Q < 1 || k.count < 1 || k.first != next) return HROM_E_INVALID;
+        if (k.m < 1 || k.m > kMaxModes) return HROM_E_UNSUPPORTED;
+        next += k.count;
+    }
+    if (next != N) return HROM_E_INVALID;
+    hrom_plan_s* h = new (std::nothrow) hrom_plan_s;
+    if (!h) return HROM_E_NOMEM;
+    Plan& p = h->p;
+    p.ncl = ncl;
+    p.N = N;
+    p.prec = precision;
+    p.flags = flags;
+    (void)hipGetDevice(&p.device);
+    int64_t off_a = 0, off_kaa = 0, off_kaf = 0, ws_k = 0, ws_L = 0;
+    int rc = HROM_OK;
+    for (int c = 0; c < ncl && rc == HROM_OK; c++) {
+        const hrom_cluster& k = clusters[c];
+        ClusterDev d{};
+        d.m = k.m;
+        d.Q = k.Q;
+        d.Qpad = (k.Q + 63) / 64 * 64;
+        d.MT = (k.m + 10 + 15) / 16;
+        d.MP = 16 * d.MT;
+        d.res_t = (k.m + 9) / 16;
+        d.res_c = (k.m + 9) % 16;
+        d.first = k.first;
+        d.count = k.count;
+        d.off_a = off_a;
+        d.off_kaa = off_kaa;
+        d.off_kaf = off_kaf;
+        d.ws_khat = ws_k;
+        d.ws_L = ws_L;
+        off_a += (int64_t)k.m * k.count;
+        off_kaa += (int64_t)k.m * k.m * k.count;
+        off_kaf += (int64_t)9 * k.m * k.count;
+        ws_k += (int64_t)(d.MT * (d.MT + 1) / 2) * 256 * k.count;
+        ws_L += (int64_t)k.m * k.m * k.count;
+        rc = dalloc(&d.Ghat, (int64_t)d.Qpad * 9 * d.MP);
+        if (rc == HROM_OK) rc = dalloc(&d.GT, (int64_t)d.Qpad * 9 * d.m);
+        if (rc == HROM_OK) rc = dalloc(&d.w, d.Qpad);
+        if (rc == HROM_OK) rc = dalloc(&d.phase, d.Qpad);
+        if (rc == HROM_OK && precision != HROM_FP64) {
+            rc = dalloc(&d.Fhi, (int64_t)d.Qpad * d.MT * 256);
+            if (rc == HROM_OK) rc = dalloc(&d.Flo, (int64_t)d.Qpad * d.MT * 256);
+        }
+        p.cl.push_back(d);
+        if (rc != HROM_OK) break;
+        LayoutArgs la{};
+        la.m = d.m; la.Q = d.Q; la.Qpad = d.Qpad; la.MT = d.MT; la.MP = d.MP; la.prec = precision;
+        la.G = k.G; la.w = k.w; la.phase = k.phase;
+        la.Ghat = d.Ghat; la.GT = d.GT; la.wpad = d.w; la.phpad = d.phase; la.Fhi = d.Fhi; la.Flo = d.Flo;
+        launch_build_layouts(la, nullptr);
+        if (hipDeviceSynchronize() != hipSuccess) rc = HROM_E_HIP;
+    }
+    p.a_len = off_a;
+    p.kaa_len = off_kaa;
+    p.kaf_len = off_kaf;
+    p.khat_len = ws_k;
+    p.L_len = ws_L;
+    const int64_t n = N;
+    if (rc == HROM_OK) rc = dalloc(&p.Fr, 9 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.polar, 21 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.Pr, 9 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.r, off_a);
+    if (rc == HROM_OK) {
+        if (precision == HROM_FP64) rc = dalloc((double**)&p.Khat, ws_k);
+        else rc = dalloc((float**)&p.Khat, ws_k);
+    }
+    if (rc == HROM_OK) rc = dalloc(&p.L, ws_L);
+    if (rc == HROM_OK) rc = dalloc(&p.piv, off_a);
+    if (rc == HROM_OK) rc = dalloc(&p.y, off_a);
+    if (rc == HROM_OK) rc = dalloc(&p.X, 9 * off_a);
+    if (rc == HROM_OK) rc = dalloc(&p.Palg, 9 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.Cr, 81 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.S, 9 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.rnorm, n);
+    if (rc == HROM_OK) rc = dalloc(&p.dU, 9 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.gr, 9 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.Lam, 9 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.lam, off_a);
+    if (rc == HROM_OK) rc = dalloc(&p.rho, off_a);
+    if (rc == HROM_OK) rc = dalloc(&p.hr, 9 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.gth, 4 * n);
+    if (rc != HROM_OK) {
+        free_plan(p);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return HROM_OK;
+}
+
+int hrom_plan_destroy(hrom_plan plan) {
+    if (!plan) return HROM_E_INVALID;
+    (void)hipDeviceSynchronize();
+    free_plan(plan->p);
+    delete plan;
+    return HROM_OK;
+}
+
+int64_t hrom_plan_offset(hrom_plan plan, int32_t c, int32_t kind) {
+    if (!plan || c < 0 || c > plan->p.ncl) return -1;
+    const Plan& p = plan->p;
+    if (c == p.ncl) {
+        if (kind == HROM_OFF_A) return p.a_len;
+        if (kind == HROM_OFF_KAA) return p.kaa_len;
+        if (kind == HROM_OFF_KAF) return p.kaf_len;
+        return -1;
+    }
+    if (kind == HROM_OFF_A) return p.cl[c].off_a;
+    if (kind == HROM_OFF_KAA) return p.cl[c].off_kaa;
+    if (kind == HROM_OFF_KAF) return p.cl[c].off_kaf;
+    return -1;
+}
+
+int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const double* a, double* r,
+              double* Pr, double* Kaa, double* KaF, double* KFF, int32_t* status, hipStream_t stream) {
+    if (!plan || !theta || !Fbar || !a || !status) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    PointArgs pa{p.N, (p.flags & HROM_OBJECTIVE) ? 1 : 0, Fbar, p.Fr, p.polar, status};
+    launch_prepare(pa, stream);
+    const size_t tsz = mixed(p) ? sizeof(float) : sizeof(double);
+    for (const auto& c : p.cl) {
+        EvalArgs e{};
+        e.m = c.m; e.Q = c.Q; e.Qpad = c.Qpad; e.MP = c.MP; e.res_t = c.res_t; e.res_c = c.res_c;
+        e.first = c.first; e.count = c.count; e.N = p.N;
+        e.Ghat = c.Ghat; e.GT = c.GT; e.w = c.w; e.phase = c.phase; e.Fhi = c.Fhi; e.Flo = c.Flo;
+        e.theta = theta; e.Fr = p.Fr; e.a = a + c.off_a;
+        e.Khat = (char*)p.Khat + tsz * (size_t)c.ws_khat;
+        e.r = p.r + c.off_a;
+        e.Pr = p.Pr;
+        e.status = status;
+        e.wscale = wscale_for(c.Q);
+        const int rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, e, stream)
+                                : launch_eval_f64(c.MT, e, stream);
+        if (rc != HROM_OK) return rc;
+    }
+    if (Kaa || KaF || KFF) {
+        for (const auto& c : p.cl) {
+            CondenseArgs ca{};
+            ca.m = c.m; ca.MT = c.MT; ca.res_t = c.res_t; ca.res_c = c.res_c; ca.mixed = mixed(p);
+            ca.first = c.first; ca.count = c.count; ca.N = p.N;
+            ca.Khat = (const char*)p.Khat + tsz * (size_t)c.ws_khat;
+            ca.r = p.r + c.off_a; ca.Pr = p.Pr;
+            ca.kscale = mixed(p) ? 1.0f / wscale_for(c.Q) : 1.0f;
+            ca.outKaa = Kaa ? Kaa + c.off_kaa : nullptr;
+            ca.outKaF = KaF ? KaF + c.off_kaf : nullptr;
+            ca.outKFF = KFF;
+            const int rc = launch_unpack_condense(ca, false, stream);
+            if (rc != HROM_OK) return rc;
+        }
+    }
+    if (r) (void)hipMemcpyAsync(r, p.r, sizeof(double) * p.a_len, hipMemcpyDeviceToDevice, stream);
+    if (Pr) (void)hipMemcpyAsync(Pr, p.Pr, sizeof(double) * 9 * p.N, hipMemcpyDeviceToDevice, stream);
+    const int rc = hip_status();
+    if (rc == HROM_OK) p.stage = 1;
+    return rc;
+}
+
+int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int32_t* status,
+                  hipStream_t stream) {
+    if (!plan || !Pbar || !Cbar || !status) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    if (p.stage < 1) return HROM_E_ORDER;
+    const size_t tsz = mixed(p) ? sizeof(float) : sizeof(double);
+    for (const auto& c : p.cl) {
+        CondenseArgs ca{};
+        ca.m = c.m; ca.MT = c.MT; ca.res_t = c.res_t; ca.res_c = c.res_c; ca.mixed = mixed(p);
+        ca.first = c.first; ca.count = c.count; ca.N = p.N;
+        ca.Khat = (const char*)p.Khat + tsz * (size_t)c.ws_khat;
+        ca.r = p.r + c.off_a; ca.Pr = p.Pr;
+        ca.L = p.L + c.ws_L; ca.piv = p.piv + c.off_a;
+        ca.y = p.y + c.off_a; ca.X = p.X + 9 * c.off_a;
+        ca.Palg = p.Palg; ca.Cr = p.Cr; ca.rnorm = p.rnorm; ca.status = status;
+        ca.kscale = mixed(p) ? 1.0f / wscale_for(c.Q) : 1.0f;
+        const int rc = launch_unpack_condense(ca, true, stream);
+        if (rc != HROM_OK) return rc;
+    }
+    PushArgs pa{p.N, (p.flags & HROM_OBJECTIVE) ? 1 : 0, p.polar, p.Palg, p.Cr, Pbar, Cbar, p.S, status};
+    launch_pushout(pa, stream);
+    if (rnorm) (void)hipMemcpyAsync(rnorm, p.rnorm, sizeof(double) * p.N, hipMemcpyDeviceToDevice, stream);
+    const int rc = hip_status();
+    if (rc == HROM_OK) p.stage = 2;
+    return rc;
+}
+
+}  // extern "C"
+
+static int update_impl(Plan& p, const double* dFbar, double tol, double* a, const int* status,
+                       hipStream_t stream) {
+    UpdateArgs u{};
+    u.N = p.N;
+    u.objective = (p.flags & HROM_OBJECTIVE) ? 1 : 0;
+    u.dFbar = dFbar;
+    u.polar = p.polar;
+    u.dU = p.dU;
+    u.rnorm = p.rnorm;
+    u.status = status;
+    u.tol = tol;
+    launch_stretch_increment(u, stream);
+    for (const auto& c : p.cl) {
+        u.m = c.m;
+        u.first = c.first;
+        u.count = c.count;
+        u.y = p.y + c.off_a;
+        u.X = p.X + 9 * c.off_a;
+        u.a = a + c.off_a;
+        launch_update(u, stream);
+    }
+    return hip_status();
+}
+
+extern "C" {
+
+int hrom_update(hrom_plan plan, const double* dFbar, double tol, double* a, const int32_t* status,
+                hipStream_t stream) {
+    if (!plan || !a || !status) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    if (p.stage < 2) return HROM_E_ORDER;
+    const int rc = update_impl(p, dFbar, tol, a, status, stream);
+    if (rc == HROM_OK) p.stage = 0;
+    return rc;
+}
+
+int hrom_newton(hrom_plan plan, const double* theta, const double* Fbar, double* a, double tol,
+                int32_t max_it, double* Pbar, double* Cbar, double* rnorm, int32_t* status,
+                hipStream_t stream) {
+    if (!plan || max_it < 1) return HROM_E_INVALID;
+    int rc = HROM_OK;
+    for (int it = 0; it < max_it && rc == HROM_OK; it++) {
+        rc = hrom_eval(plan, theta, Fbar, a, nullptr, nullptr, nullptr, nullptr, nullptr, status, stream);
+        if (rc == HROM_OK) rc = hrom_condense(plan, Pbar, Cbar, rnorm, status, stream);
+        if (rc == HROM_OK && it + 1 < max_it) {
+            rc = update_impl(plan->p, nullptr, tol, a, status, stream);
+            // the state of the last evaluation stays valid for the frozen points only;
+            // the next iteration re-evaluates every point
+        }
+    }
+    if (rc == HROM_OK) {
+        launch_mark_unconverged(plan->p.N, plan->p.rnorm, tol, status, stream);
+        rc = hip_status();
+    }
+    return rc;
+}
+
+int hrom_backward(hrom_plan plan, const double* theta, const double* a, const double* gPbar,
+                  double* gFbar, double* gtheta, int32_t* status, hipStream_t stream) {
+    if (!plan || !theta || !a || !gPbar || !gFbar || !gtheta || !status) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    if (p.stage < 2) return HROM_E_ORDER;
+    const int objective = (p.flags & HROM_OBJECTIVE) ? 1 : 0;
+    BwPointArgs bp{p.N, objective, p.polar, p.S, gPbar, p.gr, p.Lam, p.hr, gFbar};
+    launch_bw_pullback(bp, stream);
+    for (const auto& c : p.cl) {
+        LambdaArgs la{c.m, c.first, c.count, p.N, p.X + 9 * c.off_a, p.gr, p.lam + c.off_a};
+        launch_lambda(la, stream);
+        BackwardArgs ba{};
+        ba.m = c.m; ba.Q = c.Q; ba.Qpad = c.Qpad; ba.mixed = mixed(p); ba.objective = objective;
+        ba.first = c.first; ba.count = c.count; ba.N = p.N;
+        ba.GT = c.GT; ba.Ghat = c.Ghat; ba.MP = c.MP; ba.w = c.w; ba.phase = c.phase;
+        ba.theta = theta; ba.Fr = p.Fr; ba.a = a + c.off_a; ba.lam = p.lam + c.off_a;
+        ba.gr = p.gr; ba.hr = p.hr; ba.gth = p.gth; ba.rho = p.rho + c.off_a; ba.status = status;
+        if (mixed(p)) {
+            // one step of iterative refinement of the adjoint solve: the residual
+            // rho = KaF g_r - Kaa lambda with the accurate (FP32-tangent) operator,
+            // corrected with the factor of the low-precision Kaa
+            ba.with_rho = 1;
+            launch_backward_q(ba, stream);
+            RefineArgs ra{c.m, c.first, c.count, p.L + c.ws_L, p.piv + c.off_a, status,
+                          p.rho + c.off_a, p.lam + c.off_a};
+            launch_refine_lambda(ra, stream);
+        }
+        ba.with_rho = 0;
+        launch_backward_q(ba, stream);
+    }
+    launch_bw_pushforward(bp, stream);
+    launch_reduce_theta(p.N, p.gth, gtheta, stream);
+    return hip_status();
+}
+
+}  // extern "C"

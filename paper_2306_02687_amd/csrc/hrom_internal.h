@@ -1,0 +1,228 @@
+// Internal declarations of the gfx950 hyper-reduced RVE library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "hrom.h"
+
+namespace hrom {
+
+constexpr int kMaxModes = 96;   // m <= 96
+constexpr int kMaxTiles = 7;    // ceil((96 + 10) / 16)
+constexpr int kQChunk = 64;     // ECM points per phase-A chunk (one per lane)
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Device-side description of one RVE cluster, in the layouts the kernels read.
+struct ClusterDev {
+    int m, Q, Qpad;        // Qpad: Q rounded up to a multiple of 64
+    int MT, MP;            // column tiles of the augmented mode matrix, MP = 16 MT
+    int res_t, res_c;      // tile / lane column holding the residual column m + 9
+    int64_t first, count;
+    int64_t off_a, off_kaa, off_kaf;   // offsets in caller mode-indexed arrays
+    int64_t ws_khat;       // element offset of the cluster's tile workspace
+    int64_t ws_L;          // element offset of the cluster's factor workspace
+    double* Ghat;          // [Qpad][9][MP]  augmented [G | I_9 | 0] (FP64)
+    double* GT;            // [Qpad/64][9][m][64]  G, ECM point fastest (FP64)
+    double* w;             // [Qpad] (zero padded)
+    int* phase;            // [Qpad]
+    uint16_t* Fhi;         // [Qpad][MT][64][4] low-precision fragments of Ghat (hi part)
+    uint16_t* Flo;         // same, lo part (Ghat - hi)
+};
+
+struct Plan {
+    int ncl = 0;
+    int64_t N = 0;
+    int prec = HROM_FP64;
+    unsigned flags = 0;
+    int device = 0;
+    std::vector<ClusterDev> cl;
+    int64_t a_len = 0, kaa_len = 0, kaf_len = 0, x_len = 0;
+    // per-point workspace
+    double* Fr = nullptr;      // [9][N] RVE-frame deformation gradient
+    double* polar = nullptr;   // [21][N] Fbar (9), eigenvectors V (9), stretches u (3)
+    double* Pr = nullptr;      // [9][N]
+    double* r = nullptr;       // mode-indexed [m][count] blocks
+    void* Khat = nullptr;      // per-cluster tile blocks (double or float)
+    double* L = nullptr;       // per-cluster [count][m][m] factor
+    int* piv = nullptr;        // per-cluster [count][m] pivots (LU fallback)
+    double* y = nullptr;       // mode-indexed
+    double* X = nullptr;       // [9 m][count] blocks, offset 9*off_a
+    double* Palg = nullptr;    // [9][N]
+    double* Cr = nullptr;      // [81][N]
+    double* S = nullptr;       // [9][N] second Piola stress of the push-out
+    double* rnorm = nullptr;   // [N]
+    double* dU = nullptr;      // [9][N] stretch increment scratch
+    double* gr = nullptr;      // [9][N] backward: RVE-frame cotangent
+    double* Lam = nullptr;     // [9][N] backward: Linv(sym(F^T g))
+    double* lam = nullptr;     // mode-indexed: adjoint solution lambda
+    double* rho = nullptr;     // mode-indexed: refinement residual
+    double* hr = nullptr;      // [9][N]
+    double* gth = nullptr;     // [4][N] per-point theta gradients
+    int64_t khat_len = 0, L_len = 0;
+    int stage = 0;             // 0 = nothing, 1 = evaluated, 2 = condensed
+};
+
+// ---------------------------------------------------------------- kernels
+struct PointArgs {
+    int64_t N;
+    int objective;
+    const double* Fbar;
+    double* Fr;
+    double* polar;
+    int* status;
+};
+void launch_prepare(const PointArgs& a, hipStream_t s);
+
+struct EvalArgs {
+    int m, Q, Qpad, MP, res_t, res_c;
+    int64_t first, count, N;
+    const double* Ghat;
+    const double* GT;
+    const double* w;
+    const int* phase;
+    const uint16_t* Fhi;
+    const uint16_t* Flo;
+    const double* theta;
+    const double* Fr;
+    const double* a;       // cluster block [m][count]
+    void* Khat;            // cluster block [count][ntiles][256]
+    double* r;             // cluster block [m][count]
+    double* Pr;            // [9][N]
+    int* status;           // [N]
+    float wscale;          // mixed: power-of-two scaling of w_q A_q
+};
+int launch_eval_f64(int MT, const EvalArgs& a, hipStream_t s);
+int launch_eval_mixed(int MT, int prec, bool split, const EvalArgs& a, hipStream_t s);
+
+struct CondenseArgs {
+    int m, MT, res_t, res_c;
+    int mixed;
+    int64_t first, count, N;
+    const void* Khat;
+    const double* r;       // cluster block
+    const double* Pr;
+    double* L;             // cluster block [count][m][m]
+    int* piv;              // cluster block [count][m]
+    double* y;             // cluster block [m][count]
+    double* X;             // cluster block [9m][count]
+    double* Palg;          // [9][N]
+    double* Cr;            // [81][N]
+    double* rnorm;         // [N]
+    int* status;
+    float kscale;          // inverse of the mixed-mode scaling
+    // optional exports (NULL = skip)
+    double* outKaa;        // [m*m][count]
+    double* outKaF;        // [m*9][count]
+    double* outKFF;        // [81][N]
+};
+int launch_unpack_condense(const CondenseArgs& a, bool condense, hipStream_t s);
+
+struct PushArgs {
+    int64_t N;
+    int objective;
+    const double* polar;
+    const double* Palg;
+    const double* Cr;
+    double* Pbar;
+    double* Cbar;
+    double* S;
+    int* status;
+};
+void launch_pushout(const PushArgs& a, hipStream_t s);
+
+struct UpdateArgs {
+    int m;
+    int64_t first, count, N;
+    int objective;
+    const double* dFbar;   // [9][N] or null
+    const double* polar;
+    double* dU;            // [9][N]
+    const double* y;       // cluster block
+    const double* X;       // cluster block
+    const double* rnorm;
+    const int* status;
+    double tol;
+    double* a;             // cluster block
+};
+void launch_stretch_increment(const UpdateArgs& a, hipStream_t s);
+void launch_update(const UpdateArgs& a, hipStream_t s);
+
+struct BackwardArgs {
+    int m, Q, Qpad, mixed, objective, with_rho;
+    int64_t first, count, N;
+    const double* GT;
+    const double* Ghat;
+    int MP;
+    const double* w;
+    const int* phase;
+    const double* theta;
+    const double* Fr;
+    const double* a;       // cluster block
+    const double* lam;     // cluster block
+    const double* gr;      // [9][N]
+    double* hr;            // [9][N]
+    double* gth;           // [4][N]
+    double* rho;           // cluster block (refinement residual) or null
+    int* status;
+};
+int launch_backward_q(const BackwardArgs& a, hipStream_t s);
+
+struct BwPointArgs {
+    int64_t N;
+    int objective;
+    const double* polar;
+    const double* S;
+    const double* g;
+    double* gr;
+    double* Lam;
+    const double* hr;
+    double* gF;
+};
+void launch_bw_pullback(const BwPointArgs& a, hipStream_t s);
+void launch_bw_pushforward(const BwPointArgs& a, hipStream_t s);
+
+struct LambdaArgs {
+    int m;
+    int64_t first, count, N;
+    const double* X;       // cluster block [9m][count]
+    const double* gr;      // [9][N]
+    double* lam;           // cluster block [m][count]
+};
+void launch_lambda(const LambdaArgs& a, hipStream_t s);
+
+struct RefineArgs {
+    int m;
+    int64_t first, count;
+    const double* L;
+    const int* piv;
+    const int* status;
+    const double* rho;     // cluster block
+    double* lam;           // cluster block, updated in place
+};
+void launch_refine_lambda(const RefineArgs& a, hipStream_t s);
+
+void launch_reduce_theta(int64_t N, const double* gth, double* out, hipStream_t s);
+void launch_mark_unconverged(int64_t N, const double* rnorm, double tol, int* status,
+                             hipStream_t s);
+
+// plan-time layout builders
+struct LayoutArgs {
+    int m, Q, Qpad, MT, MP, prec;
+    const double* G;
+    const double* w;
+    const int* phase;
+    double* Ghat;
+    double* GT;
+    double* wpad;
+    int* phpad;
+    uint16_t* Fhi;
+    uint16_t* Flo;
+};
+void launch_build_layouts(const LayoutArgs& a, hipStream_t s);
+
+}  // namespace hrom

@@ -1,0 +1,386 @@
+// Static condensation of the ROM amplitudes at every macro point
+// (Sec. 3.2.3, eq. Biot_Tangent): factor Kaa (Cholesky; LU with partial
+// pivoting when a pivot is not positive, Sec. 4: factorise, never invert),
+// solve y = Kaa^{-1} r and X = Kaa^{-1} KaF, and form
+//   Palg = Pr - KaF^T y,   Cr = KFF - KaF^T X.
+// One wavefront per macro point; the blocks of the point live in LDS.  Rows
+// are distributed over lanes (row i on lane i mod 64).
+#include <hip/hip_runtime.h>
+
+#include "hrom_internal.h"
+
+namespace hrom {
+
+struct CondLds {
+    int ld;
+    double *K, *KaF, *KFF, *B, *Pr, *rv;
+    __device__ CondLds(double* sm, int m) {
+        ld = m + 1;
+        K = sm;                 // [m][ld]
+        KaF = K + m * ld;       // [m][9]
+        KFF = KaF + 9 * m;      // [81]
+        B = KFF + 81;           // [m][10]: r | KaF, overwritten by y | X
+        Pr = B + 10 * m;        // [9]
+        rv = Pr + 9;            // [m]
+    }
+};
+
+static size_t cond_lds_bytes(int m) {
+    return sizeof(double) * ((size_t)m * (m + 1) + 9 * m + 81 + 10 * m + 9 + m);
+}
+
+template <typename TT>
+__device__ void unpack_tiles(const CondenseArgs& A, const TT* kh, CondLds& S, bool kaa_only) {
+    const int m = A.m, MT = A.MT, lane = threadIdx.x;
+    const int g = lane >> 4, c = lane & 15;
+    const double ks = (double)A.kscale;
+    int idx = 0;
+    for (int ti = 0; ti < MT; ti++)
+        for (int tj = ti; tj < MT; tj++, idx++) {
+            const TT* p = kh + (int64_t)idx * 256 + lane * 4;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int R = 16 * ti + 4 * g + e, C = 16 * tj + c;
+                const double v = (double)p[e] * ks;
+                if (R < m) {
+                    if (C < m) {
+                        S.K[R * S.ld + C] = v;
+                        if (ti < tj) S.K[C * S.ld + R] = v;
+                    } else if (C < m + 9 && !kaa_only) {
+                        S.KaF[R * 9 + (C - m)] = v;
+                    }
+                } else if (R < m + 9 && C >= m && C < m + 9 && !kaa_only) {
+                    S.KFF[(R - m) * 9 + (C - m)] = v;
+                    if (ti < tj) S.KFF[(C - m) * 9 + (R - m)] = v;
+                }
+            }
+        }
+}
+
+template <typename TT>
+__global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int do_condense) {
+    extern __shared__ double sm[];
+    const int m = A.m, lane = threadIdx.x;
+    const int64_t pl = blockIdx.x;
+    const int64_t b = A.first + pl;
+    const int MT = A.MT, NT = MT * (MT + 1) / 2;
+    CondLds S(sm, m);
+    const TT* kh = (const TT*)A.Khat + (int64_t)pl * NT * 256;
+    unpack_tiles<TT>(A, kh, S, false);
+    for (int i = lane; i < m; i += 64) {
+        const double ri = A.r[(int64_t)i * A.count + pl];
+        S.rv[i] = ri;
+        S.B[i * 10] = ri;
+    }
+    if (lane < 9) S.Pr[lane] = A.Pr[(int64_t)lane * A.N + b];
+    __syncthreads();
+    for (int i = lane; i < m; i += 64)
+#pragma unroll
+        for (int J = 0; J < 9; J++) S.B[i * 10 + 1 + J] = S.KaF[i * 9 + J];
+
+    if (!do_condense) {
+        // test exports of the raw blocks
+        if (A.outKaa)
+            for (int e = lane; e < m * m; e += 64)
+                A.outKaa[(int64_t)e * A.count + pl] = S.K[(e / m) * S.ld + (e % m)];
+        if (A.outKaF)
+            for (int e = lane; e < m * 9; e += 64) A.outKaF[(int64_t)e * A.count + pl] = S.KaF[e];
+        if (A.outKFF)
+            for (int e = lane; e < 81; e += 64) A.outKFF[(int64_t)e * A.N + b] = S.KFF[e];
+        return;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------ Cholesky, right-looking
+    bool spd = true;
+    for (int j = 0; j < m; j++) {
+        const double d = S.K[j * S.ld + j];
+        if (!(d > 0.0)) {
+            spd = false;
+            break;
+        }
+        const double sd = sqrt(d);
+        __syncthreads();
+        for (int i = lane; i < m; i += 64) {
+            if (i > j) S.K[i * S.ld + j] = S.K[i * S.ld + j] / sd;
+            else if (i == j) S.K[j * S.ld + j] = sd;
+        }
+        __syncthreads();
+        for (int i = lane; i < m; i += 64) {
+            if (i > j) {
+                const double lij = S.K[i * S.ld + j];
+                for (int k = j + 1; k <= i; k++) S.K[i * S.ld + k] -= lij * S.K[k * S.ld + j];
+            }
+        }
+        __syncthreads();
+    }
+    int st = 0;
+    int* piv = A.piv + pl * m;
+    if (spd) {
+        // L z = B, then L^T x = z (10 right-hand sides)
+        for (int j = 0; j < m; j++) {
+            __syncthreads();
+            const double djj = S.K[j * S.ld + j];
+            double z[10];
+#pragma unroll
+            for (int r = 0; r < 10; r++) z[r] = S.B[j * 10 + r] / djj;
+            __syncthreads();
+            for (int i = lane; i < m; i += 64) {
+                if (i == j) {
+#pragma unroll
+                    for (int r = 0; r < 10; r++) S.B[j * 10 + r] = z[r];
+                } else if (i > j) {
+                    const double lij = S.K[i * S.ld + j];
+#pragma unroll
+                    for (int r = 0; r < 10; r++) S.B[i * 10 + r] -= lij * z[r];
+                }
+            }
+        }
+        for (int j = m - 1; j >= 0; j--) {
+            __syncthreads();
+            const double djj = S.K[j * S.ld + j];
+            double x[10];
+#pragma unroll
+            for (int r = 0; r < 10; r++) x[r] = S.B[j * 10 + r] / djj;
+            __syncthreads();
+            for (int i = lane; i < m; i += 64) {
+                if (i == j) {
+#pragma unroll
+                    for (int r = 0; r < 10; r++) S.B[j * 10 + r] = x[r];
+                } else if (i < j) {
+                    const double lji = S.K[j * S.ld + i];
+#pragma unroll
+                    for (int r = 0; r < 10; r++) S.B[i * 10 + r] -= lji * x[r];
+                }
+            }
+        }
+        if (lane == 0) piv[0] = -1;   // marks a Cholesky factor
+    } else {
+        // ------------------------------------------------ LU with partial pivoting
+        st |= HROM_PT_NOT_SPD;
+        __syncthreads();
+        unpack_tiles<TT>(A, kh, S, true);
+        for (int i = lane; i < m; i += 64) {
+            S.B[i * 10] = S.rv[i];
+#pragma unroll
+            for (int J = 0; J < 9; J++) S.B[i * 10 + 1 + J] = S.KaF[i * 9 + J];
+        }
+        __syncthreads();
+        for (int j = 0; j < m; j++) {
+            // pivot: largest |K[i][j]|, i >= j, smallest index on ties
+            double best = -1.0;
+            int bi = j;
+            for (int i = lane; i < m; i += 64) {
+                if (i >= j) {
+                    const double v = fabs(S.K[i * S.ld + j]);
+                    if (v > best) { best = v; bi = i; }
+                }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (lane == 0) piv[j] = bi;
+            if (!(best > 0.0)) {
+                st |= HROM_PT_NONFINITE;
+                break;
+            }
+            __syncthreads();
+            if (bi != j) {
+                for (int k = lane; k < m; k += 64) {
+                    const double t = S.K[j * S.ld + k];
+                    S.K[j * S.ld + k] = S.K[bi * S.ld + k];
+                    S.K[bi * S.ld + k] = t;
+                }
+                if (lane < 10) {
+                    const double t = S.B[j * 10 + lane];
+                    S.B[j * 10 + lane] = S.B[bi * 10 + lane];
+                    S.B[bi * 10 + lane] = t;
+                }
+            }
+            __syncthreads();
+            const double pj = S.K[j * S.ld + j];
+            for (int i = lane; i < m; i += 64) {
+                if (i > j) {
+                    const double lij = S.K[i * S.ld + j] / pj;
+                    S.K[i * S.ld + j] = lij;
+                    for (int k = j + 1; k < m; k++) S.K[i * S.ld + k] -= lij * S.K[j * S.ld + k];
+                }
+            }
+            __syncthreads();
+        }
+        if (!(st & HROM_PT_NONFINITE)) {
+            for (int j = 0; j < m; j++) {   // unit lower
+                __syncthreads();
+                double z[10];
+#pragma unroll
+                for (int r = 0; r < 10; r++) z[r] = S.B[j * 10 + r];
+                __syncthreads();
+                for (int i = lane; i < m; i += 64)
+                    if (i > j) {
+                        const double lij = S.K[i * S.ld + j];
+#pragma unroll
+                        for (int r = 0; r < 10; r++) S.B[i * 10 + r] -= lij * z[r];
+                    }
+            }
+            for (int j = m - 1; j >= 0; j--) {
+                __syncthreads();
+                const double ujj = S.K[j * S.ld + j];
+                double x[10];
+#pragma unroll
+                for (int r = 0; r < 10; r++) x[r] = S.B[j * 10 + r] / ujj;
+                __syncthreads();
+                for (int i = lane; i < m; i += 64) {
+                    if (i == j) {
+#pragma unroll
+                        for (int r = 0; r < 10; r++) S.B[j * 10 + r] = x[r];
+                    } else if (i < j) {
+                        const double uij = S.K[i * S.ld + j];
+#pragma unroll
+                        for (int r = 0; r < 10; r++) S.B[i * 10 + r] -= uij * x[r];
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------ condensation and outputs
+    bool fin = true;
+    for (int o = lane; o < 90; o += 64) {
+        if (o < 9) {
+            double v = S.Pr[o];
+            for (int k = 0; k < m; k++) v -= S.KaF[k * 9 + o] * S.B[k * 10];
+            A.Palg[(int64_t)o * A.N + b] = v;
+            fin = fin && isfinite(v);
+        } else {
+            const int I = (o - 9) / 9, J = (o - 9) % 9;
+            double v = S.KFF[I * 9 + J];
+            for (int k = 0; k < m; k++) v -= S.KaF[k * 9 + I] * S.B[k * 10 + 1 + J];
+            A.Cr[(int64_t)(I * 9 + J) * A.N + b] = v;
+            fin = fin && isfinite(v);
+        }
+    }
+    double rr = 0.0;
+    for (int i = lane; i < m; i += 64) {
+        rr += S.rv[i] * S.rv[i];
+        A.y[(int64_t)i * A.count + pl] = S.B[i * 10];
+#pragma unroll
+        for (int J = 0; J < 9; J++) A.X[((int64_t)i * 9 + J) * A.count + pl] = S.B[i * 10 + 1 + J];
+        double* Lrow = A.L + (pl * m + i) * (int64_t)m;
+        for (int k = 0; k < m; k++) Lrow[k] = S.K[i * S.ld + k];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rr += __shfl_xor(rr, off);
+    const uint64_t bad = __ballot(!fin);
+    if (lane == 0) {
+        A.rnorm[b] = sqrt(rr);
+        if (bad) st |= HROM_PT_NONFINITE;
+        if (st) A.status[b] |= st;
+    }
+}
+
+int launch_unpack_condense(const CondenseArgs& a, bool condense, hipStream_t s) {
+    const size_t bytes = cond_lds_bytes(a.m);
+    if (bytes > 160 * 1024) return HROM_E_UNSUPPORTED;
+    const dim3 grid((unsigned)a.count), block(64);
+    if (a.mixed) {
+        static bool attr = false;
+        if (!attr) {
+            hipFuncSetAttribute((const void*)k_unpack_condense<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_unpack_condense<float>, grid, block, bytes, s, a, (int)condense);
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            hipFuncSetAttribute((const void*)k_unpack_condense<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_unpack_condense<double>, grid, block, bytes, s, a, (int)condense);
+    }
+    return HROM_OK;
+}
+
+// ---------------------------------------------------------------- refinement
+// lambda <- lambda + Kaa~^{-1} rho with the stored factor of the evaluated
+// (low-precision) Kaa~: one step of iterative refinement of the adjoint solve.
+__global__ void __launch_bounds__(64) k_refine_lambda(RefineArgs A) {
+    extern __shared__ double sm[];
+    const int m = A.m, lane = threadIdx.x;
+    const int64_t pl = blockIdx.x;
+    const int64_t b = A.first + pl;
+    const int st = A.status[b];
+    if (st & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) return;
+    double* L = sm;           // [m][m]
+    double* x = L + m * m;    // [m]
+    const double* Lg = A.L + pl * (int64_t)m * m;
+    for (int e = lane; e < m * m; e += 64) L[e] = Lg[e];
+    for (int i = lane; i < m; i += 64) x[i] = A.rho[(int64_t)i * A.count + pl];
+    const int* piv = A.piv + pl * m;
+    const bool chol = (piv[0] < 0);
+    __syncthreads();
+    if (chol) {
+        for (int j = 0; j < m; j++) {
+            __syncthreads();
+            const double z = x[j] / L[j * m + j];
+            __syncthreads();
+            for (int i = lane; i < m; i += 64) {
+                if (i == j) x[j] = z;
+                else if (i > j) x[i] -= L[i * m + j] * z;
+            }
+        }
+        for (int j = m - 1; j >= 0; j--) {
+            __syncthreads();
+            const double z = x[j] / L[j * m + j];
+            __syncthreads();
+            for (int i = lane; i < m; i += 64) {
+                if (i == j) x[j] = z;
+                else if (i < j) x[i] -= L[j * m + i] * z;
+            }
+        }
+    } else {
+        if (lane == 0)
+            for (int j = 0; j < m; j++)
+                if (piv[j] != j) {
+                    const double t = x[j];
+                    x[j] = x[piv[j]];
+                    x[piv[j]] = t;
+                }
+        for (int j = 0; j < m; j++) {
+            __syncthreads();
+            const double z = x[j];
+            __syncthreads();
+            for (int i = lane; i < m; i += 64)
+                if (i > j) x[i] -= L[i * m + j] * z;
+        }
+        for (int j = m - 1; j >= 0; j--) {
+            __syncthreads();
+            const double z = x[j] / L[j * m + j];
+            __syncthreads();
+            for (int i = lane; i < m; i += 64) {
+                if (i == j) x[j] = z;
+                else if (i < j) x[i] -= L[i * m + j] * z;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < m; i += 64) A.lam[(int64_t)i * A.count + pl] += x[i];
+}
+
+void launch_refine_lambda(const RefineArgs& a, hipStream_t s) {
+    const size_t bytes = sizeof(double) * ((size_t)a.m * a.m + a.m);
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void*)k_refine_lambda, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_refine_lambda, dim3((unsigned)a.count), dim3(64), bytes, s, a);
+}
+
+}  // namespace hrom

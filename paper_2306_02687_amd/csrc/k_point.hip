@@ -1,0 +1,430 @@
+// Per-macro-point kernels: polar split, push-out to the macro frame, the
+// monolithic update, the backward pull-back / push-forward, reductions and
+// the plan-time layout builder.  One thread per macro point (or per
+// (mode, point) pair); all per-point arrays are component-major [k][N], so
+// consecutive threads touch consecutive addresses.
+#include <hip/hip_runtime.h>
+
+#include "hrom_internal.h"
+#include "hrom_math.h"
+
+namespace hrom {
+
+static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------- polar split
+// Fbar = Rbar Ubar (Sec. 3.2.2): eigen-decomposition of C = Fbar^T Fbar,
+// Ubar = V diag(sqrt c) V^T.  The RVE frame sees Fr = Ubar (objective) or
+// Fr = Fbar (direct).  Non-finite input or det Fbar <= 0 flags the point and
+// substitutes the identity so that no NaN leaves the point.
+__global__ void k_prepare(PointArgs A) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.N) return;
+    const int64_t N = A.N;
+    double F[9];
+    int st = 0;
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        F[k] = A.Fbar[k * N + b];
+        fin = fin && isfinite(F[k]);
+    }
+    if (!fin) st |= HROM_PT_NONFINITE;
+    if (fin && A.objective && !(det3(F) > 0.0)) st |= HROM_PT_JNONPOS;
+    if (st) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) F[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    }
+    double V[9], u[3], U[9];
+    if (A.objective) {
+        double C[9], c[3];
+        tmul3(F, F, C);
+        eigsym3(C, V, c);
+#pragma unroll
+        for (int i = 0; i < 3; i++) u[i] = sqrt(c[i]);
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                U[3 * i + j] = V[3 * i] * u[0] * V[3 * j] + V[3 * i + 1] * u[1] * V[3 * j + 1] +
+                               V[3 * i + 2] * u[2] * V[3 * j + 2];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            U[k] = F[k];
+            V[k] = (k % 4 == 0) ? 1.0 : 0.0;
+        }
+        u[0] = u[1] = u[2] = 1.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        A.Fr[k * N + b] = U[k];
+        A.polar[k * N + b] = F[k];
+        A.polar[(9 + k) * N + b] = V[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) A.polar[(18 + k) * N + b] = u[k];
+    A.status[b] = st;
+}
+
+void launch_prepare(const PointArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_prepare, dim3(nblocks(a.N, 256)), dim3(256), 0, s, a);
+}
+
+__device__ __forceinline__ void load_polar(const double* polar, int64_t N, int64_t b, double* F,
+                                           double* V, double* u) {
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        F[k] = polar[k * N + b];
+        V[k] = polar[(9 + k) * N + b];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) u[k] = polar[(18 + k) * N + b];
+}
+
+// ---------------------------------------------------------------- push-out
+// Biot stress T = sym(Palg_r) (eq. workconjugacy), second Piola S from
+// Ubar S + S Ubar = 2 T, Pbar = Fbar S; tangent column k along E_k:
+// dU = Linv(E_k^T F + F^T E_k), dT = sym(Cr dU),
+// dS = Linv(2 dT - dU S - S dU), Cbar e_k = E_k S + F dS.
+__global__ void k_pushout(PushArgs A) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.N) return;
+    const int64_t N = A.N;
+    double Pa[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) Pa[k] = A.Palg[k * N + b];
+    int st = A.status[b];
+    if (!A.objective) {
+        bool fin = true;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            A.Pbar[k * N + b] = Pa[k];
+            fin = fin && isfinite(Pa[k]);
+        }
+        for (int k = 0; k < 81; k++) {
+            const double v = A.Cr[k * N + b];
+            A.Cbar[k * N + b] = v;
+            fin = fin && isfinite(v);
+        }
+        if (!fin) A.status[b] = st | HROM_PT_NONFINITE;
+        return;
+    }
+    double F[9], V[9], u[3];
+    load_polar(A.polar, N, b, F, V, u);
+    double T2[9], S[9], P[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) T2[3 * i + j] = Pa[3 * i + j] + Pa[3 * j + i];
+    lyap_solve(V, u, T2, S);
+    mul3(F, S, P);
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        A.Pbar[k * N + b] = P[k];
+        A.S[k * N + b] = S[k];
+        fin = fin && isfinite(P[k]);
+    }
+    for (int kc = 0; kc < 9; kc++) {
+        const int ka = kc / 3, kb = kc % 3;   // E_k = e_ka (x) e_kb
+        double dC[9], dU[9];
+        // (E_k^T F)_ij = delta_{i kb} F_{ka j};  dC = E_k^T F + F^T E_k
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                dC[3 * i + j] = (i == kb ? F[3 * ka + j] : 0.0) + (j == kb ? F[3 * ka + i] : 0.0);
+        lyap_solve(V, u, dC, dU);
+        double dP[9];
+        for (int I = 0; I < 9; I++) {
+            double s = 0.0;
+#pragma unroll
+            for (int J = 0; J < 9; J++) s = fma(A.Cr[(9 * I + J) * N + b], dU[J], s);
+            dP[I] = s;
+        }
+        double B[9], t1[9], t2[9], dS[9], FdS[9];
+        mul3(dU, S, t1);
+        mul3(S, dU, t2);
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                B[3 * i + j] = (dP[3 * i + j] + dP[3 * j + i]) - t1[3 * i + j] - t2[3 * i + j];
+        lyap_solve(V, u, B, dS);
+        mul3(F, dS, FdS);
+#pragma unroll
+        for (int I = 0; I < 9; I++) {
+            const int i = I / 3, j = I % 3;
+            const double v = (i == ka ? S[3 * kb + j] : 0.0) + FdS[I];
+            A.Cbar[(9 * I + kc) * N + b] = v;
+            fin = fin && isfinite(v);
+        }
+    }
+    if (!fin) A.status[b] = st | HROM_PT_NONFINITE;
+}
+
+void launch_pushout(const PushArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_pushout, dim3(nblocks(a.N, 128)), dim3(128), 0, s, a);
+}
+
+// ---------------------------------------------------------------- update
+// linearised macro stretch increment dU = Linv(dF^T F + F^T dF) (objective)
+// or dF (direct); zero when no increment is given (pure micro Newton step).
+__global__ void k_stretch_increment(UpdateArgs A) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.N) return;
+    const int64_t N = A.N;
+    double dU[9];
+    if (!A.dFbar) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) dU[k] = 0.0;
+    } else if (!A.objective) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) dU[k] = A.dFbar[k * N + b];
+    } else {
+        double F[9], V[9], u[3], dF[9], a1[9], dC[9];
+        load_polar(A.polar, N, b, F, V, u);
+#pragma unroll
+        for (int k = 0; k < 9; k++) dF[k] = A.dFbar[k * N + b];
+        tmul3(dF, F, a1);
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) dC[3 * i + j] = a1[3 * i + j] + a1[3 * j + i];
+        lyap_solve(V, u, dC, dU);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) A.dU[k * N + b] = dU[k];
+}
+
+void launch_stretch_increment(const UpdateArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_stretch_increment, dim3(nblocks(a.N, 256)), dim3(256), 0, s, a);
+}
+
+// a <- a - (y + X dU)  (Sec. 3.2.3), one thread per (mode, point).  Points
+// flagged as failed are left unchanged; without an increment (pure micro
+// Newton step) converged points (rnorm < tol) are frozen.
+__global__ void k_update(UpdateArgs A) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)A.m * A.count) return;
+    const int k = (int)(t / A.count);
+    const int64_t pl = t - (int64_t)k * A.count;
+    const int64_t b = A.first + pl;
+    if (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) return;
+    if (!A.dFbar && !(A.rnorm[b] >= A.tol)) return;
+    double s = A.y[(int64_t)k * A.count + pl];
+#pragma unroll
+    for (int J = 0; J < 9; J++)
+        s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], A.dU[J * A.N + b], s);
+    A.a[(int64_t)k * A.count + pl] -= s;
+}
+
+void launch_update(const UpdateArgs& a, hipStream_t s) {
+    const int64_t n = (int64_t)a.m * a.count;
+    hipLaunchKernelGGL(k_update, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------- backward
+// pull-back of the macro cotangent: Lam = Linv(sym(F^T g)), g_r = 2 Lam
+__global__ void k_bw_pullback(BwPointArgs A) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.N) return;
+    const int64_t N = A.N;
+    double g[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) g[k] = A.g[k * N + b];
+    if (!A.objective) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            A.gr[k * N + b] = g[k];
+            A.Lam[k * N + b] = 0.5 * g[k];
+        }
+        return;
+    }
+    double F[9], V[9], u[3], Ftg[9], H[9], Lam[9];
+    load_polar(A.polar, N, b, F, V, u);
+    tmul3(F, g, Ftg);
+    sym3(Ftg, H);
+    lyap_solve(V, u, H, Lam);
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        A.Lam[k * N + b] = Lam[k];
+        A.gr[k * N + b] = 2.0 * Lam[k];
+    }
+}
+
+void launch_bw_pullback(const BwPointArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_bw_pullback, dim3(nblocks(a.N, 256)), dim3(256), 0, s, a);
+}
+
+// dL/dFbar = g S + 2 F Linv(sym(h_r) - Lam S - S Lam)
+__global__ void k_bw_pushforward(BwPointArgs A) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.N) return;
+    const int64_t N = A.N;
+    double h[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) h[k] = A.hr[k * N + b];
+    if (!A.objective) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) A.gF[k * N + b] = h[k];
+        return;
+    }
+    double F[9], V[9], u[3], S[9], Lam[9], g[9], M[9], t1[9], t2[9], Z[9], FZ[9], gS[9];
+    load_polar(A.polar, N, b, F, V, u);
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        S[k] = A.S[k * N + b];
+        Lam[k] = A.Lam[k * N + b];
+        g[k] = A.g[k * N + b];
+    }
+    mul3(Lam, S, t1);
+    mul3(S, Lam, t2);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            M[3 * i + j] = 0.5 * (h[3 * i + j] + h[3 * j + i]) - t1[3 * i + j] - t2[3 * i + j];
+    lyap_solve(V, u, M, Z);
+    mul3(F, Z, FZ);
+    mul3(g, S, gS);
+#pragma unroll
+    for (int k = 0; k < 9; k++) A.gF[k * N + b] = gS[k] + 2.0 * FZ[k];
+}
+
+void launch_bw_pushforward(const BwPointArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_bw_pushforward, dim3(nblocks(a.N, 256)), dim3(256), 0, s, a);
+}
+
+// adjoint solve with the stored factor: lambda = Kaa^{-T} KaF g_r = X g_r
+__global__ void k_lambda(LambdaArgs A) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)A.m * A.count) return;
+    const int k = (int)(t / A.count);
+    const int64_t pl = t - (int64_t)k * A.count;
+    const int64_t b = A.first + pl;
+    double s = 0.0;
+#pragma unroll
+    for (int J = 0; J < 9; J++) s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], A.gr[J * A.N + b], s);
+    A.lam[(int64_t)k * A.count + pl] = s;
+}
+
+void launch_lambda(const LambdaArgs& a, hipStream_t s) {
+    const int64_t n = (int64_t)a.m * a.count;
+    hipLaunchKernelGGL(k_lambda, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------- reductions
+// dL/dtheta: fixed-order sum over points (bitwise reproducible): thread t of
+// component c sums points t, t + 256, ... in order, then a fixed tree.
+__global__ void k_reduce_theta(int64_t N, const double* gth, double* out) {
+    __shared__ double s[256];
+    const int c = blockIdx.x;
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    for (int64_t b = t; b < N; b += 256) acc += gth[c * N + b];
+    s[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) s[t] += s[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[c] = s[0];
+}
+
+void launch_reduce_theta(int64_t N, const double* gth, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_theta, dim3(4), dim3(256), 0, s, N, gth, out);
+}
+
+__global__ void k_mark_unconverged(int64_t N, const double* rnorm, double tol, int* status) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= N) return;
+    if (!(rnorm[b] < tol)) status[b] |= HROM_PT_NOCONV;
+}
+
+void launch_mark_unconverged(int64_t N, const double* rnorm, double tol, int* status,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_mark_unconverged, dim3(nblocks(N, 256)), dim3(256), 0, s, N, rnorm, tol,
+                       status);
+}
+
+// ---------------------------------------------------------------- plan-time layouts
+__device__ __forceinline__ uint16_t to_bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16_bits(uint16_t h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+__device__ __forceinline__ uint16_t to_f16_bits(float x) {
+    _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float from_f16_bits(uint16_t h) {
+    return (float)__builtin_bit_cast(_Float16, h);
+}
+
+// One thread per (q, row J, column n) of the augmented mode matrix
+// Ghat_q = [G_q | I_9 | 0] (9 x MP).
+__global__ void k_build_ghat(LayoutArgs A) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)A.Qpad * 9 * A.MP;
+    if (t >= tot) return;
+    const int n = (int)(t % A.MP);
+    const int J = (int)((t / A.MP) % 9);
+    const int q = (int)(t / (9 * (int64_t)A.MP));
+    double v = 0.0;
+    if (q < A.Q) {
+        if (n < A.m) v = A.G[((int64_t)q * 9 + J) * A.m + n];
+        else if (n < A.m + 9) v = (n - A.m == J) ? 1.0 : 0.0;
+    }
+    A.Ghat[t] = v;
+    if (n < A.m) {
+        // GT[(q/64)][J][n][q%64]
+        A.GT[(((int64_t)(q >> 6) * 9 + J) * A.m + n) * 64 + (q & 63)] = (q < A.Q) ? v : 0.0;
+    }
+    if (J == 0 && n == 0) {
+        A.wpad[q] = (q < A.Q) ? A.w[q] : 0.0;
+        A.phpad[q] = (q < A.Q) ? A.phase[q] : 0;
+    }
+}
+
+// MFMA fragments: lane (g, c) of tile t holds Ghat[q][4g + e][16 t + c], e = 0..3
+// (rows >= 9 are zero), split into a hi part and the rounded remainder.
+__global__ void k_build_frags(LayoutArgs A) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)A.Qpad * A.MT * 64 * 4;
+    if (t >= tot) return;
+    const int e = (int)(t & 3);
+    const int lane = (int)((t >> 2) & 63);
+    const int tile = (int)((t >> 8) % A.MT);
+    const int q = (int)((t >> 8) / A.MT);
+    const int g = lane >> 4, c = lane & 15;
+    const int J = 4 * g + e;
+    const int n = 16 * tile + c;
+    double v = 0.0;
+    if (J < 9) v = A.Ghat[((int64_t)q * 9 + J) * A.MP + n];
+    uint16_t hi, lo;
+    if (A.prec == HROM_MIXED_BF16) {
+        hi = to_bf16_bits((float)v);
+        lo = to_bf16_bits((float)(v - (double)from_bf16_bits(hi)));
+    } else {
+        hi = to_f16_bits((float)v);
+        lo = to_f16_bits((float)(v - (double)from_f16_bits(hi)));
+    }
+    A.Fhi[t] = hi;
+    A.Flo[t] = lo;
+}
+
+void launch_build_layouts(const LayoutArgs& a, hipStream_t s) {
+    const int64_t n1 = (int64_t)a.Qpad * 9 * a.MP;
+    hipLaunchKernelGGL(k_build_ghat, dim3(nblocks(n1, 256)), dim3(256), 0, s, a);
+    if (a.prec != HROM_FP64) {
+        const int64_t n2 = (int64_t)a.Qpad * a.MT * 256;
+        hipLaunchKernelGGL(k_build_frags, dim3(nblocks(n2, 256)), dim3(256), 0, s, a);
+    }
+}
+
+}  // namespace hrom
