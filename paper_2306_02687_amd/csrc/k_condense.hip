@@ -29,6 +29,17 @@ static size_t cond_lds_bytes(int m) {
     return sizeof(double) * ((size_t)m * (m + 1) + 9 * m + 81 + 10 * m + 9 + m);
 }
 
+// Row of accumulator element e held by lane group g inside a 16x16 tile:
+// FP64 16x16x4 MFMA interleaves (row g + 4e), the 16-bit MFMAs with FP32
+// accumulation keep rows contiguous per lane group (row 4g + e); the column
+// is the lane index mod 16 in both.
+template <typename TT>
+__device__ __forceinline__ int acc_row(int g, int e);
+template <>
+__device__ __forceinline__ int acc_row<double>(int g, int e) { return g + 4 * e; }
+template <>
+__device__ __forceinline__ int acc_row<float>(int g, int e) { return 4 * g + e; }
+
 template <typename TT>
 __device__ void unpack_tiles(const CondenseArgs& A, const TT* kh, CondLds& S, bool kaa_only) {
     const int m = A.m, MT = A.MT, lane = threadIdx.x;
@@ -40,7 +51,7 @@ __device__ void unpack_tiles(const CondenseArgs& A, const TT* kh, CondLds& S, bo
             const TT* p = kh + (int64_t)idx * 256 + lane * 4;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const int R = 16 * ti + 4 * g + e, C = 16 * tj + c;
+                const int R = 16 * ti + acc_row<TT>(g, e), C = 16 * tj + c;
                 const double v = (double)p[e] * ks;
                 if (R < m) {
                     if (C < m) {

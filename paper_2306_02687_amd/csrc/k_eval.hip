@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(256, 1) k_eval_f64(EvalArgs A) {
             const int idx = ti * MT - ti * (ti - 1) / 2 + (MT - 1 - ti);
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const int row = 16 * ti + 4 * g + e;
+                const int row = 16 * ti + g + 4 * e;   // FP64 MFMA accumulator rows interleave
                 const double v = acc[idx][e];
                 if (row < m) A.r[(int64_t)row * A.count + pl] = v;
                 else if (row < m + 9) A.Pr[(int64_t)(row - m) * A.N + b] = v;
