@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the hyper-reduced RVE evaluation on one MI355X.
+
+One step = one pass of the whole hot path over every macro point of the
+workload: polar split, reduced kinematics, Neo-Hooke stress and tangent at
+every ECM point, the ECM sums (r, Kaa, KaF, KFF, Pbar), Cholesky
+condensation with the objective push-out (Pbar_alg, Cbar), the adjoint
+backward (dL/dFbar, dL/dtheta) and the monolithic update of the ROM
+amplitudes.  Inputs are resident in HBM before the timed region.
+
+Default workload: 131,072 macro points, m = 64 ROM modes, Q = 512 ECM points,
+mixed precision (BF16 MFMA with hi/lo split operands, FP32 tangent, FP64
+kinematics / residual / factorisation / condensation).  The same step on the
+plain FP64 path is timed beside it; one JSON line goes to stdout.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16|fp16|fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RVE point-evals/s (m=64,Q=512) mixed vs FP64 at 1e-5 rel; % MFMA roofline"
+PEAK = {"bf16": 2.5e15, "fp16": 2.5e15, "fp64": 78.6e12}
+PREC = {"fp64": 0, "bf16": 1, "fp16": 2}
+
+
+def eval_flops_per_point(m: int, Q: int) -> float:
+    """Algorithmic flops of the evaluation kernel per macro point (FMA = 2):
+    Kaa = G^T (wA) G: 18 Q m^2; T = (wA) G: 162 Q m; kinematics F_q and the
+    residual r: 36 Q m; Neo-Hooke P and A: about 600 per ECM point."""
+    return 18.0 * Q * m * m + 162.0 * Q * m + 36.0 * Q * m + 600.0 * Q
+
+
+def step_flops_per_point(m: int, Q: int) -> float:
+    """Whole step: evaluation + factor/solves (m^3/3 + 20 m^2) + adjoint
+    re-evaluation (F_q, G lambda: 36 Q m; A v and dtheta: ~300 Q)."""
+    return eval_flops_per_point(m, Q) + m ** 3 / 3.0 + 20.0 * m * m + 36.0 * Q * m + 300.0 * Q
+
+
+def read_traffic(kernel_tag: str):
+    """HBM bytes per launch from a committed counter summary, if present."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    return float(m.group(1)) if m else None
+
+
+def build_inputs(N, m, Q, amp, seed):
+    from hrom_inputs import make_cluster, make_macro_points
+    cl = make_cluster(m, Q, seed)
+    F, _, _ = make_macro_points(N, seed + 1, amp=amp)
+    return cl, F
+
+
+def run_gpu(prec_name, cl, F, N, steps, warmup, split=True):
+    import torch
+
+    import paper_2306_02687_amd as P
+    from hrom_inputs import THETA_REF
+    from paper_2306_02687_amd import solve
+
+    plan = P.Plan([solve.upload_cluster(cl, N)], precision=PREC[prec_name], split=split)
+    th = solve.theta_dev(THETA_REF)
+    Fd = solve.points_to_soa(F)
+    st = solve.State(plan)
+    # bring the ROM state near convergence (untimed set-up)
+    for _ in range(2):
+        plan.eval(th, Fd, st.a, st.status)
+        plan.condense(st.Pbar, st.Cbar, st.rnorm, st.status)
+        plan.update(None, st.a, st.status, tol=0.0)
+    g = torch.from_numpy(np.random.default_rng(7).standard_normal((9, N)) * 1e-2).cuda()
+    gF = plan.zeros_points(9)
+    gth = torch.zeros(4, dtype=torch.float64, device="cuda")
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        plan.eval(th, Fd, st.a, st.status)
+        if ev is not None:
+            ev[1].record()
+        plan.condense(st.Pbar, st.Cbar, st.rnorm, st.status)
+        plan.backward(th, st.a, g, gF, gth, st.status)
+        plan.update(None, st.a, st.status, tol=0.0)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    eval_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    # one more forward for the accuracy comparison
+    plan.eval(th, Fd, st.a, st.status)
+    plan.condense(st.Pbar, st.Cbar, st.rnorm, st.status)
+    torch.cuda.synchronize()
+    out = dict(wall=wall, eval_ms=eval_ms, a=st.a.clone(), Pbar=st.Pbar.clone(),
+               Cbar=st.Cbar.clone(), status=int(st.status.max().item()))
+    plan.close()
+    del st
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(cl, F, budget_s=12.0):
+    """The oracle (plain C, OpenMP over points) on a bounded sample of the same
+    workload: per point one evaluate + condense + adjoint backward."""
+    import oracle
+    from hrom_inputs import THETA_REF
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal((F.shape[0], 9)) * 1e-2
+    a = np.zeros((F.shape[0], cl.m))
+    n0 = 32
+    t = time.perf_counter()
+    oracle.backward(cl, THETA_REF, F[:n0], a[:n0], g[:n0])
+    dt = time.perf_counter() - t
+    n = int(min(F.shape[0], max(n0, budget_s / max(dt, 1e-6) * n0)))
+    t = time.perf_counter()
+    oracle.backward(cl, THETA_REF, F[:n], a[:n], g[:n])
+    dt = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return n, dt, threads
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp64"])
+    ap.add_argument("--no-split", action="store_true", help="plain (single-term) low precision")
+    ap.add_argument("--N", type=int, default=131072)
+    ap.add_argument("--m", type=int, default=64)
+    ap.add_argument("--Q", type=int, default=512)
+    ap.add_argument("--amp", type=float, default=0.05)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the hyper-reduced RVE evaluation is "
+              "sharded by macro points across GPUs with no exchange but a 4-value "
+              "theta-gradient all-reduce; no multi-GPU figure is produced here.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    N, m, Q = args.N, args.m, args.Q
+    print(f"[bench] building inputs N={N} m={m} Q={Q}", file=sys.stderr, flush=True)
+    cl, F = build_inputs(N, m, Q, args.amp, 4000)
+
+    split = not args.no_split
+    print(f"[bench] timing {args.precision} (split={split})", file=sys.stderr, flush=True)
+    res = run_gpu(args.precision, cl, F, N, args.steps, args.warmup, split=split)
+    ms_step = res["wall"] / args.steps * 1e3
+    value = N / (ms_step * 1e-3)
+    fl_eval = eval_flops_per_point(m, Q) * N
+    achieved = fl_eval / (res["eval_ms"] * 1e-3)
+    peak = PEAK[args.precision]
+    tag = f"eval_{args.precision}_m{m}_q{Q}"
+    traffic = read_traffic(tag)
+
+    fp64 = None
+    if args.precision != "fp64" and not args.skip_fp64:
+        print("[bench] timing fp64 reference path", file=sys.stderr, flush=True)
+        ref = run_gpu("fp64", cl, F, N, max(2, args.steps // 2), 1)
+        ms64 = ref["wall"] / max(2, args.steps // 2) * 1e3
+        P1, P0 = res["Pbar"].cpu().numpy(), ref["Pbar"].cpu().numpy()
+        C1, C0 = res["Cbar"].cpu().numpy(), ref["Cbar"].cpu().numpy()
+        eP = np.linalg.norm(P1 - P0, axis=0) / np.maximum(np.linalg.norm(P0, axis=0), 1e-300)
+        eC = np.linalg.norm(C1 - C0, axis=0) / np.maximum(np.linalg.norm(C0, axis=0), 1e-300)
+        fp64 = {"value": N / (ms64 * 1e-3), "ms_per_step": ms64, "eval_ms": ref["eval_ms"],
+                "eval_tflops": eval_flops_per_point(m, Q) * N / (ref["eval_ms"] * 1e-3) / 1e12,
+                "eval_frac_of_fp64_peak": eval_flops_per_point(m, Q) * N
+                / (ref["eval_ms"] * 1e-3) / PEAK["fp64"],
+                "speedup_mixed_over_fp64": ms64 / ms_step,
+                "mixed_vs_fp64_rel_err_max": {"Pbar": float(eP.max()), "Cbar": float(eC.max())},
+                "mixed_vs_fp64_rel_err_median": {"Pbar": float(np.median(eP)),
+                                                 "Cbar": float(np.median(eC))}}
+
+    cpu = None
+    if not args.skip_cpu:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        n, dt, thr = cpu_baseline(cl, F)
+        cpu = {"value": n / dt, "unit": "point-evals/s", "cores": thr, "kind": "oracle",
+               "sample": f"{n} of the {N} macro points, one evaluate + condense + adjoint "
+                         f"backward each (plain C, FP64, OpenMP over points)"}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "point-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision if args.precision == "fp64" else
+        f"{args.precision} MFMA{'x3 split' if split else ''} + fp32 tangent + fp64",
+        "data": "synthetic",
+        "config": {"workload": f"hyper-reduced RVE, {N} macro points, m={m} ROM modes, "
+                               f"Q={Q} ECM points, one cluster, strain amplitude {args.amp}",
+                   "N": N, "m": m, "Q": Q, "precision": args.precision, "split": split,
+                   "step": "eval + condense + adjoint backward + update"},
+        "roofline": {"bound": "mfma", "kernel": "evaluation (k_eval)", "achieved": achieved / 1e12,
+                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": traffic, "eval_ms": res["eval_ms"],
+                     "flops_per_point": eval_flops_per_point(m, Q)},
+        "step_tflops": step_flops_per_point(m, Q) * N / (ms_step * 1e-3) / 1e12,
+        "status_max": res["status"],
+        "fp64": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -37,12 +37,13 @@ void free_plan(Plan& p) {
     for (auto& c : p.cl) {
         dfree(c.Ghat);
         dfree(c.GT);
+        dfree(c.Gf);
         dfree(c.w);
         dfree(c.phase);
         dfree(c.Fhi);
         dfree(c.Flo);
     }
-    dfree(p.Fr); dfree(p.polar); dfree(p.Pr); dfree(p.r); dfree(p.Khat); dfree(p.L);
+    dfree(p.Fr); dfree(p.polar); dfree(p.Pr); dfree(p.r); dfree(p.Khat); dfree(p.qs); dfree(p.L);
     dfree(p.piv); dfree(p.y); dfree(p.X); dfree(p.Palg); dfree(p.Cr); dfree(p.S);
     dfree(p.rnorm); dfree(p.dU); dfree(p.gr); dfree(p.Lam); dfree(p.lam); dfree(p.rho);
     dfree(p.hr); dfree(p.gth);
@@ -93,7 +94,7 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
     p.prec = precision;
     p.flags = flags;
     (void)hipGetDevice(&p.device);
-    int64_t off_a = 0, off_kaa = 0, off_kaf = 0, ws_k = 0, ws_L = 0;
+    int64_t off_a = 0, off_kaa = 0, off_kaf = 0, ws_k = 0, ws_L = 0, ws_q = 0;
     int rc = HROM_OK;
     for (int c = 0; c < ncl && rc == HROM_OK; c++) {
         const hrom_cluster& k = clusters[c];
@@ -105,6 +106,7 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
         d.MP = 16 * d.MT;
         d.res_t = (k.m + 9) / 16;
         d.res_c = (k.m + 9) % 16;
+        d.KS = (k.m + 3) / 4;
         d.first = k.first;
         d.count = k.count;
         d.off_a = off_a;
@@ -112,13 +114,16 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
         d.off_kaf = off_kaf;
         d.ws_khat = ws_k;
         d.ws_L = ws_L;
+        d.ws_qs = ws_q;
         off_a += (int64_t)k.m * k.count;
         off_kaa += (int64_t)k.m * k.m * k.count;
         off_kaf += (int64_t)9 * k.m * k.count;
         ws_k += (int64_t)(d.MT * (d.MT + 1) / 2) * 256 * k.count;
         ws_L += (int64_t)k.m * k.m * k.count;
+        ws_q += (int64_t)12 * d.Qpad * k.count;
         rc = dalloc(&d.Ghat, (int64_t)d.Qpad * 9 * d.MP);
         if (rc == HROM_OK) rc = dalloc(&d.GT, (int64_t)d.Qpad * 9 * d.m);
+        if (rc == HROM_OK) rc = dalloc(&d.Gf, (int64_t)d.Qpad * 9 / 16 * d.KS * 64);
         if (rc == HROM_OK) rc = dalloc(&d.w, d.Qpad);
         if (rc == HROM_OK) rc = dalloc(&d.phase, d.Qpad);
         if (rc == HROM_OK && precision != HROM_FP64) {
@@ -130,7 +135,7 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
         LayoutArgs la{};
         la.m = d.m; la.Q = d.Q; la.Qpad = d.Qpad; la.MT = d.MT; la.MP = d.MP; la.prec = precision;
         la.G = k.G; la.w = k.w; la.phase = k.phase;
-        la.Ghat = d.Ghat; la.GT = d.GT; la.wpad = d.w; la.phpad = d.phase; la.Fhi = d.Fhi; la.Flo = d.Flo;
+        la.Ghat = d.Ghat; la.GT = d.GT; la.Gf = d.Gf; la.KS = d.KS; la.wpad = d.w; la.phpad = d.phase; la.Fhi = d.Fhi; la.Flo = d.Flo;
         launch_build_layouts(la, nullptr);
         if (hipDeviceSynchronize() != hipSuccess) rc = HROM_E_HIP;
     }
@@ -139,6 +144,7 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
     p.kaf_len = off_kaf;
     p.khat_len = ws_k;
     p.L_len = ws_L;
+    p.qs_len = ws_q;
     const int64_t n = N;
     if (rc == HROM_OK) rc = dalloc(&p.Fr, 9 * n);
     if (rc == HROM_OK) rc = dalloc(&p.polar, 21 * n);
@@ -147,6 +153,10 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
     if (rc == HROM_OK) {
         if (precision == HROM_FP64) rc = dalloc((double**)&p.Khat, ws_k);
         else rc = dalloc((float**)&p.Khat, ws_k);
+    }
+    if (rc == HROM_OK) {
+        if (precision == HROM_FP64) rc = dalloc((double**)&p.qs, ws_q);
+        else rc = dalloc((float**)&p.qs, ws_q);
     }
     if (rc == HROM_OK) rc = dalloc(&p.L, ws_L);
     if (rc == HROM_OK) rc = dalloc(&p.piv, off_a);
@@ -204,17 +214,20 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
     const size_t tsz = mixed(p) ? sizeof(float) : sizeof(double);
     for (const auto& c : p.cl) {
         EvalArgs e{};
-        e.m = c.m; e.Q = c.Q; e.Qpad = c.Qpad; e.MP = c.MP; e.res_t = c.res_t; e.res_c = c.res_c;
+        e.m = c.m; e.Q = c.Q; e.Qpad = c.Qpad; e.MP = c.MP; e.MT = c.MT; e.KS = c.KS;
         e.first = c.first; e.count = c.count; e.N = p.N;
-        e.Ghat = c.Ghat; e.GT = c.GT; e.w = c.w; e.phase = c.phase; e.Fhi = c.Fhi; e.Flo = c.Flo;
+        e.Ghat = c.Ghat; e.Gf = c.Gf; e.w = c.w; e.phase = c.phase; e.Fhi = c.Fhi; e.Flo = c.Flo;
         e.theta = theta; e.Fr = p.Fr; e.a = a + c.off_a;
+        e.qs = (char*)p.qs + tsz * (size_t)c.ws_qs;
         e.Khat = (char*)p.Khat + tsz * (size_t)c.ws_khat;
         e.r = p.r + c.off_a;
         e.Pr = p.Pr;
         e.status = status;
         e.wscale = wscale_for(c.Q);
-        const int rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, e, stream)
-                                : launch_eval_f64(c.MT, e, stream);
+        int rc = launch_kin(mixed(p) ? 1 : 0, e, stream);
+        if (rc == HROM_OK)
+            rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, e, stream)
+                          : launch_eval_f64(c.MT, e, stream);
         if (rc != HROM_OK) return rc;
     }
     if (Kaa || KaF || KFF) {
@@ -228,7 +241,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
             ca.outKaa = Kaa ? Kaa + c.off_kaa : nullptr;
             ca.outKaF = KaF ? KaF + c.off_kaf : nullptr;
             ca.outKFF = KFF;
-            const int rc = launch_unpack_condense(ca, false, stream);
+            const int rc = launch_unpack_condense(ca, 0, stream);
             if (rc != HROM_OK) return rc;
         }
     }
@@ -255,7 +268,7 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
         ca.y = p.y + c.off_a; ca.X = p.X + 9 * c.off_a;
         ca.Palg = p.Palg; ca.Cr = p.Cr; ca.rnorm = p.rnorm; ca.status = status;
         ca.kscale = mixed(p) ? 1.0f / wscale_for(c.Q) : 1.0f;
-        const int rc = launch_unpack_condense(ca, true, stream);
+        const int rc = launch_unpack_condense(ca, 1, stream);
         if (rc != HROM_OK) return rc;
     }
     PushArgs pa{p.N, (p.flags & HROM_OBJECTIVE) ? 1 : 0, p.polar, p.Palg, p.Cr, Pbar, Cbar, p.S, status};
@@ -339,7 +352,8 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
         BackwardArgs ba{};
         ba.m = c.m; ba.Q = c.Q; ba.Qpad = c.Qpad; ba.mixed = mixed(p); ba.objective = objective;
         ba.first = c.first; ba.count = c.count; ba.N = p.N;
-        ba.GT = c.GT; ba.Ghat = c.Ghat; ba.MP = c.MP; ba.w = c.w; ba.phase = c.phase;
+        ba.GT = c.GT; ba.Ghat = c.Ghat; ba.Gf = c.Gf; ba.MP = c.MP; ba.MT = c.MT; ba.KS = c.KS;
+        ba.w = c.w; ba.phase = c.phase;
         ba.theta = theta; ba.Fr = p.Fr; ba.a = a + c.off_a; ba.lam = p.lam + c.off_a;
         ba.gr = p.gr; ba.hr = p.hr; ba.gth = p.gth; ba.rho = p.rho + c.off_a; ba.status = status;
         if (mixed(p)) {
@@ -347,13 +361,13 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
             // rho = KaF g_r - Kaa lambda with the accurate (FP32-tangent) operator,
             // corrected with the factor of the low-precision Kaa
             ba.with_rho = 1;
-            launch_backward_q(ba, stream);
+            launch_backward_b(ba, stream);
             RefineArgs ra{c.m, c.first, c.count, p.L + c.ws_L, p.piv + c.off_a, status,
                           p.rho + c.off_a, p.lam + c.off_a};
             launch_refine_lambda(ra, stream);
         }
         ba.with_rho = 0;
-        launch_backward_q(ba, stream);
+        launch_backward_b(ba, stream);
     }
     launch_bw_pushforward(bp, stream);
     launch_reduce_theta(p.N, p.gth, gtheta, stream);

@@ -26,8 +26,11 @@ struct ClusterDev {
     int64_t off_a, off_kaa, off_kaf;   // offsets in caller mode-indexed arrays
     int64_t ws_khat;       // element offset of the cluster's tile workspace
     int64_t ws_L;          // element offset of the cluster's factor workspace
+    int64_t ws_qs;         // element offset of the cluster's per-ECM-point scalars
     double* Ghat;          // [Qpad][9][MP]  augmented [G | I_9 | 0] (FP64)
     double* GT;            // [Qpad/64][9][m][64]  G, ECM point fastest (FP64)
+    double* Gf;            // [9 Qpad/16][KS][64]  A-operand fragments of the kinematics GEMM
+    int KS;                // ceil(m / 4) k-steps of the kinematics GEMM
     double* w;             // [Qpad] (zero padded)
     int* phase;            // [Qpad]
     uint16_t* Fhi;         // [Qpad][MT][64][4] low-precision fragments of Ghat (hi part)
@@ -48,6 +51,7 @@ struct Plan {
     double* Pr = nullptr;      // [9][N]
     double* r = nullptr;       // mode-indexed [m][count] blocks
     void* Khat = nullptr;      // per-cluster tile blocks (double or float)
+    void* qs = nullptr;        // per-cluster [count][Qpad][12] tangent scalars (double or float)
     double* L = nullptr;       // per-cluster [count][m][m] factor
     int* piv = nullptr;        // per-cluster [count][m] pivots (LU fallback)
     double* y = nullptr;       // mode-indexed
@@ -63,7 +67,7 @@ struct Plan {
     double* rho = nullptr;     // mode-indexed: refinement residual
     double* hr = nullptr;      // [9][N]
     double* gth = nullptr;     // [4][N] per-point theta gradients
-    int64_t khat_len = 0, L_len = 0;
+    int64_t khat_len = 0, L_len = 0, qs_len = 0;
     int stage = 0;             // 0 = nothing, 1 = evaluated, 2 = condensed
 };
 
@@ -79,10 +83,10 @@ struct PointArgs {
 void launch_prepare(const PointArgs& a, hipStream_t s);
 
 struct EvalArgs {
-    int m, Q, Qpad, MP, res_t, res_c;
+    int m, Q, Qpad, MP, MT, KS;
     int64_t first, count, N;
     const double* Ghat;
-    const double* GT;
+    const double* Gf;      // kinematics-GEMM fragments [9 Qpad / 16][KS][64]
     const double* w;
     const int* phase;
     const uint16_t* Fhi;
@@ -90,12 +94,14 @@ struct EvalArgs {
     const double* theta;
     const double* Fr;
     const double* a;       // cluster block [m][count]
+    void* qs;              // cluster block [count][Qpad][12] per-ECM-point tangent scalars
     void* Khat;            // cluster block [count][ntiles][256]
     double* r;             // cluster block [m][count]
     double* Pr;            // [9][N]
     int* status;           // [N]
     float wscale;          // mixed: power-of-two scaling of w_q A_q
 };
+int launch_kin(int mixed, const EvalArgs& a, hipStream_t s);
 int launch_eval_f64(int MT, const EvalArgs& a, hipStream_t s);
 int launch_eval_mixed(int MT, int prec, bool split, const EvalArgs& a, hipStream_t s);
 
@@ -120,7 +126,7 @@ struct CondenseArgs {
     double* outKaF;        // [m*9][count]
     double* outKFF;        // [81][N]
 };
-int launch_unpack_condense(const CondenseArgs& a, bool condense, hipStream_t s);
+int launch_unpack_condense(const CondenseArgs& a, int mode, hipStream_t s);
 
 struct PushArgs {
     int64_t N;
@@ -157,7 +163,8 @@ struct BackwardArgs {
     int64_t first, count, N;
     const double* GT;
     const double* Ghat;
-    int MP;
+    const double* Gf;
+    int MP, MT, KS;
     const double* w;
     const int* phase;
     const double* theta;
@@ -170,7 +177,7 @@ struct BackwardArgs {
     double* rho;           // cluster block (refinement residual) or null
     int* status;
 };
-int launch_backward_q(const BackwardArgs& a, hipStream_t s);
+int launch_backward_b(const BackwardArgs& a, hipStream_t s);
 
 struct BwPointArgs {
     int64_t N;
@@ -218,6 +225,8 @@ struct LayoutArgs {
     const int* phase;
     double* Ghat;
     double* GT;
+    double* Gf;
+    int KS;
     double* wpad;
     int* phpad;
     uint16_t* Fhi;

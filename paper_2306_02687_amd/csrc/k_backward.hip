@@ -7,14 +7,11 @@
 // for the phase p of q.  Optionally the refinement residual
 //   rho = sum_q G_q^T (w_q A_q v_q)  (= KaF g_r - Kaa lambda)
 // of the adjoint system is accumulated with the same operator.
-// One wavefront per macro point, lane = ECM point.
 #include <hip/hip_runtime.h>
 
 #include "hrom_internal.h"
 
 namespace hrom {
-
-static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // (A : v)_ij = mu v_ij + (mu - lam ln J) (Fi v Fi)_ji + lam Fi_ji tr(Fi v)
 template <typename T>
@@ -39,25 +36,40 @@ __device__ __forceinline__ void nh_apply(const T* Fi, T mu, T la, T ell, const T
             Av[3 * i + j] = mu * v[3 * i + j] + cm * FVF[3 * j + i] + la * Fi[3 * j + i] * tr;
 }
 
-__global__ void __launch_bounds__(256) k_backward_q(BackwardArgs A) {
-    __shared__ double s_a[4][kMaxModes];
-    __shared__ double s_l[4][kMaxModes];
-    __shared__ double s_v[4][9 * 64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int64_t pl = (int64_t)blockIdx.x * 4 + wave;
-    const bool valid = pl < A.count;
-    if (!valid) pl = A.count - 1;
-    const int64_t b = A.first + pl;
-    const int m = A.m;
-    for (int k = lane; k < m; k += 64) {
-        s_a[wave][k] = A.a[(int64_t)k * A.count + pl];
-        s_l[wave][k] = A.lam[(int64_t)k * A.count + pl];
+
+
+// Point-batched form of the adjoint re-evaluation: sixteen macro points per
+// workgroup; F_q - Fr = G a and G lambda are two GEMMs with the cluster's G
+// as the shared operand (FP64 MFMA, N = the 16 points); the law and its
+// adjoint run one (point, ECM point) pair per thread; the refinement
+// residual rho = G^T (w A v) is a third FP64 GEMM.  Per-point sums over the
+// ECM points (h_r, dL/dtheta) reduce in a fixed order.
+__global__ void __launch_bounds__(256) k_backward_b(BackwardArgs A) {
+    constexpr int PT = 16, QC = 16, LD = 17;
+    __shared__ double sA[kMaxModes + 4][PT];
+    __shared__ double sL[kMaxModes + 4][PT];
+    __shared__ double sF[QC * 9][LD];
+    __shared__ double sV[QC * 9][LD];
+    __shared__ double sU[9][PT];
+    __shared__ double sG[9][PT];
+    __shared__ int sbits[PT];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const int m = A.m, KS = A.KS, MP = A.MP, MT = A.MT;
+    const int64_t p0 = (int64_t)blockIdx.x * PT;
+    const int np = (int)min((int64_t)PT, A.count - p0);
+    if (tid < PT) sbits[tid] = 0;
+    for (int e = tid; e < 4 * KS * PT; e += 256) {
+        const int k = e / PT, p = e % PT;
+        const bool in = (k < m && p < np);
+        sA[k][p] = in ? A.a[(int64_t)k * A.count + p0 + p] : 0.0;
+        sL[k][p] = in ? A.lam[(int64_t)k * A.count + p0 + p] : 0.0;
     }
-    double Fr[9], gr[9];
-#pragma unroll
-    for (int I = 0; I < 9; I++) {
-        Fr[I] = A.Fr[I * A.N + b];
-        gr[I] = A.gr[I * A.N + b];
+    for (int e = tid; e < 9 * PT; e += 256) {
+        const int I = e / PT, p = e % PT;
+        const int64_t b = A.first + p0 + p;
+        sU[I][p] = (p < np) ? A.Fr[(int64_t)I * A.N + b] : ((I % 4 == 0) ? 1.0 : 0.0);
+        sG[I][p] = (p < np) ? A.gr[(int64_t)I * A.N + b] : 0.0;
     }
     const double mu0 = A.theta[0], la0 = A.theta[1], mu1 = A.theta[2], la1 = A.theta[3];
     double h[9], gt[4];
@@ -65,129 +77,178 @@ __global__ void __launch_bounds__(256) k_backward_q(BackwardArgs A) {
     for (int I = 0; I < 9; I++) h[I] = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; i++) gt[i] = 0.0;
-    double rho0 = 0.0, rho1 = 0.0;
-    int bits = 0;
-    __syncthreads();
-    for (int q0 = 0; q0 < A.Qpad; q0 += 64) {
-        const int q = q0 + lane;
-        double F[9], v[9];
+    v4d racc[8];
 #pragma unroll
-        for (int I = 0; I < 9; I++) {
-            F[I] = Fr[I];
-            v[I] = gr[I];
+    for (int t = 0; t < 8; t++) racc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+
+    for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
+        double gr[9][8];
+        if (A.with_rho) {
+            const double* gh = A.Ghat + (int64_t)(q0 * 9 + 36 * wave + g) * MP + c;
+#pragma unroll
+            for (int j = 0; j < 9; j++)
+#pragma unroll
+                for (int t = 0; t < 8; t++)
+                    if (t < MT) gr[j][t] = gh[(int64_t)(4 * j) * MP + 16 * t];
         }
-        const double* gt_ = A.GT + (int64_t)(q0 >> 6) * 9 * m * 64 + lane;
-        for (int k = 0; k < m; k++) {
-            const double ak = s_a[wave][k], lk = s_l[wave][k];
+        const int rt0 = (q0 / 16) * 9;
+        for (int t = wave; t < 9; t += 4) {
+            const double* gf = A.Gf + ((int64_t)(rt0 + t) * KS) * 64 + lane;
+            double af[24];
+#pragma unroll
+            for (int s2 = 0; s2 < 24; s2++)
+                if (s2 < KS) af[s2] = gf[(int64_t)s2 * 64];
+            v4d accF = v4d{0.0, 0.0, 0.0, 0.0}, accL = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s2 = 0; s2 < 24; s2++)
+                if (s2 < KS) {
+                    accF = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][c], accF, 0, 0, 0);
+                    accL = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sL[4 * s2 + g][c], accL, 0, 0, 0);
+                }
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int row = 16 * t + g + 4 * e;
+                sF[row][c] = accF[e] + sU[row % 9][c];
+                sV[row][c] = sG[row % 9][c] - accL[e];
+            }
+        }
+        __syncthreads();
+        {
+            const int p = tid >> 4, qq = tid & 15, q = q0 + qq;
+            double F[9], v[9];
 #pragma unroll
             for (int I = 0; I < 9; I++) {
-                const double gv = gt_[(int64_t)(I * m + k) * 64];
-                F[I] = fma(ak, gv, F[I]);
-                v[I] = fma(-lk, gv, v[I]);
+                F[I] = sF[qq * 9 + I][p];
+                v[I] = sV[qq * 9 + I][p];
+            }
+            const double wq = A.w[q];
+            const int ph = A.phase[q];
+            const double mu = ph ? mu1 : mu0, la = ph ? la1 : la0;
+            double Fi[9];
+            const double c00 = F[4] * F[8] - F[5] * F[7];
+            const double c01 = F[5] * F[6] - F[3] * F[8];
+            const double c02 = F[3] * F[7] - F[4] * F[6];
+            const double J = F[0] * c00 + F[1] * c01 + F[2] * c02;
+            {
+                const double id = 1.0 / J;
+                Fi[0] = c00 * id;
+                Fi[3] = c01 * id;
+                Fi[6] = c02 * id;
+                Fi[1] = (F[2] * F[7] - F[1] * F[8]) * id;
+                Fi[4] = (F[0] * F[8] - F[2] * F[6]) * id;
+                Fi[7] = (F[1] * F[6] - F[0] * F[7]) * id;
+                Fi[2] = (F[1] * F[5] - F[2] * F[4]) * id;
+                Fi[5] = (F[2] * F[3] - F[0] * F[5]) * id;
+                Fi[8] = (F[0] * F[4] - F[1] * F[3]) * id;
+            }
+            const bool live = (q < A.Q) && (p < np);
+            const bool ok = live && (J > 0.0);
+            if (live && !(J > 0.0)) atomicOr(&sbits[p], HROM_PT_JNONPOS);
+            const double ell = ok ? log(J) : 0.0;
+            double Av[9];
+            if (A.mixed) {
+                float Fif[9], vf[9], Avf[9];
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    Fif[k] = (float)Fi[k];
+                    vf[k] = (float)v[k];
+                }
+                nh_apply<float>(Fif, (float)mu, (float)la, (float)ell, vf, Avf);
+#pragma unroll
+                for (int k = 0; k < 9; k++) Av[k] = (double)Avf[k];
+            } else {
+                nh_apply<double>(Fi, mu, la, ell, v, Av);
+            }
+            const double wo = ok ? wq : 0.0;
+            double dmu = 0.0, dla = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    dmu = fma(v[3 * i + j], F[3 * i + j] - Fi[3 * j + i], dmu);
+                    dla = fma(v[3 * i + j], ell * Fi[3 * j + i], dla);
+                }
+#pragma unroll
+            for (int I = 0; I < 9; I++) h[I] = fma(wo, Av[I], h[I]);
+            const double wm = ph ? 0.0 : wo, wi = ph ? wo : 0.0;
+            gt[0] = fma(wm, dmu, gt[0]);
+            gt[1] = fma(wm, dla, gt[1]);
+            gt[2] = fma(wi, dmu, gt[2]);
+            gt[3] = fma(wi, dla, gt[3]);
+            if (A.with_rho) {
+#pragma unroll
+                for (int I = 0; I < 9; I++) sV[qq * 9 + I][p] = wo * Av[I];
             }
         }
-        const double wq = A.w[q];
-        const int p = A.phase[q];
-        const double mu = p ? mu1 : mu0, la = p ? la1 : la0;
-        const double c00 = F[4] * F[8] - F[5] * F[7];
-        const double c01 = F[5] * F[6] - F[3] * F[8];
-        const double c02 = F[3] * F[7] - F[4] * F[6];
-        const double J = F[0] * c00 + F[1] * c01 + F[2] * c02;
-        const bool ok = (q < A.Q) && (J > 0.0);
-        if (q < A.Q && !(J > 0.0)) bits |= HROM_PT_JNONPOS;
-        double Fi[9];
-        {
-            const double id = 1.0 / J;
-            Fi[0] = c00 * id;
-            Fi[3] = c01 * id;
-            Fi[6] = c02 * id;
-            Fi[1] = (F[2] * F[7] - F[1] * F[8]) * id;
-            Fi[4] = (F[0] * F[8] - F[2] * F[6]) * id;
-            Fi[7] = (F[1] * F[6] - F[0] * F[7]) * id;
-            Fi[2] = (F[1] * F[5] - F[2] * F[4]) * id;
-            Fi[5] = (F[2] * F[3] - F[0] * F[5]) * id;
-            Fi[8] = (F[0] * F[4] - F[1] * F[3]) * id;
-        }
-        const double ell = ok ? log(J) : 0.0;
-        double Av[9];
-        if (A.mixed) {
-            float Fif[9], vf[9], Avf[9];
-#pragma unroll
-            for (int k = 0; k < 9; k++) {
-                Fif[k] = (float)Fi[k];
-                vf[k] = (float)v[k];
-            }
-            nh_apply<float>(Fif, (float)mu, (float)la, (float)ell, vf, Avf);
-#pragma unroll
-            for (int k = 0; k < 9; k++) Av[k] = (double)Avf[k];
-        } else {
-            nh_apply<double>(Fi, mu, la, ell, v, Av);
-        }
-        double dmu = 0.0, dla = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                dmu = fma(v[3 * i + j], F[3 * i + j] - Fi[3 * j + i], dmu);
-                dla = fma(v[3 * i + j], ell * Fi[3 * j + i], dla);
-            }
-        const double wo = ok ? wq : 0.0;
-#pragma unroll
-        for (int I = 0; I < 9; I++) h[I] = fma(wo, Av[I], h[I]);
-        const double wm = p ? 0.0 : wo, wi = p ? wo : 0.0;
-        gt[0] = fma(wm, dmu, gt[0]);
-        gt[1] = fma(wm, dla, gt[1]);
-        gt[2] = fma(wi, dmu, gt[2]);
-        gt[3] = fma(wi, dla, gt[3]);
+        __syncthreads();
         if (A.with_rho) {
 #pragma unroll
-            for (int I = 0; I < 9; I++) s_v[wave][I * 64 + lane] = wo * Av[I];
-            __syncthreads();
-            const double* gh = A.Ghat + (int64_t)q0 * 9 * A.MP;
-            for (int qq = 0; qq < 64; qq++) {
+            for (int j = 0; j < 9; j++) {
+                const double bv = sV[36 * wave + 4 * j + g][c];
 #pragma unroll
-                for (int I = 0; I < 9; I++) {
-                    const double sv = s_v[wave][I * 64 + qq];
-                    const double* row = gh + (int64_t)(qq * 9 + I) * A.MP;
-                    if (lane < m) rho0 = fma(sv, row[lane], rho0);
-                    if (lane + 64 < m) rho1 = fma(sv, row[lane + 64], rho1);
-                }
+                for (int t = 0; t < 8; t++)
+                    if (t < MT) racc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gr[j][t], bv, racc[t], 0, 0, 0);
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
+    // per-point sums over the 16 threads of the point (lanes 16p' .. 16p'+15
+    // of a wave hold point p = tid >> 4): fixed butterfly within 16 lanes
 #pragma unroll
     for (int I = 0; I < 9; I++)
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) h[I] += __shfl_xor(h[I], off);
+        for (int off = 8; off > 0; off >>= 1) h[I] += __shfl_xor(h[I], off);
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) gt[i] += __shfl_xor(gt[i], off);
-    const uint64_t bad = __ballot(bits);
-    if (!valid) return;
-    const bool failed = (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) || bad;
-    if (lane < 9) {
-        double v = 0.0;
+        for (int off = 8; off > 0; off >>= 1) gt[i] += __shfl_xor(gt[i], off);
+    {
+        const int p = tid >> 4, sub = tid & 15;
+        if (p < np) {
+            const int64_t b = A.first + p0 + p;
+            const bool failed = (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) || sbits[p];
+            double v = 0.0;
 #pragma unroll
-        for (int I = 0; I < 9; I++) v = (lane == I) ? h[I] : v;
-        A.hr[(int64_t)lane * A.N + b] = failed ? 0.0 : v;
-    }
-    if (lane < 4) {
-        double v = 0.0;
+            for (int I = 0; I < 9; I++) v = (sub == I) ? h[I] : v;
+            if (sub < 9) A.hr[(int64_t)sub * A.N + b] = failed ? 0.0 : v;
+            double u = 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; i++) v = (lane == i) ? gt[i] : v;
-        A.gth[(int64_t)lane * A.N + b] = failed ? 0.0 : v;
+            for (int i = 0; i < 4; i++) u = (sub == 9 + i) ? gt[i] : u;
+            if (sub >= 9 && sub < 13) A.gth[(int64_t)(sub - 9) * A.N + b] = failed ? 0.0 : u;
+        }
     }
     if (A.with_rho) {
-        if (lane < m) A.rho[(int64_t)lane * A.count + pl] = failed ? 0.0 : rho0;
-        if (lane + 64 < m) A.rho[(int64_t)(lane + 64) * A.count + pl] = failed ? 0.0 : rho1;
+        double* red = &sF[0][0];
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            if (t >= MT) break;
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 4; e++) red[(wave * 16 + g + 4 * e) * 16 + c] = racc[t][e];
+            __syncthreads();
+            if (wave == 0) {
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int rr = g + 4 * e;
+                    const double v = ((red[(0 * 16 + rr) * 16 + c] + red[(1 * 16 + rr) * 16 + c]) +
+                                      red[(2 * 16 + rr) * 16 + c]) + red[(3 * 16 + rr) * 16 + c];
+                    const int row = 16 * t + rr;
+                    if (c < np && row < m) {
+                        const bool failed = sbits[c] != 0;
+                        A.rho[(int64_t)row * A.count + p0 + c] = failed ? 0.0 : v;
+                    }
+                }
+            }
+        }
     }
-    if (lane == 0 && bad) A.status[b] |= HROM_PT_JNONPOS;
+    __syncthreads();
+    if (tid < np && sbits[tid]) A.status[A.first + p0 + tid] |= HROM_PT_JNONPOS;
 }
 
-int launch_backward_q(const BackwardArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_backward_q, dim3(nblocks(a.count, 4)), dim3(256), 0, s, a);
+int launch_backward_b(const BackwardArgs& a, hipStream_t s) {
+    if (a.MT > 8) return HROM_E_UNSUPPORTED;
+    hipLaunchKernelGGL(k_backward_b, dim3((unsigned)((a.count + 15) / 16)), dim3(256), 0, s, a);
     return HROM_OK;
 }
 

@@ -26,7 +26,7 @@ struct CondLds {
 };
 
 static size_t cond_lds_bytes(int m) {
-    return sizeof(double) * ((size_t)m * (m + 1) + 9 * m + 81 + 10 * m + 9 + m);
+    return sizeof(double) * ((size_t)m * (m + 1) + 9 * m + 81 + 10 * m + 9 + m + 1);
 }
 
 // Row of accumulator element e held by lane group g inside a 16x16 tile:
@@ -68,12 +68,17 @@ __device__ void unpack_tiles(const CondenseArgs& A, const TT* kh, CondLds& S, bo
         }
 }
 
+// mode 0: export the raw blocks; 1: full condensation (Cholesky, LU on a
+// non-positive pivot); 2: LU condensation of the points already flagged
+// HROM_PT_NOT_SPD by the register kernel, every other point is skipped.
 template <typename TT>
-__global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int do_condense) {
+__global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int mode) {
     extern __shared__ double sm[];
     const int m = A.m, lane = threadIdx.x;
     const int64_t pl = blockIdx.x;
     const int64_t b = A.first + pl;
+    if (mode == 2 && !(A.status[b] & HROM_PT_NOT_SPD)) return;
+    const int do_condense = mode;
     const int MT = A.MT, NT = MT * (MT + 1) / 2;
     CondLds S(sm, m);
     const TT* kh = (const TT*)A.Khat + (int64_t)pl * NT * 256;
@@ -102,26 +107,46 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int do_c
     }
     __syncthreads();
 
-    // ------------------------------------------------ Cholesky, right-looking
-    bool spd = true;
-    for (int j = 0; j < m; j++) {
-        const double d = S.K[j * S.ld + j];
+    // ------------------------------------------------ Cholesky, left-looking
+    // column j: s_i = K[i][j] - sum_{k<j} L[i][k] L[j][k] for every row i >= j
+    // (independent loads, four partial sums), pivot d = s_j, L[j][j] = sqrt(d),
+    // L[i][j] = s_i / L[j][j].
+    bool spd = (mode != 2);
+    double* piv_d = S.rv + m;   // one broadcast slot after the residual copy
+    for (int j = 0; j < m && spd; j++) {
+        double sv[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int i = lane + 64 * h;
+            sv[h] = 0.0;
+            if (i < m && i >= j) {
+                const double* Li = S.K + i * S.ld;
+                const double* Lj = S.K + j * S.ld;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int k = 0;
+                for (; k + 4 <= j; k += 4) {
+                    a0 = fma(Li[k], Lj[k], a0);
+                    a1 = fma(Li[k + 1], Lj[k + 1], a1);
+                    a2 = fma(Li[k + 2], Lj[k + 2], a2);
+                    a3 = fma(Li[k + 3], Lj[k + 3], a3);
+                }
+                for (; k < j; k++) a0 = fma(Li[k], Lj[k], a0);
+                sv[h] = Li[j] - ((a0 + a1) + (a2 + a3));
+            }
+        }
+        if (lane == (j & 63)) piv_d[0] = sv[j >> 6];
+        __syncthreads();
+        const double d = piv_d[0];
         if (!(d > 0.0)) {
             spd = false;
             break;
         }
         const double sd = sqrt(d);
-        __syncthreads();
-        for (int i = lane; i < m; i += 64) {
-            if (i > j) S.K[i * S.ld + j] = S.K[i * S.ld + j] / sd;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int i = lane + 64 * h;
+            if (i < m && i > j) S.K[i * S.ld + j] = sv[h] / sd;
             else if (i == j) S.K[j * S.ld + j] = sd;
-        }
-        __syncthreads();
-        for (int i = lane; i < m; i += 64) {
-            if (i > j) {
-                const double lij = S.K[i * S.ld + j];
-                for (int k = j + 1; k <= i; k++) S.K[i * S.ld + k] -= lij * S.K[k * S.ld + j];
-            }
         }
         __syncthreads();
     }
@@ -293,7 +318,7 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int do_c
     }
 }
 
-int launch_unpack_condense(const CondenseArgs& a, bool condense, hipStream_t s) {
+int launch_unpack_condense(const CondenseArgs& a, int mode, hipStream_t s) {
     const size_t bytes = cond_lds_bytes(a.m);
     if (bytes > 160 * 1024) return HROM_E_UNSUPPORTED;
     const dim3 grid((unsigned)a.count), block(64);
@@ -304,7 +329,7 @@ int launch_unpack_condense(const CondenseArgs& a, bool condense, hipStream_t s) 
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
-        hipLaunchKernelGGL(k_unpack_condense<float>, grid, block, bytes, s, a, (int)condense);
+        hipLaunchKernelGGL(k_unpack_condense<float>, grid, block, bytes, s, a, mode);
     } else {
         static bool attr = false;
         if (!attr) {
@@ -312,7 +337,7 @@ int launch_unpack_condense(const CondenseArgs& a, bool condense, hipStream_t s) 
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
-        hipLaunchKernelGGL(k_unpack_condense<double>, grid, block, bytes, s, a, (int)condense);
+        hipLaunchKernelGGL(k_unpack_condense<double>, grid, block, bytes, s, a, mode);
     }
     return HROM_OK;
 }
@@ -395,3 +420,4 @@ void launch_refine_lambda(const RefineArgs& a, hipStream_t s) {
 }
 
 }  // namespace hrom
+

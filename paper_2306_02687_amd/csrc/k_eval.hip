@@ -1,21 +1,20 @@
 // Evaluation of the hyper-reduced RVE at every macro point (Sec. 3.2.1 and
-// 3.3): per ECM point q the reduced kinematics F_q = Fr + sum_m a_m G_qm, the
-// Neo-Hooke stress P_q and tangent A_q, and the ECM sums
-//   Khat = sum_q Ghat_q^T (w_q A_q) Ghat_q,   Ghat_q = [G_q | I_9 | 0]
-// whose blocks are Kaa (modes x modes), KaF (modes x macro), KFF
-// (macro x macro); the FP64 kernel also carries the column w_q P_q, giving
-// the residual r and the homogenised stress Pr in the same contraction.
+// 3.3), in two kernels.
 //
-// Work layout: a workgroup of 4 wavefronts evaluates 4 macro points of one
-// cluster, one point per wavefront.  Each wavefront loops over the ECM points
-// in chunks of 64:
-//   phase A (lane = ECM point): kinematics and material law, with G read in
-//            the [chunk][9][m][64] layout (coalesced); per-point scalars of
-//            the tangent go to LDS;
-//   phase B (MFMA): the contraction over k = (ECM point, tensor row), into
-//            upper-triangular 16x16 tiles of Khat held in registers.
-// G (shared by every point of the cluster) is streamed from L2; nothing of
-// size Q leaves the chip.
+// k_kin -- kinematics, material law and residual, sixteen macro points per
+// workgroup.  The reduced kinematics F_q - Fr = sum_m a_m G_qm of all points
+// of the workgroup is one GEMM with the cluster's G as the shared operand
+// (rows: ECM point x tensor row, K: modes, N: the 16 points) on FP64 MFMA;
+// the Neo-Hooke stress P_q runs one (point, ECM point) pair per thread; the
+// residual and homogenised stress rhat = Ghat^T (w P) = [r; Pr] is a second
+// FP64 GEMM (K: ECM point x tensor row).  The tangent of every ECM point
+// leaves as 12 scalars (F_q^{-1}, w mu, w (mu - lam ln J), w lam).
+//
+// k_eval_f64 / k_eval_mixed -- the tangent contraction
+//   Khat = sum_q Ghat_q^T (w_q A_q) Ghat_q,   Ghat_q = [G_q | I_9 | 0],
+// whose blocks are Kaa, KaF and KFF, one macro point per wavefront, four per
+// workgroup, accumulated over the ECM points into upper-triangular 16x16
+// tiles held in registers.
 #include <hip/hip_runtime.h>
 
 #include "hrom_internal.h"
@@ -58,10 +57,175 @@ __device__ __forceinline__ void tangent_row(const T* Fi, T c0, T c1, T c2, T* W)
         }
 }
 
+
+// ============================================================== kinematics
+template <bool MIXED>
+__global__ void __launch_bounds__(256) k_kin(EvalArgs A) {
+    constexpr int PT = 16, QC = 16, LD = 17;
+    __shared__ double sA[kMaxModes + 4][PT];
+    __shared__ double sF[QC * 9][LD];
+    __shared__ double sWP[QC * 9][LD];
+    __shared__ double sU[9][PT];
+    __shared__ int sbits[PT];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const int m = A.m, KS = A.KS, MP = A.MP, MT = A.MT;
+    const int64_t p0 = (int64_t)blockIdx.x * PT;
+    const int np = (int)min((int64_t)PT, A.count - p0);
+    if (tid < PT) sbits[tid] = 0;
+    __syncthreads();
+    for (int e = tid; e < 4 * KS * PT; e += 256) {
+        const int k = e / PT, p = e % PT;
+        double v = 0.0;
+        if (k < m && p < np) {
+            v = A.a[(int64_t)k * A.count + p0 + p];
+            if (!isfinite(v)) {
+                atomicOr(&sbits[p], HROM_PT_NONFINITE);
+                v = 0.0;
+            }
+        }
+        sA[k][p] = v;
+    }
+    for (int e = tid; e < 9 * PT; e += 256) {
+        const int I = e / PT, p = e % PT;
+        sU[I][p] = (p < np) ? A.Fr[(int64_t)I * A.N + A.first + p0 + p] : ((I % 4 == 0) ? 1.0 : 0.0);
+    }
+    const double mu0 = A.theta[0], la0 = A.theta[1], mu1 = A.theta[2], la1 = A.theta[3];
+    // rhat partial sums: wave w takes k-steps 9w .. 9w+8 of every chunk, all tiles
+    v4d racc[8];
+#pragma unroll
+    for (int t = 0; t < 8; t++) racc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+
+    for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
+        // operands of this chunk's residual GEMM, issued first so that their
+        // latency hides behind the kinematics GEMM and the material law
+        double gr[9][8];
+        {
+            const double* gh = A.Ghat + (int64_t)(q0 * 9 + 36 * wave + g) * MP + c;
+#pragma unroll
+            for (int j = 0; j < 9; j++)
+#pragma unroll
+                for (int t = 0; t < 8; t++)
+                    if (t < MT) gr[j][t] = gh[(int64_t)(4 * j) * MP + 16 * t];
+        }
+        // F - Fr for the 16 points and the 16 ECM points of the chunk: 9 row tiles
+        const int rt0 = (q0 / 16) * 9;
+        for (int t = wave; t < 9; t += 4) {
+            const double* gf = A.Gf + ((int64_t)(rt0 + t) * KS) * 64 + lane;
+            double af[24];
+#pragma unroll
+            for (int s2 = 0; s2 < 24; s2++)
+                if (s2 < KS) af[s2] = gf[(int64_t)s2 * 64];
+            v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s2 = 0; s2 < 24; s2++)
+                if (s2 < KS)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][c], acc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int row = 16 * t + g + 4 * e;   // FP64 MFMA accumulator rows interleave
+                sF[row][c] = acc[e] + sU[row % 9][c];
+            }
+        }
+        __syncthreads();
+        // material law: thread = (point p, ECM point q0 + qq)
+        {
+            const int p = tid >> 4, qq = tid & 15, q = q0 + qq;
+            double F[9];
+#pragma unroll
+            for (int I = 0; I < 9; I++) F[I] = sF[qq * 9 + I][p];
+            const double wq = A.w[q];
+            const int ph = A.phase[q];
+            const double mu = ph ? mu1 : mu0, la = ph ? la1 : la0;
+            double Fi[9];
+            const double J = inv3d(F, Fi);
+            const bool live = (q < A.Q) && (p < np);
+            const bool ok = live && (J > 0.0);
+            if (live && !(J > 0.0)) atomicOr(&sbits[p], HROM_PT_JNONPOS);
+            const double ell = ok ? log(J) : 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++)
+                    sWP[qq * 9 + 3 * i + j][p] =
+                        ok ? wq * (mu * (F[3 * i + j] - Fi[3 * j + i]) + la * ell * Fi[3 * j + i]) : 0.0;
+            if (p < np) {
+                const double c0 = ok ? wq * mu : 0.0;
+                const double c1 = ok ? wq * (mu - la * ell) : 0.0;
+                const double c2 = ok ? wq * la : 0.0;
+                const int64_t off = ((p0 + p) * A.Qpad + q) * 12;
+                if (MIXED) {
+                    const float ws = A.wscale;
+                    float* o = (float*)A.qs + off;
+                    v4f v0 = v4f{(float)Fi[0], (float)Fi[1], (float)Fi[2], (float)Fi[3]};
+                    v4f v1 = v4f{(float)Fi[4], (float)Fi[5], (float)Fi[6], (float)Fi[7]};
+                    v4f v2 = v4f{(float)Fi[8], (float)c0 * ws, (float)c1 * ws, (float)c2 * ws};
+                    if (!ok) v0 = v1 = v2 = v4f{0.f, 0.f, 0.f, 0.f};
+                    *(v4f*)(o) = v0;
+                    *(v4f*)(o + 4) = v1;
+                    *(v4f*)(o + 8) = v2;
+                } else {
+                    double* o = (double*)A.qs + off;
+#pragma unroll
+                    for (int k = 0; k < 9; k++) o[k] = ok ? Fi[k] : 0.0;
+                    o[9] = c0;
+                    o[10] = c1;
+                    o[11] = c2;
+                }
+            }
+        }
+        __syncthreads();
+        // rhat += Ghat^T (w P): this wave's 9 k-steps of the chunk
+#pragma unroll
+        for (int j = 0; j < 9; j++) {
+            const double bv = sWP[36 * wave + 4 * j + g][c];
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                if (t < MT) racc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gr[j][t], bv, racc[t], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // fixed-order sum of the four waves' partial rhat, through LDS (sF reused:
+    // [wave][tile rows][point] would need 4 x 128 x 16 doubles, so the sum runs
+    // tile by tile)
+    double* red = &sF[0][0];
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+        if (t >= MT) break;
+#pragma unroll
+        for (int e = 0; e < 4; e++) red[(wave * 16 + g + 4 * e) * 16 + c] = racc[t][e];
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int rr = g + 4 * e;
+                const double v = ((red[(0 * 16 + rr) * 16 + c] + red[(1 * 16 + rr) * 16 + c]) +
+                                  red[(2 * 16 + rr) * 16 + c]) + red[(3 * 16 + rr) * 16 + c];
+                const int row = 16 * t + rr;
+                if (c < np) {
+                    if (row < m) A.r[(int64_t)row * A.count + p0 + c] = v;
+                    else if (row < m + 9) A.Pr[(int64_t)(row - m) * A.N + A.first + p0 + c] = v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid < np && sbits[tid]) A.status[A.first + p0 + tid] |= sbits[tid];
+}
+
+int launch_kin(int mixed, const EvalArgs& a, hipStream_t s) {
+    const dim3 grid(nblocks(a.count, 16)), block(256);
+    if (a.MT > 8) return HROM_E_UNSUPPORTED;
+    if (mixed) hipLaunchKernelGGL(k_kin<true>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_kin<false>, grid, block, 0, s, a);
+    return HROM_OK;
+}
+
+// ============================================================== FP64 tangent
 template <int I, int MT>
 __device__ __forceinline__ void row_step_f64(const double* Fi, double c0, double c1, double c2,
-                                             double wPI, const double (&Gc)[MT][9], bool res_lane,
-                                             int res_t, v4d* acc) {
+                                             const double (&Gc)[MT][9], v4d* acc) {
     double W[9];
     tangent_row<I>(Fi, c0, c1, c2, W);
     double Bv[MT];
@@ -70,7 +234,7 @@ __device__ __forceinline__ void row_step_f64(const double* Fi, double c0, double
         double s = 0.0;
 #pragma unroll
         for (int J = 0; J < 9; J++) s = fma(W[J], Gc[t][J], s);
-        Bv[t] = (res_lane && t == res_t) ? wPI : s;
+        Bv[t] = s;
     }
     int idx = 0;
 #pragma unroll
@@ -82,130 +246,84 @@ __device__ __forceinline__ void row_step_f64(const double* Fi, double c0, double
         }
 }
 
-// ============================================================== FP64
+// FP64: the tangent product T_q = (w_q A_q) Ghat_q is formed on the vector
+// ALUs straight into the B operand of the FP64 MFMA; the contraction index is
+// k = (ECM point, tensor row), lane group g taking ECM point q0 + 4 qb + g.
+template <int MT>
+__device__ __forceinline__ void load_ghat(const double* gh, int MP, double (&Gc)[MT][9]) {
+#pragma unroll
+    for (int t = 0; t < MT; t++)
+#pragma unroll
+        for (int J = 0; J < 9; J++) Gc[t][J] = gh[J * MP + 16 * t];
+}
+
+template <int MT>
+__device__ __forceinline__ void tangent_block_f64(const double* st, int qq, const double (&Gc)[MT][9],
+                                                  v4d* acc) {
+    double Fi[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) Fi[k] = st[k * 64 + qq];
+    const double c0 = st[9 * 64 + qq], c1 = st[10 * 64 + qq], c2 = st[11 * 64 + qq];
+    row_step_f64<0, MT>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<1, MT>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<2, MT>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<3, MT>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<4, MT>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<5, MT>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<6, MT>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<7, MT>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<8, MT>(Fi, c0, c1, c2, Gc, acc);
+}
+
 template <int MT>
 __global__ void __launch_bounds__(256, 1) k_eval_f64(EvalArgs A) {
     constexpr int NT = MT * (MT + 1) / 2;
-    constexpr int NS = 21;   // LDS scalars per ECM point: Fi (9), c0, c1, c2, w P (9)
-    __shared__ double s_st[4][NS * 64];
-    __shared__ double s_a[4][kMaxModes];
+    constexpr bool PF = (MT <= 5);   // register budget of the double buffer
+    __shared__ double s_st[4][12 * 64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
     int64_t pl = (int64_t)blockIdx.x * 4 + wave;
     const bool valid = pl < A.count;
     if (!valid) pl = A.count - 1;
-    const int64_t b = A.first + pl;
-    const int m = A.m, MP = A.MP;
+    const int MP = A.MP;
     double* st = s_st[wave];
-    int bits = 0;
-    for (int k = lane; k < m; k += 64) {
-        const double ak = A.a[(int64_t)k * A.count + pl];
-        if (!isfinite(ak)) bits |= HROM_PT_NONFINITE;
-        s_a[wave][k] = ak;
-    }
-    double Fr[9];
-#pragma unroll
-    for (int I = 0; I < 9; I++) Fr[I] = A.Fr[I * A.N + b];
-    const double mu0 = A.theta[0], la0 = A.theta[1], mu1 = A.theta[2], la1 = A.theta[3];
+    const double* qsp = (const double*)A.qs + (pl * A.Qpad) * 12;
     v4d acc[NT];
 #pragma unroll
     for (int i = 0; i < NT; i++) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
-    const bool res_lane = (c == A.res_c);
-    __syncthreads();
 
     for (int q0 = 0; q0 < A.Qpad; q0 += 64) {
-        // ---------------- phase A: lane = ECM point q0 + lane
         {
-            const int q = q0 + lane;
-            double F[9];
+            const double* src = qsp + (int64_t)(q0 + lane) * 12;
 #pragma unroll
-            for (int I = 0; I < 9; I++) F[I] = Fr[I];
-            const double* gt = A.GT + (int64_t)(q0 >> 6) * 9 * m * 64 + lane;
-            for (int k = 0; k < m; k++) {
-                const double ak = s_a[wave][k];
-#pragma unroll
-                for (int I = 0; I < 9; I++) F[I] = fma(ak, gt[(int64_t)(I * m + k) * 64], F[I]);
-            }
-            const double wq = A.w[q];
-            const int ph = A.phase[q];
-            const double mu = ph ? mu1 : mu0, la = ph ? la1 : la0;
-            double Fi[9];
-            const double J = inv3d(F, Fi);
-            double c0 = 0.0, c1 = 0.0, c2 = 0.0, wP[9];
-            const bool ok = (q < A.Q) && (J > 0.0);
-            if (q < A.Q && !(J > 0.0)) bits |= HROM_PT_JNONPOS;
-            const double ell = ok ? log(J) : 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int j = 0; j < 3; j++)
-                    wP[3 * i + j] = ok ? wq * (mu * (F[3 * i + j] - Fi[3 * j + i]) + la * ell * Fi[3 * j + i])
-                                       : 0.0;
-            if (ok) {
-                c0 = wq * mu;
-                c1 = wq * (mu - la * ell);
-                c2 = wq * la;
-            }
-#pragma unroll
-            for (int k = 0; k < 9; k++) st[k * 64 + lane] = ok ? Fi[k] : 0.0;
-            st[9 * 64 + lane] = c0;
-            st[10 * 64 + lane] = c1;
-            st[11 * 64 + lane] = c2;
-#pragma unroll
-            for (int k = 0; k < 9; k++) st[(12 + k) * 64 + lane] = wP[k];
+            for (int k = 0; k < 12; k++) st[k * 64 + lane] = src[k];
         }
         __syncthreads();
-        // ---------------- phase B: MFMA over k = (ECM point, row I); lane group g
-        // takes ECM point q0 + 4 qb + g, all 16 lanes of a group share it.
-        for (int qb = 0; qb < 16; qb++) {
-            const int qq = 4 * qb + g;
-            const double* gh = A.Ghat + (int64_t)(q0 + qq) * 9 * MP + c;
-            double Gc[MT][9];
-#pragma unroll
-            for (int t = 0; t < MT; t++)
-#pragma unroll
-                for (int J = 0; J < 9; J++) Gc[t][J] = gh[J * MP + 16 * t];
-            double Fi[9];
-#pragma unroll
-            for (int k = 0; k < 9; k++) Fi[k] = st[k * 64 + qq];
-            const double c0 = st[9 * 64 + qq], c1 = st[10 * 64 + qq], c2 = st[11 * 64 + qq];
-            const double* wp = st + 12 * 64 + qq;
-            row_step_f64<0, MT>(Fi, c0, c1, c2, wp[0 * 64], Gc, res_lane, A.res_t, acc);
-            row_step_f64<1, MT>(Fi, c0, c1, c2, wp[1 * 64], Gc, res_lane, A.res_t, acc);
-            row_step_f64<2, MT>(Fi, c0, c1, c2, wp[2 * 64], Gc, res_lane, A.res_t, acc);
-            row_step_f64<3, MT>(Fi, c0, c1, c2, wp[3 * 64], Gc, res_lane, A.res_t, acc);
-            row_step_f64<4, MT>(Fi, c0, c1, c2, wp[4 * 64], Gc, res_lane, A.res_t, acc);
-            row_step_f64<5, MT>(Fi, c0, c1, c2, wp[5 * 64], Gc, res_lane, A.res_t, acc);
-            row_step_f64<6, MT>(Fi, c0, c1, c2, wp[6 * 64], Gc, res_lane, A.res_t, acc);
-            row_step_f64<7, MT>(Fi, c0, c1, c2, wp[7 * 64], Gc, res_lane, A.res_t, acc);
-            row_step_f64<8, MT>(Fi, c0, c1, c2, wp[8 * 64], Gc, res_lane, A.res_t, acc);
+        if (PF) {
+            // two register buffers: the next ECM point's Ghat rows load while
+            // the current one is contracted
+            double GA[MT][9], GB[MT][9];
+            load_ghat<MT>(A.Ghat + (int64_t)(q0 + g) * 9 * MP + c, MP, GA);
+            for (int qb = 0; qb < 16; qb += 2) {
+                load_ghat<MT>(A.Ghat + (int64_t)(q0 + 4 * (qb + 1) + g) * 9 * MP + c, MP, GB);
+                tangent_block_f64<MT>(st, 4 * qb + g, GA, acc);
+                if (qb + 2 < 16)
+                    load_ghat<MT>(A.Ghat + (int64_t)(q0 + 4 * (qb + 2) + g) * 9 * MP + c, MP, GA);
+                tangent_block_f64<MT>(st, 4 * (qb + 1) + g, GB, acc);
+            }
+        } else {
+            for (int qb = 0; qb < 16; qb++) {
+                double Gc[MT][9];
+                load_ghat<MT>(A.Ghat + (int64_t)(q0 + 4 * qb + g) * 9 * MP + c, MP, Gc);
+                tangent_block_f64<MT>(st, 4 * qb + g, Gc, acc);
+            }
         }
         __syncthreads();
     }
-
-    // status of the point: OR over lanes
-    const uint64_t bad_j = __ballot(bits & HROM_PT_JNONPOS);
-    const uint64_t bad_n = __ballot(bits & HROM_PT_NONFINITE);
     if (!valid) return;
-    if (lane == 0 && (bad_j | bad_n))
-        A.status[b] |= (bad_j ? HROM_PT_JNONPOS : 0) | (bad_n ? HROM_PT_NONFINITE : 0);
     double* kh = (double*)A.Khat + (int64_t)pl * NT * 256 + lane * 4;
 #pragma unroll
     for (int i = 0; i < NT; i++) *(v4d*)(kh + i * 256) = acc[i];
-    // residual column m + 9: r (rows < m) and Pr (rows m .. m+8)
-    if (res_lane) {
-#pragma unroll
-        for (int ti = 0; ti < MT; ti++) {
-            const int idx = ti * MT - ti * (ti - 1) / 2 + (MT - 1 - ti);
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int row = 16 * ti + g + 4 * e;   // FP64 MFMA accumulator rows interleave
-                const double v = acc[idx][e];
-                if (row < m) A.r[(int64_t)row * A.count + pl] = v;
-                else if (row < m + 9) A.Pr[(int64_t)(row - m) * A.N + b] = v;
-            }
-        }
-    }
 }
 
 int launch_eval_f64(int MT, const EvalArgs& a, hipStream_t s) {
@@ -222,7 +340,7 @@ int launch_eval_f64(int MT, const EvalArgs& a, hipStream_t s) {
     return HROM_OK;
 }
 
-// ============================================================== mixed
+// ============================================================== mixed tangent
 // Low-precision operand types.  bf16 fragments are carried as 16-bit
 // patterns; the conversion rounds to nearest even.
 typedef short v4s __attribute__((ext_vector_type(4)));
@@ -288,204 +406,137 @@ __device__ __forceinline__ void split4(const float* x, v4u& hi, v4u& lo) {
     }
 }
 
-// Mixed path.  Kinematics, stress, residual and homogenised stress in FP64;
-// the tangent A_q in FP32; the contraction Khat = sum_q Ghat_q^T (w_q A_q) Ghat_q
-// on BF16/FP16 MFMA with FP32 accumulation, in two chained steps per ECM point:
-//   T_q = (w_q A_q) Ghat_q       16x16x16 MFMA, rows I of T come out in the
+// Mixed path, tangent contraction on BF16/FP16 MFMA with FP32 accumulation,
+// in two chained steps per ECM point:
+//   T_q = (w_q A_q) Ghat_q       16x16x16 MFMA; rows I of T come out in the
 //                                accumulator layout (lane (g,c): rows 4g..4g+3,
 //                                column c), which is the B-operand layout of
 //   Khat += Ghat^T [T_q0 ; T_q1] 16x16x32 MFMA over a pair of ECM points.
-// With SPLIT every operand x is carried as hi + lo (both low precision) and
-// each product as hi*hi + lo*hi + hi*lo.
+// The A operand of the first step, W[I = c][J = 4g + e], is rebuilt by every
+// lane from the 12 FP32 scalars of the ECM point (already scaled by a power of
+// two for the low-precision range).  With SPLIT every operand x is carried as
+// hi + lo (both low precision) and each product as hi*hi + lo*hi + hi*lo.
+template <int MT>
+struct Frags {
+    v4u h[2][MT], l[2][MT];
+};
+
+// fragments of Ghat for the ECM point pair (q, q + 1)
+template <int MT, bool SPLIT>
+__device__ __forceinline__ void load_frags(const EvalArgs& A, int q, int lane, Frags<MT>& F) {
+#pragma unroll
+    for (int s2 = 0; s2 < 2; s2++) {
+        const v4u* fh = (const v4u*)(A.Fhi) + ((int64_t)(q + s2) * MT) * 64 + lane;
+        const v4u* fl = (const v4u*)(A.Flo) + ((int64_t)(q + s2) * MT) * 64 + lane;
+#pragma unroll
+        for (int t = 0; t < MT; t++) {
+            F.h[s2][t] = fh[t * 64];
+            if (SPLIT) F.l[s2][t] = fl[t * 64];
+        }
+    }
+}
+
+// contraction of one ECM point pair; bq points at the pair's 2 x 13 scalars
+template <int MT, int PREC, bool SPLIT>
+__device__ __forceinline__ void tangent_pair(const float* bq0, const Frags<MT>& G, const int* o1,
+                                             const int* o2, const int* o3, const int* o4,
+                                             const float* dl, const float* vl, v4f* acc) {
+    constexpr int LQ = 13;
+    v4u Th[2][MT], Tl[2][MT];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; s2++) {
+        const float* bq = bq0 + s2 * LQ;
+        const float c0 = bq[9], c1 = bq[10], c2 = bq[11];
+        float wv[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+            wv[e] = vl[e] * (c1 * bq[o1[e]] * bq[o2[e]] + c2 * bq[o3[e]] * bq[o4[e]] + dl[e] * c0);
+        v4u Wh, Wl;
+        split4<PREC>(wv, Wh, Wl);
+#pragma unroll
+        for (int t = 0; t < MT; t++) {
+            v4f T = v4f{0.f, 0.f, 0.f, 0.f};
+            T = LP<PREC>::mfma16(Wh, G.h[s2][t], T);
+            if (SPLIT) {
+                T = LP<PREC>::mfma16(Wl, G.h[s2][t], T);
+                T = LP<PREC>::mfma16(Wh, G.l[s2][t], T);
+            }
+            float tv[4] = {T[0], T[1], T[2], T[3]};
+            split4<PREC>(tv, Th[s2][t], Tl[s2][t]);
+        }
+    }
+    int idx = 0;
+#pragma unroll
+    for (int ti = 0; ti < MT; ti++)
+#pragma unroll
+        for (int tj = ti; tj < MT; tj++) {
+            acc[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Th[0][tj], Th[1][tj], acc[idx]);
+            if (SPLIT) {
+                acc[idx] = LP<PREC>::mfma32(G.l[0][ti], G.l[1][ti], Th[0][tj], Th[1][tj], acc[idx]);
+                acc[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Tl[0][tj], Tl[1][tj], acc[idx]);
+            }
+            idx++;
+        }
+}
+
 template <int MT, int PREC, bool SPLIT>
 __global__ void __launch_bounds__(256, 1) k_eval_mixed(EvalArgs A) {
     constexpr int NT = MT * (MT + 1) / 2;
-    constexpr int QC = 32;   // ECM points per chunk
-    __shared__ float s_W[4][QC * 81];
-    __shared__ double s_wP[4][9 * QC];
-    __shared__ double s_a[4][kMaxModes];
+    constexpr int LQ = 13;   // padded stride of the 12 scalars in LDS
+    __shared__ float s_q[4][64 * LQ];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
     int64_t pl = (int64_t)blockIdx.x * 4 + wave;
     const bool valid = pl < A.count;
     if (!valid) pl = A.count - 1;
-    const int64_t b = A.first + pl;
-    const int m = A.m, MP = A.MP;
-    int bits = 0;
-    for (int k = lane; k < m; k += 64) {
-        const double ak = A.a[(int64_t)k * A.count + pl];
-        if (!isfinite(ak)) bits |= HROM_PT_NONFINITE;
-        s_a[wave][k] = ak;
-    }
-    double Fr[9];
+    float* sq = s_q[wave];
+    const float* qsp = (const float*)A.qs + (pl * A.Qpad) * 12;
+    // lane's entries of W: I = c = (i, j), J = 4 g + e = (k, l)
+    int o1[4], o2[4], o3[4], o4[4];
+    float dl[4], vl[4];
+    {
+        const int cc = c < 9 ? c : 0;
+        const int i = cc / 3, j = cc % 3;
 #pragma unroll
-    for (int I = 0; I < 9; I++) Fr[I] = A.Fr[I * A.N + b];
-    const double mu0 = A.theta[0], la0 = A.theta[1], mu1 = A.theta[2], la1 = A.theta[3];
-    const float wscale = A.wscale;
+        for (int e = 0; e < 4; e++) {
+            const int J = 4 * g + e < 9 ? 4 * g + e : 0;
+            const int k = J / 3, l = J % 3;
+            o1[e] = 3 * l + i;
+            o2[e] = 3 * j + k;
+            o3[e] = 3 * j + i;
+            o4[e] = 3 * l + k;
+            dl[e] = (k == i && l == j) ? 1.f : 0.f;
+            vl[e] = (c < 9 && 4 * g + e < 9) ? 1.f : 0.f;
+        }
+    }
     v4f acc[NT];
 #pragma unroll
     for (int i = 0; i < NT; i++) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
-    double Pacc[9];
-#pragma unroll
-    for (int I = 0; I < 9; I++) Pacc[I] = 0.0;
-    double racc0 = 0.0, racc1 = 0.0;   // residual of modes lane and lane + 64
-    float* sW = s_W[wave];
-    double* swP = s_wP[wave];
-    __syncthreads();
 
-    for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
-        // ---------------- phase A: lanes 0..31 = ECM points q0 .. q0+31
-        if (lane < QC) {
-            const int q = q0 + lane;
-            double F[9];
-#pragma unroll
-            for (int I = 0; I < 9; I++) F[I] = Fr[I];
-            const double* gt = A.GT + (int64_t)(q >> 6) * 9 * m * 64 + (q & 63);
-            for (int k = 0; k < m; k++) {
-                const double ak = s_a[wave][k];
-#pragma unroll
-                for (int I = 0; I < 9; I++) F[I] = fma(ak, gt[(int64_t)(I * m + k) * 64], F[I]);
-            }
-            const double wq = A.w[q];
-            const int ph = A.phase[q];
-            const double mu = ph ? mu1 : mu0, la = ph ? la1 : la0;
-            double Fi[9];
-            const double J = inv3d(F, Fi);
-            const bool ok = (q < A.Q) && (J > 0.0);
-            if (q < A.Q && !(J > 0.0)) bits |= HROM_PT_JNONPOS;
-            const double ell = ok ? log(J) : 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int j = 0; j < 3; j++) {
-                    const double v = ok ? wq * (mu * (F[3 * i + j] - Fi[3 * j + i]) + la * ell * Fi[3 * j + i])
-                                        : 0.0;
-                    swP[(3 * i + j) * QC + lane] = v;
-                    Pacc[3 * i + j] += v;
-                }
-            // FP32 tangent, scaled by a power of two for the low-precision range
-            float Fif[9];
-#pragma unroll
-            for (int k = 0; k < 9; k++) Fif[k] = ok ? (float)Fi[k] : 0.f;
-            const float c0 = ok ? (float)(wq * mu) * wscale : 0.f;
-            const float c1 = ok ? (float)(wq * (mu - la * ell)) * wscale : 0.f;
-            const float c2 = ok ? (float)(wq * la) * wscale : 0.f;
-            float* wr = sW + lane * 81;
-            float Wrow[9];
-            tangent_row<0>(Fif, c0, c1, c2, Wrow);
-#pragma unroll
-            for (int J2 = 0; J2 < 9; J2++) wr[0 * 9 + J2] = Wrow[J2];
-            tangent_row<1>(Fif, c0, c1, c2, Wrow);
-#pragma unroll
-            for (int J2 = 0; J2 < 9; J2++) wr[1 * 9 + J2] = Wrow[J2];
-            tangent_row<2>(Fif, c0, c1, c2, Wrow);
-#pragma unroll
-            for (int J2 = 0; J2 < 9; J2++) wr[2 * 9 + J2] = Wrow[J2];
-            tangent_row<3>(Fif, c0, c1, c2, Wrow);
-#pragma unroll
-            for (int J2 = 0; J2 < 9; J2++) wr[3 * 9 + J2] = Wrow[J2];
-            tangent_row<4>(Fif, c0, c1, c2, Wrow);
-#pragma unroll
-            for (int J2 = 0; J2 < 9; J2++) wr[4 * 9 + J2] = Wrow[J2];
-            tangent_row<5>(Fif, c0, c1, c2, Wrow);
-#pragma unroll
-            for (int J2 = 0; J2 < 9; J2++) wr[5 * 9 + J2] = Wrow[J2];
-            tangent_row<6>(Fif, c0, c1, c2, Wrow);
-#pragma unroll
-            for (int J2 = 0; J2 < 9; J2++) wr[6 * 9 + J2] = Wrow[J2];
-            tangent_row<7>(Fif, c0, c1, c2, Wrow);
-#pragma unroll
-            for (int J2 = 0; J2 < 9; J2++) wr[7 * 9 + J2] = Wrow[J2];
-            tangent_row<8>(Fif, c0, c1, c2, Wrow);
-#pragma unroll
-            for (int J2 = 0; J2 < 9; J2++) wr[8 * 9 + J2] = Wrow[J2];
-        }
-        __syncthreads();
-        // ---------------- phase R: FP64 residual, lane = mode
+    for (int q0 = 0; q0 < A.Qpad; q0 += 64) {
         {
-            const double* gh = A.Ghat + (int64_t)q0 * 9 * MP;
-            for (int qq = 0; qq < QC; qq++) {
+            const v4f* src = (const v4f*)(qsp + (int64_t)(q0 + lane) * 12);
+            const v4f x0 = src[0], x1 = src[1], x2 = src[2];
+            float* d = sq + lane * LQ;
 #pragma unroll
-                for (int I = 0; I < 9; I++) {
-                    const double wp = swP[I * QC + qq];
-                    const double* row = gh + (int64_t)(qq * 9 + I) * MP;
-                    if (lane < m) racc0 = fma(wp, row[lane], racc0);
-                    if (lane + 64 < m) racc1 = fma(wp, row[lane + 64], racc1);
-                }
+            for (int k = 0; k < 4; k++) {
+                d[k] = x0[k];
+                d[4 + k] = x1[k];
+                d[8 + k] = x2[k];
             }
         }
-        // ---------------- phase B: chained MFMA over pairs of ECM points
-        for (int qp = 0; qp < QC / 2; qp++) {
-            v4u Gh[2][MT], Gl[2][MT], Th[2][MT], Tl[2][MT];
-#pragma unroll
-            for (int s2 = 0; s2 < 2; s2++) {
-                const int qq = 2 * qp + s2;
-                const int q = q0 + qq;
-                // W fragment: lane (g, c) holds W[I = c][J = 4g + e]
-                float wv[4];
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int J2 = 4 * g + e;
-                    wv[e] = (c < 9 && J2 < 9) ? sW[qq * 81 + c * 9 + J2] : 0.f;
-                }
-                v4u Wh, Wl;
-                split4<PREC>(wv, Wh, Wl);
-                const v4u* fh = (const v4u*)(A.Fhi) + ((int64_t)q * MT) * 64 + lane;
-                const v4u* fl = (const v4u*)(A.Flo) + ((int64_t)q * MT) * 64 + lane;
-#pragma unroll
-                for (int t = 0; t < MT; t++) {
-                    Gh[s2][t] = fh[t * 64];
-                    if (SPLIT) Gl[s2][t] = fl[t * 64];
-                }
-#pragma unroll
-                for (int t = 0; t < MT; t++) {
-                    v4f T = v4f{0.f, 0.f, 0.f, 0.f};
-                    T = LP<PREC>::mfma16(Wh, Gh[s2][t], T);
-                    if (SPLIT) {
-                        T = LP<PREC>::mfma16(Wl, Gh[s2][t], T);
-                        T = LP<PREC>::mfma16(Wh, Gl[s2][t], T);
-                    }
-                    float tv[4] = {T[0], T[1], T[2], T[3]};
-                    split4<PREC>(tv, Th[s2][t], Tl[s2][t]);
-                }
-            }
-            int idx = 0;
-#pragma unroll
-            for (int ti = 0; ti < MT; ti++)
-#pragma unroll
-                for (int tj = ti; tj < MT; tj++) {
-                    acc[idx] = LP<PREC>::mfma32(Gh[0][ti], Gh[1][ti], Th[0][tj], Th[1][tj], acc[idx]);
-                    if (SPLIT) {
-                        acc[idx] = LP<PREC>::mfma32(Gl[0][ti], Gl[1][ti], Th[0][tj], Th[1][tj], acc[idx]);
-                        acc[idx] = LP<PREC>::mfma32(Gh[0][ti], Gh[1][ti], Tl[0][tj], Tl[1][tj], acc[idx]);
-                    }
-                    idx++;
-                }
+        __syncthreads();
+        Frags<MT> FA, FB;
+        load_frags<MT, SPLIT>(A, q0, lane, FA);
+        for (int qp = 0; qp < 32; qp += 2) {
+            load_frags<MT, SPLIT>(A, q0 + 2 * (qp + 1), lane, FB);
+            tangent_pair<MT, PREC, SPLIT>(sq + (2 * qp) * LQ, FA, o1, o2, o3, o4, dl, vl, acc);
+            if (qp + 2 < 32) load_frags<MT, SPLIT>(A, q0 + 2 * (qp + 2), lane, FA);
+            tangent_pair<MT, PREC, SPLIT>(sq + (2 * qp + 2) * LQ, FB, o1, o2, o3, o4, dl, vl, acc);
         }
         __syncthreads();
     }
-
-    // homogenised stress: fixed-order butterfly over the 64 lanes
-#pragma unroll
-    for (int I = 0; I < 9; I++) {
-        double v = Pacc[I];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        Pacc[I] = v;
-    }
-    const uint64_t bad_j = __ballot(bits & HROM_PT_JNONPOS);
-    const uint64_t bad_n = __ballot(bits & HROM_PT_NONFINITE);
     if (!valid) return;
-    if (lane == 0 && (bad_j | bad_n))
-        A.status[b] |= (bad_j ? HROM_PT_JNONPOS : 0) | (bad_n ? HROM_PT_NONFINITE : 0);
-    if (lane < 9) {
-        double v = 0.0;
-#pragma unroll
-        for (int I = 0; I < 9; I++) v = (lane == I) ? Pacc[I] : v;
-        A.Pr[(int64_t)lane * A.N + b] = v;
-    }
-    if (lane < m) A.r[(int64_t)lane * A.count + pl] = racc0;
-    if (lane + 64 < m) A.r[(int64_t)(lane + 64) * A.count + pl] = racc1;
     float* kh = (float*)A.Khat + (int64_t)pl * NT * 256 + lane * 4;
 #pragma unroll
     for (int i = 0; i < NT; i++) *(v4f*)(kh + i * 256) = acc[i];

@@ -418,9 +418,27 @@ __global__ void k_build_frags(LayoutArgs A) {
     A.Flo[t] = lo;
 }
 
+// A-operand fragments of the kinematics GEMM (FP64 16x16x4 MFMA): row tile
+// rt, k-step s, lane (g, c) holds G[q][I][k] with 9 q + I = 16 rt + c and
+// k = 4 s + g (zero beyond m and beyond Q).
+__global__ void k_build_gf(LayoutArgs A) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ntile = (int64_t)A.Qpad * 9 / 16;
+    if (t >= ntile * A.KS * 64) return;
+    const int lane = (int)(t & 63);
+    const int s = (int)((t >> 6) % A.KS);
+    const int64_t rt = (t >> 6) / A.KS;
+    const int64_t row = rt * 16 + (lane & 15);
+    const int q = (int)(row / 9), I = (int)(row % 9);
+    const int k = 4 * s + (lane >> 4);
+    A.Gf[t] = (q < A.Q && k < A.m) ? A.G[((int64_t)q * 9 + I) * A.m + k] : 0.0;
+}
+
 void launch_build_layouts(const LayoutArgs& a, hipStream_t s) {
     const int64_t n1 = (int64_t)a.Qpad * 9 * a.MP;
     hipLaunchKernelGGL(k_build_ghat, dim3(nblocks(n1, 256)), dim3(256), 0, s, a);
+    const int64_t n3 = (int64_t)a.Qpad * 9 / 16 * a.KS * 64;
+    hipLaunchKernelGGL(k_build_gf, dim3(nblocks(n3, 256)), dim3(256), 0, s, a);
     if (a.prec != HROM_FP64) {
         const int64_t n2 = (int64_t)a.Qpad * a.MT * 256;
         hipLaunchKernelGGL(k_build_frags, dim3(nblocks(n2, 256)), dim3(256), 0, s, a);
