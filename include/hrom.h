@@ -71,6 +71,7 @@ extern "C" {
 /* plan flags */
 #define HROM_OBJECTIVE 1u    /* RVE sees Ubar of Fbar = Rbar Ubar (Sec. 3.2.2) */
 #define HROM_SPLIT 2u        /* mixed modes: hi/lo split operands (3 MFMA terms) */
+#define HROM_REFINE 4u       /* mixed modes: refine the adjoint solve (default without SPLIT) */
 
 /* offset kinds for hrom_plan_offset */
 #define HROM_OFF_A 0         /* a, r, y: [m_c][count_c] */

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libhrom.so")
 HROM_OK = 0
 PT_JNONPOS, PT_NOT_SPD, PT_NOCONV, PT_NONFINITE = 1, 2, 4, 8
 FP64, MIXED_BF16, MIXED_FP16 = 0, 1, 2
-OBJECTIVE, SPLIT = 1, 2
+OBJECTIVE, SPLIT, REFINE = 1, 2, 4
 OFF_A, OFF_KAA, OFF_KAF = 0, 1, 2
 
 EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_eval",
@@ -106,7 +106,7 @@ class Plan:
     """A plan for N macro points partitioned into RVE clusters (in order)."""
 
     def __init__(self, clusters, precision: int = FP64, objective: bool = True,
-                 split: bool = False):
+                 split: bool = False, refine: bool = False):
         L = load()
         self.clusters = list(clusters)
         self.N = sum(c.count for c in self.clusters)
@@ -120,7 +120,8 @@ class Plan:
             arr[i] = _Cluster(c.m, c.Q, c.G.data_ptr(), c.w.data_ptr(), c.phase.data_ptr(),
                               first, c.count)
             first += c.count
-        flags = (OBJECTIVE if objective else 0) | (SPLIT if split else 0)
+        flags = ((OBJECTIVE if objective else 0) | (SPLIT if split else 0)
+                 | (REFINE if refine else 0))
         h = C.c_void_p()
         torch.cuda.synchronize()
         _check(L.hrom_plan_create(C.byref(h), arr, len(self.clusters), self.N, precision, flags),

@@ -53,6 +53,12 @@ int hip_status() { return hipGetLastError() == hipSuccess ? HROM_OK : HROM_E_HIP
 
 bool mixed(const Plan& p) { return p.prec != HROM_FP64; }
 
+// one step of iterative refinement of the adjoint solve: on by default for
+// plain low-precision tangents, optional for split operands
+bool refine(const Plan& p) {
+    return mixed(p) && (!(p.flags & HROM_SPLIT) || (p.flags & HROM_REFINE));
+}
+
 // power-of-two scaling of w_q A_q for the low-precision operands (w ~ 1/Q)
 float wscale_for(int Q) { return std::ldexp(1.0f, (int)std::ceil(std::log2((double)Q))); }
 
@@ -158,7 +164,7 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
         if (precision == HROM_FP64) rc = dalloc((double**)&p.qs, ws_q);
         else rc = dalloc((float**)&p.qs, ws_q);
     }
-    if (rc == HROM_OK) rc = dalloc(&p.L, ws_L);
+    if (rc == HROM_OK) rc = dalloc(&p.L, refine(p) ? ws_L : 1);
     if (rc == HROM_OK) rc = dalloc(&p.piv, off_a);
     if (rc == HROM_OK) rc = dalloc(&p.y, off_a);
     if (rc == HROM_OK) rc = dalloc(&p.X, 9 * off_a);
@@ -264,11 +270,14 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
         ca.first = c.first; ca.count = c.count; ca.N = p.N;
         ca.Khat = (const char*)p.Khat + tsz * (size_t)c.ws_khat;
         ca.r = p.r + c.off_a; ca.Pr = p.Pr;
-        ca.L = p.L + c.ws_L; ca.piv = p.piv + c.off_a;
+        ca.L = refine(p) ? p.L + c.ws_L : nullptr;
+        ca.piv = p.piv + c.off_a;
         ca.y = p.y + c.off_a; ca.X = p.X + 9 * c.off_a;
         ca.Palg = p.Palg; ca.Cr = p.Cr; ca.rnorm = p.rnorm; ca.status = status;
         ca.kscale = mixed(p) ? 1.0f / wscale_for(c.Q) : 1.0f;
-        const int rc = launch_unpack_condense(ca, 1, stream);
+        // SPD path on the packed triangle; non-positive pivots finish on the LU path
+        int rc = launch_condense_spd(ca, stream);
+        if (rc == HROM_OK) rc = launch_unpack_condense(ca, 2, stream);
         if (rc != HROM_OK) return rc;
     }
     PushArgs pa{p.N, (p.flags & HROM_OBJECTIVE) ? 1 : 0, p.polar, p.Palg, p.Cr, Pbar, Cbar, p.S, status};
@@ -356,7 +365,7 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
         ba.w = c.w; ba.phase = c.phase;
         ba.theta = theta; ba.Fr = p.Fr; ba.a = a + c.off_a; ba.lam = p.lam + c.off_a;
         ba.gr = p.gr; ba.hr = p.hr; ba.gth = p.gth; ba.rho = p.rho + c.off_a; ba.status = status;
-        if (mixed(p)) {
+        if (refine(p)) {
             // one step of iterative refinement of the adjoint solve: the residual
             // rho = KaF g_r - Kaa lambda with the accurate (FP32-tangent) operator,
             // corrected with the factor of the low-precision Kaa

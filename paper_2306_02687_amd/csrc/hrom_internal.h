@@ -127,6 +127,7 @@ struct CondenseArgs {
     double* outKFF;        // [81][N]
 };
 int launch_unpack_condense(const CondenseArgs& a, int mode, hipStream_t s);
+int launch_condense_spd(const CondenseArgs& a, hipStream_t s);
 
 struct PushArgs {
     int64_t N;

@@ -108,10 +108,12 @@ __device__ inline void lyap_solve(const double* V, const double* u, const double
     double T[9], M[9];
     tmul3(V, B, T);   // V^T B
     mul3(T, V, M);    // V^T B V
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) M[3 * i + j] /= (u[i] + u[j]);
+    const double h00 = 0.5 / u[0], h11 = 0.5 / u[1], h22 = 0.5 / u[2];
+    const double h01 = 1.0 / (u[0] + u[1]), h02 = 1.0 / (u[0] + u[2]), h12 = 1.0 / (u[1] + u[2]);
+    M[0] *= h00; M[4] *= h11; M[8] *= h22;
+    M[1] *= h01; M[3] *= h01;
+    M[2] *= h02; M[6] *= h02;
+    M[5] *= h12; M[7] *= h12;
     // Z = V M V^T
 #pragma unroll
     for (int i = 0; i < 3; i++)

@@ -107,46 +107,27 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int mode
     }
     __syncthreads();
 
-    // ------------------------------------------------ Cholesky, left-looking
-    // column j: s_i = K[i][j] - sum_{k<j} L[i][k] L[j][k] for every row i >= j
-    // (independent loads, four partial sums), pivot d = s_j, L[j][j] = sqrt(d),
-    // L[i][j] = s_i / L[j][j].
+    // ------------------------------------------------ Cholesky, right-looking
+    // column j scaled by the pivot, then the trailing update of the lower
+    // triangle spread over the 64 lanes in an 8 x 8 pattern (row i = j+1+r+8s,
+    // column k = j+1+c+8t <= i): independent read-modify-writes.
     bool spd = (mode != 2);
-    double* piv_d = S.rv + m;   // one broadcast slot after the residual copy
+    const int lr = lane >> 3, lcol = lane & 7;
     for (int j = 0; j < m && spd; j++) {
-        double sv[2];
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int i = lane + 64 * h;
-            sv[h] = 0.0;
-            if (i < m && i >= j) {
-                const double* Li = S.K + i * S.ld;
-                const double* Lj = S.K + j * S.ld;
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                int k = 0;
-                for (; k + 4 <= j; k += 4) {
-                    a0 = fma(Li[k], Lj[k], a0);
-                    a1 = fma(Li[k + 1], Lj[k + 1], a1);
-                    a2 = fma(Li[k + 2], Lj[k + 2], a2);
-                    a3 = fma(Li[k + 3], Lj[k + 3], a3);
-                }
-                for (; k < j; k++) a0 = fma(Li[k], Lj[k], a0);
-                sv[h] = Li[j] - ((a0 + a1) + (a2 + a3));
-            }
-        }
-        if (lane == (j & 63)) piv_d[0] = sv[j >> 6];
-        __syncthreads();
-        const double d = piv_d[0];
+        const double d = S.K[j * S.ld + j];
         if (!(d > 0.0)) {
             spd = false;
             break;
         }
         const double sd = sqrt(d);
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int i = lane + 64 * h;
-            if (i < m && i > j) S.K[i * S.ld + j] = sv[h] / sd;
-            else if (i == j) S.K[j * S.ld + j] = sd;
+        __syncthreads();
+        for (int i = j + 1 + lane; i < m; i += 64) S.K[i * S.ld + j] = S.K[i * S.ld + j] / sd;
+        if (lane == 0) S.K[j * S.ld + j] = sd;
+        __syncthreads();
+        for (int i = j + 1 + lr; i < m; i += 8) {
+            const double lij = S.K[i * S.ld + j];
+            double* Ki = S.K + i * S.ld;
+            for (int k = j + 1 + lcol; k <= i; k += 8) Ki[k] -= lij * S.K[k * S.ld + j];
         }
         __syncthreads();
     }
@@ -156,10 +137,10 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int mode
         // L z = B, then L^T x = z (10 right-hand sides)
         for (int j = 0; j < m; j++) {
             __syncthreads();
-            const double djj = S.K[j * S.ld + j];
+            const double rjj = 1.0 / S.K[j * S.ld + j];
             double z[10];
 #pragma unroll
-            for (int r = 0; r < 10; r++) z[r] = S.B[j * 10 + r] / djj;
+            for (int r = 0; r < 10; r++) z[r] = S.B[j * 10 + r] * rjj;
             __syncthreads();
             for (int i = lane; i < m; i += 64) {
                 if (i == j) {
@@ -174,10 +155,10 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int mode
         }
         for (int j = m - 1; j >= 0; j--) {
             __syncthreads();
-            const double djj = S.K[j * S.ld + j];
+            const double rjj = 1.0 / S.K[j * S.ld + j];
             double x[10];
 #pragma unroll
-            for (int r = 0; r < 10; r++) x[r] = S.B[j * 10 + r] / djj;
+            for (int r = 0; r < 10; r++) x[r] = S.B[j * 10 + r] * rjj;
             __syncthreads();
             for (int i = lane; i < m; i += 64) {
                 if (i == j) {
@@ -263,10 +244,10 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int mode
             }
             for (int j = m - 1; j >= 0; j--) {
                 __syncthreads();
-                const double ujj = S.K[j * S.ld + j];
+                const double rjj = 1.0 / S.K[j * S.ld + j];
                 double x[10];
 #pragma unroll
-                for (int r = 0; r < 10; r++) x[r] = S.B[j * 10 + r] / ujj;
+                for (int r = 0; r < 10; r++) x[r] = S.B[j * 10 + r] * rjj;
                 __syncthreads();
                 for (int i = lane; i < m; i += 64) {
                     if (i == j) {
@@ -284,18 +265,29 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int mode
     __syncthreads();
 
     // ------------------------------------------------ condensation and outputs
+    // Palg = Pr - KaF^T y (outputs 0..8), Cr = KFF - KaF^T X (outputs 9..89):
+    // dot products over the modes with four independent partial sums
     bool fin = true;
     for (int o = lane; o < 90; o += 64) {
+        const int I = (o < 9) ? o : (o - 9) / 9;
+        const int col = (o < 9) ? 0 : 1 + (o - 9) % 9;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int k = 0;
+        for (; k + 4 <= m; k += 4) {
+            s0 = fma(S.KaF[k * 9 + I], S.B[k * 10 + col], s0);
+            s1 = fma(S.KaF[(k + 1) * 9 + I], S.B[(k + 1) * 10 + col], s1);
+            s2 = fma(S.KaF[(k + 2) * 9 + I], S.B[(k + 2) * 10 + col], s2);
+            s3 = fma(S.KaF[(k + 3) * 9 + I], S.B[(k + 3) * 10 + col], s3);
+        }
+        for (; k < m; k++) s0 = fma(S.KaF[k * 9 + I], S.B[k * 10 + col], s0);
+        const double dot = (s0 + s1) + (s2 + s3);
         if (o < 9) {
-            double v = S.Pr[o];
-            for (int k = 0; k < m; k++) v -= S.KaF[k * 9 + o] * S.B[k * 10];
+            const double v = S.Pr[o] - dot;
             A.Palg[(int64_t)o * A.N + b] = v;
             fin = fin && isfinite(v);
         } else {
-            const int I = (o - 9) / 9, J = (o - 9) % 9;
-            double v = S.KFF[I * 9 + J];
-            for (int k = 0; k < m; k++) v -= S.KaF[k * 9 + I] * S.B[k * 10 + 1 + J];
-            A.Cr[(int64_t)(I * 9 + J) * A.N + b] = v;
+            const double v = S.KFF[I * 9 + (col - 1)] - dot;
+            A.Cr[(int64_t)(I * 9 + (col - 1)) * A.N + b] = v;
             fin = fin && isfinite(v);
         }
     }
@@ -305,8 +297,10 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int mode
         A.y[(int64_t)i * A.count + pl] = S.B[i * 10];
 #pragma unroll
         for (int J = 0; J < 9; J++) A.X[((int64_t)i * 9 + J) * A.count + pl] = S.B[i * 10 + 1 + J];
-        double* Lrow = A.L + (pl * m + i) * (int64_t)m;
-        for (int k = 0; k < m; k++) Lrow[k] = S.K[i * S.ld + k];
+        if (A.L) {
+            double* Lrow = A.L + (pl * m + i) * (int64_t)m;
+            for (int k = 0; k < m; k++) Lrow[k] = S.K[i * S.ld + k];
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) rr += __shfl_xor(rr, off);
@@ -421,3 +415,199 @@ void launch_refine_lambda(const RefineArgs& a, hipStream_t s) {
 
 }  // namespace hrom
 
+
+namespace hrom {
+
+// SPD path of the condensation with Kaa held as a packed lower triangle in
+// LDS (row i at offset i (i + 1) / 2), which fits about twice as many macro
+// points per CU as the full-matrix kernel.  Same algorithm: right-looking
+// Cholesky with the trailing update spread over the lanes, forward and
+// backward substitution for [r | KaF], then Palg and Cr.  A point whose
+// Cholesky meets a non-positive pivot is only flagged HROM_PT_NOT_SPD here and
+// finished by k_unpack_condense (mode 2, LU with partial pivoting).
+template <typename TT>
+__global__ void __launch_bounds__(64) k_condense_spd(CondenseArgs A) {
+    extern __shared__ double sm[];
+    const int m = A.m, lane = threadIdx.x;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t pl = blockIdx.x;
+    const int64_t b = A.first + pl;
+    const int MT = A.MT, NT = MT * (MT + 1) / 2;
+    double* K = sm;                          // packed lower, m (m + 1) / 2
+    double* KaF = K + m * (m + 1) / 2;       // [m][9]
+    double* KFF = KaF + 9 * m;               // [81]
+    double* B = KFF + 81;                    // [m][10]
+    double* Pr = B + 10 * m;                 // [9]
+    double* rv = Pr + 9;                     // [m]
+    const TT* kh = (const TT*)A.Khat + (int64_t)pl * NT * 256;
+    const double ks = (double)A.kscale;
+    {
+        int idx = 0;
+        for (int ti = 0; ti < MT; ti++)
+            for (int tj = ti; tj < MT; tj++, idx++) {
+                const TT* p = kh + (int64_t)idx * 256 + lane * 4;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int R = 16 * ti + acc_row<TT>(g, e), C = 16 * tj + c;
+                    const double v = (double)p[e] * ks;
+                    if (R < m) {
+                        if (C < m) {
+                            if (C <= R) K[R * (R + 1) / 2 + C] = v;      // lower part of the tile
+                            else if (ti < tj) K[C * (C + 1) / 2 + R] = v; // mirror of an upper tile
+                        } else if (C < m + 9) {
+                            KaF[R * 9 + (C - m)] = v;
+                        }
+                    } else if (R < m + 9 && C >= m && C < m + 9) {
+                        KFF[(R - m) * 9 + (C - m)] = v;
+                        if (ti < tj) KFF[(C - m) * 9 + (R - m)] = v;
+                    }
+                }
+            }
+    }
+    for (int i = lane; i < m; i += 64) {
+        const double ri = A.r[(int64_t)i * A.count + pl];
+        rv[i] = ri;
+        B[i * 10] = ri;
+    }
+    if (lane < 9) Pr[lane] = A.Pr[(int64_t)lane * A.N + b];
+    __syncthreads();
+    for (int i = lane; i < m; i += 64)
+#pragma unroll
+        for (int J = 0; J < 9; J++) B[i * 10 + 1 + J] = KaF[i * 9 + J];
+
+    const int lr = lane >> 3, lcol = lane & 7;
+    bool spd = true;
+    for (int j = 0; j < m; j++) {
+        __syncthreads();
+        const double d = K[j * (j + 1) / 2 + j];
+        if (!(d > 0.0)) {
+            spd = false;
+            break;
+        }
+        const double sd = sqrt(d), rsd = 1.0 / sd;
+        __syncthreads();
+        for (int i = j + 1 + lane; i < m; i += 64) K[i * (i + 1) / 2 + j] *= rsd;
+        if (lane == 0) K[j * (j + 1) / 2 + j] = sd;
+        __syncthreads();
+        for (int i = j + 1 + lr; i < m; i += 8) {
+            double* Ki = K + i * (i + 1) / 2;
+            const double lij = Ki[j];
+            for (int k = j + 1 + lcol; k <= i; k += 8) Ki[k] -= lij * K[k * (k + 1) / 2 + j];
+        }
+    }
+    if (!spd) {
+        if (lane == 0) A.status[b] |= HROM_PT_NOT_SPD;
+        return;
+    }
+    // L z = B
+    for (int j = 0; j < m; j++) {
+        __syncthreads();
+        const double rjj = 1.0 / K[j * (j + 1) / 2 + j];
+        double z[10];
+#pragma unroll
+        for (int r = 0; r < 10; r++) z[r] = B[j * 10 + r] * rjj;
+        __syncthreads();
+        for (int i = lane; i < m; i += 64) {
+            if (i == j) {
+#pragma unroll
+                for (int r = 0; r < 10; r++) B[j * 10 + r] = z[r];
+            } else if (i > j) {
+                const double lij = K[i * (i + 1) / 2 + j];
+#pragma unroll
+                for (int r = 0; r < 10; r++) B[i * 10 + r] -= lij * z[r];
+            }
+        }
+    }
+    // L^T x = z
+    for (int j = m - 1; j >= 0; j--) {
+        __syncthreads();
+        const double* Kj = K + j * (j + 1) / 2;
+        const double rjj = 1.0 / Kj[j];
+        double x[10];
+#pragma unroll
+        for (int r = 0; r < 10; r++) x[r] = B[j * 10 + r] * rjj;
+        __syncthreads();
+        for (int i = lane; i < m; i += 64) {
+            if (i == j) {
+#pragma unroll
+                for (int r = 0; r < 10; r++) B[j * 10 + r] = x[r];
+            } else if (i < j) {
+                const double lji = Kj[i];
+#pragma unroll
+                for (int r = 0; r < 10; r++) B[i * 10 + r] -= lji * x[r];
+            }
+        }
+    }
+    __syncthreads();
+    bool fin = true;
+    for (int o = lane; o < 90; o += 64) {
+        const int I = (o < 9) ? o : (o - 9) / 9;
+        const int col = (o < 9) ? 0 : 1 + (o - 9) % 9;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int k = 0;
+        for (; k + 4 <= m; k += 4) {
+            s0 = fma(KaF[k * 9 + I], B[k * 10 + col], s0);
+            s1 = fma(KaF[(k + 1) * 9 + I], B[(k + 1) * 10 + col], s1);
+            s2 = fma(KaF[(k + 2) * 9 + I], B[(k + 2) * 10 + col], s2);
+            s3 = fma(KaF[(k + 3) * 9 + I], B[(k + 3) * 10 + col], s3);
+        }
+        for (; k < m; k++) s0 = fma(KaF[k * 9 + I], B[k * 10 + col], s0);
+        const double dot = (s0 + s1) + (s2 + s3);
+        if (o < 9) {
+            const double v = Pr[o] - dot;
+            A.Palg[(int64_t)o * A.N + b] = v;
+            fin = fin && isfinite(v);
+        } else {
+            const double v = KFF[I * 9 + (col - 1)] - dot;
+            A.Cr[(int64_t)(I * 9 + (col - 1)) * A.N + b] = v;
+            fin = fin && isfinite(v);
+        }
+    }
+    double rr = 0.0;
+    for (int i = lane; i < m; i += 64) {
+        rr += rv[i] * rv[i];
+        A.y[(int64_t)i * A.count + pl] = B[i * 10];
+#pragma unroll
+        for (int J = 0; J < 9; J++) A.X[((int64_t)i * 9 + J) * A.count + pl] = B[i * 10 + 1 + J];
+        if (A.L) {
+            double* Lrow = A.L + (pl * m + i) * (int64_t)m;
+            const double* Ki = K + i * (i + 1) / 2;
+            for (int k = 0; k < m; k++) Lrow[k] = (k <= i) ? Ki[k] : 0.0;
+        }
+    }
+    if (lane == 0) A.piv[pl * m] = -1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rr += __shfl_xor(rr, off);
+    const uint64_t bad = __ballot(!fin);
+    if (lane == 0) {
+        A.rnorm[b] = sqrt(rr);
+        if (bad) A.status[b] |= HROM_PT_NONFINITE;
+    }
+}
+
+int launch_condense_spd(const CondenseArgs& a, hipStream_t s) {
+    const int m = a.m;
+    const size_t bytes = sizeof(double) * ((size_t)m * (m + 1) / 2 + 9 * m + 81 + 10 * m + 9 + m);
+    if (bytes > 160 * 1024) return HROM_E_UNSUPPORTED;
+    const dim3 grid((unsigned)a.count), block(64);
+    if (a.mixed) {
+        static bool attr = false;
+        if (!attr) {
+            hipFuncSetAttribute((const void*)k_condense_spd<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_condense_spd<float>, grid, block, bytes, s, a);
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            hipFuncSetAttribute((const void*)k_condense_spd<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_condense_spd<double>, grid, block, bytes, s, a);
+    }
+    return HROM_OK;
+}
+
+}  // namespace hrom

@@ -453,34 +453,48 @@ __device__ __forceinline__ void tangent_pair(const float* bq0, const Frags<MT>& 
             wv[e] = vl[e] * (c1 * bq[o1[e]] * bq[o2[e]] + c2 * bq[o3[e]] * bq[o4[e]] + dl[e] * c0);
         v4u Wh, Wl;
         split4<PREC>(wv, Wh, Wl);
+        // split terms outermost so that consecutive MFMAs write independent tiles
+        v4f T[MT];
+#pragma unroll
+        for (int t = 0; t < MT; t++) T[t] = LP<PREC>::mfma16(Wh, G.h[s2][t], v4f{0.f, 0.f, 0.f, 0.f});
+        if (SPLIT) {
+#pragma unroll
+            for (int t = 0; t < MT; t++) T[t] = LP<PREC>::mfma16(Wl, G.h[s2][t], T[t]);
+#pragma unroll
+            for (int t = 0; t < MT; t++) T[t] = LP<PREC>::mfma16(Wh, G.l[s2][t], T[t]);
+        }
 #pragma unroll
         for (int t = 0; t < MT; t++) {
-            v4f T = v4f{0.f, 0.f, 0.f, 0.f};
-            T = LP<PREC>::mfma16(Wh, G.h[s2][t], T);
-            if (SPLIT) {
-                T = LP<PREC>::mfma16(Wl, G.h[s2][t], T);
-                T = LP<PREC>::mfma16(Wh, G.l[s2][t], T);
-            }
-            float tv[4] = {T[0], T[1], T[2], T[3]};
+            float tv[4] = {T[t][0], T[t][1], T[t][2], T[t][3]};
             split4<PREC>(tv, Th[s2][t], Tl[s2][t]);
         }
     }
-    int idx = 0;
+    {
+        int idx = 0;
 #pragma unroll
-    for (int ti = 0; ti < MT; ti++)
+        for (int ti = 0; ti < MT; ti++)
 #pragma unroll
-        for (int tj = ti; tj < MT; tj++) {
-            acc[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Th[0][tj], Th[1][tj], acc[idx]);
-            if (SPLIT) {
+            for (int tj = ti; tj < MT; tj++, idx++)
+                acc[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Th[0][tj], Th[1][tj], acc[idx]);
+    }
+    if (SPLIT) {
+        int idx = 0;
+#pragma unroll
+        for (int ti = 0; ti < MT; ti++)
+#pragma unroll
+            for (int tj = ti; tj < MT; tj++, idx++)
                 acc[idx] = LP<PREC>::mfma32(G.l[0][ti], G.l[1][ti], Th[0][tj], Th[1][tj], acc[idx]);
+        idx = 0;
+#pragma unroll
+        for (int ti = 0; ti < MT; ti++)
+#pragma unroll
+            for (int tj = ti; tj < MT; tj++, idx++)
                 acc[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Tl[0][tj], Tl[1][tj], acc[idx]);
-            }
-            idx++;
-        }
+    }
 }
 
 template <int MT, int PREC, bool SPLIT>
-__global__ void __launch_bounds__(256, 1) k_eval_mixed(EvalArgs A) {
+__global__ void __launch_bounds__(256, (MT <= 5) ? 2 : 1) k_eval_mixed(EvalArgs A) {
     constexpr int NT = MT * (MT + 1) / 2;
     constexpr int LQ = 13;   // padded stride of the 12 scalars in LDS
     __shared__ float s_q[4][64 * LQ];

@@ -28,10 +28,10 @@ def dev():
     return P
 
 
-def make_plan(P, cls_counts, precision=0, objective=True, split=False):
+def make_plan(P, cls_counts, precision=0, objective=True, split=False, refine=False):
     from paper_2306_02687_amd import solve
     specs = [solve.upload_cluster(cl, n) for cl, n in cls_counts]
-    return P.Plan(specs, precision=precision, objective=objective, split=split)
+    return P.Plan(specs, precision=precision, objective=objective, split=split, refine=refine)
 
 
 def run_eval(P, plan, theta, F, a_list, blocks=True):
@@ -193,8 +193,10 @@ def test_mixed_vs_oracle(dev, orc, precision, split, amp):
     plan.close()
 
 
-@pytest.mark.parametrize("precision", [0, 2, 1])
-def test_backward_vs_oracle(dev, orc, precision):
+@pytest.mark.parametrize("precision,split,refine", [(0, False, False), (2, True, False),
+                                                    (1, True, False), (1, True, True),
+                                                    (2, False, False)])
+def test_backward_vs_oracle(dev, orc, precision, split, refine):
     """Adjoint gradients dL/dFbar, dL/dtheta of L = sum ||Pbar - Pbar*||^2 at
     the converged state (m = 48, Q = 384) vs the oracle's adjoint."""
     from paper_2306_02687_amd import solve
@@ -204,7 +206,7 @@ def test_backward_vs_oracle(dev, orc, precision):
     F, _, _ = make_macro_points(N, 5001, amp=0.05)
     th_star, _ = perturbed_theta(5002)
     target = orc.newton(cl, th_star, F, tol=1e-14)["Pbar"]
-    plan = make_plan(dev, [(cl, N)], precision=precision, split=True)
+    plan = make_plan(dev, [(cl, N)], precision=precision, split=split, refine=refine)
     th = solve.theta_dev(THETA_REF)
     st = solve.newton(plan, th, solve.points_to_soa(F), tol=1e-12)
     g = 2.0 * (st.Pbar - solve.points_to_soa(target))
@@ -218,9 +220,9 @@ def test_backward_vs_oracle(dev, orc, precision):
     ref = orc.backward(cl, THETA_REF, F, ref_o["a"], gref)
     egF = rel_err_points(gF.cpu().numpy().T, ref["gF"])
     egt = np.linalg.norm(gth.cpu().numpy() - ref["gtheta"]) / np.linalg.norm(ref["gtheta"])
-    print("prec", precision, "gF", egF.max(), "gtheta", egt, "a", np.abs(a_conv - ref_o["a"]).max(),
-          flush=True)
-    bound = 1e-10 if precision == 0 else 1e-5
+    print("prec", precision, "split", split, "refine", refine, "gF", egF.max(), "gtheta", egt,
+          "a", np.abs(a_conv - ref_o["a"]).max(), flush=True)
+    bound = 1e-10 if precision == 0 else (1e-5 if split or refine else 1e-3)
     assert egF.max() < bound and egt < bound
     plan.close()
 
