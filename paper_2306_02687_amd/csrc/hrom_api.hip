@@ -3,6 +3,7 @@
 // which only enqueue kernels on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 
@@ -47,6 +48,7 @@ void free_plan(Plan& p) {
     dfree(p.piv); dfree(p.y); dfree(p.X); dfree(p.Palg); dfree(p.Cr); dfree(p.S);
     dfree(p.rnorm); dfree(p.dU); dfree(p.gr); dfree(p.Lam); dfree(p.lam); dfree(p.rho);
     dfree(p.hr); dfree(p.gth);
+    dfree(p.cls_dev); dfree(p.items_kin); dfree(p.items_tan); dfree(p.counter);
 }
 
 int hip_status() { return hipGetLastError() == hipSuccess ? HROM_OK : HROM_E_HIP; }
@@ -61,6 +63,69 @@ bool refine(const Plan& p) {
 
 // power-of-two scaling of w_q A_q for the low-precision operands (w ~ 1/Q)
 float wscale_for(int Q) { return std::ldexp(1.0f, (int)std::ceil(std::log2((double)Q))); }
+
+template <typename T>
+int upload(T** dst, const std::vector<T>& v) {
+    int rc = dalloc(dst, (int64_t)v.size());
+    if (rc == HROM_OK && !v.empty() &&
+        hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
+        rc = HROM_E_HIP;
+    return rc;
+}
+
+// Device cluster table and the cost-sorted work queues of the grouped launches.
+int build_groups(Plan& p) {
+    p.grouped = p.ncl > 1;
+    std::vector<ClusterGPU> cg;
+    std::vector<WorkItem> kin, tan;
+    p.max_m = 0;
+    for (int c = 0; c < p.ncl; c++) {
+        const ClusterDev& d = p.cl[c];
+        ClusterGPU g{};
+        g.m = d.m; g.Q = d.Q; g.Qpad = d.Qpad; g.MP = d.MP; g.MT = d.MT; g.KS = d.KS;
+        g.first = d.first; g.count = d.count; g.off_a = d.off_a; g.ws_qs = d.ws_qs;
+        g.ws_khat = d.ws_khat; g.ws_L = d.ws_L;
+        g.Ghat = d.Ghat; g.Gf = d.Gf; g.w = d.w; g.phase = d.phase; g.Fhi = d.Fhi; g.Flo = d.Flo;
+        g.wscale = mixed(p) ? wscale_for(d.Q) : 1.0f;
+        cg.push_back(g);
+        p.max_m = std::max(p.max_m, d.m);
+        for (int64_t u = 0; u < (d.count + 15) / 16; u++) kin.push_back(WorkItem{c, (int)u});
+        for (int64_t u = 0; u < (d.count + 3) / 4; u++) tan.push_back(WorkItem{c, (int)u});
+    }
+    // most expensive tiles first: kinematics ~ m Q, tangent ~ MT^2 Q
+    auto cost_kin = [&](const WorkItem& w) { return (double)p.cl[w.c].m * p.cl[w.c].Q; };
+    auto cost_tan = [&](const WorkItem& w) {
+        const double mt = p.cl[w.c].MT;
+        return mt * (mt + 1) * p.cl[w.c].Q;
+    };
+    std::stable_sort(kin.begin(), kin.end(),
+                     [&](const WorkItem& x, const WorkItem& y) { return cost_kin(x) > cost_kin(y); });
+    std::stable_sort(tan.begin(), tan.end(),
+                     [&](const WorkItem& x, const WorkItem& y) { return cost_tan(x) > cost_tan(y); });
+    p.n_kin = (int)kin.size();
+    p.n_tan = (int)tan.size();
+    int ncu = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p.device) == hipSuccess && prop.multiProcessorCount > 0)
+        ncu = prop.multiProcessorCount;
+    p.persistent_grid = std::min(p.n_tan, 2 * ncu);
+    int rc = upload(&p.cls_dev, cg);
+    if (rc == HROM_OK) rc = upload(&p.items_kin, kin);
+    if (rc == HROM_OK) rc = upload(&p.items_tan, tan);
+    if (rc == HROM_OK) rc = dalloc(&p.counter, 1);
+    return rc;
+}
+
+GroupCall group_call(const Plan& p) {
+    GroupCall g{};
+    g.cls = p.cls_dev;
+    g.ncl = p.ncl;
+    g.N = p.N;
+    g.counter = p.counter;
+    g.mixed = mixed(p) ? 1 : 0;
+    g.objective = (p.flags & HROM_OBJECTIVE) ? 1 : 0;
+    return g;
+}
 
 }  // namespace
 
@@ -179,11 +244,13 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
     if (rc == HROM_OK) rc = dalloc(&p.rho, off_a);
     if (rc == HROM_OK) rc = dalloc(&p.hr, 9 * n);
     if (rc == HROM_OK) rc = dalloc(&p.gth, 4 * n);
+    if (rc == HROM_OK) rc = build_groups(p);
     if (rc != HROM_OK) {
         free_plan(p);
         delete h;
         return rc;
     }
+    set_kernel_attributes();
     *out = h;
     return HROM_OK;
 }
@@ -218,7 +285,19 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
     PointArgs pa{p.N, (p.flags & HROM_OBJECTIVE) ? 1 : 0, Fbar, p.Fr, p.polar, status};
     launch_prepare(pa, stream);
     const size_t tsz = mixed(p) ? sizeof(float) : sizeof(double);
+    if (p.grouped) {
+        GroupCall g = group_call(p);
+        g.theta = theta; g.Fr = p.Fr; g.a = a; g.qs = p.qs; g.Khat = p.Khat;
+        g.r = p.r; g.Pr = p.Pr; g.status = status;
+        g.items = p.items_kin; g.nitems = p.n_kin;
+        int rc = launch_kin_grouped(mixed(p) ? 1 : 0, g, stream);
+        g.items = p.items_tan; g.nitems = p.n_tan;
+        if (rc == HROM_OK)
+            rc = launch_tan_persistent(p.prec, (p.flags & HROM_SPLIT) != 0, g, p.persistent_grid, stream);
+        if (rc != HROM_OK) return rc;
+    }
     for (const auto& c : p.cl) {
+        if (p.grouped) break;
         EvalArgs e{};
         e.m = c.m; e.Q = c.Q; e.Qpad = c.Qpad; e.MP = c.MP; e.MT = c.MT; e.KS = c.KS;
         e.first = c.first; e.count = c.count; e.N = p.N;
@@ -264,6 +343,14 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
     Plan& p = plan->p;
     if (p.stage < 1) return HROM_E_ORDER;
     const size_t tsz = mixed(p) ? sizeof(float) : sizeof(double);
+    if (p.grouped) {
+        GroupCall g = group_call(p);
+        g.Khat = p.Khat; g.r = p.r; g.Pr = p.Pr; g.status = status;
+        g.L = refine(p) ? p.L : nullptr; g.piv = p.piv; g.y = p.y; g.X = p.X;
+        g.Palg = p.Palg; g.Cr = p.Cr; g.rnorm = p.rnorm;
+        const int rc = launch_condense_grouped(g, p.max_m, stream);
+        if (rc != HROM_OK) return rc;
+    }
     for (const auto& c : p.cl) {
         CondenseArgs ca{};
         ca.m = c.m; ca.MT = c.MT; ca.res_t = c.res_t; ca.res_c = c.res_c; ca.mixed = mixed(p);
@@ -276,7 +363,7 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
         ca.Palg = p.Palg; ca.Cr = p.Cr; ca.rnorm = p.rnorm; ca.status = status;
         ca.kscale = mixed(p) ? 1.0f / wscale_for(c.Q) : 1.0f;
         // SPD path on the packed triangle; non-positive pivots finish on the LU path
-        int rc = launch_condense_spd(ca, stream);
+        int rc = p.grouped ? HROM_OK : launch_condense_spd(ca, stream);
         if (rc == HROM_OK) rc = launch_unpack_condense(ca, 2, stream);
         if (rc != HROM_OK) return rc;
     }
@@ -302,6 +389,13 @@ static int update_impl(Plan& p, const double* dFbar, double tol, double* a, cons
     u.status = status;
     u.tol = tol;
     launch_stretch_increment(u, stream);
+    if (p.grouped) {
+        GroupCall g = group_call(p);
+        g.y = p.y; g.X = p.X; g.dU = p.dU; g.dFbar = dFbar; g.rnorm = p.rnorm; g.tol = tol;
+        g.status = const_cast<int*>(status); g.a_out = a;
+        launch_update_grouped(g, p.a_len, stream);
+        return hip_status();
+    }
     for (const auto& c : p.cl) {
         u.m = c.m;
         u.first = c.first;
@@ -355,6 +449,27 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
     const int objective = (p.flags & HROM_OBJECTIVE) ? 1 : 0;
     BwPointArgs bp{p.N, objective, p.polar, p.S, gPbar, p.gr, p.Lam, p.hr, gFbar};
     launch_bw_pullback(bp, stream);
+    if (p.grouped) {
+        GroupCall g = group_call(p);
+        g.theta = theta; g.Fr = p.Fr; g.a = a; g.lam = p.lam; g.gr = p.gr; g.hr = p.hr;
+        g.gth = p.gth; g.rho = p.rho; g.status = status; g.X = p.X;
+        g.items = p.items_kin; g.nitems = p.n_kin;
+        launch_lambda_grouped(g, p.a_len, stream);
+        if (refine(p)) {
+            g.with_rho = 1;
+            launch_backward_grouped(g, stream);
+            for (const auto& c : p.cl) {
+                RefineArgs ra{c.m, c.first, c.count, p.L + c.ws_L, p.piv + c.off_a, status,
+                              p.rho + c.off_a, p.lam + c.off_a};
+                launch_refine_lambda(ra, stream);
+            }
+        }
+        g.with_rho = 0;
+        launch_backward_grouped(g, stream);
+        launch_bw_pushforward(bp, stream);
+        launch_reduce_theta(p.N, p.gth, gtheta, stream);
+        return hip_status();
+    }
     for (const auto& c : p.cl) {
         LambdaArgs la{c.m, c.first, c.count, p.N, p.X + 9 * c.off_a, p.gr, p.lam + c.off_a};
         launch_lambda(la, stream);

@@ -37,6 +37,9 @@ struct ClusterDev {
     uint16_t* Flo;         // same, lo part (Ghat - hi)
 };
 
+struct ClusterGPU;
+struct WorkItem;
+
 struct Plan {
     int ncl = 0;
     int64_t N = 0;
@@ -69,6 +72,15 @@ struct Plan {
     double* gth = nullptr;     // [4][N] per-point theta gradients
     int64_t khat_len = 0, L_len = 0, qs_len = 0;
     int stage = 0;             // 0 = nothing, 1 = evaluated, 2 = condensed
+    // grouped launches (more than one cluster)
+    bool grouped = false;
+    int max_m = 0;
+    int persistent_grid = 512;
+    ClusterGPU* cls_dev = nullptr;
+    WorkItem* items_kin = nullptr;   // 16-point tiles, decreasing cost
+    WorkItem* items_tan = nullptr;   // 4-point tiles, decreasing cost
+    int n_kin = 0, n_tan = 0;
+    int* counter = nullptr;
 };
 
 // ---------------------------------------------------------------- kernels
@@ -234,5 +246,73 @@ struct LayoutArgs {
     uint16_t* Flo;
 };
 void launch_build_layouts(const LayoutArgs& a, hipStream_t s);
+
+
+// ---------------------------------------------------------------- grouped launches
+// Several RVE clusters in one launch: every kernel body runs on one work item
+// (cluster c, tile `unit` of that cluster); the per-cluster constants live in
+// a device array built at plan creation, the per-call pointers in GroupCall.
+struct ClusterGPU {
+    int m, Q, Qpad, MP, MT, KS;
+    int64_t first, count, off_a, ws_qs, ws_khat, ws_L;
+    const double* Ghat;
+    const double* Gf;
+    const double* w;
+    const int* phase;
+    const uint16_t* Fhi;
+    const uint16_t* Flo;
+    float wscale;
+};
+
+struct WorkItem {
+    int c;      // cluster
+    int unit;   // tile of the cluster (16 points for the kinematics and adjoint
+                // kernels, 4 points for the tangent contraction)
+};
+
+struct GroupCall {
+    const ClusterGPU* cls;
+    int ncl;
+    const WorkItem* items;
+    int nitems;
+    int* counter;          // work-queue head of the persistent tangent kernel
+    int64_t N;
+    const double* theta;
+    const double* Fr;
+    const double* a;
+    void* qs;
+    void* Khat;
+    double* r;
+    double* Pr;
+    int* status;
+    // adjoint
+    const double* lam;
+    const double* gr;
+    double* hr;
+    double* gth;
+    double* rho;
+    int mixed, objective, with_rho;
+    // condensation
+    double* L;
+    int* piv;
+    double* y;
+    double* X;
+    double* Palg;
+    double* Cr;
+    double* rnorm;
+    // update
+    const double* dFbar;
+    const double* dU;
+    double tol;
+    double* a_out;
+};
+
+int launch_kin_grouped(int mixed, const GroupCall& g, hipStream_t s);
+int launch_tan_persistent(int prec, bool split, const GroupCall& g, int grid, hipStream_t s);
+int launch_backward_grouped(const GroupCall& g, hipStream_t s);
+int launch_condense_grouped(const GroupCall& g, int max_m, hipStream_t s);
+void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);
+void launch_lambda_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);
+void set_kernel_attributes();
 
 }  // namespace hrom

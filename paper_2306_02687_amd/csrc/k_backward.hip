@@ -44,19 +44,28 @@ __device__ __forceinline__ void nh_apply(const T* Fi, T mu, T la, T ell, const T
 // adjoint run one (point, ECM point) pair per thread; the refinement
 // residual rho = G^T (w A v) is a third FP64 GEMM.  Per-point sums over the
 // ECM points (h_r, dL/dtheta) reduce in a fixed order.
-__global__ void __launch_bounds__(256) k_backward_b(BackwardArgs A) {
-    constexpr int PT = 16, QC = 16, LD = 17;
-    __shared__ double sA[kMaxModes + 4][PT];
-    __shared__ double sL[kMaxModes + 4][PT];
-    __shared__ double sF[QC * 9][LD];
-    __shared__ double sV[QC * 9][LD];
-    __shared__ double sU[9][PT];
-    __shared__ double sG[9][PT];
-    __shared__ int sbits[PT];
+struct BwLds {
+    double sA[kMaxModes + 4][16];
+    double sL[kMaxModes + 4][16];
+    double sF[16 * 9][17];
+    double sV[16 * 9][17];
+    double sU[9][16];
+    double sG[9][16];
+    int sbits[16];
+};
+
+__device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
+    constexpr int PT = 16, QC = 16;
+    auto& sA = Ls.sA;
+    auto& sL = Ls.sL;
+    auto& sF = Ls.sF;
+    auto& sV = Ls.sV;
+    auto& sU = Ls.sU;
+    auto& sG = Ls.sG;
+    auto& sbits = Ls.sbits;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, c = lane & 15;
     const int m = A.m, KS = A.KS, MP = A.MP, MT = A.MT;
-    const int64_t p0 = (int64_t)blockIdx.x * PT;
     const int np = (int)min((int64_t)PT, A.count - p0);
     if (tid < PT) sbits[tid] = 0;
     for (int e = tid; e < 4 * KS * PT; e += 256) {
@@ -244,6 +253,31 @@ __global__ void __launch_bounds__(256) k_backward_b(BackwardArgs A) {
     }
     __syncthreads();
     if (tid < np && sbits[tid]) A.status[A.first + p0 + tid] |= HROM_PT_JNONPOS;
+}
+
+__global__ void __launch_bounds__(256) k_backward_b(BackwardArgs A) {
+    __shared__ BwLds Ls;
+    bw_body(A, (int64_t)blockIdx.x * 16, Ls);
+}
+
+// adjoint re-evaluation of every cluster in one launch (16-point tiles)
+__global__ void __launch_bounds__(256) k_backward_grouped(GroupCall G) {
+    __shared__ BwLds Ls;
+    const WorkItem w = G.items[blockIdx.x];
+    const ClusterGPU& C = G.cls[w.c];
+    BackwardArgs A;
+    A.m = C.m; A.Q = C.Q; A.Qpad = C.Qpad; A.mixed = G.mixed; A.objective = G.objective;
+    A.with_rho = G.with_rho; A.first = C.first; A.count = C.count; A.N = G.N;
+    A.GT = nullptr; A.Ghat = C.Ghat; A.Gf = C.Gf; A.MP = C.MP; A.MT = C.MT; A.KS = C.KS;
+    A.w = C.w; A.phase = C.phase; A.theta = G.theta; A.Fr = G.Fr; A.a = G.a + C.off_a;
+    A.lam = G.lam + C.off_a; A.gr = G.gr; A.hr = G.hr; A.gth = G.gth;
+    A.rho = G.rho ? G.rho + C.off_a : nullptr; A.status = G.status;
+    bw_body(A, (int64_t)w.unit * 16, Ls);
+}
+
+int launch_backward_grouped(const GroupCall& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_backward_grouped, dim3(g.nitems), dim3(256), 0, s, g);
+    return HROM_OK;
 }
 
 int launch_backward_b(const BackwardArgs& a, hipStream_t s) {

@@ -426,11 +426,9 @@ namespace hrom {
 // Cholesky meets a non-positive pivot is only flagged HROM_PT_NOT_SPD here and
 // finished by k_unpack_condense (mode 2, LU with partial pivoting).
 template <typename TT>
-__global__ void __launch_bounds__(64) k_condense_spd(CondenseArgs A) {
-    extern __shared__ double sm[];
+__device__ void condense_spd_body(const CondenseArgs& A, int64_t pl, double* sm) {
     const int m = A.m, lane = threadIdx.x;
     const int g = lane >> 4, c = lane & 15;
-    const int64_t pl = blockIdx.x;
     const int64_t b = A.first + pl;
     const int MT = A.MT, NT = MT * (MT + 1) / 2;
     double* K = sm;                          // packed lower, m (m + 1) / 2
@@ -585,6 +583,58 @@ __global__ void __launch_bounds__(64) k_condense_spd(CondenseArgs A) {
     }
 }
 
+template <typename TT>
+__global__ void __launch_bounds__(64) k_condense_spd(CondenseArgs A) {
+    extern __shared__ double sm[];
+    condense_spd_body<TT>(A, (int64_t)blockIdx.x, sm);
+}
+
+// every macro point of every cluster in one launch: block b = macro point b
+template <typename TT>
+__global__ void __launch_bounds__(64) k_condense_grouped(GroupCall G) {
+    extern __shared__ double sm[];
+    const int64_t b = blockIdx.x;
+    int c = 0;
+    while (c + 1 < G.ncl && b >= G.cls[c + 1].first) c++;
+    const ClusterGPU& C = G.cls[c];
+    CondenseArgs A;
+    A.m = C.m; A.MT = C.MT; A.res_t = 0; A.res_c = 0; A.mixed = G.mixed;
+    A.first = C.first; A.count = C.count; A.N = G.N;
+    A.Khat = (const char*)G.Khat + sizeof(TT) * (size_t)C.ws_khat;
+    A.r = G.r + C.off_a; A.Pr = G.Pr;
+    A.L = G.L ? G.L + C.ws_L : nullptr; A.piv = G.piv + C.off_a;
+    A.y = G.y + C.off_a; A.X = G.X + 9 * C.off_a;
+    A.Palg = G.Palg; A.Cr = G.Cr; A.rnorm = G.rnorm; A.status = G.status;
+    A.kscale = 1.0f / C.wscale;
+    A.outKaa = A.outKaF = A.outKFF = nullptr;
+    condense_spd_body<TT>(A, b - C.first, sm);
+}
+
+int launch_condense_grouped(const GroupCall& g, int max_m, hipStream_t s) {
+    const size_t bytes = sizeof(double) *
+        ((size_t)max_m * (max_m + 1) / 2 + 9 * max_m + 81 + 10 * max_m + 9 + max_m);
+    if (bytes > 160 * 1024) return HROM_E_UNSUPPORTED;
+    const dim3 grid((unsigned)g.N), block(64);
+    if (g.mixed) {
+        static bool attr = false;
+        if (!attr) {
+            hipFuncSetAttribute((const void*)k_condense_grouped<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_condense_grouped<float>, grid, block, bytes, s, g);
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            hipFuncSetAttribute((const void*)k_condense_grouped<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_condense_grouped<double>, grid, block, bytes, s, g);
+    }
+    return HROM_OK;
+}
+
 int launch_condense_spd(const CondenseArgs& a, hipStream_t s) {
     const int m = a.m;
     const size_t bytes = sizeof(double) * ((size_t)m * (m + 1) / 2 + 9 * m + 81 + 10 * m + 9 + m);
@@ -610,4 +660,18 @@ int launch_condense_spd(const CondenseArgs& a, hipStream_t s) {
     return HROM_OK;
 }
 
+}  // namespace hrom
+
+namespace hrom {
+// dynamic-LDS limits, set once before any launch (also before graph capture)
+void set_kernel_attributes() {
+    const int lim = 160 * 1024;
+    hipFuncSetAttribute((const void*)k_unpack_condense<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_unpack_condense<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_condense_spd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_condense_spd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_condense_grouped<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_condense_grouped<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void*)k_refine_lambda, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+}
 }  // namespace hrom

@@ -59,18 +59,26 @@ __device__ __forceinline__ void tangent_row(const T* Fi, T c0, T c1, T c2, T* W)
 
 
 // ============================================================== kinematics
+struct KinLds {
+    double sA[kMaxModes + 4][16];
+    double sF[16 * 9][17];
+    double sWP[16 * 9][17];
+    double sU[9][16];
+    int sbits[16];
+};
+
+// the 16 macro points p0 .. p0+15 of the cluster described by A
 template <bool MIXED>
-__global__ void __launch_bounds__(256) k_kin(EvalArgs A) {
-    constexpr int PT = 16, QC = 16, LD = 17;
-    __shared__ double sA[kMaxModes + 4][PT];
-    __shared__ double sF[QC * 9][LD];
-    __shared__ double sWP[QC * 9][LD];
-    __shared__ double sU[9][PT];
-    __shared__ int sbits[PT];
+__device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
+    constexpr int PT = 16, QC = 16;
+    auto& sA = L.sA;
+    auto& sF = L.sF;
+    auto& sWP = L.sWP;
+    auto& sU = L.sU;
+    auto& sbits = L.sbits;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, c = lane & 15;
     const int m = A.m, KS = A.KS, MP = A.MP, MT = A.MT;
-    const int64_t p0 = (int64_t)blockIdx.x * PT;
     const int np = (int)min((int64_t)PT, A.count - p0);
     if (tid < PT) sbits[tid] = 0;
     __syncthreads();
@@ -214,6 +222,12 @@ __global__ void __launch_bounds__(256) k_kin(EvalArgs A) {
     if (tid < np && sbits[tid]) A.status[A.first + p0 + tid] |= sbits[tid];
 }
 
+template <bool MIXED>
+__global__ void __launch_bounds__(256) k_kin(EvalArgs A) {
+    __shared__ KinLds L;
+    kin_body<MIXED>(A, (int64_t)blockIdx.x * 16, L);
+}
+
 int launch_kin(int mixed, const EvalArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(a.count, 16)), block(256);
     if (a.MT > 8) return HROM_E_UNSUPPORTED;
@@ -275,14 +289,14 @@ __device__ __forceinline__ void tangent_block_f64(const double* st, int qq, cons
     row_step_f64<8, MT>(Fi, c0, c1, c2, Gc, acc);
 }
 
+// the 4 macro points pl0 .. pl0+3 of the cluster, one per wavefront
 template <int MT>
-__global__ void __launch_bounds__(256, 1) k_eval_f64(EvalArgs A) {
+__device__ void tan_f64_body(const EvalArgs& A, int64_t pl0, double (*s_st)[12 * 64]) {
     constexpr int NT = MT * (MT + 1) / 2;
     constexpr bool PF = (MT <= 5);   // register budget of the double buffer
-    __shared__ double s_st[4][12 * 64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
-    int64_t pl = (int64_t)blockIdx.x * 4 + wave;
+    int64_t pl = pl0 + wave;
     const bool valid = pl < A.count;
     if (!valid) pl = A.count - 1;
     const int MP = A.MP;
@@ -324,6 +338,12 @@ __global__ void __launch_bounds__(256, 1) k_eval_f64(EvalArgs A) {
     double* kh = (double*)A.Khat + (int64_t)pl * NT * 256 + lane * 4;
 #pragma unroll
     for (int i = 0; i < NT; i++) *(v4d*)(kh + i * 256) = acc[i];
+}
+
+template <int MT>
+__global__ void __launch_bounds__(256, 1) k_eval_f64(EvalArgs A) {
+    __shared__ double s_st[4][12 * 64];
+    tan_f64_body<MT>(A, (int64_t)blockIdx.x * 4, s_st);
 }
 
 int launch_eval_f64(int MT, const EvalArgs& a, hipStream_t s) {
@@ -493,14 +513,15 @@ __device__ __forceinline__ void tangent_pair(const float* bq0, const Frags<MT>& 
     }
 }
 
+constexpr int kLQ = 13;   // padded stride of the 12 tangent scalars in LDS
+
 template <int MT, int PREC, bool SPLIT>
-__global__ void __launch_bounds__(256, (MT <= 5) ? 2 : 1) k_eval_mixed(EvalArgs A) {
+__device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, float (*s_q)[64 * kLQ]) {
     constexpr int NT = MT * (MT + 1) / 2;
-    constexpr int LQ = 13;   // padded stride of the 12 scalars in LDS
-    __shared__ float s_q[4][64 * LQ];
+    constexpr int LQ = kLQ;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
-    int64_t pl = (int64_t)blockIdx.x * 4 + wave;
+    int64_t pl = pl0 + wave;
     const bool valid = pl < A.count;
     if (!valid) pl = A.count - 1;
     float* sq = s_q[wave];
@@ -556,6 +577,12 @@ __global__ void __launch_bounds__(256, (MT <= 5) ? 2 : 1) k_eval_mixed(EvalArgs 
     for (int i = 0; i < NT; i++) *(v4f*)(kh + i * 256) = acc[i];
 }
 
+template <int MT, int PREC, bool SPLIT>
+__global__ void __launch_bounds__(256, (MT <= 5) ? 2 : 1) k_eval_mixed(EvalArgs A) {
+    __shared__ float s_q[4][64 * kLQ];
+    tan_mixed_body<MT, PREC, SPLIT>(A, (int64_t)blockIdx.x * 4, s_q);
+}
+
 template <int PREC, bool SPLIT>
 static int launch_mixed_t(int MT, const EvalArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(a.count, 4)), block(256);
@@ -579,6 +606,91 @@ int launch_eval_mixed(int MT, int prec, bool split, const EvalArgs& a, hipStream
         return split ? launch_mixed_t<HROM_MIXED_FP16, true>(MT, a, s)
                      : launch_mixed_t<HROM_MIXED_FP16, false>(MT, a, s);
     return HROM_E_INVALID;
+}
+
+// ============================================================== grouped launches
+__device__ inline EvalArgs group_eval_args(const GroupCall& G, int c, size_t tsz) {
+    const ClusterGPU& C = G.cls[c];
+    EvalArgs A;
+    A.m = C.m; A.Q = C.Q; A.Qpad = C.Qpad; A.MP = C.MP; A.MT = C.MT; A.KS = C.KS;
+    A.first = C.first; A.count = C.count; A.N = G.N;
+    A.Ghat = C.Ghat; A.Gf = C.Gf; A.w = C.w; A.phase = C.phase; A.Fhi = C.Fhi; A.Flo = C.Flo;
+    A.theta = G.theta; A.Fr = G.Fr; A.a = G.a + C.off_a;
+    A.qs = (char*)G.qs + tsz * (size_t)C.ws_qs;
+    A.Khat = (char*)G.Khat + tsz * (size_t)C.ws_khat;
+    A.r = G.r + C.off_a; A.Pr = G.Pr; A.status = G.status;
+    A.wscale = C.wscale;
+    return A;
+}
+
+// kinematics of every cluster in one launch: one 16-point tile per workgroup
+template <bool MIXED>
+__global__ void __launch_bounds__(256) k_kin_grouped(GroupCall G) {
+    __shared__ KinLds L;
+    const WorkItem w = G.items[blockIdx.x];
+    const EvalArgs A = group_eval_args(G, w.c, MIXED ? sizeof(float) : sizeof(double));
+    kin_body<MIXED>(A, (int64_t)w.unit * 16, L);
+}
+
+int launch_kin_grouped(int mixed, const GroupCall& g, hipStream_t s) {
+    if (mixed) hipLaunchKernelGGL(k_kin_grouped<true>, dim3(g.nitems), dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_kin_grouped<false>, dim3(g.nitems), dim3(256), 0, s, g);
+    return HROM_OK;
+}
+
+__global__ void k_reset_counter(int* counter) { *counter = 0; }
+
+// One persistent launch for the tangent contraction of every cluster: the
+// workgroups pull 4-point tiles from a work queue sorted by decreasing cost
+// (largest m first), so the uneven clusters balance over the CUs.  Every
+// workgroup leaves when the queue is exhausted.
+template <int PREC, bool SPLIT>
+__global__ void __launch_bounds__(256, 1) k_tan_persistent(GroupCall G) {
+    __shared__ float s_q[4][64 * kLQ];
+    __shared__ double s_st[4][12 * 64];
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(G.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= G.nitems) break;
+        const WorkItem w = G.items[it];
+        const int64_t pl0 = (int64_t)w.unit * 4;
+        if constexpr (PREC == HROM_FP64) {
+            const EvalArgs A = group_eval_args(G, w.c, sizeof(double));
+            switch (A.MT) {
+                case 2: tan_f64_body<2>(A, pl0, s_st); break;
+                case 3: tan_f64_body<3>(A, pl0, s_st); break;
+                case 4: tan_f64_body<4>(A, pl0, s_st); break;
+                case 5: tan_f64_body<5>(A, pl0, s_st); break;
+                case 6: tan_f64_body<6>(A, pl0, s_st); break;
+                default: tan_f64_body<7>(A, pl0, s_st); break;
+            }
+        } else {
+            const EvalArgs A = group_eval_args(G, w.c, sizeof(float));
+            switch (A.MT) {
+                case 2: tan_mixed_body<2, PREC, SPLIT>(A, pl0, s_q); break;
+                case 3: tan_mixed_body<3, PREC, SPLIT>(A, pl0, s_q); break;
+                case 4: tan_mixed_body<4, PREC, SPLIT>(A, pl0, s_q); break;
+                case 5: tan_mixed_body<5, PREC, SPLIT>(A, pl0, s_q); break;
+                case 6: tan_mixed_body<6, PREC, SPLIT>(A, pl0, s_q); break;
+                default: tan_mixed_body<7, PREC, SPLIT>(A, pl0, s_q); break;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+int launch_tan_persistent(int prec, bool split, const GroupCall& g, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, g.counter);
+    const dim3 gr(grid), bl(256);
+    if (prec == HROM_FP64) hipLaunchKernelGGL((k_tan_persistent<HROM_FP64, false>), gr, bl, 0, s, g);
+    else if (prec == HROM_MIXED_BF16 && split) hipLaunchKernelGGL((k_tan_persistent<HROM_MIXED_BF16, true>), gr, bl, 0, s, g);
+    else if (prec == HROM_MIXED_BF16) hipLaunchKernelGGL((k_tan_persistent<HROM_MIXED_BF16, false>), gr, bl, 0, s, g);
+    else if (split) hipLaunchKernelGGL((k_tan_persistent<HROM_MIXED_FP16, true>), gr, bl, 0, s, g);
+    else hipLaunchKernelGGL((k_tan_persistent<HROM_MIXED_FP16, false>), gr, bl, 0, s, g);
+    return HROM_OK;
 }
 
 }  // namespace hrom
