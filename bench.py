@@ -71,10 +71,13 @@ def run_gpu(prec_name, cl, F, N, steps, warmup, split=True):
     from hrom_inputs import THETA_REF
     from paper_2306_02687_amd import solve
 
+    from paper_2306_02687_amd import tune
+
     plan = P.Plan([solve.upload_cluster(cl, N)], precision=PREC[prec_name], split=split)
     th = solve.theta_dev(THETA_REF)
     Fd = solve.points_to_soa(F)
     st = solve.State(plan)
+    tuned = tune.autotune(plan, th, Fd, st.a, use_cache=False)
     # bring the ROM state near convergence (untimed set-up)
     for _ in range(2):
         plan.eval(th, Fd, st.a, st.status)
@@ -110,7 +113,8 @@ def run_gpu(prec_name, cl, F, N, steps, warmup, split=True):
     plan.condense(st.Pbar, st.Cbar, st.rnorm, st.status)
     torch.cuda.synchronize()
     out = dict(wall=wall, eval_ms=eval_ms, a=st.a.clone(), Pbar=st.Pbar.clone(),
-               Cbar=st.Cbar.clone(), status=int(st.status.max().item()))
+               Cbar=st.Cbar.clone(), status=int(st.status.max().item()),
+               variant=tuned["variant"], tune_ms={str(k): v for k, v in tuned["ms"].items()})
     plan.close()
     del st
     torch.cuda.empty_cache()
@@ -137,8 +141,90 @@ def cpu_baseline(cl, F, budget_s=12.0):
     return n, dt, threads
 
 
+def run_batched(args):
+    """Eight uneven RVE clusters (m in {8..96}, Q = 6 m, Zipf(1.1) split of the
+    macro points), one HIP graph of 10 monolithic iterations (evaluate,
+    condense, update with dFbar_k), mixed and FP64."""
+    import torch
+
+    import paper_2306_02687_amd as P
+    from hrom_inputs import THETA_REF, make_cluster, make_increments, make_macro_points, zipf_counts
+    from paper_2306_02687_amd import solve, tune
+
+    N, K = args.N if args.N != 131072 else 262144, 10
+    ms = [8, 16, 24, 32, 48, 64, 80, 96]
+    counts = zipf_counts(N, len(ms), 1.1)
+    cls = [make_cluster(m, 6 * m, 3000 + i) for i, m in enumerate(ms)]
+    F, R, _ = make_macro_points(N, 3100, amp=0.05)
+    dF = make_increments(R, K, 3200, amp=0.005)
+    Fk = [F]
+    for k in range(K - 1):
+        Fk.append(Fk[-1] + dF[k])
+    Fd = [solve.points_to_soa(x) for x in Fk]
+    dFd = [solve.points_to_soa(x) for x in dF]
+    del Fk
+    th = solve.theta_dev(THETA_REF)
+    res = {}
+    for name, prec, split in (("mixed", PREC[args.precision], True), ("fp64", 0, False)):
+        print(f"[bench] batched {name}", file=sys.stderr, flush=True)
+        plan = P.Plan([solve.upload_cluster(c, n) for c, n in zip(cls, counts)],
+                      precision=prec, split=split)
+        a = plan.zeros_modes()
+        st = plan.status()
+        Pb, Cb = plan.zeros_points(9), plan.zeros_points(81)
+        rn = torch.zeros(N, dtype=torch.float64, device="cuda")
+        tuned = tune.autotune(plan, th, Fd[0], a, use_cache=False)
+
+        def iterations():
+            for k in range(K):
+                plan.eval(th, Fd[k], a, st)
+                plan.condense(Pb, Cb, rn, st)
+                plan.update(dFd[k], a, st)
+
+        iterations()   # eager warm-up
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                iterations()
+        torch.cuda.synchronize()
+        reps = max(1, args.steps // 5)
+        a.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            a.zero_()
+            g.replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = dict(ms_per_graph=dt * 1e3, value=N * K / dt, variant=tuned["variant"],
+                         Cbar=Cb.cpu().numpy(), Pbar=Pb.cpu().numpy(),
+                         status=int(st.max().item()))
+        plan.close()
+        torch.cuda.empty_cache()
+    eC = (np.linalg.norm(res["mixed"]["Cbar"] - res["fp64"]["Cbar"], axis=0)
+          / np.linalg.norm(res["fp64"]["Cbar"], axis=0))
+    line = {"metric": "RVE point-evals/s, batched uneven clusters, graph of 10 monolithic iterations",
+            "value": res["mixed"]["value"], "unit": "point-evals/s", "n_gpus": 1,
+            "ms_per_graph": res["mixed"]["ms_per_graph"], "higher_is_better": True,
+            "dtype": f"{args.precision} MFMAx3 split + fp32 tangent + fp64", "data": "synthetic",
+            "config": {"workload": f"{N} macro points over 8 clusters m={ms}, Q=6m, Zipf(1.1) "
+                                   f"counts {counts}, 10 monolithic iterations in one HIP graph"},
+            "fp64": {"value": res["fp64"]["value"], "ms_per_graph": res["fp64"]["ms_per_graph"]},
+            "speedup_mixed_over_fp64": res["fp64"]["ms_per_graph"] / res["mixed"]["ms_per_graph"],
+            "mixed_vs_fp64_Cbar_rel_err_max": float(eC.max()),
+            "variants": {"mixed": res["mixed"]["variant"], "fp64": res["fp64"]["variant"]},
+            "status_max": max(res["mixed"]["status"], res["fp64"]["status"])}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "batched"],
+                    help="mixed: the headline (m=64, Q=512) step; batched: uneven clusters")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -150,7 +236,20 @@ def main():
     ap.add_argument("--amp", type=float, default=0.05)
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe > 0:
+        import torch
+        n = int(args.copy_probe * 2 ** 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read_per_launch": 8 * n,
+                          "copy_probe_bytes_written_per_launch": 8 * n}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hyper-reduced RVE evaluation is "
               "sharded by macro points across GPUs with no exchange but a 4-value "
@@ -161,6 +260,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "batched":
+        run_batched(args)
+        return
     N, m, Q = args.N, args.m, args.Q
     print(f"[bench] building inputs N={N} m={m} Q={Q}", file=sys.stderr, flush=True)
     cl, F = build_inputs(N, m, Q, args.amp, 4000)
@@ -219,6 +321,7 @@ def main():
                      "flops_per_point": eval_flops_per_point(m, Q)},
         "step_tflops": step_flops_per_point(m, Q) * N / (ms_step * 1e-3) / 1e12,
         "status_max": res["status"],
+        "tuned_variant": res["variant"], "variant_eval_ms": res["tune_ms"],
         "fp64": fp64,
         "cpu_baseline": cpu,
     }

@@ -145,6 +145,15 @@ int hrom_newton(hrom_plan plan, const double* theta, const double* Fbar, double*
 int hrom_backward(hrom_plan plan, const double* theta, const double* a, const double* gPbar,
                   double* gFbar, double* gtheta, int32_t* status, hipStream_t stream);
 
+/* Launch variants of the tangent contraction, chosen by the autotuner.
+ * Single-cluster plans: bit 0 asks for one wavefront per SIMD instead of two
+ * (mixed kernels), bit 1 turns off the double-buffered Ghat loads.  Plans with
+ * several clusters: the persistent launch uses (variant + 1) x #CUs
+ * workgroups.  c = -1 applies to every cluster.  Results do not depend on the
+ * variant (same arithmetic, same order). */
+int32_t hrom_num_variants(void);
+int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant);
+
 const char* hrom_strerror(int code);
 
 #ifdef __cplusplus

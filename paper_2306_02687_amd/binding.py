@@ -27,7 +27,8 @@ OBJECTIVE, SPLIT, REFINE = 1, 2, 4
 OFF_A, OFF_KAA, OFF_KAF = 0, 1, 2
 
 EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_eval",
-            "hrom_condense", "hrom_update", "hrom_newton", "hrom_backward", "hrom_strerror")
+            "hrom_condense", "hrom_update", "hrom_newton", "hrom_backward", "hrom_strerror",
+            "hrom_num_variants", "hrom_plan_set_variant")
 
 
 class HromError(RuntimeError):
@@ -61,6 +62,9 @@ def load(path: str = LIB_PATH):
     L.hrom_update.argtypes = [P, P, d, P, P, P]
     L.hrom_newton.argtypes = [P, P, P, P, d, i32, P, P, P, P, P]
     L.hrom_backward.argtypes = [P, P, P, P, P, P, P, P]
+    L.hrom_num_variants.argtypes = []
+    L.hrom_num_variants.restype = i32
+    L.hrom_plan_set_variant.argtypes = [P, i32, i32]
     L.hrom_strerror.argtypes = [C.c_int]
     L.hrom_strerror.restype = C.c_char_p
     _lib = L
@@ -160,6 +164,14 @@ class Plan:
 
     def status(self):
         return torch.zeros(self.N, dtype=torch.int32, device=self._dev())
+
+    def set_variant(self, variant: int, cluster: int = -1):
+        _check(load().hrom_plan_set_variant(self._h, int(cluster), int(variant)),
+               "hrom_plan_set_variant")
+
+    @staticmethod
+    def num_variants() -> int:
+        return int(load().hrom_num_variants())
 
     # ------------------------------------------------------------ entry points
     def eval(self, theta, Fbar, a, status, r=None, Pr=None, Kaa=None, KaF=None, KFF=None,

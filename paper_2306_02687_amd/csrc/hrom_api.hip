@@ -255,6 +255,25 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
     return HROM_OK;
 }
 
+int32_t hrom_num_variants(void) { return 4; }
+
+int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant) {
+    if (!plan || variant < 0 || variant >= 4 || c < -1 || c >= plan->p.ncl) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    if (p.grouped) {
+        // one persistent launch for every cluster: the variant picks its grid
+        int ncu = 256;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, p.device) == hipSuccess && prop.multiProcessorCount > 0)
+            ncu = prop.multiProcessorCount;
+        p.persistent_grid = std::min(p.n_tan, (variant + 1) * ncu);
+        return HROM_OK;
+    }
+    for (int k = 0; k < p.ncl; k++)
+        if (c < 0 || c == k) p.cl[k].variant = variant;
+    return HROM_OK;
+}
+
 int hrom_plan_destroy(hrom_plan plan) {
     if (!plan) return HROM_E_INVALID;
     (void)hipDeviceSynchronize();
@@ -311,8 +330,8 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         e.wscale = wscale_for(c.Q);
         int rc = launch_kin(mixed(p) ? 1 : 0, e, stream);
         if (rc == HROM_OK)
-            rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, e, stream)
-                          : launch_eval_f64(c.MT, e, stream);
+            rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, c.variant, e, stream)
+                          : launch_eval_f64(c.MT, c.variant, e, stream);
         if (rc != HROM_OK) return rc;
     }
     if (Kaa || KaF || KFF) {

@@ -27,6 +27,7 @@ struct ClusterDev {
     int64_t ws_khat;       // element offset of the cluster's tile workspace
     int64_t ws_L;          // element offset of the cluster's factor workspace
     int64_t ws_qs;         // element offset of the cluster's per-ECM-point scalars
+    int variant;           // launch variant of the tangent contraction (autotuned)
     double* Ghat;          // [Qpad][9][MP]  augmented [G | I_9 | 0] (FP64)
     double* GT;            // [Qpad/64][9][m][64]  G, ECM point fastest (FP64)
     double* Gf;            // [9 Qpad/16][KS][64]  A-operand fragments of the kinematics GEMM
@@ -114,8 +115,8 @@ struct EvalArgs {
     float wscale;          // mixed: power-of-two scaling of w_q A_q
 };
 int launch_kin(int mixed, const EvalArgs& a, hipStream_t s);
-int launch_eval_f64(int MT, const EvalArgs& a, hipStream_t s);
-int launch_eval_mixed(int MT, int prec, bool split, const EvalArgs& a, hipStream_t s);
+int launch_eval_f64(int MT, int variant, const EvalArgs& a, hipStream_t s);
+int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s);
 
 struct CondenseArgs {
     int m, MT, res_t, res_c;

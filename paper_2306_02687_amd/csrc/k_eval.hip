@@ -290,10 +290,10 @@ __device__ __forceinline__ void tangent_block_f64(const double* st, int qq, cons
 }
 
 // the 4 macro points pl0 .. pl0+3 of the cluster, one per wavefront
-template <int MT>
+template <int MT, bool PFREQ = true>
 __device__ void tan_f64_body(const EvalArgs& A, int64_t pl0, double (*s_st)[12 * 64]) {
     constexpr int NT = MT * (MT + 1) / 2;
-    constexpr bool PF = (MT <= 5);   // register budget of the double buffer
+    constexpr bool PF = PFREQ && (MT <= 5);   // register budget of the double buffer
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
     int64_t pl = pl0 + wave;
@@ -340,24 +340,30 @@ __device__ void tan_f64_body(const EvalArgs& A, int64_t pl0, double (*s_st)[12 *
     for (int i = 0; i < NT; i++) *(v4d*)(kh + i * 256) = acc[i];
 }
 
-template <int MT>
+template <int MT, bool PF>
 __global__ void __launch_bounds__(256, 1) k_eval_f64(EvalArgs A) {
     __shared__ double s_st[4][12 * 64];
-    tan_f64_body<MT>(A, (int64_t)blockIdx.x * 4, s_st);
+    tan_f64_body<MT, PF>(A, (int64_t)blockIdx.x * 4, s_st);
 }
 
-int launch_eval_f64(int MT, const EvalArgs& a, hipStream_t s) {
+template <bool PF>
+static int launch_f64_t(int MT, const EvalArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(a.count, 4)), block(256);
     switch (MT) {
-        case 2: hipLaunchKernelGGL(k_eval_f64<2>, grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL(k_eval_f64<3>, grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_eval_f64<4>, grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL(k_eval_f64<5>, grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL(k_eval_f64<6>, grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL(k_eval_f64<7>, grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_eval_f64<2, PF>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_eval_f64<3, PF>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_eval_f64<4, PF>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_eval_f64<5, PF>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_eval_f64<6, PF>), grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_eval_f64<7, PF>), grid, block, 0, s, a); break;
         default: return HROM_E_UNSUPPORTED;
     }
     return HROM_OK;
+}
+
+// variant bit 1: G double-buffering off (the FP64 kernel has one occupancy)
+int launch_eval_f64(int MT, int variant, const EvalArgs& a, hipStream_t s) {
+    return (variant & 2) ? launch_f64_t<false>(MT, a, s) : launch_f64_t<true>(MT, a, s);
 }
 
 // ============================================================== mixed tangent
@@ -515,7 +521,7 @@ __device__ __forceinline__ void tangent_pair(const float* bq0, const Frags<MT>& 
 
 constexpr int kLQ = 13;   // padded stride of the 12 tangent scalars in LDS
 
-template <int MT, int PREC, bool SPLIT>
+template <int MT, int PREC, bool SPLIT, bool PF = true>
 __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, float (*s_q)[64 * kLQ]) {
     constexpr int NT = MT * (MT + 1) / 2;
     constexpr int LQ = kLQ;
@@ -561,13 +567,22 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, float (*s_q)[64 *
             }
         }
         __syncthreads();
-        Frags<MT> FA, FB;
-        load_frags<MT, SPLIT>(A, q0, lane, FA);
-        for (int qp = 0; qp < 32; qp += 2) {
-            load_frags<MT, SPLIT>(A, q0 + 2 * (qp + 1), lane, FB);
-            tangent_pair<MT, PREC, SPLIT>(sq + (2 * qp) * LQ, FA, o1, o2, o3, o4, dl, vl, acc);
-            if (qp + 2 < 32) load_frags<MT, SPLIT>(A, q0 + 2 * (qp + 2), lane, FA);
-            tangent_pair<MT, PREC, SPLIT>(sq + (2 * qp + 2) * LQ, FB, o1, o2, o3, o4, dl, vl, acc);
+        if (PF) {
+            // two fragment buffers: the next pair loads while this one is contracted
+            Frags<MT> FA, FB;
+            load_frags<MT, SPLIT>(A, q0, lane, FA);
+            for (int qp = 0; qp < 32; qp += 2) {
+                load_frags<MT, SPLIT>(A, q0 + 2 * (qp + 1), lane, FB);
+                tangent_pair<MT, PREC, SPLIT>(sq + (2 * qp) * LQ, FA, o1, o2, o3, o4, dl, vl, acc);
+                if (qp + 2 < 32) load_frags<MT, SPLIT>(A, q0 + 2 * (qp + 2), lane, FA);
+                tangent_pair<MT, PREC, SPLIT>(sq + (2 * qp + 2) * LQ, FB, o1, o2, o3, o4, dl, vl, acc);
+            }
+        } else {
+            for (int qp = 0; qp < 32; qp++) {
+                Frags<MT> FA;
+                load_frags<MT, SPLIT>(A, q0 + 2 * qp, lane, FA);
+                tangent_pair<MT, PREC, SPLIT>(sq + (2 * qp) * LQ, FA, o1, o2, o3, o4, dl, vl, acc);
+            }
         }
         __syncthreads();
     }
@@ -577,34 +592,46 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, float (*s_q)[64 *
     for (int i = 0; i < NT; i++) *(v4f*)(kh + i * 256) = acc[i];
 }
 
-template <int MT, int PREC, bool SPLIT>
-__global__ void __launch_bounds__(256, (MT <= 5) ? 2 : 1) k_eval_mixed(EvalArgs A) {
+// OCC2: ask for two wavefronts per SIMD (register cap 256) where MT <= 5
+template <int MT, int PREC, bool SPLIT, bool PF, bool OCC2>
+__global__ void __launch_bounds__(256, (OCC2 && MT <= 5) ? 2 : 1) k_eval_mixed(EvalArgs A) {
     __shared__ float s_q[4][64 * kLQ];
-    tan_mixed_body<MT, PREC, SPLIT>(A, (int64_t)blockIdx.x * 4, s_q);
+    tan_mixed_body<MT, PREC, SPLIT, PF>(A, (int64_t)blockIdx.x * 4, s_q);
 }
 
-template <int PREC, bool SPLIT>
+template <int PREC, bool SPLIT, bool PF, bool OCC2>
 static int launch_mixed_t(int MT, const EvalArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(a.count, 4)), block(256);
     switch (MT) {
-        case 2: hipLaunchKernelGGL((k_eval_mixed<2, PREC, SPLIT>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_eval_mixed<3, PREC, SPLIT>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_eval_mixed<4, PREC, SPLIT>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_eval_mixed<5, PREC, SPLIT>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_eval_mixed<6, PREC, SPLIT>), grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_eval_mixed<7, PREC, SPLIT>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_eval_mixed<2, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_eval_mixed<3, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_eval_mixed<4, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_eval_mixed<5, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_eval_mixed<6, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_eval_mixed<7, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
         default: return HROM_E_UNSUPPORTED;
     }
     return HROM_OK;
 }
 
-int launch_eval_mixed(int MT, int prec, bool split, const EvalArgs& a, hipStream_t s) {
+template <int PREC, bool SPLIT>
+static int launch_mixed_v(int MT, int variant, const EvalArgs& a, hipStream_t s) {
+    switch (variant & 3) {
+        case 0: return launch_mixed_t<PREC, SPLIT, true, true>(MT, a, s);
+        case 1: return launch_mixed_t<PREC, SPLIT, true, false>(MT, a, s);
+        case 2: return launch_mixed_t<PREC, SPLIT, false, true>(MT, a, s);
+        default: return launch_mixed_t<PREC, SPLIT, false, false>(MT, a, s);
+    }
+}
+
+// variant bit 0: one wavefront per SIMD instead of two; bit 1: no double buffer
+int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s) {
     if (prec == HROM_MIXED_BF16)
-        return split ? launch_mixed_t<HROM_MIXED_BF16, true>(MT, a, s)
-                     : launch_mixed_t<HROM_MIXED_BF16, false>(MT, a, s);
+        return split ? launch_mixed_v<HROM_MIXED_BF16, true>(MT, variant, a, s)
+                     : launch_mixed_v<HROM_MIXED_BF16, false>(MT, variant, a, s);
     if (prec == HROM_MIXED_FP16)
-        return split ? launch_mixed_t<HROM_MIXED_FP16, true>(MT, a, s)
-                     : launch_mixed_t<HROM_MIXED_FP16, false>(MT, a, s);
+        return split ? launch_mixed_v<HROM_MIXED_FP16, true>(MT, variant, a, s)
+                     : launch_mixed_v<HROM_MIXED_FP16, false>(MT, variant, a, s);
     return HROM_E_INVALID;
 }
 
