@@ -131,6 +131,10 @@ class Plan:
         _check(L.hrom_plan_create(C.byref(h), arr, len(self.clusters), self.N, precision, flags),
                "hrom_plan_create")
         self._h = h
+        # Counts the calls that change the plan's stored state (eval, update,
+        # newton); an adjoint taken later checks it to know whether the state
+        # of its forward solve is still the stored one.
+        self.generation = 0
         self.precision = precision
         self.objective = objective
         self.split = split
@@ -176,6 +180,7 @@ class Plan:
     # ------------------------------------------------------------ entry points
     def eval(self, theta, Fbar, a, status, r=None, Pr=None, Kaa=None, KaF=None, KFF=None,
              stream=None):
+        self.generation += 1
         _check(load().hrom_eval(self._h, _ptr(theta), _ptr(Fbar), _ptr(a), _ptr(r), _ptr(Pr),
                                 _ptr(Kaa), _ptr(KaF), _ptr(KFF), _ptr(status), _stream(stream)),
                "hrom_eval")
@@ -185,11 +190,13 @@ class Plan:
                                     _stream(stream)), "hrom_condense")
 
     def update(self, dFbar, a, status, tol=0.0, stream=None):
+        self.generation += 1
         _check(load().hrom_update(self._h, _ptr(dFbar), float(tol), _ptr(a), _ptr(status),
                                   _stream(stream)), "hrom_update")
 
     def newton(self, theta, Fbar, a, Pbar, Cbar, rnorm, status, tol=1e-10, max_it=6,
                stream=None):
+        self.generation += 1
         _check(load().hrom_newton(self._h, _ptr(theta), _ptr(Fbar), _ptr(a), float(tol),
                                   int(max_it), _ptr(Pbar), _ptr(Cbar), _ptr(rnorm), _ptr(status),
                                   _stream(stream)), "hrom_newton")

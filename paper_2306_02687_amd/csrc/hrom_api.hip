@@ -367,7 +367,7 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
         g.Khat = p.Khat; g.r = p.r; g.Pr = p.Pr; g.status = status;
         g.L = refine(p) ? p.L : nullptr; g.piv = p.piv; g.y = p.y; g.X = p.X;
         g.Palg = p.Palg; g.Cr = p.Cr; g.rnorm = p.rnorm;
-        const int rc = launch_condense_grouped(g, p.max_m, stream);
+        const int rc = launch_condense_reg_grouped(g, stream);
         if (rc != HROM_OK) return rc;
     }
     for (const auto& c : p.cl) {
@@ -381,8 +381,12 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
         ca.y = p.y + c.off_a; ca.X = p.X + 9 * c.off_a;
         ca.Palg = p.Palg; ca.Cr = p.Cr; ca.rnorm = p.rnorm; ca.status = status;
         ca.kscale = mixed(p) ? 1.0f / wscale_for(c.Q) : 1.0f;
-        // SPD path on the packed triangle; non-positive pivots finish on the LU path
-        int rc = p.grouped ? HROM_OK : launch_condense_spd(ca, stream);
+        // SPD path: register-resident elimination up to m = 64 (grouped plans:
+        // one launch above), packed triangle in LDS beyond; non-positive
+        // pivots finish on the LU path
+        int rc = HROM_OK;
+        if (c.m > 64) rc = launch_condense_spd(ca, stream);
+        else if (!p.grouped) rc = launch_condense_reg(ca, stream);
         if (rc == HROM_OK) rc = launch_unpack_condense(ca, 2, stream);
         if (rc != HROM_OK) return rc;
     }

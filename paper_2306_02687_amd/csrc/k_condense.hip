@@ -610,6 +610,298 @@ __global__ void __launch_bounds__(64) k_condense_grouped(GroupCall G) {
     condense_spd_body<TT>(A, b - C.first, sm);
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident condensation (m <= 64): one wavefront per macro point.
+//
+// The symmetric augmented matrix
+//     M = [[Kaa, KaF, r], [KaF^T, KFF, Pr], [r^T, Pr^T, 0]]
+// is eliminated over its m mode pivots (LDL^T, no square roots).  The
+// trailing 10 x 10 block is then the Schur complement
+//     [[KFF - KaF^T Kaa^-1 KaF, Pr - KaF^T Kaa^-1 r], [., -r^T Kaa^-1 r]],
+// i.e. the condensed RVE-frame tangent C_r and the algorithmic stress P_alg
+// (Sec. 3.2.3), and the eliminated rows of [KaF | r] hold L^-1 [KaF | r];
+// one backward substitution with D L^T gives X = Kaa^-1 KaF and y = Kaa^-1 r
+// for the monolithic update.
+//
+// Index space: modes 0..m-1, identity padding up to mp = 8 ceil(m / 8), the
+// nine macro components at mp..mp+8, the residual row at mp+9, zero padding
+// to 8 MB.  The 8 x 8 lane grid (lr = lane / 8, lc = lane % 8) owns element
+// (8t + lr, 8u + lc) of every lower block t >= u in register M[t(t+1)/2 + u];
+// block indices are compile-time constants, so the matrix never leaves the
+// register file.  Columns and rows are broadcast through a few LDS words.
+// A non-positive pivot flags HROM_PT_NOT_SPD (the LU pass finishes the point).
+// ---------------------------------------------------------------------------
+
+__host__ __device__ constexpr int lblk(int t, int u) { return t * (t + 1) / 2 + u; }
+
+// block -> point order: workgroups are dispatched round-robin over the eight
+// XCDs; give each XCD a contiguous range of points so the component-major
+// stores of neighbouring points meet in the same L2
+__device__ __forceinline__ int64_t xcd_order(int64_t bid, int64_t n) {
+    const int64_t q = n >> 3, rem = n & 7, x = bid & 7;
+    return x * q + (x < rem ? x : rem) + (bid >> 3);
+}
+
+template <typename TT, int MB>
+__device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
+    constexpr int NB = MB * (MB + 1) / 2;
+    constexpr int JB = MB - 2;               // pivot blocks
+    const int m = A.m, mp = 8 * JB, MT = A.MT;
+    const int lane = threadIdx.x, lr = lane >> 3, lc = lane & 7;
+    const int64_t b = A.first + pl;
+    const TT* kh = (const TT*)A.Khat + (int64_t)pl * (MT * (MT + 1) / 2) * 256;
+    const double ks = (double)A.kscale;
+    __shared__ double cb[8 * MB];            // column / row broadcast
+    __shared__ double zb[16];                // right-hand sides of one row
+
+    // ---- gather the lower blocks of M from the K-hat tiles, r and Pr
+    double M[NB];
+    double rr = 0.0;
+#pragma unroll
+    for (int t = 0; t < MB; t++) {
+#pragma unroll
+        for (int u = 0; u <= t; u++) {
+            const int i = 8 * t + lr, k = 8 * u + lc;
+            // augmented index of K-hat (modes, then the nine macro columns);
+            // -1 identity padding, -2 residual row, -3 zero padding
+            const int xi = i < m ? i : (i < mp ? -1 : (i < mp + 9 ? m + i - mp : (i == mp + 9 ? -2 : -3)));
+            const int xk = k < m ? k : (k < mp ? -1 : (k < mp + 9 ? m + k - mp : (k == mp + 9 ? -2 : -3)));
+            double v = 0.0;
+            if (xi >= 0 && xk >= 0) {
+                const int lo = xi < xk ? xi : xk, hi = xi < xk ? xk : xi;
+                const int ti = lo >> 4, tj = hi >> 4, rw = lo & 15, cl = hi & 15;
+                const int g = (sizeof(TT) == 4) ? (rw >> 2) : (rw & 3);
+                const int e = (sizeof(TT) == 4) ? (rw & 3) : (rw >> 2);
+                const int idx = ti * MT - ti * (ti - 1) / 2 + (tj - ti);
+                v = (double)kh[(int64_t)idx * 256 + (cl + 16 * g) * 4 + e] * ks;
+            } else if (xi == -1 || xk == -1) {
+                v = (i == k) ? 1.0 : 0.0;
+            } else if ((xi == -2) != (xk == -2) && xi != -3 && xk != -3) {
+                const int o = xi == -2 ? xk : xi;
+                if (o < m) {
+                    v = A.r[(int64_t)o * A.count + pl];
+                    rr = fma(v, v, rr);
+                } else {
+                    v = A.Pr[(int64_t)(o - m) * A.N + b];
+                }
+            }
+            M[lblk(t, u)] = v;
+        }
+    }
+
+    // ---- LDL^T elimination of the mp mode pivots (right-looking)
+    bool spd = true;
+#pragma unroll
+    for (int J = 0; J < JB; J++) {
+#pragma unroll 1
+        for (int jj = 0; jj < 8; jj++) {
+            const int j = 8 * J + jj;
+            if (lc == jj) {
+#pragma unroll
+                for (int t = J; t < MB; t++) cb[8 * t + lr] = M[lblk(t, J)];
+            }
+            __syncthreads();
+            const double d = cb[j];
+            if (!(d > 0.0)) {
+                spd = false;
+                break;
+            }
+            const double rd = 1.0 / d;
+            double ci[MB], ck[MB];
+#pragma unroll
+            for (int t = J; t < MB; t++) {
+                const double v = cb[8 * t + lr] * rd;
+                ci[t] = (t > J || lr > jj) ? v : 0.0;
+            }
+#pragma unroll
+            for (int u = J; u < MB; u++) {
+                const double v = cb[8 * u + lc];
+                ck[u] = (u > J || lc > jj) ? v : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = J; t < MB; t++)
+#pragma unroll
+                for (int u = J; u <= t; u++) M[lblk(t, u)] = fma(-ci[t], ck[u], M[lblk(t, u)]);
+        }
+        if (!spd) break;
+    }
+    if (!spd) {
+        if (lane == 0) A.status[b] |= HROM_PT_NOT_SPD;
+        return;
+    }
+
+    // ---- optional Cholesky factor for the adjoint refinement: L = c / sqrt(d)
+    if (A.L) {
+        // pivots d_k of the lane's columns: diagonal (k, k) is held by lane (k%8, k%8)
+        if (lr == lc) {
+#pragma unroll
+            for (int u = 0; u < JB; u++) cb[8 * u + lc] = M[lblk(u, u)];
+        }
+        __syncthreads();
+        double* Lp = A.L + pl * (int64_t)m * m;
+#pragma unroll
+        for (int t = 0; t < JB; t++)
+#pragma unroll
+            for (int u = 0; u <= t; u++) {
+                const int i = 8 * t + lr, k = 8 * u + lc;
+                if (i < m && k <= i) {
+                    const double sk = sqrt(cb[k]);
+                    Lp[(int64_t)i * m + k] = (i == k) ? sk : M[lblk(t, u)] / sk;
+                }
+            }
+        __syncthreads();
+    }
+    if (lane == 0) A.piv[pl * m] = -1;
+
+    // ---- backward substitution (D L^T) [X | y] = L^-1 [KaF | r], right-looking
+    // right-hand side c = lr in block JB, c = 8 + lr (lr < 2) in block JB + 1
+#pragma unroll
+    for (int J = JB - 1; J >= 0; J--) {
+#pragma unroll 1
+        for (int jj = 7; jj >= 0; jj--) {
+            const int j = 8 * J + jj;
+            if (lr == jj) {
+#pragma unroll
+                for (int u = 0; u <= J; u++) cb[8 * u + lc] = M[lblk(J, u)];
+            }
+            if (lc == jj) {
+                zb[lr] = M[lblk(JB, J)];
+                zb[8 + lr] = M[lblk(JB + 1, J)];
+            }
+            __syncthreads();
+            const double rdj = 1.0 / cb[j];
+            const double x0 = zb[lr] * rdj;
+            const double x1 = (lr < 2) ? zb[8 + lr] * rdj : 0.0;
+            double l[MB];
+#pragma unroll
+            for (int u = 0; u <= J; u++) l[u] = (u < J || lc < jj) ? cb[8 * u + lc] : 0.0;
+            __syncthreads();
+            if (lc == jj) {
+                M[lblk(JB, J)] = x0;
+                M[lblk(JB + 1, J)] = x1;
+            }
+#pragma unroll
+            for (int u = 0; u <= J; u++) {
+                M[lblk(JB, u)] = fma(-l[u], x0, M[lblk(JB, u)]);
+                M[lblk(JB + 1, u)] = fma(-l[u], x1, M[lblk(JB + 1, u)]);
+            }
+        }
+    }
+
+    // ---- outputs: y, X (mode-indexed, component-major), P_alg, C_r, rnorm
+#pragma unroll
+    for (int u = 0; u < JB; u++) {
+        const int i = 8 * u + lc;
+        if (i < m) {
+            A.X[((int64_t)i * 9 + lr) * A.count + pl] = M[lblk(JB, u)];
+            if (lr == 0) A.X[((int64_t)i * 9 + 8) * A.count + pl] = M[lblk(JB + 1, u)];
+            if (lr == 1) A.y[(int64_t)i * A.count + pl] = M[lblk(JB + 1, u)];
+        }
+    }
+    bool fin = true;
+    {
+        // C_r rows/cols 0..7: block (JB, JB), full 8 x 8 (symmetric updates)
+        const double c0 = M[lblk(JB, JB)];
+        A.Cr[(int64_t)(lr * 9 + lc) * A.N + b] = c0;
+        fin = fin && isfinite(c0);
+        if (lr == 0) {          // row / column 8 of C_r from block (JB + 1, JB)
+            const double c8 = M[lblk(JB + 1, JB)];
+            A.Cr[(int64_t)(8 * 9 + lc) * A.N + b] = c8;
+            A.Cr[(int64_t)(lc * 9 + 8) * A.N + b] = c8;
+            fin = fin && isfinite(c8);
+            if (lc == 0) {
+                const double c88 = M[lblk(JB + 1, JB + 1)];
+                A.Cr[(int64_t)80 * A.N + b] = c88;
+                fin = fin && isfinite(c88);
+            }
+        } else if (lr == 1) {   // residual row: P_alg
+            const double p0 = M[lblk(JB + 1, JB)];
+            A.Palg[(int64_t)lc * A.N + b] = p0;
+            fin = fin && isfinite(p0);
+            if (lc == 0) {
+                const double p8 = M[lblk(JB + 1, JB + 1)];
+                A.Palg[(int64_t)8 * A.N + b] = p8;
+                fin = fin && isfinite(p8);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rr += __shfl_xor(rr, off);
+    const uint64_t bad = __ballot(!fin);
+    if (lane == 0) {
+        A.rnorm[b] = sqrt(rr);
+        if (bad) A.status[b] |= HROM_PT_NONFINITE;
+    }
+}
+
+template <typename TT, int MB>
+__global__ void __launch_bounds__(64, 2) k_condense_reg(CondenseArgs A) {
+    condense_reg_body<TT, MB>(A, xcd_order(blockIdx.x, A.count));
+}
+
+// every macro point of every cluster with m <= 64 in one launch
+template <typename TT>
+__global__ void __launch_bounds__(64, 2) k_condense_reg_grouped(GroupCall G) {
+    const int64_t b = xcd_order(blockIdx.x, G.N);
+    int c = 0;
+    while (c + 1 < G.ncl && b >= G.cls[c + 1].first) c++;
+    const ClusterGPU& C = G.cls[c];
+    if (C.m > 64) return;
+    CondenseArgs A;
+    A.m = C.m; A.MT = C.MT; A.res_t = 0; A.res_c = 0; A.mixed = G.mixed;
+    A.first = C.first; A.count = C.count; A.N = G.N;
+    A.Khat = (const char*)G.Khat + sizeof(TT) * (size_t)C.ws_khat;
+    A.r = G.r + C.off_a; A.Pr = G.Pr;
+    A.L = G.L ? G.L + C.ws_L : nullptr; A.piv = G.piv + C.off_a;
+    A.y = G.y + C.off_a; A.X = G.X + 9 * C.off_a;
+    A.Palg = G.Palg; A.Cr = G.Cr; A.rnorm = G.rnorm; A.status = G.status;
+    A.kscale = 1.0f / C.wscale;
+    A.outKaa = A.outKaF = A.outKFF = nullptr;
+    const int64_t pl = b - C.first;
+    switch ((C.m + 7) / 8) {
+        case 1: condense_reg_body<TT, 3>(A, pl); break;
+        case 2: condense_reg_body<TT, 4>(A, pl); break;
+        case 3: condense_reg_body<TT, 5>(A, pl); break;
+        case 4: condense_reg_body<TT, 6>(A, pl); break;
+        case 5: condense_reg_body<TT, 7>(A, pl); break;
+        case 6: condense_reg_body<TT, 8>(A, pl); break;
+        case 7: condense_reg_body<TT, 9>(A, pl); break;
+        default: condense_reg_body<TT, 10>(A, pl); break;
+    }
+}
+
+template <typename TT>
+static void launch_reg_t(const CondenseArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)a.count), block(64);
+    switch ((a.m + 7) / 8) {
+        case 1: hipLaunchKernelGGL((k_condense_reg<TT, 3>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_condense_reg<TT, 4>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_condense_reg<TT, 5>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_condense_reg<TT, 6>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_condense_reg<TT, 7>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_condense_reg<TT, 8>), grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_condense_reg<TT, 9>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_condense_reg<TT, 10>), grid, block, 0, s, a); break;
+    }
+}
+
+int launch_condense_reg(const CondenseArgs& a, hipStream_t s) {
+    if (a.m < 1 || a.m > 64) return HROM_E_UNSUPPORTED;
+    if (a.count == 0) return HROM_OK;
+    if (a.mixed) launch_reg_t<float>(a, s);
+    else launch_reg_t<double>(a, s);
+    return HROM_OK;
+}
+
+int launch_condense_reg_grouped(const GroupCall& g, hipStream_t s) {
+    if (g.N == 0) return HROM_OK;
+    const dim3 grid((unsigned)g.N), block(64);
+    if (g.mixed) hipLaunchKernelGGL(k_condense_reg_grouped<float>, grid, block, 0, s, g);
+    else hipLaunchKernelGGL(k_condense_reg_grouped<double>, grid, block, 0, s, g);
+    return HROM_OK;
+}
+
 int launch_condense_grouped(const GroupCall& g, int max_m, hipStream_t s) {
     const size_t bytes = sizeof(double) *
         ((size_t)max_m * (max_m + 1) / 2 + 9 * max_m + 81 + 10 * max_m + 9 + max_m);
