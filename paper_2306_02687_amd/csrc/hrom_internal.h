@@ -11,6 +11,17 @@
 namespace hrom {
 
 constexpr int kMaxModes = 96;   // m <= 96
+
+// Per-point K-hat record, in tiles of 256 entries (one 16 x 16 MFMA
+// accumulator tile each).  FP64 path: the upper tiles of the augmented
+// contraction over Ghat = [G | I_9 | 0], MT (MT + 1) / 2 tiles.  Mixed path:
+// the upper Kaa tiles over the MA = ceil(m / 16) mode tiles, then MA tiles of
+// KaF^T, then one tile of KFF.
+__host__ __device__ inline int khat_tiles(int m, int MT, bool mixed) {
+    if (!mixed) return MT * (MT + 1) / 2;
+    const int MA = (m + 15) / 16;
+    return MA * (MA + 1) / 2 + MA + 1;
+}
 constexpr int kMaxTiles = 7;    // ceil((96 + 10) / 16)
 constexpr int kQChunk = 64;     // ECM points per phase-A chunk (one per lane)
 

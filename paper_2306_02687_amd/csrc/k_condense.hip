@@ -40,32 +40,49 @@ __device__ __forceinline__ int acc_row<double>(int g, int e) { return g + 4 * e;
 template <>
 __device__ __forceinline__ int acc_row<float>(int g, int e) { return 4 * g + e; }
 
+// entry (xi, xk) of the symmetric augmented tangent (indices 0..m-1 modes,
+// m..m+8 macro components) from a point's K-hat record
+template <typename TT>
+__device__ __forceinline__ double khat_at(const TT* kh, int m, int MT, int xi, int xk);
+
+template <>
+__device__ __forceinline__ double khat_at<double>(const double* kh, int m, int MT, int xi, int xk) {
+    (void)m;
+    const int lo = xi < xk ? xi : xk, hi = xi < xk ? xk : xi;
+    const int ti = lo >> 4, tj = hi >> 4, rw = lo & 15, cl = hi & 15;
+    const int idx = ti * MT - ti * (ti - 1) / 2 + (tj - ti);
+    return kh[(int64_t)idx * 256 + (cl + 16 * (rw & 3)) * 4 + (rw >> 2)];
+}
+
+template <>
+__device__ __forceinline__ double khat_at<float>(const float* kh, int m, int MT, int xi, int xk) {
+    (void)MT;
+    const int MA = (m + 15) / 16, NA = MA * (MA + 1) / 2;
+    const int lo = xi < xk ? xi : xk, hi = xi < xk ? xk : xi;
+    if (hi < m) {            // Kaa, accumulator rows 4g + e
+        const int ti = lo >> 4, tj = hi >> 4, rw = lo & 15, cl = hi & 15;
+        const int idx = ti * MA - ti * (ti - 1) / 2 + (tj - ti);
+        return (double)kh[(int64_t)idx * 256 + (cl + 16 * (rw >> 2)) * 4 + (rw & 3)];
+    }
+    if (lo < m) {            // KaF^T: row I (accumulator row), column = mode lo
+        const int I = hi - m;
+        return (double)kh[(int64_t)(NA + (lo >> 4)) * 256 + ((lo & 15) + 16 * (I >> 2)) * 4 + (I & 3)];
+    }
+    const int I = lo - m, J = hi - m;   // KFF in the A-operand layout W[I = c][J = 4g + e]
+    return (double)kh[(int64_t)(NA + MA) * 256 + (I + 16 * (J >> 2)) * 4 + (J & 3)];
+}
+
 template <typename TT>
 __device__ void unpack_tiles(const CondenseArgs& A, const TT* kh, CondLds& S, bool kaa_only) {
     const int m = A.m, MT = A.MT, lane = threadIdx.x;
-    const int g = lane >> 4, c = lane & 15;
     const double ks = (double)A.kscale;
-    int idx = 0;
-    for (int ti = 0; ti < MT; ti++)
-        for (int tj = ti; tj < MT; tj++, idx++) {
-            const TT* p = kh + (int64_t)idx * 256 + lane * 4;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int R = 16 * ti + acc_row<TT>(g, e), C = 16 * tj + c;
-                const double v = (double)p[e] * ks;
-                if (R < m) {
-                    if (C < m) {
-                        S.K[R * S.ld + C] = v;
-                        if (ti < tj) S.K[C * S.ld + R] = v;
-                    } else if (C < m + 9 && !kaa_only) {
-                        S.KaF[R * 9 + (C - m)] = v;
-                    }
-                } else if (R < m + 9 && C >= m && C < m + 9 && !kaa_only) {
-                    S.KFF[(R - m) * 9 + (C - m)] = v;
-                    if (ti < tj) S.KFF[(C - m) * 9 + (R - m)] = v;
-                }
-            }
-        }
+    for (int e = lane; e < m * m; e += 64) {
+        const int i = e / m, k = e % m;
+        S.K[i * S.ld + k] = khat_at<TT>(kh, m, MT, i, k) * ks;
+    }
+    if (kaa_only) return;
+    for (int e = lane; e < m * 9; e += 64) S.KaF[e] = khat_at<TT>(kh, m, MT, e / 9, m + e % 9) * ks;
+    for (int e = lane; e < 81; e += 64) S.KFF[e] = khat_at<TT>(kh, m, MT, m + e / 9, m + e % 9) * ks;
 }
 
 // mode 0: export the raw blocks; 1: full condensation (Cholesky, LU on a
@@ -79,9 +96,8 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int mode
     const int64_t b = A.first + pl;
     if (mode == 2 && !(A.status[b] & HROM_PT_NOT_SPD)) return;
     const int do_condense = mode;
-    const int MT = A.MT, NT = MT * (MT + 1) / 2;
     CondLds S(sm, m);
-    const TT* kh = (const TT*)A.Khat + (int64_t)pl * NT * 256;
+    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_tiles(m, A.MT, sizeof(TT) == 4) * 256;
     unpack_tiles<TT>(A, kh, S, false);
     for (int i = lane; i < m; i += 64) {
         const double ri = A.r[(int64_t)i * A.count + pl];
@@ -430,38 +446,24 @@ __device__ void condense_spd_body(const CondenseArgs& A, int64_t pl, double* sm)
     const int m = A.m, lane = threadIdx.x;
     const int g = lane >> 4, c = lane & 15;
     const int64_t b = A.first + pl;
-    const int MT = A.MT, NT = MT * (MT + 1) / 2;
+    const int MT = A.MT;
     double* K = sm;                          // packed lower, m (m + 1) / 2
     double* KaF = K + m * (m + 1) / 2;       // [m][9]
     double* KFF = KaF + 9 * m;               // [81]
     double* B = KFF + 81;                    // [m][10]
     double* Pr = B + 10 * m;                 // [9]
     double* rv = Pr + 9;                     // [m]
-    const TT* kh = (const TT*)A.Khat + (int64_t)pl * NT * 256;
+    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_tiles(m, MT, sizeof(TT) == 4) * 256;
     const double ks = (double)A.kscale;
-    {
-        int idx = 0;
-        for (int ti = 0; ti < MT; ti++)
-            for (int tj = ti; tj < MT; tj++, idx++) {
-                const TT* p = kh + (int64_t)idx * 256 + lane * 4;
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int R = 16 * ti + acc_row<TT>(g, e), C = 16 * tj + c;
-                    const double v = (double)p[e] * ks;
-                    if (R < m) {
-                        if (C < m) {
-                            if (C <= R) K[R * (R + 1) / 2 + C] = v;      // lower part of the tile
-                            else if (ti < tj) K[C * (C + 1) / 2 + R] = v; // mirror of an upper tile
-                        } else if (C < m + 9) {
-                            KaF[R * 9 + (C - m)] = v;
-                        }
-                    } else if (R < m + 9 && C >= m && C < m + 9) {
-                        KFF[(R - m) * 9 + (C - m)] = v;
-                        if (ti < tj) KFF[(C - m) * 9 + (R - m)] = v;
-                    }
-                }
-            }
+    for (int e = lane; e < m * (m + 1) / 2; e += 64) {
+        // packed lower triangle: row R at offset R (R + 1) / 2
+        int R = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (R * (R + 1) / 2 > e) R--;
+        while ((R + 1) * (R + 2) / 2 <= e) R++;
+        K[e] = khat_at<TT>(kh, m, MT, R, e - R * (R + 1) / 2) * ks;
     }
+    for (int e = lane; e < m * 9; e += 64) KaF[e] = khat_at<TT>(kh, m, MT, e / 9, m + e % 9) * ks;
+    for (int e = lane; e < 81; e += 64) KFF[e] = khat_at<TT>(kh, m, MT, m + e / 9, m + e % 9) * ks;
     for (int i = lane; i < m; i += 64) {
         const double ri = A.r[(int64_t)i * A.count + pl];
         rv[i] = ri;
@@ -649,7 +651,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
     const int m = A.m, mp = 8 * JB, MT = A.MT;
     const int lane = threadIdx.x, lr = lane >> 3, lc = lane & 7;
     const int64_t b = A.first + pl;
-    const TT* kh = (const TT*)A.Khat + (int64_t)pl * (MT * (MT + 1) / 2) * 256;
+    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_tiles(m, MT, sizeof(TT) == 4) * 256;
     const double ks = (double)A.kscale;
     __shared__ double cb[8 * MB];            // column / row broadcast
     __shared__ double zb[16];                // right-hand sides of one row
@@ -668,12 +670,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
             const int xk = k < m ? k : (k < mp ? -1 : (k < mp + 9 ? m + k - mp : (k == mp + 9 ? -2 : -3)));
             double v = 0.0;
             if (xi >= 0 && xk >= 0) {
-                const int lo = xi < xk ? xi : xk, hi = xi < xk ? xk : xi;
-                const int ti = lo >> 4, tj = hi >> 4, rw = lo & 15, cl = hi & 15;
-                const int g = (sizeof(TT) == 4) ? (rw >> 2) : (rw & 3);
-                const int e = (sizeof(TT) == 4) ? (rw & 3) : (rw >> 2);
-                const int idx = ti * MT - ti * (ti - 1) / 2 + (tj - ti);
-                v = (double)kh[(int64_t)idx * 256 + (cl + 16 * g) * 4 + e] * ks;
+                v = khat_at<TT>(kh, m, MT, xi, xk) * ks;
             } else if (xi == -1 || xk == -1) {
                 v = (i == k) ? 1.0 : 0.0;
             } else if ((xi == -2) != (xk == -2) && xi != -3 && xk != -3) {

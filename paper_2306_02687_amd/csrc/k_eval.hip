@@ -381,9 +381,7 @@ struct LP;
 template <>
 struct LP<HROM_MIXED_BF16> {
     static __device__ __forceinline__ unsigned short cvt(float x) {
-        uint32_t u = __float_as_uint(x);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        return (unsigned short)(u >> 16);
+        return __builtin_bit_cast(unsigned short, (__bf16)x);   // round to nearest even
     }
     static __device__ __forceinline__ float back(unsigned short h) {
         return __uint_as_float(((uint32_t)h) << 16);
@@ -422,75 +420,112 @@ struct LP<HROM_MIXED_FP16> {
     }
 };
 
+// x (FP32) -> hi + lo in the low-precision type, both rounded to nearest even;
+// x - hi is exact in FP32, so hi + lo carries about twice the mantissa bits
 template <int PREC>
-__device__ __forceinline__ void split4(const float* x, v4u& hi, v4u& lo) {
+__device__ __forceinline__ void split4(const float* x, v4u& hi, v4u& lo);
+
+template <>
+__device__ __forceinline__ void split4<HROM_MIXED_BF16>(const float* x, v4u& hi, v4u& lo) {
+    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    typedef unsigned short v2u __attribute__((ext_vector_type(2)));
+    const v2f a = {x[0], x[1]}, b = {x[2], x[3]};
+    const v2bf ha = __builtin_convertvector(a, v2bf), hb = __builtin_convertvector(b, v2bf);
+    const v2bf la = __builtin_convertvector(a - __builtin_convertvector(ha, v2f), v2bf);
+    const v2bf lb = __builtin_convertvector(b - __builtin_convertvector(hb, v2f), v2bf);
+    const v2u hau = __builtin_bit_cast(v2u, ha), hbu = __builtin_bit_cast(v2u, hb);
+    const v2u lau = __builtin_bit_cast(v2u, la), lbu = __builtin_bit_cast(v2u, lb);
+    hi = v4u{hau[0], hau[1], hbu[0], hbu[1]};
+    lo = v4u{lau[0], lau[1], lbu[0], lbu[1]};
+}
+
+template <>
+__device__ __forceinline__ void split4<HROM_MIXED_FP16>(const float* x, v4u& hi, v4u& lo) {
 #pragma unroll
     for (int e = 0; e < 4; e++) {
-        const unsigned short h = LP<PREC>::cvt(x[e]);
-        hi[e] = h;
-        lo[e] = LP<PREC>::cvt(x[e] - LP<PREC>::back(h));
+        const _Float16 h = (_Float16)x[e];
+        hi[e] = __builtin_bit_cast(unsigned short, h);
+        lo[e] = __builtin_bit_cast(unsigned short, (_Float16)(x[e] - (float)h));
     }
 }
 
-// Mixed path, tangent contraction on BF16/FP16 MFMA with FP32 accumulation,
-// in two chained steps per ECM point:
-//   T_q = (w_q A_q) Ghat_q       16x16x16 MFMA; rows I of T come out in the
-//                                accumulator layout (lane (g,c): rows 4g..4g+3,
-//                                column c), which is the B-operand layout of
-//   Khat += Ghat^T [T_q0 ; T_q1] 16x16x32 MFMA over a pair of ECM points.
+// Mixed path, tangent contraction on BF16/FP16 MFMA with FP32 accumulation.
+// Only the mode block is contracted; per ECM point q
+//   T_q = (w_q A_q) G_q          16x16x16 MFMA over the MA = ceil(m / 16) mode
+//                                tiles; rows I of T come out in the accumulator
+//                                layout (lane (g, c): rows 4g..4g+3, column c),
+//                                which is the B-operand layout of
+//   Kaa += G^T [T_q0 ; T_q1]     16x16x32 MFMA over a pair of ECM points,
+//   KaF^T += T_q                 FP32 sums in the accumulator layout,
+//   KFF += w_q A_q               FP32 sums of the A operand below,
+// since Ghat_q = [G_q | I_9] gives KaF = sum G^T (wA) and KFF = sum wA.
 // The A operand of the first step, W[I = c][J = 4g + e], is rebuilt by every
 // lane from the 12 FP32 scalars of the ECM point (already scaled by a power of
 // two for the low-precision range).  With SPLIT every operand x is carried as
 // hi + lo (both low precision) and each product as hi*hi + lo*hi + hi*lo.
-template <int MT>
+// Record per point: Kaa upper tiles [MA(MA+1)/2][256], KaF^T tiles [MA][256],
+// KFF tile [256].
+template <int MA>
 struct Frags {
-    v4u h[2][MT], l[2][MT];
+    v4u h[2][MA], l[2][MA];
 };
 
-// fragments of Ghat for the ECM point pair (q, q + 1)
-template <int MT, bool SPLIT>
-__device__ __forceinline__ void load_frags(const EvalArgs& A, int q, int lane, Frags<MT>& F) {
+// fragments of the mode tiles of Ghat for the ECM point pair (q, q + 1);
+// the fragment array holds MT tiles per ECM point
+template <int MA, bool SPLIT>
+__device__ __forceinline__ void load_frags(const EvalArgs& A, int q, int lane, Frags<MA>& F) {
 #pragma unroll
     for (int s2 = 0; s2 < 2; s2++) {
-        const v4u* fh = (const v4u*)(A.Fhi) + ((int64_t)(q + s2) * MT) * 64 + lane;
-        const v4u* fl = (const v4u*)(A.Flo) + ((int64_t)(q + s2) * MT) * 64 + lane;
+        const v4u* fh = (const v4u*)(A.Fhi) + ((int64_t)(q + s2) * A.MT) * 64 + lane;
+        const v4u* fl = (const v4u*)(A.Flo) + ((int64_t)(q + s2) * A.MT) * 64 + lane;
 #pragma unroll
-        for (int t = 0; t < MT; t++) {
+        for (int t = 0; t < MA; t++) {
             F.h[s2][t] = fh[t * 64];
             if (SPLIT) F.l[s2][t] = fl[t * 64];
         }
     }
 }
 
+template <int MA>
+struct MixAcc {
+    v4f kaa[MA * (MA + 1) / 2];
+    v4f kaf[MA];
+    float kff[4];
+};
+
 // contraction of one ECM point pair; bq points at the pair's 2 x 13 scalars
-template <int MT, int PREC, bool SPLIT>
-__device__ __forceinline__ void tangent_pair(const float* bq0, const Frags<MT>& G, const int* o1,
+template <int MA, int PREC, bool SPLIT>
+__device__ __forceinline__ void tangent_pair(const float* bq0, const Frags<MA>& G, const int* o1,
                                              const int* o2, const int* o3, const int* o4,
-                                             const float* dl, const float* vl, v4f* acc) {
+                                             const float* dl, const float* vl, MixAcc<MA>& R) {
     constexpr int LQ = 13;
-    v4u Th[2][MT], Tl[2][MT];
+    v4u Th[2][MA], Tl[2][MA];
 #pragma unroll
     for (int s2 = 0; s2 < 2; s2++) {
         const float* bq = bq0 + s2 * LQ;
         const float c0 = bq[9], c1 = bq[10], c2 = bq[11];
         float wv[4];
 #pragma unroll
-        for (int e = 0; e < 4; e++)
+        for (int e = 0; e < 4; e++) {
             wv[e] = vl[e] * (c1 * bq[o1[e]] * bq[o2[e]] + c2 * bq[o3[e]] * bq[o4[e]] + dl[e] * c0);
+            R.kff[e] += wv[e];
+        }
         v4u Wh, Wl;
         split4<PREC>(wv, Wh, Wl);
         // split terms outermost so that consecutive MFMAs write independent tiles
-        v4f T[MT];
+        v4f T[MA];
 #pragma unroll
-        for (int t = 0; t < MT; t++) T[t] = LP<PREC>::mfma16(Wh, G.h[s2][t], v4f{0.f, 0.f, 0.f, 0.f});
+        for (int t = 0; t < MA; t++) T[t] = LP<PREC>::mfma16(Wh, G.h[s2][t], v4f{0.f, 0.f, 0.f, 0.f});
         if (SPLIT) {
 #pragma unroll
-            for (int t = 0; t < MT; t++) T[t] = LP<PREC>::mfma16(Wl, G.h[s2][t], T[t]);
+            for (int t = 0; t < MA; t++) T[t] = LP<PREC>::mfma16(Wl, G.h[s2][t], T[t]);
 #pragma unroll
-            for (int t = 0; t < MT; t++) T[t] = LP<PREC>::mfma16(Wh, G.l[s2][t], T[t]);
+            for (int t = 0; t < MA; t++) T[t] = LP<PREC>::mfma16(Wh, G.l[s2][t], T[t]);
         }
 #pragma unroll
-        for (int t = 0; t < MT; t++) {
+        for (int t = 0; t < MA; t++) {
+            R.kaf[t] += T[t];
             float tv[4] = {T[t][0], T[t][1], T[t][2], T[t][3]};
             split4<PREC>(tv, Th[s2][t], Tl[s2][t]);
         }
@@ -498,32 +533,32 @@ __device__ __forceinline__ void tangent_pair(const float* bq0, const Frags<MT>& 
     {
         int idx = 0;
 #pragma unroll
-        for (int ti = 0; ti < MT; ti++)
+        for (int ti = 0; ti < MA; ti++)
 #pragma unroll
-            for (int tj = ti; tj < MT; tj++, idx++)
-                acc[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Th[0][tj], Th[1][tj], acc[idx]);
+            for (int tj = ti; tj < MA; tj++, idx++)
+                R.kaa[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Th[0][tj], Th[1][tj], R.kaa[idx]);
     }
     if (SPLIT) {
         int idx = 0;
 #pragma unroll
-        for (int ti = 0; ti < MT; ti++)
+        for (int ti = 0; ti < MA; ti++)
 #pragma unroll
-            for (int tj = ti; tj < MT; tj++, idx++)
-                acc[idx] = LP<PREC>::mfma32(G.l[0][ti], G.l[1][ti], Th[0][tj], Th[1][tj], acc[idx]);
+            for (int tj = ti; tj < MA; tj++, idx++)
+                R.kaa[idx] = LP<PREC>::mfma32(G.l[0][ti], G.l[1][ti], Th[0][tj], Th[1][tj], R.kaa[idx]);
         idx = 0;
 #pragma unroll
-        for (int ti = 0; ti < MT; ti++)
+        for (int ti = 0; ti < MA; ti++)
 #pragma unroll
-            for (int tj = ti; tj < MT; tj++, idx++)
-                acc[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Tl[0][tj], Tl[1][tj], acc[idx]);
+            for (int tj = ti; tj < MA; tj++, idx++)
+                R.kaa[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Tl[0][tj], Tl[1][tj], R.kaa[idx]);
     }
 }
 
 constexpr int kLQ = 13;   // padded stride of the 12 tangent scalars in LDS
 
-template <int MT, int PREC, bool SPLIT, bool PF = true>
+template <int MA, int PREC, bool SPLIT, bool PF = true>
 __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, float (*s_q)[64 * kLQ]) {
-    constexpr int NT = MT * (MT + 1) / 2;
+    constexpr int NA = MA * (MA + 1) / 2;
     constexpr int LQ = kLQ;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
@@ -550,9 +585,13 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, float (*s_q)[64 *
             vl[e] = (c < 9 && 4 * g + e < 9) ? 1.f : 0.f;
         }
     }
-    v4f acc[NT];
+    MixAcc<MA> R;
 #pragma unroll
-    for (int i = 0; i < NT; i++) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < NA; i++) R.kaa[i] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < MA; i++) R.kaf[i] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int e = 0; e < 4; e++) R.kff[e] = 0.f;
 
     for (int q0 = 0; q0 < A.Qpad; q0 += 64) {
         {
@@ -569,69 +608,73 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, float (*s_q)[64 *
         __syncthreads();
         if (PF) {
             // two fragment buffers: the next pair loads while this one is contracted
-            Frags<MT> FA, FB;
-            load_frags<MT, SPLIT>(A, q0, lane, FA);
+            Frags<MA> FA, FB;
+            load_frags<MA, SPLIT>(A, q0, lane, FA);
             for (int qp = 0; qp < 32; qp += 2) {
-                load_frags<MT, SPLIT>(A, q0 + 2 * (qp + 1), lane, FB);
-                tangent_pair<MT, PREC, SPLIT>(sq + (2 * qp) * LQ, FA, o1, o2, o3, o4, dl, vl, acc);
-                if (qp + 2 < 32) load_frags<MT, SPLIT>(A, q0 + 2 * (qp + 2), lane, FA);
-                tangent_pair<MT, PREC, SPLIT>(sq + (2 * qp + 2) * LQ, FB, o1, o2, o3, o4, dl, vl, acc);
+                load_frags<MA, SPLIT>(A, q0 + 2 * (qp + 1), lane, FB);
+                tangent_pair<MA, PREC, SPLIT>(sq + (2 * qp) * LQ, FA, o1, o2, o3, o4, dl, vl, R);
+                if (qp + 2 < 32) load_frags<MA, SPLIT>(A, q0 + 2 * (qp + 2), lane, FA);
+                tangent_pair<MA, PREC, SPLIT>(sq + (2 * qp + 2) * LQ, FB, o1, o2, o3, o4, dl, vl, R);
             }
         } else {
             for (int qp = 0; qp < 32; qp++) {
-                Frags<MT> FA;
-                load_frags<MT, SPLIT>(A, q0 + 2 * qp, lane, FA);
-                tangent_pair<MT, PREC, SPLIT>(sq + (2 * qp) * LQ, FA, o1, o2, o3, o4, dl, vl, acc);
+                Frags<MA> FA;
+                load_frags<MA, SPLIT>(A, q0 + 2 * qp, lane, FA);
+                tangent_pair<MA, PREC, SPLIT>(sq + (2 * qp) * LQ, FA, o1, o2, o3, o4, dl, vl, R);
             }
         }
         __syncthreads();
     }
     if (!valid) return;
-    float* kh = (float*)A.Khat + (int64_t)pl * NT * 256 + lane * 4;
+    float* kh = (float*)A.Khat + (int64_t)pl * (NA + MA + 1) * 256 + lane * 4;
 #pragma unroll
-    for (int i = 0; i < NT; i++) *(v4f*)(kh + i * 256) = acc[i];
+    for (int i = 0; i < NA; i++) *(v4f*)(kh + i * 256) = R.kaa[i];
+#pragma unroll
+    for (int i = 0; i < MA; i++) *(v4f*)(kh + (NA + i) * 256) = R.kaf[i];
+    *(v4f*)(kh + (NA + MA) * 256) = v4f{R.kff[0], R.kff[1], R.kff[2], R.kff[3]};
 }
 
-// OCC2: ask for two wavefronts per SIMD (register cap 256) where MT <= 5
-template <int MT, int PREC, bool SPLIT, bool PF, bool OCC2>
-__global__ void __launch_bounds__(256, (OCC2 && MT <= 5) ? 2 : 1) k_eval_mixed(EvalArgs A) {
+// OCC2: ask for two wavefronts per SIMD (register cap 256)
+template <int MA, int PREC, bool SPLIT, bool PF, bool OCC2>
+__global__ void __launch_bounds__(256, (OCC2 && MA <= 4) ? 2 : 1) k_eval_mixed(EvalArgs A) {
     __shared__ float s_q[4][64 * kLQ];
-    tan_mixed_body<MT, PREC, SPLIT, PF>(A, (int64_t)blockIdx.x * 4, s_q);
+    tan_mixed_body<MA, PREC, SPLIT, PF>(A, (int64_t)blockIdx.x * 4, s_q);
 }
 
 template <int PREC, bool SPLIT, bool PF, bool OCC2>
-static int launch_mixed_t(int MT, const EvalArgs& a, hipStream_t s) {
+static int launch_mixed_t(const EvalArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(a.count, 4)), block(256);
-    switch (MT) {
+    switch ((a.m + 15) / 16) {
+        case 1: hipLaunchKernelGGL((k_eval_mixed<1, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_eval_mixed<2, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
         case 3: hipLaunchKernelGGL((k_eval_mixed<3, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
         case 4: hipLaunchKernelGGL((k_eval_mixed<4, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
         case 5: hipLaunchKernelGGL((k_eval_mixed<5, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
         case 6: hipLaunchKernelGGL((k_eval_mixed<6, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_eval_mixed<7, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
         default: return HROM_E_UNSUPPORTED;
     }
     return HROM_OK;
 }
 
 template <int PREC, bool SPLIT>
-static int launch_mixed_v(int MT, int variant, const EvalArgs& a, hipStream_t s) {
+static int launch_mixed_v(int variant, const EvalArgs& a, hipStream_t s) {
     switch (variant & 3) {
-        case 0: return launch_mixed_t<PREC, SPLIT, true, true>(MT, a, s);
-        case 1: return launch_mixed_t<PREC, SPLIT, true, false>(MT, a, s);
-        case 2: return launch_mixed_t<PREC, SPLIT, false, true>(MT, a, s);
-        default: return launch_mixed_t<PREC, SPLIT, false, false>(MT, a, s);
+        case 0: return launch_mixed_t<PREC, SPLIT, true, true>(a, s);
+        case 1: return launch_mixed_t<PREC, SPLIT, true, false>(a, s);
+        case 2: return launch_mixed_t<PREC, SPLIT, false, true>(a, s);
+        default: return launch_mixed_t<PREC, SPLIT, false, false>(a, s);
     }
 }
 
 // variant bit 0: one wavefront per SIMD instead of two; bit 1: no double buffer
 int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s) {
+    (void)MT;
     if (prec == HROM_MIXED_BF16)
-        return split ? launch_mixed_v<HROM_MIXED_BF16, true>(MT, variant, a, s)
-                     : launch_mixed_v<HROM_MIXED_BF16, false>(MT, variant, a, s);
+        return split ? launch_mixed_v<HROM_MIXED_BF16, true>(variant, a, s)
+                     : launch_mixed_v<HROM_MIXED_BF16, false>(variant, a, s);
     if (prec == HROM_MIXED_FP16)
-        return split ? launch_mixed_v<HROM_MIXED_FP16, true>(MT, variant, a, s)
-                     : launch_mixed_v<HROM_MIXED_FP16, false>(MT, variant, a, s);
+        return split ? launch_mixed_v<HROM_MIXED_FP16, true>(variant, a, s)
+                     : launch_mixed_v<HROM_MIXED_FP16, false>(variant, a, s);
     return HROM_E_INVALID;
 }
 
@@ -696,13 +739,13 @@ __global__ void __launch_bounds__(256, 1) k_tan_persistent(GroupCall G) {
             }
         } else {
             const EvalArgs A = group_eval_args(G, w.c, sizeof(float));
-            switch (A.MT) {
+            switch ((A.m + 15) / 16) {
+                case 1: tan_mixed_body<1, PREC, SPLIT>(A, pl0, s_q); break;
                 case 2: tan_mixed_body<2, PREC, SPLIT>(A, pl0, s_q); break;
                 case 3: tan_mixed_body<3, PREC, SPLIT>(A, pl0, s_q); break;
                 case 4: tan_mixed_body<4, PREC, SPLIT>(A, pl0, s_q); break;
                 case 5: tan_mixed_body<5, PREC, SPLIT>(A, pl0, s_q); break;
-                case 6: tan_mixed_body<6, PREC, SPLIT>(A, pl0, s_q); break;
-                default: tan_mixed_body<7, PREC, SPLIT>(A, pl0, s_q); break;
+                default: tan_mixed_body<6, PREC, SPLIT>(A, pl0, s_q); break;
             }
         }
         __syncthreads();
