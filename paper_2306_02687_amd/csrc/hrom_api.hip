@@ -41,8 +41,7 @@ void free_plan(Plan& p) {
         dfree(c.Gf);
         dfree(c.w);
         dfree(c.phase);
-        dfree(c.Fhi);
-        dfree(c.Flo);
+        dfree(c.Fpk);
     }
     dfree(p.Fr); dfree(p.polar); dfree(p.Pr); dfree(p.r); dfree(p.Khat); dfree(p.qs); dfree(p.L);
     dfree(p.piv); dfree(p.y); dfree(p.X); dfree(p.Palg); dfree(p.Cr); dfree(p.S);
@@ -85,7 +84,7 @@ int build_groups(Plan& p) {
         g.m = d.m; g.Q = d.Q; g.Qpad = d.Qpad; g.MP = d.MP; g.MT = d.MT; g.KS = d.KS;
         g.first = d.first; g.count = d.count; g.off_a = d.off_a; g.ws_qs = d.ws_qs;
         g.ws_khat = d.ws_khat; g.ws_L = d.ws_L;
-        g.Ghat = d.Ghat; g.Gf = d.Gf; g.w = d.w; g.phase = d.phase; g.Fhi = d.Fhi; g.Flo = d.Flo;
+        g.Ghat = d.Ghat; g.Gf = d.Gf; g.w = d.w; g.phase = d.phase; g.Fpk = d.Fpk;
         g.wscale = mixed(p) ? wscale_for(d.Q) : 1.0f;
         cg.push_back(g);
         p.max_m = std::max(p.max_m, d.m);
@@ -198,15 +197,14 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
         if (rc == HROM_OK) rc = dalloc(&d.w, d.Qpad);
         if (rc == HROM_OK) rc = dalloc(&d.phase, d.Qpad);
         if (rc == HROM_OK && precision != HROM_FP64) {
-            rc = dalloc(&d.Fhi, (int64_t)d.Qpad * d.MT * 256);
-            if (rc == HROM_OK) rc = dalloc(&d.Flo, (int64_t)d.Qpad * d.MT * 256);
+            rc = dalloc(&d.Fpk, (int64_t)d.Qpad * ((d.m + 15) / 16) * 512);
         }
         p.cl.push_back(d);
         if (rc != HROM_OK) break;
         LayoutArgs la{};
         la.m = d.m; la.Q = d.Q; la.Qpad = d.Qpad; la.MT = d.MT; la.MP = d.MP; la.prec = precision;
         la.G = k.G; la.w = k.w; la.phase = k.phase;
-        la.Ghat = d.Ghat; la.GT = d.GT; la.Gf = d.Gf; la.KS = d.KS; la.wpad = d.w; la.phpad = d.phase; la.Fhi = d.Fhi; la.Flo = d.Flo;
+        la.Ghat = d.Ghat; la.GT = d.GT; la.Gf = d.Gf; la.KS = d.KS; la.wpad = d.w; la.phpad = d.phase; la.Fpk = d.Fpk; la.split = (flags & HROM_SPLIT) ? 1 : 0;
         launch_build_layouts(la, nullptr);
         if (hipDeviceSynchronize() != hipSuccess) rc = HROM_E_HIP;
     }
@@ -320,7 +318,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         EvalArgs e{};
         e.m = c.m; e.Q = c.Q; e.Qpad = c.Qpad; e.MP = c.MP; e.MT = c.MT; e.KS = c.KS;
         e.first = c.first; e.count = c.count; e.N = p.N;
-        e.Ghat = c.Ghat; e.Gf = c.Gf; e.w = c.w; e.phase = c.phase; e.Fhi = c.Fhi; e.Flo = c.Flo;
+        e.Ghat = c.Ghat; e.Gf = c.Gf; e.w = c.w; e.phase = c.phase; e.Fpk = c.Fpk;
         e.theta = theta; e.Fr = p.Fr; e.a = a + c.off_a;
         e.qs = (char*)p.qs + tsz * (size_t)c.ws_qs;
         e.Khat = (char*)p.Khat + tsz * (size_t)c.ws_khat;

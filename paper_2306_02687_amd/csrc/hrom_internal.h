@@ -45,8 +45,7 @@ struct ClusterDev {
     int KS;                // ceil(m / 4) k-steps of the kinematics GEMM
     double* w;             // [Qpad] (zero padded)
     int* phase;            // [Qpad]
-    uint16_t* Fhi;         // [Qpad][MT][64][4] low-precision fragments of Ghat (hi part)
-    uint16_t* Flo;         // same, lo part (Ghat - hi)
+    uint16_t* Fpk;         // [Qpad][MA][64][8] packed low-precision fragments of G (mixed path)
 };
 
 struct ClusterGPU;
@@ -113,8 +112,7 @@ struct EvalArgs {
     const double* Gf;      // kinematics-GEMM fragments [9 Qpad / 16][KS][64]
     const double* w;
     const int* phase;
-    const uint16_t* Fhi;
-    const uint16_t* Flo;
+    const uint16_t* Fpk;
     const double* theta;
     const double* Fr;
     const double* a;       // cluster block [m][count]
@@ -255,8 +253,8 @@ struct LayoutArgs {
     int KS;
     double* wpad;
     int* phpad;
-    uint16_t* Fhi;
-    uint16_t* Flo;
+    uint16_t* Fpk;         // packed mixed-path fragments [Qpad][MA][64][8]
+    int split;
 };
 void launch_build_layouts(const LayoutArgs& a, hipStream_t s);
 
@@ -272,8 +270,7 @@ struct ClusterGPU {
     const double* Gf;
     const double* w;
     const int* phase;
-    const uint16_t* Fhi;
-    const uint16_t* Flo;
+    const uint16_t* Fpk;
     float wscale;
 };
 

@@ -54,6 +54,9 @@ __device__ __forceinline__ double khat_at<double>(const double* kh, int m, int M
     return kh[(int64_t)idx * 256 + (cl + 16 * (rw & 3)) * 4 + (rw >> 2)];
 }
 
+// accumulator row of tensor component K in the mixed-path tiles
+__device__ __forceinline__ int comp_row(int K) { return K < 6 ? 4 * (K >> 1) + (K & 1) : 6 + K; }
+
 template <>
 __device__ __forceinline__ double khat_at<float>(const float* kh, int m, int MT, int xi, int xk) {
     (void)MT;
@@ -64,12 +67,12 @@ __device__ __forceinline__ double khat_at<float>(const float* kh, int m, int MT,
         const int idx = ti * MA - ti * (ti - 1) / 2 + (tj - ti);
         return (double)kh[(int64_t)idx * 256 + (cl + 16 * (rw >> 2)) * 4 + (rw & 3)];
     }
-    if (lo < m) {            // KaF^T: row I (accumulator row), column = mode lo
-        const int I = hi - m;
-        return (double)kh[(int64_t)(NA + (lo >> 4)) * 256 + ((lo & 15) + 16 * (I >> 2)) * 4 + (I & 3)];
+    if (lo < m) {            // KaF: row = mode lo, column = accumulator row of the component
+        const int rw = lo & 15;
+        return (double)kh[(int64_t)(NA + (lo >> 4)) * 256 + (comp_row(hi - m) + 16 * (rw >> 2)) * 4 + (rw & 3)];
     }
-    const int I = lo - m, J = hi - m;   // KFF in the A-operand layout W[I = c][J = 4g + e]
-    return (double)kh[(int64_t)(NA + MA) * 256 + (I + 16 * (J >> 2)) * 4 + (J & 3)];
+    const int ri = comp_row(lo - m), cj = comp_row(hi - m);   // KFF
+    return (double)kh[(int64_t)(NA + MA) * 256 + (cj + 16 * (ri >> 2)) * 4 + (ri & 3)];
 }
 
 template <typename TT>

@@ -367,278 +367,225 @@ int launch_eval_f64(int MT, int variant, const EvalArgs& a, hipStream_t s) {
 }
 
 // ============================================================== mixed tangent
-// Low-precision operand types.  bf16 fragments are carried as 16-bit
-// patterns; the conversion rounds to nearest even.
-typedef short v4s __attribute__((ext_vector_type(4)));
-typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+// Low-precision operand types: fragments are carried as 16-bit patterns, two
+// per dword; conversions round to nearest even.
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
-typedef unsigned short v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
 template <int PREC>
-struct LP;
+struct Pk;
 
 template <>
-struct LP<HROM_MIXED_BF16> {
-    static __device__ __forceinline__ unsigned short cvt(float x) {
-        return __builtin_bit_cast(unsigned short, (__bf16)x);   // round to nearest even
+struct Pk<HROM_MIXED_BF16> {
+    // (x0, x1) -> one dword, x0 in the low half
+    static __device__ __forceinline__ uint32_t pack(float x0, float x1) {
+        typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+        typedef float v2f __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f{x0, x1}), v2bf));
     }
-    static __device__ __forceinline__ float back(unsigned short h) {
-        return __uint_as_float(((uint32_t)h) << 16);
-    }
-    static __device__ __forceinline__ v4f mfma16(v4u a, v4u b, v4f c) {
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, a),
-                                                         __builtin_bit_cast(v4s, b), c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ v4f mfma32(v4u a0, v4u a1, v4u b0, v4u b1, v4f c) {
-        typedef unsigned short v8u __attribute__((ext_vector_type(8)));
-        const v8u a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
-        const v8u b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+    static __device__ __forceinline__ float lo(uint32_t h) { return __uint_as_float(h << 16); }
+    static __device__ __forceinline__ float hi(uint32_t h) { return __uint_as_float(h & 0xFFFF0000u); }
+    static constexpr uint32_t one = 0x3F80u;
+    static __device__ __forceinline__ v4f mfma(v4u32 a, v4u32 b, v4f c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
                                                        __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
     }
 };
 
 template <>
-struct LP<HROM_MIXED_FP16> {
-    static __device__ __forceinline__ unsigned short cvt(float x) {
-        return __builtin_bit_cast(unsigned short, (_Float16)x);
+struct Pk<HROM_MIXED_FP16> {
+    static __device__ __forceinline__ uint32_t pack(float x0, float x1) {
+        typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+        typedef float v2f __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f{x0, x1}), v2h));
     }
-    static __device__ __forceinline__ float back(unsigned short h) {
-        return (float)__builtin_bit_cast(_Float16, h);
+    static __device__ __forceinline__ float lo(uint32_t h) {
+        return (float)__builtin_bit_cast(_Float16, (unsigned short)(h & 0xFFFFu));
     }
-    static __device__ __forceinline__ v4f mfma16(v4u a, v4u b, v4f c) {
-        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, a),
-                                                     __builtin_bit_cast(v4h, b), c, 0, 0, 0);
+    static __device__ __forceinline__ float hi(uint32_t h) {
+        return (float)__builtin_bit_cast(_Float16, (unsigned short)(h >> 16));
     }
-    static __device__ __forceinline__ v4f mfma32(v4u a0, v4u a1, v4u b0, v4u b1, v4f c) {
-        typedef unsigned short v8u __attribute__((ext_vector_type(8)));
-        const v8u a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
-        const v8u b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+    static constexpr uint32_t one = 0x3C00u;
+    static __device__ __forceinline__ v4f mfma(v4u32 a, v4u32 b, v4f c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a),
                                                       __builtin_bit_cast(v8h, b), c, 0, 0, 0);
     }
 };
 
-// x (FP32) -> hi + lo in the low-precision type, both rounded to nearest even;
-// x - hi is exact in FP32, so hi + lo carries about twice the mantissa bits
-template <int PREC>
-__device__ __forceinline__ void split4(const float* x, v4u& hi, v4u& lo);
+// Mixed path: tangent contraction on BF16/FP16 MFMA (16x16x32, FP32
+// accumulation), one macro point per wavefront.  Per ECM point q, with
+// W_q = w_q A_q (9 x 9, FP32, scaled by a power of two) and the mode tiles G_t:
+//   T_t  = W_q G_t          one MFMA per mode tile,
+//   Kaa += G_ti^T T_tj      one MFMA per upper tile pair (T re-split into hi/lo),
+//   KaF += G_t^T W_q        one MFMA per mode tile,
+//   KFF += W_q              one MFMA against a constant identity fragment.
+// Every operand is carried as hi + lo and all three split products
+// hi*hi + lo*hi + hi*lo of the nine-component contraction share the 32 k-slots
+// of one MFMA: the components sit in the accumulator rows 0,1 | 4,5 | 8,9 |
+// 12,13,14 of the four lane groups, so lane group g holds rows 4g + e of T and
+// its k-slots pair (G parts) x (W or T parts) as
+//   groups 0..2: Gh.Th(a) Gh.Th(b) Gl.Th(a) Gl.Th(b) Gh.Tl(a) Gh.Tl(b) [g1: Gh.Tl(8)] 0
+//   group 3:     same for a = 6, b = 7, then Gh.Th(8) Gl.Th(8)
+// The one term that does not fit its own lane group, Tl(8), moves from group 3
+// to group 1 with a single lane-half swap.  W is built once per ECM point in
+// LDS by the whole wavefront (16 ECM points per round) rather than per lane.
+// Record per point: Kaa upper tiles [MA(MA+1)/2][256], KaF tiles [MA][256]
+// (row = mode, column = accumulator row of the component), KFF tile [256].
+constexpr int kCQ = 16;   // ECM points per LDS round
 
-template <>
-__device__ __forceinline__ void split4<HROM_MIXED_BF16>(const float* x, v4u& hi, v4u& lo) {
-    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
-    typedef float v2f __attribute__((ext_vector_type(2)));
-    typedef unsigned short v2u __attribute__((ext_vector_type(2)));
-    const v2f a = {x[0], x[1]}, b = {x[2], x[3]};
-    const v2bf ha = __builtin_convertvector(a, v2bf), hb = __builtin_convertvector(b, v2bf);
-    const v2bf la = __builtin_convertvector(a - __builtin_convertvector(ha, v2f), v2bf);
-    const v2bf lb = __builtin_convertvector(b - __builtin_convertvector(hb, v2f), v2bf);
-    const v2u hau = __builtin_bit_cast(v2u, ha), hbu = __builtin_bit_cast(v2u, hb);
-    const v2u lau = __builtin_bit_cast(v2u, la), lbu = __builtin_bit_cast(v2u, lb);
-    hi = v4u{hau[0], hau[1], hbu[0], hbu[1]};
-    lo = v4u{lau[0], lau[1], lbu[0], lbu[1]};
+__device__ __forceinline__ int comp_pos(int K) { return K < 6 ? 4 * (K >> 1) + (K & 1) : 6 + K; }
+__device__ __forceinline__ int pos_comp(int r) {
+    const int g = r >> 2, e = r & 3;
+    if (g < 3) return e < 2 ? 2 * g + e : -1;
+    return e < 3 ? 6 + e : -1;
 }
 
-template <>
-__device__ __forceinline__ void split4<HROM_MIXED_FP16>(const float* x, v4u& hi, v4u& lo) {
+// the four lane records (lane groups 0..3) of W row KI, from w[J] = W[KI][J]
+template <int PREC, bool SPLIT>
+__device__ __forceinline__ void w_records(const float* w, v4u32* rec) {
+    uint32_t h[5], l[5];
 #pragma unroll
-    for (int e = 0; e < 4; e++) {
-        const _Float16 h = (_Float16)x[e];
-        hi[e] = __builtin_bit_cast(unsigned short, h);
-        lo[e] = __builtin_bit_cast(unsigned short, (_Float16)(x[e] - (float)h));
+    for (int p = 0; p < 4; p++) {
+        h[p] = Pk<PREC>::pack(w[2 * p], w[2 * p + 1]);
+        l[p] = SPLIT ? Pk<PREC>::pack(w[2 * p] - Pk<PREC>::lo(h[p]), w[2 * p + 1] - Pk<PREC>::hi(h[p])) : 0u;
     }
+    h[4] = Pk<PREC>::pack(w[8], w[8]);
+    l[4] = SPLIT ? Pk<PREC>::pack(w[8] - Pk<PREC>::lo(h[4]), 0.f) : 0u;
+    rec[0] = v4u32{h[0], h[0], l[0], 0u};
+    rec[1] = v4u32{h[1], h[1], l[1], l[4]};
+    rec[2] = v4u32{h[2], h[2], l[2], 0u};
+    rec[3] = v4u32{h[3], h[3], l[3], h[4]};
 }
 
-// Mixed path, tangent contraction on BF16/FP16 MFMA with FP32 accumulation.
-// Only the mode block is contracted; per ECM point q
-//   T_q = (w_q A_q) G_q          16x16x16 MFMA over the MA = ceil(m / 16) mode
-//                                tiles; rows I of T come out in the accumulator
-//                                layout (lane (g, c): rows 4g..4g+3, column c),
-//                                which is the B-operand layout of
-//   Kaa += G^T [T_q0 ; T_q1]     16x16x32 MFMA over a pair of ECM points,
-//   KaF^T += T_q                 FP32 sums in the accumulator layout,
-//   KFF += w_q A_q               FP32 sums of the A operand below,
-// since Ghat_q = [G_q | I_9] gives KaF = sum G^T (wA) and KFF = sum wA.
-// The A operand of the first step, W[I = c][J = 4g + e], is rebuilt by every
-// lane from the 12 FP32 scalars of the ECM point (already scaled by a power of
-// two for the low-precision range).  With SPLIT every operand x is carried as
-// hi + lo (both low precision) and each product as hi*hi + lo*hi + hi*lo.
-// Record per point: Kaa upper tiles [MA(MA+1)/2][256], KaF^T tiles [MA][256],
-// KFF tile [256].
-template <int MA>
-struct Frags {
-    v4u h[2][MA], l[2][MA];
-};
-
-// fragments of the mode tiles of Ghat for the ECM point pair (q, q + 1);
-// the fragment array holds MT tiles per ECM point
-template <int MA, bool SPLIT>
-__device__ __forceinline__ void load_frags(const EvalArgs& A, int q, int lane, Frags<MA>& F) {
-#pragma unroll
-    for (int s2 = 0; s2 < 2; s2++) {
-        const v4u* fh = (const v4u*)(A.Fhi) + ((int64_t)(q + s2) * A.MT) * 64 + lane;
-        const v4u* fl = (const v4u*)(A.Flo) + ((int64_t)(q + s2) * A.MT) * 64 + lane;
-#pragma unroll
-        for (int t = 0; t < MA; t++) {
-            F.h[s2][t] = fh[t * 64];
-            if (SPLIT) F.l[s2][t] = fl[t * 64];
-        }
-    }
+// T tile (accumulator rows 4g + e) -> K-step B operand
+template <int PREC, bool SPLIT>
+__device__ __forceinline__ v4u32 t_operand(v4f T) {
+    const uint32_t hA = Pk<PREC>::pack(T[0], T[1]);
+    const uint32_t lA = SPLIT ? Pk<PREC>::pack(T[0] - Pk<PREC>::lo(hA), T[1] - Pk<PREC>::hi(hA)) : 0u;
+    const uint32_t hB = Pk<PREC>::pack(T[2], T[2]);
+    const uint32_t lB = SPLIT ? Pk<PREC>::pack(T[2] - Pk<PREC>::lo(hB), 0.f) : 0u;
+    // lanes 0..31 take lB of lanes 32..63, lanes 32..63 keep hB
+    const auto sw = __builtin_amdgcn_permlane32_swap(lB, hB, false, false);
+    return v4u32{hA, hA, lA, (uint32_t)sw[1]};
 }
 
-template <int MA>
-struct MixAcc {
-    v4f kaa[MA * (MA + 1) / 2];
-    v4f kaf[MA];
-    float kff[4];
-};
-
-// contraction of one ECM point pair; bq points at the pair's 2 x 13 scalars
-template <int MA, int PREC, bool SPLIT>
-__device__ __forceinline__ void tangent_pair(const float* bq0, const Frags<MA>& G, const int* o1,
-                                             const int* o2, const int* o3, const int* o4,
-                                             const float* dl, const float* vl, MixAcc<MA>& R) {
-    constexpr int LQ = 13;
-    v4u Th[2][MA], Tl[2][MA];
-#pragma unroll
-    for (int s2 = 0; s2 < 2; s2++) {
-        const float* bq = bq0 + s2 * LQ;
-        const float c0 = bq[9], c1 = bq[10], c2 = bq[11];
-        float wv[4];
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            wv[e] = vl[e] * (c1 * bq[o1[e]] * bq[o2[e]] + c2 * bq[o3[e]] * bq[o4[e]] + dl[e] * c0);
-            R.kff[e] += wv[e];
-        }
-        v4u Wh, Wl;
-        split4<PREC>(wv, Wh, Wl);
-        // split terms outermost so that consecutive MFMAs write independent tiles
-        v4f T[MA];
-#pragma unroll
-        for (int t = 0; t < MA; t++) T[t] = LP<PREC>::mfma16(Wh, G.h[s2][t], v4f{0.f, 0.f, 0.f, 0.f});
-        if (SPLIT) {
-#pragma unroll
-            for (int t = 0; t < MA; t++) T[t] = LP<PREC>::mfma16(Wl, G.h[s2][t], T[t]);
-#pragma unroll
-            for (int t = 0; t < MA; t++) T[t] = LP<PREC>::mfma16(Wh, G.l[s2][t], T[t]);
-        }
-#pragma unroll
-        for (int t = 0; t < MA; t++) {
-            R.kaf[t] += T[t];
-            float tv[4] = {T[t][0], T[t][1], T[t][2], T[t][3]};
-            split4<PREC>(tv, Th[s2][t], Tl[s2][t]);
-        }
-    }
-    {
-        int idx = 0;
-#pragma unroll
-        for (int ti = 0; ti < MA; ti++)
-#pragma unroll
-            for (int tj = ti; tj < MA; tj++, idx++)
-                R.kaa[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Th[0][tj], Th[1][tj], R.kaa[idx]);
-    }
-    if (SPLIT) {
-        int idx = 0;
-#pragma unroll
-        for (int ti = 0; ti < MA; ti++)
-#pragma unroll
-            for (int tj = ti; tj < MA; tj++, idx++)
-                R.kaa[idx] = LP<PREC>::mfma32(G.l[0][ti], G.l[1][ti], Th[0][tj], Th[1][tj], R.kaa[idx]);
-        idx = 0;
-#pragma unroll
-        for (int ti = 0; ti < MA; ti++)
-#pragma unroll
-            for (int tj = ti; tj < MA; tj++, idx++)
-                R.kaa[idx] = LP<PREC>::mfma32(G.h[0][ti], G.h[1][ti], Tl[0][tj], Tl[1][tj], R.kaa[idx]);
-    }
-}
-
-constexpr int kLQ = 13;   // padded stride of the 12 tangent scalars in LDS
-
-template <int MA, int PREC, bool SPLIT, bool PF = true>
-__device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, float (*s_q)[64 * kLQ]) {
+template <int MA, int PREC, bool SPLIT, bool PF>
+__device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ * 64]) {
     constexpr int NA = MA * (MA + 1) / 2;
-    constexpr int LQ = kLQ;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
     int64_t pl = pl0 + wave;
     const bool valid = pl < A.count;
     if (!valid) pl = A.count - 1;
-    float* sq = s_q[wave];
+    v4u32* sw = s_w[wave];
     const float* qsp = (const float*)A.qs + (pl * A.Qpad) * 12;
-    // lane's entries of W: I = c = (i, j), J = 4 g + e = (k, l)
-    int o1[4], o2[4], o3[4], o4[4];
-    float dl[4], vl[4];
+    const v4u32* fp = (const v4u32*)A.Fpk + lane;
+    // records of lanes that carry no tensor row stay zero
+    for (int i = lane; i < kCQ * 64; i += 64) sw[i] = v4u32{0u, 0u, 0u, 0u};
+    // identity fragment: G[J][column c] = 1 for J = component of accumulator row c
+    v4u32 Ip;
     {
-        const int cc = c < 9 ? c : 0;
-        const int i = cc / 3, j = cc % 3;
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const int J = 4 * g + e < 9 ? 4 * g + e : 0;
-            const int k = J / 3, l = J % 3;
-            o1[e] = 3 * l + i;
-            o2[e] = 3 * j + k;
-            o3[e] = 3 * j + i;
-            o4[e] = 3 * l + k;
-            dl[e] = (k == i && l == j) ? 1.f : 0.f;
-            vl[e] = (c < 9 && 4 * g + e < 9) ? 1.f : 0.f;
-        }
+        const int K = pos_comp(c);
+        const int a = (g < 3) ? 2 * g : 6, b = a + 1;
+        const uint32_t ha = (K == a) ? Pk<PREC>::one : 0u, hb = (K == b) ? Pk<PREC>::one : 0u;
+        const uint32_t h8 = (K == 8) ? Pk<PREC>::one : 0u;
+        Ip = v4u32{ha | (hb << 16), 0u, ha | (hb << 16), (g == 1 || g == 3) ? h8 : 0u};
     }
-    MixAcc<MA> R;
+    v4f acc[NA], accF[MA], accFF = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < NA; i++) R.kaa[i] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < NA; i++) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < MA; i++) R.kaf[i] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int e = 0; e < 4; e++) R.kff[e] = 0.f;
+    for (int i = 0; i < MA; i++) accF[i] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    for (int q0 = 0; q0 < A.Qpad; q0 += 64) {
-        {
-            const v4f* src = (const v4f*)(qsp + (int64_t)(q0 + lane) * 12);
-            const v4f x0 = src[0], x1 = src[1], x2 = src[2];
-            float* d = sq + lane * LQ;
+    v4u32 Gc[MA];
+    if (PF) {
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                d[k] = x0[k];
-                d[4 + k] = x1[k];
-                d[8 + k] = x2[k];
+        for (int t = 0; t < MA; t++) Gc[t] = fp[t * 64];
+    }
+    for (int q0 = 0; q0 < A.Qpad; q0 += kCQ) {
+        // ---- W rows of this round: lane (qq, u) builds rows u, u + 4, u + 8 of W_{q0+qq}
+        {
+            const int qq = lane >> 2, u = lane & 3;
+            const v4f* src = (const v4f*)(qsp + (int64_t)(q0 + qq) * 12);
+            const v4f x0 = src[0], x1 = src[1], x2 = src[2];
+            const float F[9] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3], x2[0]};
+            const float c0 = x2[1], c1 = x2[2], c2 = x2[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                const int KI = u + 4 * r;
+                if (KI < 9) {
+                    // W[(i,j)][(k,l)] = c1 F(l,i) F(j,k) + c2 F(j,i) F(l,k) + c0 [k = i][l = j]
+                    const int i = KI / 3, j = KI - 3 * (KI / 3);
+                    float col[3], row[3], ei[3], ej[3];
+#pragma unroll
+                    for (int t = 0; t < 3; t++) {
+                        col[t] = c1 * (i == 0 ? F[3 * t] : (i == 1 ? F[3 * t + 1] : F[3 * t + 2]));
+                        row[t] = (j == 0 ? F[t] : (j == 1 ? F[3 + t] : F[6 + t]));
+                        ei[t] = (t == i) ? c0 : 0.f;
+                        ej[t] = (t == j) ? 1.f : 0.f;
+                    }
+                    const float sji = c2 * (i == 0 ? row[0] : (i == 1 ? row[1] : row[2]));
+                    float w[9];
+#pragma unroll
+                    for (int k = 0; k < 3; k++)
+#pragma unroll
+                        for (int l = 0; l < 3; l++)
+                            w[3 * k + l] = fmaf(col[l], row[k], fmaf(sji, F[3 * l + k], ei[k] * ej[l]));
+                    v4u32 rec[4];
+                    w_records<PREC, SPLIT>(w, rec);
+                    v4u32* dst = sw + qq * 64 + comp_pos(KI);
+#pragma unroll
+                    for (int gg = 0; gg < 4; gg++) dst[16 * gg] = rec[gg];
+                }
             }
         }
-        __syncthreads();
-        if (PF) {
-            // two fragment buffers: the next pair loads while this one is contracted
-            Frags<MA> FA, FB;
-            load_frags<MA, SPLIT>(A, q0, lane, FA);
-            for (int qp = 0; qp < 32; qp += 2) {
-                load_frags<MA, SPLIT>(A, q0 + 2 * (qp + 1), lane, FB);
-                tangent_pair<MA, PREC, SPLIT>(sq + (2 * qp) * LQ, FA, o1, o2, o3, o4, dl, vl, R);
-                if (qp + 2 < 32) load_frags<MA, SPLIT>(A, q0 + 2 * (qp + 2), lane, FA);
-                tangent_pair<MA, PREC, SPLIT>(sq + (2 * qp + 2) * LQ, FB, o1, o2, o3, o4, dl, vl, R);
+        // ---- contraction over the round (LDS traffic of one wavefront is in order)
+        for (int qi = 0; qi < kCQ; qi++) {
+            const int q = q0 + qi;
+            const v4u32 Wp = sw[qi * 64 + lane];
+            v4u32 Gn[MA];
+            if (PF) {
+                const int qn = (q + 1 < A.Qpad) ? q + 1 : q;
+#pragma unroll
+                for (int t = 0; t < MA; t++) Gn[t] = fp[((int64_t)qn * MA + t) * 64];
+            } else {
+#pragma unroll
+                for (int t = 0; t < MA; t++) Gc[t] = fp[((int64_t)q * MA + t) * 64];
             }
-        } else {
-            for (int qp = 0; qp < 32; qp++) {
-                Frags<MA> FA;
-                load_frags<MA, SPLIT>(A, q0 + 2 * qp, lane, FA);
-                tangent_pair<MA, PREC, SPLIT>(sq + (2 * qp) * LQ, FA, o1, o2, o3, o4, dl, vl, R);
+            v4u32 BK[MA];
+#pragma unroll
+            for (int t = 0; t < MA; t++) {
+                const v4f T = Pk<PREC>::mfma(Wp, Gc[t], v4f{0.f, 0.f, 0.f, 0.f});
+                accF[t] = Pk<PREC>::mfma(Gc[t], Wp, accF[t]);
+                BK[t] = t_operand<PREC, SPLIT>(T);
+            }
+            accFF = Pk<PREC>::mfma(Wp, Ip, accFF);
+            int idx = 0;
+#pragma unroll
+            for (int ti = 0; ti < MA; ti++)
+#pragma unroll
+                for (int tj = ti; tj < MA; tj++, idx++) acc[idx] = Pk<PREC>::mfma(Gc[ti], BK[tj], acc[idx]);
+            if (PF) {
+#pragma unroll
+                for (int t = 0; t < MA; t++) Gc[t] = Gn[t];
             }
         }
-        __syncthreads();
     }
     if (!valid) return;
     float* kh = (float*)A.Khat + (int64_t)pl * (NA + MA + 1) * 256 + lane * 4;
 #pragma unroll
-    for (int i = 0; i < NA; i++) *(v4f*)(kh + i * 256) = R.kaa[i];
+    for (int i = 0; i < NA; i++) *(v4f*)(kh + i * 256) = acc[i];
 #pragma unroll
-    for (int i = 0; i < MA; i++) *(v4f*)(kh + (NA + i) * 256) = R.kaf[i];
-    *(v4f*)(kh + (NA + MA) * 256) = v4f{R.kff[0], R.kff[1], R.kff[2], R.kff[3]};
+    for (int i = 0; i < MA; i++) *(v4f*)(kh + (NA + i) * 256) = accF[i];
+    *(v4f*)(kh + (NA + MA) * 256) = accFF;
 }
 
 // OCC2: ask for two wavefronts per SIMD (register cap 256)
 template <int MA, int PREC, bool SPLIT, bool PF, bool OCC2>
 __global__ void __launch_bounds__(256, (OCC2 && MA <= 4) ? 2 : 1) k_eval_mixed(EvalArgs A) {
-    __shared__ float s_q[4][64 * kLQ];
-    tan_mixed_body<MA, PREC, SPLIT, PF>(A, (int64_t)blockIdx.x * 4, s_q);
+    __shared__ v4u32 s_w[4][kCQ * 64];
+    tan_mixed_body<MA, PREC, SPLIT, PF>(A, (int64_t)blockIdx.x * 4, s_w);
 }
 
 template <int PREC, bool SPLIT, bool PF, bool OCC2>
@@ -666,7 +613,7 @@ static int launch_mixed_v(int variant, const EvalArgs& a, hipStream_t s) {
     }
 }
 
-// variant bit 0: one wavefront per SIMD instead of two; bit 1: no double buffer
+// variant bit 0: one wavefront per SIMD instead of two; bit 1: no prefetch
 int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s) {
     (void)MT;
     if (prec == HROM_MIXED_BF16)
@@ -684,7 +631,7 @@ __device__ inline EvalArgs group_eval_args(const GroupCall& G, int c, size_t tsz
     EvalArgs A;
     A.m = C.m; A.Q = C.Q; A.Qpad = C.Qpad; A.MP = C.MP; A.MT = C.MT; A.KS = C.KS;
     A.first = C.first; A.count = C.count; A.N = G.N;
-    A.Ghat = C.Ghat; A.Gf = C.Gf; A.w = C.w; A.phase = C.phase; A.Fhi = C.Fhi; A.Flo = C.Flo;
+    A.Ghat = C.Ghat; A.Gf = C.Gf; A.w = C.w; A.phase = C.phase; A.Fpk = C.Fpk;
     A.theta = G.theta; A.Fr = G.Fr; A.a = G.a + C.off_a;
     A.qs = (char*)G.qs + tsz * (size_t)C.ws_qs;
     A.Khat = (char*)G.Khat + tsz * (size_t)C.ws_khat;
@@ -716,8 +663,6 @@ __global__ void k_reset_counter(int* counter) { *counter = 0; }
 // workgroup leaves when the queue is exhausted.
 template <int PREC, bool SPLIT>
 __global__ void __launch_bounds__(256, 1) k_tan_persistent(GroupCall G) {
-    __shared__ float s_q[4][64 * kLQ];
-    __shared__ double s_st[4][12 * 64];
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(G.counter, 1);
@@ -728,6 +673,7 @@ __global__ void __launch_bounds__(256, 1) k_tan_persistent(GroupCall G) {
         const WorkItem w = G.items[it];
         const int64_t pl0 = (int64_t)w.unit * 4;
         if constexpr (PREC == HROM_FP64) {
+            __shared__ double s_st[4][12 * 64];
             const EvalArgs A = group_eval_args(G, w.c, sizeof(double));
             switch (A.MT) {
                 case 2: tan_f64_body<2>(A, pl0, s_st); break;
@@ -738,14 +684,15 @@ __global__ void __launch_bounds__(256, 1) k_tan_persistent(GroupCall G) {
                 default: tan_f64_body<7>(A, pl0, s_st); break;
             }
         } else {
+            __shared__ v4u32 s_w[4][kCQ * 64];
             const EvalArgs A = group_eval_args(G, w.c, sizeof(float));
             switch ((A.m + 15) / 16) {
-                case 1: tan_mixed_body<1, PREC, SPLIT>(A, pl0, s_q); break;
-                case 2: tan_mixed_body<2, PREC, SPLIT>(A, pl0, s_q); break;
-                case 3: tan_mixed_body<3, PREC, SPLIT>(A, pl0, s_q); break;
-                case 4: tan_mixed_body<4, PREC, SPLIT>(A, pl0, s_q); break;
-                case 5: tan_mixed_body<5, PREC, SPLIT>(A, pl0, s_q); break;
-                default: tan_mixed_body<6, PREC, SPLIT>(A, pl0, s_q); break;
+                case 1: tan_mixed_body<1, PREC, SPLIT, true>(A, pl0, s_w); break;
+                case 2: tan_mixed_body<2, PREC, SPLIT, true>(A, pl0, s_w); break;
+                case 3: tan_mixed_body<3, PREC, SPLIT, true>(A, pl0, s_w); break;
+                case 4: tan_mixed_body<4, PREC, SPLIT, true>(A, pl0, s_w); break;
+                case 5: tan_mixed_body<5, PREC, SPLIT, true>(A, pl0, s_w); break;
+                default: tan_mixed_body<6, PREC, SPLIT, true>(A, pl0, s_w); break;
             }
         }
         __syncthreads();

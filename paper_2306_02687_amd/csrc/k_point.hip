@@ -391,31 +391,49 @@ __global__ void k_build_ghat(LayoutArgs A) {
     }
 }
 
-// MFMA fragments: lane (g, c) of tile t holds Ghat[q][4g + e][16 t + c], e = 0..3
-// (rows >= 9 are zero), split into a hi part and the rounded remainder.
+// Packed MFMA fragments of the mode gradients for the mixed tangent: ECM point
+// q, mode tile t, lane (g, c) holds 8 low-precision values for mode column
+// n = 16 t + c, one per k-slot of a 16x16x32 MFMA.  The nine tensor
+// components are spread over the four lane groups as (0,1), (2,3), (4,5),
+// (6,7,8); with a, b (and d = 8 in group 3) the group's components the slots
+// are
+//   groups 0..2: Gh[a] Gh[b] Gl[a] Gl[b] Gh[a] Gh[b] (group 1: Gh[8]) 0
+//   group 3:     Gh[a] Gh[b] Gl[a] Gl[b] Gh[a] Gh[b] Gh[8] Gl[8]
+// (hi part Gh and rounded remainder Gl; Gl = 0 without the split).  Paired
+// with the matching W or T slots, one MFMA forms all three split products
+// hi*hi + lo*hi + hi*lo of the nine-component contraction.
 __global__ void k_build_frags(LayoutArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t tot = (int64_t)A.Qpad * A.MT * 64 * 4;
+    const int MA = (A.m + 15) / 16;
+    const int64_t tot = (int64_t)A.Qpad * MA * 64 * 8;
     if (t >= tot) return;
-    const int e = (int)(t & 3);
-    const int lane = (int)((t >> 2) & 63);
-    const int tile = (int)((t >> 8) % A.MT);
-    const int q = (int)((t >> 8) / A.MT);
+    const int s = (int)(t & 7);
+    const int lane = (int)((t >> 3) & 63);
+    const int tile = (int)((t >> 9) % MA);
+    const int q = (int)((t >> 9) / MA);
     const int g = lane >> 4, c = lane & 15;
-    const int J = 4 * g + e;
     const int n = 16 * tile + c;
-    double v = 0.0;
-    if (J < 9) v = A.Ghat[((int64_t)q * 9 + J) * A.MP + n];
-    uint16_t hi, lo;
-    if (A.prec == HROM_MIXED_BF16) {
-        hi = to_bf16_bits((float)v);
-        lo = to_bf16_bits((float)(v - (double)from_bf16_bits(hi)));
-    } else {
-        hi = to_f16_bits((float)v);
-        lo = to_f16_bits((float)(v - (double)from_f16_bits(hi)));
+    const int a = (g < 3) ? 2 * g : 6, b = a + 1;
+    int comp = -1, lo = 0;
+    switch (s) {
+        case 0: case 4: comp = a; break;
+        case 1: case 5: comp = b; break;
+        case 2: comp = a; lo = 1; break;
+        case 3: comp = b; lo = 1; break;
+        case 6: comp = (g == 1 || g == 3) ? 8 : -1; break;
+        default: comp = (g == 3) ? 8 : -1; lo = 1; break;
     }
-    A.Fhi[t] = hi;
-    A.Flo[t] = lo;
+    double v = 0.0;
+    if (comp >= 0 && q < A.Q && n < A.m) v = A.G[((int64_t)q * 9 + comp) * A.m + n];
+    uint16_t bits;
+    if (A.prec == HROM_MIXED_BF16) {
+        const uint16_t hi = to_bf16_bits((float)v);
+        bits = lo ? (A.split ? to_bf16_bits((float)(v - (double)from_bf16_bits(hi))) : 0) : hi;
+    } else {
+        const uint16_t hi = to_f16_bits((float)v);
+        bits = lo ? (A.split ? to_f16_bits((float)(v - (double)from_f16_bits(hi))) : 0) : hi;
+    }
+    A.Fpk[t] = bits;
 }
 
 // A-operand fragments of the kinematics GEMM (FP64 16x16x4 MFMA): row tile
@@ -440,7 +458,7 @@ void launch_build_layouts(const LayoutArgs& a, hipStream_t s) {
     const int64_t n3 = (int64_t)a.Qpad * 9 / 16 * a.KS * 64;
     hipLaunchKernelGGL(k_build_gf, dim3(nblocks(n3, 256)), dim3(256), 0, s, a);
     if (a.prec != HROM_FP64) {
-        const int64_t n2 = (int64_t)a.Qpad * a.MT * 256;
+        const int64_t n2 = (int64_t)a.Qpad * ((a.m + 15) / 16) * 512;
         hipLaunchKernelGGL(k_build_frags, dim3(nblocks(n2, 256)), dim3(256), 0, s, a);
     }
 }
