@@ -47,7 +47,7 @@ void free_plan(Plan& p) {
     dfree(p.piv); dfree(p.y); dfree(p.X); dfree(p.Palg); dfree(p.Cr); dfree(p.S);
     dfree(p.rnorm); dfree(p.dU); dfree(p.gr); dfree(p.Lam); dfree(p.lam); dfree(p.rho);
     dfree(p.hr); dfree(p.gth);
-    dfree(p.cls_dev); dfree(p.items_kin); dfree(p.items_tan); dfree(p.counter);
+    dfree(p.cls_dev); dfree(p.items_kin); dfree(p.items_bw); dfree(p.items_tan); dfree(p.counter);
 }
 
 int hip_status() { return hipGetLastError() == hipSuccess ? HROM_OK : HROM_E_HIP; }
@@ -76,7 +76,7 @@ int upload(T** dst, const std::vector<T>& v) {
 int build_groups(Plan& p) {
     p.grouped = p.ncl > 1;
     std::vector<ClusterGPU> cg;
-    std::vector<WorkItem> kin, tan;
+    std::vector<WorkItem> kin, bw, tan;
     p.max_m = 0;
     for (int c = 0; c < p.ncl; c++) {
         const ClusterDev& d = p.cl[c];
@@ -88,7 +88,8 @@ int build_groups(Plan& p) {
         g.wscale = mixed(p) ? wscale_for(d.Q) : 1.0f;
         cg.push_back(g);
         p.max_m = std::max(p.max_m, d.m);
-        for (int64_t u = 0; u < (d.count + 15) / 16; u++) kin.push_back(WorkItem{c, (int)u});
+        for (int64_t u = 0; u < (d.count + 31) / 32; u++) kin.push_back(WorkItem{c, (int)u});
+        for (int64_t u = 0; u < (d.count + 15) / 16; u++) bw.push_back(WorkItem{c, (int)u});
         for (int64_t u = 0; u < (d.count + 3) / 4; u++) tan.push_back(WorkItem{c, (int)u});
     }
     // most expensive tiles first: kinematics ~ m Q, tangent ~ MT^2 Q
@@ -99,9 +100,12 @@ int build_groups(Plan& p) {
     };
     std::stable_sort(kin.begin(), kin.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost_kin(x) > cost_kin(y); });
+    std::stable_sort(bw.begin(), bw.end(),
+                     [&](const WorkItem& x, const WorkItem& y) { return cost_kin(x) > cost_kin(y); });
     std::stable_sort(tan.begin(), tan.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost_tan(x) > cost_tan(y); });
     p.n_kin = (int)kin.size();
+    p.n_bw = (int)bw.size();
     p.n_tan = (int)tan.size();
     int ncu = 256;
     hipDeviceProp_t prop;
@@ -110,6 +114,7 @@ int build_groups(Plan& p) {
     p.persistent_grid = std::min(p.n_tan, 2 * ncu);
     int rc = upload(&p.cls_dev, cg);
     if (rc == HROM_OK) rc = upload(&p.items_kin, kin);
+    if (rc == HROM_OK) rc = upload(&p.items_bw, bw);
     if (rc == HROM_OK) rc = upload(&p.items_tan, tan);
     if (rc == HROM_OK) rc = dalloc(&p.counter, 1);
     return rc;
@@ -474,7 +479,7 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
         GroupCall g = group_call(p);
         g.theta = theta; g.Fr = p.Fr; g.a = a; g.lam = p.lam; g.gr = p.gr; g.hr = p.hr;
         g.gth = p.gth; g.rho = p.rho; g.status = status; g.X = p.X;
-        g.items = p.items_kin; g.nitems = p.n_kin;
+        g.items = p.items_bw; g.nitems = p.n_bw;
         launch_lambda_grouped(g, p.a_len, stream);
         if (refine(p)) {
             g.with_rho = 1;

@@ -88,9 +88,10 @@ struct Plan {
     int max_m = 0;
     int persistent_grid = 512;
     ClusterGPU* cls_dev = nullptr;
-    WorkItem* items_kin = nullptr;   // 16-point tiles, decreasing cost
+    WorkItem* items_kin = nullptr;   // 32-point tiles (kinematics), decreasing cost
+    WorkItem* items_bw = nullptr;    // 16-point tiles (adjoint), decreasing cost
     WorkItem* items_tan = nullptr;   // 4-point tiles, decreasing cost
-    int n_kin = 0, n_tan = 0;
+    int n_kin = 0, n_bw = 0, n_tan = 0;
     int* counter = nullptr;
 };
 
@@ -276,8 +277,8 @@ struct ClusterGPU {
 
 struct WorkItem {
     int c;      // cluster
-    int unit;   // tile of the cluster (16 points for the kinematics and adjoint
-                // kernels, 4 points for the tangent contraction)
+    int unit;   // tile of the cluster (32 points for the kinematics, 16 for the
+                // adjoint, 4 for the tangent contraction)
 };
 
 struct GroupCall {

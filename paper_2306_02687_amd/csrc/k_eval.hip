@@ -59,30 +59,43 @@ __device__ __forceinline__ void tangent_row(const T* Fi, T c0, T c1, T c2, T* W)
 
 
 // ============================================================== kinematics
+// 32 macro points per workgroup of eight wavefronts, ECM points in rounds of
+// 16.  Every FP64 MFMA operand of G is used for two 16-point column tiles.
+// Per round:
+//   F - F_r = G a      144 rows (ECM point, component) x 32 points; wave w takes
+//                      row tile w, waves 0..3 also a k-range of row tile 8
+//                      (partial sums added in a fixed order)
+//   law                thread = (point, ECM point): w P, tangent scalars
+//   r += G^T (w P)     the round's 36 k-steps split over the waves
+//                      (fixed-order sum over the waves at the end)
+//   Pbar_r += w P      fixed-order sum over the round's ECM points
+constexpr int kKinPT = 32;
 struct KinLds {
-    double sA[kMaxModes + 4][16];
-    double sF[16 * 9][17];
-    double sWP[16 * 9][17];
-    double sU[9][16];
-    int sbits[16];
+    double sA[kMaxModes + 4][kKinPT];
+    double sF[16 * 9][kKinPT + 1];
+    double sF8[4][16][kKinPT + 1];
+    double sWP[16 * 9][kKinPT + 1];
+    double sU[9][kKinPT];
+    int sbits[kKinPT];
 };
 
-// the 16 macro points p0 .. p0+15 of the cluster described by A
-template <bool MIXED>
+// the 32 macro points p0 .. p0+31 of the cluster described by A; MA = ceil(m / 16)
+template <bool MIXED, int MA>
 __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
-    constexpr int PT = 16, QC = 16;
+    constexpr int PT = kKinPT, QC = 16;
     auto& sA = L.sA;
     auto& sF = L.sF;
+    auto& sF8 = L.sF8;
     auto& sWP = L.sWP;
     auto& sU = L.sU;
     auto& sbits = L.sbits;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, c = lane & 15;
-    const int m = A.m, KS = A.KS, MP = A.MP, MT = A.MT;
+    const int m = A.m, KS = A.KS, MP = A.MP;
     const int np = (int)min((int64_t)PT, A.count - p0);
     if (tid < PT) sbits[tid] = 0;
     __syncthreads();
-    for (int e = tid; e < 4 * KS * PT; e += 256) {
+    for (int e = tid; e < 4 * KS * PT; e += 512) {
         const int k = e / PT, p = e % PT;
         double v = 0.0;
         if (k < m && p < np) {
@@ -94,55 +107,69 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
         }
         sA[k][p] = v;
     }
-    for (int e = tid; e < 9 * PT; e += 256) {
+    for (int e = tid; e < 9 * PT; e += 512) {
         const int I = e / PT, p = e % PT;
         sU[I][p] = (p < np) ? A.Fr[(int64_t)I * A.N + A.first + p0 + p] : ((I % 4 == 0) ? 1.0 : 0.0);
     }
     const double mu0 = A.theta[0], la0 = A.theta[1], mu1 = A.theta[2], la1 = A.theta[3];
-    // rhat partial sums: wave w takes k-steps 9w .. 9w+8 of every chunk, all tiles
-    v4d racc[8];
+    v4d racc[MA][2];
 #pragma unroll
-    for (int t = 0; t < 8; t++) racc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < MA; t++) racc[t][0] = racc[t][1] = v4d{0.0, 0.0, 0.0, 0.0};
+    double pacc = 0.0;   // Pbar_r (I = tid / 32, point tid % 32) for tid < 288
+    const int klo = (wave * KS) >> 2, khi = ((wave + 1) * KS) >> 2;
+    const int js = (wave * 36) >> 3, je = ((wave + 1) * 36) >> 3;
     __syncthreads();
 
     for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
-        // operands of this chunk's residual GEMM, issued first so that their
-        // latency hides behind the kinematics GEMM and the material law
-        double gr[9][8];
-        {
-            const double* gh = A.Ghat + (int64_t)(q0 * 9 + 36 * wave + g) * MP + c;
-#pragma unroll
-            for (int j = 0; j < 9; j++)
-#pragma unroll
-                for (int t = 0; t < 8; t++)
-                    if (t < MT) gr[j][t] = gh[(int64_t)(4 * j) * MP + 16 * t];
-        }
-        // F - Fr for the 16 points and the 16 ECM points of the chunk: 9 row tiles
         const int rt0 = (q0 / 16) * 9;
-        for (int t = wave; t < 9; t += 4) {
-            const double* gf = A.Gf + ((int64_t)(rt0 + t) * KS) * 64 + lane;
-            double af[24];
+        // ---- F - Fr: row tile `wave`
+        {
+            const double* gf = A.Gf + ((int64_t)(rt0 + wave) * KS) * 64 + lane;
+            double af[4 * MA];
 #pragma unroll
-            for (int s2 = 0; s2 < 24; s2++)
+            for (int s2 = 0; s2 < 4 * MA; s2++)
                 if (s2 < KS) af[s2] = gf[(int64_t)s2 * 64];
-            v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+            v4d a0 = v4d{0.0, 0.0, 0.0, 0.0}, a1 = a0;
 #pragma unroll
-            for (int s2 = 0; s2 < 24; s2++)
-                if (s2 < KS)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][c], acc, 0, 0, 0);
+            for (int s2 = 0; s2 < 4 * MA; s2++)
+                if (s2 < KS) {
+                    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][c], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][16 + c], a1, 0, 0, 0);
+                }
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const int row = 16 * t + g + 4 * e;   // FP64 MFMA accumulator rows interleave
-                sF[row][c] = acc[e] + sU[row % 9][c];
+                const int row = 16 * wave + g + 4 * e;   // FP64 MFMA accumulator rows interleave
+                sF[row][c] = a0[e] + sU[row % 9][c];
+                sF[row][16 + c] = a1[e] + sU[row % 9][16 + c];
+            }
+        }
+        // ---- row tile 8: a k-range per wave 0..3
+        if (wave < 4) {
+            const double* gf = A.Gf + ((int64_t)(rt0 + 8) * KS) * 64 + lane;
+            v4d a0 = v4d{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+            for (int s2 = klo; s2 < khi; s2++) {
+                const double av = gf[(int64_t)s2 * 64];
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sA[4 * s2 + g][c], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sA[4 * s2 + g][16 + c], a1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                sF8[wave][g + 4 * e][c] = a0[e];
+                sF8[wave][g + 4 * e][16 + c] = a1[e];
             }
         }
         __syncthreads();
-        // material law: thread = (point p, ECM point q0 + qq)
+        // ---- material law: thread = (point p, ECM point q0 + qq)
         {
             const int p = tid >> 4, qq = tid & 15, q = q0 + qq;
             double F[9];
 #pragma unroll
-            for (int I = 0; I < 9; I++) F[I] = sF[qq * 9 + I][p];
+            for (int I = 0; I < 9; I++) {
+                const int row = qq * 9 + I;
+                F[I] = (row < 128) ? sF[row][p]
+                                   : ((sF8[0][row - 128][p] + sF8[1][row - 128][p]) +
+                                      (sF8[2][row - 128][p] + sF8[3][row - 128][p])) + sU[I][p];
+            }
             const double wq = A.w[q];
             const int ph = A.phase[q];
             const double mu = ph ? mu1 : mu0, la = ph ? la1 : la0;
@@ -184,37 +211,47 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
             }
         }
         __syncthreads();
-        // rhat += Ghat^T (w P): this wave's 9 k-steps of the chunk
+        // ---- r += G^T (w P): this wave's k-steps of the round, the mode tiles
+        for (int j = js; j < je; j++) {
+            const double b0 = sWP[4 * j + g][c], b1 = sWP[4 * j + g][16 + c];
+            const double* gh = A.Ghat + (int64_t)(q0 * 9 + 4 * j + g) * MP + c;
 #pragma unroll
-        for (int j = 0; j < 9; j++) {
-            const double bv = sWP[36 * wave + 4 * j + g][c];
+            for (int t = 0; t < MA; t++) {
+                    const double av = gh[16 * t];
+                    racc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, racc[t][0], 0, 0, 0);
+                    racc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, racc[t][1], 0, 0, 0);
+                }
+        }
+        // ---- Pbar_r += sum over the round's ECM points of w P
+        if (tid < 9 * PT) {
+            const int I = tid >> 5, p = tid & 31;
+            double sp = 0.0;
 #pragma unroll
-            for (int t = 0; t < 8; t++)
-                if (t < MT) racc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gr[j][t], bv, racc[t], 0, 0, 0);
+            for (int qq = 0; qq < QC; qq++) sp += sWP[qq * 9 + I][p];
+            pacc += sp;
         }
         __syncthreads();
     }
-    // fixed-order sum of the four waves' partial rhat, through LDS (sF reused:
-    // [wave][tile rows][point] would need 4 x 128 x 16 doubles, so the sum runs
-    // tile by tile)
+    if (tid < 9 * PT && (tid & 31) < np)
+        A.Pr[(int64_t)(tid >> 5) * A.N + A.first + p0 + (tid & 31)] = pacc;
+    // fixed-order sum of the eight waves' partial r through LDS (sF reused)
     double* red = &sF[0][0];
 #pragma unroll
-    for (int t = 0; t < 8; t++) {
-        if (t >= MT) break;
+    for (int t = 0; t < MA; t++) {
 #pragma unroll
-        for (int e = 0; e < 4; e++) red[(wave * 16 + g + 4 * e) * 16 + c] = racc[t][e];
+        for (int e = 0; e < 4; e++) {
+            red[(wave * 16 + g + 4 * e) * PT + c] = racc[t][0][e];
+            red[(wave * 16 + g + 4 * e) * PT + 16 + c] = racc[t][1][e];
+        }
         __syncthreads();
-        if (wave == 0) {
+        {
+            const int rr = tid >> 5, p = tid & 31;   // 16 rows x 32 points
+            if (tid < 16 * PT) {
+                double v = 0.0;
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int rr = g + 4 * e;
-                const double v = ((red[(0 * 16 + rr) * 16 + c] + red[(1 * 16 + rr) * 16 + c]) +
-                                  red[(2 * 16 + rr) * 16 + c]) + red[(3 * 16 + rr) * 16 + c];
+                for (int w = 0; w < 8; w++) v += red[(w * 16 + rr) * PT + p];
                 const int row = 16 * t + rr;
-                if (c < np) {
-                    if (row < m) A.r[(int64_t)row * A.count + p0 + c] = v;
-                    else if (row < m + 9) A.Pr[(int64_t)(row - m) * A.N + A.first + p0 + c] = v;
-                }
+                if (p < np && row < m) A.r[(int64_t)row * A.count + p0 + p] = v;
             }
         }
         __syncthreads();
@@ -222,17 +259,41 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
     if (tid < np && sbits[tid]) A.status[A.first + p0 + tid] |= sbits[tid];
 }
 
-template <bool MIXED>
-__global__ void __launch_bounds__(256) k_kin(EvalArgs A) {
+template <bool MIXED, int MA>
+__global__ void __launch_bounds__(512) k_kin(EvalArgs A) {
     __shared__ KinLds L;
-    kin_body<MIXED>(A, (int64_t)blockIdx.x * 16, L);
+    kin_body<MIXED, MA>(A, (int64_t)blockIdx.x * kKinPT, L);
+}
+
+template <bool MIXED>
+__device__ void kin_dispatch(const EvalArgs& A, int64_t p0, KinLds& L) {
+    switch ((A.m + 15) / 16) {
+        case 1: kin_body<MIXED, 1>(A, p0, L); break;
+        case 2: kin_body<MIXED, 2>(A, p0, L); break;
+        case 3: kin_body<MIXED, 3>(A, p0, L); break;
+        case 4: kin_body<MIXED, 4>(A, p0, L); break;
+        case 5: kin_body<MIXED, 5>(A, p0, L); break;
+        default: kin_body<MIXED, 6>(A, p0, L); break;
+    }
+}
+
+template <bool MIXED>
+static void launch_kin_t(const EvalArgs& a, hipStream_t s) {
+    const dim3 grid(nblocks(a.count, kKinPT)), block(512);
+    switch ((a.m + 15) / 16) {
+        case 1: hipLaunchKernelGGL((k_kin<MIXED, 1>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_kin<MIXED, 2>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_kin<MIXED, 3>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_kin<MIXED, 4>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_kin<MIXED, 5>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_kin<MIXED, 6>), grid, block, 0, s, a); break;
+    }
 }
 
 int launch_kin(int mixed, const EvalArgs& a, hipStream_t s) {
-    const dim3 grid(nblocks(a.count, 16)), block(256);
-    if (a.MT > 8) return HROM_E_UNSUPPORTED;
-    if (mixed) hipLaunchKernelGGL(k_kin<true>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(k_kin<false>, grid, block, 0, s, a);
+    if ((a.m + 15) / 16 > 6) return HROM_E_UNSUPPORTED;
+    if (mixed) launch_kin_t<true>(a, s);
+    else launch_kin_t<false>(a, s);
     return HROM_OK;
 }
 
@@ -498,13 +559,22 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
 #pragma unroll
     for (int i = 0; i < MA; i++) accF[i] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    v4u32 Gc[MA];
-    if (PF) {
+    // Software pipeline over ECM points: iteration q issues the T, KaF and
+    // KFF products of q, then the Kaa products of q - 1 (operands kept from the
+    // previous iteration) interleaved with the hi/lo split of T(q), so the
+    // matrix core and the VALU work side by side within one wavefront.
+    v4u32 Gp[MA], Bp[MA];      // previous ECM point: fragments and split T
 #pragma unroll
-        for (int t = 0; t < MA; t++) Gc[t] = fp[t * 64];
+    for (int t = 0; t < MA; t++) {
+        Gp[t] = v4u32{0u, 0u, 0u, 0u};
+        Bp[t] = v4u32{0u, 0u, 0u, 0u};
     }
+    v4u32 Gc[MA];
+#pragma unroll
+    for (int t = 0; t < MA; t++) Gc[t] = fp[t * 64];
     for (int q0 = 0; q0 < A.Qpad; q0 += kCQ) {
-        // ---- W rows of this round: lane (qq, u) builds rows u, u + 4, u + 8 of W_{q0+qq}
+        // ---- W rows of this round: lane (qq, u) builds rows u, u + 4, min(u + 8, 8)
+        // of W_{q0+qq} (row 8 is written by four lanes with identical values)
         {
             const int qq = lane >> 2, u = lane & 3;
             const v4f* src = (const v4f*)(qsp + (int64_t)(q0 + qq) * 12);
@@ -513,64 +583,85 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
             const float c0 = x2[1], c1 = x2[2], c2 = x2[3];
 #pragma unroll
             for (int r = 0; r < 3; r++) {
-                const int KI = u + 4 * r;
-                if (KI < 9) {
-                    // W[(i,j)][(k,l)] = c1 F(l,i) F(j,k) + c2 F(j,i) F(l,k) + c0 [k = i][l = j]
-                    const int i = KI / 3, j = KI - 3 * (KI / 3);
-                    float col[3], row[3], ei[3], ej[3];
+                const int KI = (u + 4 * r < 9) ? u + 4 * r : 8;
+                // W[(i,j)][(k,l)] = c1 F(l,i) F(j,k) + c2 F(j,i) F(l,k) + c0 [k = i][l = j]
+                const int i = KI / 3, j = KI - 3 * (KI / 3);
+                float col[3], row[3], ei[3], ej[3];
 #pragma unroll
-                    for (int t = 0; t < 3; t++) {
-                        col[t] = c1 * (i == 0 ? F[3 * t] : (i == 1 ? F[3 * t + 1] : F[3 * t + 2]));
-                        row[t] = (j == 0 ? F[t] : (j == 1 ? F[3 + t] : F[6 + t]));
-                        ei[t] = (t == i) ? c0 : 0.f;
-                        ej[t] = (t == j) ? 1.f : 0.f;
-                    }
-                    const float sji = c2 * (i == 0 ? row[0] : (i == 1 ? row[1] : row[2]));
-                    float w[9];
-#pragma unroll
-                    for (int k = 0; k < 3; k++)
-#pragma unroll
-                        for (int l = 0; l < 3; l++)
-                            w[3 * k + l] = fmaf(col[l], row[k], fmaf(sji, F[3 * l + k], ei[k] * ej[l]));
-                    v4u32 rec[4];
-                    w_records<PREC, SPLIT>(w, rec);
-                    v4u32* dst = sw + qq * 64 + comp_pos(KI);
-#pragma unroll
-                    for (int gg = 0; gg < 4; gg++) dst[16 * gg] = rec[gg];
+                for (int t = 0; t < 3; t++) {
+                    col[t] = c1 * (i == 0 ? F[3 * t] : (i == 1 ? F[3 * t + 1] : F[3 * t + 2]));
+                    row[t] = (j == 0 ? F[t] : (j == 1 ? F[3 + t] : F[6 + t]));
+                    ei[t] = (t == i) ? c0 : 0.f;
+                    ej[t] = (t == j) ? 1.f : 0.f;
                 }
+                const float sji = c2 * (i == 0 ? row[0] : (i == 1 ? row[1] : row[2]));
+                float w[9];
+#pragma unroll
+                for (int k = 0; k < 3; k++)
+#pragma unroll
+                    for (int l = 0; l < 3; l++)
+                        w[3 * k + l] = fmaf(col[l], row[k], fmaf(sji, F[3 * l + k], ei[k] * ej[l]));
+                v4u32 rec[4];
+                w_records<PREC, SPLIT>(w, rec);
+                v4u32* dst = sw + qq * 64 + comp_pos(KI);
+#pragma unroll
+                for (int gg = 0; gg < 4; gg++) dst[16 * gg] = rec[gg];
             }
         }
         // ---- contraction over the round (LDS traffic of one wavefront is in order)
+        v4u32 Wq = sw[lane];
+#pragma unroll 2
         for (int qi = 0; qi < kCQ; qi++) {
             const int q = q0 + qi;
-            const v4u32 Wp = sw[qi * 64 + lane];
+            const v4u32 Wn = sw[(qi + 1 < kCQ ? qi + 1 : qi) * 64 + lane];
             v4u32 Gn[MA];
             if (PF) {
                 const int qn = (q + 1 < A.Qpad) ? q + 1 : q;
 #pragma unroll
                 for (int t = 0; t < MA; t++) Gn[t] = fp[((int64_t)qn * MA + t) * 64];
-            } else {
-#pragma unroll
-                for (int t = 0; t < MA; t++) Gc[t] = fp[((int64_t)q * MA + t) * 64];
             }
-            v4u32 BK[MA];
+            v4f T[MA];
 #pragma unroll
             for (int t = 0; t < MA; t++) {
-                const v4f T = Pk<PREC>::mfma(Wp, Gc[t], v4f{0.f, 0.f, 0.f, 0.f});
-                accF[t] = Pk<PREC>::mfma(Gc[t], Wp, accF[t]);
-                BK[t] = t_operand<PREC, SPLIT>(T);
+                T[t] = Pk<PREC>::mfma(Wq, Gc[t], v4f{0.f, 0.f, 0.f, 0.f});
+                accF[t] = Pk<PREC>::mfma(Gc[t], Wq, accF[t]);
             }
-            accFF = Pk<PREC>::mfma(Wp, Ip, accFF);
+            accFF = Pk<PREC>::mfma(Wq, Ip, accFF);
             int idx = 0;
 #pragma unroll
             for (int ti = 0; ti < MA; ti++)
 #pragma unroll
-                for (int tj = ti; tj < MA; tj++, idx++) acc[idx] = Pk<PREC>::mfma(Gc[ti], BK[tj], acc[idx]);
+                for (int tj = ti; tj < MA; tj++, idx++) acc[idx] = Pk<PREC>::mfma(Gp[ti], Bp[tj], acc[idx]);
+#pragma unroll
+            for (int t = 0; t < MA; t++) {
+                Bp[t] = t_operand<PREC, SPLIT>(T[t]);
+                Gp[t] = Gc[t];
+            }
+            // issue order: the 2 MA + 1 products of q, then one Kaa product of
+            // q - 1 after every few VALU instructions of the split
+            __builtin_amdgcn_sched_group_barrier(0x008, 2 * MA + 1, 0);
+#pragma unroll
+            for (int i = 0; i < NA; i++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, (13 * MA + NA - 1) / NA, 0);
+            }
             if (PF) {
 #pragma unroll
                 for (int t = 0; t < MA; t++) Gc[t] = Gn[t];
+            } else {
+                const int qn = (q + 1 < A.Qpad) ? q + 1 : q;
+#pragma unroll
+                for (int t = 0; t < MA; t++) Gc[t] = fp[((int64_t)qn * MA + t) * 64];
             }
+            Wq = Wn;
         }
+    }
+    {   // Kaa products of the last ECM point
+        int idx = 0;
+#pragma unroll
+        for (int ti = 0; ti < MA; ti++)
+#pragma unroll
+            for (int tj = ti; tj < MA; tj++, idx++) acc[idx] = Pk<PREC>::mfma(Gp[ti], Bp[tj], acc[idx]);
     }
     if (!valid) return;
     float* kh = (float*)A.Khat + (int64_t)pl * (NA + MA + 1) * 256 + lane * 4;
@@ -642,16 +733,16 @@ __device__ inline EvalArgs group_eval_args(const GroupCall& G, int c, size_t tsz
 
 // kinematics of every cluster in one launch: one 16-point tile per workgroup
 template <bool MIXED>
-__global__ void __launch_bounds__(256) k_kin_grouped(GroupCall G) {
+__global__ void __launch_bounds__(512) k_kin_grouped(GroupCall G) {
     __shared__ KinLds L;
     const WorkItem w = G.items[blockIdx.x];
     const EvalArgs A = group_eval_args(G, w.c, MIXED ? sizeof(float) : sizeof(double));
-    kin_body<MIXED>(A, (int64_t)w.unit * 16, L);
+    kin_dispatch<MIXED>(A, (int64_t)w.unit * kKinPT, L);
 }
 
 int launch_kin_grouped(int mixed, const GroupCall& g, hipStream_t s) {
-    if (mixed) hipLaunchKernelGGL(k_kin_grouped<true>, dim3(g.nitems), dim3(256), 0, s, g);
-    else hipLaunchKernelGGL(k_kin_grouped<false>, dim3(g.nitems), dim3(256), 0, s, g);
+    if (mixed) hipLaunchKernelGGL(k_kin_grouped<true>, dim3(g.nitems), dim3(512), 0, s, g);
+    else hipLaunchKernelGGL(k_kin_grouped<false>, dim3(g.nitems), dim3(512), 0, s, g);
     return HROM_OK;
 }
 
