@@ -89,7 +89,7 @@ int build_groups(Plan& p) {
         cg.push_back(g);
         p.max_m = std::max(p.max_m, d.m);
         for (int64_t u = 0; u < (d.count + 31) / 32; u++) kin.push_back(WorkItem{c, (int)u});
-        for (int64_t u = 0; u < (d.count + 15) / 16; u++) bw.push_back(WorkItem{c, (int)u});
+        for (int64_t u = 0; u < (d.count + 31) / 32; u++) bw.push_back(WorkItem{c, (int)u});
         for (int64_t u = 0; u < (d.count + 3) / 4; u++) tan.push_back(WorkItem{c, (int)u});
     }
     // most expensive tiles first: kinematics ~ m Q, tangent ~ MT^2 Q

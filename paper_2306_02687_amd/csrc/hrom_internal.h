@@ -89,7 +89,7 @@ struct Plan {
     int persistent_grid = 512;
     ClusterGPU* cls_dev = nullptr;
     WorkItem* items_kin = nullptr;   // 32-point tiles (kinematics), decreasing cost
-    WorkItem* items_bw = nullptr;    // 16-point tiles (adjoint), decreasing cost
+    WorkItem* items_bw = nullptr;    // 32-point tiles (adjoint), decreasing cost
     WorkItem* items_tan = nullptr;   // 4-point tiles, decreasing cost
     int n_kin = 0, n_bw = 0, n_tan = 0;
     int* counter = nullptr;
@@ -277,7 +277,7 @@ struct ClusterGPU {
 
 struct WorkItem {
     int c;      // cluster
-    int unit;   // tile of the cluster (32 points for the kinematics, 16 for the
+    int unit;   // tile of the cluster (32 points for the kinematics and the
                 // adjoint, 4 for the tangent contraction)
 };
 

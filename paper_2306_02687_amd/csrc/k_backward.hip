@@ -38,24 +38,28 @@ __device__ __forceinline__ void nh_apply(const T* Fi, T mu, T la, T ell, const T
 
 
 
-// Point-batched form of the adjoint re-evaluation: sixteen macro points per
-// workgroup; F_q - Fr = G a and G lambda are two GEMMs with the cluster's G
-// as the shared operand (FP64 MFMA, N = the 16 points); the law and its
-// adjoint run one (point, ECM point) pair per thread; the refinement
-// residual rho = G^T (w A v) is a third FP64 GEMM.  Per-point sums over the
-// ECM points (h_r, dL/dtheta) reduce in a fixed order.
+// Point-batched form of the adjoint re-evaluation: 32 macro points per
+// workgroup of eight wavefronts; F_q - Fr = G a and G lambda are GEMMs with the
+// cluster's G as the shared operand (FP64 MFMA, two 16-point column tiles),
+// wave w taking row tile w of the round's 144 rows (ECM point, component) and
+// waves 0..3 one of the four products (F or G lambda, column tile) of tile 8;
+// the law and its adjoint run one (point, ECM point) pair per thread; the
+// refinement residual rho = G^T (w A v) is a third FP64 GEMM.  Per-point sums
+// over the ECM points (h_r, dL/dtheta) reduce in a fixed order.
+constexpr int kBwPT = 32, kBwThreads = 512;
 struct BwLds {
-    double sA[kMaxModes + 4][16];
-    double sL[kMaxModes + 4][16];
-    double sF[16 * 9][17];
-    double sV[16 * 9][17];
-    double sU[9][16];
-    double sG[9][16];
-    int sbits[16];
+    double sA[kMaxModes + 4][kBwPT];
+    double sL[kMaxModes + 4][kBwPT];
+    double sF[16 * 9][kBwPT + 1];
+    double sV[16 * 9][kBwPT + 1];
+    double sU[9][kBwPT];
+    double sG[9][kBwPT];
+    int sbits[kBwPT];
 };
 
+template <int MA, bool MIXED, bool RHO>
 __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
-    constexpr int PT = 16, QC = 16;
+    constexpr int PT = kBwPT, QC = 16, NT = kBwThreads;
     auto& sA = Ls.sA;
     auto& sL = Ls.sL;
     auto& sF = Ls.sF;
@@ -65,16 +69,16 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
     auto& sbits = Ls.sbits;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, c = lane & 15;
-    const int m = A.m, KS = A.KS, MP = A.MP, MT = A.MT;
+    const int m = A.m, KS = A.KS, MP = A.MP;
     const int np = (int)min((int64_t)PT, A.count - p0);
     if (tid < PT) sbits[tid] = 0;
-    for (int e = tid; e < 4 * KS * PT; e += 256) {
+    for (int e = tid; e < 4 * KS * PT; e += NT) {
         const int k = e / PT, p = e % PT;
         const bool in = (k < m && p < np);
         sA[k][p] = in ? A.a[(int64_t)k * A.count + p0 + p] : 0.0;
         sL[k][p] = in ? A.lam[(int64_t)k * A.count + p0 + p] : 0.0;
     }
-    for (int e = tid; e < 9 * PT; e += 256) {
+    for (int e = tid; e < 9 * PT; e += NT) {
         const int I = e / PT, p = e % PT;
         const int64_t b = A.first + p0 + p;
         sU[I][p] = (p < np) ? A.Fr[(int64_t)I * A.N + b] : ((I % 4 == 0) ? 1.0 : 0.0);
@@ -86,40 +90,54 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
     for (int I = 0; I < 9; I++) h[I] = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; i++) gt[i] = 0.0;
-    v4d racc[8];
+    v4d racc[RHO ? MA : 1][2];
 #pragma unroll
-    for (int t = 0; t < 8; t++) racc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < (RHO ? MA : 1); t++) racc[t][0] = racc[t][1] = v4d{0.0, 0.0, 0.0, 0.0};
     __syncthreads();
 
     for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
-        double gr[9][8];
-        if (A.with_rho) {
-            const double* gh = A.Ghat + (int64_t)(q0 * 9 + 36 * wave + g) * MP + c;
-#pragma unroll
-            for (int j = 0; j < 9; j++)
-#pragma unroll
-                for (int t = 0; t < 8; t++)
-                    if (t < MT) gr[j][t] = gh[(int64_t)(4 * j) * MP + 16 * t];
-        }
         const int rt0 = (q0 / 16) * 9;
-        for (int t = wave; t < 9; t += 4) {
-            const double* gf = A.Gf + ((int64_t)(rt0 + t) * KS) * 64 + lane;
-            double af[24];
+        {
+            const double* gf = A.Gf + ((int64_t)(rt0 + wave) * KS) * 64 + lane;
+            double af[4 * MA];
 #pragma unroll
-            for (int s2 = 0; s2 < 24; s2++)
+            for (int s2 = 0; s2 < 4 * MA; s2++)
                 if (s2 < KS) af[s2] = gf[(int64_t)s2 * 64];
-            v4d accF = v4d{0.0, 0.0, 0.0, 0.0}, accL = v4d{0.0, 0.0, 0.0, 0.0};
+            v4d f0 = v4d{0.0, 0.0, 0.0, 0.0}, f1 = f0, l0 = f0, l1 = f0;
 #pragma unroll
-            for (int s2 = 0; s2 < 24; s2++)
+            for (int s2 = 0; s2 < 4 * MA; s2++)
                 if (s2 < KS) {
-                    accF = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][c], accF, 0, 0, 0);
-                    accL = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sL[4 * s2 + g][c], accL, 0, 0, 0);
+                    f0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][c], f0, 0, 0, 0);
+                    f1 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][16 + c], f1, 0, 0, 0);
+                    l0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sL[4 * s2 + g][c], l0, 0, 0, 0);
+                    l1 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sL[4 * s2 + g][16 + c], l1, 0, 0, 0);
                 }
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const int row = 16 * t + g + 4 * e;
-                sF[row][c] = accF[e] + sU[row % 9][c];
-                sV[row][c] = sG[row % 9][c] - accL[e];
+                const int row = 16 * wave + g + 4 * e;   // FP64 MFMA accumulator rows interleave
+                sF[row][c] = f0[e] + sU[row % 9][c];
+                sF[row][16 + c] = f1[e] + sU[row % 9][16 + c];
+                sV[row][c] = sG[row % 9][c] - l0[e];
+                sV[row][16 + c] = sG[row % 9][16 + c] - l1[e];
+            }
+        }
+        if (wave < 4) {
+            // row tile 8: wave 0 / 1 the F columns 0..15 / 16..31, wave 2 / 3 G lambda
+            const double* gf = A.Gf + ((int64_t)(rt0 + 8) * KS) * 64 + lane;
+            const int col = 16 * (wave & 1) + c;
+            const bool isF = wave < 2;
+            v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s2 = 0; s2 < 4 * MA; s2++)
+                if (s2 < KS)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(gf[(int64_t)s2 * 64],
+                                                               isF ? sA[4 * s2 + g][col] : sL[4 * s2 + g][col],
+                                                               acc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int row = 128 + g + 4 * e;
+                if (isF) sF[row][col] = acc[e] + sU[row % 9][col];
+                else sV[row][col] = sG[row % 9][col] - acc[e];
             }
         }
         __syncthreads();
@@ -156,7 +174,7 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
             if (live && !(J > 0.0)) atomicOr(&sbits[p], HROM_PT_JNONPOS);
             const double ell = ok ? log(J) : 0.0;
             double Av[9];
-            if (A.mixed) {
+            if constexpr (MIXED) {
                 float Fif[9], vf[9], Avf[9];
 #pragma unroll
                 for (int k = 0; k < 9; k++) {
@@ -185,22 +203,26 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
             gt[1] = fma(wm, dla, gt[1]);
             gt[2] = fma(wi, dmu, gt[2]);
             gt[3] = fma(wi, dla, gt[3]);
-            if (A.with_rho) {
+            if constexpr (RHO) {
 #pragma unroll
                 for (int I = 0; I < 9; I++) sV[qq * 9 + I][p] = wo * Av[I];
             }
         }
         __syncthreads();
-        if (A.with_rho) {
+        if constexpr (RHO) {
+            // the round's 36 k-steps split over the eight waves
+            for (int j = (wave * 36) >> 3; j < ((wave + 1) * 36) >> 3; j++) {
+                const double b0 = sV[4 * j + g][c], b1 = sV[4 * j + g][16 + c];
+                const double* gh = A.Ghat + (int64_t)(q0 * 9 + 4 * j + g) * MP + c;
 #pragma unroll
-            for (int j = 0; j < 9; j++) {
-                const double bv = sV[36 * wave + 4 * j + g][c];
-#pragma unroll
-                for (int t = 0; t < 8; t++)
-                    if (t < MT) racc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gr[j][t], bv, racc[t], 0, 0, 0);
+                for (int t = 0; t < MA; t++) {
+                    const double av = gh[16 * t];
+                    racc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, racc[t][0], 0, 0, 0);
+                    racc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, racc[t][1], 0, 0, 0);
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
     // per-point sums over the 16 threads of the point (lanes 16p' .. 16p'+15
     // of a wave hold point p = tid >> 4): fixed butterfly within 16 lanes
@@ -227,27 +249,25 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
             if (sub >= 9 && sub < 13) A.gth[(int64_t)(sub - 9) * A.N + b] = failed ? 0.0 : u;
         }
     }
-    if (A.with_rho) {
+    if constexpr (RHO) {
+        // fixed-order sum of the eight waves' partial rho through LDS (sF reused)
         double* red = &sF[0][0];
 #pragma unroll
-        for (int t = 0; t < 8; t++) {
-            if (t >= MT) break;
+        for (int t = 0; t < MA; t++) {
             __syncthreads();
 #pragma unroll
-            for (int e = 0; e < 4; e++) red[(wave * 16 + g + 4 * e) * 16 + c] = racc[t][e];
+            for (int e = 0; e < 4; e++) {
+                red[(wave * 16 + g + 4 * e) * PT + c] = racc[t][0][e];
+                red[(wave * 16 + g + 4 * e) * PT + 16 + c] = racc[t][1][e];
+            }
             __syncthreads();
-            if (wave == 0) {
+            if (tid < 16 * PT) {
+                const int rr = tid >> 5, p = tid & 31;
+                double v = 0.0;
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int rr = g + 4 * e;
-                    const double v = ((red[(0 * 16 + rr) * 16 + c] + red[(1 * 16 + rr) * 16 + c]) +
-                                      red[(2 * 16 + rr) * 16 + c]) + red[(3 * 16 + rr) * 16 + c];
-                    const int row = 16 * t + rr;
-                    if (c < np && row < m) {
-                        const bool failed = sbits[c] != 0;
-                        A.rho[(int64_t)row * A.count + p0 + c] = failed ? 0.0 : v;
-                    }
-                }
+                for (int w = 0; w < 8; w++) v += red[(w * 16 + rr) * PT + p];
+                const int row = 16 * t + rr;
+                if (p < np && row < m) A.rho[(int64_t)row * A.count + p0 + p] = sbits[p] ? 0.0 : v;
             }
         }
     }
@@ -255,13 +275,27 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
     if (tid < np && sbits[tid]) A.status[A.first + p0 + tid] |= HROM_PT_JNONPOS;
 }
 
-__global__ void __launch_bounds__(256) k_backward_b(BackwardArgs A) {
-    __shared__ BwLds Ls;
-    bw_body(A, (int64_t)blockIdx.x * 16, Ls);
+template <bool MIXED, bool RHO>
+__device__ void bw_dispatch(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
+    switch ((A.m + 15) / 16) {
+        case 1: bw_body<1, MIXED, RHO>(A, p0, Ls); break;
+        case 2: bw_body<2, MIXED, RHO>(A, p0, Ls); break;
+        case 3: bw_body<3, MIXED, RHO>(A, p0, Ls); break;
+        case 4: bw_body<4, MIXED, RHO>(A, p0, Ls); break;
+        case 5: bw_body<5, MIXED, RHO>(A, p0, Ls); break;
+        default: bw_body<6, MIXED, RHO>(A, p0, Ls); break;
+    }
 }
 
-// adjoint re-evaluation of every cluster in one launch (16-point tiles)
-__global__ void __launch_bounds__(256) k_backward_grouped(GroupCall G) {
+template <int MA, bool MIXED, bool RHO>
+__global__ void __launch_bounds__(kBwThreads) k_backward_b(BackwardArgs A) {
+    __shared__ BwLds Ls;
+    bw_body<MA, MIXED, RHO>(A, (int64_t)blockIdx.x * kBwPT, Ls);
+}
+
+// adjoint re-evaluation of every cluster in one launch (32-point tiles)
+template <bool MIXED, bool RHO>
+__global__ void __launch_bounds__(kBwThreads) k_backward_grouped(GroupCall G) {
     __shared__ BwLds Ls;
     const WorkItem w = G.items[blockIdx.x];
     const ClusterGPU& C = G.cls[w.c];
@@ -272,18 +306,38 @@ __global__ void __launch_bounds__(256) k_backward_grouped(GroupCall G) {
     A.w = C.w; A.phase = C.phase; A.theta = G.theta; A.Fr = G.Fr; A.a = G.a + C.off_a;
     A.lam = G.lam + C.off_a; A.gr = G.gr; A.hr = G.hr; A.gth = G.gth;
     A.rho = G.rho ? G.rho + C.off_a : nullptr; A.status = G.status;
-    bw_body(A, (int64_t)w.unit * 16, Ls);
+    bw_dispatch<MIXED, RHO>(A, (int64_t)w.unit * kBwPT, Ls);
 }
 
 int launch_backward_grouped(const GroupCall& g, hipStream_t s) {
-    hipLaunchKernelGGL(k_backward_grouped, dim3(g.nitems), dim3(256), 0, s, g);
+    const dim3 grid(g.nitems), block(kBwThreads);
+    if (g.mixed && g.with_rho) hipLaunchKernelGGL((k_backward_grouped<true, true>), grid, block, 0, s, g);
+    else if (g.mixed) hipLaunchKernelGGL((k_backward_grouped<true, false>), grid, block, 0, s, g);
+    else if (g.with_rho) hipLaunchKernelGGL((k_backward_grouped<false, true>), grid, block, 0, s, g);
+    else hipLaunchKernelGGL((k_backward_grouped<false, false>), grid, block, 0, s, g);
+    return HROM_OK;
+}
+
+template <bool MIXED, bool RHO>
+static int launch_bw_t(const BackwardArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)((a.count + kBwPT - 1) / kBwPT)), block(kBwThreads);
+    switch ((a.m + 15) / 16) {
+        case 1: hipLaunchKernelGGL((k_backward_b<1, MIXED, RHO>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_backward_b<2, MIXED, RHO>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_backward_b<3, MIXED, RHO>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_backward_b<4, MIXED, RHO>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_backward_b<5, MIXED, RHO>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_backward_b<6, MIXED, RHO>), grid, block, 0, s, a); break;
+        default: return HROM_E_UNSUPPORTED;
+    }
     return HROM_OK;
 }
 
 int launch_backward_b(const BackwardArgs& a, hipStream_t s) {
-    if (a.MT > 8) return HROM_E_UNSUPPORTED;
-    hipLaunchKernelGGL(k_backward_b, dim3((unsigned)((a.count + 15) / 16)), dim3(256), 0, s, a);
-    return HROM_OK;
+    if (a.mixed && a.with_rho) return launch_bw_t<true, true>(a, s);
+    if (a.mixed) return launch_bw_t<true, false>(a, s);
+    if (a.with_rho) return launch_bw_t<false, true>(a, s);
+    return launch_bw_t<false, false>(a, s);
 }
 
 }  // namespace hrom
