@@ -146,8 +146,9 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
                   double* gFbar, double* gtheta, int32_t* status, hipStream_t stream);
 
 /* Launch variants of the tangent contraction, chosen by the autotuner.
- * Single-cluster plans: bit 0 asks for one wavefront per SIMD instead of two
- * (mixed kernels), bit 1 turns off the double-buffered Ghat loads.  Plans with
+ * Single-cluster plans: bit 0 asks for three wavefronts per SIMD instead of
+ * two (mixed kernels), bit 1 turns off the prefetch of the next ECM point's
+ * mode-gradient operands.  Plans with
  * several clusters: the persistent launch uses (variant + 1) x #CUs
  * workgroups.  c = -1 applies to every cluster.  Results do not depend on the
  * variant (same arithmetic, same order). */

@@ -494,6 +494,10 @@ struct Pk<HROM_MIXED_FP16> {
 // Record per point: Kaa upper tiles [MA(MA+1)/2][256], KaF tiles [MA][256]
 // (row = mode, column = accumulator row of the component), KFF tile [256].
 constexpr int kCQ = 16;   // ECM points per LDS round
+// LDS records of one round: per ECM point the 36 records (component K, lane
+// group g) at 4 K + g, then one zero record read by the lanes that carry no
+// tensor row
+constexpr int kWR = 37;
 
 __device__ __forceinline__ int comp_pos(int K) { return K < 6 ? 4 * (K >> 1) + (K & 1) : 6 + K; }
 __device__ __forceinline__ int pos_comp(int r) {
@@ -532,7 +536,7 @@ __device__ __forceinline__ v4u32 t_operand(v4f T) {
 }
 
 template <int MA, int PREC, bool SPLIT, bool PF>
-__device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ * 64]) {
+__device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ * kWR]) {
     constexpr int NA = MA * (MA + 1) / 2;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
@@ -542,8 +546,9 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
     v4u32* sw = s_w[wave];
     const float* qsp = (const float*)A.qs + (pl * A.Qpad) * 12;
     const v4u32* fp = (const v4u32*)A.Fpk + lane;
-    // records of lanes that carry no tensor row stay zero
-    for (int i = lane; i < kCQ * 64; i += 64) sw[i] = v4u32{0u, 0u, 0u, 0u};
+    // the zero record of every ECM point slot
+    if (lane < kCQ) sw[lane * kWR + 36] = v4u32{0u, 0u, 0u, 0u};
+    const int wrec = (pos_comp(c) >= 0) ? 4 * pos_comp(c) + g : 36;   // this lane's record
     // identity fragment: G[J][column c] = 1 for J = component of accumulator row c
     v4u32 Ip;
     {
@@ -603,17 +608,17 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
                         w[3 * k + l] = fmaf(col[l], row[k], fmaf(sji, F[3 * l + k], ei[k] * ej[l]));
                 v4u32 rec[4];
                 w_records<PREC, SPLIT>(w, rec);
-                v4u32* dst = sw + qq * 64 + comp_pos(KI);
+                v4u32* dst = sw + qq * kWR + 4 * KI;
 #pragma unroll
-                for (int gg = 0; gg < 4; gg++) dst[16 * gg] = rec[gg];
+                for (int gg = 0; gg < 4; gg++) dst[gg] = rec[gg];
             }
         }
         // ---- contraction over the round (LDS traffic of one wavefront is in order)
-        v4u32 Wq = sw[lane];
+        v4u32 Wq = sw[wrec];
 #pragma unroll 2
         for (int qi = 0; qi < kCQ; qi++) {
             const int q = q0 + qi;
-            const v4u32 Wn = sw[(qi + 1 < kCQ ? qi + 1 : qi) * 64 + lane];
+            const v4u32 Wn = sw[(qi + 1 < kCQ ? qi + 1 : qi) * kWR + wrec];
             v4u32 Gn[MA];
             if (PF) {
                 const int qn = (q + 1 < A.Qpad) ? q + 1 : q;
@@ -672,23 +677,23 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
     *(v4f*)(kh + (NA + MA) * 256) = accFF;
 }
 
-// OCC2: ask for two wavefronts per SIMD (register cap 256)
-template <int MA, int PREC, bool SPLIT, bool PF, bool OCC2>
-__global__ void __launch_bounds__(256, (OCC2 && MA <= 4) ? 2 : 1) k_eval_mixed(EvalArgs A) {
-    __shared__ v4u32 s_w[4][kCQ * 64];
+// OCC3: ask for three wavefronts per SIMD (register cap 168) instead of two
+template <int MA, int PREC, bool SPLIT, bool PF, bool OCC3>
+__global__ void __launch_bounds__(256, (OCC3 && MA <= 4) ? 3 : 2) k_eval_mixed(EvalArgs A) {
+    __shared__ v4u32 s_w[4][kCQ * kWR];
     tan_mixed_body<MA, PREC, SPLIT, PF>(A, (int64_t)blockIdx.x * 4, s_w);
 }
 
-template <int PREC, bool SPLIT, bool PF, bool OCC2>
+template <int PREC, bool SPLIT, bool PF, bool OCC3>
 static int launch_mixed_t(const EvalArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(a.count, 4)), block(256);
     switch ((a.m + 15) / 16) {
-        case 1: hipLaunchKernelGGL((k_eval_mixed<1, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_eval_mixed<2, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_eval_mixed<3, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_eval_mixed<4, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_eval_mixed<5, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_eval_mixed<6, PREC, SPLIT, PF, OCC2>), grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_eval_mixed<1, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_eval_mixed<2, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_eval_mixed<3, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_eval_mixed<4, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_eval_mixed<5, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_eval_mixed<6, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
         default: return HROM_E_UNSUPPORTED;
     }
     return HROM_OK;
@@ -697,14 +702,14 @@ static int launch_mixed_t(const EvalArgs& a, hipStream_t s) {
 template <int PREC, bool SPLIT>
 static int launch_mixed_v(int variant, const EvalArgs& a, hipStream_t s) {
     switch (variant & 3) {
-        case 0: return launch_mixed_t<PREC, SPLIT, true, true>(a, s);
-        case 1: return launch_mixed_t<PREC, SPLIT, true, false>(a, s);
-        case 2: return launch_mixed_t<PREC, SPLIT, false, true>(a, s);
-        default: return launch_mixed_t<PREC, SPLIT, false, false>(a, s);
+        case 0: return launch_mixed_t<PREC, SPLIT, true, false>(a, s);
+        case 1: return launch_mixed_t<PREC, SPLIT, true, true>(a, s);
+        case 2: return launch_mixed_t<PREC, SPLIT, false, false>(a, s);
+        default: return launch_mixed_t<PREC, SPLIT, false, true>(a, s);
     }
 }
 
-// variant bit 0: one wavefront per SIMD instead of two; bit 1: no prefetch
+// variant bit 0: three wavefronts per SIMD instead of two; bit 1: no prefetch
 int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s) {
     (void)MT;
     if (prec == HROM_MIXED_BF16)
@@ -775,7 +780,7 @@ __global__ void __launch_bounds__(256, 1) k_tan_persistent(GroupCall G) {
                 default: tan_f64_body<7>(A, pl0, s_st); break;
             }
         } else {
-            __shared__ v4u32 s_w[4][kCQ * 64];
+            __shared__ v4u32 s_w[4][kCQ * kWR];
             const EvalArgs A = group_eval_args(G, w.c, sizeof(float));
             switch ((A.m + 15) / 16) {
                 case 1: tan_mixed_body<1, PREC, SPLIT, true>(A, pl0, s_w); break;
