@@ -193,7 +193,7 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
         off_a += (int64_t)k.m * k.count;
         off_kaa += (int64_t)k.m * k.m * k.count;
         off_kaf += (int64_t)9 * k.m * k.count;
-        ws_k += (int64_t)khat_tiles(d.m, d.MT, precision != HROM_FP64) * 256 * k.count;
+        ws_k += khat_len(d.m, d.MT, precision != HROM_FP64) * k.count;
         ws_L += (int64_t)k.m * k.m * k.count;
         ws_q += (int64_t)12 * d.Qpad * k.count;
         rc = dalloc(&d.Ghat, (int64_t)d.Qpad * 9 * d.MP);

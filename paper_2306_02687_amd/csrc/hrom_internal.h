@@ -12,15 +12,17 @@ namespace hrom {
 
 constexpr int kMaxModes = 96;   // m <= 96
 
-// Per-point K-hat record, in tiles of 256 entries (one 16 x 16 MFMA
-// accumulator tile each).  FP64 path: the upper tiles of the augmented
-// contraction over Ghat = [G | I_9 | 0], MT (MT + 1) / 2 tiles.  Mixed path:
-// the upper Kaa tiles over the MA = ceil(m / 16) mode tiles, then MA tiles of
-// KaF^T, then one tile of KFF.
-__host__ __device__ inline int khat_tiles(int m, int MT, bool mixed) {
-    if (!mixed) return MT * (MT + 1) / 2;
-    const int MA = (m + 15) / 16;
-    return MA * (MA + 1) / 2 + MA + 1;
+// Per-point K-hat record.  FP64 path: the upper 16 x 16 accumulator tiles of
+// the augmented contraction over Ghat = [G | I_9 | 0], MT (MT + 1) / 2 tiles of
+// 256 entries.  Mixed path: the symmetric matrix [[Kaa, KaF], [KaF^T, KFF]] in
+// the order the condensation reads it: indices 0..m-1 modes, 9 macro
+// components at mp = 8 ceil(m / 8), lower 8 x 8 blocks (t >= u) in the order
+// t (t + 1) / 2 + u, block entry (r, c) at 8 r + c; entries outside the modes
+// and the macro components are not written.
+__host__ __device__ inline int64_t khat_len(int m, int MT, bool mixed) {
+    if (!mixed) return (int64_t)(MT * (MT + 1) / 2) * 256;
+    const int MB = (m + 7) / 8 + 2;
+    return (int64_t)(MB * (MB + 1) / 2) * 64;
 }
 constexpr int kMaxTiles = 7;    // ceil((96 + 10) / 16)
 constexpr int kQChunk = 64;     // ECM points per phase-A chunk (one per lane)

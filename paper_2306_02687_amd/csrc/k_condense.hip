@@ -54,25 +54,14 @@ __device__ __forceinline__ double khat_at<double>(const double* kh, int m, int M
     return kh[(int64_t)idx * 256 + (cl + 16 * (rw & 3)) * 4 + (rw >> 2)];
 }
 
-// accumulator row of tensor component K in the mixed-path tiles
-__device__ __forceinline__ int comp_row(int K) { return K < 6 ? 4 * (K >> 1) + (K & 1) : 6 + K; }
-
 template <>
 __device__ __forceinline__ double khat_at<float>(const float* kh, int m, int MT, int xi, int xk) {
     (void)MT;
-    const int MA = (m + 15) / 16, NA = MA * (MA + 1) / 2;
-    const int lo = xi < xk ? xi : xk, hi = xi < xk ? xk : xi;
-    if (hi < m) {            // Kaa, accumulator rows 4g + e
-        const int ti = lo >> 4, tj = hi >> 4, rw = lo & 15, cl = hi & 15;
-        const int idx = ti * MA - ti * (ti - 1) / 2 + (tj - ti);
-        return (double)kh[(int64_t)idx * 256 + (cl + 16 * (rw >> 2)) * 4 + (rw & 3)];
-    }
-    if (lo < m) {            // KaF: row = mode lo, column = accumulator row of the component
-        const int rw = lo & 15;
-        return (double)kh[(int64_t)(NA + (lo >> 4)) * 256 + (comp_row(hi - m) + 16 * (rw >> 2)) * 4 + (rw & 3)];
-    }
-    const int ri = comp_row(lo - m), cj = comp_row(hi - m);   // KFF
-    return (double)kh[(int64_t)(NA + MA) * 256 + (cj + 16 * (ri >> 2)) * 4 + (ri & 3)];
+    const int mp = 8 * ((m + 7) / 8);
+    const int ci = xi < m ? xi : mp + (xi - m), ck = xk < m ? xk : mp + (xk - m);
+    const int r = ci > ck ? ci : ck, c = ci > ck ? ck : ci;
+    const int t = r >> 3, u = c >> 3;
+    return (double)kh[(int64_t)(t * (t + 1) / 2 + u) * 64 + 8 * (r & 7) + (c & 7)];
 }
 
 template <typename TT>
@@ -100,7 +89,7 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int mode
     if (mode == 2 && !(A.status[b] & HROM_PT_NOT_SPD)) return;
     const int do_condense = mode;
     CondLds S(sm, m);
-    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_tiles(m, A.MT, sizeof(TT) == 4) * 256;
+    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_len(m, A.MT, sizeof(TT) == 4);
     unpack_tiles<TT>(A, kh, S, false);
     for (int i = lane; i < m; i += 64) {
         const double ri = A.r[(int64_t)i * A.count + pl];
@@ -456,7 +445,7 @@ __device__ void condense_spd_body(const CondenseArgs& A, int64_t pl, double* sm)
     double* B = KFF + 81;                    // [m][10]
     double* Pr = B + 10 * m;                 // [9]
     double* rv = Pr + 9;                     // [m]
-    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_tiles(m, MT, sizeof(TT) == 4) * 256;
+    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_len(m, MT, sizeof(TT) == 4);
     const double ks = (double)A.kscale;
     for (int e = lane; e < m * (m + 1) / 2; e += 64) {
         // packed lower triangle: row R at offset R (R + 1) / 2
@@ -654,7 +643,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
     const int m = A.m, mp = 8 * JB, MT = A.MT;
     const int lane = threadIdx.x, lr = lane >> 3, lc = lane & 7;
     const int64_t b = A.first + pl;
-    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_tiles(m, MT, sizeof(TT) == 4) * 256;
+    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_len(m, MT, sizeof(TT) == 4);
     const double ks = (double)A.kscale;
     __shared__ double cb[8 * MB];            // column / row broadcast
     __shared__ double zb[16];                // right-hand sides of one row
@@ -673,7 +662,8 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
             const int xk = k < m ? k : (k < mp ? -1 : (k < mp + 9 ? m + k - mp : (k == mp + 9 ? -2 : -3)));
             double v = 0.0;
             if (xi >= 0 && xk >= 0) {
-                v = khat_at<TT>(kh, m, MT, xi, xk) * ks;
+                if constexpr (sizeof(TT) == 4) v = (double)kh[lblk(t, u) * 64 + lane] * ks;   // lane order
+                else v = khat_at<TT>(kh, m, MT, xi, xk) * ks;
             } else if (xi == -1 || xk == -1) {
                 v = (i == k) ? 1.0 : 0.0;
             } else if ((xi == -2) != (xk == -2) && xi != -3 && xk != -3) {
@@ -707,22 +697,20 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
                 break;
             }
             const double rd = 1.0 / d;
-            double ci[MB], ck[MB];
-#pragma unroll
-            for (int t = J; t < MB; t++) {
-                const double v = cb[8 * t + lr] * rd;
-                ci[t] = (t > J || lr > jj) ? v : 0.0;
-            }
+            double ck[MB];
 #pragma unroll
             for (int u = J; u < MB; u++) {
                 const double v = cb[8 * u + lc];
                 ck[u] = (u > J || lc > jj) ? v : 0.0;
             }
+#pragma unroll
+            for (int t = J; t < MB; t++) {
+                const double v = cb[8 * t + lr] * rd;
+                const double ci = (t > J || lr > jj) ? v : 0.0;
+#pragma unroll
+                for (int u = J; u <= t; u++) M[lblk(t, u)] = fma(-ci, ck[u], M[lblk(t, u)]);
+            }
             __syncthreads();
-#pragma unroll
-            for (int t = J; t < MB; t++)
-#pragma unroll
-                for (int u = J; u <= t; u++) M[lblk(t, u)] = fma(-ci[t], ck[u], M[lblk(t, u)]);
         }
         if (!spd) break;
     }
@@ -773,19 +761,17 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
             const double rdj = 1.0 / cb[j];
             const double x0 = zb[lr] * rdj;
             const double x1 = (lr < 2) ? zb[8 + lr] * rdj : 0.0;
-            double l[MB];
-#pragma unroll
-            for (int u = 0; u <= J; u++) l[u] = (u < J || lc < jj) ? cb[8 * u + lc] : 0.0;
-            __syncthreads();
             if (lc == jj) {
                 M[lblk(JB, J)] = x0;
                 M[lblk(JB + 1, J)] = x1;
             }
 #pragma unroll
             for (int u = 0; u <= J; u++) {
-                M[lblk(JB, u)] = fma(-l[u], x0, M[lblk(JB, u)]);
-                M[lblk(JB + 1, u)] = fma(-l[u], x1, M[lblk(JB + 1, u)]);
+                const double l = (u < J || lc < jj) ? cb[8 * u + lc] : 0.0;
+                M[lblk(JB, u)] = fma(-l, x0, M[lblk(JB, u)]);
+                M[lblk(JB + 1, u)] = fma(-l, x1, M[lblk(JB + 1, u)]);
             }
+            __syncthreads();
         }
     }
 
@@ -836,7 +822,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
 }
 
 template <typename TT, int MB>
-__global__ void __launch_bounds__(64, 2) k_condense_reg(CondenseArgs A) {
+__global__ void __launch_bounds__(64, 3) k_condense_reg(CondenseArgs A) {
     condense_reg_body<TT, MB>(A, xcd_order(blockIdx.x, A.count));
 }
 

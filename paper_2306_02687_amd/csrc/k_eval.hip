@@ -669,12 +669,43 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
             for (int tj = ti; tj < MA; tj++, idx++) acc[idx] = Pk<PREC>::mfma(Gp[ti], Bp[tj], acc[idx]);
     }
     if (!valid) return;
-    float* kh = (float*)A.Khat + (int64_t)pl * (NA + MA + 1) * 256 + lane * 4;
+    // record in the condensation's order: lower 8 x 8 blocks of the augmented
+    // matrix (modes, then the components at mp), entry (r, c) of block (t, u)
+    // at 64 (t (t + 1) / 2 + u) + 8 (r % 8) + c % 8; each symmetric pair comes
+    // from one accumulator entry (upper Kaa, the KaF tiles, KFF with I >= J)
+    const int m = A.m, mp = 8 * ((m + 7) / 8);
+    float* kh = (float*)A.Khat + (int64_t)pl * khat_len(m, 0, true);
+    auto put = [&](int r, int cc, float v) {   // r >= cc
+        const int t = r >> 3, u = cc >> 3;
+        float* blk = kh + (t * (t + 1) / 2 + u) * 64;
+        blk[8 * (r & 7) + (cc & 7)] = v;
+        if (t == u) blk[8 * (cc & 7) + (r & 7)] = v;
+    };
+    {
+        int idx = 0;
 #pragma unroll
-    for (int i = 0; i < NA; i++) *(v4f*)(kh + i * 256) = acc[i];
+        for (int ti = 0; ti < MA; ti++)
 #pragma unroll
-    for (int i = 0; i < MA; i++) *(v4f*)(kh + (NA + i) * 256) = accF[i];
-    *(v4f*)(kh + (NA + MA) * 256) = accFF;
+            for (int tj = ti; tj < MA; tj++, idx++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int R = 16 * ti + 4 * g + e, C = 16 * tj + c;
+                    if (R < m && C < m && R <= C) put(C, R, acc[idx][e]);
+                }
+    }
+    const int Kc = pos_comp(c);
+#pragma unroll
+    for (int t = 0; t < MA; t++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int k = 16 * t + 4 * g + e;
+            if (Kc >= 0 && k < m) put(mp + Kc, k, accF[t][e]);
+        }
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const int KI = pos_comp(4 * g + e);
+        if (KI >= 0 && Kc >= 0 && KI >= Kc) put(mp + KI, mp + Kc, accFF[e]);
+    }
 }
 
 // OCC3: ask for three wavefronts per SIMD (register cap 168) instead of two

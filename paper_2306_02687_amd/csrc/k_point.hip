@@ -87,85 +87,92 @@ __device__ __forceinline__ void load_polar(const double* polar, int64_t N, int64
 // Ubar S + S Ubar = 2 T, Pbar = Fbar S; tangent column k along E_k:
 // dU = Linv(E_k^T F + F^T E_k), dT = sym(Cr dU),
 // dS = Linv(2 dT - dU S - S dU), Cbar e_k = E_k S + F dS.
+// One thread per (column k, macro point), k-major so that every load and
+// store is coalesced over the points; the k = 0 thread also writes Pbar, S.
 __global__ void k_pushout(PushArgs A) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= A.N) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t N = A.N;
+    if (t >= 9 * N) return;
+    const int kc = (int)(t / N);
+    const int64_t b = t - (int64_t)kc * N;
     double Pa[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) Pa[k] = A.Palg[k * N + b];
-    int st = A.status[b];
+    bool fin = true;
     if (!A.objective) {
-        bool fin = true;
+        if (kc == 0) {
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
-            A.Pbar[k * N + b] = Pa[k];
-            fin = fin && isfinite(Pa[k]);
+            for (int k = 0; k < 9; k++) {
+                A.Pbar[k * N + b] = Pa[k];
+                fin = fin && isfinite(Pa[k]);
+            }
         }
-        for (int k = 0; k < 81; k++) {
-            const double v = A.Cr[k * N + b];
-            A.Cbar[k * N + b] = v;
+#pragma unroll
+        for (int I = 0; I < 9; I++) {
+            const double v = A.Cr[(9 * I + kc) * N + b];
+            A.Cbar[(9 * I + kc) * N + b] = v;
             fin = fin && isfinite(v);
         }
-        if (!fin) A.status[b] = st | HROM_PT_NONFINITE;
+        if (!fin) atomicOr(&A.status[b], HROM_PT_NONFINITE);
         return;
     }
     double F[9], V[9], u[3];
     load_polar(A.polar, N, b, F, V, u);
-    double T2[9], S[9], P[9];
+    double T2[9], S[9];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) T2[3 * i + j] = Pa[3 * i + j] + Pa[3 * j + i];
     lyap_solve(V, u, T2, S);
-    mul3(F, S, P);
-    bool fin = true;
+    if (kc == 0) {
+        double P[9];
+        mul3(F, S, P);
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
-        A.Pbar[k * N + b] = P[k];
-        A.S[k * N + b] = S[k];
-        fin = fin && isfinite(P[k]);
-    }
-    for (int kc = 0; kc < 9; kc++) {
-        const int ka = kc / 3, kb = kc % 3;   // E_k = e_ka (x) e_kb
-        double dC[9], dU[9];
-        // (E_k^T F)_ij = delta_{i kb} F_{ka j};  dC = E_k^T F + F^T E_k
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int j = 0; j < 3; j++)
-                dC[3 * i + j] = (i == kb ? F[3 * ka + j] : 0.0) + (j == kb ? F[3 * ka + i] : 0.0);
-        lyap_solve(V, u, dC, dU);
-        double dP[9];
-        for (int I = 0; I < 9; I++) {
-            double s = 0.0;
-#pragma unroll
-            for (int J = 0; J < 9; J++) s = fma(A.Cr[(9 * I + J) * N + b], dU[J], s);
-            dP[I] = s;
-        }
-        double B[9], t1[9], t2[9], dS[9], FdS[9];
-        mul3(dU, S, t1);
-        mul3(S, dU, t2);
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int j = 0; j < 3; j++)
-                B[3 * i + j] = (dP[3 * i + j] + dP[3 * j + i]) - t1[3 * i + j] - t2[3 * i + j];
-        lyap_solve(V, u, B, dS);
-        mul3(F, dS, FdS);
-#pragma unroll
-        for (int I = 0; I < 9; I++) {
-            const int i = I / 3, j = I % 3;
-            const double v = (i == ka ? S[3 * kb + j] : 0.0) + FdS[I];
-            A.Cbar[(9 * I + kc) * N + b] = v;
-            fin = fin && isfinite(v);
+        for (int k = 0; k < 9; k++) {
+            A.Pbar[k * N + b] = P[k];
+            A.S[k * N + b] = S[k];
+            fin = fin && isfinite(P[k]);
         }
     }
-    if (!fin) A.status[b] = st | HROM_PT_NONFINITE;
+    const int ka = kc / 3, kb = kc % 3;   // E_k = e_ka (x) e_kb
+    double dC[9], dU[9];
+    // (E_k^T F)_ij = delta_{i kb} F_{ka j};  dC = E_k^T F + F^T E_k
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            dC[3 * i + j] = (i == kb ? F[3 * ka + j] : 0.0) + (j == kb ? F[3 * ka + i] : 0.0);
+    lyap_solve(V, u, dC, dU);
+    double dP[9];
+#pragma unroll
+    for (int I = 0; I < 9; I++) {
+        double s = 0.0;
+#pragma unroll
+        for (int J = 0; J < 9; J++) s = fma(A.Cr[(9 * I + J) * N + b], dU[J], s);
+        dP[I] = s;
+    }
+    double B[9], t1[9], t2[9], dS[9], FdS[9];
+    mul3(dU, S, t1);
+    mul3(S, dU, t2);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            B[3 * i + j] = (dP[3 * i + j] + dP[3 * j + i]) - t1[3 * i + j] - t2[3 * i + j];
+    lyap_solve(V, u, B, dS);
+    mul3(F, dS, FdS);
+#pragma unroll
+    for (int I = 0; I < 9; I++) {
+        const int i = I / 3, j = I % 3;
+        const double v = (i == ka ? S[3 * kb + j] : 0.0) + FdS[I];
+        A.Cbar[(9 * I + kc) * N + b] = v;
+        fin = fin && isfinite(v);
+    }
+    if (!fin) atomicOr(&A.status[b], HROM_PT_NONFINITE);
 }
 
 void launch_pushout(const PushArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_pushout, dim3(nblocks(a.N, 128)), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(k_pushout, dim3(nblocks(9 * a.N, 256)), dim3(256), 0, s, a);
 }
 
 // ---------------------------------------------------------------- update
