@@ -155,6 +155,16 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
 int32_t hrom_num_variants(void);
 int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant);
 
+/* Measurement hook (not part of the method): with enable != 0 every later
+ * hrom_eval records two HIP events on its stream around the tangent
+ * contraction (the persistent launch of a grouped plan, the single tangent
+ * launch of a one-cluster plan).  hrom_plan_tangent_ms waits for the second
+ * event and returns the elapsed milliseconds of the last recorded launch;
+ * HROM_E_ORDER if profiling is off.  The events are created on the first
+ * enable and destroyed with the plan. */
+int hrom_plan_profile(hrom_plan plan, int32_t enable);
+int hrom_plan_tangent_ms(hrom_plan plan, float* ms);
+
 const char* hrom_strerror(int code);
 
 #ifdef __cplusplus

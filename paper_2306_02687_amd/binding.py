@@ -28,7 +28,8 @@ OFF_A, OFF_KAA, OFF_KAF = 0, 1, 2
 
 EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_eval",
             "hrom_condense", "hrom_update", "hrom_newton", "hrom_backward", "hrom_strerror",
-            "hrom_num_variants", "hrom_plan_set_variant")
+            "hrom_num_variants", "hrom_plan_set_variant", "hrom_plan_profile",
+            "hrom_plan_tangent_ms")
 
 
 class HromError(RuntimeError):
@@ -65,6 +66,8 @@ def load(path: str = LIB_PATH):
     L.hrom_num_variants.argtypes = []
     L.hrom_num_variants.restype = i32
     L.hrom_plan_set_variant.argtypes = [P, i32, i32]
+    L.hrom_plan_profile.argtypes = [P, i32]
+    L.hrom_plan_tangent_ms.argtypes = [P, C.POINTER(C.c_float)]
     L.hrom_strerror.argtypes = [C.c_int]
     L.hrom_strerror.restype = C.c_char_p
     _lib = L
@@ -172,6 +175,16 @@ class Plan:
     def set_variant(self, variant: int, cluster: int = -1):
         _check(load().hrom_plan_set_variant(self._h, int(cluster), int(variant)),
                "hrom_plan_set_variant")
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around the tangent contraction of every eval."""
+        _check(load().hrom_plan_profile(self._h, 1 if enable else 0), "hrom_plan_profile")
+
+    def tangent_ms(self) -> float:
+        """Duration of the last recorded tangent launch (waits for it)."""
+        v = C.c_float()
+        _check(load().hrom_plan_tangent_ms(self._h, C.byref(v)), "hrom_plan_tangent_ms")
+        return float(v.value)
 
     @staticmethod
     def num_variants() -> int:

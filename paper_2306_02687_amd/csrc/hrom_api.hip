@@ -280,9 +280,30 @@ int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant) {
 int hrom_plan_destroy(hrom_plan plan) {
     if (!plan) return HROM_E_INVALID;
     (void)hipDeviceSynchronize();
+    for (auto& e : plan->p.ev_tan)
+        if (e) (void)hipEventDestroy(e);
     free_plan(plan->p);
     delete plan;
     return HROM_OK;
+}
+
+int hrom_plan_profile(hrom_plan plan, int32_t enable) {
+    if (!plan) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    if (enable && !p.ev_tan[0]) {
+        if (hipEventCreate(&p.ev_tan[0]) != hipSuccess || hipEventCreate(&p.ev_tan[1]) != hipSuccess)
+            return HROM_E_HIP;
+    }
+    p.profile = enable != 0;
+    return HROM_OK;
+}
+
+int hrom_plan_tangent_ms(hrom_plan plan, float* ms) {
+    if (!plan || !ms) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    if (!p.profile) return HROM_E_ORDER;
+    if (hipEventSynchronize(p.ev_tan[1]) != hipSuccess) return HROM_E_HIP;
+    return hipEventElapsedTime(ms, p.ev_tan[0], p.ev_tan[1]) == hipSuccess ? HROM_OK : HROM_E_HIP;
 }
 
 int64_t hrom_plan_offset(hrom_plan plan, int32_t c, int32_t kind) {
@@ -314,8 +335,10 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         g.items = p.items_kin; g.nitems = p.n_kin;
         int rc = launch_kin_grouped(mixed(p) ? 1 : 0, g, stream);
         g.items = p.items_tan; g.nitems = p.n_tan;
+        if (p.profile) (void)hipEventRecord(p.ev_tan[0], stream);
         if (rc == HROM_OK)
             rc = launch_tan_persistent(p.prec, (p.flags & HROM_SPLIT) != 0, g, p.persistent_grid, stream);
+        if (p.profile) (void)hipEventRecord(p.ev_tan[1], stream);
         if (rc != HROM_OK) return rc;
     }
     for (const auto& c : p.cl) {
@@ -332,9 +355,12 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         e.status = status;
         e.wscale = wscale_for(c.Q);
         int rc = launch_kin(mixed(p) ? 1 : 0, e, stream);
+        // single-cluster plans: the events bracket the (only) tangent launch
+        if (p.profile && p.ncl == 1) (void)hipEventRecord(p.ev_tan[0], stream);
         if (rc == HROM_OK)
             rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, c.variant, e, stream)
                           : launch_eval_f64(c.MT, c.variant, e, stream);
+        if (p.profile && p.ncl == 1) (void)hipEventRecord(p.ev_tan[1], stream);
         if (rc != HROM_OK) return rc;
     }
     if (Kaa || KaF || KFF) {

@@ -59,6 +59,9 @@ struct Plan {
     int prec = HROM_FP64;
     unsigned flags = 0;
     int device = 0;
+    // optional HIP events around the tangent contraction of hrom_eval
+    bool profile = false;
+    hipEvent_t ev_tan[2] = {nullptr, nullptr};
     std::vector<ClusterDev> cl;
     int64_t a_len = 0, kaa_len = 0, kaf_len = 0, x_len = 0;
     // per-point workspace
