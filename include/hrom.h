@@ -146,9 +146,12 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
                   double* gFbar, double* gtheta, int32_t* status, hipStream_t stream);
 
 /* Launch variants of the tangent contraction, chosen by the autotuner.
- * Single-cluster plans: bit 0 asks for three wavefronts per SIMD instead of
- * two (mixed kernels), bit 1 turns off the prefetch of the next ECM point's
- * mode-gradient operands.  Plans with
+ * Single-cluster plans, variants 0..3: bit 0 asks for three wavefronts per
+ * SIMD instead of two (mixed kernels), bit 1 turns off the prefetch of the
+ * next ECM point's mode-gradient operands; variants 4 and 5 (mixed kernels,
+ * m <= 64; otherwise as variant 2 and 0) put two macro points on each
+ * wavefront, sharing every mode-gradient operand, without / with that
+ * prefetch (the FP64 kernel reads both as variant 0).  Plans with
  * several clusters: the persistent launch uses (variant + 1) x #CUs
  * workgroups.  c = -1 applies to every cluster.  Results do not depend on the
  * variant (same arithmetic, same order). */

@@ -258,10 +258,10 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
     return HROM_OK;
 }
 
-int32_t hrom_num_variants(void) { return 4; }
+int32_t hrom_num_variants(void) { return 6; }
 
 int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant) {
-    if (!plan || variant < 0 || variant >= 4 || c < -1 || c >= plan->p.ncl) return HROM_E_INVALID;
+    if (!plan || variant < 0 || variant >= hrom_num_variants() || c < -1 || c >= plan->p.ncl) return HROM_E_INVALID;
     Plan& p = plan->p;
     if (p.grouped) {
         // one persistent launch for every cluster: the variant picks its grid

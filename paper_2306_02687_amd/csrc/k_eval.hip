@@ -445,8 +445,9 @@ struct Pk<HROM_MIXED_BF16> {
         typedef float v2f __attribute__((ext_vector_type(2)));
         return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f{x0, x1}), v2bf));
     }
-    static __device__ __forceinline__ float lo(uint32_t h) { return __uint_as_float(h << 16); }
-    static __device__ __forceinline__ float hi(uint32_t h) { return __uint_as_float(h & 0xFFFF0000u); }
+    // x minus the value in the low / high half of h (exact in FP32)
+    static __device__ __forceinline__ float res_lo(uint32_t h, float x) { return x - __uint_as_float(h << 16); }
+    static __device__ __forceinline__ float res_hi(uint32_t h, float x) { return x - __uint_as_float(h & 0xFFFF0000u); }
     static constexpr uint32_t one = 0x3F80u;
     static __device__ __forceinline__ v4f mfma(v4u32 a, v4u32 b, v4f c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
@@ -461,11 +462,11 @@ struct Pk<HROM_MIXED_FP16> {
         typedef float v2f __attribute__((ext_vector_type(2)));
         return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f{x0, x1}), v2h));
     }
-    static __device__ __forceinline__ float lo(uint32_t h) {
-        return (float)__builtin_bit_cast(_Float16, (unsigned short)(h & 0xFFFFu));
+    static __device__ __forceinline__ float res_lo(uint32_t h, float x) {
+        return x - (float)__builtin_bit_cast(_Float16, (unsigned short)(h & 0xFFFFu));
     }
-    static __device__ __forceinline__ float hi(uint32_t h) {
-        return (float)__builtin_bit_cast(_Float16, (unsigned short)(h >> 16));
+    static __device__ __forceinline__ float res_hi(uint32_t h, float x) {
+        return x - (float)__builtin_bit_cast(_Float16, (unsigned short)(h >> 16));
     }
     static constexpr uint32_t one = 0x3C00u;
     static __device__ __forceinline__ v4f mfma(v4u32 a, v4u32 b, v4f c) {
@@ -513,10 +514,10 @@ __device__ __forceinline__ void w_records(const float* w, v4u32* rec) {
 #pragma unroll
     for (int p = 0; p < 4; p++) {
         h[p] = Pk<PREC>::pack(w[2 * p], w[2 * p + 1]);
-        l[p] = SPLIT ? Pk<PREC>::pack(w[2 * p] - Pk<PREC>::lo(h[p]), w[2 * p + 1] - Pk<PREC>::hi(h[p])) : 0u;
+        l[p] = SPLIT ? Pk<PREC>::pack(Pk<PREC>::res_lo(h[p], w[2 * p]), Pk<PREC>::res_hi(h[p], w[2 * p + 1])) : 0u;
     }
     h[4] = Pk<PREC>::pack(w[8], w[8]);
-    l[4] = SPLIT ? Pk<PREC>::pack(w[8] - Pk<PREC>::lo(h[4]), 0.f) : 0u;
+    l[4] = SPLIT ? Pk<PREC>::pack(Pk<PREC>::res_lo(h[4], w[8]), 0.f) : 0u;
     rec[0] = v4u32{h[0], h[0], l[0], 0u};
     rec[1] = v4u32{h[1], h[1], l[1], l[4]};
     rec[2] = v4u32{h[2], h[2], l[2], 0u};
@@ -527,24 +528,36 @@ __device__ __forceinline__ void w_records(const float* w, v4u32* rec) {
 template <int PREC, bool SPLIT>
 __device__ __forceinline__ v4u32 t_operand(v4f T) {
     const uint32_t hA = Pk<PREC>::pack(T[0], T[1]);
-    const uint32_t lA = SPLIT ? Pk<PREC>::pack(T[0] - Pk<PREC>::lo(hA), T[1] - Pk<PREC>::hi(hA)) : 0u;
+    const uint32_t lA = SPLIT ? Pk<PREC>::pack(Pk<PREC>::res_lo(hA, T[0]), Pk<PREC>::res_hi(hA, T[1])) : 0u;
     const uint32_t hB = Pk<PREC>::pack(T[2], T[2]);
-    const uint32_t lB = SPLIT ? Pk<PREC>::pack(T[2] - Pk<PREC>::lo(hB), 0.f) : 0u;
+    const uint32_t lB = SPLIT ? Pk<PREC>::pack(Pk<PREC>::res_lo(hB, T[2]), 0.f) : 0u;
     // lanes 0..31 take lB of lanes 32..63, lanes 32..63 keep hB
     const auto sw = __builtin_amdgcn_permlane32_swap(lB, hB, false, false);
     return v4u32{hA, hA, lA, (uint32_t)sw[1]};
 }
 
-template <int MA, int PREC, bool SPLIT, bool PF>
+// NP macro points per wavefront (1 or 2): with two, both points' products
+// take the same mode fragments, so each fragment is fetched once for two
+// points (half the fragment traffic through the CU's load path).
+template <int MA, int PREC, bool SPLIT, bool PF, int NP = 1>
 __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ * kWR]) {
     constexpr int NA = MA * (MA + 1) / 2;
+    constexpr int QR = kCQ / NP;   // ECM points per LDS round
+    static_assert(NP == 1 || NP == 2, "one or two points per wavefront");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
-    int64_t pl = pl0 + wave;
-    const bool valid = pl < A.count;
-    if (!valid) pl = A.count - 1;
+    int64_t pl[NP];
+    bool valid[NP];
+#pragma unroll
+    for (int pp = 0; pp < NP; pp++) {
+        pl[pp] = pl0 + NP * wave + pp;
+        valid[pp] = pl[pp] < A.count;
+        if (!valid[pp]) pl[pp] = A.count - 1;
+    }
     v4u32* sw = s_w[wave];
-    const float* qsp = (const float*)A.qs + (pl * A.Qpad) * 12;
+    // W builder of this lane: point pb, ECM point qq of the round, row set u
+    const int pb = (NP == 1) ? 0 : lane / (4 * QR), qq = (lane >> 2) & (QR - 1), u = lane & 3;
+    const float* qsp = (const float*)A.qs + ((pb == 0 ? pl[0] : pl[NP - 1]) * A.Qpad) * 12;
     const v4u32* fp = (const v4u32*)A.Fpk + lane;
     // the zero record of every ECM point slot
     if (lane < kCQ) sw[lane * kWR + 36] = v4u32{0u, 0u, 0u, 0u};
@@ -558,98 +571,112 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
         const uint32_t h8 = (K == 8) ? Pk<PREC>::one : 0u;
         Ip = v4u32{ha | (hb << 16), 0u, ha | (hb << 16), (g == 1 || g == 3) ? h8 : 0u};
     }
-    v4f acc[NA], accF[MA], accFF = v4f{0.f, 0.f, 0.f, 0.f};
+    v4f acc[NP][NA], accF[NP][MA], accFF[NP];
 #pragma unroll
-    for (int i = 0; i < NA; i++) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int pp = 0; pp < NP; pp++) {
+        accFF[pp] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < MA; i++) accF[i] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < NA; i++) acc[pp][i] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < MA; i++) accF[pp][i] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
 
     // Software pipeline over ECM points: iteration q issues the T, KaF and
     // KFF products of q, then the Kaa products of q - 1 (operands kept from the
     // previous iteration) interleaved with the hi/lo split of T(q), so the
     // matrix core and the VALU work side by side within one wavefront.
-    v4u32 Gp[MA], Bp[MA];      // previous ECM point: fragments and split T
+    v4u32 Gp[MA], Bp[NP][MA];  // previous ECM point: fragments and split T
 #pragma unroll
     for (int t = 0; t < MA; t++) {
         Gp[t] = v4u32{0u, 0u, 0u, 0u};
-        Bp[t] = v4u32{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int pp = 0; pp < NP; pp++) Bp[pp][t] = v4u32{0u, 0u, 0u, 0u};
     }
     v4u32 Gc[MA];
 #pragma unroll
     for (int t = 0; t < MA; t++) Gc[t] = fp[t * 64];
-    for (int q0 = 0; q0 < A.Qpad; q0 += kCQ) {
-        // ---- W rows of this round: lane (qq, u) builds rows u, u + 4, min(u + 8, 8)
-        // of W_{q0+qq} (row 8 is written by four lanes with identical values)
+    for (int q0 = 0; q0 < A.Qpad; q0 += QR) {
+        // ---- W rows of this round: lane (pb, qq, u < 3) builds the rows
+        // (i, j) = (u, 0..2) of W_{q0+qq} of point pb; the lanes u = 3 build none
         {
-            const int qq = lane >> 2, u = lane & 3;
             const v4f* src = (const v4f*)(qsp + (int64_t)(q0 + qq) * 12);
             const v4f x0 = src[0], x1 = src[1], x2 = src[2];
             const float F[9] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3], x2[0]};
             const float c0 = x2[1], c1 = x2[2], c2 = x2[3];
+            // W[(i,j)][(k,l)] = c1 F(l,i) F(j,k) + c2 F(j,i) F(l,k) + c0 [k = i][l = j]:
+            // with i the lane's own index only F(., i) and the diagonal term
+            // need a per-lane choice, once per round
+            float fc[3], col[3], d[3];
 #pragma unroll
-            for (int r = 0; r < 3; r++) {
-                const int KI = (u + 4 * r < 9) ? u + 4 * r : 8;
-                // W[(i,j)][(k,l)] = c1 F(l,i) F(j,k) + c2 F(j,i) F(l,k) + c0 [k = i][l = j]
-                const int i = KI / 3, j = KI - 3 * (KI / 3);
-                float col[3], row[3], ei[3], ej[3];
+            for (int t = 0; t < 3; t++) {
+                fc[t] = (u == 0) ? F[3 * t] : ((u == 1) ? F[3 * t + 1] : F[3 * t + 2]);   // F(t, i)
+                col[t] = c1 * fc[t];
+                d[t] = (t == u) ? c0 : 0.f;
+            }
 #pragma unroll
-                for (int t = 0; t < 3; t++) {
-                    col[t] = c1 * (i == 0 ? F[3 * t] : (i == 1 ? F[3 * t + 1] : F[3 * t + 2]));
-                    row[t] = (j == 0 ? F[t] : (j == 1 ? F[3 + t] : F[6 + t]));
-                    ei[t] = (t == i) ? c0 : 0.f;
-                    ej[t] = (t == j) ? 1.f : 0.f;
-                }
-                const float sji = c2 * (i == 0 ? row[0] : (i == 1 ? row[1] : row[2]));
+            for (int j = 0; j < 3; j++) {
+                const float sji = c2 * fc[j];
                 float w[9];
 #pragma unroll
                 for (int k = 0; k < 3; k++)
 #pragma unroll
                     for (int l = 0; l < 3; l++)
-                        w[3 * k + l] = fmaf(col[l], row[k], fmaf(sji, F[3 * l + k], ei[k] * ej[l]));
+                        w[3 * k + l] = fmaf(col[l], F[3 * j + k],
+                                            fmaf(sji, F[3 * l + k], (l == j) ? d[k] : 0.f));
                 v4u32 rec[4];
                 w_records<PREC, SPLIT>(w, rec);
-                v4u32* dst = sw + qq * kWR + 4 * KI;
+                if (u < 3) {
+                    v4u32* dst = sw + (pb * QR + qq) * kWR + 4 * (3 * u + j);
 #pragma unroll
-                for (int gg = 0; gg < 4; gg++) dst[gg] = rec[gg];
+                    for (int gg = 0; gg < 4; gg++) dst[gg] = rec[gg];
+                }
             }
         }
         // ---- contraction over the round (LDS traffic of one wavefront is in order)
-        v4u32 Wq = sw[wrec];
+        v4u32 Wq[NP];
+#pragma unroll
+        for (int pp = 0; pp < NP; pp++) Wq[pp] = sw[pp * QR * kWR + wrec];
 #pragma unroll 2
-        for (int qi = 0; qi < kCQ; qi++) {
+        for (int qi = 0; qi < QR; qi++) {
             const int q = q0 + qi;
-            const v4u32 Wn = sw[(qi + 1 < kCQ ? qi + 1 : qi) * kWR + wrec];
+            v4u32 Wn[NP];
+#pragma unroll
+            for (int pp = 0; pp < NP; pp++) Wn[pp] = sw[(pp * QR + (qi + 1 < QR ? qi + 1 : qi)) * kWR + wrec];
             v4u32 Gn[MA];
             if (PF) {
                 const int qn = (q + 1 < A.Qpad) ? q + 1 : q;
 #pragma unroll
                 for (int t = 0; t < MA; t++) Gn[t] = fp[((int64_t)qn * MA + t) * 64];
             }
-            v4f T[MA];
+            // point by point, so that one point's T is live at a time
 #pragma unroll
-            for (int t = 0; t < MA; t++) {
-                T[t] = Pk<PREC>::mfma(Wq, Gc[t], v4f{0.f, 0.f, 0.f, 0.f});
-                accF[t] = Pk<PREC>::mfma(Gc[t], Wq, accF[t]);
+            for (int pp = 0; pp < NP; pp++) {
+                v4f T[MA];
+#pragma unroll
+                for (int t = 0; t < MA; t++) {
+                    T[t] = Pk<PREC>::mfma(Wq[pp], Gc[t], v4f{0.f, 0.f, 0.f, 0.f});
+                    accF[pp][t] = Pk<PREC>::mfma(Gc[t], Wq[pp], accF[pp][t]);
+                }
+                accFF[pp] = Pk<PREC>::mfma(Wq[pp], Ip, accFF[pp]);
+                int idx = 0;
+#pragma unroll
+                for (int ti = 0; ti < MA; ti++)
+#pragma unroll
+                    for (int tj = ti; tj < MA; tj++, idx++)
+                        acc[pp][idx] = Pk<PREC>::mfma(Gp[ti], Bp[pp][tj], acc[pp][idx]);
+#pragma unroll
+                for (int t = 0; t < MA; t++) Bp[pp][t] = t_operand<PREC, SPLIT>(T[t]);
+                // issue order: the 2 MA + 1 products of q, then one Kaa product
+                // of q - 1 after every few VALU instructions of the split
+                __builtin_amdgcn_sched_group_barrier(0x008, 2 * MA + 1, 0);
+#pragma unroll
+                for (int i = 0; i < NA; i++) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, (13 * MA + NA - 1) / NA, 0);
+                }
             }
-            accFF = Pk<PREC>::mfma(Wq, Ip, accFF);
-            int idx = 0;
 #pragma unroll
-            for (int ti = 0; ti < MA; ti++)
-#pragma unroll
-                for (int tj = ti; tj < MA; tj++, idx++) acc[idx] = Pk<PREC>::mfma(Gp[ti], Bp[tj], acc[idx]);
-#pragma unroll
-            for (int t = 0; t < MA; t++) {
-                Bp[t] = t_operand<PREC, SPLIT>(T[t]);
-                Gp[t] = Gc[t];
-            }
-            // issue order: the 2 MA + 1 products of q, then one Kaa product of
-            // q - 1 after every few VALU instructions of the split
-            __builtin_amdgcn_sched_group_barrier(0x008, 2 * MA + 1, 0);
-#pragma unroll
-            for (int i = 0; i < NA; i++) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x002, (13 * MA + NA - 1) / NA, 0);
-            }
+            for (int t = 0; t < MA; t++) Gp[t] = Gc[t];
             if (PF) {
 #pragma unroll
                 for (int t = 0; t < MA; t++) Gc[t] = Gn[t];
@@ -658,7 +685,8 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
 #pragma unroll
                 for (int t = 0; t < MA; t++) Gc[t] = fp[((int64_t)qn * MA + t) * 64];
             }
-            Wq = Wn;
+#pragma unroll
+            for (int pp = 0; pp < NP; pp++) Wq[pp] = Wn[pp];
         }
     }
     {   // Kaa products of the last ECM point
@@ -666,22 +694,27 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
 #pragma unroll
         for (int ti = 0; ti < MA; ti++)
 #pragma unroll
-            for (int tj = ti; tj < MA; tj++, idx++) acc[idx] = Pk<PREC>::mfma(Gp[ti], Bp[tj], acc[idx]);
+            for (int tj = ti; tj < MA; tj++, idx++)
+#pragma unroll
+                for (int pp = 0; pp < NP; pp++)
+                    acc[pp][idx] = Pk<PREC>::mfma(Gp[ti], Bp[pp][tj], acc[pp][idx]);
     }
-    if (!valid) return;
     // record in the condensation's order: lower 8 x 8 blocks of the augmented
     // matrix (modes, then the components at mp), entry (r, c) of block (t, u)
     // at 64 (t (t + 1) / 2 + u) + 8 (r % 8) + c % 8; each symmetric pair comes
     // from one accumulator entry (upper Kaa, the KaF tiles, KFF with I >= J)
     const int m = A.m, mp = 8 * ((m + 7) / 8);
-    float* kh = (float*)A.Khat + (int64_t)pl * khat_len(m, 0, true);
-    auto put = [&](int r, int cc, float v) {   // r >= cc
-        const int t = r >> 3, u = cc >> 3;
-        float* blk = kh + (t * (t + 1) / 2 + u) * 64;
-        blk[8 * (r & 7) + (cc & 7)] = v;
-        if (t == u) blk[8 * (cc & 7) + (r & 7)] = v;
-    };
-    {
+    const int Kc = pos_comp(c);
+#pragma unroll
+    for (int pp = 0; pp < NP; pp++) {
+        if (!valid[pp]) continue;
+        float* kh = (float*)A.Khat + pl[pp] * khat_len(m, 0, true);
+        auto put = [&](int r, int cc, float v) {   // r >= cc
+            const int t = r >> 3, uu = cc >> 3;
+            float* blk = kh + (t * (t + 1) / 2 + uu) * 64;
+            blk[8 * (r & 7) + (cc & 7)] = v;
+            if (t == uu) blk[8 * (cc & 7) + (r & 7)] = v;
+        };
         int idx = 0;
 #pragma unroll
         for (int ti = 0; ti < MA; ti++)
@@ -690,41 +723,42 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
                     const int R = 16 * ti + 4 * g + e, C = 16 * tj + c;
-                    if (R < m && C < m && R <= C) put(C, R, acc[idx][e]);
+                    if (R < m && C < m && R <= C) put(C, R, acc[pp][idx][e]);
                 }
-    }
-    const int Kc = pos_comp(c);
 #pragma unroll
-    for (int t = 0; t < MA; t++)
+        for (int t = 0; t < MA; t++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int k = 16 * t + 4 * g + e;
+                if (Kc >= 0 && k < m) put(mp + Kc, k, accF[pp][t][e]);
+            }
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const int k = 16 * t + 4 * g + e;
-            if (Kc >= 0 && k < m) put(mp + Kc, k, accF[t][e]);
+            const int KI = pos_comp(4 * g + e);
+            if (KI >= 0 && Kc >= 0 && KI >= Kc) put(mp + KI, mp + Kc, accFF[pp][e]);
         }
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-        const int KI = pos_comp(4 * g + e);
-        if (KI >= 0 && Kc >= 0 && KI >= Kc) put(mp + KI, mp + Kc, accFF[e]);
     }
 }
 
-// OCC3: ask for three wavefronts per SIMD (register cap 168) instead of two
-template <int MA, int PREC, bool SPLIT, bool PF, bool OCC3>
-__global__ void __launch_bounds__(256, (OCC3 && MA <= 4) ? 3 : 2) k_eval_mixed(EvalArgs A) {
+// OCC3: ask for three wavefronts per SIMD (register cap 168) instead of two;
+// NP: macro points per wavefront
+template <int MA, int PREC, bool SPLIT, bool PF, bool OCC3, int NP>
+__global__ void __launch_bounds__(256, (OCC3 && MA <= 4 && NP == 1) ? 3 : 2) k_eval_mixed(EvalArgs A) {
     __shared__ v4u32 s_w[4][kCQ * kWR];
-    tan_mixed_body<MA, PREC, SPLIT, PF>(A, (int64_t)blockIdx.x * 4, s_w);
+    tan_mixed_body<MA, PREC, SPLIT, PF, NP>(A, (int64_t)blockIdx.x * (4 * NP), s_w);
 }
 
-template <int PREC, bool SPLIT, bool PF, bool OCC3>
+template <int PREC, bool SPLIT, bool PF, bool OCC3, int NP>
 static int launch_mixed_t(const EvalArgs& a, hipStream_t s) {
-    const dim3 grid(nblocks(a.count, 4)), block(256);
+    const dim3 grid(nblocks(a.count, 4 * NP)), block(256);
     switch ((a.m + 15) / 16) {
-        case 1: hipLaunchKernelGGL((k_eval_mixed<1, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_eval_mixed<2, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_eval_mixed<3, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_eval_mixed<4, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_eval_mixed<5, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_eval_mixed<6, PREC, SPLIT, PF, OCC3>), grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_eval_mixed<1, PREC, SPLIT, PF, OCC3, NP>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_eval_mixed<2, PREC, SPLIT, PF, OCC3, NP>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_eval_mixed<3, PREC, SPLIT, PF, OCC3, NP>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_eval_mixed<4, PREC, SPLIT, PF, OCC3, NP>), grid, block, 0, s, a); break;
+        // two points per wavefront do not fit the register file beyond m = 64
+        case 5: hipLaunchKernelGGL((k_eval_mixed<5, PREC, SPLIT, PF, OCC3, 1>), dim3(nblocks(a.count, 4)), block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_eval_mixed<6, PREC, SPLIT, PF, OCC3, 1>), dim3(nblocks(a.count, 4)), block, 0, s, a); break;
         default: return HROM_E_UNSUPPORTED;
     }
     return HROM_OK;
@@ -732,15 +766,18 @@ static int launch_mixed_t(const EvalArgs& a, hipStream_t s) {
 
 template <int PREC, bool SPLIT>
 static int launch_mixed_v(int variant, const EvalArgs& a, hipStream_t s) {
-    switch (variant & 3) {
-        case 0: return launch_mixed_t<PREC, SPLIT, true, false>(a, s);
-        case 1: return launch_mixed_t<PREC, SPLIT, true, true>(a, s);
-        case 2: return launch_mixed_t<PREC, SPLIT, false, false>(a, s);
-        default: return launch_mixed_t<PREC, SPLIT, false, true>(a, s);
+    switch (variant) {
+        case 0: return launch_mixed_t<PREC, SPLIT, true, false, 1>(a, s);
+        case 1: return launch_mixed_t<PREC, SPLIT, true, true, 1>(a, s);
+        case 2: return launch_mixed_t<PREC, SPLIT, false, false, 1>(a, s);
+        case 3: return launch_mixed_t<PREC, SPLIT, false, true, 1>(a, s);
+        case 4: return launch_mixed_t<PREC, SPLIT, false, false, 2>(a, s);
+        default: return launch_mixed_t<PREC, SPLIT, true, false, 2>(a, s);
     }
 }
 
-// variant bit 0: three wavefronts per SIMD instead of two; bit 1: no prefetch
+// variants 0..3: bit 0 three wavefronts per SIMD instead of two, bit 1 no
+// prefetch; 4, 5: two macro points per wavefront (without, with prefetch)
 int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s) {
     (void)MT;
     if (prec == HROM_MIXED_BF16)
