@@ -445,9 +445,26 @@ struct Pk<HROM_MIXED_BF16> {
         typedef float v2f __attribute__((ext_vector_type(2)));
         return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f{x0, x1}), v2bf));
     }
-    // x minus the value in the low / high half of h (exact in FP32)
-    static __device__ __forceinline__ float res_lo(uint32_t h, float x) { return x - __uint_as_float(h << 16); }
-    static __device__ __forceinline__ float res_hi(uint32_t h, float x) { return x - __uint_as_float(h & 0xFFFF0000u); }
+    // x minus the value in the low / high half of h, as one dot2 with the
+    // packed factor (-1, 0) or (0, -1); x - round(x) is exact in FP32 and so
+    // is the dot2 result.  The factor sits in a scalar register: folded into an
+    // inline constant it reaches the hardware with its halves swapped.
+    template <uint32_t V>
+    static __device__ __forceinline__ uint32_t in_sgpr() {
+        uint32_t r;
+        asm("s_mov_b32 %0, %1" : "=s"(r) : "n"(V));
+        return r;
+    }
+    static __device__ __forceinline__ float res_lo(uint32_t h, float x) {
+        typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2bf, h),
+                                               __builtin_bit_cast(v2bf, in_sgpr<0x0000BF80u>()), x, false);
+    }
+    static __device__ __forceinline__ float res_hi(uint32_t h, float x) {
+        typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2bf, h),
+                                               __builtin_bit_cast(v2bf, in_sgpr<0xBF800000u>()), x, false);
+    }
     static constexpr uint32_t one = 0x3F80u;
     static __device__ __forceinline__ v4f mfma(v4u32 a, v4u32 b, v4f c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
@@ -462,6 +479,8 @@ struct Pk<HROM_MIXED_FP16> {
         typedef float v2f __attribute__((ext_vector_type(2)));
         return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f{x0, x1}), v2h));
     }
+    // x minus the value in the low / high half of h (exact in FP32; the
+    // FP16 dot2 is not exact for subnormal halves)
     static __device__ __forceinline__ float res_lo(uint32_t h, float x) {
         return x - (float)__builtin_bit_cast(_Float16, (unsigned short)(h & 0xFFFFu));
     }
