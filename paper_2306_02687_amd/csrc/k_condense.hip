@@ -628,6 +628,14 @@ __global__ void __launch_bounds__(64) k_condense_grouped(GroupCall G) {
 
 __host__ __device__ constexpr int lblk(int t, int u) { return t * (t + 1) / 2 + u; }
 
+// The register condensation runs one wavefront per workgroup: LDS accesses of
+// one wavefront complete in issue order, so exchanging values between its
+// lanes needs only a wavefront-scope fence (no hardware barrier)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // block -> point order: workgroups are dispatched round-robin over the eight
 // XCDs; give each XCD a contiguous range of points so the component-major
 // stores of neighbouring points meet in the same L2
@@ -690,7 +698,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
 #pragma unroll
                 for (int t = J; t < MB; t++) cb[8 * t + lr] = M[lblk(t, J)];
             }
-            __syncthreads();
+            wave_sync();
             const double d = cb[j];
             if (!(d > 0.0)) {
                 spd = false;
@@ -710,7 +718,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
 #pragma unroll
                 for (int u = J; u <= t; u++) M[lblk(t, u)] = fma(-ci, ck[u], M[lblk(t, u)]);
             }
-            __syncthreads();
+            wave_sync();
         }
         if (!spd) break;
     }
@@ -726,7 +734,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
 #pragma unroll
             for (int u = 0; u < JB; u++) cb[8 * u + lc] = M[lblk(u, u)];
         }
-        __syncthreads();
+        wave_sync();
         double* Lp = A.L + pl * (int64_t)m * m;
 #pragma unroll
         for (int t = 0; t < JB; t++)
@@ -738,7 +746,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
                     Lp[(int64_t)i * m + k] = (i == k) ? sk : M[lblk(t, u)] / sk;
                 }
             }
-        __syncthreads();
+        wave_sync();
     }
     if (lane == 0) A.piv[pl * m] = -1;
 
@@ -757,7 +765,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
                 zb[lr] = M[lblk(JB, J)];
                 zb[8 + lr] = M[lblk(JB + 1, J)];
             }
-            __syncthreads();
+            wave_sync();
             const double rdj = 1.0 / cb[j];
             const double x0 = zb[lr] * rdj;
             const double x1 = (lr < 2) ? zb[8 + lr] * rdj : 0.0;
@@ -771,7 +779,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
                 M[lblk(JB, u)] = fma(-l, x0, M[lblk(JB, u)]);
                 M[lblk(JB + 1, u)] = fma(-l, x1, M[lblk(JB + 1, u)]);
             }
-            __syncthreads();
+            wave_sync();
         }
     }
 
