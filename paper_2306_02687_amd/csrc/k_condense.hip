@@ -628,6 +628,15 @@ __global__ void __launch_bounds__(64) k_condense_grouped(GroupCall G) {
 
 __host__ __device__ constexpr int lblk(int t, int u) { return t * (t + 1) / 2 + u; }
 
+// 1 / d for a pivot d > 0: hardware reciprocal refined by two Newton steps
+// (a few units in the last place; shorter dependency chain than a division)
+__device__ __forceinline__ double recip_pos(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
 // The register condensation runs one wavefront per workgroup: LDS accesses of
 // one wavefront complete in issue order, so exchanging values between its
 // lanes needs only a wavefront-scope fence (no hardware barrier)
@@ -699,12 +708,11 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
                 for (int t = J; t < MB; t++) cb[8 * t + lr] = M[lblk(t, J)];
             }
             wave_sync();
+            // a non-positive pivot is only flagged here: the sweep finishes
+            // with meaningless values and the point goes to the LU pass
             const double d = cb[j];
-            if (!(d > 0.0)) {
-                spd = false;
-                break;
-            }
-            const double rd = 1.0 / d;
+            spd = spd && (d > 0.0);
+            const double rd = recip_pos(d);
             double ck[MB];
 #pragma unroll
             for (int u = J; u < MB; u++) {
@@ -720,7 +728,6 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
             }
             wave_sync();
         }
-        if (!spd) break;
     }
     if (!spd) {
         if (lane == 0) A.status[b] |= HROM_PT_NOT_SPD;
@@ -766,7 +773,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
                 zb[8 + lr] = M[lblk(JB + 1, J)];
             }
             wave_sync();
-            const double rdj = 1.0 / cb[j];
+            const double rdj = recip_pos(cb[j]);
             const double x0 = zb[lr] * rdj;
             const double x1 = (lr < 2) ? zb[8 + lr] * rdj : 0.0;
             if (lc == jj) {
