@@ -53,13 +53,14 @@ def tangent_flops_per_point(m, Q):
     return 18.0 * Q * m * m + 324.0 * Q * m + 81.0 * Q
 
 
-def read_traffic(kernel_tag: str):
-    """HBM bytes per launch from a committed counter summary, if present."""
+def read_traffic(kernel_tag: str, variant: int):
+    """HBM bytes per launch of the given launch variant from a committed
+    counter summary (lines ``traffic_bytes_per_launch[variant=v]: X``), if present."""
     path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m = re.search(r"traffic_bytes_per_launch\[variant=%d\]:\s*([0-9.eE+]+)" % int(variant), txt)
     return float(m.group(1)) if m else None
 
 
@@ -289,7 +290,7 @@ def main():
     achieved = fl_tan / (res["tan_ms"] * 1e-3)
     peak = PEAK[args.precision]
     tag = f"tangent_{args.precision}_m{m}_q{Q}"
-    traffic = read_traffic(tag)
+    traffic = read_traffic(tag, res["variant"])
 
     fp64 = None
     if args.precision != "fp64" and not args.skip_fp64:

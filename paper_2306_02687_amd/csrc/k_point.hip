@@ -17,7 +17,7 @@ static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 
 // Ubar = V diag(sqrt c) V^T.  The RVE frame sees Fr = Ubar (objective) or
 // Fr = Fbar (direct).  Non-finite input or det Fbar <= 0 flags the point and
 // substitutes the identity so that no NaN leaves the point.
-__global__ void k_prepare(PointArgs A) {
+__global__ void __launch_bounds__(256) k_prepare(PointArgs A) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= A.N) return;
     const int64_t N = A.N;
@@ -89,7 +89,7 @@ __device__ __forceinline__ void load_polar(const double* polar, int64_t N, int64
 // dS = Linv(2 dT - dU S - S dU), Cbar e_k = E_k S + F dS.
 // One thread per (column k, macro point), k-major so that every load and
 // store is coalesced over the points; the k = 0 thread also writes Pbar, S.
-__global__ void k_pushout(PushArgs A) {
+__global__ void __launch_bounds__(256) k_pushout(PushArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t N = A.N;
     if (t >= 9 * N) return;
@@ -178,7 +178,7 @@ void launch_pushout(const PushArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------- update
 // linearised macro stretch increment dU = Linv(dF^T F + F^T dF) (objective)
 // or dF (direct); zero when no increment is given (pure micro Newton step).
-__global__ void k_stretch_increment(UpdateArgs A) {
+__global__ void __launch_bounds__(256) k_stretch_increment(UpdateArgs A) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= A.N) return;
     const int64_t N = A.N;
@@ -212,7 +212,7 @@ void launch_stretch_increment(const UpdateArgs& a, hipStream_t s) {
 // a <- a - (y + X dU)  (Sec. 3.2.3), one thread per (mode, point).  Points
 // flagged as failed are left unchanged; without an increment (pure micro
 // Newton step) converged points (rnorm < tol) are frozen.
-__global__ void k_update(UpdateArgs A) {
+__global__ void __launch_bounds__(256) k_update(UpdateArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)A.m * A.count) return;
     const int k = (int)(t / A.count);
@@ -234,7 +234,7 @@ void launch_update(const UpdateArgs& a, hipStream_t s) {
 
 // ---------------------------------------------------------------- backward
 // pull-back of the macro cotangent: Lam = Linv(sym(F^T g)), g_r = 2 Lam
-__global__ void k_bw_pullback(BwPointArgs A) {
+__global__ void __launch_bounds__(256) k_bw_pullback(BwPointArgs A) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= A.N) return;
     const int64_t N = A.N;
@@ -266,7 +266,7 @@ void launch_bw_pullback(const BwPointArgs& a, hipStream_t s) {
 }
 
 // dL/dFbar = g S + 2 F Linv(sym(h_r) - Lam S - S Lam)
-__global__ void k_bw_pushforward(BwPointArgs A) {
+__global__ void __launch_bounds__(256) k_bw_pushforward(BwPointArgs A) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= A.N) return;
     const int64_t N = A.N;
@@ -305,7 +305,7 @@ void launch_bw_pushforward(const BwPointArgs& a, hipStream_t s) {
 }
 
 // adjoint solve with the stored factor: lambda = Kaa^{-T} KaF g_r = X g_r
-__global__ void k_lambda(LambdaArgs A) {
+__global__ void __launch_bounds__(256) k_lambda(LambdaArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)A.m * A.count) return;
     const int k = (int)(t / A.count);
@@ -325,7 +325,7 @@ void launch_lambda(const LambdaArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------- reductions
 // dL/dtheta: fixed-order sum over points (bitwise reproducible): thread t of
 // component c sums points t, t + 256, ... in order, then a fixed tree.
-__global__ void k_reduce_theta(int64_t N, const double* gth, double* out) {
+__global__ void __launch_bounds__(256) k_reduce_theta(int64_t N, const double* gth, double* out) {
     __shared__ double s[256];
     const int c = blockIdx.x;
     const int t = threadIdx.x;
@@ -344,7 +344,7 @@ void launch_reduce_theta(int64_t N, const double* gth, double* out, hipStream_t 
     hipLaunchKernelGGL(k_reduce_theta, dim3(4), dim3(256), 0, s, N, gth, out);
 }
 
-__global__ void k_mark_unconverged(int64_t N, const double* rnorm, double tol, int* status) {
+__global__ void __launch_bounds__(256) k_mark_unconverged(int64_t N, const double* rnorm, double tol, int* status) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= N) return;
     if (!(rnorm[b] < tol)) status[b] |= HROM_PT_NOCONV;
@@ -375,7 +375,7 @@ __device__ __forceinline__ float from_f16_bits(uint16_t h) {
 
 // One thread per (q, row J, column n) of the augmented mode matrix
 // Ghat_q = [G_q | I_9 | 0] (9 x MP).
-__global__ void k_build_ghat(LayoutArgs A) {
+__global__ void __launch_bounds__(256) k_build_ghat(LayoutArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = (int64_t)A.Qpad * 9 * A.MP;
     if (t >= tot) return;
@@ -409,7 +409,7 @@ __global__ void k_build_ghat(LayoutArgs A) {
 // (hi part Gh and rounded remainder Gl; Gl = 0 without the split).  Paired
 // with the matching W or T slots, one MFMA forms all three split products
 // hi*hi + lo*hi + hi*lo of the nine-component contraction.
-__global__ void k_build_frags(LayoutArgs A) {
+__global__ void __launch_bounds__(256) k_build_frags(LayoutArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int MA = (A.m + 15) / 16;
     const int64_t tot = (int64_t)A.Qpad * MA * 64 * 8;
@@ -446,7 +446,7 @@ __global__ void k_build_frags(LayoutArgs A) {
 // A-operand fragments of the kinematics GEMM (FP64 16x16x4 MFMA): row tile
 // rt, k-step s, lane (g, c) holds G[q][I][k] with 9 q + I = 16 rt + c and
 // k = 4 s + g (zero beyond m and beyond Q).
-__global__ void k_build_gf(LayoutArgs A) {
+__global__ void __launch_bounds__(256) k_build_gf(LayoutArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ntile = (int64_t)A.Qpad * 9 / 16;
     if (t >= ntile * A.KS * 64) return;
@@ -477,7 +477,7 @@ __device__ inline int find_cluster_by_offset(const GroupCall& G, int64_t t) {
     return c;
 }
 
-__global__ void k_update_grouped(GroupCall G, int64_t a_len) {
+__global__ void __launch_bounds__(256) k_update_grouped(GroupCall G, int64_t a_len) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a_len) return;
     const ClusterGPU& C = G.cls[find_cluster_by_offset(G, t)];
@@ -499,7 +499,7 @@ void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s) {
     hipLaunchKernelGGL(k_update_grouped, dim3(nblocks(a_len, 256)), dim3(256), 0, s, g, a_len);
 }
 
-__global__ void k_lambda_grouped(GroupCall G, int64_t a_len) {
+__global__ void __launch_bounds__(256) k_lambda_grouped(GroupCall G, int64_t a_len) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a_len) return;
     const ClusterGPU& C = G.cls[find_cluster_by_offset(G, t)];
