@@ -59,34 +59,43 @@ __device__ __forceinline__ void tangent_row(const T* Fi, T c0, T c1, T c2, T* W)
 
 
 // ============================================================== kinematics
-// 32 macro points per workgroup of eight wavefronts, ECM points in rounds of
-// 16.  Every FP64 MFMA operand of G is used for two 16-point column tiles.
-// Per round:
+// 32 macro points per workgroup of NW = 4 or 8 wavefronts, ECM points in
+// rounds of 16.  Every FP64 MFMA operand of G is used for two 16-point column
+// tiles.  Per round:
 //   F - F_r = G a      144 rows (ECM point, component) x 32 points; wave w takes
-//                      row tile w, waves 0..3 also a k-range of row tile 8
-//                      (partial sums added in a fixed order)
-//   law                thread = (point, ECM point): w P, tangent scalars
-//   r += G^T (w P)     the round's 36 k-steps split over the waves
-//                      (fixed-order sum over the waves at the end)
+//                      row tiles w (+ NW ...) < 8, waves 0..3 a k-range of row
+//                      tile 8 (partial sums added in a fixed order)
+//   law                thread = 8 / NW (point, ECM point) pairs: w P, tangent
+//                      scalars (w P overwrites F in place)
+//   r += G^T (w P)     the round's 36 k-steps in four k-ranges of nine, one
+//                      per wave w % 4 (eight waves: waves w and w + 4 split
+//                      the mode tiles by parity); fixed-order sum over the four
+//                      k-ranges at the end, so that both workgroup shapes give
+//                      bitwise the same r
 //   Pbar_r += w P      fixed-order sum over the round's ECM points
+// With four wavefronts and m <= 64 the workgroup holds about 73 KB of LDS, so
+// two workgroups share a CU and the matrix phases of one overlap the material
+// law of the other.
 constexpr int kKinPT = 32;
+template <int AR>   // rows of the mode amplitudes (>= 4 ceil(m / 4))
 struct KinLds {
-    double sA[kMaxModes + 4][kKinPT];
-    double sF[16 * 9][kKinPT + 1];
+    double sA[AR][kKinPT];
+    double sF[16 * 9][kKinPT + 1];   // F of the round, then w P in place
     double sF8[4][16][kKinPT + 1];
-    double sWP[16 * 9][kKinPT + 1];
     double sU[9][kKinPT];
     int sbits[kKinPT];
 };
 
 // the 32 macro points p0 .. p0+31 of the cluster described by A; MA = ceil(m / 16)
-template <bool MIXED, int MA>
-__device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
-    constexpr int PT = kKinPT, QC = 16;
+template <bool MIXED, int MA, int NW, int AR>
+__device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
+    constexpr int PT = kKinPT, QC = 16, NT = 64 * NW;
+    static_assert(AR >= 16 * MA, "mode amplitude rows");
+    static_assert(NW == 4 || NW == 8, "four or eight wavefronts");
     auto& sA = L.sA;
     auto& sF = L.sF;
+    auto& sWP = L.sF;
     auto& sF8 = L.sF8;
-    auto& sWP = L.sWP;
     auto& sU = L.sU;
     auto& sbits = L.sbits;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -95,7 +104,7 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
     const int np = (int)min((int64_t)PT, A.count - p0);
     if (tid < PT) sbits[tid] = 0;
     __syncthreads();
-    for (int e = tid; e < 4 * KS * PT; e += 512) {
+    for (int e = tid; e < 4 * KS * PT; e += NT) {
         const int k = e / PT, p = e % PT;
         double v = 0.0;
         if (k < m && p < np) {
@@ -107,7 +116,7 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
         }
         sA[k][p] = v;
     }
-    for (int e = tid; e < 9 * PT; e += 512) {
+    for (int e = tid; e < 9 * PT; e += NT) {
         const int I = e / PT, p = e % PT;
         sU[I][p] = (p < np) ? A.Fr[(int64_t)I * A.N + A.first + p0 + p] : ((I % 4 == 0) ? 1.0 : 0.0);
     }
@@ -115,16 +124,25 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
     v4d racc[MA][2];
 #pragma unroll
     for (int t = 0; t < MA; t++) racc[t][0] = racc[t][1] = v4d{0.0, 0.0, 0.0, 0.0};
-    double pacc = 0.0;   // Pbar_r (I = tid / 32, point tid % 32) for tid < 288
+    // Pbar_r (I = e / 32, point e % 32) for the entries e = tid + NT h < 288
+    constexpr int NPB = (9 * PT + NT - 1) / NT;
+    double pacc[NPB];
+#pragma unroll
+    for (int h = 0; h < NPB; h++) pacc[h] = 0.0;
     const int klo = (wave * KS) >> 2, khi = ((wave + 1) * KS) >> 2;
-    const int js = (wave * 36) >> 3, je = ((wave + 1) * 36) >> 3;
+    const int v = wave & 3;                        // k-range of the residual GEMM
+    const int js = 9 * v, je = 9 * v + 9;
+    const int tpar = (NW == 8) ? (wave >> 2) : 0;  // mode-tile parity (eight waves)
+    auto holds = [&](int t) { return NW == 4 || (t & 1) == tpar; };
     __syncthreads();
 
     for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
         const int rt0 = (q0 / 16) * 9;
-        // ---- F - Fr: row tile `wave`
-        {
-            const double* gf = A.Gf + ((int64_t)(rt0 + wave) * KS) * 64 + lane;
+        // ---- F - Fr: row tiles wave, wave + NW, ... < 8
+#pragma unroll
+        for (int h = 0; h < 8 / NW; h++) {
+            const int rt = wave + NW * h;
+            const double* gf = A.Gf + ((int64_t)(rt0 + rt) * KS) * 64 + lane;
             double af[4 * MA];
 #pragma unroll
             for (int s2 = 0; s2 < 4 * MA; s2++)
@@ -138,7 +156,7 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
                 }
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const int row = 16 * wave + g + 4 * e;   // FP64 MFMA accumulator rows interleave
+                const int row = 16 * rt + g + 4 * e;   // FP64 MFMA accumulator rows interleave
                 sF[row][c] = a0[e] + sU[row % 9][c];
                 sF[row][16 + c] = a1[e] + sU[row % 9][16 + c];
             }
@@ -159,9 +177,11 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
             }
         }
         __syncthreads();
-        // ---- material law: thread = (point p, ECM point q0 + qq)
-        {
-            const int p = tid >> 4, qq = tid & 15, q = q0 + qq;
+        // ---- material law: thread = (point p, ECM point q0 + qq), 8 / NW per thread
+#pragma unroll 1
+        for (int h = 0; h < 8 / NW; h++) {
+            const int e2 = tid + NT * h;
+            const int p = e2 >> 4, qq = e2 & 15, q = q0 + qq;
             double F[9];
 #pragma unroll
             for (int I = 0; I < 9; I++) {
@@ -179,6 +199,7 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
             const bool ok = live && (J > 0.0);
             if (live && !(J > 0.0)) atomicOr(&sbits[p], HROM_PT_JNONPOS);
             const double ell = ok ? log(J) : 0.0;
+            // w P over the same slots the thread read F from
 #pragma unroll
             for (int i = 0; i < 3; i++)
 #pragma unroll
@@ -216,43 +237,54 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
             const double b0 = sWP[4 * j + g][c], b1 = sWP[4 * j + g][16 + c];
             const double* gh = A.Ghat + (int64_t)(q0 * 9 + 4 * j + g) * MP + c;
 #pragma unroll
-            for (int t = 0; t < MA; t++) {
+            for (int t = 0; t < MA; t++)
+                if (holds(t)) {
                     const double av = gh[16 * t];
                     racc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, racc[t][0], 0, 0, 0);
                     racc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, racc[t][1], 0, 0, 0);
                 }
         }
         // ---- Pbar_r += sum over the round's ECM points of w P
-        if (tid < 9 * PT) {
-            const int I = tid >> 5, p = tid & 31;
-            double sp = 0.0;
 #pragma unroll
-            for (int qq = 0; qq < QC; qq++) sp += sWP[qq * 9 + I][p];
-            pacc += sp;
+        for (int h = 0; h < NPB; h++) {
+            const int e2 = tid + NT * h;
+            if (e2 < 9 * PT) {
+                const int I = e2 >> 5, p = e2 & 31;
+                double sp = 0.0;
+#pragma unroll
+                for (int qq = 0; qq < QC; qq++) sp += sWP[qq * 9 + I][p];
+                pacc[h] += sp;
+            }
         }
         __syncthreads();
     }
-    if (tid < 9 * PT && (tid & 31) < np)
-        A.Pr[(int64_t)(tid >> 5) * A.N + A.first + p0 + (tid & 31)] = pacc;
-    // fixed-order sum of the eight waves' partial r through LDS (sF reused)
+#pragma unroll
+    for (int h = 0; h < NPB; h++) {
+        const int e2 = tid + NT * h;
+        if (e2 < 9 * PT && (e2 & 31) < np)
+            A.Pr[(int64_t)(e2 >> 5) * A.N + A.first + p0 + (e2 & 31)] = pacc[h];
+    }
+    // fixed-order sum of the four k-range partials of r through LDS (sF reused)
     double* red = &sF[0][0];
 #pragma unroll
     for (int t = 0; t < MA; t++) {
+        if (holds(t)) {
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            red[(wave * 16 + g + 4 * e) * PT + c] = racc[t][0][e];
-            red[(wave * 16 + g + 4 * e) * PT + 16 + c] = racc[t][1][e];
+            for (int e = 0; e < 4; e++) {
+                red[(v * 16 + g + 4 * e) * PT + c] = racc[t][0][e];
+                red[(v * 16 + g + 4 * e) * PT + 16 + c] = racc[t][1][e];
+            }
         }
         __syncthreads();
-        {
-            const int rr = tid >> 5, p = tid & 31;   // 16 rows x 32 points
-            if (tid < 16 * PT) {
-                double v = 0.0;
 #pragma unroll
-                for (int w = 0; w < 8; w++) v += red[(w * 16 + rr) * PT + p];
-                const int row = 16 * t + rr;
-                if (p < np && row < m) A.r[(int64_t)row * A.count + p0 + p] = v;
-            }
+        for (int h = 0; h < 512 / NT; h++) {
+            const int e2 = tid + NT * h;   // 16 rows x 32 points
+            const int rr = e2 >> 5, p = e2 & 31;
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; w++) sum += red[(w * 16 + rr) * PT + p];
+            const int row = 16 * t + rr;
+            if (p < np && row < m) A.r[(int64_t)row * A.count + p0 + p] = sum;
         }
         __syncthreads();
     }
@@ -260,26 +292,28 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds& L) {
 }
 
 template <bool MIXED, int MA>
-__global__ void __launch_bounds__(512) k_kin(EvalArgs A) {
-    __shared__ KinLds L;
-    kin_body<MIXED, MA>(A, (int64_t)blockIdx.x * kKinPT, L);
+__global__ void __launch_bounds__(256, 2) k_kin(EvalArgs A) {
+    __shared__ KinLds<16 * MA> L;
+    kin_body<MIXED, MA, 4>(A, (int64_t)blockIdx.x * kKinPT, L);
 }
 
+using KinLdsMax = KinLds<16 * ((kMaxModes + 15) / 16)>;
+
 template <bool MIXED>
-__device__ void kin_dispatch(const EvalArgs& A, int64_t p0, KinLds& L) {
+__device__ void kin_dispatch(const EvalArgs& A, int64_t p0, KinLdsMax& L) {
     switch ((A.m + 15) / 16) {
-        case 1: kin_body<MIXED, 1>(A, p0, L); break;
-        case 2: kin_body<MIXED, 2>(A, p0, L); break;
-        case 3: kin_body<MIXED, 3>(A, p0, L); break;
-        case 4: kin_body<MIXED, 4>(A, p0, L); break;
-        case 5: kin_body<MIXED, 5>(A, p0, L); break;
-        default: kin_body<MIXED, 6>(A, p0, L); break;
+        case 1: kin_body<MIXED, 1, 8>(A, p0, L); break;
+        case 2: kin_body<MIXED, 2, 8>(A, p0, L); break;
+        case 3: kin_body<MIXED, 3, 8>(A, p0, L); break;
+        case 4: kin_body<MIXED, 4, 8>(A, p0, L); break;
+        case 5: kin_body<MIXED, 5, 8>(A, p0, L); break;
+        default: kin_body<MIXED, 6, 8>(A, p0, L); break;
     }
 }
 
 template <bool MIXED>
 static void launch_kin_t(const EvalArgs& a, hipStream_t s) {
-    const dim3 grid(nblocks(a.count, kKinPT)), block(512);
+    const dim3 grid(nblocks(a.count, kKinPT)), block(256);
     switch ((a.m + 15) / 16) {
         case 1: hipLaunchKernelGGL((k_kin<MIXED, 1>), grid, block, 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_kin<MIXED, 2>), grid, block, 0, s, a); break;
@@ -823,10 +857,10 @@ __device__ inline EvalArgs group_eval_args(const GroupCall& G, int c, size_t tsz
     return A;
 }
 
-// kinematics of every cluster in one launch: one 16-point tile per workgroup
+// kinematics of every cluster in one launch: one 32-point tile per workgroup
 template <bool MIXED>
 __global__ void __launch_bounds__(512) k_kin_grouped(GroupCall G) {
-    __shared__ KinLds L;
+    __shared__ KinLdsMax L;
     const WorkItem w = G.items[blockIdx.x];
     const EvalArgs A = group_eval_args(G, w.c, MIXED ? sizeof(float) : sizeof(double));
     kin_dispatch<MIXED>(A, (int64_t)w.unit * kKinPT, L);
