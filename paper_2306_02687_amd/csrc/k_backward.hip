@@ -9,6 +9,8 @@
 // of the adjoint system is accumulated with the same operator.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "hrom_internal.h"
 
 namespace hrom {
@@ -39,27 +41,34 @@ __device__ __forceinline__ void nh_apply(const T* Fi, T mu, T la, T ell, const T
 
 
 // Point-batched form of the adjoint re-evaluation: 32 macro points per
-// workgroup of eight wavefronts; F_q - Fr = G a and G lambda are GEMMs with the
-// cluster's G as the shared operand (FP64 MFMA, two 16-point column tiles),
-// wave w taking row tile w of the round's 144 rows (ECM point, component) and
-// waves 0..3 one of the four products (F or G lambda, column tile) of tile 8;
-// the law and its adjoint run one (point, ECM point) pair per thread; the
-// refinement residual rho = G^T (w A v) is a third FP64 GEMM.  Per-point sums
-// over the ECM points (h_r, dL/dtheta) reduce in a fixed order.
-constexpr int kBwPT = 32, kBwThreads = 512;
+// workgroup of NW = 4 or 8 wavefronts; F_q - Fr = G a and G lambda are GEMMs
+// with the cluster's G as the shared operand (FP64 MFMA, two 16-point column
+// tiles), wave w taking row tiles w (+ NW ...) < 8 of the round's 144 rows
+// (ECM point, component) and waves 0..3 one of the four products (F or
+// G lambda, column tile) of tile 8; the law and its adjoint run per (point,
+// ECM point) pair (eight waves: one pair per thread; four waves: the pairs
+// (p, s) and (p, s + 8) of one point per thread); the refinement residual
+// rho = G^T (w A v) is a third FP64 GEMM in four k-ranges.  Per-point sums
+// over the ECM points (h_r, dL/dtheta) reduce in a fixed order.  The mixed
+// path keeps F_q and v_q in FP32 in LDS (its law evaluates A v in FP32), so
+// that four wavefronts fit two workgroups per CU.
+constexpr int kBwPT = 32;
+template <int AR, typename LT>
 struct BwLds {
-    double sA[kMaxModes + 4][kBwPT];
-    double sL[kMaxModes + 4][kBwPT];
-    double sF[16 * 9][kBwPT + 1];
-    double sV[16 * 9][kBwPT + 1];
+    double sA[AR][kBwPT];
+    double sL[AR][kBwPT];
+    LT sF[16 * 9][kBwPT + 1];
+    LT sV[16 * 9][kBwPT + 1];
     double sU[9][kBwPT];
     double sG[9][kBwPT];
     int sbits[kBwPT];
 };
 
-template <int MA, bool MIXED, bool RHO>
-__device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
-    constexpr int PT = kBwPT, QC = 16, NT = kBwThreads;
+template <int MA, bool MIXED, bool RHO, int NW, int AR, typename LT>
+__device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
+    constexpr int PT = kBwPT, QC = 16, NT = 64 * NW;
+    static_assert(NW == 4 || NW == 8, "four or eight wavefronts");
+    static_assert(AR >= 16 * MA, "mode amplitude rows");
     auto& sA = Ls.sA;
     auto& sL = Ls.sL;
     auto& sF = Ls.sF;
@@ -85,11 +94,17 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
         sG[I][p] = (p < np) ? A.gr[(int64_t)I * A.N + b] : 0.0;
     }
     const double mu0 = A.theta[0], la0 = A.theta[1], mu1 = A.theta[2], la1 = A.theta[3];
+    // law pairs of this thread: (point pp, ECM points qa + 8 h)
+    constexpr int NPAIR = 8 / NW, LPP = 16 / NPAIR;   // pairs per thread, lanes per point
+    const int pp = tid / LPP, qa = tid % LPP;
     double h[9], gt[4];
 #pragma unroll
     for (int I = 0; I < 9; I++) h[I] = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; i++) gt[i] = 0.0;
+    const int v4 = wave & 3;                        // k-range of the rho GEMM
+    const int tpar = (NW == 8) ? (wave >> 2) : 0;  // mode-tile parity (eight waves)
+    auto holds = [&](int t) { return NW == 4 || (t & 1) == tpar; };
     v4d racc[RHO ? MA : 1][2];
 #pragma unroll
     for (int t = 0; t < (RHO ? MA : 1); t++) racc[t][0] = racc[t][1] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -97,8 +112,10 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
 
     for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
         const int rt0 = (q0 / 16) * 9;
-        {
-            const double* gf = A.Gf + ((int64_t)(rt0 + wave) * KS) * 64 + lane;
+#pragma unroll
+        for (int hh = 0; hh < 8 / NW; hh++) {
+            const int rt = wave + NW * hh;
+            const double* gf = A.Gf + ((int64_t)(rt0 + rt) * KS) * 64 + lane;
             double af[4 * MA];
 #pragma unroll
             for (int s2 = 0; s2 < 4 * MA; s2++)
@@ -114,11 +131,11 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
                 }
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const int row = 16 * wave + g + 4 * e;   // FP64 MFMA accumulator rows interleave
-                sF[row][c] = f0[e] + sU[row % 9][c];
-                sF[row][16 + c] = f1[e] + sU[row % 9][16 + c];
-                sV[row][c] = sG[row % 9][c] - l0[e];
-                sV[row][16 + c] = sG[row % 9][16 + c] - l1[e];
+                const int row = 16 * rt + g + 4 * e;   // FP64 MFMA accumulator rows interleave
+                sF[row][c] = (LT)(f0[e] + sU[row % 9][c]);
+                sF[row][16 + c] = (LT)(f1[e] + sU[row % 9][16 + c]);
+                sV[row][c] = (LT)(sG[row % 9][c] - l0[e]);
+                sV[row][16 + c] = (LT)(sG[row % 9][16 + c] - l1[e]);
             }
         }
         if (wave < 4) {
@@ -136,18 +153,19 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const int row = 128 + g + 4 * e;
-                if (isF) sF[row][col] = acc[e] + sU[row % 9][col];
-                else sV[row][col] = sG[row % 9][col] - acc[e];
+                if (isF) sF[row][col] = (LT)(acc[e] + sU[row % 9][col]);
+                else sV[row][col] = (LT)(sG[row % 9][col] - acc[e]);
             }
         }
         __syncthreads();
-        {
-            const int p = tid >> 4, qq = tid & 15, q = q0 + qq;
+#pragma unroll 1
+        for (int k2 = 0; k2 < NPAIR; k2++) {
+            const int p = pp, qq = qa + LPP * k2, q = q0 + qq;
             double F[9], v[9];
 #pragma unroll
             for (int I = 0; I < 9; I++) {
-                F[I] = sF[qq * 9 + I][p];
-                v[I] = sV[qq * 9 + I][p];
+                F[I] = (double)sF[qq * 9 + I][p];
+                v[I] = (double)sV[qq * 9 + I][p];
             }
             const double wq = A.w[q];
             const int ph = A.phase[q];
@@ -205,69 +223,75 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
             gt[3] = fma(wi, dla, gt[3]);
             if constexpr (RHO) {
 #pragma unroll
-                for (int I = 0; I < 9; I++) sV[qq * 9 + I][p] = wo * Av[I];
+                for (int I = 0; I < 9; I++) sV[qq * 9 + I][p] = (LT)(wo * Av[I]);
             }
         }
         __syncthreads();
         if constexpr (RHO) {
-            // the round's 36 k-steps split over the eight waves
-            for (int j = (wave * 36) >> 3; j < ((wave + 1) * 36) >> 3; j++) {
-                const double b0 = sV[4 * j + g][c], b1 = sV[4 * j + g][16 + c];
+            // the round's 36 k-steps in four k-ranges of nine
+            for (int j = 9 * v4; j < 9 * v4 + 9; j++) {
+                const double b0 = (double)sV[4 * j + g][c], b1 = (double)sV[4 * j + g][16 + c];
                 const double* gh = A.Ghat + (int64_t)(q0 * 9 + 4 * j + g) * MP + c;
 #pragma unroll
-                for (int t = 0; t < MA; t++) {
-                    const double av = gh[16 * t];
-                    racc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, racc[t][0], 0, 0, 0);
-                    racc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, racc[t][1], 0, 0, 0);
-                }
+                for (int t = 0; t < MA; t++)
+                    if (holds(t)) {
+                        const double av = gh[16 * t];
+                        racc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, racc[t][0], 0, 0, 0);
+                        racc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, racc[t][1], 0, 0, 0);
+                    }
             }
             __syncthreads();
         }
     }
-    // per-point sums over the 16 threads of the point (lanes 16p' .. 16p'+15
-    // of a wave hold point p = tid >> 4): fixed butterfly within 16 lanes
+    // per-point sums over the LPP threads of the point (consecutive lanes of a
+    // wave): fixed butterfly
 #pragma unroll
     for (int I = 0; I < 9; I++)
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) h[I] += __shfl_xor(h[I], off);
+        for (int off = LPP / 2; off > 0; off >>= 1) h[I] += __shfl_xor(h[I], off);
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) gt[i] += __shfl_xor(gt[i], off);
-    {
-        const int p = tid >> 4, sub = tid & 15;
-        if (p < np) {
-            const int64_t b = A.first + p0 + p;
-            const bool failed = (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) || sbits[p];
-            double v = 0.0;
+        for (int off = LPP / 2; off > 0; off >>= 1) gt[i] += __shfl_xor(gt[i], off);
+    if (pp < np) {
+        const int64_t b = A.first + p0 + pp;
+        const bool failed = (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) || sbits[pp];
+        // outputs 0..8 = h_r, 9..12 = dL/dtheta, written by the point's lanes
 #pragma unroll
-            for (int I = 0; I < 9; I++) v = (sub == I) ? h[I] : v;
-            if (sub < 9) A.hr[(int64_t)sub * A.N + b] = failed ? 0.0 : v;
-            double u = 0.0;
+        for (int o0 = 0; o0 < 13; o0 += LPP) {
+            const int o = o0 + qa;
+            double val = 0.0;
 #pragma unroll
-            for (int i = 0; i < 4; i++) u = (sub == 9 + i) ? gt[i] : u;
-            if (sub >= 9 && sub < 13) A.gth[(int64_t)(sub - 9) * A.N + b] = failed ? 0.0 : u;
+            for (int I = 0; I < 9; I++) val = (o == I) ? h[I] : val;
+#pragma unroll
+            for (int i = 0; i < 4; i++) val = (o == 9 + i) ? gt[i] : val;
+            if (o < 9) A.hr[(int64_t)o * A.N + b] = failed ? 0.0 : val;
+            else if (o < 13) A.gth[(int64_t)(o - 9) * A.N + b] = failed ? 0.0 : val;
         }
     }
     if constexpr (RHO) {
-        // fixed-order sum of the eight waves' partial rho through LDS (sF reused)
-        double* red = &sF[0][0];
+        // fixed-order sum of the four k-range partials of rho through LDS
+        double* red = reinterpret_cast<double*>(&sF[0][0]);
 #pragma unroll
         for (int t = 0; t < MA; t++) {
             __syncthreads();
+            if (holds(t)) {
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                red[(wave * 16 + g + 4 * e) * PT + c] = racc[t][0][e];
-                red[(wave * 16 + g + 4 * e) * PT + 16 + c] = racc[t][1][e];
+                for (int e = 0; e < 4; e++) {
+                    red[(v4 * 16 + g + 4 * e) * PT + c] = racc[t][0][e];
+                    red[(v4 * 16 + g + 4 * e) * PT + 16 + c] = racc[t][1][e];
+                }
             }
             __syncthreads();
-            if (tid < 16 * PT) {
-                const int rr = tid >> 5, p = tid & 31;
-                double v = 0.0;
 #pragma unroll
-                for (int w = 0; w < 8; w++) v += red[(w * 16 + rr) * PT + p];
+            for (int k2 = 0; k2 < 512 / NT; k2++) {
+                const int e2 = tid + NT * k2;   // 16 rows x 32 points
+                const int rr = e2 >> 5, p = e2 & 31;
+                double sum = 0.0;
+#pragma unroll
+                for (int w = 0; w < 4; w++) sum += red[(w * 16 + rr) * PT + p];
                 const int row = 16 * t + rr;
-                if (p < np && row < m) A.rho[(int64_t)row * A.count + p0 + p] = sbits[p] ? 0.0 : v;
+                if (p < np && row < m) A.rho[(int64_t)row * A.count + p0 + p] = sbits[p] ? 0.0 : sum;
             }
         }
     }
@@ -275,28 +299,33 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
     if (tid < np && sbits[tid]) A.status[A.first + p0 + tid] |= HROM_PT_JNONPOS;
 }
 
+template <bool MIXED>
+using BwLdsMax = BwLds<16 * ((kMaxModes + 15) / 16), typename std::conditional<MIXED, float, double>::type>;
+
 template <bool MIXED, bool RHO>
-__device__ void bw_dispatch(const BackwardArgs& A, int64_t p0, BwLds& Ls) {
+__device__ void bw_dispatch(const BackwardArgs& A, int64_t p0, BwLdsMax<MIXED>& Ls) {
     switch ((A.m + 15) / 16) {
-        case 1: bw_body<1, MIXED, RHO>(A, p0, Ls); break;
-        case 2: bw_body<2, MIXED, RHO>(A, p0, Ls); break;
-        case 3: bw_body<3, MIXED, RHO>(A, p0, Ls); break;
-        case 4: bw_body<4, MIXED, RHO>(A, p0, Ls); break;
-        case 5: bw_body<5, MIXED, RHO>(A, p0, Ls); break;
-        default: bw_body<6, MIXED, RHO>(A, p0, Ls); break;
+        case 1: bw_body<1, MIXED, RHO, 8>(A, p0, Ls); break;
+        case 2: bw_body<2, MIXED, RHO, 8>(A, p0, Ls); break;
+        case 3: bw_body<3, MIXED, RHO, 8>(A, p0, Ls); break;
+        case 4: bw_body<4, MIXED, RHO, 8>(A, p0, Ls); break;
+        case 5: bw_body<5, MIXED, RHO, 8>(A, p0, Ls); break;
+        default: bw_body<6, MIXED, RHO, 8>(A, p0, Ls); break;
     }
 }
 
+// single cluster: the mixed path with four wavefronts (two workgroups per CU),
+// the FP64 path with eight
 template <int MA, bool MIXED, bool RHO>
-__global__ void __launch_bounds__(kBwThreads) k_backward_b(BackwardArgs A) {
-    __shared__ BwLds Ls;
-    bw_body<MA, MIXED, RHO>(A, (int64_t)blockIdx.x * kBwPT, Ls);
+__global__ void __launch_bounds__(MIXED ? 256 : 512, MIXED ? 2 : 1) k_backward_b(BackwardArgs A) {
+    __shared__ BwLds<16 * MA, typename std::conditional<MIXED, float, double>::type> Ls;
+    bw_body<MA, MIXED, RHO, MIXED ? 4 : 8>(A, (int64_t)blockIdx.x * kBwPT, Ls);
 }
 
 // adjoint re-evaluation of every cluster in one launch (32-point tiles)
 template <bool MIXED, bool RHO>
-__global__ void __launch_bounds__(kBwThreads) k_backward_grouped(GroupCall G) {
-    __shared__ BwLds Ls;
+__global__ void __launch_bounds__(512) k_backward_grouped(GroupCall G) {
+    __shared__ BwLdsMax<MIXED> Ls;
     const WorkItem w = G.items[blockIdx.x];
     const ClusterGPU& C = G.cls[w.c];
     BackwardArgs A;
@@ -310,7 +339,7 @@ __global__ void __launch_bounds__(kBwThreads) k_backward_grouped(GroupCall G) {
 }
 
 int launch_backward_grouped(const GroupCall& g, hipStream_t s) {
-    const dim3 grid(g.nitems), block(kBwThreads);
+    const dim3 grid(g.nitems), block(512);
     if (g.mixed && g.with_rho) hipLaunchKernelGGL((k_backward_grouped<true, true>), grid, block, 0, s, g);
     else if (g.mixed) hipLaunchKernelGGL((k_backward_grouped<true, false>), grid, block, 0, s, g);
     else if (g.with_rho) hipLaunchKernelGGL((k_backward_grouped<false, true>), grid, block, 0, s, g);
@@ -320,7 +349,7 @@ int launch_backward_grouped(const GroupCall& g, hipStream_t s) {
 
 template <bool MIXED, bool RHO>
 static int launch_bw_t(const BackwardArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.count + kBwPT - 1) / kBwPT)), block(kBwThreads);
+    const dim3 grid((unsigned)((a.count + kBwPT - 1) / kBwPT)), block(MIXED ? 256 : 512);
     switch ((a.m + 15) / 16) {
         case 1: hipLaunchKernelGGL((k_backward_b<1, MIXED, RHO>), grid, block, 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_backward_b<2, MIXED, RHO>), grid, block, 0, s, a); break;
