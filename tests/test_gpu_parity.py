@@ -252,6 +252,56 @@ def test_clusters_in_one_plan_match_single_plans(dev, orc):
     plan.close()
 
 
+@pytest.mark.parametrize("precision,split,refine", [(0, False, False), (1, True, False),
+                                                    (1, False, True)])
+def test_backward_clusters_in_one_plan(dev, orc, precision, split, refine):
+    """Adjoint of a plan holding several clusters (the grouped launches) vs the
+    oracle's adjoint cluster by cluster; dL/dtheta sums over all points.  On
+    the FP64 path dL/dFbar also equals that of one plan per cluster bitwise."""
+    from paper_2306_02687_amd import solve
+    log_case("backward_multi", precision, split, refine)
+    shapes = [(8, 48, 5), (24, 144, 4), (48, 288, 3)]
+    cls = [make_cluster(m, Q, 3200 + m) for m, Q, _ in shapes]
+    Ns = [n for _, _, n in shapes]
+    F, _, _ = make_macro_points(sum(Ns), 3300, amp=0.05)
+    th_star, _ = perturbed_theta(3301)
+    th = solve.theta_dev(THETA_REF)
+
+    def adjoint(cls_counts, Fp, target):
+        plan = make_plan(dev, cls_counts, precision=precision, split=split, refine=refine)
+        st = solve.newton(plan, th, solve.points_to_soa(Fp), tol=1e-12)
+        g = 2.0 * (st.Pbar - solve.points_to_soa(target))
+        gF = plan.zeros_points(9)
+        gth = torch.zeros(4, dtype=torch.float64, device="cuda")
+        plan.backward(th, st.a, g.contiguous(), gF, gth, st.status)
+        torch.cuda.synchronize()
+        assert int(st.status.max().item()) == 0
+        plan.close()
+        return gF.cpu(), gth.cpu().numpy()
+
+    targets, refs, first = [], [], 0
+    for c, n in zip(cls, Ns):
+        Fc = F[first:first + n]
+        tgt = orc.newton(c, th_star, Fc, tol=1e-14)["Pbar"]
+        conv = orc.newton(c, THETA_REF, Fc, tol=1e-14)
+        refs.append(orc.backward(c, THETA_REF, Fc, conv["a"], 2.0 * (conv["Pbar"] - tgt)))
+        targets.append(tgt)
+        first += n
+    gF, gth = adjoint(list(zip(cls, Ns)), F, np.concatenate(targets))
+    egF = rel_err_points(gF.numpy().T, np.concatenate([r["gF"] for r in refs]))
+    gth_ref = sum(r["gtheta"] for r in refs)
+    egt = np.linalg.norm(gth - gth_ref) / np.linalg.norm(gth_ref)
+    print("backward multi", precision, split, refine, "gF", egF.max(), "gtheta", egt, flush=True)
+    bound = 1e-10 if precision == 0 else 1e-5
+    assert egF.max() < bound and egt < bound
+    if precision == 0:
+        first = 0
+        for c, n, tgt in zip(cls, Ns, targets):
+            gF1, _ = adjoint([(c, n)], F[first:first + n], tgt)
+            assert torch.equal(gF[:, first:first + n], gF1)
+            first += n
+
+
 def test_status_flags_and_isolation(dev, orc):
     """Failed points are flagged and do not disturb their neighbours."""
     log_case("status_flags")
