@@ -499,6 +499,12 @@ struct Pk<HROM_MIXED_BF16> {
         return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2bf, h),
                                                __builtin_bit_cast(v2bf, in_sgpr<0xBF800000u>()), x, false);
     }
+    // per-lane form: x - lo(h) where f = (-1, 0), x where f = 0 (f a register)
+    static __device__ __forceinline__ uint32_t g1_factor() { return 0x0000BF80u; }
+    static __device__ __forceinline__ float res_lo_if(uint32_t h, float x, uint32_t f) {
+        typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2bf, h), __builtin_bit_cast(v2bf, f), x, false);
+    }
     static constexpr uint32_t one = 0x3F80u;
     static __device__ __forceinline__ v4f mfma(v4u32 a, v4u32 b, v4f c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
@@ -521,6 +527,11 @@ struct Pk<HROM_MIXED_FP16> {
     static __device__ __forceinline__ float res_hi(uint32_t h, float x) {
         return x - (float)__builtin_bit_cast(_Float16, (unsigned short)(h >> 16));
     }
+    // per-lane form: f = 1.0f (bits) or 0: x - lo(h) or x, one FMA
+    static __device__ __forceinline__ uint32_t g1_factor() { return 0x3F800000u; }
+    static __device__ __forceinline__ float res_lo_if(uint32_t h, float x, uint32_t f) {
+        return fmaf(-(float)__builtin_bit_cast(_Float16, (unsigned short)(h & 0xFFFFu)), __uint_as_float(f), x);
+    }
     static constexpr uint32_t one = 0x3C00u;
     static __device__ __forceinline__ v4f mfma(v4u32 a, v4u32 b, v4f c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a),
@@ -542,9 +553,11 @@ struct Pk<HROM_MIXED_FP16> {
 // its k-slots pair (G parts) x (W or T parts) as
 //   groups 0..2: Gh.Th(a) Gh.Th(b) Gl.Th(a) Gl.Th(b) Gh.Tl(a) Gh.Tl(b) [g1: Gh.Tl(8)] 0
 //   group 3:     same for a = 6, b = 7, then Gh.Th(8) Gl.Th(8)
-// The one term that does not fit its own lane group, Tl(8), moves from group 3
-// to group 1 with a single lane-half swap.  W is built once per ECM point in
-// LDS by the whole wavefront (16 ECM points per round) rather than per lane.
+// The one term that does not fit its own lane group, Tl(8), is formed in
+// group 1 itself: its lanes read the W row of component 8 for their otherwise
+// unused accumulator row 6, so row 6 of T is a copy of component 8 (ignored on
+// output).  W is built once per ECM point in LDS by the whole wavefront (16 ECM
+// points per round) rather than per lane.
 // Record per point: Kaa upper tiles [MA(MA+1)/2][256], KaF tiles [MA][256]
 // (row = mode, column = accumulator row of the component), KFF tile [256].
 constexpr int kCQ = 16;   // ECM points per LDS round
@@ -577,16 +590,16 @@ __device__ __forceinline__ void w_records(const float* w, v4u32* rec) {
     rec[3] = v4u32{h[3], h[3], l[3], h[4]};
 }
 
-// T tile (accumulator rows 4g + e) -> K-step B operand
+// T tile (accumulator rows 4g + e) -> K-step B operand.  Row 4g + 2 is
+// component 8 in groups 1 and 3 (zero in groups 0, 2); g1 = 1 in group 1:
+// its last dword becomes (Tl(8), Tl(8)), that of group 3 (Th(8), Th(8)).
 template <int PREC, bool SPLIT>
-__device__ __forceinline__ v4u32 t_operand(v4f T) {
+__device__ __forceinline__ v4u32 t_operand(v4f T, uint32_t g1) {
     const uint32_t hA = Pk<PREC>::pack(T[0], T[1]);
     const uint32_t lA = SPLIT ? Pk<PREC>::pack(Pk<PREC>::res_lo(hA, T[0]), Pk<PREC>::res_hi(hA, T[1])) : 0u;
-    const uint32_t hB = Pk<PREC>::pack(T[2], T[2]);
-    const uint32_t lB = SPLIT ? Pk<PREC>::pack(Pk<PREC>::res_lo(hB, T[2]), 0.f) : 0u;
-    // lanes 0..31 take lB of lanes 32..63, lanes 32..63 keep hB
-    const auto sw = __builtin_amdgcn_permlane32_swap(lB, hB, false, false);
-    return v4u32{hA, hA, lA, (uint32_t)sw[1]};
+    const uint32_t h8 = Pk<PREC>::pack(T[2], T[2]);
+    const float x8 = SPLIT ? Pk<PREC>::res_lo_if(h8, T[2], g1) : (g1 ? 0.f : T[2]);
+    return v4u32{hA, hA, lA, Pk<PREC>::pack(x8, x8)};
 }
 
 // NP macro points per wavefront (1 or 2): with two, both points' products
@@ -614,7 +627,11 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
     const v4u32* fp = (const v4u32*)A.Fpk + lane;
     // the zero record of every ECM point slot
     if (lane < kCQ) sw[lane * kWR + 36] = v4u32{0u, 0u, 0u, 0u};
-    const int wrec = (pos_comp(c) >= 0) ? 4 * pos_comp(c) + g : 36;   // this lane's record
+    // this lane's record: row c of W (component pos_comp(c); row 6 takes
+    // component 8 as well, see above), else the zero record
+    const int rcomp = (c == 6) ? 8 : pos_comp(c);
+    const int wrec = (rcomp >= 0) ? 4 * rcomp + g : 36;
+    const uint32_t in_g1 = (g == 1) ? Pk<PREC>::g1_factor() : 0u;   // see t_operand
     // identity fragment: G[J][column c] = 1 for J = component of accumulator row c
     v4u32 Ip;
     {
@@ -718,7 +735,7 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
                     for (int tj = ti; tj < MA; tj++, idx++)
                         acc[pp][idx] = Pk<PREC>::mfma(Gp[ti], Bp[pp][tj], acc[pp][idx]);
 #pragma unroll
-                for (int t = 0; t < MA; t++) Bp[pp][t] = t_operand<PREC, SPLIT>(T[t]);
+                for (int t = 0; t < MA; t++) Bp[pp][t] = t_operand<PREC, SPLIT>(T[t], in_g1);
                 // issue order: the 2 MA + 1 products of q, then one Kaa product
                 // of q - 1 after every few VALU instructions of the split
                 __builtin_amdgcn_sched_group_barrier(0x008, 2 * MA + 1, 0);
