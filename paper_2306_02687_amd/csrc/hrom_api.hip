@@ -181,7 +181,7 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
         d.MP = 16 * d.MT;
         d.res_t = (k.m + 9) / 16;
         d.res_c = (k.m + 9) % 16;
-        d.KS = (k.m + 3) / 4;
+        d.KS = 4 * ((k.m + 15) / 16);   // k-steps padded to whole mode tiles (zeros beyond m)
         d.first = k.first;
         d.count = k.count;
         d.off_a = off_a;

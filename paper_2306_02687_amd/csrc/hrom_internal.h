@@ -44,7 +44,7 @@ struct ClusterDev {
     double* Ghat;          // [Qpad][9][MP]  augmented [G | I_9 | 0] (FP64)
     double* GT;            // [Qpad/64][9][m][64]  G, ECM point fastest (FP64)
     double* Gf;            // [9 Qpad/16][KS][64]  A-operand fragments of the kinematics GEMM
-    int KS;                // ceil(m / 4) k-steps of the kinematics GEMM
+    int KS;                // 4 ceil(m / 16) k-steps of the kinematics GEMM (zero beyond m)
     double* w;             // [Qpad] (zero padded)
     int* phase;            // [Qpad]
     uint16_t* Fpk;         // [Qpad][MA][64][8] packed low-precision fragments of G (mixed path)

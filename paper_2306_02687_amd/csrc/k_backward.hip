@@ -78,7 +78,8 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
     auto& sbits = Ls.sbits;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, c = lane & 15;
-    const int m = A.m, KS = A.KS, MP = A.MP;
+    const int m = A.m, MP = A.MP;
+    constexpr int KS = 4 * MA;   // k-steps of the G a GEMM (the plan pads them to whole mode tiles)
     const int np = (int)min((int64_t)PT, A.count - p0);
     if (tid < PT) sbits[tid] = 0;
     for (int e = tid; e < 4 * KS * PT; e += NT) {
@@ -119,11 +120,11 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
             double af[4 * MA];
 #pragma unroll
             for (int s2 = 0; s2 < 4 * MA; s2++)
-                if (s2 < KS) af[s2] = gf[(int64_t)s2 * 64];
+                af[s2] = gf[(int64_t)s2 * 64];
             v4d f0 = v4d{0.0, 0.0, 0.0, 0.0}, f1 = f0, l0 = f0, l1 = f0;
 #pragma unroll
-            for (int s2 = 0; s2 < 4 * MA; s2++)
-                if (s2 < KS) {
+            for (int s2 = 0; s2 < KS; s2++)
+                {
                     f0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][c], f0, 0, 0, 0);
                     f1 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][16 + c], f1, 0, 0, 0);
                     l0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sL[4 * s2 + g][c], l0, 0, 0, 0);
@@ -145,9 +146,8 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
             const bool isF = wave < 2;
             v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int s2 = 0; s2 < 4 * MA; s2++)
-                if (s2 < KS)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(gf[(int64_t)s2 * 64],
+            for (int s2 = 0; s2 < KS; s2++)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(gf[(int64_t)s2 * 64],
                                                                isF ? sA[4 * s2 + g][col] : sL[4 * s2 + g][col],
                                                                acc, 0, 0, 0);
 #pragma unroll

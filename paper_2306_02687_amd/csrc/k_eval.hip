@@ -100,7 +100,8 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
     auto& sbits = L.sbits;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, c = lane & 15;
-    const int m = A.m, KS = A.KS, MP = A.MP;
+    const int m = A.m, MP = A.MP;
+    constexpr int KS = 4 * MA;   // k-steps of the G a GEMM (the plan pads them to whole mode tiles)
     const int np = (int)min((int64_t)PT, A.count - p0);
     if (tid < PT) sbits[tid] = 0;
     __syncthreads();
@@ -146,14 +147,13 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
             double af[4 * MA];
 #pragma unroll
             for (int s2 = 0; s2 < 4 * MA; s2++)
-                if (s2 < KS) af[s2] = gf[(int64_t)s2 * 64];
+                af[s2] = gf[(int64_t)s2 * 64];
             v4d a0 = v4d{0.0, 0.0, 0.0, 0.0}, a1 = a0;
 #pragma unroll
-            for (int s2 = 0; s2 < 4 * MA; s2++)
-                if (s2 < KS) {
-                    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][c], a0, 0, 0, 0);
-                    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][16 + c], a1, 0, 0, 0);
-                }
+            for (int s2 = 0; s2 < KS; s2++) {
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][c], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s2], sA[4 * s2 + g][16 + c], a1, 0, 0, 0);
+            }
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const int row = 16 * rt + g + 4 * e;   // FP64 MFMA accumulator rows interleave
