@@ -130,9 +130,9 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
     double pacc[NPB];
 #pragma unroll
     for (int h = 0; h < NPB; h++) pacc[h] = 0.0;
-    const int klo = (wave * KS) >> 2, khi = ((wave + 1) * KS) >> 2;
+    const int klo = wave * (KS / 4);   // k-range of row tile 8 (waves 0..3)
     const int v = wave & 3;                        // k-range of the residual GEMM
-    const int js = 9 * v, je = 9 * v + 9;
+    const int js = 9 * v;                          // k-steps js .. js + 8
     const int tpar = (NW == 8) ? (wave >> 2) : 0;  // mode-tile parity (eight waves)
     auto holds = [&](int t) { return NW == 4 || (t & 1) == tpar; };
     __syncthreads();
@@ -165,7 +165,9 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
         if (wave < 4) {
             const double* gf = A.Gf + ((int64_t)(rt0 + 8) * KS) * 64 + lane;
             v4d a0 = v4d{0.0, 0.0, 0.0, 0.0}, a1 = a0;
-            for (int s2 = klo; s2 < khi; s2++) {
+#pragma unroll
+            for (int s = 0; s < KS / 4; s++) {   // k-steps klo .. klo + KS / 4 - 1
+                const int s2 = klo + s;
                 const double av = gf[(int64_t)s2 * 64];
                 a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sA[4 * s2 + g][c], a0, 0, 0, 0);
                 a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sA[4 * s2 + g][16 + c], a1, 0, 0, 0);
@@ -233,7 +235,8 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
         }
         __syncthreads();
         // ---- r += G^T (w P): this wave's k-steps of the round, the mode tiles
-        for (int j = js; j < je; j++) {
+        for (int jj = 0; jj < 9; jj++) {
+            const int j = js + jj;
             const double b0 = sWP[4 * j + g][c], b1 = sWP[4 * j + g][16 + c];
             const double* gh = A.Ghat + (int64_t)(q0 * 9 + 4 * j + g) * MP + c;
 #pragma unroll
