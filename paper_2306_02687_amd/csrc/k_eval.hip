@@ -77,7 +77,7 @@ __device__ __forceinline__ void tangent_row(const T* Fi, T c0, T c1, T c2, T* W)
 // two workgroups share a CU and the matrix phases of one overlap the material
 // law of the other.
 constexpr int kKinPT = 32;
-template <int AR>   // rows of the mode amplitudes (>= 4 ceil(m / 4))
+template <int AR>   // rows of the mode amplitudes (>= 16 ceil(m / 16))
 struct KinLds {
     double sA[AR][kKinPT];
     double sF[16 * 9][kKinPT + 1];   // F of the round, then w P in place
