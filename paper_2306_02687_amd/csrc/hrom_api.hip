@@ -410,12 +410,11 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
         ca.y = p.y + c.off_a; ca.X = p.X + 9 * c.off_a;
         ca.Palg = p.Palg; ca.Cr = p.Cr; ca.rnorm = p.rnorm; ca.status = status;
         ca.kscale = mixed(p) ? 1.0f / wscale_for(c.Q) : 1.0f;
-        // SPD path: register-resident elimination up to m = 64 (grouped plans:
-        // one launch above), packed triangle in LDS beyond; non-positive
+        // SPD path: register-resident elimination (grouped plans: clusters with
+        // m <= 64 in one launch above, larger ones one launch each); non-positive
         // pivots finish on the LU path
         int rc = HROM_OK;
-        if (c.m > 64) rc = launch_condense_spd(ca, stream);
-        else if (!p.grouped) rc = launch_condense_reg(ca, stream);
+        if (c.m > 64 || !p.grouped) rc = launch_condense_reg(ca, stream);
         if (rc == HROM_OK) rc = launch_unpack_condense(ca, 2, stream);
         if (rc != HROM_OK) return rc;
     }

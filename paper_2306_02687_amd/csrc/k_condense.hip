@@ -837,7 +837,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
 }
 
 template <typename TT, int MB>
-__global__ void __launch_bounds__(64, 3) k_condense_reg(CondenseArgs A) {
+__global__ void __launch_bounds__(64, MB <= 10 ? 3 : 2) k_condense_reg(CondenseArgs A) {
     condense_reg_body<TT, MB>(A, xcd_order(blockIdx.x, A.count));
 }
 
@@ -883,12 +883,17 @@ static void launch_reg_t(const CondenseArgs& a, hipStream_t s) {
         case 5: hipLaunchKernelGGL((k_condense_reg<TT, 7>), grid, block, 0, s, a); break;
         case 6: hipLaunchKernelGGL((k_condense_reg<TT, 8>), grid, block, 0, s, a); break;
         case 7: hipLaunchKernelGGL((k_condense_reg<TT, 9>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_condense_reg<TT, 10>), grid, block, 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_condense_reg<TT, 10>), grid, block, 0, s, a); break;
+        // m = 65 .. 96: two wavefronts per SIMD
+        case 9: hipLaunchKernelGGL((k_condense_reg<TT, 11>), grid, block, 0, s, a); break;
+        case 10: hipLaunchKernelGGL((k_condense_reg<TT, 12>), grid, block, 0, s, a); break;
+        case 11: hipLaunchKernelGGL((k_condense_reg<TT, 13>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_condense_reg<TT, 14>), grid, block, 0, s, a); break;
     }
 }
 
 int launch_condense_reg(const CondenseArgs& a, hipStream_t s) {
-    if (a.m < 1 || a.m > 64) return HROM_E_UNSUPPORTED;
+    if (a.m < 1 || a.m > 96) return HROM_E_UNSUPPORTED;
     if (a.count == 0) return HROM_OK;
     if (a.mixed) launch_reg_t<float>(a, s);
     else launch_reg_t<double>(a, s);
