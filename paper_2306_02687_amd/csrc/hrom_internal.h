@@ -155,7 +155,6 @@ struct CondenseArgs {
     double* outKFF;        // [81][N]
 };
 int launch_unpack_condense(const CondenseArgs& a, int mode, hipStream_t s);
-int launch_condense_spd(const CondenseArgs& a, hipStream_t s);
 int launch_condense_reg(const CondenseArgs& a, hipStream_t s);   // m <= 64
 
 struct PushArgs {
@@ -326,7 +325,6 @@ struct GroupCall {
 int launch_kin_grouped(int mixed, const GroupCall& g, hipStream_t s);
 int launch_tan_persistent(int prec, bool split, const GroupCall& g, int grid, hipStream_t s);
 int launch_backward_grouped(const GroupCall& g, hipStream_t s);
-int launch_condense_grouped(const GroupCall& g, int max_m, hipStream_t s);
 int launch_condense_reg_grouped(const GroupCall& g, hipStream_t s);   // clusters with m <= 64
 void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);
 void launch_lambda_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);

@@ -3,8 +3,10 @@
 // pivoting when a pivot is not positive, Sec. 4: factorise, never invert),
 // solve y = Kaa^{-1} r and X = Kaa^{-1} KaF, and form
 //   Palg = Pr - KaF^T y,   Cr = KFF - KaF^T X.
-// One wavefront per macro point; the blocks of the point live in LDS.  Rows
-// are distributed over lanes (row i on lane i mod 64).
+// One wavefront per macro point.  The SPD path keeps the point's augmented
+// matrix in registers (condense_reg_body below); points with a non-positive
+// pivot are finished by the full-matrix LU kernel, whose blocks live in LDS
+// with rows distributed over lanes (row i on lane i mod 64).
 #include <hip/hip_runtime.h>
 
 #include "hrom_internal.h"
@@ -426,184 +428,6 @@ void launch_refine_lambda(const RefineArgs& a, hipStream_t s) {
 
 namespace hrom {
 
-// SPD path of the condensation with Kaa held as a packed lower triangle in
-// LDS (row i at offset i (i + 1) / 2), which fits about twice as many macro
-// points per CU as the full-matrix kernel.  Same algorithm: right-looking
-// Cholesky with the trailing update spread over the lanes, forward and
-// backward substitution for [r | KaF], then Palg and Cr.  A point whose
-// Cholesky meets a non-positive pivot is only flagged HROM_PT_NOT_SPD here and
-// finished by k_unpack_condense (mode 2, LU with partial pivoting).
-template <typename TT>
-__device__ void condense_spd_body(const CondenseArgs& A, int64_t pl, double* sm) {
-    const int m = A.m, lane = threadIdx.x;
-    const int g = lane >> 4, c = lane & 15;
-    const int64_t b = A.first + pl;
-    const int MT = A.MT;
-    double* K = sm;                          // packed lower, m (m + 1) / 2
-    double* KaF = K + m * (m + 1) / 2;       // [m][9]
-    double* KFF = KaF + 9 * m;               // [81]
-    double* B = KFF + 81;                    // [m][10]
-    double* Pr = B + 10 * m;                 // [9]
-    double* rv = Pr + 9;                     // [m]
-    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_len(m, MT, sizeof(TT) == 4);
-    const double ks = (double)A.kscale;
-    for (int e = lane; e < m * (m + 1) / 2; e += 64) {
-        // packed lower triangle: row R at offset R (R + 1) / 2
-        int R = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while (R * (R + 1) / 2 > e) R--;
-        while ((R + 1) * (R + 2) / 2 <= e) R++;
-        K[e] = khat_at<TT>(kh, m, MT, R, e - R * (R + 1) / 2) * ks;
-    }
-    for (int e = lane; e < m * 9; e += 64) KaF[e] = khat_at<TT>(kh, m, MT, e / 9, m + e % 9) * ks;
-    for (int e = lane; e < 81; e += 64) KFF[e] = khat_at<TT>(kh, m, MT, m + e / 9, m + e % 9) * ks;
-    for (int i = lane; i < m; i += 64) {
-        const double ri = A.r[(int64_t)i * A.count + pl];
-        rv[i] = ri;
-        B[i * 10] = ri;
-    }
-    if (lane < 9) Pr[lane] = A.Pr[(int64_t)lane * A.N + b];
-    __syncthreads();
-    for (int i = lane; i < m; i += 64)
-#pragma unroll
-        for (int J = 0; J < 9; J++) B[i * 10 + 1 + J] = KaF[i * 9 + J];
-
-    const int lr = lane >> 3, lcol = lane & 7;
-    bool spd = true;
-    for (int j = 0; j < m; j++) {
-        __syncthreads();
-        const double d = K[j * (j + 1) / 2 + j];
-        if (!(d > 0.0)) {
-            spd = false;
-            break;
-        }
-        const double sd = sqrt(d), rsd = 1.0 / sd;
-        __syncthreads();
-        for (int i = j + 1 + lane; i < m; i += 64) K[i * (i + 1) / 2 + j] *= rsd;
-        if (lane == 0) K[j * (j + 1) / 2 + j] = sd;
-        __syncthreads();
-        for (int i = j + 1 + lr; i < m; i += 8) {
-            double* Ki = K + i * (i + 1) / 2;
-            const double lij = Ki[j];
-            for (int k = j + 1 + lcol; k <= i; k += 8) Ki[k] -= lij * K[k * (k + 1) / 2 + j];
-        }
-    }
-    if (!spd) {
-        if (lane == 0) A.status[b] |= HROM_PT_NOT_SPD;
-        return;
-    }
-    // L z = B
-    for (int j = 0; j < m; j++) {
-        __syncthreads();
-        const double rjj = 1.0 / K[j * (j + 1) / 2 + j];
-        double z[10];
-#pragma unroll
-        for (int r = 0; r < 10; r++) z[r] = B[j * 10 + r] * rjj;
-        __syncthreads();
-        for (int i = lane; i < m; i += 64) {
-            if (i == j) {
-#pragma unroll
-                for (int r = 0; r < 10; r++) B[j * 10 + r] = z[r];
-            } else if (i > j) {
-                const double lij = K[i * (i + 1) / 2 + j];
-#pragma unroll
-                for (int r = 0; r < 10; r++) B[i * 10 + r] -= lij * z[r];
-            }
-        }
-    }
-    // L^T x = z
-    for (int j = m - 1; j >= 0; j--) {
-        __syncthreads();
-        const double* Kj = K + j * (j + 1) / 2;
-        const double rjj = 1.0 / Kj[j];
-        double x[10];
-#pragma unroll
-        for (int r = 0; r < 10; r++) x[r] = B[j * 10 + r] * rjj;
-        __syncthreads();
-        for (int i = lane; i < m; i += 64) {
-            if (i == j) {
-#pragma unroll
-                for (int r = 0; r < 10; r++) B[j * 10 + r] = x[r];
-            } else if (i < j) {
-                const double lji = Kj[i];
-#pragma unroll
-                for (int r = 0; r < 10; r++) B[i * 10 + r] -= lji * x[r];
-            }
-        }
-    }
-    __syncthreads();
-    bool fin = true;
-    for (int o = lane; o < 90; o += 64) {
-        const int I = (o < 9) ? o : (o - 9) / 9;
-        const int col = (o < 9) ? 0 : 1 + (o - 9) % 9;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int k = 0;
-        for (; k + 4 <= m; k += 4) {
-            s0 = fma(KaF[k * 9 + I], B[k * 10 + col], s0);
-            s1 = fma(KaF[(k + 1) * 9 + I], B[(k + 1) * 10 + col], s1);
-            s2 = fma(KaF[(k + 2) * 9 + I], B[(k + 2) * 10 + col], s2);
-            s3 = fma(KaF[(k + 3) * 9 + I], B[(k + 3) * 10 + col], s3);
-        }
-        for (; k < m; k++) s0 = fma(KaF[k * 9 + I], B[k * 10 + col], s0);
-        const double dot = (s0 + s1) + (s2 + s3);
-        if (o < 9) {
-            const double v = Pr[o] - dot;
-            A.Palg[(int64_t)o * A.N + b] = v;
-            fin = fin && isfinite(v);
-        } else {
-            const double v = KFF[I * 9 + (col - 1)] - dot;
-            A.Cr[(int64_t)(I * 9 + (col - 1)) * A.N + b] = v;
-            fin = fin && isfinite(v);
-        }
-    }
-    double rr = 0.0;
-    for (int i = lane; i < m; i += 64) {
-        rr += rv[i] * rv[i];
-        A.y[(int64_t)i * A.count + pl] = B[i * 10];
-#pragma unroll
-        for (int J = 0; J < 9; J++) A.X[((int64_t)i * 9 + J) * A.count + pl] = B[i * 10 + 1 + J];
-        if (A.L) {
-            double* Lrow = A.L + (pl * m + i) * (int64_t)m;
-            const double* Ki = K + i * (i + 1) / 2;
-            for (int k = 0; k < m; k++) Lrow[k] = (k <= i) ? Ki[k] : 0.0;
-        }
-    }
-    if (lane == 0) A.piv[pl * m] = -1;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) rr += __shfl_xor(rr, off);
-    const uint64_t bad = __ballot(!fin);
-    if (lane == 0) {
-        A.rnorm[b] = sqrt(rr);
-        if (bad) A.status[b] |= HROM_PT_NONFINITE;
-    }
-}
-
-template <typename TT>
-__global__ void __launch_bounds__(64) k_condense_spd(CondenseArgs A) {
-    extern __shared__ double sm[];
-    condense_spd_body<TT>(A, (int64_t)blockIdx.x, sm);
-}
-
-// every macro point of every cluster in one launch: block b = macro point b
-template <typename TT>
-__global__ void __launch_bounds__(64) k_condense_grouped(GroupCall G) {
-    extern __shared__ double sm[];
-    const int64_t b = blockIdx.x;
-    int c = 0;
-    while (c + 1 < G.ncl && b >= G.cls[c + 1].first) c++;
-    const ClusterGPU& C = G.cls[c];
-    CondenseArgs A;
-    A.m = C.m; A.MT = C.MT; A.res_t = 0; A.res_c = 0; A.mixed = G.mixed;
-    A.first = C.first; A.count = C.count; A.N = G.N;
-    A.Khat = (const char*)G.Khat + sizeof(TT) * (size_t)C.ws_khat;
-    A.r = G.r + C.off_a; A.Pr = G.Pr;
-    A.L = G.L ? G.L + C.ws_L : nullptr; A.piv = G.piv + C.off_a;
-    A.y = G.y + C.off_a; A.X = G.X + 9 * C.off_a;
-    A.Palg = G.Palg; A.Cr = G.Cr; A.rnorm = G.rnorm; A.status = G.status;
-    A.kscale = 1.0f / C.wscale;
-    A.outKaa = A.outKaF = A.outKFF = nullptr;
-    condense_spd_body<TT>(A, b - C.first, sm);
-}
-
 // ---------------------------------------------------------------------------
 // Register-resident condensation (m <= 64): one wavefront per macro point.
 //
@@ -908,56 +732,6 @@ int launch_condense_reg_grouped(const GroupCall& g, hipStream_t s) {
     return HROM_OK;
 }
 
-int launch_condense_grouped(const GroupCall& g, int max_m, hipStream_t s) {
-    const size_t bytes = sizeof(double) *
-        ((size_t)max_m * (max_m + 1) / 2 + 9 * max_m + 81 + 10 * max_m + 9 + max_m);
-    if (bytes > 160 * 1024) return HROM_E_UNSUPPORTED;
-    const dim3 grid((unsigned)g.N), block(64);
-    if (g.mixed) {
-        static bool attr = false;
-        if (!attr) {
-            hipFuncSetAttribute((const void*)k_condense_grouped<float>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
-        }
-        hipLaunchKernelGGL(k_condense_grouped<float>, grid, block, bytes, s, g);
-    } else {
-        static bool attr = false;
-        if (!attr) {
-            hipFuncSetAttribute((const void*)k_condense_grouped<double>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
-        }
-        hipLaunchKernelGGL(k_condense_grouped<double>, grid, block, bytes, s, g);
-    }
-    return HROM_OK;
-}
-
-int launch_condense_spd(const CondenseArgs& a, hipStream_t s) {
-    const int m = a.m;
-    const size_t bytes = sizeof(double) * ((size_t)m * (m + 1) / 2 + 9 * m + 81 + 10 * m + 9 + m);
-    if (bytes > 160 * 1024) return HROM_E_UNSUPPORTED;
-    const dim3 grid((unsigned)a.count), block(64);
-    if (a.mixed) {
-        static bool attr = false;
-        if (!attr) {
-            hipFuncSetAttribute((const void*)k_condense_spd<float>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
-        }
-        hipLaunchKernelGGL(k_condense_spd<float>, grid, block, bytes, s, a);
-    } else {
-        static bool attr = false;
-        if (!attr) {
-            hipFuncSetAttribute((const void*)k_condense_spd<double>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
-        }
-        hipLaunchKernelGGL(k_condense_spd<double>, grid, block, bytes, s, a);
-    }
-    return HROM_OK;
-}
-
 }  // namespace hrom
 
 namespace hrom {
@@ -966,10 +740,6 @@ void set_kernel_attributes() {
     const int lim = 160 * 1024;
     hipFuncSetAttribute((const void*)k_unpack_condense<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void*)k_unpack_condense<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void*)k_condense_spd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void*)k_condense_spd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void*)k_condense_grouped<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void*)k_condense_grouped<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void*)k_refine_lambda, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 }  // namespace hrom
