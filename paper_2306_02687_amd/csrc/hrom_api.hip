@@ -47,7 +47,7 @@ void free_plan(Plan& p) {
     dfree(p.piv); dfree(p.y); dfree(p.X); dfree(p.Palg); dfree(p.Cr); dfree(p.S);
     dfree(p.rnorm); dfree(p.dU); dfree(p.gr); dfree(p.Lam); dfree(p.lam); dfree(p.rho);
     dfree(p.hr); dfree(p.gth);
-    dfree(p.cls_dev); dfree(p.items_kin); dfree(p.items_bw); dfree(p.items_tan); dfree(p.counter);
+    dfree(p.cls_dev); dfree(p.items_kin); dfree(p.items_bw); dfree(p.items_tan); dfree(p.items_tan2); dfree(p.counter);
 }
 
 int hip_status() { return hipGetLastError() == hipSuccess ? HROM_OK : HROM_E_HIP; }
@@ -76,7 +76,7 @@ int upload(T** dst, const std::vector<T>& v) {
 int build_groups(Plan& p) {
     p.grouped = p.ncl > 1;
     std::vector<ClusterGPU> cg;
-    std::vector<WorkItem> kin, bw, tan;
+    std::vector<WorkItem> kin, bw, tan, tan2;
     p.max_m = 0;
     for (int c = 0; c < p.ncl; c++) {
         const ClusterDev& d = p.cl[c];
@@ -90,7 +90,12 @@ int build_groups(Plan& p) {
         p.max_m = std::max(p.max_m, d.m);
         for (int64_t u = 0; u < (d.count + 31) / 32; u++) kin.push_back(WorkItem{c, (int)u});
         for (int64_t u = 0; u < (d.count + 31) / 32; u++) bw.push_back(WorkItem{c, (int)u});
-        for (int64_t u = 0; u < (d.count + 3) / 4; u++) tan.push_back(WorkItem{c, (int)u});
+        // mixed plans: clusters with m <= 64 go to a launch of 8-point tiles,
+        // two points per wavefront
+        if (mixed(p) && d.m <= 64)
+            for (int64_t u = 0; u < (d.count + 7) / 8; u++) tan2.push_back(WorkItem{c, (int)u});
+        else
+            for (int64_t u = 0; u < (d.count + 3) / 4; u++) tan.push_back(WorkItem{c, (int)u});
     }
     // most expensive tiles first: kinematics ~ m Q, tangent ~ MT^2 Q
     auto cost_kin = [&](const WorkItem& w) { return (double)p.cl[w.c].m * p.cl[w.c].Q; };
@@ -104,9 +109,12 @@ int build_groups(Plan& p) {
                      [&](const WorkItem& x, const WorkItem& y) { return cost_kin(x) > cost_kin(y); });
     std::stable_sort(tan.begin(), tan.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost_tan(x) > cost_tan(y); });
+    std::stable_sort(tan2.begin(), tan2.end(),
+                     [&](const WorkItem& x, const WorkItem& y) { return cost_tan(x) > cost_tan(y); });
     p.n_kin = (int)kin.size();
     p.n_bw = (int)bw.size();
     p.n_tan = (int)tan.size();
+    p.n_tan2 = (int)tan2.size();
     int ncu = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, p.device) == hipSuccess && prop.multiProcessorCount > 0)
@@ -116,6 +124,7 @@ int build_groups(Plan& p) {
     if (rc == HROM_OK) rc = upload(&p.items_kin, kin);
     if (rc == HROM_OK) rc = upload(&p.items_bw, bw);
     if (rc == HROM_OK) rc = upload(&p.items_tan, tan);
+    if (rc == HROM_OK) rc = upload(&p.items_tan2, tan2);
     if (rc == HROM_OK) rc = dalloc(&p.counter, 1);
     return rc;
 }
@@ -334,10 +343,15 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         g.r = p.r; g.Pr = p.Pr; g.status = status;
         g.items = p.items_kin; g.nitems = p.n_kin;
         int rc = launch_kin_grouped(mixed(p) ? 1 : 0, g, stream);
-        g.items = p.items_tan; g.nitems = p.n_tan;
         if (p.profile) (void)hipEventRecord(p.ev_tan[0], stream);
-        if (rc == HROM_OK)
+        if (rc == HROM_OK && p.n_tan > 0) {
+            g.items = p.items_tan; g.nitems = p.n_tan; g.counter = p.counter;
             rc = launch_tan_persistent(p.prec, (p.flags & HROM_SPLIT) != 0, g, p.persistent_grid, stream);
+        }
+        if (rc == HROM_OK && p.n_tan2 > 0) {
+            g.items = p.items_tan2; g.nitems = p.n_tan2;
+            rc = launch_tan_tiles8(p.prec, (p.flags & HROM_SPLIT) != 0, g, stream);
+        }
         if (p.profile) (void)hipEventRecord(p.ev_tan[1], stream);
         if (rc != HROM_OK) return rc;
     }

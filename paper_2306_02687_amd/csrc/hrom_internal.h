@@ -95,9 +95,10 @@ struct Plan {
     ClusterGPU* cls_dev = nullptr;
     WorkItem* items_kin = nullptr;   // 32-point tiles (kinematics), decreasing cost
     WorkItem* items_bw = nullptr;    // 32-point tiles (adjoint), decreasing cost
-    WorkItem* items_tan = nullptr;   // 4-point tiles, decreasing cost
-    int n_kin = 0, n_bw = 0, n_tan = 0;
-    int* counter = nullptr;
+    WorkItem* items_tan = nullptr;   // 4-point tiles, decreasing cost (mixed plans: m > 64)
+    WorkItem* items_tan2 = nullptr;  // mixed plans: 8-point tiles of the clusters with m <= 64
+    int n_kin = 0, n_bw = 0, n_tan = 0, n_tan2 = 0;
+    int* counter = nullptr;          // work-queue head of the persistent tangent launch
 };
 
 // ---------------------------------------------------------------- kernels
@@ -282,7 +283,7 @@ struct ClusterGPU {
 struct WorkItem {
     int c;      // cluster
     int unit;   // tile of the cluster (32 points for the kinematics and the
-                // adjoint, 4 for the tangent contraction)
+                // adjoint, 4 or 8 for the tangent contraction)
 };
 
 struct GroupCall {
@@ -324,6 +325,7 @@ struct GroupCall {
 
 int launch_kin_grouped(int mixed, const GroupCall& g, hipStream_t s);
 int launch_tan_persistent(int prec, bool split, const GroupCall& g, int grid, hipStream_t s);
+int launch_tan_tiles8(int prec, bool split, const GroupCall& g, hipStream_t s);
 int launch_backward_grouped(const GroupCall& g, hipStream_t s);
 int launch_condense_reg_grouped(const GroupCall& g, hipStream_t s);   // clusters with m <= 64
 void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);

@@ -936,6 +936,33 @@ __global__ void __launch_bounds__(256, 1) k_tan_persistent(GroupCall G) {
     }
 }
 
+// Mixed clusters with m <= 64: one workgroup per 8-point tile (two macro
+// points per wavefront, two wavefronts per SIMD); the tiles are ordered by
+// decreasing cost, so the dispatcher hands out the expensive ones first
+template <int PREC, bool SPLIT>
+__global__ void __launch_bounds__(256, 2) k_tan_tiles8(GroupCall G) {
+    __shared__ v4u32 s_w[4][kCQ * kWR];
+    const WorkItem w = G.items[blockIdx.x];
+    const int64_t pl0 = (int64_t)w.unit * 8;
+    const EvalArgs A = group_eval_args(G, w.c, sizeof(float));
+    switch ((A.m + 15) / 16) {
+        case 1: tan_mixed_body<1, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
+        case 2: tan_mixed_body<2, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
+        case 3: tan_mixed_body<3, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
+        default: tan_mixed_body<4, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
+    }
+}
+
+int launch_tan_tiles8(int prec, bool split, const GroupCall& g, hipStream_t s) {
+    if (prec == HROM_FP64) return HROM_E_INVALID;
+    const dim3 gr(g.nitems), bl(256);
+    if (prec == HROM_MIXED_BF16 && split) hipLaunchKernelGGL((k_tan_tiles8<HROM_MIXED_BF16, true>), gr, bl, 0, s, g);
+    else if (prec == HROM_MIXED_BF16) hipLaunchKernelGGL((k_tan_tiles8<HROM_MIXED_BF16, false>), gr, bl, 0, s, g);
+    else if (split) hipLaunchKernelGGL((k_tan_tiles8<HROM_MIXED_FP16, true>), gr, bl, 0, s, g);
+    else hipLaunchKernelGGL((k_tan_tiles8<HROM_MIXED_FP16, false>), gr, bl, 0, s, g);
+    return HROM_OK;
+}
+
 int launch_tan_persistent(int prec, bool split, const GroupCall& g, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, g.counter);
     const dim3 gr(grid), bl(256);
