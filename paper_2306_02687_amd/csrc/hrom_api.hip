@@ -405,14 +405,6 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
     Plan& p = plan->p;
     if (p.stage < 1) return HROM_E_ORDER;
     const size_t tsz = mixed(p) ? sizeof(float) : sizeof(double);
-    if (p.grouped) {
-        GroupCall g = group_call(p);
-        g.Khat = p.Khat; g.r = p.r; g.Pr = p.Pr; g.status = status;
-        g.L = refine(p) ? p.L : nullptr; g.piv = p.piv; g.y = p.y; g.X = p.X;
-        g.Palg = p.Palg; g.Cr = p.Cr; g.rnorm = p.rnorm;
-        const int rc = launch_condense_reg_grouped(g, stream);
-        if (rc != HROM_OK) return rc;
-    }
     for (const auto& c : p.cl) {
         CondenseArgs ca{};
         ca.m = c.m; ca.MT = c.MT; ca.res_t = c.res_t; ca.res_c = c.res_c; ca.mixed = mixed(p);
@@ -424,11 +416,10 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
         ca.y = p.y + c.off_a; ca.X = p.X + 9 * c.off_a;
         ca.Palg = p.Palg; ca.Cr = p.Cr; ca.rnorm = p.rnorm; ca.status = status;
         ca.kscale = mixed(p) ? 1.0f / wscale_for(c.Q) : 1.0f;
-        // SPD path: register-resident elimination (grouped plans: clusters with
-        // m <= 64 in one launch above, larger ones one launch each); non-positive
+        // SPD path: register-resident elimination, one launch per cluster so
+        // that each runs at the occupancy its mode count allows; non-positive
         // pivots finish on the LU path
-        int rc = HROM_OK;
-        if (c.m > 64 || !p.grouped) rc = launch_condense_reg(ca, stream);
+        int rc = launch_condense_reg(ca, stream);
         if (rc == HROM_OK) rc = launch_unpack_condense(ca, 2, stream);
         if (rc != HROM_OK) return rc;
     }

@@ -156,7 +156,7 @@ struct CondenseArgs {
     double* outKFF;        // [81][N]
 };
 int launch_unpack_condense(const CondenseArgs& a, int mode, hipStream_t s);
-int launch_condense_reg(const CondenseArgs& a, hipStream_t s);   // m <= 64
+int launch_condense_reg(const CondenseArgs& a, hipStream_t s);   // m <= 96
 
 struct PushArgs {
     int64_t N;
@@ -327,7 +327,6 @@ int launch_kin_grouped(int mixed, const GroupCall& g, hipStream_t s);
 int launch_tan_persistent(int prec, bool split, const GroupCall& g, int grid, hipStream_t s);
 int launch_tan_tiles8(int prec, bool split, const GroupCall& g, hipStream_t s);
 int launch_backward_grouped(const GroupCall& g, hipStream_t s);
-int launch_condense_reg_grouped(const GroupCall& g, hipStream_t s);   // clusters with m <= 64
 void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);
 void launch_lambda_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);
 void set_kernel_attributes();

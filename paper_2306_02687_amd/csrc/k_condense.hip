@@ -429,7 +429,7 @@ void launch_refine_lambda(const RefineArgs& a, hipStream_t s) {
 namespace hrom {
 
 // ---------------------------------------------------------------------------
-// Register-resident condensation (m <= 64): one wavefront per macro point.
+// Register-resident condensation (m <= 96): one wavefront per macro point.
 //
 // The symmetric augmented matrix
 //     M = [[Kaa, KaF, r], [KaF^T, KFF, Pr], [r^T, Pr^T, 0]]
@@ -665,37 +665,6 @@ __global__ void __launch_bounds__(64, MB <= 10 ? 3 : 2) k_condense_reg(CondenseA
     condense_reg_body<TT, MB>(A, xcd_order(blockIdx.x, A.count));
 }
 
-// every macro point of every cluster with m <= 64 in one launch
-template <typename TT>
-__global__ void __launch_bounds__(64, 2) k_condense_reg_grouped(GroupCall G) {
-    const int64_t b = xcd_order(blockIdx.x, G.N);
-    int c = 0;
-    while (c + 1 < G.ncl && b >= G.cls[c + 1].first) c++;
-    const ClusterGPU& C = G.cls[c];
-    if (C.m > 64) return;
-    CondenseArgs A;
-    A.m = C.m; A.MT = C.MT; A.res_t = 0; A.res_c = 0; A.mixed = G.mixed;
-    A.first = C.first; A.count = C.count; A.N = G.N;
-    A.Khat = (const char*)G.Khat + sizeof(TT) * (size_t)C.ws_khat;
-    A.r = G.r + C.off_a; A.Pr = G.Pr;
-    A.L = G.L ? G.L + C.ws_L : nullptr; A.piv = G.piv + C.off_a;
-    A.y = G.y + C.off_a; A.X = G.X + 9 * C.off_a;
-    A.Palg = G.Palg; A.Cr = G.Cr; A.rnorm = G.rnorm; A.status = G.status;
-    A.kscale = 1.0f / C.wscale;
-    A.outKaa = A.outKaF = A.outKFF = nullptr;
-    const int64_t pl = b - C.first;
-    switch ((C.m + 7) / 8) {
-        case 1: condense_reg_body<TT, 3>(A, pl); break;
-        case 2: condense_reg_body<TT, 4>(A, pl); break;
-        case 3: condense_reg_body<TT, 5>(A, pl); break;
-        case 4: condense_reg_body<TT, 6>(A, pl); break;
-        case 5: condense_reg_body<TT, 7>(A, pl); break;
-        case 6: condense_reg_body<TT, 8>(A, pl); break;
-        case 7: condense_reg_body<TT, 9>(A, pl); break;
-        default: condense_reg_body<TT, 10>(A, pl); break;
-    }
-}
-
 template <typename TT>
 static void launch_reg_t(const CondenseArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)a.count), block(64);
@@ -721,14 +690,6 @@ int launch_condense_reg(const CondenseArgs& a, hipStream_t s) {
     if (a.count == 0) return HROM_OK;
     if (a.mixed) launch_reg_t<float>(a, s);
     else launch_reg_t<double>(a, s);
-    return HROM_OK;
-}
-
-int launch_condense_reg_grouped(const GroupCall& g, hipStream_t s) {
-    if (g.N == 0) return HROM_OK;
-    const dim3 grid((unsigned)g.N), block(64);
-    if (g.mixed) hipLaunchKernelGGL(k_condense_reg_grouped<float>, grid, block, 0, s, g);
-    else hipLaunchKernelGGL(k_condense_reg_grouped<double>, grid, block, 0, s, g);
     return HROM_OK;
 }
 
