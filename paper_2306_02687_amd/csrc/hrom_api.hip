@@ -47,7 +47,7 @@ void free_plan(Plan& p) {
     dfree(p.piv); dfree(p.y); dfree(p.X); dfree(p.Palg); dfree(p.Cr); dfree(p.S);
     dfree(p.rnorm); dfree(p.dU); dfree(p.gr); dfree(p.Lam); dfree(p.lam); dfree(p.rho);
     dfree(p.hr); dfree(p.gth);
-    dfree(p.cls_dev); dfree(p.items_kin); dfree(p.items_bw); dfree(p.items_tan); dfree(p.items_tan2); dfree(p.counter);
+    dfree(p.cls_dev); dfree(p.items_tan); dfree(p.items_tan2); dfree(p.counter);
 }
 
 int hip_status() { return hipGetLastError() == hipSuccess ? HROM_OK : HROM_E_HIP; }
@@ -72,11 +72,11 @@ int upload(T** dst, const std::vector<T>& v) {
     return rc;
 }
 
-// Device cluster table and the cost-sorted work queues of the grouped launches.
+// Device cluster table and the cost-sorted work queues of the tangent launches.
 int build_groups(Plan& p) {
     p.grouped = p.ncl > 1;
     std::vector<ClusterGPU> cg;
-    std::vector<WorkItem> kin, bw, tan, tan2;
+    std::vector<WorkItem> tan, tan2;
     p.max_m = 0;
     for (int c = 0; c < p.ncl; c++) {
         const ClusterDev& d = p.cl[c];
@@ -88,8 +88,6 @@ int build_groups(Plan& p) {
         g.wscale = mixed(p) ? wscale_for(d.Q) : 1.0f;
         cg.push_back(g);
         p.max_m = std::max(p.max_m, d.m);
-        for (int64_t u = 0; u < (d.count + 31) / 32; u++) kin.push_back(WorkItem{c, (int)u});
-        for (int64_t u = 0; u < (d.count + 31) / 32; u++) bw.push_back(WorkItem{c, (int)u});
         // mixed plans: clusters with m <= 64 go to a launch of 8-point tiles,
         // two points per wavefront
         if (mixed(p) && d.m <= 64)
@@ -97,22 +95,15 @@ int build_groups(Plan& p) {
         else
             for (int64_t u = 0; u < (d.count + 3) / 4; u++) tan.push_back(WorkItem{c, (int)u});
     }
-    // most expensive tiles first: kinematics ~ m Q, tangent ~ MT^2 Q
-    auto cost_kin = [&](const WorkItem& w) { return (double)p.cl[w.c].m * p.cl[w.c].Q; };
+    // most expensive tiles first: tangent ~ MT^2 Q
     auto cost_tan = [&](const WorkItem& w) {
         const double mt = p.cl[w.c].MT;
         return mt * (mt + 1) * p.cl[w.c].Q;
     };
-    std::stable_sort(kin.begin(), kin.end(),
-                     [&](const WorkItem& x, const WorkItem& y) { return cost_kin(x) > cost_kin(y); });
-    std::stable_sort(bw.begin(), bw.end(),
-                     [&](const WorkItem& x, const WorkItem& y) { return cost_kin(x) > cost_kin(y); });
     std::stable_sort(tan.begin(), tan.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost_tan(x) > cost_tan(y); });
     std::stable_sort(tan2.begin(), tan2.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost_tan(x) > cost_tan(y); });
-    p.n_kin = (int)kin.size();
-    p.n_bw = (int)bw.size();
     p.n_tan = (int)tan.size();
     p.n_tan2 = (int)tan2.size();
     int ncu = 256;
@@ -121,8 +112,6 @@ int build_groups(Plan& p) {
         ncu = prop.multiProcessorCount;
     p.persistent_grid = std::min(p.n_tan, 2 * ncu);
     int rc = upload(&p.cls_dev, cg);
-    if (rc == HROM_OK) rc = upload(&p.items_kin, kin);
-    if (rc == HROM_OK) rc = upload(&p.items_bw, bw);
     if (rc == HROM_OK) rc = upload(&p.items_tan, tan);
     if (rc == HROM_OK) rc = upload(&p.items_tan2, tan2);
     if (rc == HROM_OK) rc = dalloc(&p.counter, 1);
@@ -135,8 +124,6 @@ GroupCall group_call(const Plan& p) {
     g.ncl = p.ncl;
     g.N = p.N;
     g.counter = p.counter;
-    g.mixed = mixed(p) ? 1 : 0;
-    g.objective = (p.flags & HROM_OBJECTIVE) ? 1 : 0;
     return g;
 }
 
@@ -337,26 +324,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
     PointArgs pa{p.N, (p.flags & HROM_OBJECTIVE) ? 1 : 0, Fbar, p.Fr, p.polar, status};
     launch_prepare(pa, stream);
     const size_t tsz = mixed(p) ? sizeof(float) : sizeof(double);
-    if (p.grouped) {
-        GroupCall g = group_call(p);
-        g.theta = theta; g.Fr = p.Fr; g.a = a; g.qs = p.qs; g.Khat = p.Khat;
-        g.r = p.r; g.Pr = p.Pr; g.status = status;
-        g.items = p.items_kin; g.nitems = p.n_kin;
-        int rc = launch_kin_grouped(mixed(p) ? 1 : 0, g, stream);
-        if (p.profile) (void)hipEventRecord(p.ev_tan[0], stream);
-        if (rc == HROM_OK && p.n_tan > 0) {
-            g.items = p.items_tan; g.nitems = p.n_tan; g.counter = p.counter;
-            rc = launch_tan_persistent(p.prec, (p.flags & HROM_SPLIT) != 0, g, p.persistent_grid, stream);
-        }
-        if (rc == HROM_OK && p.n_tan2 > 0) {
-            g.items = p.items_tan2; g.nitems = p.n_tan2;
-            rc = launch_tan_tiles8(p.prec, (p.flags & HROM_SPLIT) != 0, g, stream);
-        }
-        if (p.profile) (void)hipEventRecord(p.ev_tan[1], stream);
-        if (rc != HROM_OK) return rc;
-    }
     for (const auto& c : p.cl) {
-        if (p.grouped) break;
         EvalArgs e{};
         e.m = c.m; e.Q = c.Q; e.Qpad = c.Qpad; e.MP = c.MP; e.MT = c.MT; e.KS = c.KS;
         e.first = c.first; e.count = c.count; e.N = p.N;
@@ -369,12 +337,30 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         e.status = status;
         e.wscale = wscale_for(c.Q);
         int rc = launch_kin(mixed(p) ? 1 : 0, e, stream);
+        if (p.grouped) { if (rc != HROM_OK) return rc; continue; }
         // single-cluster plans: the events bracket the (only) tangent launch
         if (p.profile && p.ncl == 1) (void)hipEventRecord(p.ev_tan[0], stream);
         if (rc == HROM_OK)
             rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, c.variant, e, stream)
                           : launch_eval_f64(c.MT, c.variant, e, stream);
         if (p.profile && p.ncl == 1) (void)hipEventRecord(p.ev_tan[1], stream);
+        if (rc != HROM_OK) return rc;
+    }
+    if (p.grouped) {
+        GroupCall g = group_call(p);
+        g.theta = theta; g.Fr = p.Fr; g.a = a; g.qs = p.qs; g.Khat = p.Khat;
+        g.r = p.r; g.Pr = p.Pr; g.status = status;
+        int rc = HROM_OK;
+        if (p.profile) (void)hipEventRecord(p.ev_tan[0], stream);
+        if (rc == HROM_OK && p.n_tan > 0) {
+            g.items = p.items_tan; g.nitems = p.n_tan; g.counter = p.counter;
+            rc = launch_tan_persistent(p.prec, (p.flags & HROM_SPLIT) != 0, g, p.persistent_grid, stream);
+        }
+        if (rc == HROM_OK && p.n_tan2 > 0) {
+            g.items = p.items_tan2; g.nitems = p.n_tan2;
+            rc = launch_tan_tiles8(p.prec, (p.flags & HROM_SPLIT) != 0, g, stream);
+        }
+        if (p.profile) (void)hipEventRecord(p.ev_tan[1], stream);
         if (rc != HROM_OK) return rc;
     }
     if (Kaa || KaF || KFF) {
@@ -505,27 +491,6 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
     const int objective = (p.flags & HROM_OBJECTIVE) ? 1 : 0;
     BwPointArgs bp{p.N, objective, p.polar, p.S, gPbar, p.gr, p.Lam, p.hr, gFbar};
     launch_bw_pullback(bp, stream);
-    if (p.grouped) {
-        GroupCall g = group_call(p);
-        g.theta = theta; g.Fr = p.Fr; g.a = a; g.lam = p.lam; g.gr = p.gr; g.hr = p.hr;
-        g.gth = p.gth; g.rho = p.rho; g.status = status; g.X = p.X;
-        g.items = p.items_bw; g.nitems = p.n_bw;
-        launch_lambda_grouped(g, p.a_len, stream);
-        if (refine(p)) {
-            g.with_rho = 1;
-            launch_backward_grouped(g, stream);
-            for (const auto& c : p.cl) {
-                RefineArgs ra{c.m, c.first, c.count, p.L + c.ws_L, p.piv + c.off_a, status,
-                              p.rho + c.off_a, p.lam + c.off_a};
-                launch_refine_lambda(ra, stream);
-            }
-        }
-        g.with_rho = 0;
-        launch_backward_grouped(g, stream);
-        launch_bw_pushforward(bp, stream);
-        launch_reduce_theta(p.N, p.gth, gtheta, stream);
-        return hip_status();
-    }
     for (const auto& c : p.cl) {
         LambdaArgs la{c.m, c.first, c.count, p.N, p.X + 9 * c.off_a, p.gr, p.lam + c.off_a};
         launch_lambda(la, stream);

@@ -93,11 +93,9 @@ struct Plan {
     int max_m = 0;
     int persistent_grid = 512;
     ClusterGPU* cls_dev = nullptr;
-    WorkItem* items_kin = nullptr;   // 32-point tiles (kinematics), decreasing cost
-    WorkItem* items_bw = nullptr;    // 32-point tiles (adjoint), decreasing cost
     WorkItem* items_tan = nullptr;   // 4-point tiles, decreasing cost (mixed plans: m > 64)
     WorkItem* items_tan2 = nullptr;  // mixed plans: 8-point tiles of the clusters with m <= 64
-    int n_kin = 0, n_bw = 0, n_tan = 0, n_tan2 = 0;
+    int n_tan = 0, n_tan2 = 0;
     int* counter = nullptr;          // work-queue head of the persistent tangent launch
 };
 
@@ -266,9 +264,12 @@ void launch_build_layouts(const LayoutArgs& a, hipStream_t s);
 
 
 // ---------------------------------------------------------------- grouped launches
-// Several RVE clusters in one launch: every kernel body runs on one work item
-// (cluster c, tile `unit` of that cluster); the per-cluster constants live in
-// a device array built at plan creation, the per-call pointers in GroupCall.
+// Several RVE clusters in one launch (the tangent contraction and the
+// monolithic update; the kinematics, the condensation and the adjoint launch
+// once per cluster, each at the occupancy its mode count allows): a kernel
+// body runs on one work item (cluster c, tile `unit` of that cluster); the
+// per-cluster constants live in a device array built at plan creation, the
+// per-call pointers in GroupCall.
 struct ClusterGPU {
     int m, Q, Qpad, MP, MT, KS;
     int64_t first, count, off_a, ws_qs, ws_khat, ws_L;
@@ -301,34 +302,19 @@ struct GroupCall {
     double* r;
     double* Pr;
     int* status;
-    // adjoint
-    const double* lam;
-    const double* gr;
-    double* hr;
-    double* gth;
-    double* rho;
-    int mixed, objective, with_rho;
-    // condensation
-    double* L;
-    int* piv;
+    // update
     double* y;
     double* X;
-    double* Palg;
-    double* Cr;
     double* rnorm;
-    // update
     const double* dFbar;
     const double* dU;
     double tol;
     double* a_out;
 };
 
-int launch_kin_grouped(int mixed, const GroupCall& g, hipStream_t s);
 int launch_tan_persistent(int prec, bool split, const GroupCall& g, int grid, hipStream_t s);
 int launch_tan_tiles8(int prec, bool split, const GroupCall& g, hipStream_t s);
-int launch_backward_grouped(const GroupCall& g, hipStream_t s);
 void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);
-void launch_lambda_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);
 void set_kernel_attributes();
 
 }  // namespace hrom

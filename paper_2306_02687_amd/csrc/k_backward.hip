@@ -299,52 +299,12 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
     if (tid < np && sbits[tid]) A.status[A.first + p0 + tid] |= HROM_PT_JNONPOS;
 }
 
-template <bool MIXED>
-using BwLdsMax = BwLds<16 * ((kMaxModes + 15) / 16), typename std::conditional<MIXED, float, double>::type>;
-
-template <bool MIXED, bool RHO>
-__device__ void bw_dispatch(const BackwardArgs& A, int64_t p0, BwLdsMax<MIXED>& Ls) {
-    switch ((A.m + 15) / 16) {
-        case 1: bw_body<1, MIXED, RHO, 8>(A, p0, Ls); break;
-        case 2: bw_body<2, MIXED, RHO, 8>(A, p0, Ls); break;
-        case 3: bw_body<3, MIXED, RHO, 8>(A, p0, Ls); break;
-        case 4: bw_body<4, MIXED, RHO, 8>(A, p0, Ls); break;
-        case 5: bw_body<5, MIXED, RHO, 8>(A, p0, Ls); break;
-        default: bw_body<6, MIXED, RHO, 8>(A, p0, Ls); break;
-    }
-}
-
-// single cluster: the mixed path with four wavefronts (two workgroups per CU),
-// the FP64 path with eight
+// one launch per cluster: the mixed path with four wavefronts (two workgroups
+// per CU), the FP64 path with eight
 template <int MA, bool MIXED, bool RHO>
 __global__ void __launch_bounds__(MIXED ? 256 : 512, MIXED ? 2 : 1) k_backward_b(BackwardArgs A) {
     __shared__ BwLds<16 * MA, typename std::conditional<MIXED, float, double>::type> Ls;
     bw_body<MA, MIXED, RHO, MIXED ? 4 : 8>(A, (int64_t)blockIdx.x * kBwPT, Ls);
-}
-
-// adjoint re-evaluation of every cluster in one launch (32-point tiles)
-template <bool MIXED, bool RHO>
-__global__ void __launch_bounds__(512) k_backward_grouped(GroupCall G) {
-    __shared__ BwLdsMax<MIXED> Ls;
-    const WorkItem w = G.items[blockIdx.x];
-    const ClusterGPU& C = G.cls[w.c];
-    BackwardArgs A;
-    A.m = C.m; A.Q = C.Q; A.Qpad = C.Qpad; A.mixed = G.mixed; A.objective = G.objective;
-    A.with_rho = G.with_rho; A.first = C.first; A.count = C.count; A.N = G.N;
-    A.GT = nullptr; A.Ghat = C.Ghat; A.Gf = C.Gf; A.MP = C.MP; A.MT = C.MT; A.KS = C.KS;
-    A.w = C.w; A.phase = C.phase; A.theta = G.theta; A.Fr = G.Fr; A.a = G.a + C.off_a;
-    A.lam = G.lam + C.off_a; A.gr = G.gr; A.hr = G.hr; A.gth = G.gth;
-    A.rho = G.rho ? G.rho + C.off_a : nullptr; A.status = G.status;
-    bw_dispatch<MIXED, RHO>(A, (int64_t)w.unit * kBwPT, Ls);
-}
-
-int launch_backward_grouped(const GroupCall& g, hipStream_t s) {
-    const dim3 grid(g.nitems), block(512);
-    if (g.mixed && g.with_rho) hipLaunchKernelGGL((k_backward_grouped<true, true>), grid, block, 0, s, g);
-    else if (g.mixed) hipLaunchKernelGGL((k_backward_grouped<true, false>), grid, block, 0, s, g);
-    else if (g.with_rho) hipLaunchKernelGGL((k_backward_grouped<false, true>), grid, block, 0, s, g);
-    else hipLaunchKernelGGL((k_backward_grouped<false, false>), grid, block, 0, s, g);
-    return HROM_OK;
 }
 
 template <bool MIXED, bool RHO>

@@ -300,20 +300,6 @@ __global__ void __launch_bounds__(256, 2) k_kin(EvalArgs A) {
     kin_body<MIXED, MA, 4>(A, (int64_t)blockIdx.x * kKinPT, L);
 }
 
-using KinLdsMax = KinLds<16 * ((kMaxModes + 15) / 16)>;
-
-template <bool MIXED>
-__device__ void kin_dispatch(const EvalArgs& A, int64_t p0, KinLdsMax& L) {
-    switch ((A.m + 15) / 16) {
-        case 1: kin_body<MIXED, 1, 8>(A, p0, L); break;
-        case 2: kin_body<MIXED, 2, 8>(A, p0, L); break;
-        case 3: kin_body<MIXED, 3, 8>(A, p0, L); break;
-        case 4: kin_body<MIXED, 4, 8>(A, p0, L); break;
-        case 5: kin_body<MIXED, 5, 8>(A, p0, L); break;
-        default: kin_body<MIXED, 6, 8>(A, p0, L); break;
-    }
-}
-
 template <bool MIXED>
 static void launch_kin_t(const EvalArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(a.count, kKinPT)), block(256);
@@ -875,21 +861,6 @@ __device__ inline EvalArgs group_eval_args(const GroupCall& G, int c, size_t tsz
     A.r = G.r + C.off_a; A.Pr = G.Pr; A.status = G.status;
     A.wscale = C.wscale;
     return A;
-}
-
-// kinematics of every cluster in one launch: one 32-point tile per workgroup
-template <bool MIXED>
-__global__ void __launch_bounds__(512) k_kin_grouped(GroupCall G) {
-    __shared__ KinLdsMax L;
-    const WorkItem w = G.items[blockIdx.x];
-    const EvalArgs A = group_eval_args(G, w.c, MIXED ? sizeof(float) : sizeof(double));
-    kin_dispatch<MIXED>(A, (int64_t)w.unit * kKinPT, L);
-}
-
-int launch_kin_grouped(int mixed, const GroupCall& g, hipStream_t s) {
-    if (mixed) hipLaunchKernelGGL(k_kin_grouped<true>, dim3(g.nitems), dim3(512), 0, s, g);
-    else hipLaunchKernelGGL(k_kin_grouped<false>, dim3(g.nitems), dim3(512), 0, s, g);
-    return HROM_OK;
 }
 
 __global__ void k_reset_counter(int* counter) { *counter = 0; }

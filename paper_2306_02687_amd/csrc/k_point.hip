@@ -499,23 +499,4 @@ void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s) {
     hipLaunchKernelGGL(k_update_grouped, dim3(nblocks(a_len, 256)), dim3(256), 0, s, g, a_len);
 }
 
-__global__ void __launch_bounds__(256) k_lambda_grouped(GroupCall G, int64_t a_len) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a_len) return;
-    const ClusterGPU& C = G.cls[find_cluster_by_offset(G, t)];
-    const int64_t loc = t - C.off_a;
-    const int k = (int)(loc / C.count);
-    const int64_t pl = loc - (int64_t)k * C.count;
-    const int64_t b = C.first + pl;
-    const double* X = G.X + 9 * C.off_a;
-    double s = 0.0;
-#pragma unroll
-    for (int J = 0; J < 9; J++) s = fma(X[((int64_t)k * 9 + J) * C.count + pl], G.gr[J * G.N + b], s);
-    ((double*)G.lam)[t] = s;
-}
-
-void launch_lambda_grouped(const GroupCall& g, int64_t a_len, hipStream_t s) {
-    hipLaunchKernelGGL(k_lambda_grouped, dim3(nblocks(a_len, 256)), dim3(256), 0, s, g, a_len);
-}
-
 }  // namespace hrom
