@@ -260,7 +260,8 @@ int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant) {
     if (!plan || variant < 0 || variant >= hrom_num_variants() || c < -1 || c >= plan->p.ncl) return HROM_E_INVALID;
     Plan& p = plan->p;
     if (p.grouped) {
-        // one persistent launch for every cluster: the variant picks its grid
+        // FP64: one persistent launch for every cluster, the variant picks its
+        // grid (mixed plans launch one workgroup per tile: no choice)
         int ncu = 256;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, p.device) == hipSuccess && prop.multiProcessorCount > 0)
@@ -352,13 +353,14 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         g.r = p.r; g.Pr = p.Pr; g.status = status;
         int rc = HROM_OK;
         if (p.profile) (void)hipEventRecord(p.ev_tan[0], stream);
-        if (rc == HROM_OK && p.n_tan > 0) {
-            g.items = p.items_tan; g.nitems = p.n_tan; g.counter = p.counter;
-            rc = launch_tan_persistent(p.prec, (p.flags & HROM_SPLIT) != 0, g, p.persistent_grid, stream);
-        }
-        if (rc == HROM_OK && p.n_tan2 > 0) {
+        g.items = p.items_tan; g.nitems = p.n_tan;
+        if (!mixed(p)) {
+            rc = launch_tan_persistent(g, p.persistent_grid, stream);
+        } else {
+            const bool split = (p.flags & HROM_SPLIT) != 0;
+            rc = launch_tan_tiles(p.prec, split, false, g, stream);
             g.items = p.items_tan2; g.nitems = p.n_tan2;
-            rc = launch_tan_tiles8(p.prec, (p.flags & HROM_SPLIT) != 0, g, stream);
+            if (rc == HROM_OK) rc = launch_tan_tiles(p.prec, split, true, g, stream);
         }
         if (p.profile) (void)hipEventRecord(p.ev_tan[1], stream);
         if (rc != HROM_OK) return rc;

@@ -91,12 +91,12 @@ struct Plan {
     // grouped launches (more than one cluster)
     bool grouped = false;
     int max_m = 0;
-    int persistent_grid = 512;
     ClusterGPU* cls_dev = nullptr;
     WorkItem* items_tan = nullptr;   // 4-point tiles, decreasing cost (mixed plans: m > 64)
     WorkItem* items_tan2 = nullptr;  // mixed plans: 8-point tiles of the clusters with m <= 64
+    int persistent_grid = 512;       // FP64 plans: workgroups of the persistent tangent launch
     int n_tan = 0, n_tan2 = 0;
-    int* counter = nullptr;          // work-queue head of the persistent tangent launch
+    int* counter = nullptr;          // work-queue head of the persistent tangent launch (FP64)
 };
 
 // ---------------------------------------------------------------- kernels
@@ -312,8 +312,8 @@ struct GroupCall {
     double* a_out;
 };
 
-int launch_tan_persistent(int prec, bool split, const GroupCall& g, int grid, hipStream_t s);
-int launch_tan_tiles8(int prec, bool split, const GroupCall& g, hipStream_t s);
+int launch_tan_persistent(const GroupCall& g, int grid, hipStream_t s);   // FP64
+int launch_tan_tiles(int prec, bool split, bool wide, const GroupCall& g, hipStream_t s);   // mixed
 void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);
 void set_kernel_attributes();
 

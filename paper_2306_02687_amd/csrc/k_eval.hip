@@ -865,13 +865,13 @@ __device__ inline EvalArgs group_eval_args(const GroupCall& G, int c, size_t tsz
 
 __global__ void k_reset_counter(int* counter) { *counter = 0; }
 
-// One persistent launch for the tangent contraction of every cluster: the
-// workgroups pull 4-point tiles from a work queue sorted by decreasing cost
-// (largest m first), so the uneven clusters balance over the CUs.  Every
-// workgroup leaves when the queue is exhausted.
-template <int PREC, bool SPLIT>
+// FP64 plans: one persistent launch for the tangent contraction of every
+// cluster: the workgroups pull 4-point tiles from a work queue sorted by
+// decreasing cost (largest m first), so the uneven clusters balance over the
+// CUs.  Every workgroup leaves when the queue is exhausted.
 __global__ void __launch_bounds__(256, 1) k_tan_persistent(GroupCall G) {
     __shared__ int s_item;
+    __shared__ double s_st[4][12 * 64];
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(G.counter, 1);
         __syncthreads();
@@ -880,68 +880,66 @@ __global__ void __launch_bounds__(256, 1) k_tan_persistent(GroupCall G) {
         if (it >= G.nitems) break;
         const WorkItem w = G.items[it];
         const int64_t pl0 = (int64_t)w.unit * 4;
-        if constexpr (PREC == HROM_FP64) {
-            __shared__ double s_st[4][12 * 64];
-            const EvalArgs A = group_eval_args(G, w.c, sizeof(double));
-            switch (A.MT) {
-                case 2: tan_f64_body<2>(A, pl0, s_st); break;
-                case 3: tan_f64_body<3>(A, pl0, s_st); break;
-                case 4: tan_f64_body<4>(A, pl0, s_st); break;
-                case 5: tan_f64_body<5>(A, pl0, s_st); break;
-                case 6: tan_f64_body<6>(A, pl0, s_st); break;
-                default: tan_f64_body<7>(A, pl0, s_st); break;
-            }
-        } else {
-            __shared__ v4u32 s_w[4][kCQ * kWR];
-            const EvalArgs A = group_eval_args(G, w.c, sizeof(float));
-            switch ((A.m + 15) / 16) {
-                case 1: tan_mixed_body<1, PREC, SPLIT, true>(A, pl0, s_w); break;
-                case 2: tan_mixed_body<2, PREC, SPLIT, true>(A, pl0, s_w); break;
-                case 3: tan_mixed_body<3, PREC, SPLIT, true>(A, pl0, s_w); break;
-                case 4: tan_mixed_body<4, PREC, SPLIT, true>(A, pl0, s_w); break;
-                case 5: tan_mixed_body<5, PREC, SPLIT, true>(A, pl0, s_w); break;
-                default: tan_mixed_body<6, PREC, SPLIT, true>(A, pl0, s_w); break;
-            }
+        const EvalArgs A = group_eval_args(G, w.c, sizeof(double));
+        switch (A.MT) {
+            case 2: tan_f64_body<2>(A, pl0, s_st); break;
+            case 3: tan_f64_body<3>(A, pl0, s_st); break;
+            case 4: tan_f64_body<4>(A, pl0, s_st); break;
+            case 5: tan_f64_body<5>(A, pl0, s_st); break;
+            case 6: tan_f64_body<6>(A, pl0, s_st); break;
+            default: tan_f64_body<7>(A, pl0, s_st); break;
         }
         __syncthreads();
     }
 }
 
-// Mixed clusters with m <= 64: one workgroup per 8-point tile (two macro
-// points per wavefront, two wavefronts per SIMD); the tiles are ordered by
-// decreasing cost, so the dispatcher hands out the expensive ones first
-template <int PREC, bool SPLIT>
-__global__ void __launch_bounds__(256, 2) k_tan_tiles8(GroupCall G) {
+// Mixed plans: one workgroup per tile, tiles ordered by decreasing cost (the
+// dispatcher hands out the expensive ones first), two wavefronts per SIMD.
+// WIDE: clusters with m <= 64 in 8-point tiles, two macro points per
+// wavefront; else clusters with m > 64 in 4-point tiles, one point per
+// wavefront.
+template <int PREC, bool SPLIT, bool WIDE>
+__global__ void __launch_bounds__(256, 2) k_tan_tiles(GroupCall G) {
     __shared__ v4u32 s_w[4][kCQ * kWR];
     const WorkItem w = G.items[blockIdx.x];
-    const int64_t pl0 = (int64_t)w.unit * 8;
     const EvalArgs A = group_eval_args(G, w.c, sizeof(float));
-    switch ((A.m + 15) / 16) {
-        case 1: tan_mixed_body<1, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
-        case 2: tan_mixed_body<2, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
-        case 3: tan_mixed_body<3, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
-        default: tan_mixed_body<4, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
+    const int ma = (A.m + 15) / 16;
+    if constexpr (WIDE) {
+        const int64_t pl0 = (int64_t)w.unit * 8;
+        switch (ma) {
+            case 1: tan_mixed_body<1, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
+            case 2: tan_mixed_body<2, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
+            case 3: tan_mixed_body<3, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
+            default: tan_mixed_body<4, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
+        }
+    } else {
+        const int64_t pl0 = (int64_t)w.unit * 4;   // the host routes only m > 64 here
+        if (ma <= 5) tan_mixed_body<5, PREC, SPLIT, false, 1>(A, pl0, s_w);
+        else tan_mixed_body<6, PREC, SPLIT, false, 1>(A, pl0, s_w);
     }
 }
 
-int launch_tan_tiles8(int prec, bool split, const GroupCall& g, hipStream_t s) {
-    if (prec == HROM_FP64) return HROM_E_INVALID;
+template <int PREC, bool SPLIT>
+static void launch_tiles_t(bool wide, const GroupCall& g, hipStream_t s) {
     const dim3 gr(g.nitems), bl(256);
-    if (prec == HROM_MIXED_BF16 && split) hipLaunchKernelGGL((k_tan_tiles8<HROM_MIXED_BF16, true>), gr, bl, 0, s, g);
-    else if (prec == HROM_MIXED_BF16) hipLaunchKernelGGL((k_tan_tiles8<HROM_MIXED_BF16, false>), gr, bl, 0, s, g);
-    else if (split) hipLaunchKernelGGL((k_tan_tiles8<HROM_MIXED_FP16, true>), gr, bl, 0, s, g);
-    else hipLaunchKernelGGL((k_tan_tiles8<HROM_MIXED_FP16, false>), gr, bl, 0, s, g);
+    if (wide) hipLaunchKernelGGL((k_tan_tiles<PREC, SPLIT, true>), gr, bl, 0, s, g);
+    else hipLaunchKernelGGL((k_tan_tiles<PREC, SPLIT, false>), gr, bl, 0, s, g);
+}
+
+int launch_tan_tiles(int prec, bool split, bool wide, const GroupCall& g, hipStream_t s) {
+    if (prec == HROM_FP64) return HROM_E_INVALID;
+    if (g.nitems == 0) return HROM_OK;
+    if (prec == HROM_MIXED_BF16 && split) launch_tiles_t<HROM_MIXED_BF16, true>(wide, g, s);
+    else if (prec == HROM_MIXED_BF16) launch_tiles_t<HROM_MIXED_BF16, false>(wide, g, s);
+    else if (split) launch_tiles_t<HROM_MIXED_FP16, true>(wide, g, s);
+    else launch_tiles_t<HROM_MIXED_FP16, false>(wide, g, s);
     return HROM_OK;
 }
 
-int launch_tan_persistent(int prec, bool split, const GroupCall& g, int grid, hipStream_t s) {
+int launch_tan_persistent(const GroupCall& g, int grid, hipStream_t s) {
+    if (g.nitems == 0) return HROM_OK;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, g.counter);
-    const dim3 gr(grid), bl(256);
-    if (prec == HROM_FP64) hipLaunchKernelGGL((k_tan_persistent<HROM_FP64, false>), gr, bl, 0, s, g);
-    else if (prec == HROM_MIXED_BF16 && split) hipLaunchKernelGGL((k_tan_persistent<HROM_MIXED_BF16, true>), gr, bl, 0, s, g);
-    else if (prec == HROM_MIXED_BF16) hipLaunchKernelGGL((k_tan_persistent<HROM_MIXED_BF16, false>), gr, bl, 0, s, g);
-    else if (split) hipLaunchKernelGGL((k_tan_persistent<HROM_MIXED_FP16, true>), gr, bl, 0, s, g);
-    else hipLaunchKernelGGL((k_tan_persistent<HROM_MIXED_FP16, false>), gr, bl, 0, s, g);
+    hipLaunchKernelGGL(k_tan_persistent, dim3(grid), dim3(256), 0, s, g);
     return HROM_OK;
 }
 
