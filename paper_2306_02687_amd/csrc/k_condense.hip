@@ -490,33 +490,86 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
     __shared__ double zb[16];                // right-hand sides of one row
 
     // ---- gather the lower blocks of M from the K-hat tiles, r and Pr
+    auto aug = [&](int i) {   // augmented K-hat index: -1 identity, -2 residual row, -3 zero
+        return i < m ? i : (i < mp ? -1 : (i < mp + 9 ? m + i - mp : (i == mp + 9 ? -2 : -3)));
+    };
     double M[NB];
     double rr = 0.0;
+    // BATCH: all loads of the point are issued first, unconditionally, from
+    // addresses inside their arrays (a placeholder address where the element
+    // is not read); each loaded value gets an unconditional use (an empty asm
+    // statement), so the compiler cannot sink a load into the branch that
+    // reads it, where every load waits for the one before.  Only where the
+    // loaded values fit the register budget next to the matrix.
+    constexpr bool BATCH = sizeof(TT) == 4 ? MB <= 12 : MB <= 9;
+    if constexpr (BATCH) {
+        TT raw[NB];
+        double rraw[MB];
 #pragma unroll
-    for (int t = 0; t < MB; t++) {
+        for (int t = 0; t < MB; t++) {
 #pragma unroll
-        for (int u = 0; u <= t; u++) {
-            const int i = 8 * t + lr, k = 8 * u + lc;
-            // augmented index of K-hat (modes, then the nine macro columns);
-            // -1 identity padding, -2 residual row, -3 zero padding
-            const int xi = i < m ? i : (i < mp ? -1 : (i < mp + 9 ? m + i - mp : (i == mp + 9 ? -2 : -3)));
-            const int xk = k < m ? k : (k < mp ? -1 : (k < mp + 9 ? m + k - mp : (k == mp + 9 ? -2 : -3)));
-            double v = 0.0;
-            if (xi >= 0 && xk >= 0) {
-                if constexpr (sizeof(TT) == 4) v = (double)kh[lblk(t, u) * 64 + lane] * ks;   // lane order
-                else v = khat_at<TT>(kh, m, MT, xi, xk) * ks;
-            } else if (xi == -1 || xk == -1) {
-                v = (i == k) ? 1.0 : 0.0;
-            } else if ((xi == -2) != (xk == -2) && xi != -3 && xk != -3) {
-                const int o = xi == -2 ? xk : xi;
-                if (o < m) {
-                    v = A.r[(int64_t)o * A.count + pl];
-                    rr = fma(v, v, rr);
+            for (int u = 0; u <= t; u++) {
+                if constexpr (sizeof(TT) == 4) {
+                    raw[lblk(t, u)] = kh[lblk(t, u) * 64 + lane];   // lane order, whole record
                 } else {
-                    v = A.Pr[(int64_t)(o - m) * A.N + b];
+                    const int xi = aug(8 * t + lr), xk = aug(8 * u + lc);
+                    const bool kin = xi >= 0 && xk >= 0;
+                    raw[lblk(t, u)] = khat_at<TT>(kh, m, MT, kin ? xi : 0, kin ? xk : 0);
                 }
             }
-            M[lblk(t, u)] = v;
+        }
+        // the residual row mp + 9 lies in block row JB + 1 (lane row 1): r
+        // against the mode columns, Pr against the macro columns
+#pragma unroll
+        for (int u = 0; u < MB; u++) {
+            const int xi = aug(8 * (JB + 1) + lr), xk = aug(8 * u + lc);
+            const bool rrow = xi == -2 && xk >= 0, isr = rrow && xk < m;
+            const double* rp = isr ? A.r + (int64_t)xk * A.count + pl
+                                   : (rrow ? A.Pr + (int64_t)(xk - m) * A.N + b : A.r + pl);
+            rraw[u] = *rp;
+        }
+#pragma unroll
+        for (int e = 0; e < NB; e++) asm volatile("" ::"v"(raw[e]));
+#pragma unroll
+        for (int u = 0; u < MB; u++) asm volatile("" ::"v"(rraw[u]));
+#pragma unroll
+        for (int t = 0; t < MB; t++) {
+#pragma unroll
+            for (int u = 0; u <= t; u++) {
+                const int i = 8 * t + lr, k = 8 * u + lc;
+                const int xi = aug(i), xk = aug(k);
+                double v = (xi >= 0 && xk >= 0) ? (double)raw[lblk(t, u)] * ks
+                                                 : ((xi == -1 || xk == -1) ? (i == k ? 1.0 : 0.0) : 0.0);
+                if (t == JB + 1 && xi == -2 && xk >= 0) {
+                    v = rraw[u];
+                    if (xk < m) rr = fma(v, v, rr);
+                }
+                M[lblk(t, u)] = v;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < MB; t++) {
+#pragma unroll
+            for (int u = 0; u <= t; u++) {
+                const int i = 8 * t + lr, k = 8 * u + lc;
+                const int xi = aug(i), xk = aug(k);
+                double v = 0.0;
+                if (xi >= 0 && xk >= 0) {
+                    if constexpr (sizeof(TT) == 4) v = (double)kh[lblk(t, u) * 64 + lane] * ks;
+                    else v = khat_at<TT>(kh, m, MT, xi, xk) * ks;
+                } else if (xi == -1 || xk == -1) {
+                    v = (i == k) ? 1.0 : 0.0;
+                } else if (xi == -2 && xk >= 0) {
+                    if (xk < m) {
+                        v = A.r[(int64_t)xk * A.count + pl];
+                        rr = fma(v, v, rr);
+                    } else {
+                        v = A.Pr[(int64_t)(xk - m) * A.N + b];
+                    }
+                }
+                M[lblk(t, u)] = v;
+            }
         }
     }
 
