@@ -152,16 +152,17 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
  * m <= 64; otherwise as variant 2 and 0) put two macro points on each
  * wavefront, sharing every mode-gradient operand, without / with that
  * prefetch (the FP64 kernel reads both as variant 0).  Plans with
- * several clusters: the persistent launch uses (variant + 1) x #CUs
- * workgroups.  c = -1 applies to every cluster.  Results do not depend on the
+ * several clusters: FP64 plans give their persistent tangent launch
+ * (variant + 1) x #CUs workgroups; mixed plans launch one workgroup per tile
+ * and have no variant.  c = -1 applies to every cluster.  Results do not depend on the
  * variant (same arithmetic, same order). */
 int32_t hrom_num_variants(void);
 int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant);
 
 /* Measurement hook (not part of the method): with enable != 0 every later
  * hrom_eval records two HIP events on its stream around the tangent
- * contraction (the persistent launch of a grouped plan, the single tangent
- * launch of a one-cluster plan).  hrom_plan_tangent_ms waits for the second
+ * contraction (all tangent launches of a plan with several clusters, the
+ * single tangent launch of a one-cluster plan).  hrom_plan_tangent_ms waits for the second
  * event and returns the elapsed milliseconds of the last recorded launch;
  * HROM_E_ORDER if profiling is off.  The events are created on the first
  * enable and destroyed with the plan. */
