@@ -640,17 +640,10 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
         for (int i = 0; i < MA; i++) accF[pp][i] = v4f{0.f, 0.f, 0.f, 0.f};
     }
 
-    // Software pipeline over ECM points: iteration q issues the T, KaF and
-    // KFF products of q, then the Kaa products of q - 1 (operands kept from the
-    // previous iteration) interleaved with the hi/lo split of T(q), so the
-    // matrix core and the VALU work side by side within one wavefront.
-    v4u32 Gp[MA], Bp[NP][MA];  // previous ECM point: fragments and split T
-#pragma unroll
-    for (int t = 0; t < MA; t++) {
-        Gp[t] = v4u32{0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int pp = 0; pp < NP; pp++) Bp[pp][t] = v4u32{0u, 0u, 0u, 0u};
-    }
+    // Per ECM point: the T products first, then the KaF and KFF products (their
+    // matrix time covers the latency of T), then per mode tile tj the hi/lo
+    // split of T_tj followed at once by the Kaa products of column tj, so the
+    // split of the next tile overlaps the products of this one.
     v4u32 Gc[MA];
 #pragma unroll
     for (int t = 0; t < MA; t++) Gc[t] = fp[t * 64];
@@ -712,30 +705,20 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
             for (int pp = 0; pp < NP; pp++) {
                 v4f T[MA];
 #pragma unroll
-                for (int t = 0; t < MA; t++) {
-                    T[t] = Pk<PREC>::mfma(Wq[pp], Gc[t], v4f{0.f, 0.f, 0.f, 0.f});
-                    accF[pp][t] = Pk<PREC>::mfma(Gc[t], Wq[pp], accF[pp][t]);
-                }
+                for (int t = 0; t < MA; t++) T[t] = Pk<PREC>::mfma(Wq[pp], Gc[t], v4f{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                for (int t = 0; t < MA; t++) accF[pp][t] = Pk<PREC>::mfma(Gc[t], Wq[pp], accF[pp][t]);
                 accFF[pp] = Pk<PREC>::mfma(Wq[pp], Ip, accFF[pp]);
-                int idx = 0;
 #pragma unroll
-                for (int ti = 0; ti < MA; ti++)
+                for (int tj = 0; tj < MA; tj++) {
+                    const v4u32 B = t_operand<PREC, SPLIT>(T[tj], in_g1);
 #pragma unroll
-                    for (int tj = ti; tj < MA; tj++, idx++)
-                        acc[pp][idx] = Pk<PREC>::mfma(Gp[ti], Bp[pp][tj], acc[pp][idx]);
-#pragma unroll
-                for (int t = 0; t < MA; t++) Bp[pp][t] = t_operand<PREC, SPLIT>(T[t], in_g1);
-                // issue order: the 2 MA + 1 products of q, then one Kaa product
-                // of q - 1 after every few VALU instructions of the split
-                __builtin_amdgcn_sched_group_barrier(0x008, 2 * MA + 1, 0);
-#pragma unroll
-                for (int i = 0; i < NA; i++) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, (13 * MA + NA - 1) / NA, 0);
+                    for (int ti = 0; ti <= tj; ti++) {
+                        const int idx = ti * MA - ti * (ti - 1) / 2 + (tj - ti);
+                        acc[pp][idx] = Pk<PREC>::mfma(Gc[ti], B, acc[pp][idx]);
+                    }
                 }
             }
-#pragma unroll
-            for (int t = 0; t < MA; t++) Gp[t] = Gc[t];
             if (PF) {
 #pragma unroll
                 for (int t = 0; t < MA; t++) Gc[t] = Gn[t];
@@ -747,16 +730,6 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
 #pragma unroll
             for (int pp = 0; pp < NP; pp++) Wq[pp] = Wn[pp];
         }
-    }
-    {   // Kaa products of the last ECM point
-        int idx = 0;
-#pragma unroll
-        for (int ti = 0; ti < MA; ti++)
-#pragma unroll
-            for (int tj = ti; tj < MA; tj++, idx++)
-#pragma unroll
-                for (int pp = 0; pp < NP; pp++)
-                    acc[pp][idx] = Pk<PREC>::mfma(Gp[ti], Bp[pp][tj], acc[pp][idx]);
     }
     // record in the condensation's order: lower 8 x 8 blocks of the augmented
     // matrix (modes, then the components at mp), entry (r, c) of block (t, u)
