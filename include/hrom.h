@@ -146,8 +146,8 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
                   double* gFbar, double* gtheta, int32_t* status, hipStream_t stream);
 
 /* Launch variants of the tangent contraction, chosen by the autotuner.
- * Single-cluster plans, variants 0..3: bit 0 asks for three wavefronts per
- * SIMD instead of two (mixed kernels), bit 1 turns off the prefetch of the
+ * Single-cluster plans, variants 0..3: bit 0 asks for four wavefronts per
+ * SIMD instead of three (mixed kernels), bit 1 turns off the prefetch of the
  * next ECM point's mode-gradient operands; variants 4 and 5 (mixed kernels,
  * m <= 64; otherwise as variant 2 and 0) put two macro points on each
  * wavefront, sharing every mode-gradient operand, without / with that

@@ -772,25 +772,26 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
     }
 }
 
-// OCC3: ask for three wavefronts per SIMD (register cap 168) instead of two;
+// OCC4: ask for four wavefronts per SIMD (register cap 128; one point per
+// wavefront fits three without asking);
 // NP: macro points per wavefront
-template <int MA, int PREC, bool SPLIT, bool PF, bool OCC3, int NP>
-__global__ void __launch_bounds__(256, (OCC3 && MA <= 4 && NP == 1) ? 3 : 2) k_eval_mixed(EvalArgs A) {
+template <int MA, int PREC, bool SPLIT, bool PF, bool OCC4, int NP>
+__global__ void __launch_bounds__(256, (OCC4 && MA <= 4 && NP == 1) ? 4 : 2) k_eval_mixed(EvalArgs A) {
     __shared__ v4u32 s_w[4][kCQ * kWR];
     tan_mixed_body<MA, PREC, SPLIT, PF, NP>(A, (int64_t)blockIdx.x * (4 * NP), s_w);
 }
 
-template <int PREC, bool SPLIT, bool PF, bool OCC3, int NP>
+template <int PREC, bool SPLIT, bool PF, bool OCC4, int NP>
 static int launch_mixed_t(const EvalArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(a.count, 4 * NP)), block(256);
     switch ((a.m + 15) / 16) {
-        case 1: hipLaunchKernelGGL((k_eval_mixed<1, PREC, SPLIT, PF, OCC3, NP>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_eval_mixed<2, PREC, SPLIT, PF, OCC3, NP>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_eval_mixed<3, PREC, SPLIT, PF, OCC3, NP>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_eval_mixed<4, PREC, SPLIT, PF, OCC3, NP>), grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_eval_mixed<1, PREC, SPLIT, PF, OCC4, NP>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_eval_mixed<2, PREC, SPLIT, PF, OCC4, NP>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_eval_mixed<3, PREC, SPLIT, PF, OCC4, NP>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_eval_mixed<4, PREC, SPLIT, PF, OCC4, NP>), grid, block, 0, s, a); break;
         // two points per wavefront do not fit the register file beyond m = 64
-        case 5: hipLaunchKernelGGL((k_eval_mixed<5, PREC, SPLIT, PF, OCC3, 1>), dim3(nblocks(a.count, 4)), block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_eval_mixed<6, PREC, SPLIT, PF, OCC3, 1>), dim3(nblocks(a.count, 4)), block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_eval_mixed<5, PREC, SPLIT, PF, OCC4, 1>), dim3(nblocks(a.count, 4)), block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_eval_mixed<6, PREC, SPLIT, PF, OCC4, 1>), dim3(nblocks(a.count, 4)), block, 0, s, a); break;
         default: return HROM_E_UNSUPPORTED;
     }
     return HROM_OK;
