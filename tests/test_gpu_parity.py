@@ -255,9 +255,9 @@ def test_clusters_in_one_plan_match_single_plans(dev, orc):
 @pytest.mark.parametrize("precision,split,refine", [(0, False, False), (1, True, False),
                                                     (1, False, True)])
 def test_backward_clusters_in_one_plan(dev, orc, precision, split, refine):
-    """Adjoint of a plan holding several clusters (the grouped launches) vs the
-    oracle's adjoint cluster by cluster; dL/dtheta sums over all points.  On
-    the FP64 path dL/dFbar also equals that of one plan per cluster bitwise."""
+    """Adjoint of a plan holding several clusters vs the oracle's adjoint
+    cluster by cluster; dL/dtheta sums over all points.  On the FP64 path
+    dL/dFbar also equals that of one plan per cluster bitwise."""
     from paper_2306_02687_amd import solve
     log_case("backward_multi", precision, split, refine)
     shapes = [(8, 48, 5), (24, 144, 4), (48, 288, 3)]
