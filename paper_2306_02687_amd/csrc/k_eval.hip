@@ -179,6 +179,12 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
             }
         }
         __syncthreads();
+        // ---- rows 128..143 of F: fixed-order sum of the four k-range partials
+        for (int e = tid; e < 16 * PT; e += NT) {
+            const int r = e >> 5, p = e & 31;
+            sF[128 + r][p] = ((sF8[0][r][p] + sF8[1][r][p]) + (sF8[2][r][p] + sF8[3][r][p])) + sU[(128 + r) % 9][p];
+        }
+        __syncthreads();
         // ---- material law: thread = (point p, ECM point q0 + qq), 8 / NW per thread
 #pragma unroll 1
         for (int h = 0; h < 8 / NW; h++) {
@@ -186,12 +192,7 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
             const int p = e2 >> 4, qq = e2 & 15, q = q0 + qq;
             double F[9];
 #pragma unroll
-            for (int I = 0; I < 9; I++) {
-                const int row = qq * 9 + I;
-                F[I] = (row < 128) ? sF[row][p]
-                                   : ((sF8[0][row - 128][p] + sF8[1][row - 128][p]) +
-                                      (sF8[2][row - 128][p] + sF8[3][row - 128][p])) + sU[I][p];
-            }
+            for (int I = 0; I < 9; I++) F[I] = sF[qq * 9 + I][p];
             const double wq = A.w[q];
             const int ph = A.phase[q];
             const double mu = ph ? mu1 : mu0, la = ph ? la1 : la0;
