@@ -46,7 +46,7 @@ void free_plan(Plan& p) {
     dfree(p.Fr); dfree(p.polar); dfree(p.Pr); dfree(p.r); dfree(p.Khat); dfree(p.qs); dfree(p.L);
     dfree(p.piv); dfree(p.y); dfree(p.X); dfree(p.Palg); dfree(p.Cr); dfree(p.S);
     dfree(p.rnorm); dfree(p.dU); dfree(p.gr); dfree(p.Lam); dfree(p.lam); dfree(p.rho);
-    dfree(p.hr); dfree(p.gth);
+    dfree(p.hr); dfree(p.gth); dfree(p.gth_part);
     dfree(p.cls_dev); dfree(p.items_tan); dfree(p.items_tan2); dfree(p.counter);
 }
 
@@ -243,6 +243,7 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
     if (rc == HROM_OK) rc = dalloc(&p.rho, off_a);
     if (rc == HROM_OK) rc = dalloc(&p.hr, 9 * n);
     if (rc == HROM_OK) rc = dalloc(&p.gth, 4 * n);
+    if (rc == HROM_OK) rc = dalloc(&p.gth_part, 4 * kThetaChunks);
     if (rc == HROM_OK) rc = build_groups(p);
     if (rc != HROM_OK) {
         free_plan(p);
@@ -517,7 +518,7 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
         launch_backward_b(ba, stream);
     }
     launch_bw_pushforward(bp, stream);
-    launch_reduce_theta(p.N, p.gth, gtheta, stream);
+    launch_reduce_theta(p.N, p.gth, p.gth_part, gtheta, stream);
     return hip_status();
 }
 

@@ -86,6 +86,7 @@ struct Plan {
     double* rho = nullptr;     // mode-indexed: refinement residual
     double* hr = nullptr;      // [9][N]
     double* gth = nullptr;     // [4][N] per-point theta gradients
+    double* gth_part = nullptr;  // [4][kThetaChunks] partial sums of gth
     int64_t khat_len = 0, L_len = 0, qs_len = 0;
     int stage = 0;             // 0 = nothing, 1 = evaluated, 2 = condensed
     // grouped launches (more than one cluster)
@@ -241,7 +242,8 @@ struct RefineArgs {
 };
 void launch_refine_lambda(const RefineArgs& a, hipStream_t s);
 
-void launch_reduce_theta(int64_t N, const double* gth, double* out, hipStream_t s);
+constexpr int kThetaChunks = 256;   // stage-1 partials per theta component
+void launch_reduce_theta(int64_t N, const double* gth, double* part, double* out, hipStream_t s);
 void launch_mark_unconverged(int64_t N, const double* rnorm, double tol, int* status,
                              hipStream_t s);
 

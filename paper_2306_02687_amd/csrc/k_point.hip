@@ -323,25 +323,42 @@ void launch_lambda(const LambdaArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- reductions
-// dL/dtheta: fixed-order sum over points (bitwise reproducible): thread t of
-// component c sums points t, t + 256, ... in order, then a fixed tree.
-__global__ void __launch_bounds__(256) k_reduce_theta(int64_t N, const double* gth, double* out) {
-    __shared__ double s[256];
-    const int c = blockIdx.x;
+// dL/dtheta: fixed-order sum over points (bitwise reproducible).  Stage 1:
+// block (j, c) takes the contiguous chunk j of component c, thread t sums its
+// points t, t + 256, ... of the chunk in order, then a fixed tree; stage 2:
+// one block per component adds the kThetaChunks partials by the same tree.
+__device__ __forceinline__ double block_tree_sum(double v, double* s) {
     const int t = threadIdx.x;
-    double acc = 0.0;
-    for (int64_t b = t; b < N; b += 256) acc += gth[c * N + b];
-    s[t] = acc;
+    s[t] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) s[t] += s[t + w];
         __syncthreads();
     }
-    if (t == 0) out[c] = s[0];
+    return s[0];
 }
 
-void launch_reduce_theta(int64_t N, const double* gth, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_theta, dim3(4), dim3(256), 0, s, N, gth, out);
+__global__ void __launch_bounds__(256) k_reduce_theta_chunks(int64_t N, const double* gth, double* part) {
+    __shared__ double s[256];
+    const int j = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
+    const int64_t ch = (N + kThetaChunks - 1) / kThetaChunks;
+    const int64_t b0 = (int64_t)j * ch, b1 = b0 + ch < N ? b0 + ch : N;
+    double acc = 0.0;
+    for (int64_t b = b0 + t; b < b1; b += 256) acc += gth[c * N + b];
+    const double tot = block_tree_sum(acc, s);
+    if (t == 0) part[c * kThetaChunks + j] = tot;
+}
+
+__global__ void __launch_bounds__(256) k_reduce_theta(const double* part, double* out) {
+    __shared__ double s[256];
+    const int c = blockIdx.x;
+    const double tot = block_tree_sum(part[c * kThetaChunks + threadIdx.x], s);
+    if (threadIdx.x == 0) out[c] = tot;
+}
+
+void launch_reduce_theta(int64_t N, const double* gth, double* part, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_theta_chunks, dim3(kThetaChunks, 4), dim3(256), 0, s, N, gth, part);
+    hipLaunchKernelGGL(k_reduce_theta, dim3(4), dim3(256), 0, s, (const double*)part, out);
 }
 
 __global__ void __launch_bounds__(256) k_mark_unconverged(int64_t N, const double* rnorm, double tol, int* status) {
