@@ -58,6 +58,7 @@ def lib():
         L.orc_monolithic.argtypes = [i32, i32, P, P, P, P, i32, i64, P, P, i32, P, P, P, P, P]
         L.orc_backward.argtypes = [i32, i32, P, P, P, P, i32, i64, P, P, P, P, P, P, P]
         L.orc_stretch_increment.argtypes = [i64, P, P, P]
+        L.orc_cauchy.argtypes = [i64, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -152,6 +153,20 @@ def point_eval(cl, theta, Fbar, a, objective=True):
                          _p(o["rnorm"]), _p(o["y"]), _p(o["X"]), _p(o["Palg_r"]), _p(o["Cr"]),
                          _p(o["status"]))
     return o
+
+
+def cauchy(Fbar, Palg_r, Cr):
+    """Cauchy stress sigma [N, 9] and the Updated-Lagrangian tangent
+    dsigma/dD [N, 9, 9] from the RVE-frame algorithmic stress and condensed
+    tangent at Fbar (eq. biotstress, App. A); also the per-point status."""
+    Fbar = _f64(Fbar)
+    N = Fbar.size // 9
+    Pa = _f64(Palg_r, (N, 9))
+    Cr = _f64(Cr, (N, 81))
+    sig, dsdD = np.zeros((N, 9)), np.zeros((N, 9, 9))
+    st = np.zeros(N, dtype=np.int32)
+    lib().orc_cauchy(N, _p(Fbar.reshape(N, 9)), _p(Pa), _p(Cr), _p(sig), _p(dsdD), _p(st))
+    return sig, dsdD, st
 
 
 def newton(cl, theta, Fbar, a0=None, tol=1e-10, max_it=25, objective=True):

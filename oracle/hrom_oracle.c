@@ -31,6 +31,9 @@
  *   push-out to the macro frame .... Sec. 3.2.2 eqs. (workconjugacy),
  *                                    (biotstress) in second-Piola form
  *   adjoint backward ............... derivative of the converged map
+ *   Cauchy stress and tangent ...... Sec. 3.2.2 eq. (biotstress), App. A
+ *                                    eqs. (tangent_continuum),
+ *                                    (d_Cauchy_d_Biot), (dUdot_dd)
  */
 #include <math.h>
 #include <stdint.h>
@@ -489,6 +492,55 @@ static void push_out(const polar_t *P, const double *Palg, const double *Cr,
 }
 
 /* ------------------------------------------------------------------ */
+/* Updated-Lagrangian output (Sec. 3.2.2 eq. biotstress, App. A).       */
+/* The Biot stress of the macro point is T = sym(R^T Pbar) = sym(Palg_r) */
+/* (the RVE sees Ubar, so Pbar = Rbar Palg_r).  Eq. (biotstress) links it */
+/* to the Cauchy stress sigma by the linear map                          */
+/*   T_kl = J/2 (R_ik sigma_ij Finv_lj + Finv_ki sigma_ij R_jl),         */
+/* whose 9 x 9 matrix is LU-factorised and solved (never inverted, as    */
+/* the appendix advises).  App. A: dsigma/dD = dsigma/dT : C^B : dUdot/dD */
+/* with C^B = dT/dUdot the condensed tangent restricted to symmetric     */
+/* stretch rates and symmetrised, C^B = sym o Cr o sym, and              */
+/* dUdot/dD ~ R_ki F_lj (constant rotation over the step).  Output       */
+/* sigma[3 i + j], dsdD[9 (3 i + j) + 3 k + l] = dsigma_ij / dD_kl.      */
+/* ------------------------------------------------------------------ */
+static int cauchy_out(const polar_t *P, const double *Palg, const double *Cr, double *sig,
+                      double *dsdD)
+{
+    const double J = m3_det(P->F);
+    double Fi[9], M[81], T[9];
+    int piv[9];
+    m3_inv(P->F, Fi);
+    for (int k = 0; k < 3; k++)
+        for (int l = 0; l < 3; l++)
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++)
+                    M[9 * (3 * k + l) + 3 * i + j] =
+                        0.5 * J * (P->R[3 * i + k] * Fi[3 * l + j] + Fi[3 * k + i] * P->R[3 * j + l]);
+    if (lu_factor(9, M, piv) != 0) return ORC_PT_NONFINITE;
+    m3_sym(Palg, T);
+    memcpy(sig, T, sizeof T);
+    lu_solve(9, M, piv, sig);
+    for (int k = 0; k < 3; k++)
+        for (int l = 0; l < 3; l++) {
+            /* stretch rate of a unit D_kl: Udot_ij = R_ki F_lj, symmetrised */
+            double Ud[9], dU[9], dP[9], dT[9];
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) Ud[3 * i + j] = P->R[3 * k + i] * P->F[3 * l + j];
+            m3_sym(Ud, dU);
+            for (int I = 0; I < 9; I++) {
+                double acc = 0.0;
+                for (int Jc = 0; Jc < 9; Jc++) acc += Cr[9 * I + Jc] * dU[Jc];
+                dP[I] = acc;
+            }
+            m3_sym(dP, dT);
+            lu_solve(9, M, piv, dT);
+            for (int I = 0; I < 9; I++) dsdD[9 * I + 3 * k + l] = dT[I];
+        }
+    return (all_finite(sig, 9) && all_finite(dsdD, 81)) ? 0 : ORC_PT_NONFINITE;
+}
+
+/* ------------------------------------------------------------------ */
 /* One full evaluate + condense (+ push-out) at one macro point.        */
 /* ------------------------------------------------------------------ */
 typedef struct {
@@ -811,6 +863,19 @@ int orc_backward(int m, int Q, const double *G, const double *w, const int *phas
     for (int i = 0; i < 4; i++) gtheta[i] = 0.0;
     for (int64_t b = 0; b < N; b++)
         for (int i = 0; i < 4; i++) gtheta[i] += gtheta_pt[4 * b + i];
+    return 0;
+}
+
+/* Cauchy stress and Updated-Lagrangian tangent from the RVE-frame
+   algorithmic stress Palg_r and condensed tangent Cr at Fbar */
+int orc_cauchy(int64_t N, const double *Fbar, const double *Palg_r, const double *Cr, double *sigma,
+               double *dsdD, int *status)
+{
+    for (int64_t b = 0; b < N; b++) {
+        polar_t P;
+        polar_split(Fbar + 9 * b, &P);
+        status[b] = cauchy_out(&P, Palg_r + 9 * b, Cr + 81 * b, sigma + 9 * b, dsdD + 81 * b);
+    }
     return 0;
 }
 

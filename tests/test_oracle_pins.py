@@ -422,3 +422,79 @@ def test_status_flags(orc, small):
     for b in range(2):
         res = blocks["Kaa"][b] @ o["y"][b] - blocks["r"][b]
         assert np.abs(res).max() < 1e-12 * max(np.abs(blocks["r"][b]).max(), 1e-300)
+
+
+# ---------------------------------------------------------------- Updated-Lagrangian output
+def _homogeneous_rve_frame(orc, F, mu, lam):
+    """RVE-frame inputs of a homogeneous Neo-Hooke point: Palg_r = P(Ubar),
+    Cr = A(Ubar) (no fluctuation modes)."""
+    U, _, _, _ = orc.polar(F)
+    P, A = orc.neo_hooke(U.reshape(-1, 3, 3), mu, lam)
+    return P, A
+
+
+def test_cauchy_equals_neo_hooke_cauchy_stress(orc):
+    """Homogeneous states, rotation included: the Cauchy stress obtained from
+    the Biot stress by eq. (biotstress) equals the textbook Neo-Hooke Cauchy
+    stress sigma = mu/J (F F^T - I) + lam ln J / J I."""
+    mu, lam = 10.0, 15.0
+    F, _, _ = make_macro_points(16, 8100, amp=0.2, max_angle=1.2)
+    Pa, Cr = _homogeneous_rve_frame(orc, F, mu, lam)
+    sig, dsdD, st = orc.cauchy(F, Pa, Cr)
+    assert not st.any()
+    for b in range(16):
+        J = np.linalg.det(F[b])
+        ref = mu / J * (F[b] @ F[b].T - np.eye(3)) + lam * np.log(J) / J * np.eye(3)
+        assert np.abs(sig[b].reshape(3, 3) - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+        # sigma symmetric, so is every column of the tangent
+        assert np.abs(dsdD[b].reshape(3, 3, 9) - dsdD[b].reshape(3, 3, 9).transpose(1, 0, 2)).max() < 1e-12
+
+
+def test_cauchy_tangent_is_lame_at_identity(orc):
+    """At F = I (R = U = I, J = 1, sigma = 0) the Updated-Lagrangian tangent
+    of App. A reduces to isotropic linear elasticity."""
+    mu, lam = 10.0, 15.0
+    F = np.eye(3)[None]
+    Pa, Cr = _homogeneous_rve_frame(orc, F, mu, lam)
+    sig, dsdD, _ = orc.cauchy(F, Pa, Cr)
+    d = np.eye(3)
+    ref = (mu * (np.einsum("ik,jl->ijkl", d, d) + np.einsum("il,jk->ijkl", d, d))
+           + lam * np.einsum("ij,kl->ijkl", d, d))
+    assert np.abs(sig).max() < 1e-14
+    assert np.abs(dsdD[0] - ref.reshape(9, 9)).max() < 1e-13
+
+
+def test_cauchy_tangent_pure_dilation(orc):
+    """F = s I: the Biot map is T = s^2 sigma, the stretch rate is Udot = s D
+    and C^B = sym A(sI) sym with A = mu d_ik d_jl + (mu - lam ln J)/s^2
+    d_il d_jk + lam/s^2 d_ij d_kl, so dsigma/dD = C^B / s (derived by hand
+    from the appendix's product rule)."""
+    mu, lam = 1.3, 2.2
+    d = np.eye(3)
+    Isym = 0.5 * (np.einsum("ik,jl->ijkl", d, d) + np.einsum("il,jk->ijkl", d, d))
+    for s in [0.8, 1.1, 1.5]:
+        F = s * np.eye(3)[None]
+        Pa, Cr = _homogeneous_rve_frame(orc, F, mu, lam)
+        sig, dsdD, _ = orc.cauchy(F, Pa, Cr)
+        ell = np.log(s ** 3)
+        CB = (mu + (mu - lam * ell) / s ** 2) * Isym + lam / s ** 2 * np.einsum("ij,kl->ijkl", d, d)
+        assert np.abs(dsdD[0] - (CB / s).reshape(9, 9)).max() < 1e-13
+
+
+def test_cauchy_rotation_covariance(orc):
+    """A superposed rotation Q leaves the RVE-frame state unchanged and
+    rotates the outputs: sigma(Q F) = Q sigma Q^T and the tangent transforms
+    as a fourth-order tensor.  Random RVE-frame states (not homogeneous)."""
+    rng = np.random.default_rng(8200)
+    F, _, _ = make_macro_points(8, 8201, amp=0.15, max_angle=0.8)
+    Pa = rng.standard_normal((8, 9))
+    Cr = rng.standard_normal((8, 9, 9))
+    Cr = Cr + Cr.transpose(0, 2, 1)
+    Q = make_macro_points(8, 8202, amp=0.0, max_angle=2.0)[1]
+    s1, c1, _ = orc.cauchy(F, Pa, Cr)
+    s2, c2, _ = orc.cauchy(Q @ F, Pa, Cr)
+    for b in range(8):
+        q = Q[b]
+        assert np.abs(s2[b].reshape(3, 3) - q @ s1[b].reshape(3, 3) @ q.T).max() < 1e-12
+        rot = np.einsum("ia,jb,kc,ld,abcd->ijkl", q, q, q, q, c1[b].reshape(3, 3, 3, 3))
+        assert np.abs(c2[b].reshape(3, 3, 3, 3) - rot).max() < 1e-11 * max(1.0, np.abs(rot).max())
