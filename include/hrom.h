@@ -55,7 +55,8 @@ extern "C" {
 #define HROM_E_HIP (-2)       /* a HIP runtime call failed */
 #define HROM_E_ORDER (-3)     /* call sequence violated, e.g. condense before eval */
 #define HROM_E_NOMEM (-4)     /* device allocation failed at plan creation */
-#define HROM_E_UNSUPPORTED (-5) /* size outside the supported range (m > 96, ...) */
+#define HROM_E_UNSUPPORTED (-5) /* size outside the supported range (m > 96, ...), or an
+                                 output the plan's mode does not provide */
 
 /* per-point status bits */
 #define HROM_PT_JNONPOS 1    /* det F <= 0 at an ECM point (or det Fbar <= 0) */
@@ -116,6 +117,18 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
  * stress, macro frame), Cbar [81][N], rnorm [N] = ||r||_2.  ORs status bits. */
 int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm,
                   int32_t* status, hipStream_t stream);
+
+/* Updated-Lagrangian output of the state left by the last hrom_condense
+ * (objective plans only, else HROM_E_UNSUPPORTED; HROM_E_ORDER before a
+ * condense): the Cauchy stress sigma [9][N] (3x3 row-major, symmetric) from
+ * the Biot stress sym(Palg_r) by Sec. 3.2.2 eq. (biotstress), and, unless
+ * dsdD is NULL, the consistent tangent dsdD [81][N], entry 9 (3i+j) + 3k+l =
+ * dsigma_ij / dD_kl, by the product rule of App. A with C^B = the condensed
+ * RVE-frame tangent on symmetric stretch rates and dUdot/dD ~ R_ki F_lj
+ * (constant rotation over the step).  Device pointers owned by the caller;
+ * ORs HROM_PT_NONFINITE into status for non-finite outputs.  Allocates
+ * nothing; does not change the plan's state. */
+int hrom_cauchy(hrom_plan plan, double* sigma, double* dsdD, int32_t* status, hipStream_t stream);
 
 /* Monolithic update a <- a - (y + X dFr) with the y, X of the last condense
  * (Sec. 3.2.3).  dFbar [9][N] macro-frame increment (linearised to the stretch

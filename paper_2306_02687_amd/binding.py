@@ -29,7 +29,7 @@ OFF_A, OFF_KAA, OFF_KAF = 0, 1, 2
 EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_eval",
             "hrom_condense", "hrom_update", "hrom_newton", "hrom_backward", "hrom_strerror",
             "hrom_num_variants", "hrom_plan_set_variant", "hrom_plan_profile",
-            "hrom_plan_tangent_ms")
+            "hrom_plan_tangent_ms", "hrom_cauchy")
 
 
 class HromError(RuntimeError):
@@ -63,6 +63,7 @@ def load(path: str = LIB_PATH):
     L.hrom_update.argtypes = [P, P, d, P, P, P]
     L.hrom_newton.argtypes = [P, P, P, P, d, i32, P, P, P, P, P]
     L.hrom_backward.argtypes = [P, P, P, P, P, P, P, P]
+    L.hrom_cauchy.argtypes = [P, P, P, P, P]
     L.hrom_num_variants.argtypes = []
     L.hrom_num_variants.restype = i32
     L.hrom_plan_set_variant.argtypes = [P, i32, i32]
@@ -213,6 +214,12 @@ class Plan:
         _check(load().hrom_newton(self._h, _ptr(theta), _ptr(Fbar), _ptr(a), float(tol),
                                   int(max_it), _ptr(Pbar), _ptr(Cbar), _ptr(rnorm), _ptr(status),
                                   _stream(stream)), "hrom_newton")
+
+    def cauchy(self, sigma, dsdD, status, stream=None):
+        """Cauchy stress [9][N] and Updated-Lagrangian tangent [81][N] (or None)
+        of the last condensed state."""
+        _check(load().hrom_cauchy(self._h, _ptr(sigma), _ptr(dsdD), _ptr(status), _stream(stream)),
+               "hrom_cauchy")
 
     def backward(self, theta, a, gPbar, gFbar, gtheta, status, stream=None):
         _check(load().hrom_backward(self._h, _ptr(theta), _ptr(a), _ptr(gPbar), _ptr(gFbar),

@@ -138,7 +138,7 @@ const char* hrom_strerror(int code) {
         case HROM_E_HIP: return "HIP runtime error";
         case HROM_E_ORDER: return "call order violated (evaluate before condense, condense before update/backward)";
         case HROM_E_NOMEM: return "device allocation failed";
-        case HROM_E_UNSUPPORTED: return "size outside the supported range";
+        case HROM_E_UNSUPPORTED: return "not supported (size outside the supported range, or an output the plan's mode does not provide)";
         default: return "unknown error";
     }
 }
@@ -484,6 +484,16 @@ int hrom_newton(hrom_plan plan, const double* theta, const double* Fbar, double*
         rc = hip_status();
     }
     return rc;
+}
+
+int hrom_cauchy(hrom_plan plan, double* sigma, double* dsdD, int32_t* status, hipStream_t stream) {
+    if (!plan || !sigma || !status) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    if (p.stage < 2) return HROM_E_ORDER;
+    if (!(p.flags & HROM_OBJECTIVE)) return HROM_E_UNSUPPORTED;
+    CauchyArgs ca{p.N, p.polar, p.Palg, p.Cr, sigma, dsdD, status};
+    launch_cauchy(ca, stream);
+    return hip_status();
 }
 
 int hrom_backward(hrom_plan plan, const double* theta, const double* a, const double* gPbar,

@@ -170,6 +170,17 @@ struct PushArgs {
 };
 void launch_pushout(const PushArgs& a, hipStream_t s);
 
+struct CauchyArgs {
+    int64_t N;
+    const double* polar;
+    const double* Palg;   // [9][N] RVE frame
+    const double* Cr;     // [81][N] RVE frame
+    double* sigma;        // [9][N]
+    double* dsdD;         // [81][N] or null
+    int* status;
+};
+void launch_cauchy(const CauchyArgs& a, hipStream_t s);
+
 struct UpdateArgs {
     int m;
     int64_t first, count, N;

@@ -175,6 +175,102 @@ void launch_pushout(const PushArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_pushout, dim3(nblocks(9 * a.N, 256)), dim3(256), 0, s, a);
 }
 
+// ---------------------------------------------------------------- Updated-Lagrangian output
+// Cauchy stress and the tangent dsigma/dD of App. A from the RVE-frame
+// algorithmic stress and condensed tangent.  The Biot relation (eq.
+// biotstress) T = J/2 (R^T sigma F^-T + F^-1 sigma R) reads, for the rotated
+// stress Z = R^T sigma R and F = R U,  Z U^-1 + U^-1 Z = (2/J) T, i.e.
+// U Z + Z U = (2/J) U T U: one symmetric Lyapunov solve in the eigenbasis of
+// U, then sigma = R Z R^T.  Tangent column (k, l): stretch rate
+// Udot = sym(R^T E_kl F) (constant rotation over the step), dT = sym(Cr Udot),
+// dsigma = the same Biot inversion of dT.  One thread per (column, point),
+// column-major like the push-out; the column-0 thread also writes sigma.
+__global__ void __launch_bounds__(256) k_cauchy(CauchyArgs A) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = A.N;
+    if (t >= 9 * N) return;
+    const int kc = (int)(t / N);
+    const int64_t b = t - (int64_t)kc * N;
+    double F[9], V[9], u[3];
+    load_polar(A.polar, N, b, F, V, u);
+    double U[9], Ui[9], R[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            U[3 * i + j] = V[3 * i] * u[0] * V[3 * j] + V[3 * i + 1] * u[1] * V[3 * j + 1] +
+                           V[3 * i + 2] * u[2] * V[3 * j + 2];
+            Ui[3 * i + j] = V[3 * i] / u[0] * V[3 * j] + V[3 * i + 1] / u[1] * V[3 * j + 1] +
+                            V[3 * i + 2] / u[2] * V[3 * j + 2];
+        }
+    mul3(F, Ui, R);
+    const double c2J = 2.0 / (u[0] * u[1] * u[2]);   // 2 / J, J = det U
+    // sigma = R Z R^T with U Z + Z U = (2/J) U T U
+    auto biot_to_cauchy = [&](const double* T, double* sig) {
+        double a1[9], B[9], Z[9], RZ[9];
+        mul3(U, T, a1);
+        mul3(a1, U, B);
+#pragma unroll
+        for (int k = 0; k < 9; k++) B[k] *= c2J;
+        lyap_solve(V, u, B, Z);
+        mul3(R, Z, RZ);
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                sig[3 * i + j] = RZ[3 * i] * R[3 * j] + RZ[3 * i + 1] * R[3 * j + 1] + RZ[3 * i + 2] * R[3 * j + 2];
+    };
+    bool fin = true;
+    if (kc == 0) {
+        double T[9], sig[9];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                T[3 * i + j] = 0.5 * (A.Palg[(3 * i + j) * N + b] + A.Palg[(3 * j + i) * N + b]);
+        biot_to_cauchy(T, sig);
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            A.sigma[k * N + b] = sig[k];
+            fin = fin && isfinite(sig[k]);
+        }
+    }
+    if (A.dsdD) {
+        const int ka = kc / 3, kb = kc % 3;
+        // Udot_ij = R_{ka i} F_{kb j}, symmetrised
+        double dU[9];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                dU[3 * i + j] = 0.5 * (R[3 * ka + i] * F[3 * kb + j] + R[3 * ka + j] * F[3 * kb + i]);
+        double dP[9];
+#pragma unroll
+        for (int I = 0; I < 9; I++) {
+            double acc = 0.0;
+#pragma unroll
+            for (int J = 0; J < 9; J++) acc = fma(A.Cr[(9 * I + J) * N + b], dU[J], acc);
+            dP[I] = acc;
+        }
+        double dT[9], dsig[9];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) dT[3 * i + j] = 0.5 * (dP[3 * i + j] + dP[3 * j + i]);
+        biot_to_cauchy(dT, dsig);
+#pragma unroll
+        for (int I = 0; I < 9; I++) {
+            A.dsdD[(9 * I + kc) * N + b] = dsig[I];
+            fin = fin && isfinite(dsig[I]);
+        }
+    }
+    if (!fin) atomicOr(&A.status[b], HROM_PT_NONFINITE);
+}
+
+void launch_cauchy(const CauchyArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_cauchy, dim3(nblocks(9 * a.N, 256)), dim3(256), 0, s, a);
+}
+
 // ---------------------------------------------------------------- update
 // linearised macro stretch increment dU = Linv(dF^T F + F^T dF) (objective)
 // or dF (direct); zero when no increment is given (pure micro Newton step).
