@@ -32,6 +32,10 @@ sys.path.insert(0, ROOT)
 METRIC = "RVE point-evals/s (m=64,Q=512) mixed vs FP64 at 1e-5 rel; % MFMA roofline"
 PEAK = {"bf16": 2.5e15, "fp16": 2.5e15, "fp64": 78.6e12}
 PREC = {"fp64": 0, "bf16": 1, "fp16": 2}
+HBM_PEAK = 8.0e12
+# Updated-Lagrangian output per point: reads the polar split (21), Palg_r (9)
+# and Cr (81) doubles, writes sigma (9) and dsigma/dD (81)
+CAUCHY_BYTES_PER_POINT = 8 * (21 + 9 + 81 + 9 + 81)
 
 
 def eval_flops_per_point(m: int, Q: int) -> float:
@@ -124,8 +128,20 @@ def run_gpu(prec_name, cl, F, N, steps, warmup, split=True):
     # one more forward for the accuracy comparison
     plan.eval(th, Fd, st.a, st.status)
     plan.condense(st.Pbar, st.Cbar, st.rnorm, st.status)
+    # Updated-Lagrangian output of the condensed state (not part of the step):
+    # ten launches between two events on the launch stream
+    sig, dsdD = plan.zeros_points(9), plan.zeros_points(81)
+    plan.cauchy(sig, dsdD, st.status)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        plan.cauchy(sig, dsdD, st.status)
+    e1.record()
     torch.cuda.synchronize()
-    out = dict(wall=wall, eval_ms=eval_ms, tan_ms=float(np.mean(tan_ms)), a=st.a.clone(),
+    cauchy_ms = e0.elapsed_time(e1) / 10
+    del sig, dsdD
+    out = dict(wall=wall, eval_ms=eval_ms, tan_ms=float(np.mean(tan_ms)), cauchy_ms=cauchy_ms,
+               a=st.a.clone(),
                Pbar=st.Pbar.clone(),
                Cbar=st.Cbar.clone(), status=int(st.status.max().item()),
                variant=tuned["variant"], tune_ms={str(k): v for k, v in tuned["ms"].items()})
@@ -336,6 +352,11 @@ def main():
                      "eval_ms": res["eval_ms"],
                      "eval_tflops": eval_flops_per_point(m, Q) * N / (res["eval_ms"] * 1e-3) / 1e12},
         "step_tflops": step_flops_per_point(m, Q) * N / (ms_step * 1e-3) / 1e12,
+        "ul_output": {"kernel": "k_cauchy: Cauchy stress and App. A tangent of the condensed state",
+                      "ms": res["cauchy_ms"], "bound": "hbm",
+                      "bytes_per_point": CAUCHY_BYTES_PER_POINT,
+                      "achieved_GBs": CAUCHY_BYTES_PER_POINT * N / (res["cauchy_ms"] * 1e-3) / 1e9,
+                      "frac": CAUCHY_BYTES_PER_POINT * N / (res["cauchy_ms"] * 1e-3) / HBM_PEAK},
         "status_max": res["status"],
         "tuned_variant": res["variant"], "variant_eval_ms": res["tune_ms"],
         "fp64": fp64,
