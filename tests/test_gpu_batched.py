@@ -1,6 +1,7 @@
 """Batched uneven RVE clusters (m in {8..96}, Q = 6 m, Zipf split) in one plan:
-grouped launches with one persistent, cost-sorted launch for the tangent
-contraction; and a HIP graph capturing 10 monolithic iterations."""
+the tangent contraction of every cluster in cost-ordered tile launches (FP64:
+one persistent work-queue launch), the other steps once per cluster; and a HIP
+graph capturing 10 monolithic iterations."""
 import numpy as np
 import pytest
 
