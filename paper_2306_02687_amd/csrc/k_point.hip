@@ -87,14 +87,15 @@ __device__ __forceinline__ void load_polar(const double* polar, int64_t N, int64
 // Ubar S + S Ubar = 2 T, Pbar = Fbar S; tangent column k along E_k:
 // dU = Linv(E_k^T F + F^T E_k), dT = sym(Cr dU),
 // dS = Linv(2 dT - dU S - S dU), Cbar e_k = E_k S + F dS.
-// One thread per (column k, macro point), k-major so that every load and
-// store is coalesced over the points; the k = 0 thread also writes Pbar, S.
+// One thread per (column k, macro point); the nine column threads of a point
+// are neighbours in one wavefront, so the point's tangent entries are fetched
+// once per wavefront; the k = 0 thread also writes Pbar, S.
 __global__ void __launch_bounds__(256) k_pushout(PushArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t N = A.N;
     if (t >= 9 * N) return;
-    const int kc = (int)(t / N);
-    const int64_t b = t - (int64_t)kc * N;
+    const int64_t b = t / 9;
+    const int kc = (int)(t - 9 * b);
     double Pa[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) Pa[k] = A.Palg[k * N + b];
@@ -184,13 +185,14 @@ void launch_pushout(const PushArgs& a, hipStream_t s) {
 // U, then sigma = R Z R^T.  Tangent column (k, l): stretch rate
 // Udot = sym(R^T E_kl F) (constant rotation over the step), dT = sym(Cr Udot),
 // dsigma = the same Biot inversion of dT.  One thread per (column, point),
-// column-major like the push-out; the column-0 thread also writes sigma.
+// the nine columns of a point neighbours as in the push-out; the column-0
+// thread also writes sigma.
 __global__ void __launch_bounds__(256) k_cauchy(CauchyArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t N = A.N;
     if (t >= 9 * N) return;
-    const int kc = (int)(t / N);
-    const int64_t b = t - (int64_t)kc * N;
+    const int64_t b = t / 9;
+    const int kc = (int)(t - 9 * b);
     double F[9], V[9], u[3];
     load_polar(A.polar, N, b, F, V, u);
     double U[9], Ui[9], R[9];
