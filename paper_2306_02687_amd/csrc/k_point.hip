@@ -307,26 +307,37 @@ void launch_stretch_increment(const UpdateArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_stretch_increment, dim3(nblocks(a.N, 256)), dim3(256), 0, s, a);
 }
 
-// a <- a - (y + X dU)  (Sec. 3.2.3), one thread per (mode, point).  Points
-// flagged as failed are left unchanged; without an increment (pure micro
-// Newton step) converged points (rnorm < tol) are frozen.
+// a <- a - (y + X dU)  (Sec. 3.2.3), one thread per (group of kModesPerThread
+// modes, point): the point's dU is read once for the group.  Points flagged
+// as failed are left unchanged; without an increment (pure micro Newton step)
+// converged points (rnorm < tol) are frozen.
+constexpr int kModesPerThread = 4;
 __global__ void __launch_bounds__(256) k_update(UpdateArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)A.m * A.count) return;
-    const int k = (int)(t / A.count);
-    const int64_t pl = t - (int64_t)k * A.count;
+    const int ng = (A.m + kModesPerThread - 1) / kModesPerThread;
+    if (t >= (int64_t)ng * A.count) return;
+    const int kg = (int)(t / A.count);
+    const int64_t pl = t - (int64_t)kg * A.count;
     const int64_t b = A.first + pl;
     if (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) return;
     if (!A.dFbar && !(A.rnorm[b] >= A.tol)) return;
-    double s = A.y[(int64_t)k * A.count + pl];
+    double dU[9];
 #pragma unroll
-    for (int J = 0; J < 9; J++)
-        s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], A.dU[J * A.N + b], s);
-    A.a[(int64_t)k * A.count + pl] -= s;
+    for (int J = 0; J < 9; J++) dU[J] = A.dU[J * A.N + b];
+#pragma unroll
+    for (int kk = 0; kk < kModesPerThread; kk++) {
+        const int k = kg * kModesPerThread + kk;
+        if (k < A.m) {
+            double s = A.y[(int64_t)k * A.count + pl];
+#pragma unroll
+            for (int J = 0; J < 9; J++) s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], dU[J], s);
+            A.a[(int64_t)k * A.count + pl] -= s;
+        }
+    }
 }
 
 void launch_update(const UpdateArgs& a, hipStream_t s) {
-    const int64_t n = (int64_t)a.m * a.count;
+    const int64_t n = (int64_t)((a.m + kModesPerThread - 1) / kModesPerThread) * a.count;
     hipLaunchKernelGGL(k_update, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
 }
 
@@ -402,21 +413,32 @@ void launch_bw_pushforward(const BwPointArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_bw_pushforward, dim3(nblocks(a.N, 256)), dim3(256), 0, s, a);
 }
 
-// adjoint solve with the stored factor: lambda = Kaa^{-T} KaF g_r = X g_r
+// adjoint solve with the stored factor: lambda = Kaa^{-T} KaF g_r = X g_r, one
+// thread per (group of kModesPerThread modes, point)
 __global__ void __launch_bounds__(256) k_lambda(LambdaArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)A.m * A.count) return;
-    const int k = (int)(t / A.count);
-    const int64_t pl = t - (int64_t)k * A.count;
+    const int ng = (A.m + kModesPerThread - 1) / kModesPerThread;
+    if (t >= (int64_t)ng * A.count) return;
+    const int kg = (int)(t / A.count);
+    const int64_t pl = t - (int64_t)kg * A.count;
     const int64_t b = A.first + pl;
-    double s = 0.0;
+    double gr[9];
 #pragma unroll
-    for (int J = 0; J < 9; J++) s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], A.gr[J * A.N + b], s);
-    A.lam[(int64_t)k * A.count + pl] = s;
+    for (int J = 0; J < 9; J++) gr[J] = A.gr[J * A.N + b];
+#pragma unroll
+    for (int kk = 0; kk < kModesPerThread; kk++) {
+        const int k = kg * kModesPerThread + kk;
+        if (k < A.m) {
+            double s = 0.0;
+#pragma unroll
+            for (int J = 0; J < 9; J++) s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], gr[J], s);
+            A.lam[(int64_t)k * A.count + pl] = s;
+        }
+    }
 }
 
 void launch_lambda(const LambdaArgs& a, hipStream_t s) {
-    const int64_t n = (int64_t)a.m * a.count;
+    const int64_t n = (int64_t)((a.m + kModesPerThread - 1) / kModesPerThread) * a.count;
     hipLaunchKernelGGL(k_lambda, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
 }
 
