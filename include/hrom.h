@@ -166,8 +166,9 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
  * wavefront, sharing every mode-gradient operand, without / with that
  * prefetch (the FP64 kernel reads both as variant 0).  Plans with
  * several clusters: FP64 plans give their persistent tangent launch
- * (variant + 1) x #CUs workgroups; mixed plans launch one workgroup per tile
- * and have no variant.  c = -1 applies to every cluster.  Results do not depend on the
+ * (variant + 1) x #CUs workgroups; mixed plans launch the tangent once per
+ * cluster with that cluster's variant, as above.  c = -1 applies to every
+ * cluster.  Results do not depend on the
  * variant (same arithmetic, same order). */
 int32_t hrom_num_variants(void);
 int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant);

@@ -47,7 +47,7 @@ void free_plan(Plan& p) {
     dfree(p.piv); dfree(p.y); dfree(p.X); dfree(p.Palg); dfree(p.Cr); dfree(p.S);
     dfree(p.rnorm); dfree(p.dU); dfree(p.gr); dfree(p.Lam); dfree(p.lam); dfree(p.rho);
     dfree(p.hr); dfree(p.gth); dfree(p.gth_part);
-    dfree(p.cls_dev); dfree(p.items_tan); dfree(p.items_tan2); dfree(p.counter);
+    dfree(p.cls_dev); dfree(p.items_tan); dfree(p.counter);
 }
 
 int hip_status() { return hipGetLastError() == hipSuccess ? HROM_OK : HROM_E_HIP; }
@@ -76,7 +76,7 @@ int upload(T** dst, const std::vector<T>& v) {
 int build_groups(Plan& p) {
     p.grouped = p.ncl > 1;
     std::vector<ClusterGPU> cg;
-    std::vector<WorkItem> tan, tan2;
+    std::vector<WorkItem> tan;
     p.max_m = 0;
     for (int c = 0; c < p.ncl; c++) {
         const ClusterDev& d = p.cl[c];
@@ -88,11 +88,8 @@ int build_groups(Plan& p) {
         g.wscale = mixed(p) ? wscale_for(d.Q) : 1.0f;
         cg.push_back(g);
         p.max_m = std::max(p.max_m, d.m);
-        // mixed plans: clusters with m <= 64 go to a launch of 8-point tiles,
-        // two points per wavefront
-        if (mixed(p) && d.m <= 64)
-            for (int64_t u = 0; u < (d.count + 7) / 8; u++) tan2.push_back(WorkItem{c, (int)u});
-        else
+        // FP64 plans: the persistent tangent launch takes 4-point tiles
+        if (!mixed(p))
             for (int64_t u = 0; u < (d.count + 3) / 4; u++) tan.push_back(WorkItem{c, (int)u});
     }
     // most expensive tiles first: tangent ~ MT^2 Q
@@ -102,10 +99,7 @@ int build_groups(Plan& p) {
     };
     std::stable_sort(tan.begin(), tan.end(),
                      [&](const WorkItem& x, const WorkItem& y) { return cost_tan(x) > cost_tan(y); });
-    std::stable_sort(tan2.begin(), tan2.end(),
-                     [&](const WorkItem& x, const WorkItem& y) { return cost_tan(x) > cost_tan(y); });
     p.n_tan = (int)tan.size();
-    p.n_tan2 = (int)tan2.size();
     int ncu = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, p.device) == hipSuccess && prop.multiProcessorCount > 0)
@@ -113,7 +107,6 @@ int build_groups(Plan& p) {
     p.persistent_grid = std::min(p.n_tan, 2 * ncu);
     int rc = upload(&p.cls_dev, cg);
     if (rc == HROM_OK) rc = upload(&p.items_tan, tan);
-    if (rc == HROM_OK) rc = upload(&p.items_tan2, tan2);
     if (rc == HROM_OK) rc = dalloc(&p.counter, 1);
     return rc;
 }
@@ -260,9 +253,9 @@ int32_t hrom_num_variants(void) { return 6; }
 int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant) {
     if (!plan || variant < 0 || variant >= hrom_num_variants() || c < -1 || c >= plan->p.ncl) return HROM_E_INVALID;
     Plan& p = plan->p;
-    if (p.grouped) {
-        // FP64: one persistent launch for every cluster, the variant picks its
-        // grid (mixed plans launch one workgroup per tile: no choice)
+    if (p.grouped && !mixed(p)) {
+        // FP64 with several clusters: one persistent launch for every
+        // cluster, the variant picks its grid
         int ncu = 256;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, p.device) == hipSuccess && prop.multiProcessorCount > 0)
@@ -326,6 +319,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
     PointArgs pa{p.N, (p.flags & HROM_OBJECTIVE) ? 1 : 0, Fbar, p.Fr, p.polar, status};
     launch_prepare(pa, stream);
     const size_t tsz = mixed(p) ? sizeof(float) : sizeof(double);
+    std::vector<EvalArgs> tan_args;   // per-cluster tangent launches of a mixed plan with several clusters
     for (const auto& c : p.cl) {
         EvalArgs e{};
         e.m = c.m; e.Q = c.Q; e.Qpad = c.Qpad; e.MP = c.MP; e.MT = c.MT; e.KS = c.KS;
@@ -339,29 +333,35 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         e.status = status;
         e.wscale = wscale_for(c.Q);
         int rc = launch_kin(mixed(p) ? 1 : 0, e, stream);
-        if (p.grouped) { if (rc != HROM_OK) return rc; continue; }
+        if (rc != HROM_OK) return rc;
+        if (p.grouped) {
+            tan_args.push_back(e);
+            continue;
+        }
         // single-cluster plans: the events bracket the (only) tangent launch
-        if (p.profile && p.ncl == 1) (void)hipEventRecord(p.ev_tan[0], stream);
-        if (rc == HROM_OK)
-            rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, c.variant, e, stream)
-                          : launch_eval_f64(c.MT, c.variant, e, stream);
-        if (p.profile && p.ncl == 1) (void)hipEventRecord(p.ev_tan[1], stream);
+        if (p.profile) (void)hipEventRecord(p.ev_tan[0], stream);
+        rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, c.variant, e, stream)
+                      : launch_eval_f64(c.MT, c.variant, e, stream);
+        if (p.profile) (void)hipEventRecord(p.ev_tan[1], stream);
         if (rc != HROM_OK) return rc;
     }
     if (p.grouped) {
-        GroupCall g = group_call(p);
-        g.theta = theta; g.Fr = p.Fr; g.a = a; g.qs = p.qs; g.Khat = p.Khat;
-        g.r = p.r; g.Pr = p.Pr; g.status = status;
+        // several clusters, after all kinematics launches: FP64 plans run the
+        // tangent contraction of every cluster in one persistent launch over a
+        // cost-sorted work queue; mixed plans launch it once per cluster, each
+        // at the occupancy its mode count allows
         int rc = HROM_OK;
         if (p.profile) (void)hipEventRecord(p.ev_tan[0], stream);
-        g.items = p.items_tan; g.nitems = p.n_tan;
         if (!mixed(p)) {
+            GroupCall g = group_call(p);
+            g.theta = theta; g.Fr = p.Fr; g.a = a; g.qs = p.qs; g.Khat = p.Khat;
+            g.r = p.r; g.Pr = p.Pr; g.status = status;
+            g.items = p.items_tan; g.nitems = p.n_tan;
             rc = launch_tan_persistent(g, p.persistent_grid, stream);
         } else {
-            const bool split = (p.flags & HROM_SPLIT) != 0;
-            rc = launch_tan_tiles(p.prec, split, false, g, stream);
-            g.items = p.items_tan2; g.nitems = p.n_tan2;
-            if (rc == HROM_OK) rc = launch_tan_tiles(p.prec, split, true, g, stream);
+            for (int k = 0; k < p.ncl && rc == HROM_OK; k++)
+                rc = launch_eval_mixed(p.cl[k].MT, p.prec, (p.flags & HROM_SPLIT) != 0, p.cl[k].variant,
+                                       tan_args[k], stream);
         }
         if (p.profile) (void)hipEventRecord(p.ev_tan[1], stream);
         if (rc != HROM_OK) return rc;

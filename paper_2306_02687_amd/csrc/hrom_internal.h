@@ -93,10 +93,9 @@ struct Plan {
     bool grouped = false;
     int max_m = 0;
     ClusterGPU* cls_dev = nullptr;
-    WorkItem* items_tan = nullptr;   // 4-point tiles, decreasing cost (mixed plans: m > 64)
-    WorkItem* items_tan2 = nullptr;  // mixed plans: 8-point tiles of the clusters with m <= 64
+    WorkItem* items_tan = nullptr;   // FP64 plans: 4-point tiles, decreasing cost
     int persistent_grid = 512;       // FP64 plans: workgroups of the persistent tangent launch
-    int n_tan = 0, n_tan2 = 0;
+    int n_tan = 0;
     int* counter = nullptr;          // work-queue head of the persistent tangent launch (FP64)
 };
 
@@ -277,9 +276,9 @@ void launch_build_layouts(const LayoutArgs& a, hipStream_t s);
 
 
 // ---------------------------------------------------------------- grouped launches
-// Several RVE clusters in one launch (the tangent contraction and the
-// monolithic update; the kinematics, the condensation and the adjoint launch
-// once per cluster, each at the occupancy its mode count allows): a kernel
+// Several RVE clusters in one launch (the FP64 tangent contraction and the
+// monolithic update; every other step, and the mixed tangent, launch once per
+// cluster, each at the occupancy its mode count allows): a kernel
 // body runs on one work item (cluster c, tile `unit` of that cluster); the
 // per-cluster constants live in a device array built at plan creation, the
 // per-call pointers in GroupCall.
@@ -326,7 +325,6 @@ struct GroupCall {
 };
 
 int launch_tan_persistent(const GroupCall& g, int grid, hipStream_t s);   // FP64
-int launch_tan_tiles(int prec, bool split, bool wide, const GroupCall& g, hipStream_t s);   // mixed
 void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);
 void set_kernel_attributes();
 

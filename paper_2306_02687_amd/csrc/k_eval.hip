@@ -868,49 +868,6 @@ __global__ void __launch_bounds__(256, 1) k_tan_persistent(GroupCall G) {
     }
 }
 
-// Mixed plans: one workgroup per tile, tiles ordered by decreasing cost (the
-// dispatcher hands out the expensive ones first), two wavefronts per SIMD.
-// WIDE: clusters with m <= 64 in 8-point tiles, two macro points per
-// wavefront; else clusters with m > 64 in 4-point tiles, one point per
-// wavefront.
-template <int PREC, bool SPLIT, bool WIDE>
-__global__ void __launch_bounds__(256, 2) k_tan_tiles(GroupCall G) {
-    __shared__ v4u32 s_w[4][kCQ * kWR];
-    const WorkItem w = G.items[blockIdx.x];
-    const EvalArgs A = group_eval_args(G, w.c, sizeof(float));
-    const int ma = (A.m + 15) / 16;
-    if constexpr (WIDE) {
-        const int64_t pl0 = (int64_t)w.unit * 8;
-        switch (ma) {
-            case 1: tan_mixed_body<1, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
-            case 2: tan_mixed_body<2, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
-            case 3: tan_mixed_body<3, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
-            default: tan_mixed_body<4, PREC, SPLIT, false, 2>(A, pl0, s_w); break;
-        }
-    } else {
-        const int64_t pl0 = (int64_t)w.unit * 4;   // the host routes only m > 64 here
-        if (ma <= 5) tan_mixed_body<5, PREC, SPLIT, false, 1>(A, pl0, s_w);
-        else tan_mixed_body<6, PREC, SPLIT, false, 1>(A, pl0, s_w);
-    }
-}
-
-template <int PREC, bool SPLIT>
-static void launch_tiles_t(bool wide, const GroupCall& g, hipStream_t s) {
-    const dim3 gr(g.nitems), bl(256);
-    if (wide) hipLaunchKernelGGL((k_tan_tiles<PREC, SPLIT, true>), gr, bl, 0, s, g);
-    else hipLaunchKernelGGL((k_tan_tiles<PREC, SPLIT, false>), gr, bl, 0, s, g);
-}
-
-int launch_tan_tiles(int prec, bool split, bool wide, const GroupCall& g, hipStream_t s) {
-    if (prec == HROM_FP64) return HROM_E_INVALID;
-    if (g.nitems == 0) return HROM_OK;
-    if (prec == HROM_MIXED_BF16 && split) launch_tiles_t<HROM_MIXED_BF16, true>(wide, g, s);
-    else if (prec == HROM_MIXED_BF16) launch_tiles_t<HROM_MIXED_BF16, false>(wide, g, s);
-    else if (split) launch_tiles_t<HROM_MIXED_FP16, true>(wide, g, s);
-    else launch_tiles_t<HROM_MIXED_FP16, false>(wide, g, s);
-    return HROM_OK;
-}
-
 int launch_tan_persistent(const GroupCall& g, int grid, hipStream_t s) {
     if (g.nitems == 0) return HROM_OK;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, g.counter);
