@@ -1,7 +1,10 @@
 """Autotuner of the tangent-contraction launch variants.
 
 For a plan it times every launch variant of ``hrom_eval`` (kinematics plus
-tangent contraction) on the plan's own inputs and keeps the fastest.  The
+tangent contraction) on the plan's own inputs and keeps the fastest.  Mixed
+plans with several clusters launch the tangent once per cluster, so there the
+variant is tuned cluster by cluster (the others held at their current
+choice) and ``variant`` is the list of per-cluster choices.  The
 choice is cached on disk, keyed by GPU architecture, precision, split flag and
 the (m, Q, count) of every cluster, so later plans of the same shape skip the
 timing.  The cache file is ``$HROM_TUNE_CACHE`` or
@@ -48,30 +51,52 @@ def _store_cache(path, cache):
 def autotune(plan: B.Plan, theta, Fbar, a, reps: int = 3, use_cache: bool = True,
              path: str | None = None) -> dict:
     """Pick the fastest launch variant for ``plan``; returns
-    ``{"variant": v, "ms": {v: ms, ...}, "cached": bool}``."""
+    ``{"variant": v, "ms": {v: ms, ...}, "cached": bool}`` (mixed plans with
+    several clusters: ``v`` is the list of per-cluster variants and ``ms``
+    maps each cluster to its sweep)."""
     path = path or cache_path()
     key = plan_key(plan)
     cache = _load_cache(path) if use_cache else {}
+    per_cluster = plan.precision != B.FP64 and len(plan.clusters) > 1
     if key in cache:
-        v = int(cache[key]["variant"])
-        plan.set_variant(v)
+        v = cache[key]["variant"]
+        if isinstance(v, list):
+            for c, vc in enumerate(v):
+                plan.set_variant(int(vc), c)
+        else:
+            v = int(v)
+            plan.set_variant(v)
         return {"variant": v, "ms": cache[key].get("ms", {}), "cached": True}
     status = plan.status()
-    times = {}
-    for v in range(B.Plan.num_variants()):
-        plan.set_variant(v)
-        plan.eval(theta, Fbar, a, status)           # warm-up (first launch of the variant)
-        torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        ev[0].record()
-        for _ in range(reps):
-            plan.eval(theta, Fbar, a, status)
-        ev[1].record()
-        torch.cuda.synchronize()
-        times[v] = ev[0].elapsed_time(ev[1]) / reps
-    best = min(times, key=times.get)
-    plan.set_variant(best)
+
+    def sweep(cluster):
+        times = {}
+        for v in range(B.Plan.num_variants()):
+            plan.set_variant(v, cluster)
+            plan.eval(theta, Fbar, a, status)       # warm-up (first launch of the variant)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            for _ in range(reps):
+                plan.eval(theta, Fbar, a, status)
+            ev[1].record()
+            torch.cuda.synchronize()
+            times[v] = ev[0].elapsed_time(ev[1]) / reps
+        best = min(times, key=times.get)
+        plan.set_variant(best, cluster)
+        return best, times
+
+    if per_cluster:
+        best, times = [], {}
+        for c in range(len(plan.clusters)):
+            b, t = sweep(c)
+            best.append(b)
+            times[c] = t
+    else:
+        best, times = sweep(-1)
     if use_cache:
-        cache[key] = {"variant": best, "ms": {str(k): t for k, t in times.items()}}
+        ms = ({str(c): {str(k): x for k, x in t.items()} for c, t in times.items()} if per_cluster
+              else {str(k): x for k, x in times.items()})
+        cache[key] = {"variant": best, "ms": ms}
         _store_cache(path, cache)
     return {"variant": best, "ms": times, "cached": False}
