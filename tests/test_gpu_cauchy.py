@@ -132,3 +132,30 @@ def test_cauchy_headline_workload_sample(P, orc):
     print("cauchy fullsize sigma", es, "tangent", ec, flush=True)
     assert es < BAR[1] and ec < BAR[1]
     plan.close()
+
+
+def test_cauchy_failure_isolation(P):
+    """A non-finite macro point keeps its NONFINITE flag through hrom_cauchy
+    and leaves every other point's sigma and dsigma/dD bitwise unchanged."""
+    log_case("cauchy_isolation")
+    m, Q, N = 13, 37, 6
+    cl = make_cluster(m, Q, 7700)
+    F, _, _ = make_macro_points(N, 7701, amp=0.08, max_angle=1.0)
+    a = 0.02 * np.random.default_rng(7702).standard_normal((N, m))
+    outs = []
+    for bad in (False, True):
+        Fb = F.copy()
+        if bad:
+            Fb[2, 1, 1] = np.nan
+        plan, st = _state(P, [(cl, N)], 0, Fb, [a])
+        sig, dsdD = plan.zeros_points(9), plan.zeros_points(81)
+        plan.cauchy(sig, dsdD, st)
+        torch.cuda.synchronize()
+        outs.append((sig.cpu().numpy(), dsdD.cpu().numpy(), st.cpu().numpy()))
+        plan.close()
+    (s0, c0, st0), (s1, c1, st1) = outs
+    assert not st0.any()
+    assert st1[2] & 8 and not np.delete(st1, 2).any()
+    keep = [b for b in range(N) if b != 2]
+    assert np.array_equal(s0[:, keep], s1[:, keep]) and np.array_equal(c0[:, keep], c1[:, keep])
+    assert np.isfinite(s1).all() and np.isfinite(c1).all()
