@@ -68,6 +68,16 @@ def read_traffic(kernel_tag: str, variant: int):
     return float(m.group(1)) if m else None
 
 
+def read_cauchy_traffic(m, Q):
+    """HBM bytes per launch of the Updated-Lagrangian output kernel from its
+    committed counter summary, if present."""
+    path = os.path.join(ROOT, "profiles", f"cauchy_m{m}_q{Q}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    m_ = re.search(r"traffic_bytes_per_launch\[k_cauchy\]:\s*([0-9.eE+]+)", open(path).read())
+    return float(m_.group(1)) if m_ else None
+
+
 def build_inputs(N, m, Q, amp, seed):
     from hrom_inputs import make_cluster, make_macro_points
     cl = make_cluster(m, Q, seed)
@@ -356,7 +366,8 @@ def main():
                       "ms": res["cauchy_ms"], "bound": "hbm",
                       "bytes_per_point": CAUCHY_BYTES_PER_POINT,
                       "achieved_GBs": CAUCHY_BYTES_PER_POINT * N / (res["cauchy_ms"] * 1e-3) / 1e9,
-                      "frac": CAUCHY_BYTES_PER_POINT * N / (res["cauchy_ms"] * 1e-3) / HBM_PEAK},
+                      "frac": CAUCHY_BYTES_PER_POINT * N / (res["cauchy_ms"] * 1e-3) / HBM_PEAK,
+                      "traffic": read_cauchy_traffic(m, Q)},
         "status_max": res["status"],
         "tuned_variant": res["variant"], "variant_eval_ms": res["tune_ms"],
         "fp64": fp64,
