@@ -434,13 +434,6 @@ static int update_impl(Plan& p, const double* dFbar, double tol, double* a, cons
     u.status = status;
     u.tol = tol;
     launch_stretch_increment(u, stream);
-    if (p.grouped) {
-        GroupCall g = group_call(p);
-        g.y = p.y; g.X = p.X; g.dU = p.dU; g.dFbar = dFbar; g.rnorm = p.rnorm; g.tol = tol;
-        g.status = const_cast<int*>(status); g.a_out = a;
-        launch_update_grouped(g, p.a_len, stream);
-        return hip_status();
-    }
     for (const auto& c : p.cl) {
         u.m = c.m;
         u.first = c.first;

@@ -276,9 +276,9 @@ void launch_build_layouts(const LayoutArgs& a, hipStream_t s);
 
 
 // ---------------------------------------------------------------- grouped launches
-// Several RVE clusters in one launch (the FP64 tangent contraction and the
-// monolithic update; every other step, and the mixed tangent, launch once per
-// cluster, each at the occupancy its mode count allows): a kernel
+// Several RVE clusters in one launch (the FP64 tangent contraction; every
+// other step, and the mixed tangent, launch once per cluster, each at the
+// occupancy its mode count allows): a kernel
 // body runs on one work item (cluster c, tile `unit` of that cluster); the
 // per-cluster constants live in a device array built at plan creation, the
 // per-call pointers in GroupCall.
@@ -314,18 +314,9 @@ struct GroupCall {
     double* r;
     double* Pr;
     int* status;
-    // update
-    double* y;
-    double* X;
-    double* rnorm;
-    const double* dFbar;
-    const double* dU;
-    double tol;
-    double* a_out;
 };
 
 int launch_tan_persistent(const GroupCall& g, int grid, hipStream_t s);   // FP64
-void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s);
 void set_kernel_attributes();
 
 }  // namespace hrom

@@ -607,33 +607,4 @@ void launch_build_layouts(const LayoutArgs& a, hipStream_t s) {
     }
 }
 
-// grouped forms over the concatenated mode-indexed array of every cluster
-__device__ inline int find_cluster_by_offset(const GroupCall& G, int64_t t) {
-    int c = 0;
-    while (c + 1 < G.ncl && t >= G.cls[c + 1].off_a) c++;
-    return c;
-}
-
-__global__ void __launch_bounds__(256) k_update_grouped(GroupCall G, int64_t a_len) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a_len) return;
-    const ClusterGPU& C = G.cls[find_cluster_by_offset(G, t)];
-    const int64_t loc = t - C.off_a;
-    const int k = (int)(loc / C.count);
-    const int64_t pl = loc - (int64_t)k * C.count;
-    const int64_t b = C.first + pl;
-    if (G.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) return;
-    if (!G.dFbar && !(G.rnorm[b] >= G.tol)) return;
-    const double* y = G.y + C.off_a;
-    const double* X = G.X + 9 * C.off_a;
-    double s = y[(int64_t)k * C.count + pl];
-#pragma unroll
-    for (int J = 0; J < 9; J++) s = fma(X[((int64_t)k * 9 + J) * C.count + pl], G.dU[J * G.N + b], s);
-    G.a_out[t] -= s;
-}
-
-void launch_update_grouped(const GroupCall& g, int64_t a_len, hipStream_t s) {
-    hipLaunchKernelGGL(k_update_grouped, dim3(nblocks(a_len, 256)), dim3(256), 0, s, g, a_len);
-}
-
 }  // namespace hrom
