@@ -22,6 +22,8 @@
  * Ubar; the returned macro stress is Pbar = Fbar S with Ubar S + S Ubar =
  * 2 sym(Palg) (the second-Piola form of eqs. workconjugacy / biotstress) and
  * Cbar = dPbar/dFbar.  Without the flag Fr = Fbar and Pbar = Palg, Cbar = Cr.
+ * For codes in the Updated-Lagrangian form, hrom_cauchy returns the Cauchy
+ * stress of the same state and the tangent dsigma/dD of the paper's App. A.
  *
  * Conventions.
  *  - 3x3 tensors are flattened row-major, I = 3 i + j; tangents are
