@@ -599,6 +599,7 @@ template <int MA, int PREC, bool SPLIT, bool PF, int NP = 1>
 __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ * kWR]) {
     constexpr int NA = MA * (MA + 1) / 2;
     constexpr int QR = kCQ / NP;   // ECM points per LDS round
+    constexpr int kUnrollQ = NP == 2 ? 4 : 2;   // ECM points per unrolled step (registers allow 4 with two points)
     static_assert(NP == 1 || NP == 2, "one or two points per wavefront");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
@@ -689,7 +690,7 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
         v4u32 Wq[NP];
 #pragma unroll
         for (int pp = 0; pp < NP; pp++) Wq[pp] = sw[pp * QR * kWR + wrec];
-#pragma unroll 2
+#pragma unroll(kUnrollQ)
         for (int qi = 0; qi < QR; qi++) {
             const int q = q0 + qi;
             v4u32 Wn[NP];
