@@ -44,6 +44,19 @@ def test_strerror_and_invalid_arguments_without_gpu():
     arr[0] = binding._Cluster(8, 32, 1, 1, 1, 0, 10)
     assert lib.hrom_plan_create(ctypes.byref(h), arr, 1, 11, 0, 1) == -1
     assert lib.hrom_plan_create(ctypes.byref(h), arr, 1, 10, 7, 1) == -1
+    # empty inputs: no macro points at all, or a cluster that owns none
+    assert lib.hrom_plan_create(ctypes.byref(h), arr, 1, 0, 0, 1) == -1
+    arr[0] = binding._Cluster(8, 32, 1, 1, 1, 0, 0)
+    assert lib.hrom_plan_create(ctypes.byref(h), arr, 1, 0, 0, 1) == -1
+    # cluster slices must tile [0, N) in order
+    two = (binding._Cluster * 2)()
+    two[0] = binding._Cluster(8, 32, 1, 1, 1, 0, 4)
+    two[1] = binding._Cluster(8, 32, 1, 1, 1, 5, 6)
+    assert lib.hrom_plan_create(ctypes.byref(h), two, 2, 10, 0, 1) == -1
+    two[1] = binding._Cluster(8, 32, 1, 1, 1, 4, 5)     # covers 9 of 10 points
+    assert lib.hrom_plan_create(ctypes.byref(h), two, 2, 10, 0, 1) == -1
+    assert lib.hrom_newton(None, None, None, None, 1e-10, 4, None, None, None, None, None) == -1
+    assert lib.hrom_cauchy(None, None, None, None, None) == -1
     assert lib.hrom_eval(None, None, None, None, None, None, None, None, None, None, None) == -1
     assert lib.hrom_condense(None, None, None, None, None, None) == -1
     assert lib.hrom_update(None, None, 0.0, None, None, None) == -1
