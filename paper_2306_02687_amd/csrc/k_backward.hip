@@ -206,24 +206,27 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
                 nh_apply<double>(Fi, mu, la, ell, v, Av);
             }
             const double wo = ok ? wq : 0.0;
-            double dmu = 0.0, dla = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int j = 0; j < 3; j++) {
-                    dmu = fma(v[3 * i + j], F[3 * i + j] - Fi[3 * j + i], dmu);
-                    dla = fma(v[3 * i + j], ell * Fi[3 * j + i], dla);
-                }
-#pragma unroll
-            for (int I = 0; I < 9; I++) h[I] = fma(wo, Av[I], h[I]);
-            const double wm = ph ? 0.0 : wo, wi = ph ? wo : 0.0;
-            gt[0] = fma(wm, dmu, gt[0]);
-            gt[1] = fma(wm, dla, gt[1]);
-            gt[2] = fma(wi, dmu, gt[2]);
-            gt[3] = fma(wi, dla, gt[3]);
             if constexpr (RHO) {
+                // the refinement pass needs only rho; h and dL/dtheta come from
+                // the pass that follows it
 #pragma unroll
                 for (int I = 0; I < 9; I++) sV[qq * 9 + I][p] = (LT)(wo * Av[I]);
+            } else {
+                double dmu = 0.0, dla = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+#pragma unroll
+                    for (int j = 0; j < 3; j++) {
+                        dmu = fma(v[3 * i + j], F[3 * i + j] - Fi[3 * j + i], dmu);
+                        dla = fma(v[3 * i + j], ell * Fi[3 * j + i], dla);
+                    }
+#pragma unroll
+                for (int I = 0; I < 9; I++) h[I] = fma(wo, Av[I], h[I]);
+                const double wm = ph ? 0.0 : wo, wi = ph ? wo : 0.0;
+                gt[0] = fma(wm, dmu, gt[0]);
+                gt[1] = fma(wm, dla, gt[1]);
+                gt[2] = fma(wi, dmu, gt[2]);
+                gt[3] = fma(wi, dla, gt[3]);
             }
         }
         __syncthreads();
@@ -245,28 +248,30 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
     }
     // per-point sums over the LPP threads of the point (consecutive lanes of a
     // wave): fixed butterfly
+    if constexpr (!RHO) {
 #pragma unroll
-    for (int I = 0; I < 9; I++)
+        for (int I = 0; I < 9; I++)
 #pragma unroll
-        for (int off = LPP / 2; off > 0; off >>= 1) h[I] += __shfl_xor(h[I], off);
+            for (int off = LPP / 2; off > 0; off >>= 1) h[I] += __shfl_xor(h[I], off);
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+        for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int off = LPP / 2; off > 0; off >>= 1) gt[i] += __shfl_xor(gt[i], off);
-    if (pp < np) {
-        const int64_t b = A.first + p0 + pp;
-        const bool failed = (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) || sbits[pp];
-        // outputs 0..8 = h_r, 9..12 = dL/dtheta, written by the point's lanes
+            for (int off = LPP / 2; off > 0; off >>= 1) gt[i] += __shfl_xor(gt[i], off);
+        if (pp < np) {
+            const int64_t b = A.first + p0 + pp;
+            const bool failed = (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) || sbits[pp];
+            // outputs 0..8 = h_r, 9..12 = dL/dtheta, written by the point's lanes
 #pragma unroll
-        for (int o0 = 0; o0 < 13; o0 += LPP) {
-            const int o = o0 + qa;
-            double val = 0.0;
+            for (int o0 = 0; o0 < 13; o0 += LPP) {
+                const int o = o0 + qa;
+                double val = 0.0;
 #pragma unroll
-            for (int I = 0; I < 9; I++) val = (o == I) ? h[I] : val;
+                for (int I = 0; I < 9; I++) val = (o == I) ? h[I] : val;
 #pragma unroll
-            for (int i = 0; i < 4; i++) val = (o == 9 + i) ? gt[i] : val;
-            if (o < 9) A.hr[(int64_t)o * A.N + b] = failed ? 0.0 : val;
-            else if (o < 13) A.gth[(int64_t)(o - 9) * A.N + b] = failed ? 0.0 : val;
+                for (int i = 0; i < 4; i++) val = (o == 9 + i) ? gt[i] : val;
+                if (o < 9) A.hr[(int64_t)o * A.N + b] = failed ? 0.0 : val;
+                else if (o < 13) A.gth[(int64_t)(o - 9) * A.N + b] = failed ? 0.0 : val;
+            }
         }
     }
     if constexpr (RHO) {
@@ -323,9 +328,9 @@ static int launch_bw_t(const BackwardArgs& a, hipStream_t s) {
 }
 
 int launch_backward_b(const BackwardArgs& a, hipStream_t s) {
-    if (a.mixed && a.with_rho) return launch_bw_t<true, true>(a, s);
-    if (a.mixed) return launch_bw_t<true, false>(a, s);
-    if (a.with_rho) return launch_bw_t<false, true>(a, s);
+    // the refinement pass exists for the low-precision tangents only
+    if (a.mixed) return a.with_rho ? launch_bw_t<true, true>(a, s) : launch_bw_t<true, false>(a, s);
+    if (a.with_rho) return HROM_E_INVALID;
     return launch_bw_t<false, false>(a, s);
 }
 

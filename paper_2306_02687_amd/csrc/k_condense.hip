@@ -349,78 +349,102 @@ int launch_unpack_condense(const CondenseArgs& a, int mode, hipStream_t s) {
 // ---------------------------------------------------------------- refinement
 // lambda <- lambda + Kaa~^{-1} rho with the stored factor of the evaluated
 // (low-precision) Kaa~: one step of iterative refinement of the adjoint solve.
+// One wavefront per point; x stays in registers (lane l holds rows l and
+// l + 64, m <= 96) and x_j reaches every lane by readlane, so the
+// substitutions need no LDS and no barrier.  The factor is read from HBM,
+// the loads of eight steps issued ahead of their dependent updates.
+
+__device__ __forceinline__ double lane_value(double v, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+
+// x_j of the vector held as (x0 on lane j, x1 on lane j - 64)
+__device__ __forceinline__ double row_value(double x0, double x1, int j) {
+    return j < 64 ? lane_value(x0, j) : lane_value(x1, j - 64);
+}
+
 __global__ void __launch_bounds__(64) k_refine_lambda(RefineArgs A) {
-    extern __shared__ double sm[];
+    constexpr int U = 8;
     const int m = A.m, lane = threadIdx.x;
     const int64_t pl = blockIdx.x;
     const int64_t b = A.first + pl;
-    const int st = A.status[b];
-    if (st & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) return;
-    double* L = sm;           // [m][m]
-    double* x = L + m * m;    // [m]
+    if (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) return;
     const double* Lg = A.L + pl * (int64_t)m * m;
-    for (int e = lane; e < m * m; e += 64) L[e] = Lg[e];
-    for (int i = lane; i < m; i += 64) x[i] = A.rho[(int64_t)i * A.count + pl];
     const int* piv = A.piv + pl * m;
+    const int i0 = lane, i1 = lane + 64;
+    const bool h0 = i0 < m, h1 = i1 < m;
+    double x0 = h0 ? A.rho[(int64_t)i0 * A.count + pl] : 0.0;
+    double x1 = h1 ? A.rho[(int64_t)i1 * A.count + pl] : 0.0;
     const bool chol = (piv[0] < 0);
-    __syncthreads();
-    if (chol) {
+    if (!chol) {
+        // the row interchanges of the LU factor, in order
         for (int j = 0; j < m; j++) {
-            __syncthreads();
-            const double z = x[j] / L[j * m + j];
-            __syncthreads();
-            for (int i = lane; i < m; i += 64) {
-                if (i == j) x[j] = z;
-                else if (i > j) x[i] -= L[i * m + j] * z;
-            }
-        }
-        for (int j = m - 1; j >= 0; j--) {
-            __syncthreads();
-            const double z = x[j] / L[j * m + j];
-            __syncthreads();
-            for (int i = lane; i < m; i += 64) {
-                if (i == j) x[j] = z;
-                else if (i < j) x[i] -= L[j * m + i] * z;
-            }
-        }
-    } else {
-        if (lane == 0)
-            for (int j = 0; j < m; j++)
-                if (piv[j] != j) {
-                    const double t = x[j];
-                    x[j] = x[piv[j]];
-                    x[piv[j]] = t;
-                }
-        for (int j = 0; j < m; j++) {
-            __syncthreads();
-            const double z = x[j];
-            __syncthreads();
-            for (int i = lane; i < m; i += 64)
-                if (i > j) x[i] -= L[i * m + j] * z;
-        }
-        for (int j = m - 1; j >= 0; j--) {
-            __syncthreads();
-            const double z = x[j] / L[j * m + j];
-            __syncthreads();
-            for (int i = lane; i < m; i += 64) {
-                if (i == j) x[j] = z;
-                else if (i < j) x[i] -= L[i * m + j] * z;
+            const int pj = piv[j];
+            if (pj != j) {
+                const double xj = row_value(x0, x1, j), xp = row_value(x0, x1, pj);
+                if (i0 == j) x0 = xp;
+                else if (i0 == pj) x0 = xj;
+                if (i1 == j) x1 = xp;
+                else if (i1 == pj) x1 = xj;
             }
         }
     }
-    __syncthreads();
-    for (int i = lane; i < m; i += 64) A.lam[(int64_t)i * A.count + pl] += x[i];
+    // forward: L z = x (unit diagonal for LU); lane i needs L[i][j]
+    for (int j0 = 0; j0 < m; j0 += U) {
+        double l0[U], l1[U], d[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int jj = min(j0 + u, m - 1);
+            l0[u] = h0 ? Lg[(int64_t)i0 * m + jj] : 0.0;
+            l1[u] = h1 ? Lg[(int64_t)i1 * m + jj] : 0.0;
+            d[u] = Lg[(int64_t)jj * m + jj];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int j = j0 + u;
+            if (j < m) {
+                const double xj = row_value(x0, x1, j);
+                const double z = chol ? xj / d[u] : xj;
+                if (i0 == j) x0 = z;
+                else if (i0 > j) x0 -= l0[u] * z;
+                if (i1 == j) x1 = z;
+                else if (i1 > j) x1 -= l1[u] * z;
+            }
+        }
+    }
+    // backward: L^T x = z (Cholesky, lane i needs L[j][i]) or U x = z (LU,
+    // lane i needs U[i][j])
+    for (int j0 = m - 1; j0 >= 0; j0 -= U) {
+        double l0[U], l1[U], d[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int jj = max(j0 - u, 0);
+            const int64_t a0 = chol ? (int64_t)jj * m + i0 : (int64_t)i0 * m + jj;
+            const int64_t a1 = chol ? (int64_t)jj * m + i1 : (int64_t)i1 * m + jj;
+            l0[u] = h0 ? Lg[a0] : 0.0;
+            l1[u] = h1 ? Lg[a1] : 0.0;
+            d[u] = Lg[(int64_t)jj * m + jj];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int j = j0 - u;
+            if (j >= 0) {
+                const double z = row_value(x0, x1, j) / d[u];
+                if (i0 == j) x0 = z;
+                else if (i0 < j) x0 -= l0[u] * z;
+                if (i1 == j) x1 = z;
+                else if (i1 < j) x1 -= l1[u] * z;
+            }
+        }
+    }
+    if (h0) A.lam[(int64_t)i0 * A.count + pl] += x0;
+    if (h1) A.lam[(int64_t)i1 * A.count + pl] += x1;
 }
 
 void launch_refine_lambda(const RefineArgs& a, hipStream_t s) {
-    const size_t bytes = sizeof(double) * ((size_t)a.m * a.m + a.m);
-    static bool attr = false;
-    if (!attr) {
-        hipFuncSetAttribute((const void*)k_refine_lambda, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-        attr = true;
-    }
-    hipLaunchKernelGGL(k_refine_lambda, dim3((unsigned)a.count), dim3(64), bytes, s, a);
+    hipLaunchKernelGGL(k_refine_lambda, dim3((unsigned)a.count), dim3(64), 0, s, a);
 }
 
 }  // namespace hrom
