@@ -352,7 +352,8 @@ int launch_unpack_condense(const CondenseArgs& a, int mode, hipStream_t s) {
 // One wavefront per point; x stays in registers (lane l holds rows l and
 // l + 64, m <= 96) and x_j reaches every lane by readlane, so the
 // substitutions need no LDS and no barrier.  The factor is read from HBM,
-// the loads of eight steps issued ahead of their dependent updates.
+// the loads of sixteen steps (one 128-byte line of a row) issued ahead of
+// their dependent updates.
 
 __device__ __forceinline__ double lane_value(double v, int k) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
@@ -366,7 +367,7 @@ __device__ __forceinline__ double row_value(double x0, double x1, int j) {
 }
 
 __global__ void __launch_bounds__(64) k_refine_lambda(RefineArgs A) {
-    constexpr int U = 8;
+    constexpr int U = 16;
     const int m = A.m, lane = threadIdx.x;
     const int64_t pl = blockIdx.x;
     const int64_t b = A.first + pl;
