@@ -227,6 +227,38 @@ def test_backward_vs_oracle(dev, orc, precision, split, refine):
     plan.close()
 
 
+@pytest.mark.parametrize("m,Q", [(80, 160), (96, 192)])
+@pytest.mark.parametrize("precision,split,refine", [(2, False, False), (1, True, True)])
+def test_backward_refined_beyond_64_modes(dev, orc, m, Q, precision, split, refine):
+    """The refined adjoint with more modes than lanes (rows 64.. of the
+    refinement solve on a wavefront's second register set), up to the
+    largest supported m, vs the oracle's adjoint.  FP16 without split refines
+    by default; BF16 split refines when asked."""
+    from paper_2306_02687_amd import solve
+    log_case("backward_refined", m, Q, precision, split, refine)
+    N = 3
+    cl = make_cluster(m, Q, 5100 + m)
+    F, _, _ = make_macro_points(N, 5101, amp=0.05)
+    th_star, _ = perturbed_theta(5102)
+    target = orc.newton(cl, th_star, F, tol=1e-14)["Pbar"]
+    plan = make_plan(dev, [(cl, N)], precision=precision, split=split, refine=refine)
+    th = solve.theta_dev(THETA_REF)
+    st = solve.newton(plan, th, solve.points_to_soa(F), tol=1e-12)
+    g = 2.0 * (st.Pbar - solve.points_to_soa(target))
+    gF = plan.zeros_points(9)
+    gth = torch.zeros(4, dtype=torch.float64, device="cuda")
+    plan.backward(th, st.a, g.contiguous(), gF, gth, st.status)
+    torch.cuda.synchronize()
+    assert int(st.status.max().item()) == 0
+    ref_o = orc.newton(cl, THETA_REF, F, tol=1e-14)
+    ref = orc.backward(cl, THETA_REF, F, ref_o["a"], 2.0 * (ref_o["Pbar"] - target))
+    egF = rel_err_points(gF.cpu().numpy().T, ref["gF"])
+    egt = np.linalg.norm(gth.cpu().numpy() - ref["gtheta"]) / np.linalg.norm(ref["gtheta"])
+    print("refined m", m, "prec", precision, "gF", egF.max(), "gtheta", egt, flush=True)
+    assert egF.max() < 1e-5 and egt < 1e-5
+    plan.close()
+
+
 def test_clusters_in_one_plan_match_single_plans(dev, orc):
     """Several clusters of different (m, Q) in one plan give bitwise the same
     results as one plan per cluster, and match the oracle."""
