@@ -259,6 +259,57 @@ def test_backward_refined_beyond_64_modes(dev, orc, m, Q, precision, split, refi
     plan.close()
 
 
+def test_backward_refined_lu_path(dev, orc):
+    """An indefinite Kaa (negative shear moduli): every point takes the LU
+    factor.  FP64: the adjoint matches the oracle's at the same state.  Mixed
+    (BF16 and FP16 split): this Kaa is ill-conditioned at one of the points
+    (the mixed condensed tangent itself is off by ~5e-4 there, so the 1e-5 bar
+    of the well-conditioned workloads does not apply); the refinement step,
+    which runs the row interchanges and both substitutions of the LU factor,
+    must then shrink the adjoint's error against the oracle at least five-fold
+    (observed 10-80x)."""
+    from paper_2306_02687_amd import solve
+    log_case("backward_refined_lu")
+    m, Q, N = 24, 144, 6
+    cl = make_cluster(m, Q, 5200)
+    F, _, _ = make_macro_points(N, 5201, amp=0.05)
+    a = 0.01 * np.random.default_rng(5202).standard_normal((N, m))
+    th_np = THETA_REF.copy()
+    th_np[0] = th_np[2] = -1.0
+    g = 0.1 * np.random.default_rng(5203).standard_normal((N, 9))
+    ref = orc.backward(cl, th_np, F, a, g)
+    assert np.all(ref["status"] == 2)
+
+    def adjoint_errors(precision, split, refine):
+        plan = make_plan(dev, [(cl, N)], precision=precision, split=split, refine=refine)
+        th = solve.theta_dev(th_np)
+        a_dev = solve.modes_to_dev(plan, [a])
+        st = plan.status()
+        plan.eval(th, solve.points_to_soa(F), a_dev, st)
+        Pb, Cb = plan.zeros_points(9), plan.zeros_points(81)
+        rn = torch.zeros(N, dtype=torch.float64, device="cuda")
+        plan.condense(Pb, Cb, rn, st)
+        gF = plan.zeros_points(9)
+        gth = torch.zeros(4, dtype=torch.float64, device="cuda")
+        plan.backward(th, a_dev, solve.points_to_soa(g), gF, gth, st)
+        torch.cuda.synchronize()
+        s = st.cpu().numpy()
+        assert np.all(s == 2), s                 # NOT_SPD only: the LU path, nothing else
+        egF = rel_err_points(gF.cpu().numpy().T, ref["gF"]).max()
+        egt = np.linalg.norm(gth.cpu().numpy() - ref["gtheta"]) / np.linalg.norm(ref["gtheta"])
+        plan.close()
+        print("LU path prec", precision, "split", split, "refine", refine, "gF", egF, "gtheta", egt,
+              flush=True)
+        return egF, egt
+
+    egF, egt = adjoint_errors(0, False, False)
+    assert egF < 1e-10 and egt < 1e-10
+    for precision in (1, 2):
+        plain = adjoint_errors(precision, True, False)
+        refined = adjoint_errors(precision, True, True)
+        assert refined[0] < 0.2 * plain[0] and refined[1] < 0.2 * plain[1]
+
+
 def test_clusters_in_one_plan_match_single_plans(dev, orc):
     """Several clusters of different (m, Q) in one plan give bitwise the same
     results as one plan per cluster, and match the oracle."""
