@@ -103,12 +103,14 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
     for (int I = 0; I < 9; I++) h[I] = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; i++) gt[i] = 0.0;
-    const int v4 = wave & 3;                        // k-range of the rho GEMM
-    const int tpar = (NW == 8) ? (wave >> 2) : 0;  // mode-tile parity (eight waves)
-    auto holds = [&](int t) { return NW == 4 || (t & 1) == tpar; };
-    v4d racc[RHO ? MA : 1][2];
+    // rho GEMM: wave w takes the mode tiles of parity w & 1 over the k-range
+    // w >> 1 (18 of the round's 36 k-steps)
+    static_assert(!RHO || NW == 4, "the rho pass runs with four wavefronts");
+    const int tpar = wave & 1, krange = wave >> 1;
+    constexpr int RT = RHO ? (MA + 1) / 2 : 1;
+    v4d racc[RT][2];
 #pragma unroll
-    for (int t = 0; t < (RHO ? MA : 1); t++) racc[t][0] = racc[t][1] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < RT; u++) racc[u][0] = racc[u][1] = v4d{0.0, 0.0, 0.0, 0.0};
     __syncthreads();
 
     for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
@@ -231,17 +233,18 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
         }
         __syncthreads();
         if constexpr (RHO) {
-            // the round's 36 k-steps in four k-ranges of nine
-            for (int j = 9 * v4; j < 9 * v4 + 9; j++) {
+            for (int j = 18 * krange; j < 18 * krange + 18; j++) {
                 const double b0 = (double)sV[4 * j + g][c], b1 = (double)sV[4 * j + g][16 + c];
                 const double* gh = A.Ghat + (int64_t)(q0 * 9 + 4 * j + g) * MP + c;
 #pragma unroll
-                for (int t = 0; t < MA; t++)
-                    if (holds(t)) {
+                for (int u = 0; u < RT; u++) {
+                    const int t = 2 * u + tpar;
+                    if (t < MA) {
                         const double av = gh[16 * t];
-                        racc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, racc[t][0], 0, 0, 0);
-                        racc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, racc[t][1], 0, 0, 0);
+                        racc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, racc[u][0], 0, 0, 0);
+                        racc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, racc[u][1], 0, 0, 0);
                     }
+                }
             }
             __syncthreads();
         }
@@ -275,16 +278,17 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
         }
     }
     if constexpr (RHO) {
-        // fixed-order sum of the four k-range partials of rho through LDS
+        // fixed-order sum of the two k-range partials of rho through LDS
         double* red = reinterpret_cast<double*>(&sF[0][0]);
 #pragma unroll
         for (int t = 0; t < MA; t++) {
             __syncthreads();
-            if (holds(t)) {
+            if ((t & 1) == tpar) {
+                const int u = t >> 1;
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    red[(v4 * 16 + g + 4 * e) * PT + c] = racc[t][0][e];
-                    red[(v4 * 16 + g + 4 * e) * PT + 16 + c] = racc[t][1][e];
+                    red[(krange * 16 + g + 4 * e) * PT + c] = racc[u][0][e];
+                    red[(krange * 16 + g + 4 * e) * PT + 16 + c] = racc[u][1][e];
                 }
             }
             __syncthreads();
@@ -294,7 +298,7 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
                 const int rr = e2 >> 5, p = e2 & 31;
                 double sum = 0.0;
 #pragma unroll
-                for (int w = 0; w < 4; w++) sum += red[(w * 16 + rr) * PT + p];
+                for (int w = 0; w < 2; w++) sum += red[(w * 16 + rr) * PT + p];
                 const int row = 16 * t + rr;
                 if (p < np && row < m) A.rho[(int64_t)row * A.count + p0 + p] = sbits[p] ? 0.0 : sum;
             }
