@@ -351,9 +351,10 @@ int launch_unpack_condense(const CondenseArgs& a, int mode, hipStream_t s) {
 // (low-precision) Kaa~: one step of iterative refinement of the adjoint solve.
 // One wavefront per point; x stays in registers (lane l holds rows l and
 // l + 64, m <= 96) and x_j reaches every lane by readlane, so the
-// substitutions need no LDS and no barrier.  The factor is read from HBM,
-// the loads of sixteen steps (one 128-byte line of a row) issued ahead of
-// their dependent updates.
+// substitutions need no LDS and no barrier.  The factor is read from HBM
+// (each triangle once per substitution, only the entries a lane uses), the
+// loads of sixteen steps (one 128-byte line of a row) issued ahead of their
+// dependent updates.
 
 __device__ __forceinline__ double lane_value(double v, int k) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
@@ -398,8 +399,9 @@ __global__ void __launch_bounds__(64) k_refine_lambda(RefineArgs A) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int jj = min(j0 + u, m - 1);
-            l0[u] = h0 ? Lg[(int64_t)i0 * m + jj] : 0.0;
-            l1[u] = h1 ? Lg[(int64_t)i1 * m + jj] : 0.0;
+            // only the entries left of the diagonal are used
+            l0[u] = (h0 && jj < i0) ? Lg[(int64_t)i0 * m + jj] : 0.0;
+            l1[u] = (h1 && jj < i1) ? Lg[(int64_t)i1 * m + jj] : 0.0;
             d[u] = Lg[(int64_t)jj * m + jj];
         }
 #pragma unroll
@@ -424,8 +426,9 @@ __global__ void __launch_bounds__(64) k_refine_lambda(RefineArgs A) {
             const int jj = max(j0 - u, 0);
             const int64_t a0 = chol ? (int64_t)jj * m + i0 : (int64_t)i0 * m + jj;
             const int64_t a1 = chol ? (int64_t)jj * m + i1 : (int64_t)i1 * m + jj;
-            l0[u] = h0 ? Lg[a0] : 0.0;
-            l1[u] = h1 ? Lg[a1] : 0.0;
+            // only the entries of rows i < j are used
+            l0[u] = (h0 && i0 < jj) ? Lg[a0] : 0.0;
+            l1[u] = (h1 && i1 < jj) ? Lg[a1] : 0.0;
             d[u] = Lg[(int64_t)jj * m + jj];
         }
 #pragma unroll
