@@ -52,9 +52,12 @@ def step_flops_per_point(m: int, Q: int) -> float:
 
 
 def tangent_flops_per_point(m, Q):
-    """Tangent contraction per macro point: T_q = W_q G_q (162 m), Kaa += G_q^T T_q
-    (18 m^2), KaF += G_q^T W_q (162 m), KFF += W_q (81), per ECM point."""
-    return 18.0 * Q * m * m + 324.0 * Q * m + 81.0 * Q
+    """Algorithmic flops of the tangent contraction per macro point (Sec. 3.2.1,
+    eq. ROMstiffness), per ECM point: T_q = (w_q A_q) G_q (162 m) and
+    Kaa += G_q^T T_q (18 m^2).  KaF = sum_q T_q^T needs no product of its own
+    (A_q is major-symmetric) and KFF = sum_q w_q A_q is a sum, so neither is
+    counted, even though the kernel forms them on the matrix cores."""
+    return 18.0 * Q * m * m + 162.0 * Q * m
 
 
 def read_traffic(kernel_tag: str, variant: int):
@@ -179,6 +182,29 @@ def cpu_baseline(cl, F, budget_s=12.0):
     dt = time.perf_counter() - t
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return n, dt, threads
+
+
+def host_cpu():
+    """CPU model, logical CPU count and lscpu's socket/core/thread lines of the
+    host the oracle ran on."""
+    info = {"model": None, "logical_cpus": os.cpu_count()}
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                info["model"] = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        keep = ("Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU max MHz", "NUMA node(s)")
+        info["lscpu"] = {k.strip(): v.strip() for k, v in
+                         (ln.split(":", 1) for ln in out.splitlines() if ":" in ln)
+                         if k.strip() in keep}
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
 
 
 def run_batched(args):
@@ -341,6 +367,7 @@ def main():
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         n, dt, thr = cpu_baseline(cl, F)
         cpu = {"value": n / dt, "unit": "point-evals/s", "cores": thr, "kind": "oracle",
+               "host": host_cpu(),
                "sample": f"{n} of the {N} macro points, one evaluate + condense + adjoint "
                          f"backward each (plain C, FP64, OpenMP over points)"}
 
