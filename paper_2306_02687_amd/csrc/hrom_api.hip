@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
+#include <type_traits>
 
 #include "hrom_internal.h"
 
@@ -35,18 +36,8 @@ void dfree(T*& ptr) {
 }
 
 void free_plan(Plan& p) {
-    for (auto& c : p.cl) {
-        dfree(c.Ghat);
-        dfree(c.GT);
-        dfree(c.Gf);
-        dfree(c.w);
-        dfree(c.phase);
-        dfree(c.Fpk);
-    }
-    dfree(p.Fr); dfree(p.polar); dfree(p.Pr); dfree(p.r); dfree(p.Khat); dfree(p.qs); dfree(p.L);
-    dfree(p.piv); dfree(p.y); dfree(p.X); dfree(p.Palg); dfree(p.Cr); dfree(p.S);
-    dfree(p.rnorm); dfree(p.dU); dfree(p.gr); dfree(p.Lam); dfree(p.lam); dfree(p.rho);
-    dfree(p.hr); dfree(p.gth); dfree(p.gth_part);
+    if (p.owns_arena) dfree(p.arena);
+    p.arena = nullptr;
     dfree(p.cls_dev); dfree(p.items_tan); dfree(p.counter);
 }
 
@@ -70,6 +61,133 @@ int upload(T** dst, const std::vector<T>& v) {
         hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
         rc = HROM_E_HIP;
     return rc;
+}
+
+// Validates the cluster descriptors and fills the plan's cluster geometry and
+// offsets (host only, no device access, no allocation beyond p.cl's
+// reserved capacity).
+int plan_geometry(Plan& p, const hrom_cluster* clusters, int32_t ncl, int64_t N, int32_t precision,
+                  uint32_t flags) {
+    if (!clusters || ncl < 1 || N < 1) return HROM_E_INVALID;
+    if (precision != HROM_FP64 && precision != HROM_MIXED_BF16 && precision != HROM_MIXED_FP16)
+        return HROM_E_INVALID;
+    int64_t next = 0;
+    for (int c = 0; c < ncl; c++) {
+        const hrom_cluster& k = clusters[c];
+        if (!k.G || !k.w || !k.phase || k.Q < 1 || k.count < 1 || k.first != next) return HROM_E_INVALID;
+        if (k.m < 1 || k.m > kMaxModes) return HROM_E_UNSUPPORTED;
+        next += k.count;
+    }
+    if (next != N) return HROM_E_INVALID;
+    p.ncl = ncl;
+    p.N = N;
+    p.prec = precision;
+    p.flags = flags;
+    p.cl.clear();
+    int64_t off_a = 0, off_kaa = 0, off_kaf = 0, ws_k = 0, ws_L = 0, ws_q = 0;
+    for (int c = 0; c < ncl; c++) {
+        const hrom_cluster& k = clusters[c];
+        ClusterDev d{};
+        d.m = k.m;
+        d.Q = k.Q;
+        d.Qpad = (k.Q + 63) / 64 * 64;
+        d.MT = (k.m + 10 + 15) / 16;
+        d.MP = 16 * d.MT;
+        d.res_t = (k.m + 9) / 16;
+        d.res_c = (k.m + 9) % 16;
+        d.KS = 4 * ((k.m + 15) / 16);   // k-steps padded to whole mode tiles (zeros beyond m)
+        d.first = k.first;
+        d.count = k.count;
+        d.off_a = off_a;
+        d.off_kaa = off_kaa;
+        d.off_kaf = off_kaf;
+        d.ws_khat = ws_k;
+        d.ws_L = ws_L;
+        d.ws_qs = ws_q;
+        off_a += (int64_t)k.m * k.count;
+        off_kaa += (int64_t)k.m * k.m * k.count;
+        off_kaf += (int64_t)9 * k.m * k.count;
+        ws_k += khat_len(d.m, d.MT, precision != HROM_FP64) * k.count;
+        ws_L += (int64_t)k.m * k.m * k.count;
+        ws_q += (int64_t)12 * d.Qpad * k.count;
+        p.cl.push_back(d);
+    }
+    p.a_len = off_a;
+    p.kaa_len = off_kaa;
+    p.kaf_len = off_kaf;
+    p.khat_len = ws_k;
+    p.L_len = ws_L;
+    p.qs_len = ws_q;
+    return HROM_OK;
+}
+
+// Carves every device buffer of the plan out of one region starting at base
+// (256-byte aligned pieces, in a fixed order) and returns the region's size;
+// with base == nullptr only the size is computed.
+size_t plan_carve(Plan& p, char* base) {
+    size_t off = 0;
+    auto take = [&](auto*& ptr, int64_t n) {
+        using T = std::remove_reference_t<decltype(*ptr)>;
+        if (n < 1) n = 1;
+        off = (off + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+        ptr = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += sizeof(T) * (size_t)n;
+    };
+    const bool mx = mixed(p);
+    for (auto& d : p.cl) {
+        take(d.Ghat, (int64_t)d.Qpad * 9 * d.MP);
+        take(d.GT, (int64_t)d.Qpad * 9 * d.m);
+        take(d.Gf, (int64_t)d.Qpad * 9 / 16 * d.KS * 64);
+        take(d.w, d.Qpad);
+        take(d.phase, d.Qpad);
+        if (mx) take(d.Fpk, (int64_t)d.Qpad * ((d.m + 15) / 16) * 512);
+        else d.Fpk = nullptr;
+    }
+    const int64_t n = p.N;
+    take(p.Fr, 9 * n);
+    take(p.polar, 21 * n);
+    take(p.Pr, 9 * n);
+    take(p.r, p.a_len);
+    if (mx) {
+        float* kh; take(kh, p.khat_len); p.Khat = kh;
+        float* qs; take(qs, p.qs_len); p.qs = qs;
+    } else {
+        double* kh; take(kh, p.khat_len); p.Khat = kh;
+        double* qs; take(qs, p.qs_len); p.qs = qs;
+    }
+    take(p.L, refine(p) ? p.L_len : 1);
+    take(p.piv, p.a_len);
+    take(p.y, p.a_len);
+    take(p.X, 9 * p.a_len);
+    take(p.Palg, 9 * n);
+    take(p.Cr, 81 * n);
+    take(p.S, 9 * n);
+    take(p.rnorm, n);
+    take(p.dU, 9 * n);
+    take(p.gr, 9 * n);
+    take(p.Lam, 9 * n);
+    take(p.lam, p.a_len);
+    take(p.rho, p.a_len);
+    take(p.hr, 9 * n);
+    take(p.gth, 4 * n);
+    take(p.gth_part, 4 * kThetaChunks);
+    return (off + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+}
+
+// Enqueues the build of every cluster's device layouts (Ghat, GT, Gf, the
+// packed low-precision fragments, padded w and phase) from the caller's G, w,
+// phase on stream s.
+void plan_build(const Plan& p, const hrom_cluster* clusters, hipStream_t s) {
+    for (int c = 0; c < p.ncl; c++) {
+        const hrom_cluster& k = clusters[c];
+        const ClusterDev& d = p.cl[c];
+        LayoutArgs la{};
+        la.m = d.m; la.Q = d.Q; la.Qpad = d.Qpad; la.MT = d.MT; la.MP = d.MP; la.prec = p.prec;
+        la.G = k.G; la.w = k.w; la.phase = k.phase;
+        la.Ghat = d.Ghat; la.GT = d.GT; la.Gf = d.Gf; la.KS = d.KS; la.wpad = d.w; la.phpad = d.phase;
+        la.Fpk = d.Fpk; la.split = (p.flags & HROM_SPLIT) ? 1 : 0;
+        launch_build_layouts(la, s);
+    }
 }
 
 // Device cluster table and the cost-sorted work queues of the tangent launches.
@@ -138,105 +256,29 @@ const char* hrom_strerror(int code) {
 
 int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, int64_t N,
                      int32_t precision, uint32_t flags) {
-    if (!out || !clusters || ncl < 1 || N < 1) return HROM_E_INVALID;
+    if (!out) return HROM_E_INVALID;
     *out = nullptr;
-    if (precision != HROM_FP64 && precision != HROM_MIXED_BF16 && precision != HROM_MIXED_FP16)
-        return HROM_E_INVALID;
-    int64_t next = 0;
-    for (int c = 0; c < ncl; c++) {
-        const hrom_cluster& k = clusters[c];
-        if (!k.G || !k.w || !k.phase || k.Q < 1 || k.count < 1 || k.first != next) return HROM_E_INVALID;
-        if (k.m < 1 || k.m > kMaxModes) return HROM_E_UNSUPPORTED;
-        next += k.count;
-    }
-    if (next != N) return HROM_E_INVALID;
     hrom_plan_s* h = new (std::nothrow) hrom_plan_s;
     if (!h) return HROM_E_NOMEM;
     Plan& p = h->p;
-    p.ncl = ncl;
-    p.N = N;
-    p.prec = precision;
-    p.flags = flags;
+    int rc = plan_geometry(p, clusters, ncl, N, precision, flags);
+    if (rc != HROM_OK) {
+        delete h;
+        return rc;
+    }
     (void)hipGetDevice(&p.device);
-    int64_t off_a = 0, off_kaa = 0, off_kaf = 0, ws_k = 0, ws_L = 0, ws_q = 0;
-    int rc = HROM_OK;
-    for (int c = 0; c < ncl && rc == HROM_OK; c++) {
-        const hrom_cluster& k = clusters[c];
-        ClusterDev d{};
-        d.m = k.m;
-        d.Q = k.Q;
-        d.Qpad = (k.Q + 63) / 64 * 64;
-        d.MT = (k.m + 10 + 15) / 16;
-        d.MP = 16 * d.MT;
-        d.res_t = (k.m + 9) / 16;
-        d.res_c = (k.m + 9) % 16;
-        d.KS = 4 * ((k.m + 15) / 16);   // k-steps padded to whole mode tiles (zeros beyond m)
-        d.first = k.first;
-        d.count = k.count;
-        d.off_a = off_a;
-        d.off_kaa = off_kaa;
-        d.off_kaf = off_kaf;
-        d.ws_khat = ws_k;
-        d.ws_L = ws_L;
-        d.ws_qs = ws_q;
-        off_a += (int64_t)k.m * k.count;
-        off_kaa += (int64_t)k.m * k.m * k.count;
-        off_kaf += (int64_t)9 * k.m * k.count;
-        ws_k += khat_len(d.m, d.MT, precision != HROM_FP64) * k.count;
-        ws_L += (int64_t)k.m * k.m * k.count;
-        ws_q += (int64_t)12 * d.Qpad * k.count;
-        rc = dalloc(&d.Ghat, (int64_t)d.Qpad * 9 * d.MP);
-        if (rc == HROM_OK) rc = dalloc(&d.GT, (int64_t)d.Qpad * 9 * d.m);
-        if (rc == HROM_OK) rc = dalloc(&d.Gf, (int64_t)d.Qpad * 9 / 16 * d.KS * 64);
-        if (rc == HROM_OK) rc = dalloc(&d.w, d.Qpad);
-        if (rc == HROM_OK) rc = dalloc(&d.phase, d.Qpad);
-        if (rc == HROM_OK && precision != HROM_FP64) {
-            rc = dalloc(&d.Fpk, (int64_t)d.Qpad * ((d.m + 15) / 16) * 512);
-        }
-        p.cl.push_back(d);
-        if (rc != HROM_OK) break;
-        LayoutArgs la{};
-        la.m = d.m; la.Q = d.Q; la.Qpad = d.Qpad; la.MT = d.MT; la.MP = d.MP; la.prec = precision;
-        la.G = k.G; la.w = k.w; la.phase = k.phase;
-        la.Ghat = d.Ghat; la.GT = d.GT; la.Gf = d.Gf; la.KS = d.KS; la.wpad = d.w; la.phpad = d.phase; la.Fpk = d.Fpk; la.split = (flags & HROM_SPLIT) ? 1 : 0;
-        launch_build_layouts(la, nullptr);
+    const size_t bytes = plan_carve(p, nullptr);
+    p.owns_arena = true;
+    if (hipMalloc((void**)&p.arena, bytes) != hipSuccess) {
+        p.arena = nullptr;
+        rc = HROM_E_NOMEM;
+    }
+    if (rc == HROM_OK) {
+        p.arena_bytes = bytes;
+        plan_carve(p, p.arena);
+        plan_build(p, clusters, nullptr);
         if (hipDeviceSynchronize() != hipSuccess) rc = HROM_E_HIP;
     }
-    p.a_len = off_a;
-    p.kaa_len = off_kaa;
-    p.kaf_len = off_kaf;
-    p.khat_len = ws_k;
-    p.L_len = ws_L;
-    p.qs_len = ws_q;
-    const int64_t n = N;
-    if (rc == HROM_OK) rc = dalloc(&p.Fr, 9 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.polar, 21 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.Pr, 9 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.r, off_a);
-    if (rc == HROM_OK) {
-        if (precision == HROM_FP64) rc = dalloc((double**)&p.Khat, ws_k);
-        else rc = dalloc((float**)&p.Khat, ws_k);
-    }
-    if (rc == HROM_OK) {
-        if (precision == HROM_FP64) rc = dalloc((double**)&p.qs, ws_q);
-        else rc = dalloc((float**)&p.qs, ws_q);
-    }
-    if (rc == HROM_OK) rc = dalloc(&p.L, refine(p) ? ws_L : 1);
-    if (rc == HROM_OK) rc = dalloc(&p.piv, off_a);
-    if (rc == HROM_OK) rc = dalloc(&p.y, off_a);
-    if (rc == HROM_OK) rc = dalloc(&p.X, 9 * off_a);
-    if (rc == HROM_OK) rc = dalloc(&p.Palg, 9 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.Cr, 81 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.S, 9 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.rnorm, n);
-    if (rc == HROM_OK) rc = dalloc(&p.dU, 9 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.gr, 9 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.Lam, 9 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.lam, off_a);
-    if (rc == HROM_OK) rc = dalloc(&p.rho, off_a);
-    if (rc == HROM_OK) rc = dalloc(&p.hr, 9 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.gth, 4 * n);
-    if (rc == HROM_OK) rc = dalloc(&p.gth_part, 4 * kThetaChunks);
     if (rc == HROM_OK) rc = build_groups(p);
     if (rc != HROM_OK) {
         free_plan(p);

@@ -53,7 +53,15 @@ struct ClusterDev {
 struct ClusterGPU;
 struct WorkItem;
 
+constexpr size_t kArenaAlign = 256;   // alignment of every buffer carved from a plan's arena
+
 struct Plan {
+    // every device buffer of the plan except the grouped-launch tables below
+    // is carved from one region: hipMalloc'ed at plan creation (owns_arena),
+    // or a static device array for the allocation-free entry point
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    bool owns_arena = false;
     int ncl = 0;
     int64_t N = 0;
     int prec = HROM_FP64;
