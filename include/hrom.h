@@ -45,6 +45,7 @@
 #ifndef HROM_H
 #define HROM_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -59,6 +60,7 @@ extern "C" {
 #define HROM_E_NOMEM (-4)     /* device allocation failed at plan creation */
 #define HROM_E_UNSUPPORTED (-5) /* size outside the supported range (m > 96, ...), or an
                                  output the plan's mode does not provide */
+#define HROM_E_SCRATCH (-6)   /* hrom_newton_noalloc: the request does not fit its static scratch */
 
 /* per-point status bits */
 #define HROM_PT_JNONPOS 1    /* det F <= 0 at an ECM point (or det Fbar <= 0) */
@@ -184,6 +186,29 @@ int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant);
  * enable and destroyed with the plan. */
 int hrom_plan_profile(hrom_plan plan, int32_t enable);
 int hrom_plan_tangent_ms(hrom_plan plan, float* ms);
+
+/* Allocation-free micro Newton, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same work and the same results as hrom_plan_create
+ * + hrom_newton (launch variant 0, one launch per cluster for every step),
+ * with every buffer of the plan -- device layouts of G, w, phase and the
+ * per-point workspace -- carved from a static device array of
+ * hrom_noalloc_scratch_bytes() bytes (64 MiB) that each GPU the library runs
+ * on holds until the process ends.  The layouts are rebuilt from the
+ * caller's G, w, phase on `stream` at every call.  Arguments are those of
+ * hrom_plan_create (clusters: host array, at most 16 entries) and
+ * hrom_newton (device pointers owned by the caller; a updated in place).
+ * Calls no hipMalloc / hipFree and performs no host sync.
+ * Returns HROM_E_SCRATCH (nothing enqueued) when the plan would need more
+ * than the scratch, HROM_E_UNSUPPORTED for more than 16 clusters.  Every call
+ * on one GPU shares that GPU's array, which keeps the last call's contents
+ * (no buffer needs to start at zero): calls on one GPU must be ordered (the
+ * same stream, or synchronised); calls that overlap on one GPU race. */
+int hrom_newton_noalloc(const hrom_cluster* clusters, int32_t ncl, int64_t N, int32_t precision,
+                        uint32_t flags, const double* theta, const double* Fbar, double* a,
+                        double tol, int32_t max_it, double* Pbar, double* Cbar, double* rnorm,
+                        int32_t* status, hipStream_t stream);
+size_t hrom_noalloc_scratch_bytes(void);
 
 const char* hrom_strerror(int code);
 

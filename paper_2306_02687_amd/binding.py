@@ -29,7 +29,9 @@ OFF_A, OFF_KAA, OFF_KAF = 0, 1, 2
 EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_eval",
             "hrom_condense", "hrom_update", "hrom_newton", "hrom_backward", "hrom_strerror",
             "hrom_num_variants", "hrom_plan_set_variant", "hrom_plan_profile",
-            "hrom_plan_tangent_ms", "hrom_cauchy")
+            "hrom_plan_tangent_ms", "hrom_cauchy", "hrom_newton_noalloc",
+            "hrom_noalloc_scratch_bytes")
+E_SCRATCH = -6
 
 
 class HromError(RuntimeError):
@@ -69,6 +71,11 @@ def load(path: str = LIB_PATH):
     L.hrom_plan_set_variant.argtypes = [P, i32, i32]
     L.hrom_plan_profile.argtypes = [P, i32]
     L.hrom_plan_tangent_ms.argtypes = [P, C.POINTER(C.c_float)]
+    L.hrom_newton_noalloc.argtypes = [C.POINTER(_Cluster), i32, i64, i32, C.c_uint32, P, P, P, d,
+                                      i32, P, P, P, P, P]
+    L.hrom_newton_noalloc.restype = C.c_int
+    L.hrom_noalloc_scratch_bytes.argtypes = []
+    L.hrom_noalloc_scratch_bytes.restype = C.c_size_t
     L.hrom_strerror.argtypes = [C.c_int]
     L.hrom_strerror.restype = C.c_char_p
     _lib = L
@@ -110,6 +117,45 @@ class ClusterSpec:
         return int(self.G.shape[0])
 
 
+def _cluster_array(clusters):
+    arr = (_Cluster * len(clusters))()
+    first = 0
+    for i, c in enumerate(clusters):
+        for t, dt in ((c.G, torch.float64), (c.w, torch.float64), (c.phase, torch.int32)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise HromError("cluster arrays must be contiguous CUDA tensors "
+                                "(G, w float64; phase int32)")
+        arr[i] = _Cluster(c.m, c.Q, c.G.data_ptr(), c.w.data_ptr(), c.phase.data_ptr(),
+                          first, c.count)
+        first += c.count
+    return arr
+
+
+def _flags(objective, split, refine):
+    return (OBJECTIVE if objective else 0) | (SPLIT if split else 0) | (REFINE if refine else 0)
+
+
+def newton_noalloc(clusters, theta, Fbar, a, Pbar, Cbar, rnorm, status, precision: int = FP64,
+                   objective: bool = True, split: bool = False, refine: bool = False,
+                   tol: float = 1e-10, max_it: int = 6, stream=None, check: bool = True) -> int:
+    """hrom_newton_noalloc: plan + micro Newton with every buffer in the
+    library's static device scratch (no device allocation).  Returns the C
+    return code when check is False, else raises on failure."""
+    arr = _cluster_array(list(clusters))
+    N = sum(c.count for c in clusters)
+    rc = load().hrom_newton_noalloc(arr, len(clusters), N, precision,
+                                    _flags(objective, split, refine), _ptr(theta), _ptr(Fbar),
+                                    _ptr(a), float(tol), int(max_it), _ptr(Pbar), _ptr(Cbar),
+                                    _ptr(rnorm), _ptr(status), _stream(stream))
+    if check:
+        _check(rc, "hrom_newton_noalloc")
+    return rc
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(load().hrom_noalloc_scratch_bytes())
+
+
 class Plan:
     """A plan for N macro points partitioned into RVE clusters (in order)."""
 
@@ -118,18 +164,8 @@ class Plan:
         L = load()
         self.clusters = list(clusters)
         self.N = sum(c.count for c in self.clusters)
-        arr = (_Cluster * len(self.clusters))()
-        first = 0
-        for i, c in enumerate(self.clusters):
-            for t, dt in ((c.G, torch.float64), (c.w, torch.float64), (c.phase, torch.int32)):
-                if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
-                    raise HromError("cluster arrays must be contiguous CUDA tensors "
-                                    "(G, w float64; phase int32)")
-            arr[i] = _Cluster(c.m, c.Q, c.G.data_ptr(), c.w.data_ptr(), c.phase.data_ptr(),
-                              first, c.count)
-            first += c.count
-        flags = ((OBJECTIVE if objective else 0) | (SPLIT if split else 0)
-                 | (REFINE if refine else 0))
+        arr = _cluster_array(self.clusters)
+        flags = _flags(objective, split, refine)
         h = C.c_void_p()
         torch.cuda.synchronize()
         _check(L.hrom_plan_create(C.byref(h), arr, len(self.clusters), self.N, precision, flags),

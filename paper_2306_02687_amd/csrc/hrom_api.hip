@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -250,6 +251,7 @@ const char* hrom_strerror(int code) {
         case HROM_E_ORDER: return "call order violated (evaluate before condense, condense before update/backward)";
         case HROM_E_NOMEM: return "device allocation failed";
         case HROM_E_UNSUPPORTED: return "not supported (size outside the supported range, or an output the plan's mode does not provide)";
+        case HROM_E_SCRATCH: return "the request needs more device memory than the static scratch of the allocation-free entry point";
         default: return "unknown error";
     }
 }
@@ -565,6 +567,72 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
     launch_bw_pushforward(bp, stream);
     launch_reduce_theta(p.N, p.gth, p.gth_part, gtheta, stream);
     return hip_status();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free Newton
+// hrom_newton_noalloc: the plan of hrom_plan_create + hrom_newton, with every
+// device buffer carved from a file-scope device array instead of hipMalloc.
+// The array's device address is looked up once per device (hipGetSymbolAddress
+// with that device current) and only that address is handed to kernels.
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;   // per device
+constexpr int kMaxDevices = 64;
+constexpr int kNoallocMaxClusters = 16;
+
+struct NoallocState {
+    std::mutex mu;            // serialises host-side use of the device's plan object
+    bool ready = false;
+    char* ptr = nullptr;      // device address of `scratch` on this device
+    hrom_plan_s plan;         // cluster capacity reserved at library load
+    NoallocState() { plan.p.cl.reserve(kNoallocMaxClusters); }
+};
+NoallocState g_noalloc[kMaxDevices];
+}  // namespace
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+extern "C" {
+
+size_t hrom_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int hrom_newton_noalloc(const hrom_cluster* clusters, int32_t ncl, int64_t N, int32_t precision,
+                        uint32_t flags, const double* theta, const double* Fbar, double* a,
+                        double tol, int32_t max_it, double* Pbar, double* Cbar, double* rnorm,
+                        int32_t* status, hipStream_t stream) {
+    if (!clusters || !theta || !Fbar || !a || !Pbar || !Cbar || !status || max_it < 1 || ncl < 1)
+        return HROM_E_INVALID;
+    if (ncl > kNoallocMaxClusters) return HROM_E_UNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HROM_E_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return HROM_E_UNSUPPORTED;
+    NoallocState& S = g_noalloc[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    if (!S.ready) {
+        void* addr = nullptr;
+        if (hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)) != hipSuccess || !addr) return HROM_E_HIP;
+        S.ptr = static_cast<char*>(addr);
+        set_kernel_attributes();
+        S.ready = true;
+    }
+    Plan& p = S.plan.p;
+    int rc = plan_geometry(p, clusters, ncl, N, precision, flags);
+    if (rc != HROM_OK) return rc;
+    const size_t bytes = plan_carve(p, nullptr);
+    if (bytes > kScratchBytes) return HROM_E_SCRATCH;
+    p.device = dev;
+    p.arena = S.ptr;
+    p.arena_bytes = bytes;
+    p.owns_arena = false;
+    p.grouped = false;   // one launch per cluster for every step: no device tables
+    p.profile = false;
+    p.stage = 0;
+    plan_carve(p, S.ptr);
+    plan_build(p, clusters, stream);
+    rc = hip_status();
+    if (rc != HROM_OK) return rc;
+    return hrom_newton(&S.plan, theta, Fbar, a, tol, max_it, Pbar, Cbar, rnorm, status, stream);
 }
 
 }  // extern "C"

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "hrom.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|int32_t|int64_t|const char\*)\s+(hrom_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int32_t|int64_t|size_t|const char\*)\s+(hrom_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_the_four_calls():
