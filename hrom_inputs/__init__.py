@@ -7,8 +7,10 @@ any code of the method.
 """
 from .generators import (  # noqa: F401
     THETA_REF,
+    THETA_CONTRAST,
     Cluster,
     make_cluster,
+    make_cluster_illcond,
     make_macro_points,
     make_increments,
     zipf_counts,

@@ -31,6 +31,9 @@ import numpy as np
 
 # (mu_matrix, lambda_matrix, mu_inclusion, lambda_inclusion)
 THETA_REF = np.array([1.0, 1.5, 10.0, 15.0], dtype=np.float64)
+# high phase contrast (soft matrix, stiff inclusions): the mode-space stiffness
+# is ill-conditioned through the material rather than through the basis
+THETA_CONTRAST = np.array([1.0e-3, 1.5e-3, 10.0, 15.0], dtype=np.float64)
 
 
 @dataclass
@@ -59,6 +62,47 @@ def make_cluster(m: int, Q: int, seed: int, g_std: float = 0.05,
     G = G - mean[None, :, :]
     phase = (rng.random(Q) < p_incl).astype(np.int32)
     return Cluster(m=m, Q=Q, G=np.ascontiguousarray(G), w=w, phase=phase, seed=seed)
+
+
+def make_cluster_illcond(m: int, Q: int, seed: int, cond_modes: float = 100.0,
+                         soft_modes: int = 0, g_std: float = 0.05,
+                         p_incl: float = 0.3) -> Cluster:
+    """An RVE cluster whose mode gradients span the same kind of space as
+    ``make_cluster``'s but in an ill-conditioned basis: ``G = G0 M`` with
+    ``G0`` drawn as in ``make_cluster(m, Q, seed)`` and ``M = U diag(s) V^T``,
+    ``U, V`` random orthogonal (QR of standard-normal matrices with the signs
+    of R's diagonal fixed) and ``s`` geometric from 1 down to
+    ``1 / cond_modes``.  The mode-space stiffness then has a condition number
+    of about ``cond_modes**2`` times that of ``G0``'s (real POD mode gradients
+    are far from orthogonal in the weighted gradient inner product).  The
+    mixing draws come from ``default_rng(seed + 7919)`` after ``G0``'s.
+
+    With ``soft_modes = k > 0`` the last k columns of ``G0`` are first
+    localised in the matrix phase: set to zero at the inclusion points and
+    re-centred with the weighted mean over the matrix points only (so that
+    ``sum_q w_q G_qm = 0`` still holds).  With a soft matrix and stiff
+    inclusions those modes are soft, and the mode-space stiffness is
+    ill-conditioned through the material, whatever the basis."""
+    base = make_cluster(m, Q, seed, g_std=g_std, p_incl=p_incl)
+    G0 = base.G.copy()
+    if soft_modes > 0:
+        mat = base.phase == 0
+        wm = np.where(mat, base.w, 0.0)
+        cols = slice(m - soft_modes, m)
+        Gs = np.where(mat[:, None, None], G0[:, :, cols], 0.0)
+        mean = np.tensordot(wm, Gs, axes=(0, 0)) / wm.sum()
+        G0[:, :, cols] = np.where(mat[:, None, None], Gs - mean[None], 0.0)
+    rng = np.random.default_rng(seed + 7919)
+
+    def orth(n):
+        q, r = np.linalg.qr(rng.standard_normal((n, n)))
+        return q * np.sign(np.diag(r))[None, :]
+
+    U, V = orth(m), orth(m)
+    s = np.geomspace(1.0, 1.0 / cond_modes, m) if m > 1 else np.ones(1)
+    M = (U * s[None, :]) @ V.T
+    G = np.ascontiguousarray(np.einsum("qim,mn->qin", G0, M))
+    return Cluster(m=m, Q=Q, G=G, w=base.w, phase=base.phase, seed=seed)
 
 
 def _rotations(rng: np.random.Generator, n: int, max_angle: float) -> np.ndarray:

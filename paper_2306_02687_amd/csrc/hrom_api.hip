@@ -143,7 +143,14 @@ size_t plan_carve(Plan& p, char* base) {
         take(d.phase, d.Qpad);
         if (mx) take(d.Fpk, (int64_t)d.Qpad * ((d.m + 15) / 16) * 512);
         else d.Fpk = nullptr;
+        take(d.gram, (int64_t)d.m * d.m);
+        take(d.R, (int64_t)d.m * d.m);
+        take(d.Rinv, (int64_t)d.m * d.m);
+        take(d.Gt, (int64_t)d.Q * 9 * d.m);
     }
+    take(p.basis_flag, 1);
+    take(p.at, p.a_len);
+    take(p.dt, p.a_len);
     const int64_t n = p.N;
     take(p.Fr, 9 * n);
     take(p.polar, 21 * n);
@@ -182,9 +189,11 @@ void plan_build(const Plan& p, const hrom_cluster* clusters, hipStream_t s) {
     for (int c = 0; c < p.ncl; c++) {
         const hrom_cluster& k = clusters[c];
         const ClusterDev& d = p.cl[c];
+        BasisArgs ba{d.m, d.Q, k.G, k.w, d.gram, d.R, d.Rinv, d.Gt, p.basis_flag};
+        launch_basis_build(ba, s);
         LayoutArgs la{};
         la.m = d.m; la.Q = d.Q; la.Qpad = d.Qpad; la.MT = d.MT; la.MP = d.MP; la.prec = p.prec;
-        la.G = k.G; la.w = k.w; la.phase = k.phase;
+        la.G = d.Gt; la.w = k.w; la.phase = k.phase;
         la.Ghat = d.Ghat; la.GT = d.GT; la.Gf = d.Gf; la.KS = d.KS; la.wpad = d.w; la.phpad = d.phase;
         la.Fpk = d.Fpk; la.split = (p.flags & HROM_SPLIT) ? 1 : 0;
         launch_build_layouts(la, s);
@@ -228,6 +237,14 @@ int build_groups(Plan& p) {
     if (rc == HROM_OK) rc = upload(&p.items_tan, tan);
     if (rc == HROM_OK) rc = dalloc(&p.counter, 1);
     return rc;
+}
+
+// the caller's amplitudes in the plan's mode basis: at = R a, per cluster
+void map_in(const Plan& p, const double* a, hipStream_t s) {
+    for (const auto& c : p.cl) {
+        ModeMapArgs ma{c.m, c.first, c.count, c.R, a + c.off_a, p.at + c.off_a, nullptr};
+        launch_mode_map(MAP_R, ma, s);
+    }
 }
 
 GroupCall group_call(const Plan& p) {
@@ -276,10 +293,21 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
         rc = HROM_E_NOMEM;
     }
     if (rc == HROM_OK) {
+        set_kernel_attributes();
+        rc = set_basis_attributes();
+    }
+    if (rc == HROM_OK) {
         p.arena_bytes = bytes;
         plan_carve(p, p.arena);
-        plan_build(p, clusters, nullptr);
-        if (hipDeviceSynchronize() != hipSuccess) rc = HROM_E_HIP;
+        if (hipMemset(p.basis_flag, 0, sizeof(int)) != hipSuccess) rc = HROM_E_HIP;
+        if (rc == HROM_OK) plan_build(p, clusters, nullptr);
+        if (rc == HROM_OK && hipDeviceSynchronize() != hipSuccess) rc = HROM_E_HIP;
+        int bad = 0;
+        if (rc == HROM_OK && hipMemcpy(&bad, p.basis_flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = HROM_E_HIP;
+        // mode gradients linearly dependent in the weighted inner product:
+        // Kaa would be singular at every macro point
+        if (rc == HROM_OK && bad) rc = HROM_E_INVALID;
     }
     if (rc == HROM_OK) rc = build_groups(p);
     if (rc != HROM_OK) {
@@ -287,7 +315,6 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
         delete h;
         return rc;
     }
-    set_kernel_attributes();
     *out = h;
     return HROM_OK;
 }
@@ -362,6 +389,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
     Plan& p = plan->p;
     PointArgs pa{p.N, (p.flags & HROM_OBJECTIVE) ? 1 : 0, Fbar, p.Fr, p.polar, status};
     launch_prepare(pa, stream);
+    map_in(p, a, stream);
     const size_t tsz = mixed(p) ? sizeof(float) : sizeof(double);
     std::vector<EvalArgs> tan_args;   // per-cluster tangent launches of a mixed plan with several clusters
     for (const auto& c : p.cl) {
@@ -369,7 +397,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         e.m = c.m; e.Q = c.Q; e.Qpad = c.Qpad; e.MP = c.MP; e.MT = c.MT; e.KS = c.KS;
         e.first = c.first; e.count = c.count; e.N = p.N;
         e.Ghat = c.Ghat; e.Gf = c.Gf; e.w = c.w; e.phase = c.phase; e.Fpk = c.Fpk;
-        e.theta = theta; e.Fr = p.Fr; e.a = a + c.off_a;
+        e.theta = theta; e.Fr = p.Fr; e.a = p.at + c.off_a;
         e.qs = (char*)p.qs + tsz * (size_t)c.ws_qs;
         e.Khat = (char*)p.Khat + tsz * (size_t)c.ws_khat;
         e.r = p.r + c.off_a;
@@ -398,7 +426,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         if (p.profile) (void)hipEventRecord(p.ev_tan[0], stream);
         if (!mixed(p)) {
             GroupCall g = group_call(p);
-            g.theta = theta; g.Fr = p.Fr; g.a = a; g.qs = p.qs; g.Khat = p.Khat;
+            g.theta = theta; g.Fr = p.Fr; g.a = p.at; g.qs = p.qs; g.Khat = p.Khat;
             g.r = p.r; g.Pr = p.Pr; g.status = status;
             g.items = p.items_tan; g.nitems = p.n_tan;
             rc = launch_tan_persistent(g, p.persistent_grid, stream);
@@ -423,9 +451,15 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
             ca.outKFF = KFF;
             const int rc = launch_unpack_condense(ca, 0, stream);
             if (rc != HROM_OK) return rc;
+            launch_export_basis(c.R, c.m, c.count, ca.outKaa, ca.outKaF, stream);
         }
     }
-    if (r) (void)hipMemcpyAsync(r, p.r, sizeof(double) * p.a_len, hipMemcpyDeviceToDevice, stream);
+    if (r) {
+        for (const auto& c : p.cl) {
+            ModeMapArgs ma{c.m, c.first, c.count, c.R, p.r + c.off_a, r + c.off_a, nullptr};
+            launch_mode_map(MAP_RT, ma, stream);
+        }
+    }
     if (Pr) (void)hipMemcpyAsync(Pr, p.Pr, sizeof(double) * 9 * p.N, hipMemcpyDeviceToDevice, stream);
     const int rc = hip_status();
     if (rc == HROM_OK) p.stage = 1;
@@ -455,6 +489,9 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
         int rc = launch_condense_reg(ca, stream);
         if (rc == HROM_OK) rc = launch_unpack_condense(ca, 2, stream);
         if (rc != HROM_OK) return rc;
+        // ||r||_2 in the caller's basis, r = R^T rt
+        ModeMapArgs ma{c.m, c.first, c.count, c.R, p.r + c.off_a, nullptr, p.rnorm};
+        launch_mode_map(MAP_RT, ma, stream);
     }
     PushArgs pa{p.N, (p.flags & HROM_OBJECTIVE) ? 1 : 0, p.polar, p.Palg, p.Cr, Pbar, Cbar, p.S, status};
     launch_pushout(pa, stream);
@@ -484,8 +521,10 @@ static int update_impl(Plan& p, const double* dFbar, double tol, double* a, cons
         u.count = c.count;
         u.y = p.y + c.off_a;
         u.X = p.X + 9 * c.off_a;
-        u.a = a + c.off_a;
+        u.dt = p.dt + c.off_a;
         launch_update(u, stream);
+        ModeMapArgs ma{c.m, c.first, c.count, c.Rinv, p.dt + c.off_a, a + c.off_a, nullptr};
+        launch_mode_map(MAP_RINV, ma, stream);
     }
     return hip_status();
 }
@@ -541,6 +580,7 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
     const int objective = (p.flags & HROM_OBJECTIVE) ? 1 : 0;
     BwPointArgs bp{p.N, objective, p.polar, p.S, gPbar, p.gr, p.Lam, p.hr, gFbar};
     launch_bw_pullback(bp, stream);
+    map_in(p, a, stream);
     for (const auto& c : p.cl) {
         LambdaArgs la{c.m, c.first, c.count, p.N, p.X + 9 * c.off_a, p.gr, p.lam + c.off_a};
         launch_lambda(la, stream);
@@ -549,7 +589,7 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
         ba.first = c.first; ba.count = c.count; ba.N = p.N;
         ba.GT = c.GT; ba.Ghat = c.Ghat; ba.Gf = c.Gf; ba.MP = c.MP; ba.MT = c.MT; ba.KS = c.KS;
         ba.w = c.w; ba.phase = c.phase;
-        ba.theta = theta; ba.Fr = p.Fr; ba.a = a + c.off_a; ba.lam = p.lam + c.off_a;
+        ba.theta = theta; ba.Fr = p.Fr; ba.a = p.at + c.off_a; ba.lam = p.lam + c.off_a;
         ba.gr = p.gr; ba.hr = p.hr; ba.gth = p.gth; ba.rho = p.rho + c.off_a; ba.status = status;
         if (refine(p)) {
             // one step of iterative refinement of the adjoint solve: the residual
@@ -614,6 +654,7 @@ int hrom_newton_noalloc(const hrom_cluster* clusters, int32_t ncl, int64_t N, in
         if (hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)) != hipSuccess || !addr) return HROM_E_HIP;
         S.ptr = static_cast<char*>(addr);
         set_kernel_attributes();
+        if (set_basis_attributes() != HROM_OK) return HROM_E_HIP;
         S.ready = true;
     }
     Plan& p = S.plan.p;

@@ -48,6 +48,13 @@ struct ClusterDev {
     double* w;             // [Qpad] (zero padded)
     int* phase;            // [Qpad]
     uint16_t* Fpk;         // [Qpad][MA][64][8] packed low-precision fragments of G (mixed path)
+    // mode basis of the computation: Gram = R^T R of the caller's G in the
+    // weighted gradient inner product, Gt = G R^{-1} (every layout above is
+    // built from Gt), at = R a
+    double* gram;          // [m][m]
+    double* R;             // [m][m] upper triangular
+    double* Rinv;          // [m][m] upper triangular
+    double* Gt;            // [Q][9][m]
 };
 
 struct ClusterGPU;
@@ -81,6 +88,9 @@ struct Plan {
     void* qs = nullptr;        // per-cluster [count][Qpad][12] tangent scalars (double or float)
     double* L = nullptr;       // per-cluster [count][m][m] factor
     int* piv = nullptr;        // per-cluster [count][m] pivots (LU fallback)
+    double* at = nullptr;      // mode-indexed: amplitudes in the plan's mode basis
+    double* dt = nullptr;      // mode-indexed: update increment in the plan's mode basis
+    int* basis_flag = nullptr; // set when a cluster's mode gradients are linearly dependent
     double* y = nullptr;       // mode-indexed
     double* X = nullptr;       // [9 m][count] blocks, offset 9*off_a
     double* Palg = nullptr;    // [9][N]
@@ -200,7 +210,7 @@ struct UpdateArgs {
     const double* rnorm;
     const int* status;
     double tol;
-    double* a;             // cluster block
+    double* dt;            // cluster block: amplitude increment in the plan's mode basis
 };
 void launch_stretch_increment(const UpdateArgs& a, hipStream_t s);
 void launch_update(const UpdateArgs& a, hipStream_t s);
@@ -264,6 +274,32 @@ constexpr int kThetaChunks = 256;   // stage-1 partials per theta component
 void launch_reduce_theta(int64_t N, const double* gth, double* part, double* out, hipStream_t s);
 void launch_mark_unconverged(int64_t N, const double* rnorm, double tol, int* status,
                              hipStream_t s);
+
+// mode basis (k_basis.hip)
+struct BasisArgs {
+    int m, Q;
+    const double* G;       // caller's [Q][9][m]
+    const double* w;       // caller's [Q]
+    double* gram;
+    double* R;
+    double* Rinv;
+    double* Gt;
+    int* flag;
+};
+void launch_basis_build(const BasisArgs& a, hipStream_t s);
+enum { MAP_R = 0, MAP_RT = 1, MAP_RINV = 2 };
+struct ModeMapArgs {
+    int m;
+    int64_t first, count;
+    const double* T;       // [m][m] (R or R^{-1})
+    const double* x;       // cluster block [m][count]
+    double* y;             // cluster block [m][count] (MAP_RINV: y -= T x), or null
+    double* norm;          // [N] or null: ||T x||_2 per point
+};
+void launch_mode_map(int kind, const ModeMapArgs& a, hipStream_t s);
+void launch_export_basis(const double* R, int m, int64_t count, double* Kaa, double* KaF,
+                         hipStream_t s);
+int set_basis_attributes();
 
 // plan-time layout builders
 struct LayoutArgs {

@@ -1,0 +1,227 @@
+// Mode basis of the computation.  The ROM amplitudes enter the RVE only
+// through the span of the mode gradients (Sec. 3.2.1, eq. ROM_assumption), so
+// the condensed stress and tangent do not depend on the basis chosen for that
+// span.  Every plan works in the basis that is orthonormal in the weighted
+// gradient inner product <G_i, G_j> = sum_q w_q G_qi : G_qj:
+//   Gram = R^T R (Cholesky, R upper triangular),  Gt = G R^{-1},  at = R a.
+// The low-precision contraction then sees well-scaled operands whatever the
+// caller's basis (an ill-conditioned basis would otherwise amplify the
+// rounding of G into the span), and the FP64 path is unchanged up to
+// rounding.  Caller-side arrays stay in the caller's basis: a is mapped in
+// (at = R a), the update is mapped out (a -= R^{-1} dt), the residual norm
+// and the optional r, Kaa, KaF outputs are taken back with R^T.
+#include <hip/hip_runtime.h>
+
+#include "hrom_internal.h"
+
+namespace hrom {
+
+static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Gram[i][j] = sum_q w_q sum_I G[q][I][i] G[q][I][j], one thread per (i, j),
+// a fixed summation order.
+__global__ void __launch_bounds__(256) k_gram(const double* G, const double* w, int m, int Q,
+                                              double* gram) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * m) return;
+    const int i = t / m, j = t % m;
+    double s = 0.0;
+    for (int q = 0; q < Q; q++) {
+        double sq = 0.0;
+#pragma unroll
+        for (int I = 0; I < 9; I++)
+            sq = fma(G[((int64_t)q * 9 + I) * m + i], G[((int64_t)q * 9 + I) * m + j], sq);
+        s = fma(w[q], sq, s);
+    }
+    gram[t] = s;
+}
+
+// One workgroup: Cholesky Gram = R^T R in LDS (right-looking, column by
+// column), then R^{-1} by back substitution of the identity, column k per
+// thread.  A pivot at or below 1e-13 of the largest diagonal entry (mode
+// gradients linearly dependent in the weighted inner product) sets *flag = 1
+// and leaves R, R^{-1} as NaN, so that every later use flags its points.
+__global__ void __launch_bounds__(256) k_basis_factor(const double* gram, int m, double* R,
+                                                      double* Rinv, int* flag) {
+    extern __shared__ double sm[];
+    double* A = sm;               // [m][m], upper triangle becomes R
+    int& bad = *reinterpret_cast<int*>(sm + m * m);
+    const int t = threadIdx.x;
+    if (t == 0) bad = 0;
+    for (int e = t; e < m * m; e += blockDim.x) A[e] = gram[e];
+    __syncthreads();
+    double dmax = 0.0;
+    for (int i = 0; i < m; i++) dmax = fmax(dmax, A[i * m + i]);
+    for (int j = 0; j < m; j++) {
+        const double d = A[j * m + j];
+        if (!(d > 1e-13 * dmax)) {
+            if (t == 0) bad = 1;
+            break;
+        }
+        const double rjj = sqrt(d);
+        __syncthreads();
+        // row j of R: R_jk = A_jk / r_jj for k > j
+        for (int k = j + 1 + t; k < m; k += blockDim.x) A[j * m + k] /= rjj;
+        __syncthreads();
+        if (t == 0) A[j * m + j] = rjj;
+        // trailing update of the upper triangle: A_ik -= R_ji R_jk, i <= k
+        for (int e = t; e < (m - j - 1) * (m - j - 1); e += blockDim.x) {
+            const int i = j + 1 + e / (m - j - 1), k = j + 1 + e % (m - j - 1);
+            if (k >= i) A[i * m + k] = fma(-A[j * m + i], A[j * m + k], A[i * m + k]);
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    const bool ok = bad == 0;
+    if (t == 0 && !ok) *flag = 1;
+    for (int e = t; e < m * m; e += blockDim.x) {
+        const int i = e / m, k = e % m;
+        R[e] = ok ? (k >= i ? A[e] : 0.0) : __builtin_nan("");
+    }
+    // R^{-1}: column k solves R x = e_k, x_i = 0 for i > k
+    for (int k = t; k < m; k += blockDim.x) {
+        for (int i = m - 1; i >= 0; i--) {
+            double v = 0.0;
+            if (i <= k) {
+                double s = (i == k) ? 1.0 : 0.0;
+                for (int j = i + 1; j <= k; j++) s = fma(-A[i * m + j], Rinv[j * m + k], s);
+                v = s / A[i * m + i];
+            }
+            Rinv[i * m + k] = ok ? v : __builtin_nan("");
+        }
+    }
+}
+
+// Gt[q][I][n] = sum_{j <= n} G[q][I][j] Rinv[j][n]
+__global__ void __launch_bounds__(256) k_basis_apply(const double* G, const double* Rinv, int m,
+                                                     int Q, double* Gt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)Q * 9 * m) return;
+    const int n = (int)(t % m);
+    const int64_t row = t / m;
+    double s = 0.0;
+    for (int j = 0; j <= n; j++) s = fma(G[row * m + j], Rinv[(int64_t)j * m + n], s);
+    Gt[t] = s;
+}
+
+void launch_basis_build(const BasisArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_gram, dim3(nblocks((int64_t)a.m * a.m, 256)), dim3(256), 0, s, a.G, a.w,
+                       a.m, a.Q, a.gram);
+    const size_t lds = sizeof(double) * ((size_t)a.m * a.m + 1);
+    hipLaunchKernelGGL(k_basis_factor, dim3(1), dim3(256), lds, s, (const double*)a.gram, a.m, a.R,
+                       a.Rinv, a.flag);
+    hipLaunchKernelGGL(k_basis_apply, dim3(nblocks((int64_t)a.Q * 9 * a.m, 256)), dim3(256), 0, s,
+                       a.G, (const double*)a.Rinv, a.m, a.Q, a.Gt);
+}
+
+// ---------------------------------------------------------------- per-point maps
+// y = T x for every macro point of a cluster, with T one of
+//   MAP_R    (R, upper):          at = R a
+//   MAP_RT   (R^T, lower):        r = R^T rt (optionally only ||r||_2)
+//   MAP_RINV (R^{-1}, upper):     a -= R^{-1} dt
+// Workgroup: 64 points, x staged in LDS ([m][64], coalesced), wave w takes the
+// modes i = w, w + 4, ...; T_ij is uniform per wave.  The norm is the sum of
+// the four waves' partial sums in a fixed order.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_mode_map(ModeMapArgs A) {
+    __shared__ double xs[kMaxModes][64];
+    __shared__ double part[4][64];
+    const int tid = threadIdx.x, p = tid & 63, wave = tid >> 6;
+    const int m = A.m;
+    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    const bool live = p0 + p < A.count;
+    for (int e = tid; e < m * 64; e += 256) {
+        const int j = e >> 6, pp = e & 63;
+        xs[j][pp] = (p0 + pp < A.count) ? A.x[(int64_t)j * A.count + p0 + pp] : 0.0;
+    }
+    __syncthreads();
+    double nrm = 0.0;
+    for (int i = wave; i < m; i += 4) {
+        double s = 0.0;
+        if (KIND == 1) {   // (R^T)_ij = R_ji, j <= i
+            for (int j = 0; j <= i; j++) s = fma(A.T[(int64_t)j * m + i], xs[j][p], s);
+        } else {           // upper: j >= i
+            for (int j = i; j < m; j++) s = fma(A.T[(int64_t)i * m + j], xs[j][p], s);
+        }
+        if (live) {
+            const int64_t o = (int64_t)i * A.count + p0 + p;
+            if (KIND == 2) A.y[o] -= s;
+            else if (A.y) A.y[o] = s;
+        }
+        nrm = fma(s, s, nrm);
+    }
+    if (A.norm) {
+        part[wave][p] = nrm;
+        __syncthreads();
+        if (wave == 0 && live)
+            A.norm[A.first + p0 + p] = sqrt((part[0][p] + part[1][p]) + (part[2][p] + part[3][p]));
+    }
+}
+
+void launch_mode_map(int kind, const ModeMapArgs& a, hipStream_t s) {
+    const dim3 grid(nblocks(a.count, 64)), block(256);
+    if (kind == MAP_R) hipLaunchKernelGGL(k_mode_map<0>, grid, block, 0, s, a);
+    else if (kind == MAP_RT) hipLaunchKernelGGL(k_mode_map<1>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_mode_map<2>, grid, block, 0, s, a);
+}
+
+// Exported blocks back to the caller's basis, one workgroup per macro point:
+// Kaa <- R^T Kt R, KaF <- R^T KaFt (in place, layouts [m*m][count], [m*9][count]).
+__global__ void __launch_bounds__(256) k_export_basis(const double* R, int m, int64_t count,
+                                                      double* Kaa, double* KaF) {
+    extern __shared__ double sm[];
+    double* K = sm;            // [m][m]
+    double* Z = sm + m * m;    // [m][m] = Kt R, then scratch for KaF
+    const int64_t p = blockIdx.x;
+    const int t = threadIdx.x;
+    if (Kaa) {
+        for (int e = t; e < m * m; e += blockDim.x) K[e] = Kaa[(int64_t)e * count + p];
+        __syncthreads();
+        for (int e = t; e < m * m; e += blockDim.x) {
+            const int i = e / m, k = e % m;
+            double s = 0.0;
+            for (int j = 0; j <= k; j++) s = fma(K[i * m + j], R[(int64_t)j * m + k], s);
+            Z[e] = s;
+        }
+        __syncthreads();
+        for (int e = t; e < m * m; e += blockDim.x) {
+            const int i = e / m, k = e % m;
+            double s = 0.0;
+            for (int j = 0; j <= i; j++) s = fma(R[(int64_t)j * m + i], Z[j * m + k], s);
+            Kaa[(int64_t)e * count + p] = s;
+        }
+        __syncthreads();
+    }
+    if (KaF) {
+        for (int e = t; e < m * 9; e += blockDim.x) Z[e] = KaF[(int64_t)e * count + p];
+        __syncthreads();
+        for (int e = t; e < m * 9; e += blockDim.x) {
+            const int i = e / 9, J = e % 9;
+            double s = 0.0;
+            for (int j = 0; j <= i; j++) s = fma(R[(int64_t)j * m + i], Z[j * 9 + J], s);
+            KaF[(int64_t)e * count + p] = s;
+        }
+    }
+}
+
+void launch_export_basis(const double* R, int m, int64_t count, double* Kaa, double* KaF,
+                         hipStream_t s) {
+    if (!Kaa && !KaF) return;
+    const size_t lds = sizeof(double) * 2 * (size_t)m * m + sizeof(double) * 9 * m;
+    hipLaunchKernelGGL(k_export_basis, dim3((unsigned)count), dim3(256), lds, s, R, m, count, Kaa,
+                       KaF);
+}
+
+int set_basis_attributes() {
+    const int m = kMaxModes;
+    const int lim_exp = (int)(sizeof(double) * (2 * m * m + 9 * m));
+    const int lim_fac = (int)(sizeof(double) * (m * m + 1));
+    if (hipFuncSetAttribute((const void*)k_export_basis, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim_exp) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_basis_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim_fac) != hipSuccess)
+        return HROM_E_HIP;
+    return HROM_OK;
+}
+
+}  // namespace hrom

@@ -307,10 +307,11 @@ void launch_stretch_increment(const UpdateArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_stretch_increment, dim3(nblocks(a.N, 256)), dim3(256), 0, s, a);
 }
 
-// a <- a - (y + X dU)  (Sec. 3.2.3), one thread per (group of kModesPerThread
-// modes, point): the point's dU is read once for the group.  Points flagged
-// as failed are left unchanged; without an increment (pure micro Newton step)
-// converged points (rnorm < tol) are frozen.
+// Increment of the amplitudes in the plan's mode basis, dt = y + X dU
+// (Sec. 3.2.3; the caller's a then moves by R^{-1} dt), one thread per (group
+// of kModesPerThread modes, point): the point's dU is read once for the
+// group.  Points flagged as failed get dt = 0; without an increment (pure
+// micro Newton step) so do converged points (rnorm < tol): they are frozen.
 constexpr int kModesPerThread = 4;
 __global__ void __launch_bounds__(256) k_update(UpdateArgs A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -319,19 +320,22 @@ __global__ void __launch_bounds__(256) k_update(UpdateArgs A) {
     const int kg = (int)(t / A.count);
     const int64_t pl = t - (int64_t)kg * A.count;
     const int64_t b = A.first + pl;
-    if (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) return;
-    if (!A.dFbar && !(A.rnorm[b] >= A.tol)) return;
+    const bool frozen = (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) ||
+                        (!A.dFbar && !(A.rnorm[b] >= A.tol));
     double dU[9];
 #pragma unroll
-    for (int J = 0; J < 9; J++) dU[J] = A.dU[J * A.N + b];
+    for (int J = 0; J < 9; J++) dU[J] = frozen ? 0.0 : A.dU[J * A.N + b];
 #pragma unroll
     for (int kk = 0; kk < kModesPerThread; kk++) {
         const int k = kg * kModesPerThread + kk;
         if (k < A.m) {
-            double s = A.y[(int64_t)k * A.count + pl];
+            double s = 0.0;
+            if (!frozen) {
+                s = A.y[(int64_t)k * A.count + pl];
 #pragma unroll
-            for (int J = 0; J < 9; J++) s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], dU[J], s);
-            A.a[(int64_t)k * A.count + pl] -= s;
+                for (int J = 0; J < 9; J++) s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], dU[J], s);
+            }
+            A.dt[(int64_t)k * A.count + pl] = s;
         }
     }
 }
