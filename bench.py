@@ -88,7 +88,7 @@ def build_inputs(N, m, Q, amp, seed):
     return cl, F
 
 
-def run_gpu(prec_name, cl, F, N, steps, warmup, split=True):
+def run_gpu(prec_name, cl, F, N, steps, warmup, split=True, refine=False):
     import torch
 
     import paper_2306_02687_amd as P
@@ -97,7 +97,8 @@ def run_gpu(prec_name, cl, F, N, steps, warmup, split=True):
 
     from paper_2306_02687_amd import tune
 
-    plan = P.Plan([solve.upload_cluster(cl, N)], precision=PREC[prec_name], split=split)
+    plan = P.Plan([solve.upload_cluster(cl, N)], precision=PREC[prec_name], split=split,
+                  refine=refine and prec_name != "fp64")
     th = solve.theta_dev(THETA_REF)
     Fd = solve.points_to_soa(F)
     st = solve.State(plan)
@@ -295,7 +296,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp64"])
-    ap.add_argument("--no-split", action="store_true", help="plain (single-term) low precision")
+    ap.add_argument("--refine", action="store_true",
+                    help="mixed plans: iterative refinement of the adjoint solve")
     ap.add_argument("--N", type=int, default=131072)
     ap.add_argument("--m", type=int, default=64)
     ap.add_argument("--Q", type=int, default=512)
@@ -333,9 +335,10 @@ def main():
     print(f"[bench] building inputs N={N} m={m} Q={Q}", file=sys.stderr, flush=True)
     cl, F = build_inputs(N, m, Q, args.amp, 4000)
 
-    split = not args.no_split
+    split = args.precision != "fp64"
     print(f"[bench] timing {args.precision} (split={split})", file=sys.stderr, flush=True)
-    res = run_gpu(args.precision, cl, F, N, args.steps, args.warmup, split=split)
+    res = run_gpu(args.precision, cl, F, N, args.steps, args.warmup, split=split,
+                  refine=args.refine)
     ms_step = res["wall"] / args.steps * 1e3
     value = N / (ms_step * 1e-3)
     fl_tan = tangent_flops_per_point(m, Q) * N

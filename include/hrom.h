@@ -67,16 +67,27 @@ extern "C" {
 #define HROM_PT_NOT_SPD 2    /* Cholesky of Kaa hit a non-positive pivot; LU used */
 #define HROM_PT_NOCONV 4     /* Newton did not reach the tolerance */
 #define HROM_PT_NONFINITE 8  /* non-finite input or output, or singular Kaa */
+#define HROM_PT_NOREFINE 16  /* hrom_backward with HROM_REFINE: after the last of the 3
+                                refinement steps the adjoint correction was still above 1e-5
+                                of lambda (lambda not known to the mixed path's accuracy) */
 
-/* arithmetic of the evaluation (Sec. 3.2 blocks) */
+/* arithmetic of the evaluation (Sec. 3.2 blocks).  The mixed modes require
+ * HROM_SPLIT (plan creation returns HROM_E_UNSUPPORTED without it): they are
+ * within 1e-5 (relative, per point) of the FP64 result on Pbar, Cbar and the
+ * adjoint gradients; the FP64 mode within 1e-12. */
 #define HROM_FP64 0          /* everything in double precision (FP64 MFMA) */
-#define HROM_MIXED_BF16 1    /* Kaa, KaF, KFF contraction on BF16 MFMA, FP32 accumulation */
+#define HROM_MIXED_BF16 1    /* Kaa, KaF, KFF contraction on BF16 MFMA, FP32 accumulation;
+                                residual, factorisation, Schur complement in FP64 */
 #define HROM_MIXED_FP16 2    /* same with FP16 MFMA */
 
 /* plan flags */
 #define HROM_OBJECTIVE 1u    /* RVE sees Ubar of Fbar = Rbar Ubar (Sec. 3.2.2) */
-#define HROM_SPLIT 2u        /* mixed modes: hi/lo split operands (3 MFMA terms) */
-#define HROM_REFINE 4u       /* mixed modes: refine the adjoint solve (default without SPLIT) */
+#define HROM_SPLIT 2u        /* mixed modes: hi/lo split operands (3 MFMA terms); required */
+#define HROM_REFINE 4u       /* mixed modes: the adjoint with the FP64 operator (FP64 tangent
+                                in the re-evaluation), lambda by iterative refinement whose
+                                residual uses that operator and whose correction uses the
+                                low-precision factor (per point at most 3 steps, stopping once
+                                a correction is below 1e-6 of lambda) */
 
 /* offset kinds for hrom_plan_offset */
 #define HROM_OFF_A 0         /* a, r, y: [m_c][count_c] */

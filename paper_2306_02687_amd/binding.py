@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhrom.so")
 
 HROM_OK = 0
-PT_JNONPOS, PT_NOT_SPD, PT_NOCONV, PT_NONFINITE = 1, 2, 4, 8
+PT_JNONPOS, PT_NOT_SPD, PT_NOCONV, PT_NONFINITE, PT_NOREFINE = 1, 2, 4, 8, 16
 FP64, MIXED_BF16, MIXED_FP16 = 0, 1, 2
 OBJECTIVE, SPLIT, REFINE = 1, 2, 4
 OFF_A, OFF_KAA, OFF_KAF = 0, 1, 2
@@ -160,8 +160,11 @@ class Plan:
     """A plan for N macro points partitioned into RVE clusters (in order)."""
 
     def __init__(self, clusters, precision: int = FP64, objective: bool = True,
-                 split: bool = False, refine: bool = False):
+                 split: bool | None = None, refine: bool = False):
+        """split defaults to True for the mixed precisions (which require it)."""
         L = load()
+        if split is None:
+            split = precision != FP64
         self.clusters = list(clusters)
         self.N = sum(c.count for c in self.clusters)
         arr = _cluster_array(self.clusters)

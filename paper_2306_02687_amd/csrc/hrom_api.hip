@@ -46,14 +46,12 @@ int hip_status() { return hipGetLastError() == hipSuccess ? HROM_OK : HROM_E_HIP
 
 bool mixed(const Plan& p) { return p.prec != HROM_FP64; }
 
-// one step of iterative refinement of the adjoint solve: on by default for
-// plain low-precision tangents, optional for split operands
-bool refine(const Plan& p) {
-    return mixed(p) && (!(p.flags & HROM_SPLIT) || (p.flags & HROM_REFINE));
-}
+// iterative refinement of the adjoint solve (mixed plans that ask for it)
+bool refine(const Plan& p) { return mixed(p) && (p.flags & HROM_REFINE); }
 
-// power-of-two scaling of w_q A_q for the low-precision operands (w ~ 1/Q)
-float wscale_for(int Q) { return std::ldexp(1.0f, (int)std::ceil(std::log2((double)Q))); }
+// ECM-weight part of the power-of-two scaling of w_q A_q for the low-precision
+// operands (w ~ 1/Q); the material part comes from theta on the device
+int qexp_for(int Q) { return (int)std::ceil(std::log2((double)Q)); }
 
 template <typename T>
 int upload(T** dst, const std::vector<T>& v) {
@@ -72,6 +70,9 @@ int plan_geometry(Plan& p, const hrom_cluster* clusters, int32_t ncl, int64_t N,
     if (!clusters || ncl < 1 || N < 1) return HROM_E_INVALID;
     if (precision != HROM_FP64 && precision != HROM_MIXED_BF16 && precision != HROM_MIXED_FP16)
         return HROM_E_INVALID;
+    // a single low-precision term per product misses the 1e-5 accuracy of the
+    // mixed path (and makes Kaa indefinite when some modes are soft)
+    if (precision != HROM_FP64 && !(flags & HROM_SPLIT)) return HROM_E_UNSUPPORTED;
     int64_t next = 0;
     for (int c = 0; c < ncl; c++) {
         const hrom_cluster& k = clusters[c];
@@ -147,6 +148,7 @@ size_t plan_carve(Plan& p, char* base) {
         take(d.R, (int64_t)d.m * d.m);
         take(d.Rinv, (int64_t)d.m * d.m);
         take(d.Gt, (int64_t)d.Q * 9 * d.m);
+        take(d.kscale, 1);
     }
     take(p.basis_flag, 1);
     take(p.at, p.a_len);
@@ -176,6 +178,7 @@ size_t plan_carve(Plan& p, char* base) {
     take(p.Lam, 9 * n);
     take(p.lam, p.a_len);
     take(p.rho, p.a_len);
+    take(p.conv, n);
     take(p.hr, 9 * n);
     take(p.gth, 4 * n);
     take(p.gth_part, 4 * kThetaChunks);
@@ -213,7 +216,6 @@ int build_groups(Plan& p) {
         g.first = d.first; g.count = d.count; g.off_a = d.off_a; g.ws_qs = d.ws_qs;
         g.ws_khat = d.ws_khat; g.ws_L = d.ws_L;
         g.Ghat = d.Ghat; g.Gf = d.Gf; g.w = d.w; g.phase = d.phase; g.Fpk = d.Fpk;
-        g.wscale = mixed(p) ? wscale_for(d.Q) : 1.0f;
         cg.push_back(g);
         p.max_m = std::max(p.max_m, d.m);
         // FP64 plans: the persistent tangent launch takes 4-point tiles
@@ -403,7 +405,8 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         e.r = p.r + c.off_a;
         e.Pr = p.Pr;
         e.status = status;
-        e.wscale = wscale_for(c.Q);
+        e.qexp = qexp_for(c.Q);
+        e.kscale_out = c.kscale;
         int rc = launch_kin(mixed(p) ? 1 : 0, e, stream);
         if (rc != HROM_OK) return rc;
         if (p.grouped) {
@@ -445,7 +448,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
             ca.first = c.first; ca.count = c.count; ca.N = p.N;
             ca.Khat = (const char*)p.Khat + tsz * (size_t)c.ws_khat;
             ca.r = p.r + c.off_a; ca.Pr = p.Pr;
-            ca.kscale = mixed(p) ? 1.0f / wscale_for(c.Q) : 1.0f;
+            ca.kscale = c.kscale;
             ca.outKaa = Kaa ? Kaa + c.off_kaa : nullptr;
             ca.outKaF = KaF ? KaF + c.off_kaf : nullptr;
             ca.outKFF = KFF;
@@ -482,7 +485,7 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
         ca.piv = p.piv + c.off_a;
         ca.y = p.y + c.off_a; ca.X = p.X + 9 * c.off_a;
         ca.Palg = p.Palg; ca.Cr = p.Cr; ca.rnorm = p.rnorm; ca.status = status;
-        ca.kscale = mixed(p) ? 1.0f / wscale_for(c.Q) : 1.0f;
+        ca.kscale = c.kscale;
         // SPD path: register-resident elimination, one launch per cluster so
         // that each runs at the occupancy its mode count allows; non-positive
         // pivots finish on the LU path
@@ -582,7 +585,8 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
     launch_bw_pullback(bp, stream);
     map_in(p, a, stream);
     for (const auto& c : p.cl) {
-        LambdaArgs la{c.m, c.first, c.count, p.N, p.X + 9 * c.off_a, p.gr, p.lam + c.off_a};
+        LambdaArgs la{c.m, c.first, c.count, p.N, p.X + 9 * c.off_a, p.gr, p.lam + c.off_a,
+                      p.conv + c.first};
         launch_lambda(la, stream);
         BackwardArgs ba{};
         ba.m = c.m; ba.Q = c.Q; ba.Qpad = c.Qpad; ba.mixed = mixed(p); ba.objective = objective;
@@ -592,17 +596,30 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
         ba.theta = theta; ba.Fr = p.Fr; ba.a = p.at + c.off_a; ba.lam = p.lam + c.off_a;
         ba.gr = p.gr; ba.hr = p.hr; ba.gth = p.gth; ba.rho = p.rho + c.off_a; ba.status = status;
         if (refine(p)) {
-            // one step of iterative refinement of the adjoint solve: the residual
-            // rho = KaF g_r - Kaa lambda with the accurate (FP32-tangent) operator,
-            // corrected with the factor of the low-precision Kaa
-            ba.with_rho = 1;
-            launch_backward_b(ba, stream);
-            RefineArgs ra{c.m, c.first, c.count, p.L + c.ws_L, p.piv + c.off_a, status,
-                          p.rho + c.off_a, p.lam + c.off_a};
-            launch_refine_lambda(ra, stream);
+            // iterative refinement of the adjoint solve: the residual
+            // rho = KaF g_r - Kaa lambda with the accurate (FP32-tangent)
+            // operator, corrected with the factor of the low-precision Kaa,
+            // until the correction falls below kRefineTol of lambda (per point;
+            // at most kRefineSteps steps; HROM_PT_NOREFINE when the last
+            // correction is still above kRefineFlagTol of lambda)
+            ba.conv = p.conv + c.first;
+            for (int step = 0; step < kRefineSteps; step++) {
+                ba.with_rho = 1;
+                int rc = launch_backward_b(ba, stream);
+                if (rc != HROM_OK) return rc;
+                RefineArgs ra{c.m, c.first, c.count, p.L + c.ws_L, p.piv + c.off_a, status,
+                              p.rho + c.off_a, p.lam + c.off_a, p.conv + c.first, kRefineTol,
+                              kRefineFlagTol, step + 1 == kRefineSteps ? 1 : 0};
+                launch_refine_lambda(ra, stream);
+            }
         }
+        // final pass (h_r, dL/dtheta): with refinement also on the FP64
+        // operator, so that the low-precision factor only preconditions the
+        // solve for lambda
         ba.with_rho = 0;
-        launch_backward_b(ba, stream);
+        if (refine(p)) ba.mixed = 0;
+        int rc = launch_backward_b(ba, stream);
+        if (rc != HROM_OK) return rc;
     }
     launch_bw_pushforward(bp, stream);
     launch_reduce_theta(p.N, p.gth, p.gth_part, gtheta, stream);

@@ -55,6 +55,7 @@ struct ClusterDev {
     double* R;             // [m][m] upper triangular
     double* Rinv;          // [m][m] upper triangular
     double* Gt;            // [Q][9][m]
+    float* kscale;         // [1] inverse scaling of the low-precision w_q A_q of the last eval
 };
 
 struct ClusterGPU;
@@ -102,6 +103,7 @@ struct Plan {
     double* Lam = nullptr;     // [9][N] backward: Linv(sym(F^T g))
     double* lam = nullptr;     // mode-indexed: adjoint solution lambda
     double* rho = nullptr;     // mode-indexed: refinement residual
+    int* conv = nullptr;       // [N]: adjoint refinement converged
     double* hr = nullptr;      // [9][N]
     double* gth = nullptr;     // [4][N] per-point theta gradients
     double* gth_part = nullptr;  // [4][kThetaChunks] partial sums of gth
@@ -144,7 +146,8 @@ struct EvalArgs {
     double* r;             // cluster block [m][count]
     double* Pr;            // [9][N]
     int* status;           // [N]
-    float wscale;          // mixed: power-of-two scaling of w_q A_q
+    int qexp;              // ceil(log2 Q): the ECM-weight part of the mixed-mode scaling
+    float* kscale_out;     // cluster's inverse scaling of w_q A_q (written by the kinematics)
 };
 int launch_kin(int mixed, const EvalArgs& a, hipStream_t s);
 int launch_eval_f64(int MT, int variant, const EvalArgs& a, hipStream_t s);
@@ -165,7 +168,7 @@ struct CondenseArgs {
     double* Cr;            // [81][N]
     double* rnorm;         // [N]
     int* status;
-    float kscale;          // inverse of the mixed-mode scaling
+    const float* kscale;   // device: inverse of the mixed-mode scaling of w_q A_q
     // optional exports (NULL = skip)
     double* outKaa;        // [m*m][count]
     double* outKaF;        // [m*9][count]
@@ -233,6 +236,8 @@ struct BackwardArgs {
     double* gth;           // [4][N]
     double* rho;           // cluster block (refinement residual) or null
     int* status;
+    const int* conv;       // refinement pass: cluster block [count]; workgroups whose points
+                           // have all converged skip the pass
 };
 int launch_backward_b(const BackwardArgs& a, hipStream_t s);
 
@@ -256,6 +261,7 @@ struct LambdaArgs {
     const double* X;       // cluster block [9m][count]
     const double* gr;      // [9][N]
     double* lam;           // cluster block [m][count]
+    int* conv;             // cluster block [count] or null: cleared (refinement restarts)
 };
 void launch_lambda(const LambdaArgs& a, hipStream_t s);
 
@@ -264,10 +270,17 @@ struct RefineArgs {
     int64_t first, count;
     const double* L;
     const int* piv;
-    const int* status;
+    int* status;
     const double* rho;     // cluster block
     double* lam;           // cluster block, updated in place
+    int* conv;             // cluster block [count]: 1 once the correction fell below tol
+    double tol;            // stop when ||dlambda|| <= tol ||lambda||
+    double flag_tol;       // after the last step: ||dlambda|| > flag_tol ||lambda|| flags the point
+    int last;              // last allowed step
 };
+constexpr int kRefineSteps = 3;          // cap on adjoint refinement steps
+constexpr double kRefineTol = 1e-6;      // stop: relative size of the last correction
+constexpr double kRefineFlagTol = 1e-5;  // HROM_PT_NOREFINE above this after the last step
 void launch_refine_lambda(const RefineArgs& a, hipStream_t s);
 
 constexpr int kThetaChunks = 256;   // stage-1 partials per theta component
@@ -334,7 +347,6 @@ struct ClusterGPU {
     const double* w;
     const int* phase;
     const uint16_t* Fpk;
-    float wscale;
 };
 
 struct WorkItem {

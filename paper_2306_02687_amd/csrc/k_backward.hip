@@ -6,7 +6,8 @@
 //   dmu_p  += w_q v_q : (F_q - F_q^{-T}),  dlam_p += w_q v_q : (ln J_q F_q^{-T})
 // for the phase p of q.  Optionally the refinement residual
 //   rho = sum_q G_q^T (w_q A_q v_q)  (= KaF g_r - Kaa lambda)
-// of the adjoint system is accumulated with the same operator.
+// of the adjoint system is accumulated with the same operator (for mixed
+// plans in FP64: the residual of their iterative refinement).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -81,6 +82,16 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
     const int m = A.m, MP = A.MP;
     constexpr int KS = 4 * MA;   // k-steps of the G a GEMM (the plan pads them to whole mode tiles)
     const int np = (int)min((int64_t)PT, A.count - p0);
+    if (RHO) {
+        // refinement pass: nothing to do once every point of the workgroup has converged
+        if (tid < PT) sbits[tid] = (tid < np && !A.conv[p0 + tid]) ? 1 : 0;
+        __syncthreads();
+        int live = 0;
+#pragma unroll 1
+        for (int p = 0; p < PT; p++) live |= sbits[p];
+        if (!live) return;
+        __syncthreads();
+    }
     if (tid < PT) sbits[tid] = 0;
     for (int e = tid; e < 4 * KS * PT; e += NT) {
         const int k = e / PT, p = e % PT;
@@ -309,16 +320,17 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
 }
 
 // one launch per cluster: the mixed path with four wavefronts (two workgroups
-// per CU), the FP64 path with eight
+// per CU), the FP64 path with eight; the refinement pass (the accurate
+// operator of a mixed plan: FP64 law, FP64 staging) with four
 template <int MA, bool MIXED, bool RHO>
-__global__ void __launch_bounds__(MIXED ? 256 : 512, MIXED ? 2 : 1) k_backward_b(BackwardArgs A) {
+__global__ void __launch_bounds__((MIXED || RHO) ? 256 : 512, MIXED ? 2 : 1) k_backward_b(BackwardArgs A) {
     __shared__ BwLds<16 * MA, typename std::conditional<MIXED, float, double>::type> Ls;
-    bw_body<MA, MIXED, RHO, MIXED ? 4 : 8>(A, (int64_t)blockIdx.x * kBwPT, Ls);
+    bw_body<MA, MIXED, RHO, (MIXED || RHO) ? 4 : 8>(A, (int64_t)blockIdx.x * kBwPT, Ls);
 }
 
 template <bool MIXED, bool RHO>
 static int launch_bw_t(const BackwardArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.count + kBwPT - 1) / kBwPT)), block(MIXED ? 256 : 512);
+    const dim3 grid((unsigned)((a.count + kBwPT - 1) / kBwPT)), block((MIXED || RHO) ? 256 : 512);
     switch ((a.m + 15) / 16) {
         case 1: hipLaunchKernelGGL((k_backward_b<1, MIXED, RHO>), grid, block, 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_backward_b<2, MIXED, RHO>), grid, block, 0, s, a); break;
@@ -332,9 +344,11 @@ static int launch_bw_t(const BackwardArgs& a, hipStream_t s) {
 }
 
 int launch_backward_b(const BackwardArgs& a, hipStream_t s) {
-    // the refinement pass exists for the low-precision tangents only
-    if (a.mixed) return a.with_rho ? launch_bw_t<true, true>(a, s) : launch_bw_t<true, false>(a, s);
-    if (a.with_rho) return HROM_E_INVALID;
+    // the refinement pass exists for the low-precision tangents only; its
+    // residual uses the FP64 operator (FP64 law and staging), so that the
+    // refined adjoint converges to the FP64 solution
+    if (a.with_rho) return a.mixed ? launch_bw_t<false, true>(a, s) : HROM_E_INVALID;
+    if (a.mixed) return launch_bw_t<true, false>(a, s);
     return launch_bw_t<false, false>(a, s);
 }
 

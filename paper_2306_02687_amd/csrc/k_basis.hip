@@ -119,50 +119,77 @@ void launch_basis_build(const BasisArgs& a, hipStream_t s) {
 //   MAP_R    (R, upper):          at = R a
 //   MAP_RT   (R^T, lower):        r = R^T rt (optionally only ||r||_2)
 //   MAP_RINV (R^{-1}, upper):     a -= R^{-1} dt
-// Workgroup: 64 points, x staged in LDS ([m][64], coalesced), wave w takes the
-// modes i = w, w + 4, ...; T_ij is uniform per wave.  The norm is the sum of
-// the four waves' partial sums in a fixed order.
-template <int KIND>
+// as an FP64 MFMA GEMM: workgroup = 64 points, wavefront w = points
+// 16 w .. 16 w + 15, every 16-row tile of T against them (16x16x4 MFMA: lane
+// (g, c) holds T[16 t + c][4 kb + g] and x[4 kb + g][16 w + c], accumulator
+// element e is row 16 t + g + 4 e, point 16 w + c); the k-steps left of an
+// upper tile's diagonal (right of a lower tile's) are zero and skipped.  The
+// norm sums each lane's squares, then the four lane groups in a fixed order.
+template <int KIND, int MA>
 __global__ void __launch_bounds__(256) k_mode_map(ModeMapArgs A) {
-    __shared__ double xs[kMaxModes][64];
-    __shared__ double part[4][64];
-    const int tid = threadIdx.x, p = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, c = lane & 15;
     const int m = A.m;
-    const int64_t p0 = (int64_t)blockIdx.x * 64;
-    const bool live = p0 + p < A.count;
-    for (int e = tid; e < m * 64; e += 256) {
-        const int j = e >> 6, pp = e & 63;
-        xs[j][pp] = (p0 + pp < A.count) ? A.x[(int64_t)j * A.count + p0 + pp] : 0.0;
+    const int64_t p = (int64_t)blockIdx.x * 64 + 16 * wave + c;   // this lane's point (B, D)
+    const bool live = p < A.count;
+    constexpr int KB = 4 * MA;   // k-steps over the padded modes
+    v4d acc[MA];
+#pragma unroll
+    for (int t = 0; t < MA; t++) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kb = 0; kb < KB; kb++) {
+        const int k = 4 * kb + g;
+        const double bx = (live && k < m) ? A.x[(int64_t)k * A.count + p] : 0.0;
+#pragma unroll
+        for (int t = 0; t < MA; t++) {
+            // upper T: tile t has nonzeros only for k >= 16 t; lower: k <= 16 t + 15
+            const bool used = (KIND == MAP_RT) ? (4 * kb <= 16 * t + 15) : (4 * kb + 3 >= 16 * t);
+            if (used) {
+                const int i = 16 * t + c;
+                double av = 0.0;
+                if (i < m && k < m) av = (KIND == MAP_RT) ? A.T[(int64_t)k * m + i] : A.T[(int64_t)i * m + k];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bx, acc[t], 0, 0, 0);
+            }
+        }
     }
-    __syncthreads();
     double nrm = 0.0;
-    for (int i = wave; i < m; i += 4) {
-        double s = 0.0;
-        if (KIND == 1) {   // (R^T)_ij = R_ji, j <= i
-            for (int j = 0; j <= i; j++) s = fma(A.T[(int64_t)j * m + i], xs[j][p], s);
-        } else {           // upper: j >= i
-            for (int j = i; j < m; j++) s = fma(A.T[(int64_t)i * m + j], xs[j][p], s);
+#pragma unroll
+    for (int t = 0; t < MA; t++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int i = 16 * t + g + 4 * e;
+            const double v = acc[t][e];
+            if (i < m && live) {
+                const int64_t o = (int64_t)i * A.count + p;
+                if (KIND == MAP_RINV) A.y[o] -= v;
+                else if (A.y) A.y[o] = v;
+            }
+            nrm = fma(v, v, nrm);
         }
-        if (live) {
-            const int64_t o = (int64_t)i * A.count + p0 + p;
-            if (KIND == 2) A.y[o] -= s;
-            else if (A.y) A.y[o] = s;
-        }
-        nrm = fma(s, s, nrm);
-    }
     if (A.norm) {
-        part[wave][p] = nrm;
-        __syncthreads();
-        if (wave == 0 && live)
-            A.norm[A.first + p0 + p] = sqrt((part[0][p] + part[1][p]) + (part[2][p] + part[3][p]));
+        nrm += __shfl_xor(nrm, 16);
+        nrm += __shfl_xor(nrm, 32);
+        if (g == 0 && live) A.norm[A.first + p] = sqrt(nrm);
+    }
+}
+
+template <int KIND>
+static void launch_map_t(const ModeMapArgs& a, hipStream_t s) {
+    const dim3 grid(nblocks(a.count, 64)), block(256);
+    switch ((a.m + 15) / 16) {
+        case 1: hipLaunchKernelGGL((k_mode_map<KIND, 1>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_mode_map<KIND, 2>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_mode_map<KIND, 3>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_mode_map<KIND, 4>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_mode_map<KIND, 5>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_mode_map<KIND, 6>), grid, block, 0, s, a); break;
     }
 }
 
 void launch_mode_map(int kind, const ModeMapArgs& a, hipStream_t s) {
-    const dim3 grid(nblocks(a.count, 64)), block(256);
-    if (kind == MAP_R) hipLaunchKernelGGL(k_mode_map<0>, grid, block, 0, s, a);
-    else if (kind == MAP_RT) hipLaunchKernelGGL(k_mode_map<1>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(k_mode_map<2>, grid, block, 0, s, a);
+    if (kind == MAP_R) launch_map_t<MAP_R>(a, s);
+    else if (kind == MAP_RT) launch_map_t<MAP_RT>(a, s);
+    else launch_map_t<MAP_RINV>(a, s);
 }
 
 // Exported blocks back to the caller's basis, one workgroup per macro point:

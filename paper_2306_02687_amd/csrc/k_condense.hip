@@ -69,7 +69,7 @@ __device__ __forceinline__ double khat_at<float>(const float* kh, int m, int MT,
 template <typename TT>
 __device__ void unpack_tiles(const CondenseArgs& A, const TT* kh, CondLds& S, bool kaa_only) {
     const int m = A.m, MT = A.MT, lane = threadIdx.x;
-    const double ks = (double)A.kscale;
+    const double ks = (double)*A.kscale;
     for (int e = lane; e < m * m; e += 64) {
         const int i = e / m, k = e % m;
         S.K[i * S.ld + k] = khat_at<TT>(kh, m, MT, i, k) * ks;
@@ -367,12 +367,16 @@ __device__ __forceinline__ double row_value(double x0, double x1, int j) {
     return j < 64 ? lane_value(x0, j) : lane_value(x1, j - 64);
 }
 
-__global__ void __launch_bounds__(64) k_refine_lambda(RefineArgs A) {
+// four points per workgroup, one per wavefront (no LDS, no barrier: the
+// wavefronts are independent)
+__global__ void __launch_bounds__(256) k_refine_lambda(RefineArgs A) {
     constexpr int U = 16;
-    const int m = A.m, lane = threadIdx.x;
-    const int64_t pl = blockIdx.x;
+    const int m = A.m, lane = threadIdx.x & 63;
+    const int64_t pl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pl >= A.count) return;
     const int64_t b = A.first + pl;
     if (A.status[b] & (HROM_PT_JNONPOS | HROM_PT_NONFINITE)) return;
+    if (A.conv[pl]) return;
     const double* Lg = A.L + pl * (int64_t)m * m;
     const int* piv = A.piv + pl * m;
     const int i0 = lane, i1 = lane + 64;
@@ -443,12 +447,32 @@ __global__ void __launch_bounds__(64) k_refine_lambda(RefineArgs A) {
             }
         }
     }
-    if (h0) A.lam[(int64_t)i0 * A.count + pl] += x0;
-    if (h1) A.lam[(int64_t)i1 * A.count + pl] += x1;
+    double l0 = 0.0, l1 = 0.0;
+    if (h0) {
+        l0 = A.lam[(int64_t)i0 * A.count + pl] + x0;
+        A.lam[(int64_t)i0 * A.count + pl] = l0;
+    }
+    if (h1) {
+        l1 = A.lam[(int64_t)i1 * A.count + pl] + x1;
+        A.lam[(int64_t)i1 * A.count + pl] = l1;
+    }
+    // stopping rule: the correction just applied is below tol of lambda
+    double dd = x0 * x0 + x1 * x1, ll = l0 * l0 + l1 * l1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        dd += __shfl_xor(dd, off);
+        ll += __shfl_xor(ll, off);
+    }
+    if (lane == 0) {
+        if (dd <= A.tol * A.tol * ll) A.conv[pl] = 1;
+        // after the last step a correction still above flag_tol of lambda
+        // means lambda is not known to the accuracy of the mixed path
+        else if (A.last && !(dd <= A.flag_tol * A.flag_tol * ll)) A.status[b] |= HROM_PT_NOREFINE;
+    }
 }
 
 void launch_refine_lambda(const RefineArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_refine_lambda, dim3((unsigned)a.count), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_refine_lambda, dim3((unsigned)((a.count + 3) / 4)), dim3(256), 0, s, a);
 }
 
 }  // namespace hrom
@@ -513,7 +537,7 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
     const int lane = threadIdx.x, lr = lane >> 3, lc = lane & 7;
     const int64_t b = A.first + pl;
     const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_len(m, MT, sizeof(TT) == 4);
-    const double ks = (double)A.kscale;
+    const double ks = (double)*A.kscale;
     __shared__ double cb[8 * MB];            // column / row broadcast
     __shared__ double zb[16];                // right-hand sides of one row
 

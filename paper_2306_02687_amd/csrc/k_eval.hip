@@ -122,6 +122,16 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
         sU[I][p] = (p < np) ? A.Fr[(int64_t)I * A.N + A.first + p0 + p] : ((I % 4 == 0) ? 1.0 : 0.0);
     }
     const double mu0 = A.theta[0], la0 = A.theta[1], mu1 = A.theta[2], la1 = A.theta[3];
+    // mixed path: w_q A_q leaves scaled by the power of two 2^(qexp + 4 - e),
+    // 2^(e - 1) <= max |theta| < 2^e, so that its entries are O(16) whatever the
+    // units of the moduli (FP16 range); the condensation divides it out
+    float wscale = 1.0f;
+    if (MIXED) {
+        const double mx = fmax(fmax(fabs(mu0), fabs(la0)), fmax(fabs(mu1), fabs(la1)));
+        const int e = (mx > 0.0 && isfinite(mx)) ? ilogb(mx) + 1 : 0;
+        wscale = ldexpf(1.0f, A.qexp + 4 - e);
+    }
+    if (blockIdx.x == 0 && tid == 0 && A.kscale_out) *A.kscale_out = 1.0f / wscale;
     v4d racc[MA][2];
 #pragma unroll
     for (int t = 0; t < MA; t++) racc[t][0] = racc[t][1] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -215,7 +225,7 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
                 const double c2 = ok ? wq * la : 0.0;
                 const int64_t off = ((p0 + p) * A.Qpad + q) * 12;
                 if (MIXED) {
-                    const float ws = A.wscale;
+                    const float ws = wscale;
                     float* o = (float*)A.qs + off;
                     v4f v0 = v4f{(float)Fi[0], (float)Fi[1], (float)Fi[2], (float)Fi[3]};
                     v4f v1 = v4f{(float)Fi[4], (float)Fi[5], (float)Fi[6], (float)Fi[7]};
@@ -835,7 +845,8 @@ __device__ inline EvalArgs group_eval_args(const GroupCall& G, int c, size_t tsz
     A.qs = (char*)G.qs + tsz * (size_t)C.ws_qs;
     A.Khat = (char*)G.Khat + tsz * (size_t)C.ws_khat;
     A.r = G.r + C.off_a; A.Pr = G.Pr; A.status = G.status;
-    A.wscale = C.wscale;
+    A.qexp = 0;
+    A.kscale_out = nullptr;
     return A;
 }
 

@@ -426,6 +426,7 @@ __global__ void __launch_bounds__(256) k_lambda(LambdaArgs A) {
     const int kg = (int)(t / A.count);
     const int64_t pl = t - (int64_t)kg * A.count;
     const int64_t b = A.first + pl;
+    if (kg == 0 && A.conv) A.conv[pl] = 0;
     double gr[9];
 #pragma unroll
     for (int J = 0; J < 9; J++) gr[J] = A.gr[J * A.N + b];

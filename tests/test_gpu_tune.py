@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("precision,split,m,Q", [(0, False, 32, 256), (1, True, 64, 512),
-                                                 (2, False, 24, 144)])
+                                                 (2, True, 24, 144)])
 def test_variants_identical_and_autotune(precision, split, m, Q, tmp_path):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
