@@ -100,7 +100,8 @@ typedef struct {
     int32_t m;              /* ROM modes, 1 <= m <= 96 */
     int32_t Q;              /* ECM points, Q >= 1 */
     const double* G;        /* device [Q][9][m]: gradient of mode m at point q */
-    const double* w;        /* device [Q]: ECM weights (sum = RVE measure V0 = 1) */
+    const double* w;        /* device [Q]: ECM weights; every ECM sum is divided by their sum,
+                               the RVE measure V0 (volume averages, Sec. 3.3) */
     const int32_t* phase;   /* device [Q]: 0 = matrix, 1 = inclusion */
     int64_t first;          /* macro points [first, first + count) use this cluster */
     int64_t count;

@@ -260,8 +260,9 @@ static int all_finite(const double *x, int n)
 /*   r    = sum_q w_q G_q^T P_q          Pr  = sum_q w_q P_q             */
 /*   Kaa  = sum_q G_q^T (w_q A_q) G_q    KaF = sum_q w_q G_q^T A_q       */
 /*   KFF  = sum_q w_q A_q                                               */
-/* The weights sum to the RVE measure V0 = 1, so the volume averages    */
-/* need no extra division.                                              */
+/* The weights sum to the RVE measure V0; every ECM sum is divided by  */
+/* V0 (the volume averages of Sec. 2 and 3.3), i.e. the weights enter  */
+/* as w_q / V0.  The workloads have V0 = 1.                             */
 /* ------------------------------------------------------------------ */
 typedef struct {
     int m, Q;
@@ -269,6 +270,7 @@ typedef struct {
     const double *w;   /* [Q] */
     const int *phase;  /* [Q] */
     double theta[4];   /* mu0, lam0, mu1, lam1 */
+    double V0;         /* sum of the weights, in order */
 } rve_t;
 
 static int eval_point(const rve_t *c, const double *Fr, const double *a,
@@ -284,7 +286,7 @@ static int eval_point(const rve_t *c, const double *Fr, const double *a,
     double *T = (double *)malloc(sizeof(double) * 9 * m);
     for (int q = 0; q < Q; q++) {
         const double *Gq = c->G + (size_t)q * 9 * m;
-        const double wq = c->w[q];
+        const double wq = c->w[q] / c->V0;
         const double mu = c->theta[2 * c->phase[q]], lam = c->theta[2 * c->phase[q] + 1];
         double F[9], P[9], A[81], J;
         for (int I = 0; I < 9; I++) {
@@ -622,6 +624,8 @@ static rve_t make_rve(int m, int Q, const double *G, const double *w, const int 
     rve_t c;
     c.m = m; c.Q = Q; c.G = G; c.w = w; c.phase = phase;
     for (int i = 0; i < 4; i++) c.theta[i] = theta[i];
+    c.V0 = 0.0;
+    for (int q = 0; q < Q; q++) c.V0 += w[q];
     return c;
 }
 
@@ -829,7 +833,7 @@ int orc_backward(int m, int Q, const double *G, const double *w, const int *phas
             for (int I = 0; I < 9; I++) {
                 double s = 0.0;
                 for (int J2 = 0; J2 < 9; J2++) s += A[9 * I + J2] * v[J2];
-                hr[I] += w[q] * s;
+                hr[I] += w[q] / c.V0 * s;
             }
             double dmu = 0.0, dlam = 0.0;
             for (int i = 0; i < 3; i++)
@@ -837,8 +841,8 @@ int orc_backward(int m, int Q, const double *G, const double *w, const int *phas
                     dmu += v[3 * i + j] * (F[3 * i + j] - Fi[3 * j + i]);
                     dlam += v[3 * i + j] * ell * Fi[3 * j + i];
                 }
-            gt[2 * p] += w[q] * dmu;
-            gt[2 * p + 1] += w[q] * dlam;
+            gt[2 * p] += w[q] / c.V0 * dmu;
+            gt[2 * p + 1] += w[q] / c.V0 * dlam;
         }
         double gFb[9];
         if (objective) {

@@ -534,10 +534,7 @@ __global__ void __launch_bounds__(256) k_build_ghat(LayoutArgs A) {
         // GT[(q/64)][J][n][q%64]
         A.GT[(((int64_t)(q >> 6) * 9 + J) * A.m + n) * 64 + (q & 63)] = (q < A.Q) ? v : 0.0;
     }
-    if (J == 0 && n == 0) {
-        A.wpad[q] = (q < A.Q) ? A.w[q] : 0.0;
-        A.phpad[q] = (q < A.Q) ? A.phase[q] : 0;
-    }
+    if (J == 0 && n == 0) A.phpad[q] = (q < A.Q) ? A.phase[q] : 0;
 }
 
 // Packed MFMA fragments of the mode gradients for the mixed tangent: ECM point
@@ -601,9 +598,24 @@ __global__ void __launch_bounds__(256) k_build_gf(LayoutArgs A) {
     A.Gf[t] = (q < A.Q && k < A.m) ? A.G[((int64_t)q * 9 + I) * A.m + k] : 0.0;
 }
 
+// Weights of the volume averages (Sec. 2 and 3.3): w_q / V0 with V0 = sum_q
+// w_q (summed in order), so that the ECM sums are averages over the RVE
+// whatever measure the caller's weights add up to.
+__global__ void __launch_bounds__(256) k_normalize_w(const double* w, int Q, int Qpad, double* wpad) {
+    __shared__ double V0;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < Q; q++) s += w[q];
+        V0 = s;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < Qpad; q += blockDim.x) wpad[q] = (q < Q) ? w[q] / V0 : 0.0;
+}
+
 void launch_build_layouts(const LayoutArgs& a, hipStream_t s) {
     const int64_t n1 = (int64_t)a.Qpad * 9 * a.MP;
     hipLaunchKernelGGL(k_build_ghat, dim3(nblocks(n1, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_normalize_w, dim3(1), dim3(256), 0, s, a.w, a.Q, a.Qpad, a.wpad);
     const int64_t n3 = (int64_t)a.Qpad * 9 / 16 * a.KS * 64;
     hipLaunchKernelGGL(k_build_gf, dim3(nblocks(n3, 256)), dim3(256), 0, s, a);
     if (a.prec != HROM_FP64) {

@@ -426,3 +426,30 @@ def test_determinism(dev):
         o2 = run_eval(dev, plan, THETA_REF, F, a, blocks=False)
         assert torch.equal(o1["Pbar"], o2["Pbar"]) and torch.equal(o1["Cbar"], o2["Cbar"])
         plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_weights_of_any_measure(dev, orc, precision):
+    """ECM weights that add up to V0 = 2.5 instead of 1: the sums are volume
+    averages (divided by V0), so the converged Pbar, Cbar equal those of the
+    normalised weights and the oracle's with the same weights."""
+    from paper_2306_02687_amd import solve
+    log_case("weights measure", precision)
+    N = 8
+    cl = make_cluster(16, 96, 6300)
+    F, _, _ = make_macro_points(N, 6301, amp=0.05)
+    sc = copy.copy(cl)
+    sc.w = 2.5 * cl.w
+    out = []
+    for c in (cl, sc):
+        plan = make_plan(dev, [(c, N)], precision=precision)
+        st = solve.newton(plan, solve.theta_dev(THETA_REF), solve.points_to_soa(F), tol=1e-12)
+        out.append((solve.soa_to_points(st.Pbar), solve.soa_to_points(st.Cbar)))
+        assert int(st.status.max().item()) == 0
+        plan.close()
+    ref = orc.newton(sc, THETA_REF, F, tol=1e-12)
+    bar = TOL64 if precision == 0 else TOLMIX
+    assert rel_err_points(out[1][0], ref["Pbar"]).max() < bar
+    assert rel_err_points(out[1][1], ref["Cbar"].reshape(N, -1)).max() < bar
+    assert rel_err_points(out[1][0], out[0][0]).max() < bar
+    assert rel_err_points(out[1][1], out[0][1]).max() < bar

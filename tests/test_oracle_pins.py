@@ -235,8 +235,7 @@ def test_residual_and_stress_are_energy_gradients(orc, small):
 
 def test_hyper_equals_full_integration_with_zero_weights(orc):
     """ECM sum over a subset z~ of the full points (Sec. 3.3) equals, bitwise,
-    the full-integration sum with the weights outside z~ set to zero; with
-    z~ = all points the two are the same sum."""
+    the full-integration sum with the weights outside z~ set to zero."""
     full = make_cluster(6, 40, 31)
     sub_idx = np.sort(RNG.choice(40, size=12, replace=False))
     w_hyper = np.zeros(40)
@@ -255,10 +254,36 @@ def test_hyper_equals_full_integration_with_zero_weights(orc):
     o2 = orc.eval_blocks(hyper, THETA_REF, F, a)
     for k in ("r", "Pr", "Kaa", "KaF", "KFF"):
         assert np.array_equal(o1[k], o2[k]), k
-    o3 = orc.eval_blocks(full, THETA_REF, F, a)
-    o4 = orc.eval_blocks(copy.copy(full), THETA_REF, F, a)
+
+
+def test_ecm_sums_invariant_to_point_order_and_weight_measure(orc):
+    """The ECM sums are sums over an unordered set of points (Sec. 3.3):
+    permuting the points (with their weights, gradients and phases) changes
+    the blocks only by rounding; and they are averages over the RVE (Sec. 2):
+    weights that add up to another measure V0 = 2.5 give the same blocks, and
+    the same condensed stress and tangent."""
+    cl = make_cluster(6, 40, 33)
+    F, _, _ = make_macro_points(4, 34)
+    a = 0.05 * RNG.standard_normal((4, 6))
+    o = orc.eval_blocks(cl, THETA_REF, F, a)
+    perm = RNG.permutation(40)
+    pc = copy.copy(cl)
+    pc.G = np.ascontiguousarray(cl.G[perm])
+    pc.w = np.ascontiguousarray(cl.w[perm])
+    pc.phase = np.ascontiguousarray(cl.phase[perm])
+    op = orc.eval_blocks(pc, THETA_REF, F, a)
     for k in ("r", "Pr", "Kaa", "KaF", "KFF"):
-        assert np.array_equal(o3[k], o4[k])
+        assert rel(op[k], o[k]) < 1e-14, k
+    # a permutation that is not the identity does change the summation order
+    assert any(not np.array_equal(op[k], o[k]) for k in ("r", "Kaa"))
+    sc = copy.copy(cl)
+    sc.w = 2.5 * cl.w
+    os_ = orc.eval_blocks(sc, THETA_REF, F, a)
+    for k in ("r", "Pr", "Kaa", "KaF", "KFF"):
+        assert rel(os_[k], o[k]) < 1e-15, k
+    n1 = orc.newton(cl, THETA_REF, F)
+    n2 = orc.newton(sc, THETA_REF, F)
+    assert rel(n2["Pbar"], n1["Pbar"]) < 1e-14 and rel(n2["Cbar"], n1["Cbar"]) < 1e-14
 
 
 # ---------------------------------------------------------------- condensation + Newton
