@@ -8,11 +8,13 @@ any code of the method.
 from .generators import (  # noqa: F401
     THETA_REF,
     THETA_CONTRAST,
+    MAT_J2,
     Cluster,
     make_cluster,
     make_cluster_illcond,
     make_macro_points,
     make_increments,
+    make_load_path,
     zipf_counts,
     perturbed_theta,
     WORKLOADS,

@@ -31,6 +31,12 @@ import numpy as np
 
 # (mu_matrix, lambda_matrix, mu_inclusion, lambda_inclusion)
 THETA_REF = np.array([1.0, 1.5, 10.0, 15.0], dtype=np.float64)
+# J2 plasticity of the paper's Example 1 (Sec. 5): matrix E = 1, nu = 0.3,
+# sigma_y0 = 0.01 E, hardening modulus h = 0.016 E; elastic inclusions E = 10,
+# nu = 0.3 (a yield stress beyond reach).  Per phase (mu, lambda, sigma_y0, H)
+# with mu = E / (2 (1 + nu)), lambda = E nu / ((1 + nu)(1 - 2 nu)).
+MAT_J2 = np.array([1.0 / 2.6, 0.3 / 0.52, 0.01, 0.016,
+                   10.0 / 2.6, 3.0 / 0.52, 1.0e30, 0.0], dtype=np.float64)
 # high phase contrast (soft matrix, stiff inclusions): the mode-space stiffness
 # is ill-conditioned through the material rather than through the basis
 THETA_CONTRAST = np.array([1.0e-3, 1.5e-3, 10.0, 15.0], dtype=np.float64)
@@ -151,6 +157,16 @@ def make_increments(R: np.ndarray, n_iter: int, seed: int,
         dH = _sym_from_upper(rng.uniform(-amp, amp, size=(N, 6)))
         out[k] = R @ dH
     return out
+
+
+def make_load_path(N: int, seed: int, amp: float = 0.03, levels=(0.25, 0.5, 0.75, 1.0, 0.6, 0.2),
+                   max_angle: float = 0.3):
+    """A load-unload path of macro states ``Fbar_k = R (I + t_k H)``, ``[K, N, 3, 3]``,
+    with ``H`` symmetric U(-amp, amp) and ``R`` drawn as in ``make_macro_points``,
+    ``t_k`` the given levels (rising, then falling)."""
+    _, R, H = make_macro_points(N, seed, amp=amp, max_angle=max_angle)
+    t = np.asarray(levels, dtype=np.float64)
+    return np.ascontiguousarray(R[None] @ (np.eye(3)[None, None] + t[:, None, None, None] * H[None]))
 
 
 def zipf_counts(total: int, n: int, s: float) -> list[int]:

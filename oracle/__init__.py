@@ -59,6 +59,10 @@ def lib():
         L.orc_backward.argtypes = [i32, i32, P, P, P, P, i32, i64, P, P, P, P, P, P, P]
         L.orc_stretch_increment.argtypes = [i64, P, P, P]
         L.orc_cauchy.argtypes = [i64, P, P, P, P, P, P]
+        L.orc_j2_law.argtypes = [i64, P, P, P, P, P, P]
+        L.orc_j2_eval.argtypes = [i32, i32, P, P, P, P, i64, P, P, P, P, P, P, P, P, P, P]
+        L.orc_j2_newton.argtypes = [i32, i32, P, P, P, P, i32, i64, P, P, P, d, i32, P, P, P,
+                                    P, P, P]
         _lib = L
     return _lib
 
@@ -214,3 +218,70 @@ def backward(cl, theta, Fbar, a, g, objective=True):
     lib().orc_backward(cl.m, cl.Q, _p(G), _p(w), _p(ph), _p(th), int(objective), N,
                        _p(Fbar.reshape(N, 9)), _p(a), _p(g), _p(gF), _p(gpt), _p(gth), _p(st))
     return dict(gF=gF, gtheta=gth, gtheta_pt=gpt, status=st)
+
+
+# ---------------------------------------------------------------- J2 plasticity
+# Material of the paper's Example 1 (Sec. 5): mat[8] = per phase (mu, lambda,
+# initial yield stress sigma_y0, linear hardening modulus H); history per
+# (macro point, ECM point) = (eps_p xx yy zz xy yz xz, alpha).
+
+def j2_law(F, mp, hn=None):
+    """Pointwise J2 return map: sigma[N,9], tangent dsigma/dF [N,9,9], new history [N,7]."""
+    F = _f64(F)
+    N = F.size // 9
+    hn = np.zeros((N, 7)) if hn is None else _f64(hn, (N, 7))
+    P, A, ht = np.zeros((N, 9)), np.zeros((N, 9, 9)), np.zeros((N, 7))
+    lib().orc_j2_law(N, _p(F.reshape(N, 9)), _p(_f64(mp, (4,))), _p(hn), _p(P), _p(A), _p(ht))
+    return P, A, ht
+
+
+def j2_eval(cl, mat, Fr, a, hist_n=None):
+    """Raw RVE-frame blocks with J2 at ECM points; hist_n / hist_t [N, Q, 7]."""
+    G, w, ph, _ = _cluster_args(cl, np.zeros(4))
+    Fr = _f64(Fr)
+    N = Fr.size // 9
+    a = _f64(a, (N, cl.m))
+    m, Q = cl.m, cl.Q
+    hn = np.zeros((N, Q, 7)) if hist_n is None else _f64(hist_n, (N, Q, 7))
+    out = dict(r=np.zeros((N, m)), Pr=np.zeros((N, 9)), Kaa=np.zeros((N, m, m)),
+               KaF=np.zeros((N, m, 9)), KFF=np.zeros((N, 9, 9)), hist=np.zeros((N, Q, 7)),
+               status=np.zeros(N, dtype=np.int32))
+    lib().orc_j2_eval(m, Q, _p(G), _p(w), _p(ph), _p(_f64(mat, (8,))), N, _p(Fr.reshape(N, 9)),
+                      _p(a), _p(hn), _p(out["r"]), _p(out["Pr"]), _p(out["Kaa"]), _p(out["KaF"]),
+                      _p(out["KFF"]), _p(out["hist"]), _p(out["status"]))
+    return out
+
+
+def j2_newton(cl, mat, Fbar, a0=None, hist_n=None, tol=1e-10, max_it=25, objective=True):
+    """Micro Newton at fixed Fbar from the committed history hist_n; the
+    returned 'hist' is the state of the converged evaluation (to commit)."""
+    G, w, ph, _ = _cluster_args(cl, np.zeros(4))
+    Fbar = _f64(Fbar)
+    N = Fbar.size // 9
+    a = np.zeros((N, cl.m)) if a0 is None else _f64(a0, (N, cl.m)).copy()
+    hn = np.zeros((N, cl.Q, 7)) if hist_n is None else _f64(hist_n, (N, cl.Q, 7))
+    o = dict(a=a, Pbar=np.zeros((N, 9)), Cbar=np.zeros((N, 9, 9)), rnorm=np.zeros(N),
+             iters=np.zeros(N, dtype=np.int32), status=np.zeros(N, dtype=np.int32),
+             hist=np.zeros((N, cl.Q, 7)))
+    lib().orc_j2_newton(cl.m, cl.Q, _p(G), _p(w), _p(ph), _p(_f64(mat, (8,))), int(objective), N,
+                        _p(Fbar.reshape(N, 9)), _p(a), _p(hn), float(tol), int(max_it),
+                        _p(o["Pbar"]), _p(o["Cbar"]), _p(o["rnorm"]), _p(o["iters"]),
+                        _p(o["status"]), _p(o["hist"]))
+    return o
+
+
+def j2_path(cl, mat, Fbar_path, tol=1e-10, max_it=25, objective=True):
+    """Load path of macro states Fbar_path[K, N, 3, 3]: at each state a micro
+    Newton from the previous amplitudes and the committed history, then the
+    converged history is committed.  Returns the list of per-state results."""
+    Fp = _f64(Fbar_path)
+    K = Fp.shape[0]
+    N = Fp[0].size // 9
+    a, hist = np.zeros((N, cl.m)), np.zeros((N, cl.Q, 7))
+    out = []
+    for k in range(K):
+        o = j2_newton(cl, mat, Fp[k], a0=a, hist_n=hist, tol=tol, max_it=max_it,
+                      objective=objective)
+        a, hist = o["a"], o["hist"]
+        out.append(o)
+    return out

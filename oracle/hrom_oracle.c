@@ -34,6 +34,11 @@
  *   Cauchy stress and tangent ...... Sec. 3.2.2 eq. (biotstress), App. A
  *                                    eqs. (tangent_continuum),
  *                                    (d_Cauchy_d_Biot), (dUdot_dd)
+ *   J2 plasticity at ECM points .... Sec. 5 Example 1 (elastic-plastic
+ *                                    matrix with initial yield stress and
+ *                                    linear hardening, elastic inclusions);
+ *                                    state only at the hyper integration
+ *                                    points (Sec. 4)
  */
 #include <math.h>
 #include <stdint.h>
@@ -271,10 +276,79 @@ typedef struct {
     const int *phase;  /* [Q] */
     double theta[4];   /* mu0, lam0, mu1, lam1 */
     double V0;         /* sum of the weights, in order */
+    int j2;            /* material: 0 Neo-Hooke (theta), 1 J2 plasticity (mat) */
+    double mat[8];     /* J2: per phase (mu, lam, sigma_y0, H) */
 } rve_t;
 
+/* ------------------------------------------------------------------ */
+/* Small-strain J2 (von Mises) plasticity with linear isotropic         */
+/* hardening, the material of the paper's Example 1 (Sec. 5): an        */
+/* elastic-plastic matrix with initial yield stress sigma_y0 and        */
+/* hardening modulus H, elastic inclusions (sigma_y0 beyond reach).      */
+/* Strain eps = sym(F) - I; state per ECM point h = (eps_p[6], alpha)   */
+/* with eps_p ordered xx, yy, zz, xy, yz, xz and alpha the equivalent   */
+/* plastic strain.  Radial return (a textbook algorithm, restated):     */
+/*   s_tr = 2 mu (dev eps - eps_p_n),  f = |s_tr| - sqrt(2/3) (sy0 +     */
+/*   H alpha_n);  f <= 0: elastic;  else dgam = f / (2 mu + 2 H / 3),    */
+/*   n = s_tr / |s_tr|, s = s_tr - 2 mu dgam n, eps_p += dgam n,        */
+/*   alpha += sqrt(2/3) dgam.  sigma = kappa tr(eps) I + s, kappa =      */
+/*   lam + 2 mu / 3.  Consistent tangent dsigma/deps:                   */
+/*   kappa 1x1 + 2 mu th (I_sym - 1x1 / 3) - 2 mu thb n x n,            */
+/*   th = 1 - 2 mu dgam / |s_tr|, thb = 1 / (1 + H / (3 mu)) - (1 - th). */
+/* As a function of F: P = sigma (symmetric), A[9I+J] = dsigma_I/dF_J.   */
+/* ------------------------------------------------------------------ */
+static const int kVoigt[9] = {0, 3, 5, 3, 1, 4, 5, 4, 2};   /* (i, j) -> eps_p slot */
+
+static void j2_law(const double *F, const double *mp, const double *hn, double *P, double *A,
+                   double *ht)
+{
+    const double mu = mp[0], lam = mp[1], sy0 = mp[2], H = mp[3];
+    const double kappa = lam + 2.0 * mu / 3.0;
+    double eps[9], ep[9], s_tr[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            eps[3 * i + j] = 0.5 * (F[3 * i + j] + F[3 * j + i]) - (i == j ? 1.0 : 0.0);
+            ep[3 * i + j] = hn[kVoigt[3 * i + j]];
+        }
+    const double tr = eps[0] + eps[4] + eps[8];
+    double nrm2 = 0.0;
+    for (int I = 0; I < 9; I++) {
+        const double dev = eps[I] - ((I % 4 == 0) ? tr / 3.0 : 0.0);
+        s_tr[I] = 2.0 * mu * (dev - ep[I]);
+        nrm2 += s_tr[I] * s_tr[I];
+    }
+    const double nrm = sqrt(nrm2);
+    const double f = nrm - sqrt(2.0 / 3.0) * (sy0 + H * hn[6]);
+    double dgam = 0.0, th = 1.0, thb = 0.0, n[9] = {0};
+    if (f > 0.0) {
+        dgam = f / (2.0 * mu + 2.0 * H / 3.0);
+        for (int I = 0; I < 9; I++) n[I] = s_tr[I] / nrm;
+        th = 1.0 - 2.0 * mu * dgam / nrm;
+        thb = 1.0 / (1.0 + H / (3.0 * mu)) - (1.0 - th);
+    }
+    for (int I = 0; I < 9; I++)
+        P[I] = ((I % 4 == 0) ? kappa * tr : 0.0) + s_tr[I] - 2.0 * mu * dgam * n[I];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            for (int k = 0; k < 3; k++)
+                for (int l = 0; l < 3; l++) {
+                    const double d_ij = (i == j), d_kl = (k == l);
+                    const double isym = 0.5 * ((i == k) * (j == l) + (i == l) * (j == k));
+                    A[9 * (3 * i + j) + 3 * k + l] = kappa * d_ij * d_kl
+                        + 2.0 * mu * th * (isym - d_ij * d_kl / 3.0)
+                        - 2.0 * mu * thb * n[3 * i + j] * n[3 * k + l];
+                }
+    if (ht) {
+        for (int v = 0; v < 6; v++) ht[v] = hn[v];
+        for (int i = 0; i < 3; i++)
+            for (int j = i; j < 3; j++) ht[kVoigt[3 * i + j]] = hn[kVoigt[3 * i + j]] + dgam * n[3 * i + j];
+        ht[6] = hn[6] + sqrt(2.0 / 3.0) * dgam;
+    }
+}
+
 static int eval_point(const rve_t *c, const double *Fr, const double *a,
-                      double *r, double *Pr, double *Kaa, double *KaF, double *KFF)
+                      double *r, double *Pr, double *Kaa, double *KaF, double *KFF,
+                      const double *hn, double *ht)
 {
     const int m = c->m, Q = c->Q;
     int status = 0;
@@ -294,7 +368,9 @@ static int eval_point(const rve_t *c, const double *Fr, const double *a,
             for (int k = 0; k < m; k++) s += a[k] * Gq[I * m + k];
             F[I] = s;
         }
-        if (neo_hooke(F, mu, lam, P, A, &J, NULL, NULL) != 0) {
+        if (c->j2) {
+            j2_law(F, c->mat + 4 * c->phase[q], hn + 7 * (size_t)q, P, A, ht ? ht + 7 * (size_t)q : NULL);
+        } else if (neo_hooke(F, mu, lam, P, A, &J, NULL, NULL) != 0) {
             status |= ORC_PT_JNONPOS;
             continue;
         }
@@ -568,7 +644,8 @@ static void work_free(work_t *W)
 }
 
 /* objective: 1 = RVE sees Ubar (default), 0 = RVE sees Fbar directly */
-static int point_eval(const rve_t *c, int objective, const double *Fbar, const double *a, work_t *W)
+static int point_eval(const rve_t *c, int objective, const double *Fbar, const double *a, work_t *W,
+                      const double *hn, double *ht)
 {
     int status = 0;
     const double *Fr;
@@ -581,7 +658,7 @@ static int point_eval(const rve_t *c, int objective, const double *Fbar, const d
     } else {
         Fr = Fbar;
     }
-    status |= eval_point(c, Fr, a, W->r, W->Pr, W->Kaa, W->KaF, W->KFF);
+    status |= eval_point(c, Fr, a, W->r, W->Pr, W->Kaa, W->KaF, W->KFF, hn, ht);
     if (status & ORC_PT_JNONPOS) return status;
     status |= condense_point(c->m, W->Kaa, W->KaF, W->KFF, W->r, W->Pr, W->y, W->X, W->Palg, W->Cr);
     double s = 0.0;
@@ -626,6 +703,8 @@ static rve_t make_rve(int m, int Q, const double *G, const double *w, const int 
     for (int i = 0; i < 4; i++) c.theta[i] = theta[i];
     c.V0 = 0.0;
     for (int q = 0; q < Q; q++) c.V0 += w[q];
+    c.j2 = 0;
+    for (int i = 0; i < 8; i++) c.mat[i] = 0.0;
     return c;
 }
 
@@ -672,7 +751,8 @@ int orc_eval(int m, int Q, const double *G, const double *w, const int *phase, c
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t b = 0; b < N; b++) {
         status[b] = eval_point(&c, Fr + 9 * b, a + (size_t)m * b, r + (size_t)m * b, Pr + 9 * b,
-                               Kaa + (size_t)m * m * b, KaF + (size_t)9 * m * b, KFF + 81 * b);
+                               Kaa + (size_t)m * m * b, KaF + (size_t)9 * m * b, KFF + 81 * b,
+                               NULL, NULL);
     }
     return 0;
 }
@@ -688,7 +768,7 @@ int orc_point_eval(int m, int Q, const double *G, const double *w, const int *ph
     for (int64_t b = 0; b < N; b++) {
         work_t W;
         work_alloc(&W, m);
-        int st = point_eval(&c, objective, Fbar + 9 * b, a + (size_t)m * b, &W);
+        int st = point_eval(&c, objective, Fbar + 9 * b, a + (size_t)m * b, &W, NULL, NULL);
         memcpy(Pbar + 9 * b, W.Pbar, sizeof W.Pbar);
         memcpy(Cbar + 81 * b, W.Cbar, sizeof W.Cbar);
         if (rnorm) rnorm[b] = W.rnorm;
@@ -720,7 +800,7 @@ int orc_newton(int m, int Q, const double *G, const double *w, const int *phase,
         double *ab = a + (size_t)m * b;
         int st = 0, nev = 0, conv = 0;
         for (int it = 0; it < max_it; it++) {
-            st = point_eval(&c, objective, Fbar + 9 * b, ab, &W);
+            st = point_eval(&c, objective, Fbar + 9 * b, ab, &W, NULL, NULL);
             nev++;
             if (st & (ORC_PT_JNONPOS | ORC_PT_NONFINITE)) break;
             if (W.rnorm < tol) { conv = 1; break; }
@@ -757,7 +837,7 @@ int orc_monolithic(int m, int Q, const double *G, const double *w, const int *ph
         double *ab = a + (size_t)m * b;
         int st_all = 0;
         for (int k = 0; k < K; k++) {
-            int st = point_eval(&c, objective, F, ab, &W);
+            int st = point_eval(&c, objective, F, ab, &W, NULL, NULL);
             st_all |= st;
             memcpy(Pbar + ((size_t)k * N + b) * 9, W.Pbar, sizeof W.Pbar);
             memcpy(Cbar + ((size_t)k * N + b) * 81, W.Cbar, sizeof W.Cbar);
@@ -795,7 +875,7 @@ int orc_backward(int m, int Q, const double *G, const double *w, const int *phas
         work_alloc(&W, m);
         const double *ab = a + (size_t)m * b;
         const double *gb = g + 9 * b;
-        int st = point_eval(&c, objective, Fbar + 9 * b, ab, &W);
+        int st = point_eval(&c, objective, Fbar + 9 * b, ab, &W, NULL, NULL);
         double Fr[9], gr[9], Lam[9];
         if (objective) {
             double FtG[9], H[9];
@@ -890,6 +970,83 @@ int orc_stretch_increment(int64_t N, const double *F, const double *dF, double *
         polar_t P;
         polar_split(F + 9 * b, &P);
         stretch_increment(&P, dF + 9 * b, dU + 9 * b);
+    }
+    return 0;
+}
+
+
+/* ================================================================== */
+/* J2 plasticity entry points (Sec. 5 Example 1 material, state at the  */
+/* hyper integration points).  mat[8] = per phase (mu, lam, sigma_y0,    */
+/* H); history per macro point [Q][7] (eps_p xx yy zz xy yz xz, alpha): */
+/* hist_n is the committed state of the last converged increment,       */
+/* hist_t receives the state of the evaluation (the caller commits it).  */
+/* ================================================================== */
+int orc_j2_law(int64_t N, const double *F, const double *mp, const double *hn, double *P,
+               double *A, double *ht)
+{
+    for (int64_t b = 0; b < N; b++)
+        j2_law(F + 9 * b, mp, hn + 7 * b, P + 9 * b, A + 81 * b, ht + 7 * b);
+    return 0;
+}
+
+static rve_t make_rve_j2(int m, int Q, const double *G, const double *w, const int *phase,
+                         const double *mat)
+{
+    const double th0[4] = {0.0, 0.0, 0.0, 0.0};
+    rve_t c = make_rve(m, Q, G, w, phase, th0);
+    c.j2 = 1;
+    for (int i = 0; i < 8; i++) c.mat[i] = mat[i];
+    return c;
+}
+
+int orc_j2_eval(int m, int Q, const double *G, const double *w, const int *phase,
+                const double *mat, int64_t N, const double *Fr, const double *a,
+                const double *hist_n, double *r, double *Pr, double *Kaa, double *KaF,
+                double *KFF, double *hist_t, int *status)
+{
+    rve_t c = make_rve_j2(m, Q, G, w, phase, mat);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t b = 0; b < N; b++)
+        status[b] = eval_point(&c, Fr + 9 * b, a + (size_t)m * b, r + (size_t)m * b, Pr + 9 * b,
+                               Kaa + (size_t)m * m * b, KaF + (size_t)9 * m * b, KFF + 81 * b,
+                               hist_n + (size_t)7 * Q * b, hist_t + (size_t)7 * Q * b);
+    return 0;
+}
+
+/*
+ * Micro Newton at fixed Fbar with the committed history hist_n (every
+ * evaluation returns from it); hist_t gets the history of the last
+ * evaluation, i.e. of the converged state.
+ */
+int orc_j2_newton(int m, int Q, const double *G, const double *w, const int *phase,
+                  const double *mat, int objective, int64_t N, const double *Fbar, double *a,
+                  const double *hist_n, double tol, int max_it, double *Pbar, double *Cbar,
+                  double *rnorm, int *iters, int *status, double *hist_t)
+{
+    rve_t c = make_rve_j2(m, Q, G, w, phase, mat);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < N; b++) {
+        work_t W;
+        work_alloc(&W, m);
+        double *ab = a + (size_t)m * b;
+        const double *hn = hist_n + (size_t)7 * Q * b;
+        double *ht = hist_t + (size_t)7 * Q * b;
+        int st = 0, nev = 0, conv = 0;
+        for (int it = 0; it < max_it; it++) {
+            st = point_eval(&c, objective, Fbar + 9 * b, ab, &W, hn, ht);
+            nev++;
+            if (st & (ORC_PT_JNONPOS | ORC_PT_NONFINITE)) break;
+            if (W.rnorm < tol) { conv = 1; break; }
+            if (it + 1 < max_it) update_point(&c, objective, &W, NULL, ab);
+        }
+        if (!conv) st |= ORC_PT_NOCONV;
+        memcpy(Pbar + 9 * b, W.Pbar, sizeof W.Pbar);
+        memcpy(Cbar + 81 * b, W.Cbar, sizeof W.Cbar);
+        rnorm[b] = W.rnorm;
+        if (iters) iters[b] = nev;
+        status[b] = st;
+        work_free(&W);
     }
     return 0;
 }
