@@ -83,6 +83,9 @@ extern "C" {
 /* plan flags */
 #define HROM_OBJECTIVE 1u    /* RVE sees Ubar of Fbar = Rbar Ubar (Sec. 3.2.2) */
 #define HROM_SPLIT 2u        /* mixed modes: hi/lo split operands (3 MFMA terms); required */
+#define HROM_J2 8u           /* material: small-strain J2 plasticity with linear isotropic
+                                hardening and history at the ECM points (Sec. 5 Example 1,
+                                Sec. 4); FP64 plans only; theta = device [8] */
 #define HROM_REFINE 4u       /* mixed modes: the adjoint with the FP64 operator (FP64 tangent
                                 in the re-evaluation), lambda by iterative refinement whose
                                 residual uses that operator and whose correction uses the
@@ -173,6 +176,22 @@ int hrom_newton(hrom_plan plan, const double* theta, const double* Fbar, double*
  * fixed order: bitwise reproducible). */
 int hrom_backward(hrom_plan plan, const double* theta, const double* a, const double* gPbar,
                   double* gFbar, double* gtheta, int32_t* status, hipStream_t stream);
+
+/* J2 plans (HROM_J2): every evaluation starts from the committed history
+ * of the ECM points (plastic strain xx yy zz xy yz xz and equivalent plastic
+ * strain alpha, zero at plan creation) and leaves the history of its state;
+ * theta = device [8], per phase (mu, lambda, sigma_y0, H): strain
+ * eps = sym(F) - I, radial return with linear isotropic hardening
+ * sigma_y = sigma_y0 + H alpha, P = sigma and A = the consistent tangent
+ * (Sec. 5 Example 1 material; a phase with sigma_y0 beyond reach stays
+ * elastic).  hrom_commit makes the history of the last evaluation the
+ * committed one (call it after the macro increment is accepted, e.g. after a
+ * converged hrom_newton); hrom_history copies the committed (which = 0) or
+ * last-evaluated (which = 1) history into out, one [count_c][Q_c][7] block
+ * per cluster in cluster order.  HROM_E_UNSUPPORTED for plans without
+ * HROM_J2; hrom_backward returns HROM_E_UNSUPPORTED for J2 plans. */
+int hrom_commit(hrom_plan plan, hipStream_t stream);
+int hrom_history(hrom_plan plan, int32_t which, double* out, hipStream_t stream);
 
 /* Launch variants of the tangent contraction, chosen by the autotuner.
  * Single-cluster plans, variants 0..3: bit 0 asks for four wavefronts per

@@ -23,14 +23,14 @@ LIB_PATH = os.path.join(_HERE, "libhrom.so")
 HROM_OK = 0
 PT_JNONPOS, PT_NOT_SPD, PT_NOCONV, PT_NONFINITE, PT_NOREFINE = 1, 2, 4, 8, 16
 FP64, MIXED_BF16, MIXED_FP16 = 0, 1, 2
-OBJECTIVE, SPLIT, REFINE = 1, 2, 4
+OBJECTIVE, SPLIT, REFINE, J2 = 1, 2, 4, 8
 OFF_A, OFF_KAA, OFF_KAF = 0, 1, 2
 
 EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_eval",
             "hrom_condense", "hrom_update", "hrom_newton", "hrom_backward", "hrom_strerror",
             "hrom_num_variants", "hrom_plan_set_variant", "hrom_plan_profile",
             "hrom_plan_tangent_ms", "hrom_cauchy", "hrom_newton_noalloc",
-            "hrom_noalloc_scratch_bytes")
+            "hrom_noalloc_scratch_bytes", "hrom_commit", "hrom_history")
 E_SCRATCH = -6
 
 
@@ -76,6 +76,8 @@ def load(path: str = LIB_PATH):
     L.hrom_newton_noalloc.restype = C.c_int
     L.hrom_noalloc_scratch_bytes.argtypes = []
     L.hrom_noalloc_scratch_bytes.restype = C.c_size_t
+    L.hrom_commit.argtypes = [P, P]
+    L.hrom_history.argtypes = [P, i32, P, P]
     L.hrom_strerror.argtypes = [C.c_int]
     L.hrom_strerror.restype = C.c_char_p
     _lib = L
@@ -131,8 +133,9 @@ def _cluster_array(clusters):
     return arr
 
 
-def _flags(objective, split, refine):
-    return (OBJECTIVE if objective else 0) | (SPLIT if split else 0) | (REFINE if refine else 0)
+def _flags(objective, split, refine, j2=False):
+    return ((OBJECTIVE if objective else 0) | (SPLIT if split else 0) | (REFINE if refine else 0)
+            | (J2 if j2 else 0))
 
 
 def newton_noalloc(clusters, theta, Fbar, a, Pbar, Cbar, rnorm, status, precision: int = FP64,
@@ -160,15 +163,16 @@ class Plan:
     """A plan for N macro points partitioned into RVE clusters (in order)."""
 
     def __init__(self, clusters, precision: int = FP64, objective: bool = True,
-                 split: bool | None = None, refine: bool = False):
-        """split defaults to True for the mixed precisions (which require it)."""
+                 split: bool | None = None, refine: bool = False, j2: bool = False):
+        """split defaults to True for the mixed precisions (which require it);
+        j2 selects J2 plasticity with history (theta of 8 values)."""
         L = load()
         if split is None:
             split = precision != FP64
         self.clusters = list(clusters)
         self.N = sum(c.count for c in self.clusters)
         arr = _cluster_array(self.clusters)
-        flags = _flags(objective, split, refine)
+        flags = _flags(objective, split, refine, j2)
         h = C.c_void_p()
         torch.cuda.synchronize()
         _check(L.hrom_plan_create(C.byref(h), arr, len(self.clusters), self.N, precision, flags),
@@ -181,6 +185,7 @@ class Plan:
         self.precision = precision
         self.objective = objective
         self.split = split
+        self.j2 = j2
         self.a_len = int(L.hrom_plan_offset(h, len(self.clusters), OFF_A))
         self.off_a = [int(L.hrom_plan_offset(h, i, OFF_A)) for i in range(len(self.clusters))]
         self.off_kaa = [int(L.hrom_plan_offset(h, i, OFF_KAA)) for i in range(len(self.clusters))]
@@ -259,6 +264,23 @@ class Plan:
         of the last condensed state."""
         _check(load().hrom_cauchy(self._h, _ptr(sigma), _ptr(dsdD), _ptr(status), _stream(stream)),
                "hrom_cauchy")
+
+    def commit(self, stream=None):
+        """J2 plans: the history of the last evaluation becomes the committed one."""
+        _check(load().hrom_commit(self._h, _stream(stream)), "hrom_commit")
+
+    def history(self, which: int = 0, stream=None):
+        """J2 plans: committed (0) or last-evaluated (1) history as a list of
+        per-cluster [count, Q, 7] tensors."""
+        n = sum(c.count * c.Q * 7 for c in self.clusters)
+        out = torch.empty(n, dtype=torch.float64, device=self._dev())
+        _check(load().hrom_history(self._h, int(which), _ptr(out), _stream(stream)), "hrom_history")
+        res, off = [], 0
+        for c in self.clusters:
+            k = c.count * c.Q * 7
+            res.append(out[off:off + k].view(c.count, c.Q, 7))
+            off += k
+        return res
 
     def backward(self, theta, a, gPbar, gFbar, gtheta, status, stream=None):
         _check(load().hrom_backward(self._h, _ptr(theta), _ptr(a), _ptr(gPbar), _ptr(gFbar),

@@ -73,6 +73,8 @@ int plan_geometry(Plan& p, const hrom_cluster* clusters, int32_t ncl, int64_t N,
     // a single low-precision term per product misses the 1e-5 accuracy of the
     // mixed path (and makes Kaa indefinite when some modes are soft)
     if (precision != HROM_FP64 && !(flags & HROM_SPLIT)) return HROM_E_UNSUPPORTED;
+    // J2 plasticity runs on the FP64 path
+    if ((flags & HROM_J2) && precision != HROM_FP64) return HROM_E_UNSUPPORTED;
     int64_t next = 0;
     for (int c = 0; c < ncl; c++) {
         const hrom_cluster& k = clusters[c];
@@ -85,8 +87,9 @@ int plan_geometry(Plan& p, const hrom_cluster* clusters, int32_t ncl, int64_t N,
     p.N = N;
     p.prec = precision;
     p.flags = flags;
+    p.j2 = (flags & HROM_J2) != 0;
     p.cl.clear();
-    int64_t off_a = 0, off_kaa = 0, off_kaf = 0, ws_k = 0, ws_L = 0, ws_q = 0;
+    int64_t off_a = 0, off_kaa = 0, off_kaf = 0, ws_k = 0, ws_L = 0, ws_q = 0, ws_h = 0;
     for (int c = 0; c < ncl; c++) {
         const hrom_cluster& k = clusters[c];
         ClusterDev d{};
@@ -106,6 +109,8 @@ int plan_geometry(Plan& p, const hrom_cluster* clusters, int32_t ncl, int64_t N,
         d.ws_khat = ws_k;
         d.ws_L = ws_L;
         d.ws_qs = ws_q;
+        d.ws_hist = ws_h;
+        if (p.j2) ws_h += (int64_t)8 * d.Qpad * k.count;
         off_a += (int64_t)k.m * k.count;
         off_kaa += (int64_t)k.m * k.m * k.count;
         off_kaf += (int64_t)9 * k.m * k.count;
@@ -120,6 +125,7 @@ int plan_geometry(Plan& p, const hrom_cluster* clusters, int32_t ncl, int64_t N,
     p.khat_len = ws_k;
     p.L_len = ws_L;
     p.qs_len = ws_q;
+    p.hist_len = ws_h;
     return HROM_OK;
 }
 
@@ -151,6 +157,12 @@ size_t plan_carve(Plan& p, char* base) {
         take(d.kscale, 1);
     }
     take(p.basis_flag, 1);
+    if (p.j2) {
+        take(p.hist_n, p.hist_len);
+        take(p.hist_t, p.hist_len);
+    } else {
+        p.hist_n = p.hist_t = nullptr;
+    }
     take(p.at, p.a_len);
     take(p.dt, p.a_len);
     const int64_t n = p.N;
@@ -205,7 +217,7 @@ void plan_build(const Plan& p, const hrom_cluster* clusters, hipStream_t s) {
 
 // Device cluster table and the cost-sorted work queues of the tangent launches.
 int build_groups(Plan& p) {
-    p.grouped = p.ncl > 1;
+    p.grouped = p.ncl > 1 && !p.j2;   // J2 plans: the FP64 tangent per cluster
     std::vector<ClusterGPU> cg;
     std::vector<WorkItem> tan;
     p.max_m = 0;
@@ -302,6 +314,11 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
         p.arena_bytes = bytes;
         plan_carve(p, p.arena);
         if (hipMemset(p.basis_flag, 0, sizeof(int)) != hipSuccess) rc = HROM_E_HIP;
+        // J2: virgin material (no plastic strain) in both history buffers
+        if (rc == HROM_OK && p.j2 &&
+            (hipMemset(p.hist_n, 0, sizeof(double) * p.hist_len) != hipSuccess ||
+             hipMemset(p.hist_t, 0, sizeof(double) * p.hist_len) != hipSuccess))
+            rc = HROM_E_HIP;
         if (rc == HROM_OK) plan_build(p, clusters, nullptr);
         if (rc == HROM_OK && hipDeviceSynchronize() != hipSuccess) rc = HROM_E_HIP;
         int bad = 0;
@@ -407,7 +424,9 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         e.status = status;
         e.qexp = qexp_for(c.Q);
         e.kscale_out = c.kscale;
-        int rc = launch_kin(mixed(p) ? 1 : 0, e, stream);
+        e.hist_n = p.j2 ? p.hist_n + c.ws_hist : nullptr;
+        e.hist_t = p.j2 ? p.hist_t + c.ws_hist : nullptr;
+        int rc = launch_kin(mixed(p) ? 1 : 0, p.j2 ? 1 : 0, e, stream);
         if (rc != HROM_OK) return rc;
         if (p.grouped) {
             tan_args.push_back(e);
@@ -416,7 +435,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         // single-cluster plans: the events bracket the (only) tangent launch
         if (p.profile) (void)hipEventRecord(p.ev_tan[0], stream);
         rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, c.variant, e, stream)
-                      : launch_eval_f64(c.MT, c.variant, e, stream);
+                      : launch_eval_f64(c.MT, c.variant, p.j2 ? 1 : 0, e, stream);
         if (p.profile) (void)hipEventRecord(p.ev_tan[1], stream);
         if (rc != HROM_OK) return rc;
     }
@@ -565,6 +584,30 @@ int hrom_newton(hrom_plan plan, const double* theta, const double* Fbar, double*
     return rc;
 }
 
+int hrom_commit(hrom_plan plan, hipStream_t stream) {
+    if (!plan) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    if (!p.j2) return HROM_E_UNSUPPORTED;
+    if (p.stage < 1) return HROM_E_ORDER;
+    if (hipMemcpyAsync(p.hist_n, p.hist_t, sizeof(double) * p.hist_len, hipMemcpyDeviceToDevice,
+                       stream) != hipSuccess)
+        return HROM_E_HIP;
+    return HROM_OK;
+}
+
+int hrom_history(hrom_plan plan, int32_t which, double* out, hipStream_t stream) {
+    if (!plan || !out || (which != 0 && which != 1)) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    if (!p.j2) return HROM_E_UNSUPPORTED;
+    int64_t off = 0;
+    for (const auto& c : p.cl) {
+        const double* src = (which ? p.hist_t : p.hist_n) + c.ws_hist;
+        launch_history_export(src, c.Q, c.Qpad, c.count, out + off, stream);
+        off += (int64_t)7 * c.Q * c.count;
+    }
+    return hip_status();
+}
+
 int hrom_cauchy(hrom_plan plan, double* sigma, double* dsdD, int32_t* status, hipStream_t stream) {
     if (!plan || !sigma || !status) return HROM_E_INVALID;
     Plan& p = plan->p;
@@ -579,6 +622,7 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
                   double* gFbar, double* gtheta, int32_t* status, hipStream_t stream) {
     if (!plan || !theta || !a || !gPbar || !gFbar || !gtheta || !status) return HROM_E_INVALID;
     Plan& p = plan->p;
+    if (p.j2) return HROM_E_UNSUPPORTED;   // no adjoint through the plastic history
     if (p.stage < 2) return HROM_E_ORDER;
     const int objective = (p.flags & HROM_OBJECTIVE) ? 1 : 0;
     BwPointArgs bp{p.N, objective, p.polar, p.S, gPbar, p.gr, p.Lam, p.hr, gFbar};
@@ -660,7 +704,7 @@ int hrom_newton_noalloc(const hrom_cluster* clusters, int32_t ncl, int64_t N, in
                         int32_t* status, hipStream_t stream) {
     if (!clusters || !theta || !Fbar || !a || !Pbar || !Cbar || !status || max_it < 1 || ncl < 1)
         return HROM_E_INVALID;
-    if (ncl > kNoallocMaxClusters) return HROM_E_UNSUPPORTED;
+    if (ncl > kNoallocMaxClusters || (flags & HROM_J2)) return HROM_E_UNSUPPORTED;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return HROM_E_HIP;
     if (dev < 0 || dev >= kMaxDevices) return HROM_E_UNSUPPORTED;

@@ -40,6 +40,7 @@ struct ClusterDev {
     int64_t ws_khat;       // element offset of the cluster's tile workspace
     int64_t ws_L;          // element offset of the cluster's factor workspace
     int64_t ws_qs;         // element offset of the cluster's per-ECM-point scalars
+    int64_t ws_hist;       // J2: element offset of the cluster's history [count][Qpad][8]
     int variant;           // launch variant of the tangent contraction (autotuned)
     double* Ghat;          // [Qpad][9][MP]  augmented [G | I_9 | 0] (FP64)
     double* GT;            // [Qpad/64][9][m][64]  G, ECM point fastest (FP64)
@@ -107,7 +108,10 @@ struct Plan {
     double* hr = nullptr;      // [9][N]
     double* gth = nullptr;     // [4][N] per-point theta gradients
     double* gth_part = nullptr;  // [4][kThetaChunks] partial sums of gth
-    int64_t khat_len = 0, L_len = 0, qs_len = 0;
+    int64_t khat_len = 0, L_len = 0, qs_len = 0, hist_len = 0;
+    bool j2 = false;           // J2 plasticity with history (FP64 plans)
+    double* hist_n = nullptr;  // J2: committed history, per cluster [count][Qpad][8]
+    double* hist_t = nullptr;  // J2: history of the last evaluation
     int stage = 0;             // 0 = nothing, 1 = evaluated, 2 = condensed
     // grouped launches (more than one cluster)
     bool grouped = false;
@@ -148,9 +152,11 @@ struct EvalArgs {
     int* status;           // [N]
     int qexp;              // ceil(log2 Q): the ECM-weight part of the mixed-mode scaling
     float* kscale_out;     // cluster's inverse scaling of w_q A_q (written by the kinematics)
+    const double* hist_n;  // J2: committed state [count][Qpad][8] (cluster block)
+    double* hist_t;        // J2: state of this evaluation [count][Qpad][8]
 };
-int launch_kin(int mixed, const EvalArgs& a, hipStream_t s);
-int launch_eval_f64(int MT, int variant, const EvalArgs& a, hipStream_t s);
+int launch_kin(int mixed, int j2, const EvalArgs& a, hipStream_t s);
+int launch_eval_f64(int MT, int variant, int j2, const EvalArgs& a, hipStream_t s);
 int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s);
 
 struct CondenseArgs {
@@ -285,6 +291,9 @@ void launch_refine_lambda(const RefineArgs& a, hipStream_t s);
 
 constexpr int kThetaChunks = 256;   // stage-1 partials per theta component
 void launch_reduce_theta(int64_t N, const double* gth, double* part, double* out, hipStream_t s);
+// J2 history [count][Qpad][8] -> [count][Q][7]
+void launch_history_export(const double* src, int Q, int Qpad, int64_t count, double* out,
+                           hipStream_t s);
 void launch_mark_unconverged(int64_t N, const double* rnorm, double tol, int* status,
                              hipStream_t s);
 

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "hrom_internal.h"
+#include "hrom_j2.h"
 
 namespace hrom {
 
@@ -86,9 +87,11 @@ struct KinLds {
     int sbits[kKinPT];
 };
 
-// the 32 macro points p0 .. p0+31 of the cluster described by A; MA = ceil(m / 16)
-template <bool MIXED, int MA, int NW, int AR>
+// the 32 macro points p0 .. p0+31 of the cluster described by A; MA = ceil(m / 16);
+// J2: small-strain J2 plasticity with history in place of Neo-Hooke (FP64 only)
+template <bool MIXED, int MA, int NW, int AR, bool J2 = false>
 __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
+    static_assert(!(MIXED && J2), "J2 plasticity runs on the FP64 path");
     constexpr int PT = kKinPT, QC = 16, NT = 64 * NW;
     static_assert(AR >= 16 * MA, "mode amplitude rows");
     static_assert(NW == 4 || NW == 8, "four or eight wavefronts");
@@ -205,6 +208,30 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
             for (int I = 0; I < 9; I++) F[I] = sF[qq * 9 + I][p];
             const double wq = A.w[q];
             const int ph = A.phase[q];
+            if constexpr (J2) {
+                // theta = per phase (mu, lam, sy0, H); committed state in, new state out
+                const double* mp = A.theta + 4 * ph;
+                const bool live = (q < A.Q) && (p < np);
+                const int64_t ho = ((p0 + p) * A.Qpad + q) * 8;
+                double hn[7], sig[9], t[9], ht[7];
+#pragma unroll
+                for (int k = 0; k < 7; k++) hn[k] = live ? A.hist_n[ho + k] : 0.0;
+                j2_update(F, mp[0], mp[1], mp[2], mp[3], hn, sig, t, ht);
+#pragma unroll
+                for (int I = 0; I < 9; I++) sWP[qq * 9 + I][p] = live ? wq * sig[I] : 0.0;
+                if (p < np) {
+                    double* o = (double*)A.qs + ((p0 + p) * A.Qpad + q) * 12;
+#pragma unroll
+                    for (int k = 0; k < 3; k++) o[k] = live ? wq * t[k] : 0.0;
+#pragma unroll
+                    for (int k = 3; k < 12; k++) o[k] = (live && k < 9) ? t[k] : 0.0;
+                    if (live) {
+#pragma unroll
+                        for (int k = 0; k < 7; k++) A.hist_t[ho + k] = ht[k];
+                    }
+                }
+                continue;
+            }
             const double mu = ph ? mu1 : mu0, la = ph ? la1 : la0;
             double Fi[9];
             const double J = inv3d(F, Fi);
@@ -305,38 +332,43 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
     if (tid < np && sbits[tid]) A.status[A.first + p0 + tid] |= sbits[tid];
 }
 
-template <bool MIXED, int MA>
+template <bool MIXED, int MA, bool J2>
 __global__ void __launch_bounds__(256, 2) k_kin(EvalArgs A) {
     __shared__ KinLds<16 * MA> L;
-    kin_body<MIXED, MA, 4>(A, (int64_t)blockIdx.x * kKinPT, L);
+    kin_body<MIXED, MA, 4, 16 * MA, J2>(A, (int64_t)blockIdx.x * kKinPT, L);
 }
 
-template <bool MIXED>
+template <bool MIXED, bool J2>
 static void launch_kin_t(const EvalArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(a.count, kKinPT)), block(256);
     switch ((a.m + 15) / 16) {
-        case 1: hipLaunchKernelGGL((k_kin<MIXED, 1>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_kin<MIXED, 2>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_kin<MIXED, 3>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_kin<MIXED, 4>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_kin<MIXED, 5>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_kin<MIXED, 6>), grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_kin<MIXED, 1, J2>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_kin<MIXED, 2, J2>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_kin<MIXED, 3, J2>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_kin<MIXED, 4, J2>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_kin<MIXED, 5, J2>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_kin<MIXED, 6, J2>), grid, block, 0, s, a); break;
     }
 }
 
-int launch_kin(int mixed, const EvalArgs& a, hipStream_t s) {
+int launch_kin(int mixed, int j2, const EvalArgs& a, hipStream_t s) {
     if ((a.m + 15) / 16 > 6) return HROM_E_UNSUPPORTED;
-    if (mixed) launch_kin_t<true>(a, s);
-    else launch_kin_t<false>(a, s);
+    if (j2 && mixed) return HROM_E_UNSUPPORTED;
+    if (j2) launch_kin_t<false, true>(a, s);
+    else if (mixed) launch_kin_t<true, false>(a, s);
+    else launch_kin_t<false, false>(a, s);
     return HROM_OK;
 }
 
 // ============================================================== FP64 tangent
-template <int I, int MT>
+// the W row of tensor row I, then its products with the mode tiles; J2: the
+// tangent from the nine scalars s (Neo-Hooke: F^{-1} = s, c0..c2)
+template <int I, int MT, bool J2>
 __device__ __forceinline__ void row_step_f64(const double* Fi, double c0, double c1, double c2,
                                              const double (&Gc)[MT][9], v4d* acc) {
     double W[9];
-    tangent_row<I>(Fi, c0, c1, c2, W);
+    if constexpr (J2) j2_tangent_row<I>(Fi, W);
+    else tangent_row<I>(Fi, c0, c1, c2, W);
     double Bv[MT];
 #pragma unroll
     for (int t = 0; t < MT; t++) {
@@ -366,26 +398,26 @@ __device__ __forceinline__ void load_ghat(const double* gh, int MP, double (&Gc)
         for (int J = 0; J < 9; J++) Gc[t][J] = gh[J * MP + 16 * t];
 }
 
-template <int MT>
+template <int MT, bool J2 = false>
 __device__ __forceinline__ void tangent_block_f64(const double* st, int qq, const double (&Gc)[MT][9],
                                                   v4d* acc) {
     double Fi[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) Fi[k] = st[k * 64 + qq];
     const double c0 = st[9 * 64 + qq], c1 = st[10 * 64 + qq], c2 = st[11 * 64 + qq];
-    row_step_f64<0, MT>(Fi, c0, c1, c2, Gc, acc);
-    row_step_f64<1, MT>(Fi, c0, c1, c2, Gc, acc);
-    row_step_f64<2, MT>(Fi, c0, c1, c2, Gc, acc);
-    row_step_f64<3, MT>(Fi, c0, c1, c2, Gc, acc);
-    row_step_f64<4, MT>(Fi, c0, c1, c2, Gc, acc);
-    row_step_f64<5, MT>(Fi, c0, c1, c2, Gc, acc);
-    row_step_f64<6, MT>(Fi, c0, c1, c2, Gc, acc);
-    row_step_f64<7, MT>(Fi, c0, c1, c2, Gc, acc);
-    row_step_f64<8, MT>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<0, MT, J2>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<1, MT, J2>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<2, MT, J2>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<3, MT, J2>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<4, MT, J2>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<5, MT, J2>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<6, MT, J2>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<7, MT, J2>(Fi, c0, c1, c2, Gc, acc);
+    row_step_f64<8, MT, J2>(Fi, c0, c1, c2, Gc, acc);
 }
 
 // the 4 macro points pl0 .. pl0+3 of the cluster, one per wavefront
-template <int MT, bool PFREQ = true>
+template <int MT, bool PFREQ = true, bool J2 = false>
 __device__ void tan_f64_body(const EvalArgs& A, int64_t pl0, double (*s_st)[12 * 64]) {
     constexpr int NT = MT * (MT + 1) / 2;
     constexpr bool PF = PFREQ && (MT <= 5);   // register budget of the double buffer
@@ -415,16 +447,16 @@ __device__ void tan_f64_body(const EvalArgs& A, int64_t pl0, double (*s_st)[12 *
             load_ghat<MT>(A.Ghat + (int64_t)(q0 + g) * 9 * MP + c, MP, GA);
             for (int qb = 0; qb < 16; qb += 2) {
                 load_ghat<MT>(A.Ghat + (int64_t)(q0 + 4 * (qb + 1) + g) * 9 * MP + c, MP, GB);
-                tangent_block_f64<MT>(st, 4 * qb + g, GA, acc);
+                tangent_block_f64<MT, J2>(st, 4 * qb + g, GA, acc);
                 if (qb + 2 < 16)
                     load_ghat<MT>(A.Ghat + (int64_t)(q0 + 4 * (qb + 2) + g) * 9 * MP + c, MP, GA);
-                tangent_block_f64<MT>(st, 4 * (qb + 1) + g, GB, acc);
+                tangent_block_f64<MT, J2>(st, 4 * (qb + 1) + g, GB, acc);
             }
         } else {
             for (int qb = 0; qb < 16; qb++) {
                 double Gc[MT][9];
                 load_ghat<MT>(A.Ghat + (int64_t)(q0 + 4 * qb + g) * 9 * MP + c, MP, Gc);
-                tangent_block_f64<MT>(st, 4 * qb + g, Gc, acc);
+                tangent_block_f64<MT, J2>(st, 4 * qb + g, Gc, acc);
             }
         }
         __syncthreads();
@@ -435,30 +467,32 @@ __device__ void tan_f64_body(const EvalArgs& A, int64_t pl0, double (*s_st)[12 *
     for (int i = 0; i < NT; i++) *(v4d*)(kh + i * 256) = acc[i];
 }
 
-template <int MT, bool PF>
+template <int MT, bool PF, bool J2>
 __global__ void __launch_bounds__(256, 1) k_eval_f64(EvalArgs A) {
     __shared__ double s_st[4][12 * 64];
-    tan_f64_body<MT, PF>(A, (int64_t)blockIdx.x * 4, s_st);
+    tan_f64_body<MT, PF, J2>(A, (int64_t)blockIdx.x * 4, s_st);
 }
 
-template <bool PF>
+template <bool PF, bool J2>
 static int launch_f64_t(int MT, const EvalArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(a.count, 4)), block(256);
     switch (MT) {
-        case 2: hipLaunchKernelGGL((k_eval_f64<2, PF>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_eval_f64<3, PF>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_eval_f64<4, PF>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_eval_f64<5, PF>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_eval_f64<6, PF>), grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_eval_f64<7, PF>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_eval_f64<2, PF, J2>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_eval_f64<3, PF, J2>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_eval_f64<4, PF, J2>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_eval_f64<5, PF, J2>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_eval_f64<6, PF, J2>), grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_eval_f64<7, PF, J2>), grid, block, 0, s, a); break;
         default: return HROM_E_UNSUPPORTED;
     }
     return HROM_OK;
 }
 
-// variant bit 1: G double-buffering off (the FP64 kernel has one occupancy)
-int launch_eval_f64(int MT, int variant, const EvalArgs& a, hipStream_t s) {
-    return (variant & 2) ? launch_f64_t<false>(MT, a, s) : launch_f64_t<true>(MT, a, s);
+// variant bit 1: G double-buffering off (the FP64 kernel has one occupancy);
+// j2: the J2 plasticity tangent rows
+int launch_eval_f64(int MT, int variant, int j2, const EvalArgs& a, hipStream_t s) {
+    if (j2) return (variant & 2) ? launch_f64_t<false, true>(MT, a, s) : launch_f64_t<true, true>(MT, a, s);
+    return (variant & 2) ? launch_f64_t<false, false>(MT, a, s) : launch_f64_t<true, false>(MT, a, s);
 }
 
 // ============================================================== mixed tangent
@@ -847,6 +881,8 @@ __device__ inline EvalArgs group_eval_args(const GroupCall& G, int c, size_t tsz
     A.r = G.r + C.off_a; A.Pr = G.Pr; A.status = G.status;
     A.qexp = 0;
     A.kscale_out = nullptr;
+    A.hist_n = nullptr;
+    A.hist_t = nullptr;
     return A;
 }
 

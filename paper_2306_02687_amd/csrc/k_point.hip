@@ -486,6 +486,23 @@ void launch_reduce_theta(int64_t N, const double* gth, double* part, double* out
     hipLaunchKernelGGL(k_reduce_theta, dim3(4), dim3(256), 0, s, (const double*)part, out);
 }
 
+__global__ void __launch_bounds__(256) k_history_export(const double* src, int Q, int Qpad,
+                                                        int64_t count, double* out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count * Q * 7) return;
+    const int k = (int)(t % 7);
+    const int64_t pq = t / 7;
+    const int q = (int)(pq % Q);
+    const int64_t b = pq / Q;
+    out[t] = src[(b * Qpad + q) * 8 + k];
+}
+
+void launch_history_export(const double* src, int Q, int Qpad, int64_t count, double* out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_history_export, dim3(nblocks(count * Q * 7, 256)), dim3(256), 0, s, src,
+                       Q, Qpad, count, out);
+}
+
 __global__ void __launch_bounds__(256) k_mark_unconverged(int64_t N, const double* rnorm, double tol, int* status) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= N) return;
