@@ -288,10 +288,67 @@ def run_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def run_j2(args):
+    """J2 plasticity (the Example 1 material) at the sizes of the paper's
+    Example 1 hyper ROM, m = 8 modes, Q = 250 ECM points, over 262144 macro
+    points: a load-unload path of macro states; per state a fixed-count
+    device-side micro Newton (evaluate + condense + update) and a commit of
+    the history.  FP64 path."""
+    import torch
+
+    import paper_2306_02687_amd as P
+    from hrom_inputs import MAT_J2, make_cluster, make_load_path
+    from paper_2306_02687_amd import solve
+
+    N = args.N if args.N != 131072 else 262144
+    m, Q, its = 8, 250, 4
+    levels = (0.25, 0.5, 0.75, 1.0, 0.6, 0.2)
+    cl = make_cluster(m, Q, 4900)
+    path = make_load_path(N, 4901, amp=0.03, levels=levels)
+    Fk = [solve.points_to_soa(x) for x in path]
+    del path
+    plan = P.Plan([solve.upload_cluster(cl, N)], j2=True)
+    plan.profile(True)
+    th = solve.theta_dev(MAT_J2)
+    a = plan.zeros_modes()
+    st = plan.status()
+    Pb, Cb = plan.zeros_points(9), plan.zeros_points(81)
+    rn = torch.zeros(N, dtype=torch.float64, device="cuda")
+
+    def run_path():
+        for F in Fk:
+            plan.newton(th, F, a, Pb, Cb, rn, st, tol=0.0, max_it=its)
+            plan.commit()
+
+    a.zero_()
+    run_path()   # warm-up (also yields the material)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 5)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        a.zero_()
+        run_path()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    evals = N * its * len(levels)
+    line = {"metric": "RVE point-evals/s, J2 plasticity with history (Example 1 material)",
+            "value": evals / dt, "unit": "point-evals/s", "n_gpus": 1,
+            "ms_per_path": dt * 1e3, "higher_is_better": True, "dtype": "fp64",
+            "data": "synthetic",
+            "config": {"workload": f"{N} macro points, m={m} ROM modes, Q={Q} ECM points, "
+                                   f"load-unload path of {len(levels)} macro states, {its} "
+                                   f"Newton evaluations per state, commit after each"},
+            # tol 0: every point runs the fixed count (NOCONV, bit 4, set by design)
+            "status_max": int((st & ~4).max().item())}
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="mixed", choices=["mixed", "batched"],
-                    help="mixed: the headline (m=64, Q=512) step; batched: uneven clusters")
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "batched", "j2"],
+                    help="mixed: the headline (m=64, Q=512) step; batched: uneven clusters; "
+                         "j2: J2 plasticity path at the Example 1 sizes")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -330,6 +387,9 @@ def main():
         sys.exit(1)
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "j2":
+        run_j2(args)
         return
     N, m, Q = args.N, args.m, args.Q
     print(f"[bench] building inputs N={N} m={m} Q={Q}", file=sys.stderr, flush=True)

@@ -214,3 +214,44 @@ def test_adjoint_workload(P, orc, precision):
     assert int(st.status.max().item()) == 0
     assert egF < BAR_GRAD[precision] and egt < BAR_GRAD[precision]
     plan.close()
+
+
+def test_j2_example1_sizes_load_path(P, orc):
+    """J2 plasticity at the sizes of the paper's Example 1 hyper ROM (8 modes,
+    250 ECM points) over 262144 macro points: a load-unload path of four
+    macro states, device-side Newton and a commit at each; 128 sampled points
+    against the oracle's path (Pbar, Cbar and committed history, 1e-12; the
+    stress error of a point is taken relative to its largest stress along the
+    path, since unloading leaves small stresses whose own relative error is
+    rounding amplified by cancellation)."""
+    from hrom_inputs import MAT_J2, make_load_path
+    from paper_2306_02687_amd import solve
+    log_case("fullsize_j2")
+    N, m, Q = 262144, 8, 250
+    cl = make_cluster(m, Q, 4900)
+    levels = (0.5, 1.0, 0.6, 0.2)
+    path = make_load_path(N, 4901, amp=0.03, levels=levels)
+    idx = sample(N, 4902, 128)
+    plan = P.Plan([solve.upload_cluster(cl, N)], j2=True)
+    th = solve.theta_dev(MAT_J2)
+    a = plan.zeros_modes()
+    st = plan.status()
+    Pb, Cb = plan.zeros_points(9), plan.zeros_points(81)
+    rn = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ref = orc.j2_path(cl, MAT_J2, path[:, idx], tol=1e-10)
+    for k in range(len(levels)):
+        plan.newton(th, solve.points_to_soa(path[k]), a, Pb, Cb, rn, st, tol=1e-10, max_it=8)
+        plan.commit()
+        torch.cuda.synchronize()
+        assert int(st.max().item()) == 0
+        Pg = Pb.cpu().numpy().T[idx]
+        Cg = Cb.cpu().numpy().T[idx]
+        hg = plan.history(0)[0][torch.from_numpy(idx).cuda()].cpu().numpy()
+        peak = np.max([np.linalg.norm(r["Pbar"], axis=1) for r in ref], axis=0)
+        eP = np.linalg.norm(Pg - ref[k]["Pbar"], axis=1) / peak
+        eC = rel_err_points(Cg, ref[k]["Cbar"].reshape(len(idx), -1))
+        eh = np.abs(hg - ref[k]["hist"]).max() / np.abs(ref[k]["hist"]).max()
+        print(f"j2 full size state {k}: Pbar {eP.max():.2e} Cbar {eC.max():.2e} hist {eh:.2e} "
+              f"alpha max {ref[k]['hist'][:, :, 6].max():.3e}", flush=True)
+        assert eP.max() < 1e-12 and eC.max() < 1e-12 and eh < 1e-12
+    plan.close()
