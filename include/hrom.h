@@ -113,8 +113,12 @@ typedef struct {
 typedef struct hrom_plan_s* hrom_plan;
 
 /* Create a plan for N macro points partitioned into ncl clusters (contiguous,
- * in order, covering [0, N)).  Reads G, w, phase once (synchronously) to build
- * the device layouts the kernels use; allocates the per-point workspace.
+ * in order, covering [0, N)): the RVE clusters of Sec. 3.4 with their hyper
+ * integration points and weights of Sec. 3.3.  Reads G, w, phase once
+ * (synchronously) to build the device layouts the kernels use, in the mode
+ * basis orthonormal in the weighted gradient inner product (the caller's
+ * arrays stay in the caller's basis); allocates the per-point workspace.
+ * HROM_E_INVALID for linearly dependent mode gradients.
  * Ownership: the plan owns its workspace; the caller keeps G, w, phase. */
 int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, int64_t N,
                      int32_t precision, uint32_t flags);
@@ -124,15 +128,21 @@ int hrom_plan_destroy(hrom_plan plan);
  * total length of such an array (c = ncl) */
 int64_t hrom_plan_offset(hrom_plan plan, int32_t c, int32_t kind);
 
-/* Evaluate at (Fbar, a): theta = device [4] (mu_0, lam_0, mu_1, lam_1).
- * Fbar [9][N], a (mode-indexed).  Writes status[N] (overwrites).  Optional
- * test outputs (NULL = not written), all in the RVE frame: r (mode-indexed),
- * Pr [9][N], Kaa [m*m][count] blocks, KaF [m*9][count] blocks, KFF [81][N]. */
+/* Evaluate at (Fbar, a) (Sec. 3.2.1 eqs. ROM_assumption, ROMintforce,
+ * ROMstiffness with the ECM sums of Sec. 3.3; the polar split of Sec. 3.2.2
+ * eq. ploar_decomp in objective plans): theta = device [4] (mu_0, lam_0,
+ * mu_1, lam_1), or [8] for J2 plans.  Fbar [9][N], a (mode-indexed).  Writes
+ * status[N] (overwrites).  Optional test outputs (NULL = not written), all in
+ * the RVE frame: r (mode-indexed), Pr [9][N], Kaa [m*m][count] blocks, KaF
+ * [m*9][count] blocks, KFF [81][N]. */
 int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const double* a,
               double* r, double* Pr, double* Kaa, double* KaF, double* KFF,
               int32_t* status, hipStream_t stream);
 
-/* Condense the state left by the last hrom_eval: Pbar [9][N] (algorithmic
+/* Condense the state left by the last hrom_eval (Sec. 3.2.3, eq.
+ * Biot_Tangent: Palg = Pr - KaF^T Kaa^{-1} r, Cr = KFF - KaF^T Kaa^{-1} KaF,
+ * factorised, never inverted, Sec. 4), then push out to the macro frame
+ * (Sec. 3.2.2 eqs. workconjugacy, biotstress): Pbar [9][N] (algorithmic
  * stress, macro frame), Cbar [81][N], rnorm [N] = ||r||_2.  ORs status bits. */
 int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm,
                   int32_t* status, hipStream_t stream);
@@ -150,7 +160,7 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm,
 int hrom_cauchy(hrom_plan plan, double* sigma, double* dsdD, int32_t* status, hipStream_t stream);
 
 /* Monolithic update a <- a - (y + X dFr) with the y, X of the last condense
- * (Sec. 3.2.3).  dFbar [9][N] macro-frame increment (linearised to the stretch
+ * (Sec. 3.2.3, the amplitude increment of the monolithic scheme).  dFbar [9][N] macro-frame increment (linearised to the stretch
  * increment in objective mode), or NULL for a pure micro Newton step; with
  * dFbar == NULL, points whose last rnorm < tol are left unchanged (frozen).
  * Points whose status (of the last eval/condense) has JNONPOS or NONFINITE
@@ -158,7 +168,9 @@ int hrom_cauchy(hrom_plan plan, double* sigma, double* dsdD, int32_t* status, hi
 int hrom_update(hrom_plan plan, const double* dFbar, double tol, double* a,
                 const int32_t* status, hipStream_t stream);
 
-/* Micro Newton at fixed Fbar, max_it evaluations with no host sync (so it can
+/* Micro Newton at fixed Fbar (the staggered micro solve that the monolithic
+ * scheme of Sec. 3.2.3 replaces by one update per macro iteration; used to
+ * converge the RVE state), max_it evaluations with no host sync (so it can
  * be captured in a HIP graph): max_it - 1 times {eval, condense, update with
  * converged points frozen}, then a final eval + condense.  Points still at
  * rnorm >= tol get HROM_PT_NOCONV.  Pbar, Cbar, rnorm as in hrom_condense. */
@@ -166,8 +178,10 @@ int hrom_newton(hrom_plan plan, const double* theta, const double* Fbar, double*
                 int32_t max_it, double* Pbar, double* Cbar, double* rnorm, int32_t* status,
                 hipStream_t stream);
 
-/* Adjoint backward of the converged map (Fbar, theta) -> Pbar at the state of
- * the last eval + condense (which must have been at this a and theta, i.e.
+/* Adjoint backward of the converged map (Fbar, theta) -> Pbar (the
+ * derivative of the condensed problem of Sec. 3.2.3: the adjoint system is the
+ * transpose of eq. Biot_Tangent's Kaa solve) at the state of the last eval +
+ * condense (which must have been at this a and theta, i.e.
  * no update in between).  gPbar [9][N] = dL/dPbar.  Pull-back to the RVE
  * frame g_r, adjoint solve lambda = Kaa^{-T} KaF g_r with the stored solve
  * (mixed modes: plus one refinement step with the accurate operator),

@@ -22,7 +22,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hrom_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# HROM_ORACLE_LIB: load another build of the same source (e.g. the sanitizer
+# build of check_sanitizers.sh) instead of the default one
+_LIB = os.environ.get("HROM_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
 
 PT_JNONPOS, PT_NOT_SPD, PT_NOCONV, PT_NONFINITE = 1, 2, 4, 8
 

@@ -18,7 +18,9 @@ from dataclasses import dataclass
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhrom.so")
+# HROM_LIB: load another build of the library (e.g. the host-sanitizer build
+# of oracle/check_sanitizers.sh) instead of the in-tree one
+LIB_PATH = os.environ.get("HROM_LIB", os.path.join(_HERE, "libhrom.so"))
 
 HROM_OK = 0
 PT_JNONPOS, PT_NOT_SPD, PT_NOCONV, PT_NONFINITE, PT_NOREFINE = 1, 2, 4, 8, 16
