@@ -208,17 +208,17 @@ def host_cpu():
     return info
 
 
-def run_batched(args):
+def run_batched(args, N=262144, precision="bf16"):
     """Eight uneven RVE clusters (m in {8..96}, Q = 6 m, Zipf(1.1) split of the
     macro points), one HIP graph of 10 monolithic iterations (evaluate,
-    condense, update with dFbar_k), mixed and FP64."""
+    condense, update with dFbar_k), mixed and FP64.  Returns the result line."""
     import torch
 
     import paper_2306_02687_amd as P
     from hrom_inputs import THETA_REF, make_cluster, make_increments, make_macro_points, zipf_counts
     from paper_2306_02687_amd import solve, tune
 
-    N, K = args.N if args.N != 131072 else 262144, 10
+    K = 10
     ms = [8, 16, 24, 32, 48, 64, 80, 96]
     counts = zipf_counts(N, len(ms), 1.1)
     cls = [make_cluster(m, 6 * m, 3000 + i) for i, m in enumerate(ms)]
@@ -232,7 +232,7 @@ def run_batched(args):
     del Fk
     th = solve.theta_dev(THETA_REF)
     res = {}
-    for name, prec, split in (("mixed", PREC[args.precision], True), ("fp64", 0, False)):
+    for name, prec, split in (("mixed", PREC[precision], True), ("fp64", 0, False)):
         print(f"[bench] batched {name}", file=sys.stderr, flush=True)
         plan = P.Plan([solve.upload_cluster(c, n) for c, n in zip(cls, counts)],
                       precision=prec, split=split)
@@ -257,7 +257,7 @@ def run_batched(args):
             with torch.cuda.graph(g, stream=s):
                 iterations()
         torch.cuda.synchronize()
-        reps = max(1, args.steps // 5)
+        reps = max(1, min(args.steps // 5, 2))
         a.zero_()
         g.replay()
         torch.cuda.synchronize()
@@ -277,7 +277,7 @@ def run_batched(args):
     line = {"metric": "RVE point-evals/s, batched uneven clusters, graph of 10 monolithic iterations",
             "value": res["mixed"]["value"], "unit": "point-evals/s", "n_gpus": 1,
             "ms_per_graph": res["mixed"]["ms_per_graph"], "higher_is_better": True,
-            "dtype": f"{args.precision} MFMAx3 split + fp32 tangent + fp64", "data": "synthetic",
+            "dtype": f"{precision} MFMAx3 split + fp32 tangent + fp64", "data": "synthetic",
             "config": {"workload": f"{N} macro points over 8 clusters m={ms}, Q=6m, Zipf(1.1) "
                                    f"counts {counts}, 10 monolithic iterations in one HIP graph"},
             "fp64": {"value": res["fp64"]["value"], "ms_per_graph": res["fp64"]["ms_per_graph"]},
@@ -285,10 +285,127 @@ def run_batched(args):
             "mixed_vs_fp64_Cbar_rel_err_max": float(eC.max()),
             "variants": {"mixed": res["mixed"]["variant"], "fp64": res["fp64"]["variant"]},
             "status_max": max(res["mixed"]["status"], res["fp64"]["status"])}
-    print(json.dumps(line), flush=True)
+    return line
 
 
-def run_j2(args):
+def run_adjoint(N=65536, m=48, Q=384, precision="bf16", refine=True, newton_its=4):
+    """Forward + backward at the adjoint workload's shape: a device-side micro
+    Newton of newton_its evaluations (evaluate + condense + update) from a = 0,
+    then the adjoint backward of L = sum ||Pbar - Pbar*||^2; ms of each part."""
+    import torch
+
+    import paper_2306_02687_amd as P
+    from hrom_inputs import THETA_REF, make_cluster, make_macro_points
+    from paper_2306_02687_amd import solve
+
+    cl = make_cluster(m, Q, 5000)
+    F, _, _ = make_macro_points(N, 5001, amp=0.05)
+    Fd = solve.points_to_soa(F)
+    plan = P.Plan([solve.upload_cluster(cl, N)], precision=PREC[precision],
+                  refine=refine and precision != "fp64")
+    th = solve.theta_dev(THETA_REF)
+    a = plan.zeros_modes()
+    st = plan.status()
+    Pb, Cb = plan.zeros_points(9), plan.zeros_points(81)
+    rn = torch.zeros(N, dtype=torch.float64, device="cuda")
+    target = torch.zeros_like(Pb)
+    gF = plan.zeros_points(9)
+    gth = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    times = []
+    for rep in range(3):
+        a.zero_()
+        ev[0].record()
+        plan.newton(th, Fd, a, Pb, Cb, rn, st, tol=0.0, max_it=newton_its)
+        ev[1].record()
+        g = 2.0 * (Pb - target)
+        plan.backward(th, a, g, gF, gth, st)
+        ev[2].record()
+        torch.cuda.synchronize()
+        times.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
+    fwd, bwd = times[-1]
+    out = {"workload": f"{N} macro points, m={m}, Q={Q}, {precision}"
+                       f"{' split, adjoint refinement' if precision != 'fp64' and refine else ''}: "
+                       f"{newton_its} Newton evaluations + one adjoint backward",
+           "forward_ms": fwd, "backward_ms": bwd,
+           "point_evals_per_s": N * newton_its / (fwd * 1e-3),
+           "status_max": int((st & ~4).max().item())}
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_monolithic(N=65536, m=32, Q=256, precision="fp64", iters=5):
+    """Five monolithic iterations (evaluate + condense + update with dFbar_k)
+    at the FP64-at-scale workload's shape; ms per iteration."""
+    import torch
+
+    import paper_2306_02687_amd as P
+    from hrom_inputs import THETA_REF, make_cluster, make_increments, make_macro_points
+    from paper_2306_02687_amd import solve
+
+    cl = make_cluster(m, Q, 2000)
+    F, R, _ = make_macro_points(N, 2001, amp=0.05)
+    dF = make_increments(R, iters, 2002, amp=0.005)
+    Fd = solve.points_to_soa(F)
+    dFd = [solve.points_to_soa(x) for x in dF]
+    plan = P.Plan([solve.upload_cluster(cl, N)], precision=PREC[precision])
+    th = solve.theta_dev(THETA_REF)
+    a = plan.zeros_modes()
+    st = plan.status()
+    Pb, Cb = plan.zeros_points(9), plan.zeros_points(81)
+    rn = torch.zeros(N, dtype=torch.float64, device="cuda")
+
+    def run():
+        Fk = Fd.clone()
+        for k in range(iters):
+            plan.eval(th, Fk, a, st)
+            plan.condense(Pb, Cb, rn, st)
+            plan.update(dFd[k], a, st)
+            Fk += dFd[k]
+
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.zero_()
+    e0.record()
+    run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    out = {"workload": f"{N} macro points, m={m}, Q={Q}, {precision}, {iters} monolithic iterations",
+           "ms_per_iteration": ms / iters, "point_evals_per_s": N * iters / (ms * 1e-3),
+           "status_max": int(st.max().item())}
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def oracle_errors(m=64, Q=512, n=12, amps=(0.01, 0.05, 0.2), precision="bf16"):
+    """Newton-converged Pbar, Cbar of the mixed path against the FP64 oracle
+    on n points of the headline shape at each strain amplitude."""
+    import oracle
+    from hrom_inputs import THETA_REF, make_cluster, make_macro_points
+    import paper_2306_02687_amd as P
+    from paper_2306_02687_amd import solve
+
+    cl = make_cluster(m, Q, 4000)
+    out = {}
+    for amp in amps:
+        F, _, _ = make_macro_points(n, 4001 + int(amp * 1000), amp=amp)
+        ref = oracle.newton(cl, THETA_REF, F, tol=1e-10)
+        plan = P.Plan([solve.upload_cluster(cl, n)], precision=PREC[precision])
+        st = solve.newton(plan, solve.theta_dev(THETA_REF), solve.points_to_soa(F), tol=1e-10)
+        Pg, Cg = solve.soa_to_points(st.Pbar), solve.soa_to_points(st.Cbar)
+        plan.close()
+        eP = np.linalg.norm(Pg - ref["Pbar"], axis=1) / np.linalg.norm(ref["Pbar"], axis=1)
+        eC = (np.linalg.norm(Cg - ref["Cbar"].reshape(n, 81), axis=1)
+              / np.linalg.norm(ref["Cbar"].reshape(n, 81), axis=1))
+        out[str(amp)] = {"Pbar_max": float(eP.max()), "Cbar_max": float(eC.max())}
+    return out
+
+
+def run_j2(args, quiet=False):
     """J2 plasticity (the Example 1 material) at the sizes of the paper's
     Example 1 hyper ROM, m = 8 modes, Q = 250 ECM points, over 262144 macro
     points: a load-unload path of macro states; per state a fixed-count
@@ -300,7 +417,7 @@ def run_j2(args):
     from hrom_inputs import MAT_J2, make_cluster, make_load_path
     from paper_2306_02687_amd import solve
 
-    N = args.N if args.N != 131072 else 262144
+    N = args.N if (args.N != 131072 and args.workload == "j2") else 262144
     m, Q, its = 8, 250, 4
     levels = (0.25, 0.5, 0.75, 1.0, 0.6, 0.2)
     cl = make_cluster(m, Q, 4900)
@@ -340,8 +457,12 @@ def run_j2(args):
                                    f"Newton evaluations per state, commit after each"},
             # tol 0: every point runs the fixed count (NOCONV, bit 4, set by design)
             "status_max": int((st & ~4).max().item())}
-    print(json.dumps(line), flush=True)
     plan.close()
+    torch.cuda.empty_cache()
+    if quiet:
+        return {k: line[k] for k in ("value", "ms_per_path", "status_max")} | {
+            "workload": line["config"]["workload"]}
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -361,6 +482,8 @@ def main():
     ap.add_argument("--amp", type=float, default=0.05)
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (no FP16 / batched / adjoint / monolithic / J2 legs)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -386,7 +509,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     if args.workload == "batched":
-        run_batched(args)
+        print(json.dumps(run_batched(args, N=args.N if args.N != 131072 else 262144,
+                                     precision=args.precision)), flush=True)
         return
     if args.workload == "j2":
         run_j2(args)
@@ -434,6 +558,34 @@ def main():
                "sample": f"{n} of the {N} macro points, one evaluate + condense + adjoint "
                          f"backward each (plain C, FP64, OpenMP over points)"}
 
+    extras = None
+    if not args.no_extras and args.precision != "fp64":
+        extras = {}
+        other = "fp16" if args.precision == "bf16" else "bf16"
+        print(f"[bench] extra: {other} at the headline shape", file=sys.stderr, flush=True)
+        r2 = run_gpu(other, cl, F, N, args.steps, args.warmup, split=True)
+        ms2 = r2["wall"] / args.steps * 1e3
+        extras[other] = {"ms_per_step": ms2, "value": N / (ms2 * 1e-3),
+                         "tangent_ms": r2["tan_ms"],
+                         "frac": tangent_flops_per_point(m, Q) * N / (r2["tan_ms"] * 1e-3) / PEAK[other],
+                         "status_max": r2["status"]}
+        del r2
+        print("[bench] extra: oracle errors at three amplitudes", file=sys.stderr, flush=True)
+        extras["oracle_errors_" + args.precision] = oracle_errors(precision=args.precision)
+        print("[bench] extra: batched clusters", file=sys.stderr, flush=True)
+        b = run_batched(args, precision=args.precision)
+        extras["batched"] = {k: b[k] for k in ("value", "ms_per_graph", "fp64",
+                                               "speedup_mixed_over_fp64",
+                                               "mixed_vs_fp64_Cbar_rel_err_max", "status_max")}
+        extras["batched"]["workload"] = b["config"]["workload"]
+        print("[bench] extra: adjoint workload", file=sys.stderr, flush=True)
+        extras["adjoint_48_384"] = {"mixed": run_adjoint(precision=args.precision),
+                                    "fp64": run_adjoint(precision="fp64")}
+        print("[bench] extra: FP64 monolithic iterations at (32, 256)", file=sys.stderr, flush=True)
+        extras["monolithic_32_256"] = run_monolithic()
+        print("[bench] extra: J2 plasticity path", file=sys.stderr, flush=True)
+        extras["j2_8_250"] = run_j2(args, quiet=True)
+
     line = {
         "metric": METRIC, "value": value, "unit": "point-evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -462,6 +614,7 @@ def main():
         "tuned_variant": res["variant"], "variant_eval_ms": res["tune_ms"],
         "fp64": fp64,
         "cpu_baseline": cpu,
+        "other_workloads": extras,
     }
     print(json.dumps(line), flush=True)
 
