@@ -752,9 +752,10 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
                 v4f T[MA];
 #pragma unroll
                 for (int t = 0; t < MA; t++) T[t] = Pk<PREC>::mfma(Wq[pp], Gc[t], v4f{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-                for (int t = 0; t < MA; t++) accF[pp][t] = Pk<PREC>::mfma(Gc[t], Wq[pp], accF[pp][t]);
                 accFF[pp] = Pk<PREC>::mfma(Wq[pp], Ip, accFF[pp]);
+                // KFa = sum_q T_q (W_q is symmetric): the T tiles summed in FP32
+#pragma unroll
+                for (int t = 0; t < MA; t++) accF[pp][t] += T[t];
 #pragma unroll
                 for (int tj = 0; tj < MA; tj++) {
                     const v4u32 B = t_operand<PREC, SPLIT>(T[tj], in_g1);
@@ -807,8 +808,9 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
         for (int t = 0; t < MA; t++)
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const int k = 16 * t + 4 * g + e;
-                if (Kc >= 0 && k < m) put(mp + Kc, k, accF[pp][t][e]);
+                // sum of T tiles: component row 4 g + e, mode column 16 t + c
+                const int KI = pos_comp(4 * g + e), k = 16 * t + c;
+                if (KI >= 0 && k < m) put(mp + KI, k, accF[pp][t][e]);
             }
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -857,14 +859,12 @@ static int launch_mixed_v(int variant, const EvalArgs& a, hipStream_t s) {
 
 // variants 0..3: bit 0 three wavefronts per SIMD instead of two, bit 1 no
 // prefetch; 4, 5: two macro points per wavefront (without, with prefetch)
+// (mixed plans require split operands: plan creation rejects single-term ones)
 int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s) {
     (void)MT;
-    if (prec == HROM_MIXED_BF16)
-        return split ? launch_mixed_v<HROM_MIXED_BF16, true>(variant, a, s)
-                     : launch_mixed_v<HROM_MIXED_BF16, false>(variant, a, s);
-    if (prec == HROM_MIXED_FP16)
-        return split ? launch_mixed_v<HROM_MIXED_FP16, true>(variant, a, s)
-                     : launch_mixed_v<HROM_MIXED_FP16, false>(variant, a, s);
+    if (!split) return HROM_E_UNSUPPORTED;
+    if (prec == HROM_MIXED_BF16) return launch_mixed_v<HROM_MIXED_BF16, true>(variant, a, s);
+    if (prec == HROM_MIXED_FP16) return launch_mixed_v<HROM_MIXED_FP16, true>(variant, a, s);
     return HROM_E_INVALID;
 }
 
