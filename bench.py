@@ -88,7 +88,7 @@ def build_inputs(N, m, Q, amp, seed):
     return cl, F
 
 
-def run_gpu(prec_name, cl, F, N, steps, warmup, split=True, refine=False):
+def run_gpu(prec_name, cl, F, N, steps, warmup, split=True, refine=False, biot6=False):
     import torch
 
     import paper_2306_02687_amd as P
@@ -98,7 +98,7 @@ def run_gpu(prec_name, cl, F, N, steps, warmup, split=True, refine=False):
     from paper_2306_02687_amd import tune
 
     plan = P.Plan([solve.upload_cluster(cl, N)], precision=PREC[prec_name], split=split,
-                  refine=refine and prec_name != "fp64")
+                  refine=refine and prec_name != "fp64", biot6=biot6)
     th = solve.theta_dev(THETA_REF)
     Fd = solve.points_to_soa(F)
     st = solve.State(plan)
@@ -474,6 +474,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp64"])
+    ap.add_argument("--condense", default="biot6", choices=["biot6", "nine"],
+                    help="biot6: condense the six coordinates of the symmetric stretch (the "
+                         "Biot form, same Pbar and Cbar); nine: all nine components of Fr")
     ap.add_argument("--refine", action="store_true",
                     help="mixed plans: iterative refinement of the adjoint solve")
     ap.add_argument("--N", type=int, default=131072)
@@ -521,8 +524,9 @@ def main():
 
     split = args.precision != "fp64"
     print(f"[bench] timing {args.precision} (split={split})", file=sys.stderr, flush=True)
+    biot6 = args.condense == "biot6"
     res = run_gpu(args.precision, cl, F, N, args.steps, args.warmup, split=split,
-                  refine=args.refine)
+                  refine=args.refine, biot6=biot6)
     ms_step = res["wall"] / args.steps * 1e3
     value = N / (ms_step * 1e-3)
     fl_tan = tangent_flops_per_point(m, Q) * N
@@ -534,7 +538,7 @@ def main():
     fp64 = None
     if args.precision != "fp64" and not args.skip_fp64:
         print("[bench] timing fp64 reference path", file=sys.stderr, flush=True)
-        ref = run_gpu("fp64", cl, F, N, max(2, args.steps // 2), 1)
+        ref = run_gpu("fp64", cl, F, N, max(2, args.steps // 2), 1, biot6=biot6)
         ms64 = ref["wall"] / max(2, args.steps // 2) * 1e3
         P1, P0 = res["Pbar"].cpu().numpy(), ref["Pbar"].cpu().numpy()
         C1, C0 = res["Cbar"].cpu().numpy(), ref["Cbar"].cpu().numpy()
@@ -563,7 +567,7 @@ def main():
         extras = {}
         other = "fp16" if args.precision == "bf16" else "bf16"
         print(f"[bench] extra: {other} at the headline shape", file=sys.stderr, flush=True)
-        r2 = run_gpu(other, cl, F, N, args.steps, args.warmup, split=True)
+        r2 = run_gpu(other, cl, F, N, args.steps, args.warmup, split=True, biot6=biot6)
         ms2 = r2["wall"] / args.steps * 1e3
         extras[other] = {"ms_per_step": ms2, "value": N / (ms2 * 1e-3),
                          "tangent_ms": r2["tan_ms"],
@@ -596,7 +600,9 @@ def main():
         "config": {"workload": f"hyper-reduced RVE, {N} macro points, m={m} ROM modes, "
                                f"Q={Q} ECM points, one cluster, strain amplitude {args.amp}",
                    "N": N, "m": m, "Q": Q, "precision": args.precision, "split": split,
-                   "step": "eval + condense + adjoint backward + update"},
+                   "step": "eval + condense + adjoint backward + update",
+                   "condense": "six coordinates of the symmetric stretch (Biot form)" if biot6
+                   else "nine components"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "kernel": "tangent contraction (k_eval_mixed / k_eval_f64)",

@@ -86,6 +86,10 @@ extern "C" {
 #define HROM_J2 8u           /* material: small-strain J2 plasticity with linear isotropic
                                 hardening and history at the ECM points (Sec. 5 Example 1,
                                 Sec. 4); FP64 plans only; theta = device [8] */
+#define HROM_BIOT6 16u       /* objective plans: condense only the six coordinates of the
+                                symmetric stretch (KaU = KaF E6, six right-hand sides; the
+                                paper's Biot form, Sec. 3.2.2-3.2.3): the same Pbar, Cbar,
+                                update and adjoint, one trailing block less to eliminate */
 #define HROM_REFINE 4u       /* mixed modes: the adjoint with the FP64 operator (FP64 tangent
                                 in the re-evaluation), lambda by iterative refinement whose
                                 residual uses that operator and whose correction uses the
@@ -158,6 +162,16 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm,
  * ORs HROM_PT_NONFINITE into status for non-finite outputs.  Allocates
  * nothing; does not change the plan's state. */
 int hrom_cauchy(hrom_plan plan, double* sigma, double* dsdD, int32_t* status, hipStream_t stream);
+
+/* Biot form of the state left by the last hrom_condense (objective plans,
+ * else HROM_E_UNSUPPORTED; HROM_E_ORDER before a condense): the Biot stress
+ * T [6][N] = sym(Palg_r) in Voigt order (11, 22, 33, 12, 23, 13), work
+ * conjugate to the stretch Ubar (Sec. 3.2.2 eq. workconjugacy), and unless
+ * CB is NULL the condensed Biot tangent CB [36][N], entry 6 k + l =
+ * dT_k / dgamma_l with gamma = (U11, U22, U33, 2 U12, 2 U23, 2 U13) (Sec.
+ * 3.2.3 eq. Biot_Tangent on symmetric stretch increments), the interface of
+ * codes that impose the stretch.  ORs HROM_PT_NONFINITE into status. */
+int hrom_biot(hrom_plan plan, double* T, double* CB, int32_t* status, hipStream_t stream);
 
 /* Monolithic update a <- a - (y + X dFr) with the y, X of the last condense
  * (Sec. 3.2.3, the amplitude increment of the monolithic scheme).  dFbar [9][N] macro-frame increment (linearised to the stretch

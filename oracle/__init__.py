@@ -62,6 +62,7 @@ def lib():
         L.orc_stretch_increment.argtypes = [i64, P, P, P]
         L.orc_cauchy.argtypes = [i64, P, P, P, P, P, P]
         L.orc_j2_law.argtypes = [i64, P, P, P, P, P, P]
+        L.orc_biot.argtypes = [i64, P, P, P, P]
         L.orc_j2_eval.argtypes = [i32, i32, P, P, P, P, i64, P, P, P, P, P, P, P, P, P, P]
         L.orc_j2_newton.argtypes = [i32, i32, P, P, P, P, i32, i64, P, P, P, d, i32, P, P, P,
                                     P, P, P]
@@ -287,3 +288,14 @@ def j2_path(cl, mat, Fbar_path, tol=1e-10, max_it=25, objective=True):
         a, hist = o["a"], o["hist"]
         out.append(o)
     return out
+
+
+def biot(Palg_r, Cr):
+    """Biot stress T[N, 6] (Voigt 11 22 33 12 23 13) and tangent CB[N, 6, 6] =
+    dT/dgamma (engineering shear) from the RVE-frame Palg_r[N, 9], Cr[N, 9, 9]."""
+    Palg_r = _f64(Palg_r)
+    N = Palg_r.size // 9
+    Cr = _f64(Cr, (N, 81))
+    T, CB = np.zeros((N, 6)), np.zeros((N, 6, 6))
+    lib().orc_biot(N, _p(Palg_r.reshape(N, 9)), _p(Cr), _p(T), _p(CB))
+    return T, CB

@@ -1050,3 +1050,47 @@ int orc_j2_newton(int m, int Q, const double *G, const double *w, const int *pha
     }
     return 0;
 }
+
+/* ================================================================== */
+/* Biot form of the condensed RVE-frame state (Sec. 3.2.2 eq.           */
+/* workconjugacy: the Biot stress, the symmetric part of the RVE-frame  */
+/* stress, is work conjugate to the stretch; Sec. 3.2.3 eq.             */
+/* Biot_Tangent on symmetric stretch increments).  Voigt order          */
+/* (11, 22, 33, 12, 23, 13) with engineering shear strains              */
+/* gamma = (U11, U22, U33, 2 U12, 2 U23, 2 U13): a stretch increment is */
+/* dU = sum_l dgamma_l D_l with D = (E11, E22, E33, (E12 + E21) / 2,     */
+/* (E23 + E32) / 2, (E13 + E31) / 2), the stress T_k = D_k : Palg and   */
+/* the tangent CB_kl = dT_k / dgamma_l = D_k : Cr : D_l.                */
+/* ================================================================== */
+static void voigt_dual(int k, double *D)
+{
+    static const int ii[6] = {0, 1, 2, 0, 1, 0}, jj[6] = {0, 1, 2, 1, 2, 2};
+    memset(D, 0, sizeof(double) * 9);
+    if (k < 3) {
+        D[3 * ii[k] + jj[k]] = 1.0;
+    } else {
+        D[3 * ii[k] + jj[k]] = 0.5;
+        D[3 * jj[k] + ii[k]] = 0.5;
+    }
+}
+
+int orc_biot(int64_t N, const double *Palg_r, const double *Cr, double *T, double *CB)
+{
+    double D[6][9];
+    for (int k = 0; k < 6; k++) voigt_dual(k, D[k]);
+    for (int64_t b = 0; b < N; b++) {
+        const double *P = Palg_r + 9 * b, *C = Cr + 81 * b;
+        for (int k = 0; k < 6; k++) {
+            double s = 0.0;
+            for (int I = 0; I < 9; I++) s += D[k][I] * P[I];
+            T[6 * b + k] = s;
+            for (int l = 0; l < 6; l++) {
+                double t = 0.0;
+                for (int I = 0; I < 9; I++)
+                    for (int J = 0; J < 9; J++) t += D[k][I] * C[9 * I + J] * D[l][J];
+                CB[36 * b + 6 * k + l] = t;
+            }
+        }
+    }
+    return 0;
+}

@@ -25,14 +25,14 @@ LIB_PATH = os.environ.get("HROM_LIB", os.path.join(_HERE, "libhrom.so"))
 HROM_OK = 0
 PT_JNONPOS, PT_NOT_SPD, PT_NOCONV, PT_NONFINITE, PT_NOREFINE = 1, 2, 4, 8, 16
 FP64, MIXED_BF16, MIXED_FP16 = 0, 1, 2
-OBJECTIVE, SPLIT, REFINE, J2 = 1, 2, 4, 8
+OBJECTIVE, SPLIT, REFINE, J2, BIOT6 = 1, 2, 4, 8, 16
 OFF_A, OFF_KAA, OFF_KAF = 0, 1, 2
 
 EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_eval",
             "hrom_condense", "hrom_update", "hrom_newton", "hrom_backward", "hrom_strerror",
             "hrom_num_variants", "hrom_plan_set_variant", "hrom_plan_profile",
             "hrom_plan_tangent_ms", "hrom_cauchy", "hrom_newton_noalloc",
-            "hrom_noalloc_scratch_bytes", "hrom_commit", "hrom_history")
+            "hrom_noalloc_scratch_bytes", "hrom_commit", "hrom_history", "hrom_biot")
 E_SCRATCH = -6
 
 
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
     L.hrom_noalloc_scratch_bytes.argtypes = []
     L.hrom_noalloc_scratch_bytes.restype = C.c_size_t
     L.hrom_commit.argtypes = [P, P]
+    L.hrom_biot.argtypes = [P, P, P, P, P]
     L.hrom_history.argtypes = [P, i32, P, P]
     L.hrom_strerror.argtypes = [C.c_int]
     L.hrom_strerror.restype = C.c_char_p
@@ -135,9 +136,9 @@ def _cluster_array(clusters):
     return arr
 
 
-def _flags(objective, split, refine, j2=False):
+def _flags(objective, split, refine, j2=False, biot6=False):
     return ((OBJECTIVE if objective else 0) | (SPLIT if split else 0) | (REFINE if refine else 0)
-            | (J2 if j2 else 0))
+            | (J2 if j2 else 0) | (BIOT6 if biot6 else 0))
 
 
 def newton_noalloc(clusters, theta, Fbar, a, Pbar, Cbar, rnorm, status, precision: int = FP64,
@@ -165,16 +166,18 @@ class Plan:
     """A plan for N macro points partitioned into RVE clusters (in order)."""
 
     def __init__(self, clusters, precision: int = FP64, objective: bool = True,
-                 split: bool | None = None, refine: bool = False, j2: bool = False):
+                 split: bool | None = None, refine: bool = False, j2: bool = False,
+                 biot6: bool = False):
         """split defaults to True for the mixed precisions (which require it);
-        j2 selects J2 plasticity with history (theta of 8 values)."""
+        j2 selects J2 plasticity with history (theta of 8 values); biot6 the
+        six-component condensation of the symmetric stretch."""
         L = load()
         if split is None:
             split = precision != FP64
         self.clusters = list(clusters)
         self.N = sum(c.count for c in self.clusters)
         arr = _cluster_array(self.clusters)
-        flags = _flags(objective, split, refine, j2)
+        flags = _flags(objective, split, refine, j2, biot6)
         h = C.c_void_p()
         torch.cuda.synchronize()
         _check(L.hrom_plan_create(C.byref(h), arr, len(self.clusters), self.N, precision, flags),
@@ -266,6 +269,11 @@ class Plan:
         of the last condensed state."""
         _check(load().hrom_cauchy(self._h, _ptr(sigma), _ptr(dsdD), _ptr(status), _stream(stream)),
                "hrom_cauchy")
+
+    def biot(self, T, CB, status, stream=None):
+        """Biot stress T [6][N] and tangent CB [36][N] (or None), Voigt order."""
+        _check(load().hrom_biot(self._h, _ptr(T), _ptr(CB), _ptr(status), _stream(stream)),
+               "hrom_biot")
 
     def commit(self, stream=None):
         """J2 plans: the history of the last evaluation becomes the committed one."""

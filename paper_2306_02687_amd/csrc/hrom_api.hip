@@ -75,6 +75,8 @@ int plan_geometry(Plan& p, const hrom_cluster* clusters, int32_t ncl, int64_t N,
     if (precision != HROM_FP64 && !(flags & HROM_SPLIT)) return HROM_E_UNSUPPORTED;
     // J2 plasticity runs on the FP64 path
     if ((flags & HROM_J2) && precision != HROM_FP64) return HROM_E_UNSUPPORTED;
+    // the six-component condensation condenses the symmetric stretch of the objective split
+    if ((flags & HROM_BIOT6) && !(flags & HROM_OBJECTIVE)) return HROM_E_UNSUPPORTED;
     int64_t next = 0;
     for (int c = 0; c < ncl; c++) {
         const hrom_cluster& k = clusters[c];
@@ -88,6 +90,7 @@ int plan_geometry(Plan& p, const hrom_cluster* clusters, int32_t ncl, int64_t N,
     p.prec = precision;
     p.flags = flags;
     p.j2 = (flags & HROM_J2) != 0;
+    p.nmac = (flags & HROM_BIOT6) ? 6 : 9;
     p.cl.clear();
     int64_t off_a = 0, off_kaa = 0, off_kaf = 0, ws_k = 0, ws_L = 0, ws_q = 0, ws_h = 0;
     for (int c = 0; c < ncl; c++) {
@@ -180,7 +183,7 @@ size_t plan_carve(Plan& p, char* base) {
     take(p.L, refine(p) ? p.L_len : 1);
     take(p.piv, p.a_len);
     take(p.y, p.a_len);
-    take(p.X, 9 * p.a_len);
+    take(p.X, (int64_t)p.nmac * p.a_len);
     take(p.Palg, 9 * n);
     take(p.Cr, 81 * n);
     take(p.S, 9 * n);
@@ -464,6 +467,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         for (const auto& c : p.cl) {
             CondenseArgs ca{};
             ca.m = c.m; ca.MT = c.MT; ca.res_t = c.res_t; ca.res_c = c.res_c; ca.mixed = mixed(p);
+        ca.nmac = p.nmac;
             ca.first = c.first; ca.count = c.count; ca.N = p.N;
             ca.Khat = (const char*)p.Khat + tsz * (size_t)c.ws_khat;
             ca.r = p.r + c.off_a; ca.Pr = p.Pr;
@@ -497,12 +501,13 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
     for (const auto& c : p.cl) {
         CondenseArgs ca{};
         ca.m = c.m; ca.MT = c.MT; ca.res_t = c.res_t; ca.res_c = c.res_c; ca.mixed = mixed(p);
+        ca.nmac = p.nmac;
         ca.first = c.first; ca.count = c.count; ca.N = p.N;
         ca.Khat = (const char*)p.Khat + tsz * (size_t)c.ws_khat;
         ca.r = p.r + c.off_a; ca.Pr = p.Pr;
         ca.L = refine(p) ? p.L + c.ws_L : nullptr;
         ca.piv = p.piv + c.off_a;
-        ca.y = p.y + c.off_a; ca.X = p.X + 9 * c.off_a;
+        ca.y = p.y + c.off_a; ca.X = p.X + (int64_t)p.nmac * c.off_a;
         ca.Palg = p.Palg; ca.Cr = p.Cr; ca.rnorm = p.rnorm; ca.status = status;
         ca.kscale = c.kscale;
         // SPD path: register-resident elimination, one launch per cluster so
@@ -542,7 +547,8 @@ static int update_impl(Plan& p, const double* dFbar, double tol, double* a, cons
         u.first = c.first;
         u.count = c.count;
         u.y = p.y + c.off_a;
-        u.X = p.X + 9 * c.off_a;
+        u.X = p.X + (int64_t)p.nmac * c.off_a;
+        u.nmac = p.nmac;
         u.dt = p.dt + c.off_a;
         launch_update(u, stream);
         ModeMapArgs ma{c.m, c.first, c.count, c.Rinv, p.dt + c.off_a, a + c.off_a, nullptr};
@@ -582,6 +588,16 @@ int hrom_newton(hrom_plan plan, const double* theta, const double* Fbar, double*
         rc = hip_status();
     }
     return rc;
+}
+
+int hrom_biot(hrom_plan plan, double* T, double* CB, int32_t* status, hipStream_t stream) {
+    if (!plan || !T || !status) return HROM_E_INVALID;
+    Plan& p = plan->p;
+    if (p.stage < 2) return HROM_E_ORDER;
+    if (!(p.flags & HROM_OBJECTIVE)) return HROM_E_UNSUPPORTED;
+    BiotArgs ba{p.N, p.Palg, p.Cr, T, CB, status};
+    launch_biot(ba, stream);
+    return hip_status();
 }
 
 int hrom_commit(hrom_plan plan, hipStream_t stream) {
@@ -629,8 +645,8 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
     launch_bw_pullback(bp, stream);
     map_in(p, a, stream);
     for (const auto& c : p.cl) {
-        LambdaArgs la{c.m, c.first, c.count, p.N, p.X + 9 * c.off_a, p.gr, p.lam + c.off_a,
-                      p.conv + c.first};
+        LambdaArgs la{c.m, c.first, c.count, p.N, p.nmac, p.X + (int64_t)p.nmac * c.off_a, p.gr,
+                      p.lam + c.off_a, p.conv + c.first};
         launch_lambda(la, stream);
         BackwardArgs ba{};
         ba.m = c.m; ba.Q = c.Q; ba.Qpad = c.Qpad; ba.mixed = mixed(p); ba.objective = objective;

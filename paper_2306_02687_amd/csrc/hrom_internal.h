@@ -110,6 +110,7 @@ struct Plan {
     double* gth_part = nullptr;  // [4][kThetaChunks] partial sums of gth
     int64_t khat_len = 0, L_len = 0, qs_len = 0, hist_len = 0;
     bool j2 = false;           // J2 plasticity with history (FP64 plans)
+    int nmac = 9;              // macro components condensed (6 with HROM_BIOT6)
     double* hist_n = nullptr;  // J2: committed history, per cluster [count][Qpad][8]
     double* hist_t = nullptr;  // J2: history of the last evaluation
     int stage = 0;             // 0 = nothing, 1 = evaluated, 2 = condensed
@@ -162,6 +163,7 @@ int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs&
 struct CondenseArgs {
     int m, MT, res_t, res_c;
     int mixed;
+    int nmac;              // macro components condensed: 9, or 6 (symmetric stretch)
     int64_t first, count, N;
     const void* Khat;
     const double* r;       // cluster block
@@ -169,7 +171,7 @@ struct CondenseArgs {
     double* L;             // cluster block [count][m][m]
     int* piv;              // cluster block [count][m]
     double* y;             // cluster block [m][count]
-    double* X;             // cluster block [9m][count]
+    double* X;             // cluster block [nmac m][count]
     double* Palg;          // [9][N]
     double* Cr;            // [81][N]
     double* rnorm;         // [N]
@@ -207,6 +209,16 @@ struct CauchyArgs {
 };
 void launch_cauchy(const CauchyArgs& a, hipStream_t s);
 
+struct BiotArgs {
+    int64_t N;
+    const double* Palg;   // [9][N] RVE frame
+    const double* Cr;     // [81][N] RVE frame
+    double* T;            // [6][N] Biot stress (Voigt order 11 22 33 12 23 13)
+    double* CB;           // [36][N] Biot tangent dT/dgamma (engineering shear), or null
+    int* status;
+};
+void launch_biot(const BiotArgs& a, hipStream_t s);
+
 struct UpdateArgs {
     int m;
     int64_t first, count, N;
@@ -215,7 +227,8 @@ struct UpdateArgs {
     const double* polar;
     double* dU;            // [9][N]
     const double* y;       // cluster block
-    const double* X;       // cluster block
+    const double* X;       // cluster block [nmac m][count]
+    int nmac;              // 9, or 6 (X holds the columns of the basis E6)
     const double* rnorm;
     const int* status;
     double tol;
@@ -264,7 +277,8 @@ void launch_bw_pushforward(const BwPointArgs& a, hipStream_t s);
 struct LambdaArgs {
     int m;
     int64_t first, count, N;
-    const double* X;       // cluster block [9m][count]
+    int nmac;              // 9, or 6 (X holds the columns of the basis E6)
+    const double* X;       // cluster block [nmac m][count]
     const double* gr;      // [9][N]
     double* lam;           // cluster block [m][count]
     int* conv;             // cluster block [count] or null: cleared (refinement restarts)

@@ -305,8 +305,16 @@ __global__ void __launch_bounds__(64) k_unpack_condense(CondenseArgs A, int mode
     for (int i = lane; i < m; i += 64) {
         rr += S.rv[i] * S.rv[i];
         A.y[(int64_t)i * A.count + pl] = S.B[i * 10];
+        if (A.nmac == 6) {
+            // the columns of the basis E6 (E11, E22, E33, E12 + E21, E23 + E32, E13 + E31)
+            const double* Bi = S.B + i * 10 + 1;
+            const double x6[6] = {Bi[0], Bi[4], Bi[8], Bi[1] + Bi[3], Bi[5] + Bi[7], Bi[2] + Bi[6]};
 #pragma unroll
-        for (int J = 0; J < 9; J++) A.X[((int64_t)i * 9 + J) * A.count + pl] = S.B[i * 10 + 1 + J];
+            for (int J = 0; J < 6; J++) A.X[((int64_t)i * 6 + J) * A.count + pl] = x6[J];
+        } else {
+#pragma unroll
+            for (int J = 0; J < 9; J++) A.X[((int64_t)i * 9 + J) * A.count + pl] = S.B[i * 10 + 1 + J];
+        }
         if (A.L) {
             double* Lrow = A.L + (pl * m + i) * (int64_t)m;
             for (int k = 0; k < m; k++) Lrow[k] = S.K[i * S.ld + k];
@@ -790,9 +798,251 @@ static void launch_reg_t(const CondenseArgs& a, hipStream_t s) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Six-component (Biot) condensation of objective plans: the RVE is driven by
+// the symmetric stretch Ubar (Sec. 3.2.2), so the macro degrees of freedom
+// are the six coordinates of Ubar in the basis E6 = {E11, E22, E33, E12 + E21,
+// E23 + E32, E13 + E31}: KaU = KaF E6 (m x 6), KUU = E6^T KFF E6, PU = E6^T Pr,
+// and six right-hand sides.  The augmented matrix [[Kaa, KaU, r], [., KUU, PU],
+// [., ., 0]] then has one trailing 8 x 8 block (six components, the residual
+// row at mp + 6, one zero row) instead of two.  Outputs: X6 = Kaa^{-1} KaU
+// [6m][count], y, and the symmetric projections of the condensed stress and
+// tangent, Palg = sum_k D_k (E6_k : Palg) and Cr = sum_kl D_k (E6_k : Cr :
+// E6_l) D_l^T with the dual basis D_k (E11, .., (E12 + E21) / 2, ..), which is
+// all that the objective push-out reads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int e6_count(int k) { return k < 3 ? 1 : 2; }
+// the row-major 3x3 components of E6_k
+__device__ __forceinline__ int e6_comp(int k, int n) {
+    switch (k) {
+        case 0: return 0;
+        case 1: return 4;
+        case 2: return 8;
+        case 3: return n ? 3 : 1;
+        case 4: return n ? 7 : 5;
+        default: return n ? 6 : 2;
+    }
+}
+
+template <typename TT, int MB>
+__device__ void condense6_reg_body(const CondenseArgs& A, int64_t pl) {
+    constexpr int NB = MB * (MB + 1) / 2;
+    constexpr int JB = MB - 1;               // pivot blocks
+    const int m = A.m, mp = 8 * JB, MT = A.MT;
+    const int lane = threadIdx.x, lr = lane >> 3, lc = lane & 7;
+    const int64_t b = A.first + pl;
+    const TT* kh = (const TT*)A.Khat + (int64_t)pl * khat_len(m, MT, sizeof(TT) == 4);
+    const double ks = (double)*A.kscale;
+    __shared__ double cb[8 * MB];
+    __shared__ double zb[8];
+
+    double M[NB];
+    double rr = 0.0;
+    // ---- mode blocks (t, u < JB): the same K-hat entries as the nine-component layout
+    {
+        TT raw[JB * (JB + 1) / 2];
+#pragma unroll
+        for (int t = 0; t < JB; t++)
+#pragma unroll
+            for (int u = 0; u <= t; u++) {
+                if constexpr (sizeof(TT) == 4) {
+                    raw[lblk(t, u)] = kh[lblk(t, u) * 64 + lane];
+                } else {
+                    const int i = 8 * t + lr, k = 8 * u + lc;
+                    const bool kin = i < m && k < m;
+                    raw[lblk(t, u)] = khat_at<TT>(kh, m, MT, kin ? i : 0, kin ? k : 0);
+                }
+            }
+#pragma unroll
+        for (int t = 0; t < JB; t++)
+#pragma unroll
+            for (int u = 0; u <= t; u++) {
+                const int i = 8 * t + lr, k = 8 * u + lc;
+                double v;
+                if (i < m && k < m) v = (double)raw[lblk(t, u)] * ks;
+                else v = (i == k) ? 1.0 : 0.0;       // identity padding of the modes
+                M[lblk(t, u)] = v;
+            }
+    }
+    // ---- trailing block row JB: KaU, KUU, PU and the residual row
+    {
+        const int ci = lr;   // 0..5 component, 6 residual, 7 zero
+#pragma unroll
+        for (int u = 0; u <= JB; u++) {
+            const int k = 8 * u + lc;
+            double v = 0.0;
+            if (u < JB) {
+                if (k < m) {
+                    if (ci < 6) {
+                        for (int n = 0; n < e6_count(ci); n++)
+                            v += (double)khat_at<TT>(kh, m, MT, m + e6_comp(ci, n), k);
+                        v *= ks;
+                    } else if (ci == 6) {
+                        v = A.r[(int64_t)k * A.count + pl];
+                        rr = fma(v, v, rr);
+                    }
+                }
+            } else {
+                const int cj = lc;
+                if (ci < 6 && cj < 6) {
+                    for (int n = 0; n < e6_count(ci); n++)
+                        for (int n2 = 0; n2 < e6_count(cj); n2++)
+                            v += (double)khat_at<TT>(kh, m, MT, m + e6_comp(ci, n), m + e6_comp(cj, n2));
+                    v *= ks;
+                } else if ((ci < 6 && cj == 6) || (ci == 6 && cj < 6)) {
+                    const int cc = ci < 6 ? ci : cj;
+                    for (int n = 0; n < e6_count(cc); n++) v += A.Pr[(int64_t)e6_comp(cc, n) * A.N + b];
+                }
+            }
+            M[lblk(JB, u)] = v;
+        }
+    }
+
+    // ---- LDL^T elimination of the mp mode pivots (right-looking)
+    bool spd = true;
+#pragma unroll
+    for (int J = 0; J < JB; J++) {
+#pragma unroll 1
+        for (int jj = 0; jj < 8; jj++) {
+            const int j = 8 * J + jj;
+            if (lc == jj) {
+#pragma unroll
+                for (int t = J; t < MB; t++) cb[8 * t + lr] = M[lblk(t, J)];
+            }
+            wave_sync();
+            const double d = cb[j];
+            spd = spd && (d > 0.0);
+            const double rd = recip_pos(d);
+            double ck[MB];
+#pragma unroll
+            for (int u = J; u < MB; u++) {
+                const double v = cb[8 * u + lc];
+                ck[u] = (u > J || lc > jj) ? v : 0.0;
+            }
+#pragma unroll
+            for (int t = J; t < MB; t++) {
+                const double v = cb[8 * t + lr] * rd;
+                const double ci = (t > J || lr > jj) ? v : 0.0;
+#pragma unroll
+                for (int u = J; u <= t; u++) M[lblk(t, u)] = fma(-ci, ck[u], M[lblk(t, u)]);
+            }
+            wave_sync();
+        }
+    }
+    spd = __ballot(!spd) == 0;
+    if (!spd) {
+        if (lane == 0) A.status[b] |= HROM_PT_NOT_SPD;
+        return;
+    }
+    if (A.L) {
+        if (lr == lc) {
+#pragma unroll
+            for (int u = 0; u < JB; u++) cb[8 * u + lc] = M[lblk(u, u)];
+        }
+        wave_sync();
+        double* Lp = A.L + pl * (int64_t)m * m;
+#pragma unroll
+        for (int t = 0; t < JB; t++)
+#pragma unroll
+            for (int u = 0; u <= t; u++) {
+                const int i = 8 * t + lr, k = 8 * u + lc;
+                if (i < m && k <= i) {
+                    const double sk = sqrt(cb[k]);
+                    Lp[(int64_t)i * m + k] = (i == k) ? sk : M[lblk(t, u)] / sk;
+                }
+            }
+        wave_sync();
+    }
+    if (lane == 0) A.piv[pl * m] = -1;
+
+    // ---- backward substitution (D L^T) [X6 | y] = L^-1 [KaU | r]: right-hand
+    // side c = lr of block JB
+#pragma unroll
+    for (int J = JB - 1; J >= 0; J--) {
+#pragma unroll 1
+        for (int jj = 7; jj >= 0; jj--) {
+            const int j = 8 * J + jj;
+            if (lr == jj) {
+#pragma unroll
+                for (int u = 0; u <= J; u++) cb[8 * u + lc] = M[lblk(J, u)];
+            }
+            if (lc == jj) zb[lr] = M[lblk(JB, J)];
+            wave_sync();
+            const double x0 = zb[lr] * recip_pos(cb[j]);
+            if (lc == jj) M[lblk(JB, J)] = x0;
+#pragma unroll
+            for (int u = 0; u <= J; u++) {
+                const double l = (u < J || lc < jj) ? cb[8 * u + lc] : 0.0;
+                M[lblk(JB, u)] = fma(-l, x0, M[lblk(JB, u)]);
+            }
+            wave_sync();
+        }
+    }
+
+    // ---- outputs: X6, y; the symmetric projections of P_alg and C_r
+#pragma unroll
+    for (int u = 0; u < JB; u++) {
+        const int i = 8 * u + lc;
+        if (i < m) {
+            if (lr < 6) A.X[((int64_t)i * 6 + lr) * A.count + pl] = M[lblk(JB, u)];
+            else if (lr == 6) A.y[(int64_t)i * A.count + pl] = M[lblk(JB, u)];
+        }
+    }
+    bool fin = true;
+    {
+        const double v = M[lblk(JB, JB)];   // entry (lr, lc) of the trailing block
+        const double dr = lr < 3 ? 1.0 : 0.5, dc = lc < 3 ? 1.0 : 0.5;
+        if (lr < 6 && lc < 6) {
+            fin = isfinite(v);
+            for (int n = 0; n < e6_count(lr); n++)
+                for (int n2 = 0; n2 < e6_count(lc); n2++)
+                    A.Cr[(int64_t)(9 * e6_comp(lr, n) + e6_comp(lc, n2)) * A.N + b] = v * dr * dc;
+        } else if (lr == 6 && lc < 6) {
+            fin = isfinite(v);
+            for (int n = 0; n < e6_count(lc); n++) A.Palg[(int64_t)e6_comp(lc, n) * A.N + b] = v * dc;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rr += __shfl_xor(rr, off);
+    const uint64_t bad = __ballot(!fin);
+    if (lane == 0) {
+        A.rnorm[b] = sqrt(rr);
+        if (bad) A.status[b] |= HROM_PT_NONFINITE;
+    }
+}
+
+template <typename TT, int MB>
+__global__ void __launch_bounds__(64, MB <= 10 ? 3 : 2) k_condense6_reg(CondenseArgs A) {
+    condense6_reg_body<TT, MB>(A, xcd_order(blockIdx.x, A.count));
+}
+
+template <typename TT>
+static void launch_reg6_t(const CondenseArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)a.count), block(64);
+    switch ((a.m + 7) / 8) {
+        case 1: hipLaunchKernelGGL((k_condense6_reg<TT, 2>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_condense6_reg<TT, 3>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_condense6_reg<TT, 4>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_condense6_reg<TT, 5>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_condense6_reg<TT, 6>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_condense6_reg<TT, 7>), grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_condense6_reg<TT, 8>), grid, block, 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_condense6_reg<TT, 9>), grid, block, 0, s, a); break;
+        case 9: hipLaunchKernelGGL((k_condense6_reg<TT, 10>), grid, block, 0, s, a); break;
+        case 10: hipLaunchKernelGGL((k_condense6_reg<TT, 11>), grid, block, 0, s, a); break;
+        case 11: hipLaunchKernelGGL((k_condense6_reg<TT, 12>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_condense6_reg<TT, 13>), grid, block, 0, s, a); break;
+    }
+}
+
 int launch_condense_reg(const CondenseArgs& a, hipStream_t s) {
     if (a.m < 1 || a.m > 96) return HROM_E_UNSUPPORTED;
     if (a.count == 0) return HROM_OK;
+    if (a.nmac == 6) {
+        if (a.mixed) launch_reg6_t<float>(a, s);
+        else launch_reg6_t<double>(a, s);
+        return HROM_OK;
+    }
     if (a.mixed) launch_reg_t<float>(a, s);
     else launch_reg_t<double>(a, s);
     return HROM_OK;

@@ -269,6 +269,51 @@ __global__ void __launch_bounds__(256) k_cauchy(CauchyArgs A) {
     if (!fin) atomicOr(&A.status[b], HROM_PT_NONFINITE);
 }
 
+// Biot stress and tangent in Voigt form from the RVE-frame condensed state
+// (Sec. 3.2.2 eq. workconjugacy: the Biot stress T = sym(Palg_r) is work
+// conjugate to Ubar; Sec. 3.2.3 eq. Biot_Tangent): T_k = D_k : Palg and
+// CB_kl = D_k : Cr : D_l with the dual basis D = (E11, E22, E33,
+// (E12 + E21) / 2, (E23 + E32) / 2, (E13 + E31) / 2), i.e. dT_k / dgamma_l
+// with engineering shear strains gamma = (U11, U22, U33, 2 U12, 2 U23, 2 U13).
+// One thread per (row k of CB, point); row 0 also writes T.
+__global__ void __launch_bounds__(256) k_biot(BiotArgs A) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = A.N;
+    if (t >= 6 * N) return;
+    const int64_t b = t / 6;
+    const int k = (int)(t - 6 * b);
+    constexpr int c0[6] = {0, 4, 8, 1, 5, 2}, c1[6] = {0, 4, 8, 3, 7, 6};
+    constexpr double dw[6] = {1.0, 1.0, 1.0, 0.5, 0.5, 0.5};
+    bool fin = true;
+    if (k == 0) {
+#pragma unroll
+        for (int l = 0; l < 6; l++) {
+            const double v = (l < 3) ? A.Palg[(int64_t)c0[l] * N + b]
+                                     : 0.5 * (A.Palg[(int64_t)c0[l] * N + b] + A.Palg[(int64_t)c1[l] * N + b]);
+            A.T[(int64_t)l * N + b] = v;
+            fin = fin && isfinite(v);
+        }
+    }
+    if (A.CB) {
+#pragma unroll
+        for (int l = 0; l < 6; l++) {
+            double v = 0.0;
+            // D_k : Cr : D_l, D_k = sum of its components with weight dw
+            for (int n = 0; n < (k < 3 ? 1 : 2); n++)
+                for (int n2 = 0; n2 < (l < 3 ? 1 : 2); n2++)
+                    v += A.Cr[(int64_t)(9 * (n ? c1[k] : c0[k]) + (n2 ? c1[l] : c0[l])) * N + b];
+            v *= dw[k] * dw[l];
+            A.CB[(int64_t)(6 * k + l) * N + b] = v;
+            fin = fin && isfinite(v);
+        }
+    }
+    if (!fin) atomicOr(&A.status[b], HROM_PT_NONFINITE);
+}
+
+void launch_biot(const BiotArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_biot, dim3(nblocks(6 * a.N, 256)), dim3(256), 0, s, a);
+}
+
 void launch_cauchy(const CauchyArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_cauchy, dim3(nblocks(9 * a.N, 256)), dim3(256), 0, s, a);
 }
@@ -325,6 +370,10 @@ __global__ void __launch_bounds__(256) k_update(UpdateArgs A) {
     double dU[9];
 #pragma unroll
     for (int J = 0; J < 9; J++) dU[J] = frozen ? 0.0 : A.dU[J * A.N + b];
+    // six-component plans: the coordinates of the (symmetric) increment in the
+    // dual basis of E6, (dU11, dU22, dU33, dU12, dU23, dU13)
+    const double d6[6] = {dU[0], dU[4], dU[8], 0.5 * (dU[1] + dU[3]), 0.5 * (dU[5] + dU[7]),
+                          0.5 * (dU[2] + dU[6])};
 #pragma unroll
     for (int kk = 0; kk < kModesPerThread; kk++) {
         const int k = kg * kModesPerThread + kk;
@@ -332,8 +381,13 @@ __global__ void __launch_bounds__(256) k_update(UpdateArgs A) {
             double s = 0.0;
             if (!frozen) {
                 s = A.y[(int64_t)k * A.count + pl];
+                if (A.nmac == 6) {
 #pragma unroll
-                for (int J = 0; J < 9; J++) s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], dU[J], s);
+                    for (int J = 0; J < 6; J++) s = fma(A.X[((int64_t)k * 6 + J) * A.count + pl], d6[J], s);
+                } else {
+#pragma unroll
+                    for (int J = 0; J < 9; J++) s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], dU[J], s);
+                }
             }
             A.dt[(int64_t)k * A.count + pl] = s;
         }
@@ -430,13 +484,20 @@ __global__ void __launch_bounds__(256) k_lambda(LambdaArgs A) {
     double gr[9];
 #pragma unroll
     for (int J = 0; J < 9; J++) gr[J] = A.gr[J * A.N + b];
+    const double g6[6] = {gr[0], gr[4], gr[8], 0.5 * (gr[1] + gr[3]), 0.5 * (gr[5] + gr[7]),
+                          0.5 * (gr[2] + gr[6])};
 #pragma unroll
     for (int kk = 0; kk < kModesPerThread; kk++) {
         const int k = kg * kModesPerThread + kk;
         if (k < A.m) {
             double s = 0.0;
+            if (A.nmac == 6) {
 #pragma unroll
-            for (int J = 0; J < 9; J++) s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], gr[J], s);
+                for (int J = 0; J < 6; J++) s = fma(A.X[((int64_t)k * 6 + J) * A.count + pl], g6[J], s);
+            } else {
+#pragma unroll
+                for (int J = 0; J < 9; J++) s = fma(A.X[((int64_t)k * 9 + J) * A.count + pl], gr[J], s);
+            }
             A.lam[(int64_t)k * A.count + pl] = s;
         }
     }

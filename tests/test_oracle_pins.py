@@ -523,3 +523,61 @@ def test_cauchy_rotation_covariance(orc):
         assert np.abs(s2[b].reshape(3, 3) - q @ s1[b].reshape(3, 3) @ q.T).max() < 1e-12
         rot = np.einsum("ia,jb,kc,ld,abcd->ijkl", q, q, q, q, c1[b].reshape(3, 3, 3, 3))
         assert np.abs(c2[b].reshape(3, 3, 3, 3) - rot).max() < 1e-11 * max(1.0, np.abs(rot).max())
+
+
+# ---------------------------------------------------------------- Biot form
+def _stretch_from_gamma(g):
+    """Symmetric stretch from Voigt coordinates with engineering shear."""
+    U = np.diag(g[:3]).astype(float)
+    for k, (i, j) in zip(range(3, 6), ((0, 1), (1, 2), (0, 2))):
+        U[i, j] = U[j, i] = 0.5 * g[k]
+    return U
+
+
+def test_biot_form_conjugacy_fd_and_symmetry(orc, small):
+    """T (Voigt) and CB from the condensed RVE-frame state: T . dgamma equals
+    sym(Palg) : dU for a symmetric stretch increment; CB equals central
+    differences of the Newton-converged T in the engineering strains (direct
+    frame, Fbar = U symmetric); CB is symmetric."""
+    cl, _, _, H = small
+    n = 3
+    g0 = np.stack([np.r_[1 + H[b][0, 0], 1 + H[b][1, 1], 1 + H[b][2, 2],
+                         2 * H[b][0, 1], 2 * H[b][1, 2], 2 * H[b][0, 2]] for b in range(n)])
+    U0 = np.array([_stretch_from_gamma(g) for g in g0])
+    o = orc.newton(cl, THETA_REF, U0, objective=False, tol=1e-14)
+    T, CB = orc.biot(o["Pbar"], o["Cbar"])
+    # conjugacy
+    dg = RNG.standard_normal((n, 6))
+    for b in range(n):
+        dU = _stretch_from_gamma(dg[b])
+        Ts = 0.5 * (o["Pbar"][b].reshape(3, 3) + o["Pbar"][b].reshape(3, 3).T)
+        assert abs(T[b] @ dg[b] - np.sum(Ts * dU)) < 1e-14 * max(1.0, np.abs(T[b]).max())
+    # finite differences of T in gamma
+    h = 1e-6
+    for l in range(6):
+        e = np.zeros(6)
+        e[l] = h
+        Up = np.array([_stretch_from_gamma(g + e) for g in g0])
+        Um = np.array([_stretch_from_gamma(g - e) for g in g0])
+        Tp, _ = orc.biot(orc.newton(cl, THETA_REF, Up, objective=False, tol=1e-14)["Pbar"],
+                         np.zeros((n, 81)))
+        Tm, _ = orc.biot(orc.newton(cl, THETA_REF, Um, objective=False, tol=1e-14)["Pbar"],
+                         np.zeros((n, 81)))
+        assert rel((Tp - Tm) / (2 * h), CB[:, :, l]) < 1e-8, l
+    assert np.abs(CB - np.transpose(CB, (0, 2, 1))).max() < 1e-12 * np.abs(CB).max()
+
+
+def test_biot_form_single_phase_is_voigt_neo_hooke(orc, small):
+    """One phase: CB is the Voigt matrix D_k : A_NH(U) : D_l of the pointwise
+    Neo-Hooke tangent; at U = I it is the isotropic Lame matrix."""
+    cl, _, _, H = small
+    one = copy.copy(cl)
+    one.phase = np.zeros_like(cl.phase)
+    mu, lam = THETA_REF[:2]
+    o = orc.newton(one, THETA_REF, np.eye(3)[None], objective=False)
+    _, CB = orc.biot(o["Pbar"], o["Cbar"])
+    C0 = lam * np.ones((3, 3)) + 2 * mu * np.eye(3)
+    ref = np.zeros((6, 6))
+    ref[:3, :3] = C0
+    ref[3:, 3:] = mu * np.eye(3)
+    assert np.abs(CB[0] - ref).max() < 1e-13
