@@ -63,6 +63,7 @@ def lib():
         L.orc_cauchy.argtypes = [i64, P, P, P, P, P, P]
         L.orc_j2_law.argtypes = [i64, P, P, P, P, P, P]
         L.orc_biot.argtypes = [i64, P, P, P, P]
+        L.orc_ecm_integrand.argtypes = [i32, i32, P, P, P, i32, P, P, P]
         L.orc_j2_eval.argtypes = [i32, i32, P, P, P, P, i64, P, P, P, P, P, P, P, P, P, P]
         L.orc_j2_newton.argtypes = [i32, i32, P, P, P, P, i32, i64, P, P, P, d, i32, P, P, P,
                                     P, P, P]
@@ -299,3 +300,149 @@ def biot(Palg_r, Cr):
     T, CB = np.zeros((N, 6)), np.zeros((N, 6, 6))
     lib().orc_biot(N, _p(Palg_r.reshape(N, 9)), _p(Cr), _p(T), _p(CB))
     return T, CB
+
+
+# ---------------------------------------------------------------------------
+# Empirical cubature (Sec. 3.3): training matrix, SVD basis and the greedy
+# point selection of Box 1.  Library primitives serve as steps: numpy's SVD
+# (eq. SVDlambda) and numpy.linalg.lstsq (Box 1, step 3).  The NNLS of step 5
+# is the Lawson-Hanson active-set method written out below: scipy 1.15's
+# nnls returns non-optimal results on some small problems (the optimality
+# conditions fail), so it cannot serve as a step.
+# ---------------------------------------------------------------------------
+def nnls(A, b, tol=None):
+    """argmin ||A x - b|| over x >= 0 by the active-set method of Lawson and
+    Hanson (Solving Least Squares Problems, 1974, ch. 23), from x = 0.
+
+    Outer loop: the dual vector g = A^T (b - A x); stop when no inactive
+    index has g_j > tol, else make the index of the largest g_j passive.
+    Inner loop: z = least squares on the passive columns; if every passive
+    z_j > 0 take x = z, else move x toward z until the first passive entry
+    reaches zero (step alpha = min x_j / (x_j - z_j) over z_j <= 0) and make
+    the entries that reached zero inactive.  An index whose own solution
+    entry is not positive right after it became passive is set aside until
+    x changes (the guard against cycling on rounding)."""
+    A = _f64(A)
+    b = _f64(b)
+    n = A.shape[1]
+    if tol is None:
+        tol = 1e-13 * max(1.0, np.abs(A).sum(axis=0).max()) * max(1.0, np.linalg.norm(b))
+    x = np.zeros(n)
+    P = np.zeros(n, dtype=bool)
+    blocked = np.zeros(n, dtype=bool)
+    for _ in range(3 * n + 10):
+        g = A.T @ (b - A @ x)
+        g[P | blocked] = -np.inf
+        t = int(np.argmax(g)) if n else 0
+        if n == 0 or not g[t] > tol:
+            return x
+        P[t] = True
+        first = True
+        while True:
+            z = np.zeros(n)
+            z[P] = np.linalg.lstsq(A[:, P], b, rcond=None)[0]
+            if np.all(z[P] > 0):
+                x = z
+                blocked[:] = False
+                break
+            if first and z[t] <= 0:
+                P[t] = False
+                blocked[t] = True
+                break
+            first = False
+            qi = np.flatnonzero(P & (z <= 0))
+            ratio = x[qi] / (x[qi] - z[qi])
+            alpha = ratio.min()
+            x = x + alpha * (z - x)
+            hit = np.zeros(n, dtype=bool)
+            hit[qi[ratio == alpha]] = True          # the entries that reached zero
+            hit |= P & (x <= 0)
+            x[hit] = 0.0
+            P &= ~hit
+            blocked[:] = False
+    raise RuntimeError("nnls: no convergence")
+
+
+def ecm_integrand(cl, theta, Fr, a):
+    """Force integrand f[p, m + 9, M] of every snapshot at every candidate
+    point: mode forces G_g^T P(F_g), then the nine components of P(F_g),
+    F_g = Fr^k + G_g a^k (C routine orc_ecm_integrand)."""
+    G, _, ph, th = _cluster_args(cl, theta)
+    Fr = _f64(Fr)
+    p = Fr.size // 9
+    a = _f64(a, (p, cl.m))
+    f = np.zeros((p, cl.m + 9, cl.Q))
+    bad = lib().orc_ecm_integrand(cl.m, cl.Q, _p(G), _p(ph), _p(th), p, _p(Fr.reshape(p, 9)),
+                                  _p(a), _p(f))
+    if bad:
+        raise ValueError("det F <= 0 at %d (snapshot, point) pairs" % bad)
+    return f
+
+
+def ecm_training_matrix(f, w):
+    """Training matrix x_f (Sec. 3.3, the matrix after eq. ECM1): row (k, i),
+    column g holds f^{kg}_i - f^k_i / V0, where f^k_i = sum_g w_g f^{kg}_i is
+    the fully integrated value and V0 = sum_g w_g.  Returns x_f[p (m+9), M]
+    and the integrals f^k_i as a vector of p (m+9)."""
+    f = _f64(f)
+    p, nt, M = f.shape
+    w = _f64(w, (M,))
+    V0 = w.sum()
+    fint = f.reshape(p * nt, M) @ w
+    xf = f.reshape(p * nt, M) - fint[:, None] / V0
+    return xf, fint
+
+
+def ecm_basis(xf, r):
+    """Eq. SVDlambda: x_f^T = lambda sigma v^T.  Returns the first r columns
+    of lambda (M x r, orthonormal, singular values in decreasing order) and
+    all singular values."""
+    U, s, _ = np.linalg.svd(_f64(xf).T, full_matrices=False)
+    return np.ascontiguousarray(U[:, :r]), s
+
+
+def ecm_greedy(lam, V0, mt):
+    """Box 1: greedy selection of at most mt points with non-negative weights.
+
+    J = [lambda 1]^T ((r + 1) x M), b = [0 ... 0 V0].  Readings: the residual
+    of step 7 is b - J_z w (the start value r = b and the maximised positive
+    correlation of step 1 fix its sign); ties of step 1 go to the lowest
+    index; points that the NNLS of step 5 gives zero weight leave the
+    selection for good (the excluded set); the loop also ends when no
+    candidate is left.  Returns (z, w, info) with z the selected indices in
+    selection order (dropped ones removed), w their weights and info a dict
+    with per-iteration records: 'picked', 'nnls' (bool), 'dropped' (lists)
+    and 'gap' (relative gap between the best and second best score)."""
+    lam = _f64(lam)
+    M, r = lam.shape
+    J = np.vstack([lam.T, np.ones((1, M))])
+    b = np.zeros(r + 1)
+    b[-1] = V0
+    jn = np.sqrt((J * J).sum(axis=0))
+    avail = np.ones(M, dtype=bool)
+    z, w = [], np.zeros(0)
+    res = b.copy()
+    info = dict(picked=[], nnls=[], dropped=[], gap=[])
+    while len(z) < mt and avail.any():
+        s = (J.T @ res) / jn                                   # step 1
+        s[~avail] = -np.inf
+        k = int(np.argmax(s))
+        s2 = np.partition(s[avail], -2)[-2] if avail.sum() > 1 else -np.inf
+        info["gap"].append(float((s[k] - s2) / max(abs(s[k]), 1e-300)))
+        z.append(k)                                            # step 2
+        avail[k] = False
+        Jz = J[:, z]
+        w = np.linalg.lstsq(Jz, b, rcond=None)[0]              # step 3
+        used = bool((w < 0).any())                             # step 4
+        drop = []
+        if used:
+            w = nnls(Jz, b)                                    # step 5
+            keep = w > 0                                       # step 6
+            drop = [z[i] for i in range(len(z)) if not keep[i]]
+            z = [z[i] for i in range(len(z)) if keep[i]]
+            w = w[keep]
+        res = b - J[:, z] @ w                                  # step 7
+        info["picked"].append(k)
+        info["nnls"].append(used)
+        info["dropped"].append(drop)
+    return np.array(z, dtype=np.int64), w, info

@@ -1094,3 +1094,46 @@ int orc_biot(int64_t N, const double *Palg_r, const double *Cr, double *T, doubl
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Training integrand of the empirical cubature (Sec. 3.3, eq. ECM1 and */
+/* the training matrix below it).  For snapshot k, given as the RVE-    */
+/* frame macro input Fr^k and its converged mode coefficients a^k, and  */
+/* for every candidate (full-integration) point g, the integrand is the */
+/* point's force vector: the mode forces G_g^T P(F_g) (m values) and    */
+/* the nine first Piola stress components P(F_g), with                  */
+/* F_g = Fr^k + G_g a^k.  Layout f[k][i][g], i < m + 9.  Returns the    */
+/* number of (k, g) pairs with det F_g <= 0 (their entries are zero).   */
+/* ------------------------------------------------------------------ */
+int orc_ecm_integrand(int m, int M, const double *G, const int *phase, const double *theta,
+                      int p, const double *Fr, const double *a, double *f)
+{
+    const int nt = m + 9;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (int k = 0; k < p; k++) {
+        double *fk = f + (size_t)k * nt * M;
+        for (int g = 0; g < M; g++) {
+            const double *Gg = G + (size_t)g * 9 * m;
+            double F[9], P[9];
+            for (int I = 0; I < 9; I++) {
+                double s = Fr[9 * k + I];
+                for (int n = 0; n < m; n++) s += a[(size_t)m * k + n] * Gg[I * m + n];
+                F[I] = s;
+            }
+            if (neo_hooke(F, theta[2 * phase[g]], theta[2 * phase[g] + 1], P, NULL, NULL, NULL,
+                          NULL) != 0) {
+                bad++;
+                for (int i = 0; i < nt; i++) fk[(size_t)i * M + g] = 0.0;
+                continue;
+            }
+            for (int n = 0; n < m; n++) {
+                double s = 0.0;
+                for (int I = 0; I < 9; I++) s += Gg[I * m + n] * P[I];
+                fk[(size_t)n * M + g] = s;
+            }
+            for (int I = 0; I < 9; I++) fk[(size_t)(m + I) * M + g] = P[I];
+        }
+    }
+    return bad;
+}
