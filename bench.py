@@ -465,9 +465,89 @@ def run_j2(args, quiet=False):
     print(json.dumps(line), flush=True)
 
 
+def svd_sweep_flops(P, M):
+    """FP64 flops of one sweep of the blocked one-sided Jacobi SVD: every pair
+    of 32-column blocks forms its 64 x 64 Gram matrix over the M rows and
+    multiplies its 64 columns by the 64 x 64 rotation (2 * 64 * 64 * M each)."""
+    nb = max(2, -(-P // 32))
+    nb += nb & 1
+    pairs_per_sweep = (nb - 1) * (nb // 2)
+    return pairs_per_sweep * 2 * (2.0 * 64 * 64 * M)
+
+
+def run_ecm(args, quiet=False):
+    """Empirical cubature (Sec. 3.3) at the sizes of the paper's second
+    example, 30 modes and 500 points, over 32768 candidate points and 60
+    training snapshots: macro states converged by the library's own
+    full-integration Newton (FP64, every candidate an integration point), then
+    the training matrix, the SVD basis and the Box 1 greedy on the GPU."""
+    import torch
+
+    import paper_2306_02687_amd as P
+    from hrom_inputs import WORKLOADS, make_cluster, make_macro_points
+    from paper_2306_02687_amd import binding as B
+    from paper_2306_02687_amd import solve
+
+    from hrom_inputs import THETA_REF
+    wl = WORKLOADS["ecm"]
+    m, M, p, mt = wl["m"], wl["M"], wl["p"], wl["mt"]
+    cl = make_cluster(m, M, wl["seed"])
+    F, _, _ = make_macro_points(p, wl["seed"] + 1, amp=wl["amp"])
+    spec = solve.upload_cluster(cl, p)
+    plan = P.Plan([spec], objective=False)
+    th = solve.theta_dev(THETA_REF)
+    Fd = solve.points_to_soa(F)
+    t0 = time.perf_counter()
+    st = solve.newton(plan, th, Fd, tol=1e-12, max_it=25)
+    torch.cuda.synchronize()
+    t_newton = time.perf_counter() - t0
+    status = int(st.status.max().item())
+    Fr = Fd.t().contiguous()
+    a = st.a.t().contiguous()
+    plan.close()
+    phase = spec.phase.to(torch.int32).contiguous()
+    V0 = float(cl.w.sum())
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t) * 1e3
+
+    B.ecm_training(spec.G, spec.w, phase, th, Fr, a)            # warm-up (code load)
+    (xf, fint, nbad), t_tr = timed(lambda: B.ecm_training(spec.G, spec.w, phase, th, Fr, a))
+    hist = []
+    (lam, sig, sweeps, _), t_svd = timed(lambda: B.ecm_svd(xf, mt - 1, history=hist))
+    (z, w, info), t_sel = timed(lambda: B.ecm_select(lam, V0, mt, trace_cap=8 * mt))
+    tr = info["trace"].cpu().numpy()
+    Prows = p * (m + 9)
+    flops = sweeps * svd_sweep_flops(Prows, M)
+    sig_h = sig.cpu().numpy()
+    res = {"training_ms": t_tr, "svd_ms": t_svd, "select_ms": t_sel,
+           "total_ms": t_tr + t_svd + t_sel, "newton_snapshots_ms": t_newton * 1e3,
+           "svd_sweeps": sweeps, "svd_off_history": [float("%.3g" % v) for v in hist],
+           "svd_tflops": flops / (t_svd * 1e-3) / 1e12,
+           "svd_frac_of_fp64_peak": flops / (t_svd * 1e-3) / 78.6e12,
+           "greedy_iterations": info["iters"], "nnls_calls": int(tr[:, 1].sum()),
+           "points_dropped": int(tr[:, 2].sum()), "selected": int(len(z)),
+           "sum_w_minus_V0": float(w.sum().item() - V0),
+           "sigma_ratio_at_truncation": float(sig_h[mt - 2] / sig_h[0]),
+           "status_max": status, "nbad": nbad,
+           "workload": f"{M} candidate points, {p} training snapshots (Newton-converged, "
+                       f"full integration), m={m} modes, x_f {Prows} x {M}, {mt} points selected"}
+    if quiet:
+        return res
+    line = {"metric": "ECM selection time (training matrix + SVD + Box 1 greedy)",
+            "value": res["total_ms"], "unit": "ms", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "f64", "data": "synthetic", "config": {"workload": res["workload"]},
+            "detail": res}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="mixed", choices=["mixed", "batched", "j2"],
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "batched", "j2", "ecm"],
                     help="mixed: the headline (m=64, Q=512) step; batched: uneven clusters; "
                          "j2: J2 plasticity path at the Example 1 sizes")
     ap.add_argument("--gpus", type=int, default=1)
@@ -517,6 +597,9 @@ def main():
         return
     if args.workload == "j2":
         run_j2(args)
+        return
+    if args.workload == "ecm":
+        run_ecm(args)
         return
     N, m, Q = args.N, args.m, args.Q
     print(f"[bench] building inputs N={N} m={m} Q={Q}", file=sys.stderr, flush=True)
@@ -589,6 +672,7 @@ def main():
         extras["monolithic_32_256"] = run_monolithic()
         print("[bench] extra: J2 plasticity path", file=sys.stderr, flush=True)
         extras["j2_8_250"] = run_j2(args, quiet=True)
+        extras["ecm_m30_500_of_32768"] = run_ecm(args, quiet=True)
 
     line = {
         "metric": METRIC, "value": value, "unit": "point-evals/s", "n_gpus": 1,

@@ -15,6 +15,7 @@ from .generators import (  # noqa: F401
     make_macro_points,
     make_increments,
     make_load_path,
+    make_snapshots,
     zipf_counts,
     perturbed_theta,
     WORKLOADS,

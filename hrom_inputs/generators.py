@@ -181,6 +181,17 @@ def zipf_counts(total: int, n: int, s: float) -> list[int]:
     return [int(x) for x in base]
 
 
+def make_snapshots(p: int, m: int, seed: int, amp: float = 0.05, a_std: float = 0.02):
+    """Training snapshots for the empirical cubature: RVE-frame macro inputs
+    ``Fr = I + H`` (``H`` symmetric, entries uniform in +-amp), ``[p, 9]``,
+    and mode coefficients ``a ~ N(0, a_std^2)``, ``[p, m]``."""
+    rng = np.random.default_rng(seed)
+    H = _sym_from_upper(rng.uniform(-amp, amp, size=(p, 6)))
+    Fr = (np.eye(3)[None] + H).reshape(p, 9)
+    a = rng.normal(0.0, a_std, size=(p, m))
+    return np.ascontiguousarray(Fr), np.ascontiguousarray(a)
+
+
 def perturbed_theta(seed: int, rel: float = 0.1):
     """Target parameters ``theta* = theta (1 + rel s)`` with seeded signs ``s``."""
     rng = np.random.default_rng(seed)
@@ -197,4 +208,8 @@ WORKLOADS = {
                     zipf_s=1.1, amp=0.05, seed=3000, iters=10, inc_amp=0.005),
     "mixed": dict(N=131072, m=64, Q=512, amps=[0.01, 0.05, 0.2], seed=4000),
     "adjoint": dict(N=65536, m=48, Q=384, amp=0.05, seed=5000, rel=0.1),
+    # empirical cubature: M candidate points, p training snapshots (30
+    # trajectories x 2 load levels), mt selected points (Sec. 3.3, the sizes
+    # of the paper's second example: 30 modes, 500 points)
+    "ecm": dict(m=30, M=32768, p=60, mt=500, amp=0.05, seed=6000),
 }

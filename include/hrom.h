@@ -61,6 +61,9 @@ extern "C" {
 #define HROM_E_UNSUPPORTED (-5) /* size outside the supported range (m > 96, ...), or an
                                  output the plan's mode does not provide */
 #define HROM_E_SCRATCH (-6)   /* hrom_newton_noalloc: the request does not fit its static scratch */
+#define HROM_E_NOCONV (-7)    /* an iteration did not reach its tolerance (ECM: SVD sweeps, NNLS) */
+#define HROM_E_RANK (-8)      /* ECM: truncation beyond the rank of the training matrix, or a
+                                 selected column dependent on the others */
 
 /* per-point status bits */
 #define HROM_PT_JNONPOS 1    /* det F <= 0 at an ECM point (or det Fbar <= 0) */
@@ -268,6 +271,59 @@ int hrom_newton_noalloc(const hrom_cluster* clusters, int32_t ncl, int64_t N, in
                         double tol, int32_t max_it, double* Pbar, double* Cbar, double* rnorm,
                         int32_t* status, hipStream_t stream);
 size_t hrom_noalloc_scratch_bytes(void);
+
+/* ---------------------------------------------------------------------------
+ * Empirical cubature: the offline selection of the ECM points and weights
+ * (Sec. 3.3).  The three calls run in order on the full set of M candidate
+ * integration points; each allocates its own device workspace, runs on
+ * `stream` and returns after synchronising it.  All array arguments are
+ * device pointers owned by the caller unless marked host.
+ * ------------------------------------------------------------------------- */
+
+/* Training matrix x_f (Sec. 3.3, eq. ECM1 and the matrix after it).  The
+ * candidates: mode gradients G [M][9][m] (the layout of hrom_cluster.G),
+ * weights w [M] (V0 = sum w), phase [M]; theta [4] Neo-Hooke moduli.  The p
+ * snapshots: RVE-frame macro input Fr [p][9] and converged mode
+ * coefficients a [p][m].  For snapshot k and candidate g the integrand is the
+ * point's force vector f^{kg} = [G_g^T P(F_g); P(F_g)] (m mode forces and the
+ * nine first Piola components), F_g = Fr^k + G_g a^k.  Outputs:
+ * xf [p (m + 9)][M], row k (m + 9) + i holding f^{kg}_i - f^k_i / V0, and
+ * fint [p (m + 9)] the integrals f^k_i = sum_g w_g f^{kg}_i.  *nbad (host,
+ * may be null) receives the number of (snapshot, candidate) pairs with
+ * det F_g <= 0, whose entries are zero.  Errors: HROM_E_INVALID (sizes,
+ * null pointers), HROM_E_NOMEM, HROM_E_HIP. */
+int hrom_ecm_training(int32_t m, int32_t M, const double* G, const double* w, const int32_t* phase,
+                      const double* theta, int32_t p, const double* Fr, const double* a, double* xf,
+                      double* fint, int32_t* nbad, hipStream_t stream);
+
+/* Truncated basis of eq. SVDlambda: x_f^T = lambda sigma v^T.  xf [P][M] is
+ * read only.  lam [M][r] receives the r leading left singular vectors of
+ * x_f^T (candidate-major: lam[g r + j]); sigma [P] all singular values in
+ * decreasing order.  tol: orthogonality of the Jacobi columns relative to
+ * their norms (<= 0: 1e-13); max_sweeps (<= 0: 40); *sweeps (host, may be
+ * null) the sweeps used; off_hist (host, may be null, max_sweeps entries)
+ * the largest relative off-diagonal Gram entry met in each sweep.  Singular vectors are determined up to sign (and
+ * rotation within equal singular values), which the selection does not see.
+ * Errors: HROM_E_INVALID (r > P, ...), HROM_E_NOCONV (sweeps exhausted;
+ * outputs written), HROM_E_RANK (sigma_r = 0), HROM_E_NOMEM, HROM_E_HIP. */
+int hrom_ecm_svd(int32_t P, int32_t M, const double* xf, int32_t r, double* lam, double* sigma, double tol,
+                 int32_t max_sweeps, int32_t* sweeps, double* off_hist, hipStream_t stream);
+
+/* Greedy selection of Box 1 on J = [lambda 1]^T, b = [0 ... 0 V0]: picks the
+ * available candidate of largest j_k . res / |j_k| (lowest index on ties),
+ * solves the least-squares problem on the selection, falls back to the
+ * non-negative one when a weight is negative and drops the points it gives
+ * zero weight for good, with res = b - J_z w; ends at mt points or when no
+ * candidate is left.  lam [M][r] as returned by hrom_ecm_svd, r + 1 <= 1024,
+ * 1 <= mt <= r + 1.  Outputs: z [mt] candidate indices in pick order and
+ * w [mt] their weights (the first *n_sel entries are valid; host n_sel),
+ * *iters (host) the iterations, trace [trace_cap][4] (may be null) per
+ * iteration: picked candidate, 1 if the NNLS ran, points dropped, selection
+ * size after it.  Errors: HROM_E_INVALID, HROM_E_RANK (a picked column
+ * dependent on the selection), HROM_E_NOCONV (NNLS iteration limit),
+ * HROM_E_NOMEM, HROM_E_HIP. */
+int hrom_ecm_select(int32_t M, int32_t r, const double* lam, double V0, int32_t mt, int32_t* z, double* w,
+                    int32_t* n_sel, int32_t* trace, int32_t trace_cap, int32_t* iters, hipStream_t stream);
 
 const char* hrom_strerror(int code);
 

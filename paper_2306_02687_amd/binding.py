@@ -32,8 +32,9 @@ EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_e
             "hrom_condense", "hrom_update", "hrom_newton", "hrom_backward", "hrom_strerror",
             "hrom_num_variants", "hrom_plan_set_variant", "hrom_plan_profile",
             "hrom_plan_tangent_ms", "hrom_cauchy", "hrom_newton_noalloc",
-            "hrom_noalloc_scratch_bytes", "hrom_commit", "hrom_history", "hrom_biot")
-E_SCRATCH = -6
+            "hrom_noalloc_scratch_bytes", "hrom_commit", "hrom_history", "hrom_biot",
+            "hrom_ecm_training", "hrom_ecm_svd", "hrom_ecm_select")
+E_SCRATCH, E_NOCONV, E_RANK = -6, -7, -8
 
 
 class HromError(RuntimeError):
@@ -81,6 +82,10 @@ def load(path: str = LIB_PATH):
     L.hrom_commit.argtypes = [P, P]
     L.hrom_biot.argtypes = [P, P, P, P, P]
     L.hrom_history.argtypes = [P, i32, P, P]
+    L.hrom_ecm_training.argtypes = [i32, i32, P, P, P, P, i32, P, P, P, P, C.POINTER(i32), P]
+    L.hrom_ecm_svd.argtypes = [i32, i32, P, i32, P, P, d, i32, C.POINTER(i32), P, P]
+    L.hrom_ecm_select.argtypes = [i32, i32, P, d, i32, P, P, C.POINTER(i32), P, i32,
+                                  C.POINTER(i32), P]
     L.hrom_strerror.argtypes = [C.c_int]
     L.hrom_strerror.restype = C.c_char_p
     _lib = L
@@ -160,6 +165,64 @@ def newton_noalloc(clusters, theta, Fbar, a, Pbar, Cbar, rnorm, status, precisio
 
 def noalloc_scratch_bytes() -> int:
     return int(load().hrom_noalloc_scratch_bytes())
+
+
+def ecm_training(G, w, phase, theta, Fr, a, stream=None):
+    """hrom_ecm_training: training matrix x_f [p (m + 9), M] and the integrals
+    fint [p (m + 9)] from the candidates (G [M, 9, m], w [M] float64, phase [M]
+    int32), theta [4] and the snapshots Fr [p, 9], a [p, m].  Returns
+    (xf, fint, nbad)."""
+    M, _, m = G.shape
+    p = Fr.shape[0]
+    xf = torch.empty((p * (m + 9), M), dtype=torch.float64, device=G.device)
+    fint = torch.empty(p * (m + 9), dtype=torch.float64, device=G.device)
+    nbad = C.c_int32(0)
+    _check(load().hrom_ecm_training(m, M, _ptr(G), _ptr(w), _ptr(phase), _ptr(theta), p, _ptr(Fr),
+                                    _ptr(a), _ptr(xf), _ptr(fint), C.byref(nbad), _stream(stream)),
+           "hrom_ecm_training")
+    return xf, fint, nbad.value
+
+
+def ecm_svd(xf, r, tol=0.0, max_sweeps=0, stream=None, check=True, history=None):
+    """hrom_ecm_svd: the r leading left singular vectors of x_f^T, lam [M, r],
+    and all singular values sigma [P].  Returns (lam, sigma, sweeps, rc); a
+    list passed as history receives the largest relative off-diagonal Gram
+    entry of every sweep."""
+    P, M = xf.shape
+    lam = torch.empty((M, max(r, 0)), dtype=torch.float64, device=xf.device)
+    sigma = torch.empty(P, dtype=torch.float64, device=xf.device)
+    sweeps = C.c_int32(0)
+    nh = max_sweeps if max_sweeps > 0 else 40
+    hist = (C.c_double * nh)()
+    rc = load().hrom_ecm_svd(P, M, _ptr(xf), r, _ptr(lam) if r > 0 else None, _ptr(sigma),
+                             float(tol), int(max_sweeps), C.byref(sweeps),
+                             C.cast(hist, C.c_void_p), _stream(stream))
+    if check:
+        _check(rc, "hrom_ecm_svd")
+    if history is not None:
+        history.extend(hist[:sweeps.value])
+    return lam, sigma, sweeps.value, rc
+
+
+def ecm_select(lam, V0, mt, trace_cap=0, stream=None, check=True):
+    """hrom_ecm_select: Box 1 greedy on lam [M, r].  Returns (z, w, info) with
+    z [n] int32 candidate indices in pick order, w [n] weights and info a dict
+    of iters, rc and (trace_cap > 0) trace [iters, 4]: picked, nnls, dropped, n."""
+    M, r = lam.shape
+    dev = lam.device
+    z = torch.zeros(max(mt, 1), dtype=torch.int32, device=dev)
+    w = torch.zeros(max(mt, 1), dtype=torch.float64, device=dev)
+    trace = torch.zeros((trace_cap, 4), dtype=torch.int32, device=dev) if trace_cap else None
+    n, it = C.c_int32(0), C.c_int32(0)
+    rc = load().hrom_ecm_select(M, r, _ptr(lam) if r > 0 else None, float(V0), int(mt), _ptr(z),
+                                _ptr(w), C.byref(n), _ptr(trace), int(trace_cap), C.byref(it),
+                                _stream(stream))
+    if check:
+        _check(rc, "hrom_ecm_select")
+    info = dict(iters=it.value, rc=rc)
+    if trace is not None:
+        info["trace"] = trace[:min(it.value, trace_cap)]
+    return z[:n.value], w[:n.value], info
 
 
 class Plan:

@@ -286,6 +286,8 @@ const char* hrom_strerror(int code) {
         case HROM_E_NOMEM: return "device allocation failed";
         case HROM_E_UNSUPPORTED: return "not supported (size outside the supported range, or an output the plan's mode does not provide)";
         case HROM_E_SCRATCH: return "the request needs more device memory than the static scratch of the allocation-free entry point";
+        case HROM_E_NOCONV: return "an iteration did not reach its tolerance (SVD sweeps, NNLS)";
+        case HROM_E_RANK: return "rank deficiency (truncation beyond the rank of the training matrix, or a dependent column)";
         default: return "unknown error";
     }
 }
