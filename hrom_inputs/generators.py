@@ -6,7 +6,7 @@ cluster is described by its ECM points (weights ``w``), the mode gradients
 ``G`` of its ROM modes at those points and a phase label per point; every
 macro Gauss point carries a macro deformation gradient ``Fbar``.
 
-Readings of the workload text (all documented in the design doc):
+Readings of the workload text:
 
 * ``N(0, 0.05)`` means standard deviation 0.05.
 * Draw order per cluster: weights, then mode gradients, then phases, all from

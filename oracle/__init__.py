@@ -9,8 +9,9 @@ one macro point at a time); this module only marshals numpy arrays into it.
 Every array is a row-major numpy array in its natural shape:
 ``G[Q, 9, m]``, ``Fbar[N, 3, 3]`` (or ``[N, 9]``), ``a[N, m]``.
 
-Parity status of every function is documented in the design doc; every function
-here is pinned by a test in ``tests/test_oracle_pins.py``.
+Every function here is pinned by tests against facts that do not come from
+the oracle itself (``tests/test_oracle_pins.py``, ``tests/test_oracle_j2.py``,
+``tests/test_oracle_ecm.py``).
 """
 from __future__ import annotations
 
