@@ -16,6 +16,9 @@ from .generators import (  # noqa: F401
     make_increments,
     make_load_path,
     make_snapshots,
+    make_strain_field,
+    init_indices,
+    make_pod_snapshots,
     zipf_counts,
     perturbed_theta,
     WORKLOADS,

@@ -192,6 +192,49 @@ def make_snapshots(p: int, m: int, seed: int, amp: float = 0.05, a_std: float = 
     return np.ascontiguousarray(Fr), np.ascontiguousarray(a)
 
 
+def make_strain_field(N: int, seed: int, n_groups: int = 12, amp: float = 0.05,
+                      spread: float = 0.15):
+    """Macro strain states ``[N, 6]`` (Voigt xx yy zz xy yz xz) standing in
+    for the surrogate macro simulation of the clustered training: ``n_groups``
+    loading directions (normal, unit length), each point one of them (uniform
+    draw) scaled by ``amp`` times U(0.2, 1) and perturbed by ``spread`` times
+    ``amp`` times a standard normal vector."""
+    rng = np.random.default_rng(seed)
+    D = rng.standard_normal((n_groups, 6))
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    g = rng.integers(0, n_groups, size=N)
+    t = rng.uniform(0.2, 1.0, size=N)
+    E = amp * (t[:, None] * D[g] + spread * rng.standard_normal((N, 6)))
+    return np.ascontiguousarray(E)
+
+
+def init_indices(N: int, k: int, seed: int):
+    """``k`` distinct point indices for the initial k-means centres."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(N, size=k, replace=False)).astype(np.int32)
+
+
+def make_pod_snapshots(nd: int, s_el: int, s_in: int, seed: int, n_in: int = 12,
+                       yield_frac: float = 0.5):
+    """Displacement snapshots ``[nd, s]`` with the structure of the POD
+    training: elastic snapshots ``X_el = L E`` (``L`` a random ``[nd, 6]``
+    response to the six unit strains, ``E`` random strain states) and
+    inelastic ones ``X_inel = L E' + P g(E')``, where ``P`` is a random
+    ``[nd, n_in]`` block and ``g`` takes the part of ``n_in`` random
+    projections of ``E'`` beyond a threshold (zero below it).  Returns
+    ``(X_el, X_inel, L, P)``."""
+    rng = np.random.default_rng(seed)
+    L = rng.standard_normal((nd, 6)) / np.sqrt(nd)
+    P = rng.standard_normal((nd, n_in)) / np.sqrt(nd)
+    E = rng.uniform(-1.0, 1.0, size=(6, s_el))
+    E2 = rng.uniform(-1.0, 1.0, size=(6, s_in))
+    A = rng.standard_normal((n_in, 6))
+    proj = A @ E2
+    g = np.sign(proj) * np.maximum(np.abs(proj) - yield_frac, 0.0)
+    return (np.ascontiguousarray(L @ E), np.ascontiguousarray(L @ E2 + P @ g),
+            np.ascontiguousarray(L), np.ascontiguousarray(P))
+
+
 def perturbed_theta(seed: int, rel: float = 0.1):
     """Target parameters ``theta* = theta (1 + rel s)`` with seeded signs ``s``."""
     rng = np.random.default_rng(seed)
@@ -212,4 +255,8 @@ WORKLOADS = {
     # trajectories x 2 load levels), mt selected points (Sec. 3.3, the sizes
     # of the paper's second example: 30 modes, 500 points)
     "ecm": dict(m=30, M=32768, p=60, mt=500, amp=0.05, seed=6000),
+    # clustered training: the macro strain states of 262144 points in 30
+    # clusters (the paper's first two examples); POD of 16384-dof snapshots
+    "training": dict(N=262144, k=30, n_groups=12, seed=7000, nd=16384, s_el=60, s_in=240,
+                     n_el=6, n_inel=24),
 }

@@ -447,3 +447,77 @@ def ecm_greedy(lam, V0, mt):
         info["nnls"].append(used)
         info["dropped"].append(drop)
     return np.array(z, dtype=np.int64), w, info
+
+
+# ---------------------------------------------------------------------------
+# Clustered training (Sec. 3.4, Box 2) and the POD basis (Sec. 3.2.1,
+# eqs. SVD_displacement and snapshots_displacement).
+# ---------------------------------------------------------------------------
+def kmeans(X, C0, max_iter=100):
+    """Lloyd's k-means (Box 2, step 3).  X [N, d] points, C0 [k, d] initial
+    centres.  Each iteration assigns every point to its nearest centre
+    (squared Euclidean distance; ties to the lowest centre index), then moves
+    every centre to the mean of its points (a centre without points stays).
+    Stops when no assignment changes.  Returns (centres, labels, iterations)."""
+    X = _f64(X)
+    C = _f64(C0).copy()
+    N, k = X.shape[0], C.shape[0]
+    labels = np.full(N, -1, dtype=np.int64)
+    for it in range(1, max_iter + 1):
+        d2 = ((X[:, None, :] - C[None, :, :]) ** 2).sum(axis=2)
+        new = d2.argmin(axis=1)
+        changed = int((new != labels).sum())
+        labels = new
+        for c in range(k):
+            sel = labels == c
+            if sel.any():
+                C[c] = X[sel].mean(axis=0)
+        if changed == 0:
+            return C, labels, it
+    return C, labels, max_iter
+
+
+def pod_split(X_el, X_inel, n_el, n_inel):
+    """Eq. SVD_displacement with the elastic-inelastic split: the first n_el
+    left singular vectors of the elastic snapshots X_el [nd, s_el] form
+    Phi_el; the inelastic snapshots lose their part in span Phi_el
+    (eq. snapshots_displacement: X_inel - Phi_el Phi_el^T X_inel) and the
+    first n_inel left singular vectors of the rest form Phi_inel.
+    Returns (Phi [nd, n_el + n_inel], sigma_el, sigma_inel)."""
+    X_el = _f64(X_el)
+    X_inel = _f64(X_inel)
+    U, s_el, _ = np.linalg.svd(X_el, full_matrices=False)
+    Phi_el = U[:, :n_el]
+    X_mod = X_inel - Phi_el @ (Phi_el.T @ X_inel)
+    V, s_in, _ = np.linalg.svd(X_mod, full_matrices=False)
+    return np.hstack([Phi_el, V[:, :n_inel]]), s_el, s_in
+
+
+def training_clusters(E, k, init_idx, max_iter=100):
+    """Box 2, steps 2 and 3: every strain component scaled by its root mean
+    square over the points (the normalisation of the strain values), Lloyd's
+    k-means started from the points init_idx, the centres returned in strain
+    units.  E [N, d]; returns (centres [k, d], labels, iterations)."""
+    E = _f64(E)
+    s = np.sqrt((E * E).mean(axis=0))
+    s[s == 0.0] = 1.0
+    Xn = E / s
+    C, labels, it = kmeans(Xn, Xn[np.asarray(init_idx)], max_iter)
+    return C * s, labels, it
+
+
+def training_paths(centres, n_steps):
+    """Monotonic training trajectories from the cluster centres: for centre c
+    (Voigt strain xx yy zz xy yz xz, tensor shear components) and step
+    j = 1 .. n_steps the RVE-frame macro input Fr = I + (j / n_steps) H(c),
+    H symmetric.  Returns Fr [k n_steps, 9] (centre-major)."""
+    C = _f64(centres)
+    k = C.shape[0]
+    out = np.zeros((k, n_steps, 3, 3))
+    for c in range(k):
+        H = np.array([[C[c, 0], C[c, 3], C[c, 5]],
+                      [C[c, 3], C[c, 1], C[c, 4]],
+                      [C[c, 5], C[c, 4], C[c, 2]]])
+        for j in range(n_steps):
+            out[c, j] = np.eye(3) + (j + 1) / n_steps * H
+    return out.reshape(k * n_steps, 9)
