@@ -325,6 +325,45 @@ int hrom_ecm_svd(int32_t P, int32_t M, const double* xf, int32_t r, double* lam,
 int hrom_ecm_select(int32_t M, int32_t r, const double* lam, double V0, int32_t mt, int32_t* z, double* w,
                     int32_t* n_sel, int32_t* trace, int32_t trace_cap, int32_t* iters, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Clustered training (Sec. 3.4, Box 2) and the POD basis (Sec. 3.2.1).
+ * Each call allocates its own device workspace and returns after
+ * synchronising `stream`; array arguments are device pointers owned by the
+ * caller unless marked host.
+ * ------------------------------------------------------------------------- */
+
+/* Box 2, steps 2 and 3: E [d][N] (component-major) macro strain states of N
+ * points, d <= 8 components; every component is scaled by its root mean square
+ * over the points, then Lloyd's k-means (k <= 1024 centres, started from the
+ * points init_idx [k]) runs until no label changes: every point to its nearest
+ * centre (squared Euclidean distance, ties to the lowest centre index), every
+ * centre to the mean of its points (a centre without points stays).  Outputs:
+ * centres [k][d] in the units of E, labels [N]; *iters (host, may be null) the
+ * iterations.  Errors: HROM_E_INVALID, HROM_E_NOCONV (max_iter reached;
+ * outputs of the last iteration written), HROM_E_NOMEM, HROM_E_HIP. */
+int hrom_training_clusters(int64_t N, int32_t d, const double* E, int32_t k, const int32_t* init_idx,
+                           int32_t max_iter, double* centres, int32_t* labels, int32_t* iters,
+                           hipStream_t stream);
+
+/* Monotonic training trajectories from cluster centres (Box 2, step 4):
+ * centres [k][6] (strain xx yy zz xy yz xz, tensor shear components); for step
+ * j = 1 .. n_steps, Fr[c n_steps + j - 1] = I + (j / n_steps) H(c), H
+ * symmetric, as [k n_steps][9] row-major 3x3 (RVE-frame macro inputs).  Only
+ * enqueues on `stream`.  Errors: HROM_E_INVALID, HROM_E_HIP. */
+int hrom_training_paths(int32_t k, const double* centres, int32_t n_steps, double* Fr, hipStream_t stream);
+
+/* POD with the elastic-inelastic split (Sec. 3.2.1, eqs. SVD_displacement and
+ * snapshots_displacement): X_el [s_el][nd] elastic and X_in [s_in][nd]
+ * inelastic displacement snapshots (one snapshot of nd nodal values per row).
+ * Phi [nd][n_el + n_in] receives the n_el leading left singular vectors of the
+ * elastic snapshots, then the n_in leading ones of the inelastic snapshots
+ * without their part in that span; sigma_el [s_el], sigma_in [s_in] all
+ * singular values.  Errors: HROM_E_INVALID (n_el > s_el, ...), HROM_E_RANK
+ * (fewer independent snapshots than modes asked), HROM_E_NOCONV, HROM_E_NOMEM,
+ * HROM_E_HIP. */
+int hrom_pod(int32_t nd, int32_t s_el, const double* X_el, int32_t s_in, const double* X_in, int32_t n_el,
+             int32_t n_in, double* Phi, double* sigma_el, double* sigma_in, hipStream_t stream);
+
 const char* hrom_strerror(int code);
 
 #ifdef __cplusplus

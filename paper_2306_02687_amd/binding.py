@@ -33,7 +33,8 @@ EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_e
             "hrom_num_variants", "hrom_plan_set_variant", "hrom_plan_profile",
             "hrom_plan_tangent_ms", "hrom_cauchy", "hrom_newton_noalloc",
             "hrom_noalloc_scratch_bytes", "hrom_commit", "hrom_history", "hrom_biot",
-            "hrom_ecm_training", "hrom_ecm_svd", "hrom_ecm_select")
+            "hrom_ecm_training", "hrom_ecm_svd", "hrom_ecm_select", "hrom_training_clusters",
+            "hrom_training_paths", "hrom_pod")
 E_SCRATCH, E_NOCONV, E_RANK = -6, -7, -8
 
 
@@ -86,6 +87,9 @@ def load(path: str = LIB_PATH):
     L.hrom_ecm_svd.argtypes = [i32, i32, P, i32, P, P, d, i32, C.POINTER(i32), P, P]
     L.hrom_ecm_select.argtypes = [i32, i32, P, d, i32, P, P, C.POINTER(i32), P, i32,
                                   C.POINTER(i32), P]
+    L.hrom_training_clusters.argtypes = [i64, i32, P, i32, P, i32, P, P, C.POINTER(i32), P]
+    L.hrom_training_paths.argtypes = [i32, P, i32, P, P]
+    L.hrom_pod.argtypes = [i32, i32, P, i32, P, i32, i32, P, P, P, P]
     L.hrom_strerror.argtypes = [C.c_int]
     L.hrom_strerror.restype = C.c_char_p
     _lib = L
@@ -358,3 +362,41 @@ class Plan:
     def backward(self, theta, a, gPbar, gFbar, gtheta, status, stream=None):
         _check(load().hrom_backward(self._h, _ptr(theta), _ptr(a), _ptr(gPbar), _ptr(gFbar),
                                     _ptr(gtheta), _ptr(status), _stream(stream)), "hrom_backward")
+
+
+def training_clusters(E, k, init_idx, max_iter=100, stream=None, check=True):
+    """hrom_training_clusters: E [d, N] strain states (component-major),
+    init_idx [k] int32.  Returns (centres [k, d], labels [N] int32, iters, rc)."""
+    d, N = E.shape
+    centres = torch.empty((k, d), dtype=torch.float64, device=E.device)
+    labels = torch.empty(N, dtype=torch.int32, device=E.device)
+    it = C.c_int32(0)
+    rc = load().hrom_training_clusters(N, d, _ptr(E), k, _ptr(init_idx), int(max_iter), _ptr(centres),
+                                       _ptr(labels), C.byref(it), _stream(stream))
+    if check:
+        _check(rc, "hrom_training_clusters")
+    return centres, labels, it.value, rc
+
+
+def training_paths(centres, n_steps, stream=None):
+    """hrom_training_paths: Fr [k n_steps, 9] from centres [k, 6]."""
+    k = centres.shape[0]
+    Fr = torch.empty((k * n_steps, 9), dtype=torch.float64, device=centres.device)
+    _check(load().hrom_training_paths(k, _ptr(centres), int(n_steps), _ptr(Fr), _stream(stream)),
+           "hrom_training_paths")
+    return Fr
+
+
+def pod(X_el, X_in, n_el, n_in, stream=None, check=True):
+    """hrom_pod: X_el [s_el, nd], X_in [s_in, nd] snapshots (one per row).
+    Returns (Phi [nd, n_el + n_in], sigma_el, sigma_in, rc)."""
+    s_el, nd = X_el.shape
+    s_in = X_in.shape[0]
+    Phi = torch.empty((nd, n_el + n_in), dtype=torch.float64, device=X_el.device)
+    sel = torch.empty(s_el, dtype=torch.float64, device=X_el.device)
+    sin = torch.empty(s_in, dtype=torch.float64, device=X_el.device)
+    rc = load().hrom_pod(nd, s_el, _ptr(X_el), s_in, _ptr(X_in), int(n_el), int(n_in), _ptr(Phi),
+                         _ptr(sel), _ptr(sin), _stream(stream))
+    if check:
+        _check(rc, "hrom_pod")
+    return Phi, sel, sin, rc

@@ -423,9 +423,9 @@ __global__ void k_svd_rank(const double* sig, int P, int* perm, double* sig_out)
     sig_out[rk] = s;
 }
 
-// lam[g][j] = A[perm[j]][g] / sigma_j, j < r
+// lam[g][j] = A[perm[j]][g] / sigma_j, j < r (row stride ld)
 __global__ void k_svd_extract(const double* A, int M, const int* perm, const double* sig_sorted, int r,
-                              double* lam) {
+                              double* lam, int ld) {
     __shared__ double t[32][33];
     const int g0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
     for (int jj = threadIdx.y; jj < 32; jj += 8) {
@@ -435,7 +435,7 @@ __global__ void k_svd_extract(const double* A, int M, const int* perm, const dou
     __syncthreads();
     for (int gg = threadIdx.y; gg < 32; gg += 8) {
         const int g = g0 + gg, j = j0 + threadIdx.x;
-        if (g < M && j < r) lam[(int64_t)g * r + j] = t[threadIdx.x][gg];
+        if (g < M && j < r) lam[(int64_t)g * ld + j] = t[threadIdx.x][gg];
     }
 }
 
@@ -1157,9 +1157,14 @@ int hrom_ecm_training(int32_t m, int32_t M, const double* G, const double* w, co
     return HROM_OK;
 }
 
-int hrom_ecm_svd(int32_t P, int32_t M, const double* xf, int32_t r, double* lam, double* sigma, double tol,
-                 int32_t max_sweeps, int32_t* sweeps, double* off_hist, hipStream_t stream) {
-    if (P < 1 || M < 1 || r < 0 || r > P || !xf || !sigma || (r > 0 && !lam)) return HROM_E_INVALID;
+}  // extern "C"
+
+namespace hrom {
+// the r leading left singular vectors of xf^T (xf [P][M]) into lam (row
+// stride ld), all singular values into sigma; the Jacobi of hrom_ecm_svd
+int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double* sigma, double tol,
+             int max_sweeps, int* sweeps, double* off_hist, hipStream_t stream) {
+    if (P < 1 || M < 1 || r < 0 || r > P || ld < r || !xf || !sigma || (r > 0 && !lam)) return HROM_E_INVALID;
     if (!(tol > 0.0)) tol = 1e-13;
     if (max_sweeps <= 0) max_sweeps = 40;
     int nbk = (P + kSB - 1) / kSB;
@@ -1232,7 +1237,7 @@ int hrom_ecm_svd(int32_t P, int32_t M, const double* xf, int32_t r, double* lam,
     hipLaunchKernelGGL(k_svd_rank, dim3((P + 255) / 256), dim3(256), 0, stream, sig, P, perm, sig_sorted);
     if (r > 0)
         hipLaunchKernelGGL(k_svd_extract, dim3((M + 31) / 32, (r + 31) / 32), dim3(32, 8), 0, stream, A, M,
-                           perm, sig_sorted, r, lam);
+                           perm, sig_sorted, r, lam, ld);
     if (launched() != HROM_OK) return HROM_E_HIP;
     if (hipMemcpyAsync(sigma, sig_sorted, sizeof(double) * P, hipMemcpyDeviceToDevice, stream) != hipSuccess)
         return HROM_E_HIP;
@@ -1245,6 +1250,14 @@ int hrom_ecm_svd(int32_t P, int32_t M, const double* xf, int32_t r, double* lam,
     if (!conv) return HROM_E_NOCONV;
     if (!(sr > 0.0)) return HROM_E_RANK;
     return HROM_OK;
+}
+}  // namespace hrom
+
+extern "C" {
+
+int hrom_ecm_svd(int32_t P, int32_t M, const double* xf, int32_t r, double* lam, double* sigma, double tol,
+                 int32_t max_sweeps, int32_t* sweeps, double* off_hist, hipStream_t stream) {
+    return hrom::svd_left(P, M, xf, r, lam, r, sigma, tol, max_sweeps, sweeps, off_hist, stream);
 }
 
 int hrom_ecm_select(int32_t M, int32_t r, const double* lam, double V0, int32_t mt, int32_t* z, double* w,

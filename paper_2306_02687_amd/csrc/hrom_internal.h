@@ -398,4 +398,10 @@ struct GroupCall {
 int launch_tan_persistent(const GroupCall& g, int grid, hipStream_t s);   // FP64
 void set_kernel_attributes();
 
+// the r leading left singular vectors of xf^T (xf [P][M] rows) into lam with
+// row stride ld, all singular values into sigma (one-sided block Jacobi of the
+// empirical cubature, shared by the POD of the clustered training)
+int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double* sigma, double tol,
+             int max_sweeps, int* sweeps, double* off_hist, hipStream_t stream);
+
 }  // namespace hrom
