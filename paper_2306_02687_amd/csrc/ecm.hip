@@ -10,8 +10,9 @@
 //  * hrom_ecm_svd: blocked one-sided Jacobi on x_f^T (columns = rows of x_f,
 //    length M): per round a tournament of disjoint pairs of 32-column blocks;
 //    for each pair the 64 x 64 Gram matrix (partial sums over row chunks,
-//    summed in a fixed order), its eigenvectors by cyclic Jacobi in LDS, and
-//    the product of the 64 columns with them.  Sweeps run until every pair is
+//    summed in a fixed order), one cyclic Jacobi sweep over it in LDS (a full
+//    inner solve cost more time than the extra outer sweep it saves), and the
+//    product of the 64 columns with the accumulated rotation.  Sweeps run until every pair is
 //    orthogonal to the tolerance relative to the column norms; then the
 //    columns are ranked by norm and the leading r, normalised, form lambda.
 //    One-sided Jacobi keeps small singular values accurate (a Gram matrix of
@@ -38,6 +39,8 @@
 
 namespace hrom {
 namespace ecm {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double wave_sum(double s) {
 #pragma unroll
@@ -198,41 +201,38 @@ __device__ __forceinline__ bool pair_settled(const int2 pr, const int* ver, cons
 __global__ void __launch_bounds__(256) k_svd_gram(const double* __restrict__ A, int M, const int2* pairs,
                                                   int chunk_rows, int nchunks, double* __restrict__ part,
                                                   const int* ver, const int2* pver, int pbase) {
+    // FP64 16x16x4 MFMA: wavefront w forms the four 16 x 16 tiles (w, 0..3) of
+    // the 64 x 64 Gram matrix; lane (g, c) = (lane / 16, lane % 16) feeds
+    // A[c][g] = T[16 w + c][k0 + g] and B[g][c] = T[16 J + c][k0 + g], and its
+    // accumulator element e is D[g + 4 e][c]
     __shared__ double T[kSW][kSR + 1];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
     const int2 pr = pairs[blockIdx.x];
     if (pair_settled(pr, ver, pver, pbase + blockIdx.x)) return;
     const int r0 = blockIdx.y * chunk_rows, r1 = min(M, r0 + chunk_rows);
-    double acc[4][4];
+    v4d acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
+    for (int J = 0; J < 4; J++) acc[J] = v4d{0.0, 0.0, 0.0, 0.0};
     for (int rb = r0; rb < r1; rb += kSR) {
         for (int e = tid; e < kSW * kSR; e += 256) {
-            const int c = e / kSR, rr = e % kSR, g = rb + rr;
-            T[c][rr] = (g < r1) ? A[(int64_t)pair_col(pr, c) * M + g] : 0.0;
+            const int cc = e / kSR, rr = e % kSR, gg = rb + rr;
+            T[cc][rr] = (gg < r1) ? A[(int64_t)pair_col(pr, cc) * M + gg] : 0.0;
         }
         __syncthreads();
 #pragma unroll 4
-        for (int rr = 0; rr < kSR; rr++) {
-            double x[4], y[4];
+        for (int k0 = 0; k0 < kSR; k0 += 4) {
+            const double a = T[16 * wave + c][k0 + g];
 #pragma unroll
-            for (int i = 0; i < 4; i++) x[i] = T[tx + 16 * i][rr];
-#pragma unroll
-            for (int j = 0; j < 4; j++) y[j] = T[ty + 16 * j][rr];
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int j = 0; j < 4; j++) acc[i][j] += x[i] * y[j];
+            for (int J = 0; J < 4; J++)
+                acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, T[16 * J + c][k0 + g], acc[J], 0, 0, 0);
         }
         __syncthreads();
     }
     double* out = part + ((int64_t)blockIdx.x * nchunks + blockIdx.y) * (kSW * kSW);
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int J = 0; J < 4; J++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) out[(tx + 16 * i) * kSW + ty + 16 * j] = acc[i][j];
+        for (int e = 0; e < 4; e++) out[(16 * wave + g + 4 * e) * kSW + 16 * J + c] = acc[J][e];
 }
 
 // order-preserving bits of a non-negative double, for atomicMax
@@ -356,47 +356,49 @@ __global__ void __launch_bounds__(256) k_svd_rotate(const double* __restrict__ p
     for (int e = tid; e < kSW * kSW; e += 256) Vout[(int64_t)blockIdx.x * kSW * kSW + e] = V[e / kSW][e % kSW];
 }
 
-// the pair's 64 columns times its rotation, rows blockIdx.y * 64 ...
+// the pair's 64 columns times its rotation over rows chunk blockIdx.y (1024
+// rows, the rotation loaded once), 64 rows per step: FP64 16x16x4 MFMA,
+// wavefront w the row tile w against the four column tiles (A[row][c] =
+// T[c][row], B[c][c'] = V[c][c']), the result staged in LDS for coalesced
+// stores
 __global__ void __launch_bounds__(256) k_svd_apply(double* __restrict__ A, int M, const int2* pairs,
-                                                   const double* __restrict__ Vin, const int* apply) {
+                                                   const double* __restrict__ Vin, const int* apply,
+                                                   int chunk_rows) {
     __shared__ double T[kSW][kSR + 1];
     __shared__ double Vs[kSW][kSW + 1];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
     if (!apply[blockIdx.x]) return;
     const int2 pr = pairs[blockIdx.x];
-    const int g0 = blockIdx.y * kSR;
     const double* V = Vin + (int64_t)blockIdx.x * kSW * kSW;
     for (int e = tid; e < kSW * kSW; e += 256) Vs[e / kSW][e % kSW] = V[e];
-    for (int e = tid; e < kSW * kSR; e += 256) {
-        const int c = e / kSR, rr = e % kSR, g = g0 + rr;
-        T[c][rr] = (g < M) ? A[(int64_t)pair_col(pr, c) * M + g] : 0.0;
-    }
-    __syncthreads();
-    double acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
-#pragma unroll 4
-    for (int c = 0; c < kSW; c++) {
-        double x[4], y[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) x[i] = T[c][tx + 16 * i];
-#pragma unroll
-        for (int j = 0; j < 4; j++) y[j] = Vs[c][ty + 16 * j];
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-            for (int j = 0; j < 4; j++) acc[i][j] += x[i] * y[j];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        double* col = A + (int64_t)pair_col(pr, ty + 16 * j) * M;
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int g = g0 + tx + 16 * i;
-            if (g < M) col[g] = acc[i][j];
+    const int r0 = blockIdx.y * chunk_rows, r1 = min(M, r0 + chunk_rows);
+    for (int g0 = r0; g0 < r1; g0 += kSR) {
+        for (int e = tid; e < kSW * kSR; e += 256) {
+            const int cc = e / kSR, rr = e % kSR, gg = g0 + rr;
+            T[cc][rr] = (gg < r1) ? A[(int64_t)pair_col(pr, cc) * M + gg] : 0.0;
         }
+        __syncthreads();
+        v4d acc[4];
+#pragma unroll
+        for (int C = 0; C < 4; C++) acc[C] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < kSW; k0 += 4) {
+            const double a = T[k0 + g][16 * wave + c];
+#pragma unroll
+            for (int C = 0; C < 4; C++)
+                acc[C] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vs[k0 + g][16 * C + c], acc[C], 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int C = 0; C < 4; C++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) T[16 * C + c][16 * wave + g + 4 * e] = acc[C][e];
+        __syncthreads();
+        for (int e = tid; e < kSW * kSR; e += 256) {
+            const int cc = e / kSR, rr = e % kSR, gg = g0 + rr;
+            if (gg < r1) A[(int64_t)pair_col(pr, cc) * M + gg] = T[cc][rr];
+        }
+        __syncthreads();
     }
 }
 
@@ -1217,10 +1219,10 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
             const int pbase = t * npairs;
             hipLaunchKernelGGL(k_svd_gram, dim3(npairs, nchunks), dim3(256), 0, stream, A, M, pr, chunk_rows,
                                nchunks, part, ver, pver, pbase);
-            hipLaunchKernelGGL(k_svd_rotate, dim3(npairs), dim3(256), 0, stream, part, nchunks, tol, 4, Vb,
+            hipLaunchKernelGGL(k_svd_rotate, dim3(npairs), dim3(256), 0, stream, part, nchunks, tol, 1, Vb,
                                offmax, pr, ver, pver, pbase, apply);
-            hipLaunchKernelGGL(k_svd_apply, dim3(npairs, (M + kSR - 1) / kSR), dim3(256), 0, stream, A, M, pr,
-                               Vb, apply);
+            hipLaunchKernelGGL(k_svd_apply, dim3(npairs, nchunks), dim3(256), 0, stream, A, M, pr, Vb, apply,
+                               chunk_rows);
         }
         if (launched() != HROM_OK) return HROM_E_HIP;
         unsigned long long hb = 0;

@@ -4,10 +4,10 @@
 //
 //  * hrom_training_clusters: the macro strain states scaled per component by
 //    their root mean square, then Lloyd's k-means: a thread per point finds
-//    its nearest centre (the centres in LDS) and counts changed labels; a
-//    workgroup per centre sums its points in a fixed order (labels scanned
-//    by all threads, a fixed block reduction), so every run gives the same
-//    bits; the host loop stops when no label changes.
+//    its nearest centre (the centres in LDS) and counts changed labels; per
+//    chunk of 1024 points a thread per centre sums the centre's points in
+//    order, and the chunk partials are added in chunk order (every run gives
+//    the same bits); the host loop stops when no label changes.
 //  * hrom_training_paths: monotonic trajectories Fr = I + t H(c).
 //  * hrom_pod: the elastic modes from the snapshots' left singular vectors,
 //    the inelastic snapshots without their part in the elastic span, their
@@ -63,7 +63,7 @@ __global__ void k_km_init(const double* E, int64_t N, int d, int k, const int32_
 // nearest centre of every point (ties: the lowest index); counts changes
 __global__ void __launch_bounds__(256) k_km_assign(const double* E, int64_t N, int d, int k, const double* scale,
                                                    const double* C, int32_t* labels, int* changed) {
-    __shared__ double sC[kMaxK * kMaxD];
+    extern __shared__ double sC[];   // k d centres
     for (int e = threadIdx.x; e < k * d; e += 256) sC[e] = C[e];
     __syncthreads();
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -95,27 +95,53 @@ __global__ void __launch_bounds__(256) k_km_assign(const double* E, int64_t N, i
     if ((threadIdx.x & 63) == 0 && bal) atomicAdd(changed, __popcll(bal));
 }
 
-// centre c = mean of its points, in a fixed order (a centre without points stays)
-__global__ void __launch_bounds__(256) k_km_update(const double* E, int64_t N, int d, const double* scale,
-                                                   const int32_t* labels, double* C) {
-    __shared__ double red[4];
-    const int c = blockIdx.x;
-    double s[kMaxD];
-#pragma unroll
-    for (int j = 0; j < kMaxD; j++) s[j] = 0.0;
-    double cnt = 0.0;
-    for (int64_t g = threadIdx.x; g < N; g += 256) {
-        if (labels[g] != c) continue;
-        cnt += 1.0;
-#pragma unroll
-        for (int j = 0; j < kMaxD; j++)
-            if (j < d) s[j] += E[(int64_t)j * N + g] / scale[j];
+constexpr int kChunk = 1024;     // points per workgroup of the centre update
+
+// per chunk of 1024 points and per centre: the sum of the centre's points
+// (normalised) and their count, a thread per centre scanning the chunk in
+// order from LDS (the same bits on every run)
+__global__ void __launch_bounds__(256) k_km_partial(const double* E, int64_t N, int d, int k, const double* scale,
+                                                    const int32_t* labels, double* part) {
+    __shared__ int sl[kChunk];
+    __shared__ double sx[kMaxD][kChunk];
+    const int64_t g0 = (int64_t)blockIdx.x * kChunk;
+    const int n = (int)min((int64_t)kChunk, N - g0);
+    for (int i = threadIdx.x; i < kChunk; i += 256) {
+        sl[i] = (i < n) ? labels[g0 + i] : -1;
+        for (int j = 0; j < d; j++) sx[j][i] = (i < n) ? E[(int64_t)j * N + g0 + i] / scale[j] : 0.0;
     }
-    const double n = block_sum256(cnt, red);
-    for (int j = 0; j < d; j++) {
-        const double t = block_sum256(s[j], red);
-        if (threadIdx.x == 0 && n > 0.0) C[c * d + j] = t / n;
+    __syncthreads();
+    for (int c = threadIdx.x; c < k; c += 256) {
+        double acc[kMaxD];
+#pragma unroll
+        for (int j = 0; j < kMaxD; j++) acc[j] = 0.0;
+        double cnt = 0.0;
+        for (int i = 0; i < n; i++) {
+            if (sl[i] != c) continue;
+            cnt += 1.0;
+#pragma unroll
+            for (int j = 0; j < kMaxD; j++)
+                if (j < d) acc[j] += sx[j][i];
+        }
+        double* out = part + ((int64_t)blockIdx.x * k + c) * (d + 1);
+        for (int j = 0; j < d; j++) out[j] = acc[j];
+        out[d] = cnt;
     }
+}
+
+// centre c = mean of its points from the chunk partials in chunk order (a
+// centre without points stays)
+__global__ void k_km_reduce(const double* part, int nchunks, int k, int d, double* C) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= k * d) return;
+    const int c = e / d, j = e % d;
+    double s = 0.0, n = 0.0;
+    for (int b = 0; b < nchunks; b++) {
+        const double* p = part + ((int64_t)b * k + c) * (d + 1);
+        s += p[j];
+        n += p[d];
+    }
+    if (n > 0.0) C[e] = s / n;
 }
 
 __global__ void k_km_out(const double* C, int k, int d, const double* scale, double* out) {
@@ -173,13 +199,16 @@ int hrom_training_clusters(int64_t N, int32_t d, const double* E, int32_t k, con
     if (N < 1 || d < 1 || d > kMaxD || k < 1 || k > kMaxK || k > N || max_iter < 1 || !E || !init_idx ||
         !centres || !labels)
         return HROM_E_INVALID;
-    double *scale = nullptr, *C = nullptr;
+    double *scale = nullptr, *C = nullptr, *part = nullptr;
     int* changed = nullptr;
+    const int nchunks = (int)((N + kChunk - 1) / kChunk);
     if (hipMalloc((void**)&scale, sizeof(double) * d) != hipSuccess) return HROM_E_NOMEM;
     if (hipMalloc((void**)&C, sizeof(double) * k * d) != hipSuccess ||
-        hipMalloc((void**)&changed, sizeof(int)) != hipSuccess) {
+        hipMalloc((void**)&changed, sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&part, sizeof(double) * (size_t)nchunks * k * (d + 1)) != hipSuccess) {
         (void)hipFree(scale);
         (void)hipFree(C);
+        (void)hipFree(changed);
         return HROM_E_NOMEM;
     }
     int rc = HROM_OK, it = 0, hch = 1;
@@ -192,8 +221,10 @@ int hrom_training_clusters(int64_t N, int32_t d, const double* E, int32_t k, con
             rc = HROM_E_HIP;
             break;
         }
-        hipLaunchKernelGGL(k_km_assign, dim3(nb), dim3(256), 0, stream, E, N, d, k, scale, C, labels, changed);
-        hipLaunchKernelGGL(k_km_update, dim3(k), dim3(256), 0, stream, E, N, d, scale, labels, C);
+        hipLaunchKernelGGL(k_km_assign, dim3(nb), dim3(256), sizeof(double) * k * d, stream, E, N, d, k, scale, C,
+                           labels, changed);
+        hipLaunchKernelGGL(k_km_partial, dim3(nchunks), dim3(256), 0, stream, E, N, d, k, scale, labels, part);
+        hipLaunchKernelGGL(k_km_reduce, dim3((k * d + 255) / 256), dim3(256), 0, stream, part, nchunks, k, d, C);
         it++;
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(&hch, changed, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -207,6 +238,7 @@ int hrom_training_clusters(int64_t N, int32_t d, const double* E, int32_t k, con
     (void)hipFree(scale);
     (void)hipFree(C);
     (void)hipFree(changed);
+    (void)hipFree(part);
     if (iters) *iters = it;
     if (rc == HROM_OK && hch != 0) rc = HROM_E_NOCONV;
     return rc;
