@@ -158,7 +158,8 @@ def run_gpu(prec_name, cl, F, N, steps, warmup, split=True, refine=False, biot6=
                a=st.a.clone(),
                Pbar=st.Pbar.clone(),
                Cbar=st.Cbar.clone(), status=int(st.status.max().item()),
-               variant=tuned["variant"], tune_ms={str(k): v for k, v in tuned["ms"].items()})
+               variant=tuned["variant"], kin_variant=tuned["kin"], cond_variant=tuned["cond"],
+               tune_ms={str(k): v for k, v in tuned["ms"].items()})
     plan.close()
     del st
     torch.cuda.empty_cache()
@@ -716,7 +717,8 @@ def main():
                       "frac": CAUCHY_BYTES_PER_POINT * N / (res["cauchy_ms"] * 1e-3) / HBM_PEAK,
                       "traffic": read_cauchy_traffic(m, Q)},
         "status_max": res["status"],
-        "tuned_variant": res["variant"], "variant_eval_ms": res["tune_ms"],
+        "tuned_variant": res["variant"], "tuned_kin_variant": res["kin_variant"],
+        "tuned_condense_variant": res["cond_variant"], "variant_eval_ms": res["tune_ms"],
         "fp64": fp64,
         "cpu_baseline": cpu,
         "other_workloads": extras,

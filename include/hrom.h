@@ -239,6 +239,21 @@ int hrom_history(hrom_plan plan, int32_t which, double* out, hipStream_t stream)
 int32_t hrom_num_variants(void);
 int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant);
 
+/* Launch variants of the other kernels (autotuner hooks; results never change,
+ * only speed), per cluster c (-1: every cluster):
+ *  HROM_VK_TANGENT  the tangent contraction (same as hrom_plan_set_variant);
+ *  HROM_VK_KIN      the kinematics: 0 four wavefronts per 32-point workgroup
+ *                   (two workgroups per CU), 1 eight wavefronts;
+ *  HROM_VK_CONDENSE the register condensation: 0 the register budget of three
+ *                   wavefronts per SIMD, 1 of two (no spills) -- m <= 64 only,
+ *                   larger mode counts always run at two.
+ * hrom_num_kernel_variants returns the count of a kind (0 for an unknown one). */
+#define HROM_VK_TANGENT 0
+#define HROM_VK_KIN 1
+#define HROM_VK_CONDENSE 2
+int32_t hrom_num_kernel_variants(int32_t kind);
+int hrom_plan_set_kernel_variant(hrom_plan plan, int32_t kind, int32_t c, int32_t variant);
+
 /* Measurement hook (not part of the method): with enable != 0 every later
  * hrom_eval records two HIP events on its stream around the tangent
  * contraction (all tangent launches of a plan with several clusters, the

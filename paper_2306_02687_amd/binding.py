@@ -27,6 +27,7 @@ PT_JNONPOS, PT_NOT_SPD, PT_NOCONV, PT_NONFINITE, PT_NOREFINE = 1, 2, 4, 8, 16
 FP64, MIXED_BF16, MIXED_FP16 = 0, 1, 2
 OBJECTIVE, SPLIT, REFINE, J2, BIOT6 = 1, 2, 4, 8, 16
 OFF_A, OFF_KAA, OFF_KAF = 0, 1, 2
+VK_TANGENT, VK_KIN, VK_CONDENSE = 0, 1, 2
 
 EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_eval",
             "hrom_condense", "hrom_update", "hrom_newton", "hrom_backward", "hrom_strerror",
@@ -34,7 +35,8 @@ EXPORTED = ("hrom_plan_create", "hrom_plan_destroy", "hrom_plan_offset", "hrom_e
             "hrom_plan_tangent_ms", "hrom_cauchy", "hrom_newton_noalloc",
             "hrom_noalloc_scratch_bytes", "hrom_commit", "hrom_history", "hrom_biot",
             "hrom_ecm_training", "hrom_ecm_svd", "hrom_ecm_select", "hrom_training_clusters",
-            "hrom_training_paths", "hrom_pod")
+            "hrom_training_paths", "hrom_pod", "hrom_num_kernel_variants",
+            "hrom_plan_set_kernel_variant")
 E_SCRATCH, E_NOCONV, E_RANK = -6, -7, -8
 
 
@@ -73,6 +75,9 @@ def load(path: str = LIB_PATH):
     L.hrom_num_variants.argtypes = []
     L.hrom_num_variants.restype = i32
     L.hrom_plan_set_variant.argtypes = [P, i32, i32]
+    L.hrom_num_kernel_variants.argtypes = [i32]
+    L.hrom_num_kernel_variants.restype = i32
+    L.hrom_plan_set_kernel_variant.argtypes = [P, i32, i32, i32]
     L.hrom_plan_profile.argtypes = [P, i32]
     L.hrom_plan_tangent_ms.argtypes = [P, C.POINTER(C.c_float)]
     L.hrom_newton_noalloc.argtypes = [C.POINTER(_Cluster), i32, i64, i32, C.c_uint32, P, P, P, d,
@@ -292,6 +297,16 @@ class Plan:
     def set_variant(self, variant: int, cluster: int = -1):
         _check(load().hrom_plan_set_variant(self._h, int(cluster), int(variant)),
                "hrom_plan_set_variant")
+
+    def set_kernel_variant(self, kind: int, variant: int, cluster: int = -1):
+        """Launch variant of the kinematics (VK_KIN), the condensation
+        (VK_CONDENSE) or the tangent (VK_TANGENT) of one cluster or all."""
+        _check(load().hrom_plan_set_kernel_variant(self._h, int(kind), int(cluster), int(variant)),
+               "hrom_plan_set_kernel_variant")
+
+    @staticmethod
+    def num_kernel_variants(kind: int) -> int:
+        return int(load().hrom_num_kernel_variants(int(kind)))
 
     def profile(self, enable: bool = True):
         """Record HIP events around the tangent contraction of every eval."""

@@ -345,6 +345,28 @@ int hrom_plan_create(hrom_plan* out, const hrom_cluster* clusters, int32_t ncl, 
 
 int32_t hrom_num_variants(void) { return 6; }
 
+int32_t hrom_num_kernel_variants(int32_t kind) {
+    switch (kind) {
+        case HROM_VK_TANGENT: return hrom_num_variants();
+        case HROM_VK_KIN: return 2;
+        case HROM_VK_CONDENSE: return 2;
+        default: return 0;
+    }
+}
+
+int hrom_plan_set_kernel_variant(hrom_plan plan, int32_t kind, int32_t c, int32_t variant) {
+    if (kind == HROM_VK_TANGENT) return hrom_plan_set_variant(plan, c, variant);
+    if (!plan || variant < 0 || variant >= hrom_num_kernel_variants(kind) || c < -1 || c >= plan->p.ncl)
+        return HROM_E_INVALID;
+    Plan& p = plan->p;
+    for (int k = 0; k < p.ncl; k++) {
+        if (c >= 0 && c != k) continue;
+        if (kind == HROM_VK_KIN) p.cl[k].kin_variant = variant;
+        else p.cl[k].cond_variant = variant;
+    }
+    return HROM_OK;
+}
+
 int hrom_plan_set_variant(hrom_plan plan, int32_t c, int32_t variant) {
     if (!plan || variant < 0 || variant >= hrom_num_variants() || c < -1 || c >= plan->p.ncl) return HROM_E_INVALID;
     Plan& p = plan->p;
@@ -431,7 +453,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         e.kscale_out = c.kscale;
         e.hist_n = p.j2 ? p.hist_n + c.ws_hist : nullptr;
         e.hist_t = p.j2 ? p.hist_t + c.ws_hist : nullptr;
-        int rc = launch_kin(mixed(p) ? 1 : 0, p.j2 ? 1 : 0, e, stream);
+        int rc = launch_kin(mixed(p) ? 1 : 0, p.j2 ? 1 : 0, c.kin_variant, e, stream);
         if (rc != HROM_OK) return rc;
         if (p.grouped) {
             tan_args.push_back(e);
@@ -512,6 +534,7 @@ int hrom_condense(hrom_plan plan, double* Pbar, double* Cbar, double* rnorm, int
         ca.y = p.y + c.off_a; ca.X = p.X + (int64_t)p.nmac * c.off_a;
         ca.Palg = p.Palg; ca.Cr = p.Cr; ca.rnorm = p.rnorm; ca.status = status;
         ca.kscale = c.kscale;
+        ca.variant = c.cond_variant;
         // SPD path: register-resident elimination, one launch per cluster so
         // that each runs at the occupancy its mode count allows; non-positive
         // pivots finish on the LU path

@@ -42,6 +42,8 @@ struct ClusterDev {
     int64_t ws_qs;         // element offset of the cluster's per-ECM-point scalars
     int64_t ws_hist;       // J2: element offset of the cluster's history [count][Qpad][8]
     int variant;           // launch variant of the tangent contraction (autotuned)
+    int kin_variant;       // kinematics: 0 four, 1 eight wavefronts per 32-point workgroup
+    int cond_variant;      // condensation: 0 three, 1 two wavefronts per SIMD (m <= 80)
     double* Ghat;          // [Qpad][9][MP]  augmented [G | I_9 | 0] (FP64)
     double* GT;            // [Qpad/64][9][m][64]  G, ECM point fastest (FP64)
     double* Gf;            // [9 Qpad/16][KS][64]  A-operand fragments of the kinematics GEMM
@@ -156,7 +158,7 @@ struct EvalArgs {
     const double* hist_n;  // J2: committed state [count][Qpad][8] (cluster block)
     double* hist_t;        // J2: state of this evaluation [count][Qpad][8]
 };
-int launch_kin(int mixed, int j2, const EvalArgs& a, hipStream_t s);
+int launch_kin(int mixed, int j2, int variant, const EvalArgs& a, hipStream_t s);
 int launch_eval_f64(int MT, int variant, int j2, const EvalArgs& a, hipStream_t s);
 int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s);
 
@@ -177,6 +179,7 @@ struct CondenseArgs {
     double* rnorm;         // [N]
     int* status;
     const float* kscale;   // device: inverse of the mixed-mode scaling of w_q A_q
+    int variant;           // register condensation: 0 three, 1 two wavefronts per SIMD
     // optional exports (NULL = skip)
     double* outKaa;        // [m*m][count]
     double* outKaF;        // [m*9][count]

@@ -773,29 +773,36 @@ __device__ void condense_reg_body(const CondenseArgs& A, int64_t pl) {
     }
 }
 
-template <typename TT, int MB>
-__global__ void __launch_bounds__(64, MB <= 10 ? 3 : 2) k_condense_reg(CondenseArgs A) {
+// OCC: wavefronts per SIMD the register budget is cut for (3 lets a few
+// bytes spill at the largest blocks, 2 spills nothing); m > 64 always 2
+template <typename TT, int MB, int OCC>
+__global__ void __launch_bounds__(64, OCC) k_condense_reg(CondenseArgs A) {
     condense_reg_body<TT, MB>(A, xcd_order(blockIdx.x, A.count));
 }
 
 template <typename TT>
 static void launch_reg_t(const CondenseArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)a.count), block(64);
+    const bool o2 = a.variant == 1;
+#define HROM_REG(MB_)                                                                          \
+    if (o2 || (MB_) > 10) hipLaunchKernelGGL((k_condense_reg<TT, MB_, 2>), grid, block, 0, s, a); \
+    else hipLaunchKernelGGL((k_condense_reg<TT, MB_, (MB_) <= 10 ? 3 : 2>), grid, block, 0, s, a);
     switch ((a.m + 7) / 8) {
-        case 1: hipLaunchKernelGGL((k_condense_reg<TT, 3>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_condense_reg<TT, 4>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_condense_reg<TT, 5>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_condense_reg<TT, 6>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_condense_reg<TT, 7>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_condense_reg<TT, 8>), grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_condense_reg<TT, 9>), grid, block, 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_condense_reg<TT, 10>), grid, block, 0, s, a); break;
+        case 1: { HROM_REG(3) } break;
+        case 2: { HROM_REG(4) } break;
+        case 3: { HROM_REG(5) } break;
+        case 4: { HROM_REG(6) } break;
+        case 5: { HROM_REG(7) } break;
+        case 6: { HROM_REG(8) } break;
+        case 7: { HROM_REG(9) } break;
+        case 8: { HROM_REG(10) } break;
         // m = 65 .. 96: two wavefronts per SIMD
-        case 9: hipLaunchKernelGGL((k_condense_reg<TT, 11>), grid, block, 0, s, a); break;
-        case 10: hipLaunchKernelGGL((k_condense_reg<TT, 12>), grid, block, 0, s, a); break;
-        case 11: hipLaunchKernelGGL((k_condense_reg<TT, 13>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_condense_reg<TT, 14>), grid, block, 0, s, a); break;
+        case 9: { HROM_REG(11) } break;
+        case 10: { HROM_REG(12) } break;
+        case 11: { HROM_REG(13) } break;
+        default: { HROM_REG(14) } break;
     }
+#undef HROM_REG
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,28 +1018,33 @@ __device__ void condense6_reg_body(const CondenseArgs& A, int64_t pl) {
     }
 }
 
-template <typename TT, int MB>
-__global__ void __launch_bounds__(64, MB <= 10 ? 3 : 2) k_condense6_reg(CondenseArgs A) {
+template <typename TT, int MB, int OCC>
+__global__ void __launch_bounds__(64, OCC) k_condense6_reg(CondenseArgs A) {
     condense6_reg_body<TT, MB>(A, xcd_order(blockIdx.x, A.count));
 }
 
 template <typename TT>
 static void launch_reg6_t(const CondenseArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)a.count), block(64);
+    const bool o2 = a.variant == 1;
+#define HROM_REG6(MB_)                                                                          \
+    if (o2 || (MB_) > 10) hipLaunchKernelGGL((k_condense6_reg<TT, MB_, 2>), grid, block, 0, s, a); \
+    else hipLaunchKernelGGL((k_condense6_reg<TT, MB_, (MB_) <= 10 ? 3 : 2>), grid, block, 0, s, a);
     switch ((a.m + 7) / 8) {
-        case 1: hipLaunchKernelGGL((k_condense6_reg<TT, 2>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_condense6_reg<TT, 3>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_condense6_reg<TT, 4>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_condense6_reg<TT, 5>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_condense6_reg<TT, 6>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_condense6_reg<TT, 7>), grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_condense6_reg<TT, 8>), grid, block, 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_condense6_reg<TT, 9>), grid, block, 0, s, a); break;
-        case 9: hipLaunchKernelGGL((k_condense6_reg<TT, 10>), grid, block, 0, s, a); break;
-        case 10: hipLaunchKernelGGL((k_condense6_reg<TT, 11>), grid, block, 0, s, a); break;
-        case 11: hipLaunchKernelGGL((k_condense6_reg<TT, 12>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_condense6_reg<TT, 13>), grid, block, 0, s, a); break;
+        case 1: { HROM_REG6(2) } break;
+        case 2: { HROM_REG6(3) } break;
+        case 3: { HROM_REG6(4) } break;
+        case 4: { HROM_REG6(5) } break;
+        case 5: { HROM_REG6(6) } break;
+        case 6: { HROM_REG6(7) } break;
+        case 7: { HROM_REG6(8) } break;
+        case 8: { HROM_REG6(9) } break;
+        case 9: { HROM_REG6(10) } break;
+        case 10: { HROM_REG6(11) } break;
+        case 11: { HROM_REG6(12) } break;
+        default: { HROM_REG6(13) } break;
     }
+#undef HROM_REG6
 }
 
 int launch_condense_reg(const CondenseArgs& a, hipStream_t s) {

@@ -338,25 +338,39 @@ __global__ void __launch_bounds__(256, 2) k_kin(EvalArgs A) {
     kin_body<MIXED, MA, 4, 16 * MA, J2>(A, (int64_t)blockIdx.x * kKinPT, L);
 }
 
-template <bool MIXED, bool J2>
-static void launch_kin_t(const EvalArgs& a, hipStream_t s) {
-    const dim3 grid(nblocks(a.count, kKinPT)), block(256);
-    switch ((a.m + 15) / 16) {
-        case 1: hipLaunchKernelGGL((k_kin<MIXED, 1, J2>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_kin<MIXED, 2, J2>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_kin<MIXED, 3, J2>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_kin<MIXED, 4, J2>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_kin<MIXED, 5, J2>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_kin<MIXED, 6, J2>), grid, block, 0, s, a); break;
-    }
+// the same 32 points per workgroup on eight wavefronts (row tiles w and
+// w + 8, the k-range partials of the ninth tile unchanged: the same bits)
+template <bool MIXED, int MA, bool J2>
+__global__ void __launch_bounds__(512, 1) k_kin8(EvalArgs A) {
+    __shared__ KinLds<16 * MA> L;
+    kin_body<MIXED, MA, 8, 16 * MA, J2>(A, (int64_t)blockIdx.x * kKinPT, L);
 }
 
-int launch_kin(int mixed, int j2, const EvalArgs& a, hipStream_t s) {
+template <bool MIXED, bool J2, bool W8>
+static void launch_kin_t(const EvalArgs& a, hipStream_t s) {
+    const dim3 grid(nblocks(a.count, kKinPT)), block(W8 ? 512 : 256);
+#define HROM_KIN(MA_)                                                                  \
+    if constexpr (W8) hipLaunchKernelGGL((k_kin8<MIXED, MA_, J2>), grid, block, 0, s, a); \
+    else hipLaunchKernelGGL((k_kin<MIXED, MA_, J2>), grid, block, 0, s, a);
+    switch ((a.m + 15) / 16) {
+        case 1: { HROM_KIN(1) } break;
+        case 2: { HROM_KIN(2) } break;
+        case 3: { HROM_KIN(3) } break;
+        case 4: { HROM_KIN(4) } break;
+        case 5: { HROM_KIN(5) } break;
+        default: { HROM_KIN(6) } break;
+    }
+#undef HROM_KIN
+}
+
+// variant 0: four wavefronts per workgroup (two workgroups per CU), 1: eight
+int launch_kin(int mixed, int j2, int variant, const EvalArgs& a, hipStream_t s) {
     if ((a.m + 15) / 16 > 6) return HROM_E_UNSUPPORTED;
     if (j2 && mixed) return HROM_E_UNSUPPORTED;
-    if (j2) launch_kin_t<false, true>(a, s);
-    else if (mixed) launch_kin_t<true, false>(a, s);
-    else launch_kin_t<false, false>(a, s);
+    const bool w8 = variant == 1;
+    if (j2) w8 ? launch_kin_t<false, true, true>(a, s) : launch_kin_t<false, true, false>(a, s);
+    else if (mixed) w8 ? launch_kin_t<true, false, true>(a, s) : launch_kin_t<true, false, false>(a, s);
+    else w8 ? launch_kin_t<false, false, true>(a, s) : launch_kin_t<false, false, false>(a, s);
     return HROM_OK;
 }
 
