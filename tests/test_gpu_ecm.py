@@ -175,6 +175,42 @@ def test_selection_past_256_points_against_stored_oracle(dev):
           f"NNLS {int(trace[:, 1].sum())}", flush=True)
 
 
+def test_selection_maximum_size(dev, orc):
+    """The largest selection the step kernel holds: r + 1 = 1024 rows and
+    mt = 1024 points (every position array and the triangular solve at full
+    length).  The first 100 iterations equal the oracle's; the final rule is
+    exact on its truncated system with positive weights summing to V0, and the
+    last NNLS (if any) meets the optimality conditions."""
+    from paper_2306_02687_amd import binding as B
+    log_case("ecm maximum size")
+    m, M, p, mt = 16, 6000, 48, 1024
+    cl, xf_o, lam_o, s_o, lam, sig, _ = _chains(dev, orc, m, M, p, mt, 9900)
+    V0 = float(cl.w.sum())
+    z, w, info = B.ecm_select(lam, V0, mt, trace_cap=8 * M)
+    trace = info["trace"].cpu().numpy()
+    z_o, w_o, info_o = orc.ecm_greedy(lam_o, V0, 100)
+    # the spectrum is dense at the truncation (relative gap ~1e-7), so the two
+    # truncated subspaces differ by up to ~1e-13 / gap and so may the scores
+    gap = (s_o[mt - 2] - s_o[mt - 1]) / s_o[0]
+    tie = max(1e-8, 1e-13 / gap)
+    for i in range(len(info_o["picked"])):
+        rec_o = (info_o["picked"][i], int(info_o["nnls"][i]), len(info_o["dropped"][i]))
+        rec = tuple(int(v) for v in trace[i][:3])
+        if rec != rec_o:
+            assert info_o["gap"][i] < tie, (i, rec, rec_o, info_o["gap"][i], tie)
+            break
+    z, w = z.cpu().numpy(), w.cpu().numpy()
+    lamc = lam.cpu().numpy()
+    J = np.vstack([lamc.T, np.ones((1, M))])
+    b = np.zeros(mt)
+    b[-1] = V0
+    print(f"maximum size: iterations {info['iters']} NNLS {int(trace[:, 1].sum())} "
+          f"dropped {int(trace[:, 2].sum())} residual {np.linalg.norm(J[:, z] @ w - b):.2e}", flush=True)
+    assert len(z) == mt and len(set(z.tolist())) == mt and np.all(w > 0)
+    assert np.linalg.norm(J[:, z] @ w - b) < 1e-9 * V0
+    assert abs(w.sum() - V0) < 1e-11 * V0
+
+
 def test_selection_edge_cases(dev, orc):
     from paper_2306_02687_amd import binding as B
     log_case("ecm edge cases")
