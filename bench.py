@@ -406,12 +406,13 @@ def oracle_errors(m=64, Q=512, n=12, amps=(0.01, 0.05, 0.2), precision="bf16"):
     return out
 
 
-def run_j2(args, quiet=False):
+def run_j2(args, quiet=False, precision="fp64"):
     """J2 plasticity (the Example 1 material) at the sizes of the paper's
     Example 1 hyper ROM, m = 8 modes, Q = 250 ECM points, over 262144 macro
     points: a load-unload path of macro states; per state a fixed-count
     device-side micro Newton (evaluate + condense + update) and a commit of
-    the history.  FP64 path."""
+    the history.  precision: fp64, or bf16 / fp16 (split tangent
+    contraction; the law, the history and the residual in FP64)."""
     import torch
 
     import paper_2306_02687_amd as P
@@ -425,7 +426,7 @@ def run_j2(args, quiet=False):
     path = make_load_path(N, 4901, amp=0.03, levels=levels)
     Fk = [solve.points_to_soa(x) for x in path]
     del path
-    plan = P.Plan([solve.upload_cluster(cl, N)], j2=True)
+    plan = P.Plan([solve.upload_cluster(cl, N)], j2=True, precision=PREC[precision])
     plan.profile(True)
     th = solve.theta_dev(MAT_J2)
     a = plan.zeros_modes()
@@ -451,7 +452,7 @@ def run_j2(args, quiet=False):
     evals = N * its * len(levels)
     line = {"metric": "RVE point-evals/s, J2 plasticity with history (Example 1 material)",
             "value": evals / dt, "unit": "point-evals/s", "n_gpus": 1,
-            "ms_per_path": dt * 1e3, "higher_is_better": True, "dtype": "fp64",
+            "ms_per_path": dt * 1e3, "higher_is_better": True, "dtype": precision,
             "data": "synthetic",
             "config": {"workload": f"{N} macro points, m={m} ROM modes, Q={Q} ECM points, "
                                    f"load-unload path of {len(levels)} macro states, {its} "
@@ -612,7 +613,7 @@ def main():
                                      precision=args.precision)), flush=True)
         return
     if args.workload == "j2":
-        run_j2(args)
+        run_j2(args, precision=args.precision)
         return
     if args.workload == "ecm":
         run_ecm(args)
@@ -688,6 +689,7 @@ def main():
         extras["monolithic_32_256"] = run_monolithic()
         print("[bench] extra: J2 plasticity path", file=sys.stderr, flush=True)
         extras["j2_8_250"] = run_j2(args, quiet=True)
+        extras["j2_8_250_" + args.precision] = run_j2(args, quiet=True, precision=args.precision)
         extras["offline_ecm_m30_500_of_32768"] = run_ecm(args, quiet=True)
 
     line = {

@@ -88,7 +88,8 @@ extern "C" {
 #define HROM_SPLIT 2u        /* mixed modes: hi/lo split operands (3 MFMA terms); required */
 #define HROM_J2 8u           /* material: small-strain J2 plasticity with linear isotropic
                                 hardening and history at the ECM points (Sec. 5 Example 1,
-                                Sec. 4); FP64 plans only; theta = device [8] */
+                                Sec. 4); FP64 or mixed (split) plans, the law and the
+                                history in FP64; theta = device [8] */
 #define HROM_BIOT6 16u       /* objective plans: condense only the six coordinates of the
                                 symmetric stretch (KaU = KaF E6, six right-hand sides; the
                                 paper's Biot form, Sec. 3.2.2-3.2.3): the same Pbar, Cbar,

@@ -73,8 +73,6 @@ int plan_geometry(Plan& p, const hrom_cluster* clusters, int32_t ncl, int64_t N,
     // a single low-precision term per product misses the 1e-5 accuracy of the
     // mixed path (and makes Kaa indefinite when some modes are soft)
     if (precision != HROM_FP64 && !(flags & HROM_SPLIT)) return HROM_E_UNSUPPORTED;
-    // J2 plasticity runs on the FP64 path
-    if ((flags & HROM_J2) && precision != HROM_FP64) return HROM_E_UNSUPPORTED;
     // the six-component condensation condenses the symmetric stretch of the objective split
     if ((flags & HROM_BIOT6) && !(flags & HROM_OBJECTIVE)) return HROM_E_UNSUPPORTED;
     int64_t next = 0;
@@ -461,7 +459,8 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
         }
         // single-cluster plans: the events bracket the (only) tangent launch
         if (p.profile) (void)hipEventRecord(p.ev_tan[0], stream);
-        rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, c.variant, e, stream)
+        rc = mixed(p) ? launch_eval_mixed(c.MT, p.prec, (p.flags & HROM_SPLIT) != 0, c.variant, p.j2 ? 1 : 0, e,
+                                          stream)
                       : launch_eval_f64(c.MT, c.variant, p.j2 ? 1 : 0, e, stream);
         if (p.profile) (void)hipEventRecord(p.ev_tan[1], stream);
         if (rc != HROM_OK) return rc;
@@ -481,7 +480,7 @@ int hrom_eval(hrom_plan plan, const double* theta, const double* Fbar, const dou
             rc = launch_tan_persistent(g, p.persistent_grid, stream);
         } else {
             for (int k = 0; k < p.ncl && rc == HROM_OK; k++)
-                rc = launch_eval_mixed(p.cl[k].MT, p.prec, (p.flags & HROM_SPLIT) != 0, p.cl[k].variant,
+                rc = launch_eval_mixed(p.cl[k].MT, p.prec, (p.flags & HROM_SPLIT) != 0, p.cl[k].variant, 0,
                                        tan_args[k], stream);
         }
         if (p.profile) (void)hipEventRecord(p.ev_tan[1], stream);

@@ -160,7 +160,7 @@ struct EvalArgs {
 };
 int launch_kin(int mixed, int j2, int variant, const EvalArgs& a, hipStream_t s);
 int launch_eval_f64(int MT, int variant, int j2, const EvalArgs& a, hipStream_t s);
-int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s);
+int launch_eval_mixed(int MT, int prec, bool split, int variant, int j2, const EvalArgs& a, hipStream_t s);
 
 struct CondenseArgs {
     int m, MT, res_t, res_c;

@@ -88,10 +88,11 @@ struct KinLds {
 };
 
 // the 32 macro points p0 .. p0+31 of the cluster described by A; MA = ceil(m / 16);
-// J2: small-strain J2 plasticity with history in place of Neo-Hooke (FP64 only)
+// J2: small-strain J2 plasticity with history in place of Neo-Hooke (the
+// history and the law in FP64 on both paths; the mixed path stores the nine
+// tangent scalars in FP32)
 template <bool MIXED, int MA, int NW, int AR, bool J2 = false>
 __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
-    static_assert(!(MIXED && J2), "J2 plasticity runs on the FP64 path");
     constexpr int PT = kKinPT, QC = 16, NT = 64 * NW;
     static_assert(AR >= 16 * MA, "mode amplitude rows");
     static_assert(NW == 4 || NW == 8, "four or eight wavefronts");
@@ -130,7 +131,9 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
     // units of the moduli (FP16 range); the condensation divides it out
     float wscale = 1.0f;
     if (MIXED) {
-        const double mx = fmax(fmax(fabs(mu0), fabs(la0)), fmax(fabs(mu1), fabs(la1)));
+        // J2 plans: theta = per phase (mu, lam, sy0, H), the moduli at 0, 1, 4, 5
+        const double mx = J2 ? fmax(fmax(fabs(A.theta[0]), fabs(A.theta[1])), fmax(fabs(A.theta[4]), fabs(A.theta[5])))
+                             : fmax(fmax(fabs(mu0), fabs(la0)), fmax(fabs(mu1), fabs(la1)));
         const int e = (mx > 0.0 && isfinite(mx)) ? ilogb(mx) + 1 : 0;
         wscale = ldexpf(1.0f, A.qexp + 4 - e);
     }
@@ -220,11 +223,26 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
 #pragma unroll
                 for (int I = 0; I < 9; I++) sWP[qq * 9 + I][p] = live ? wq * sig[I] : 0.0;
                 if (p < np) {
-                    double* o = (double*)A.qs + ((p0 + p) * A.Qpad + q) * 12;
+                    const int64_t off = ((p0 + p) * A.Qpad + q) * 12;
+                    if constexpr (MIXED) {
+                        // (w kappa, w 2 mu th, w 2 mu thb) scaled like the Neo-Hooke scalars, then n
+                        const float ws = wscale;
+                        float* o = (float*)A.qs + off;
+                        v4f v0 = v4f{(float)(wq * t[0]) * ws, (float)(wq * t[1]) * ws, (float)(wq * t[2]) * ws,
+                                     (float)t[3]};
+                        v4f v1 = v4f{(float)t[4], (float)t[5], (float)t[6], (float)t[7]};
+                        v4f v2 = v4f{(float)t[8], 0.f, 0.f, 0.f};
+                        if (!live) v0 = v1 = v2 = v4f{0.f, 0.f, 0.f, 0.f};
+                        *(v4f*)(o) = v0;
+                        *(v4f*)(o + 4) = v1;
+                        *(v4f*)(o + 8) = v2;
+                    } else {
+                        double* o = (double*)A.qs + off;
 #pragma unroll
-                    for (int k = 0; k < 3; k++) o[k] = live ? wq * t[k] : 0.0;
+                        for (int k = 0; k < 3; k++) o[k] = live ? wq * t[k] : 0.0;
 #pragma unroll
-                    for (int k = 3; k < 12; k++) o[k] = (live && k < 9) ? t[k] : 0.0;
+                        for (int k = 3; k < 12; k++) o[k] = (live && k < 9) ? t[k] : 0.0;
+                    }
                     if (live) {
 #pragma unroll
                         for (int k = 0; k < 7; k++) A.hist_t[ho + k] = ht[k];
@@ -366,9 +384,9 @@ static void launch_kin_t(const EvalArgs& a, hipStream_t s) {
 // variant 0: four wavefronts per workgroup (two workgroups per CU), 1: eight
 int launch_kin(int mixed, int j2, int variant, const EvalArgs& a, hipStream_t s) {
     if ((a.m + 15) / 16 > 6) return HROM_E_UNSUPPORTED;
-    if (j2 && mixed) return HROM_E_UNSUPPORTED;
     const bool w8 = variant == 1;
-    if (j2) w8 ? launch_kin_t<false, true, true>(a, s) : launch_kin_t<false, true, false>(a, s);
+    if (j2 && mixed) w8 ? launch_kin_t<true, true, true>(a, s) : launch_kin_t<true, true, false>(a, s);
+    else if (j2) w8 ? launch_kin_t<false, true, true>(a, s) : launch_kin_t<false, true, false>(a, s);
     else if (mixed) w8 ? launch_kin_t<true, false, true>(a, s) : launch_kin_t<true, false, false>(a, s);
     else w8 ? launch_kin_t<false, false, true>(a, s) : launch_kin_t<false, false, false>(a, s);
     return HROM_OK;
@@ -653,7 +671,7 @@ __device__ __forceinline__ v4u32 t_operand(v4f T, uint32_t g1) {
 // NP macro points per wavefront (1 or 2): with two, both points' products
 // take the same mode fragments, so each fragment is fetched once for two
 // points (half the fragment traffic through the CU's load path).
-template <int MA, int PREC, bool SPLIT, bool PF, int NP = 1>
+template <int MA, int PREC, bool SPLIT, bool PF, int NP = 1, bool J2 = false>
 __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ * kWR]) {
     constexpr int NA = MA * (MA + 1) / 2;
     constexpr int QR = kCQ / NP;   // ECM points per LDS round
@@ -710,7 +728,38 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
     for (int q0 = 0; q0 < A.Qpad; q0 += QR) {
         // ---- W rows of this round: lane (pb, qq, u < 3) builds the rows
         // (i, j) = (u, 0..2) of W_{q0+qq} of point pb; the lanes u = 3 build none
-        {
+        if constexpr (J2) {
+            // J2 tangent rows (i, j) = (u, 0..2) from the scalars
+            // (w kappa, w 2 mu th, w 2 mu thb, n xx yy zz xy yz xz):
+            //   W[(i,j)][(k,l)] = w kappa d_ij d_kl + w 2 mu th (sym(d_ik d_jl) - d_ij d_kl / 3)
+            //                     - w 2 mu thb n_ij n_kl
+            const v4f* src = (const v4f*)(qsp + (int64_t)(q0 + qq) * 12);
+            const v4f x0 = src[0], x1 = src[1], x2 = src[2];
+            const float a0 = x0[0], a1 = x0[1], a2 = x0[2];
+            const float nv[6] = {x0[3], x1[0], x1[1], x1[2], x1[3], x2[0]};
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const float nij = (u == 0) ? nv[j2_slot(0, j)] : ((u == 1) ? nv[j2_slot(1, j)] : nv[j2_slot(2, j)]);
+                float w[9];
+#pragma unroll
+                for (int k = 0; k < 3; k++)
+#pragma unroll
+                    for (int l = 0; l < 3; l++) {
+                        float v = -a2 * nij * nv[j2_slot(k, l)];
+                        if (u == j && k == l) v += a0 - a1 * (1.0f / 3.0f);
+                        if (u == k && j == l) v += 0.5f * a1;
+                        if (u == l && j == k) v += 0.5f * a1;
+                        w[3 * k + l] = v;
+                    }
+                v4u32 rec[4];
+                w_records<PREC, SPLIT>(w, rec);
+                if (u < 3) {
+                    v4u32* dst = sw + (pb * QR + qq) * kWR + 4 * (3 * u + j);
+#pragma unroll
+                    for (int gg = 0; gg < 4; gg++) dst[gg] = rec[gg];
+                }
+            }
+        } else {
             const v4f* src = (const v4f*)(qsp + (int64_t)(q0 + qq) * 12);
             const v4f x0 = src[0], x1 = src[1], x2 = src[2];
             const float F[9] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3], x2[0]};
@@ -837,10 +886,26 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
 // OCC4: ask for four wavefronts per SIMD (register cap 128; one point per
 // wavefront fits three without asking);
 // NP: macro points per wavefront
-template <int MA, int PREC, bool SPLIT, bool PF, bool OCC4, int NP>
+template <int MA, int PREC, bool SPLIT, bool PF, bool OCC4, int NP, bool J2 = false>
 __global__ void __launch_bounds__(256, (OCC4 && MA <= 4 && NP == 1) ? 4 : 2) k_eval_mixed(EvalArgs A) {
     __shared__ v4u32 s_w[4][kCQ * kWR];
-    tan_mixed_body<MA, PREC, SPLIT, PF, NP>(A, (int64_t)blockIdx.x * (4 * NP), s_w);
+    tan_mixed_body<MA, PREC, SPLIT, PF, NP, J2>(A, (int64_t)blockIdx.x * (4 * NP), s_w);
+}
+
+// J2 plans: one launch shape (one point per wavefront, no prefetch)
+template <int PREC>
+static int launch_mixed_j2(const EvalArgs& a, hipStream_t s) {
+    const dim3 grid(nblocks(a.count, 4)), block(256);
+    switch ((a.m + 15) / 16) {
+        case 1: hipLaunchKernelGGL((k_eval_mixed<1, PREC, true, false, false, 1, true>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_eval_mixed<2, PREC, true, false, false, 1, true>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_eval_mixed<3, PREC, true, false, false, 1, true>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_eval_mixed<4, PREC, true, false, false, 1, true>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_eval_mixed<5, PREC, true, false, false, 1, true>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_eval_mixed<6, PREC, true, false, false, 1, true>), grid, block, 0, s, a); break;
+        default: return HROM_E_UNSUPPORTED;
+    }
+    return HROM_OK;
 }
 
 template <int PREC, bool SPLIT, bool PF, bool OCC4, int NP>
@@ -874,9 +939,14 @@ static int launch_mixed_v(int variant, const EvalArgs& a, hipStream_t s) {
 // variants 0..3: bit 0 three wavefronts per SIMD instead of two, bit 1 no
 // prefetch; 4, 5: two macro points per wavefront (without, with prefetch)
 // (mixed plans require split operands: plan creation rejects single-term ones)
-int launch_eval_mixed(int MT, int prec, bool split, int variant, const EvalArgs& a, hipStream_t s) {
+int launch_eval_mixed(int MT, int prec, bool split, int variant, int j2, const EvalArgs& a, hipStream_t s) {
     (void)MT;
     if (!split) return HROM_E_UNSUPPORTED;
+    if (j2) {
+        if (prec == HROM_MIXED_BF16) return launch_mixed_j2<HROM_MIXED_BF16>(a, s);
+        if (prec == HROM_MIXED_FP16) return launch_mixed_j2<HROM_MIXED_FP16>(a, s);
+        return HROM_E_INVALID;
+    }
     if (prec == HROM_MIXED_BF16) return launch_mixed_v<HROM_MIXED_BF16, true>(variant, a, s);
     if (prec == HROM_MIXED_FP16) return launch_mixed_v<HROM_MIXED_FP16, true>(variant, a, s);
     return HROM_E_INVALID;

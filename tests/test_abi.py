@@ -46,8 +46,8 @@ def test_strerror_and_invalid_arguments_without_gpu():
     assert lib.hrom_plan_create(ctypes.byref(h), arr, 1, 10, 7, 1) == -1
     # the six-component condensation needs the objective split
     assert lib.hrom_plan_create(ctypes.byref(h), arr, 1, 10, 0, 16) == -5
-    # J2 plasticity runs on the FP64 path only
-    assert lib.hrom_plan_create(ctypes.byref(h), arr, 1, 10, 1, 1 | 2 | 8) == -5
+    # J2 plasticity on the mixed path needs the split operands like any mixed plan
+    assert lib.hrom_plan_create(ctypes.byref(h), arr, 1, 10, 1, 1 | 8) == -5
     # mixed precision without split operands misses the accuracy contract
     assert lib.hrom_plan_create(ctypes.byref(h), arr, 1, 10, 1, 1) == -5
     assert lib.hrom_plan_create(ctypes.byref(h), arr, 1, 10, 2, 1 | 4) == -5

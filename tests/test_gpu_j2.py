@@ -7,6 +7,10 @@ history at the ECM points, Sec. 4) against the FP64 oracle, bar 1e-12.
 * a load-unload path of macro states with micro Newton and commits, two
   clusters in one plan, both frames: Pbar, Cbar and the committed history at
   every state;
+* the same path and blocks on the mixed BF16 / FP16 path (law, history,
+  residual and condensation in FP64, the tangent contraction in split
+  low-precision MFMA): Pbar and the history within 1e-9 (the Newton tolerance),
+  Cbar and the raw tangent blocks within 1e-5, r and Pr within 1e-12;
 * the device-side hrom_newton and the host loop agree bitwise on J2;
 * call rules: commit before any evaluation, backward on a J2 plan, commit or
   history on a plan without J2.
@@ -32,10 +36,14 @@ def dev():
     return P
 
 
-def _plan(dev, cls_counts, objective=True):
+def _plan(dev, cls_counts, objective=True, precision=0):
     from paper_2306_02687_amd import solve
     return dev.Plan([solve.upload_cluster(c, n) for c, n in cls_counts], objective=objective,
-                    j2=True)
+                    j2=True, precision=precision)
+
+
+# per precision: bars of (Pbar, Cbar, history)
+BARS = {0: (TOL64, TOL64, TOL64), 1: (1e-9, 1e-5, 1e-9), 2: (1e-9, 1e-5, 1e-9)}
 
 
 def _run_path(dev, plan, path, tol=1e-10):
@@ -54,20 +62,27 @@ def _run_path(dev, plan, path, tol=1e-10):
     return out
 
 
-@pytest.mark.parametrize("objective", [True, False])
-def test_j2_load_path_two_clusters(dev, orc, objective):
-    log_case("j2 path", objective)
+@pytest.mark.parametrize("objective,precision", [(True, 0), (False, 0), (True, 1), (False, 2)])
+def test_j2_load_path_two_clusters(dev, orc, objective, precision):
+    log_case("j2 path", objective, precision)
     shapes = [(8, 64, 7), (13, 37, 5)]
     cls = [make_cluster(m, Q, 4500 + m) for m, Q, _ in shapes]
     Ns = [n for _, _, n in shapes]
     N = sum(Ns)
     path = make_load_path(N, 4510, amp=0.03)
-    plan = _plan(dev, list(zip(cls, Ns)), objective=objective)
-    got = _run_path(dev, plan, path)
+    plan = _plan(dev, list(zip(cls, Ns)), objective=objective, precision=precision)
+    # every converged state is only as close to the solution as |Kaa^-1| tol
+    # (small near plastic flow); the FP64 path retraces the oracle's iterates,
+    # the mixed one does not, so both sides of a mixed comparison converge to
+    # 1e-12 (the condensed stress is second order in that error, the history
+    # first order)
+    tol = 1e-10 if precision == 0 else 1e-12
+    got = _run_path(dev, plan, path, tol=tol)
+    bP, bC, bh = BARS[precision]
     first = 0
     refs = []
     for c, n in zip(cls, Ns):
-        refs.append(orc.j2_path(c, MAT_J2, path[:, first:first + n], tol=1e-10,
+        refs.append(orc.j2_path(c, MAT_J2, path[:, first:first + n], tol=tol,
                                 objective=objective))
         first += n
     yielded = False
@@ -81,25 +96,27 @@ def test_j2_load_path_two_clusters(dev, orc, objective):
             eC = rel_err_points(Cg[first:first + n], ref["Cbar"].reshape(n, -1))
             eh = np.abs(hg[ci] - ref["hist"]).max() / max(np.abs(ref["hist"]).max(), 1e-300)
             yielded |= bool(ref["hist"][:, :, 6].max() > 0)
-            print(f"j2 state {k} cluster {ci}: Pbar {eP.max():.2e} Cbar {eC.max():.2e} hist {eh:.2e} "
-                  f"alpha max {ref['hist'][:, :, 6].max():.3e}", flush=True)
-            assert eP.max() < TOL64 and eC.max() < TOL64 and eh < TOL64
+            print(f"j2 prec {precision} state {k} cluster {ci}: Pbar {eP.max():.2e} Cbar {eC.max():.2e} "
+                  f"hist {eh:.2e} alpha max {ref['hist'][:, :, 6].max():.3e}", flush=True)
+            assert eP.max() < bP and eC.max() < bC and eh < bh
             first += n
     assert yielded
     plan.close()
 
 
-def test_j2_blocks_from_committed_history(dev, orc):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_j2_blocks_from_committed_history(dev, orc, precision):
     """Raw blocks and the evaluated history at random amplitudes, starting
     from the history committed after two states of a load path."""
     from paper_2306_02687_amd import solve
-    log_case("j2 blocks")
+    log_case("j2 blocks", precision)
     m, Q, N = 16, 96, 6
     cl = make_cluster(m, Q, 4600)
     path = make_load_path(N, 4601, amp=0.03, levels=(0.6, 1.0))
-    plan = _plan(dev, [(cl, N)], objective=False)
-    _run_path(dev, plan, path)
-    ref_path = orc.j2_path(cl, MAT_J2, path, tol=1e-10, objective=False)
+    plan = _plan(dev, [(cl, N)], objective=False, precision=precision)
+    tol = 1e-10 if precision == 0 else 1e-12
+    _run_path(dev, plan, path, tol=tol)
+    ref_path = orc.j2_path(cl, MAT_J2, path, tol=tol, objective=False)
     hist_n = ref_path[-1]["hist"]
     assert hist_n[:, :, 6].max() > 0
     F = path[-1] + 0.01 * np.random.default_rng(4602).standard_normal((N, 3, 3))
@@ -121,14 +138,17 @@ def test_j2_blocks_from_committed_history(dev, orc):
                KFF=KFF.cpu().numpy().T)
     for k in ("r", "Pr", "Kaa", "KaF", "KFF"):
         e = rel_err_points(got[k], ref[k].reshape(N, -1))
-        print("j2 block", k, e.max(), flush=True)
-        assert e.max() < TOL64, k
+        print("j2 block", precision, k, e.max(), flush=True)
+        bar = TOL64 if (precision == 0 or k in ("r", "Pr")) else 1e-5
+        assert e.max() < bar, k
+    # the committed history came from a path converged to 1e-10 on either path
+    hb = TOL64 if precision == 0 else 1e-9
     ht = plan.history(1)[0].cpu().numpy()
-    assert np.abs(ht - ref["hist"]).max() < TOL64 * np.abs(ref["hist"]).max()
+    assert np.abs(ht - ref["hist"]).max() < hb * np.abs(ref["hist"]).max()
     assert np.any(ref["hist"] != hist_n)                         # this state flows further
     # the committed history is untouched by the evaluation
     hn = plan.history(0)[0].cpu().numpy()
-    assert np.abs(hn - hist_n).max() < TOL64 * np.abs(hist_n).max()
+    assert np.abs(hn - hist_n).max() < hb * np.abs(hist_n).max()
     plan.close()
 
 
