@@ -149,8 +149,13 @@ size_t plan_carve(Plan& p, char* base) {
         take(d.Gf, (int64_t)d.Qpad * 9 / 16 * d.KS * 64);
         take(d.w, d.Qpad);
         take(d.phase, d.Qpad);
-        if (mx) take(d.Fpk, (int64_t)d.Qpad * ((d.m + 15) / 16) * 512);
-        else d.Fpk = nullptr;
+        if (mx) {
+            take(d.Fpk, (int64_t)d.Qpad * ((d.m + 15) / 16) * 512);
+            take(d.Gb3, (int64_t)d.Qpad * 9 / 16 * gb3_halves(d.m) * 3 * 64 * 4);
+        } else {
+            d.Fpk = nullptr;
+            d.Gb3 = nullptr;
+        }
         take(d.gram, (int64_t)d.m * d.m);
         take(d.R, (int64_t)d.m * d.m);
         take(d.Rinv, (int64_t)d.m * d.m);
@@ -211,7 +216,7 @@ void plan_build(const Plan& p, const hrom_cluster* clusters, hipStream_t s) {
         la.m = d.m; la.Q = d.Q; la.Qpad = d.Qpad; la.MT = d.MT; la.MP = d.MP; la.prec = p.prec;
         la.G = d.Gt; la.w = k.w; la.phase = k.phase;
         la.Ghat = d.Ghat; la.GT = d.GT; la.Gf = d.Gf; la.KS = d.KS; la.wpad = d.w; la.phpad = d.phase;
-        la.Fpk = d.Fpk; la.split = (p.flags & HROM_SPLIT) ? 1 : 0;
+        la.Fpk = d.Fpk; la.Gb3 = d.Gb3; la.split = (p.flags & HROM_SPLIT) ? 1 : 0;
         launch_build_layouts(la, s);
     }
 }
@@ -675,7 +680,8 @@ int hrom_backward(hrom_plan plan, const double* theta, const double* a, const do
         BackwardArgs ba{};
         ba.m = c.m; ba.Q = c.Q; ba.Qpad = c.Qpad; ba.mixed = mixed(p); ba.objective = objective;
         ba.first = c.first; ba.count = c.count; ba.N = p.N;
-        ba.GT = c.GT; ba.Ghat = c.Ghat; ba.Gf = c.Gf; ba.MP = c.MP; ba.MT = c.MT; ba.KS = c.KS;
+        ba.GT = c.GT; ba.Ghat = c.Ghat; ba.Gf = c.Gf; ba.Gb3 = c.Gb3; ba.MP = c.MP; ba.MT = c.MT;
+        ba.KS = c.KS;
         ba.w = c.w; ba.phase = c.phase;
         ba.theta = theta; ba.Fr = p.Fr; ba.a = p.at + c.off_a; ba.lam = p.lam + c.off_a;
         ba.gr = p.gr; ba.hr = p.hr; ba.gth = p.gth; ba.rho = p.rho + c.off_a; ba.status = status;

@@ -30,6 +30,24 @@ constexpr int kQChunk = 64;     // ECM points per phase-A chunk (one per lane)
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// Three BF16 levels of an FP64 value: x = hi + mid + lo + O(2^-27 |x|), each
+// level the round-to-nearest-even BF16 of what the levels before it leave
+// (the remainders formed in FP64).  Products of two such splits keep the six
+// level pairs (hh, hm, mh, hl, lh, mm) for FP32-level accuracy.
+__device__ __forceinline__ uint16_t bf16_rne_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ void bf16_split3(double x, uint16_t lv[3]) {
+    lv[0] = bf16_rne_bits((float)x);
+    const double r1 = x - (double)__uint_as_float((uint32_t)lv[0] << 16);
+    lv[1] = bf16_rne_bits((float)r1);
+    const double r2 = r1 - (double)__uint_as_float((uint32_t)lv[1] << 16);
+    lv[2] = bf16_rne_bits((float)r2);
+}
+__host__ __device__ inline int gb3_halves(int m) { return (m + 31) / 32; }
+
 // Device-side description of one RVE cluster, in the layouts the kernels read.
 struct ClusterDev {
     int m, Q, Qpad;        // Qpad: Q rounded up to a multiple of 64
@@ -51,6 +69,8 @@ struct ClusterDev {
     double* w;             // [Qpad] (zero padded)
     int* phase;            // [Qpad]
     uint16_t* Fpk;         // [Qpad][MA][64][8] packed low-precision fragments of G (mixed path)
+    uint32_t* Gb3;         // [9 Qpad/16][NH][3][64][4]  BF16 three-level A fragments of the
+                           // mixed adjoint GEMM, NH = ceil(m / 32) halves of 32 modes (mixed path)
     // mode basis of the computation: Gram = R^T R of the caller's G in the
     // weighted gradient inner product, Gt = G R^{-1} (every layout above is
     // built from Gt), at = R a
@@ -246,6 +266,7 @@ struct BackwardArgs {
     const double* GT;
     const double* Ghat;
     const double* Gf;
+    const uint32_t* Gb3;   // mixed plans: BF16 three-level fragments of G
     int MP, MT, KS;
     const double* w;
     const int* phase;
@@ -353,6 +374,7 @@ struct LayoutArgs {
     double* wpad;
     int* phpad;
     uint16_t* Fpk;         // packed mixed-path fragments [Qpad][MA][64][8]
+    uint32_t* Gb3;         // mixed adjoint GEMM fragments [9 Qpad/16][NH][3][64][4]
     int split;
 };
 void launch_build_layouts(const LayoutArgs& a, hipStream_t s);

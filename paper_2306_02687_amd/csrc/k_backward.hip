@@ -16,6 +16,14 @@
 
 namespace hrom {
 
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f bf16_mfma(v4u32 a, v4u32 b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
+                                                   0, 0);
+}
+
 // (A : v)_ij = mu v_ij + (mu - lam ln J) (Fi v Fi)_ji + lam Fi_ji tr(Fi v)
 template <typename T>
 __device__ __forceinline__ void nh_apply(const T* Fi, T mu, T la, T ell, const T* v, T* Av) {
@@ -39,20 +47,64 @@ __device__ __forceinline__ void nh_apply(const T* Fi, T mu, T la, T ell, const T
             Av[3 * i + j] = mu * v[3 * i + j] + cm * FVF[3 * j + i] + la * Fi[3 * j + i] * tr;
 }
 
+// The law and its adjoint at one (point, ECM point) pair in precision T: F^-1
+// and ln J of F_q, A v, and the contractions v : dP/dmu = v : (F - F^-T),
+// v : dP/dlam = v : (ln J F^-T).  ok: J > 0 (else Av, dmu, dla are not used).
+// FP32 (the mixed pass): reciprocal of J to one ulp, the library log.
+template <typename T>
+__device__ __forceinline__ bool pair_law(const T* F, const T* v, T mu, T la, T* Av, T& dmu, T& dla) {
+    const T c00 = F[4] * F[8] - F[5] * F[7];
+    const T c01 = F[5] * F[6] - F[3] * F[8];
+    const T c02 = F[3] * F[7] - F[4] * F[6];
+    const T J = F[0] * c00 + F[1] * c01 + F[2] * c02;
+    T id;
+    if constexpr (std::is_same<T, float>::value) id = __builtin_amdgcn_rcpf(J);
+    else id = 1.0 / J;
+    T Fi[9];
+    Fi[0] = c00 * id;
+    Fi[3] = c01 * id;
+    Fi[6] = c02 * id;
+    Fi[1] = (F[2] * F[7] - F[1] * F[8]) * id;
+    Fi[4] = (F[0] * F[8] - F[2] * F[6]) * id;
+    Fi[7] = (F[1] * F[6] - F[0] * F[7]) * id;
+    Fi[2] = (F[1] * F[5] - F[2] * F[4]) * id;
+    Fi[5] = (F[2] * F[3] - F[0] * F[5]) * id;
+    Fi[8] = (F[0] * F[4] - F[1] * F[3]) * id;
+    const bool ok = J > T(0);
+    const T ell = ok ? log(J) : T(0);
+    nh_apply<T>(Fi, mu, la, ell, v, Av);
+    T sm = T(0), sl = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            sm = fma(v[3 * i + j], F[3 * i + j] - Fi[3 * j + i], sm);
+            sl = fma(v[3 * i + j], Fi[3 * j + i], sl);
+        }
+    dmu = sm;
+    dla = ell * sl;
+    return ok;
+}
+
 
 
 // Point-batched form of the adjoint re-evaluation: 32 macro points per
 // workgroup of NW = 4 or 8 wavefronts; F_q - Fr = G a and G lambda are GEMMs
-// with the cluster's G as the shared operand (FP64 MFMA, two 16-point column
-// tiles), wave w taking row tiles w (+ NW ...) < 8 of the round's 144 rows
-// (ECM point, component) and waves 0..3 one of the four products (F or
-// G lambda, column tile) of tile 8; the law and its adjoint run per (point,
-// ECM point) pair (eight waves: one pair per thread; four waves: the pairs
-// (p, s) and (p, s + 8) of one point per thread); the refinement residual
-// rho = G^T (w A v) is a third FP64 GEMM in four k-ranges.  Per-point sums
-// over the ECM points (h_r, dL/dtheta) reduce in a fixed order.  The mixed
-// path keeps F_q and v_q in FP32 in LDS (its law evaluates A v in FP32), so
-// that four wavefronts fit two workgroups per CU.
+// with the cluster's G as the shared operand, the law and its adjoint run per
+// (point, ECM point) pair (eight waves: one pair per thread; four waves: the
+// pairs (p, s) and (p, s + 8) of one point per thread); the refinement
+// residual rho = G^T (w A v) is a third FP64 GEMM in four k-ranges.  Per-point
+// sums over the ECM points (h_r, dL/dtheta) reduce in a fixed order.
+// FP64 operator: FP64 MFMA (two 16-point column tiles), wave w taking row
+// tiles w (+ NW ...) < 8 of the round's 144 rows (ECM point, component) and
+// waves 0..3 one of the four products (F or G lambda, column tile) of tile 8.
+// Mixed path (its law evaluates A v in FP32 and F_q, v_q sit in LDS as FP32,
+// so that four wavefronts fit two workgroups per CU): both GEMMs on BF16
+// MFMA with G, a and lambda split into three BF16 levels each (six level
+// pairs per mode, FP32 accumulation: FP32-level results at a fifth of the
+// FP64 matrix time); waves 0, 1 form F, waves 2, 3 G lambda, each for all 32
+// points over alternate row tiles, with its a or lambda fragments built once
+// in registers.
 constexpr int kBwPT = 32;
 template <int AR, typename LT>
 struct BwLds {
@@ -62,6 +114,8 @@ struct BwLds {
     LT sV[16 * 9][kBwPT + 1];
     double sU[9][kBwPT];
     double sG[9][kBwPT];
+    double sWq[16];
+    int sPh[16];
     int sbits[kBwPT];
 };
 
@@ -69,7 +123,8 @@ template <int MA, bool MIXED, bool RHO, int NW, int AR, typename LT>
 __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
     constexpr int PT = kBwPT, QC = 16, NT = 64 * NW;
     static_assert(NW == 4 || NW == 8, "four or eight wavefronts");
-    static_assert(AR >= 16 * MA, "mode amplitude rows");
+    static_assert(MIXED || AR >= 16 * MA, "mode amplitude rows");
+    static_assert(!MIXED || NW == 4, "the mixed pass runs with four wavefronts");
     auto& sA = Ls.sA;
     auto& sL = Ls.sL;
     auto& sF = Ls.sF;
@@ -93,11 +148,42 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
         __syncthreads();
     }
     if (tid < PT) sbits[tid] = 0;
-    for (int e = tid; e < 4 * KS * PT; e += NT) {
-        const int k = e / PT, p = e % PT;
-        const bool in = (k < m && p < np);
-        sA[k][p] = in ? A.a[(int64_t)k * A.count + p0 + p] : 0.0;
-        sL[k][p] = in ? A.lam[(int64_t)k * A.count + p0 + p] : 0.0;
+    if constexpr (!MIXED) {
+        for (int e = tid; e < 4 * KS * PT; e += NT) {
+            const int k = e / PT, p = e % PT;
+            const bool in = (k < m && p < np);
+            sA[k][p] = in ? A.a[(int64_t)k * A.count + p0 + p] : 0.0;
+            sL[k][p] = in ? A.lam[(int64_t)k * A.count + p0 + p] : 0.0;
+        }
+    }
+    // mixed pass: this wave's B fragments, lane (g, c) holding the three BF16
+    // levels of modes 32 h + 8 g .. + 7 of point 16 pt + c (a for waves 0, 1,
+    // lambda for waves 2, 3; zero beyond m and beyond the workgroup's points)
+    constexpr int NH = MIXED ? (MA + 1) / 2 : 1;
+    v4u32 Bf[2][NH][3];
+    if constexpr (MIXED) {
+        const double* src = (wave >> 1) ? A.lam : A.a;
+#pragma unroll
+        for (int pt = 0; pt < 2; pt++)
+#pragma unroll
+            for (int hh = 0; hh < NH; hh++) {
+                uint32_t wd[3][4];
+#pragma unroll
+                for (int d = 0; d < 4; d++) {
+                    wd[0][d] = wd[1][d] = wd[2][d] = 0u;
+#pragma unroll
+                    for (int ii = 0; ii < 2; ii++) {
+                        const int k = 32 * hh + 8 * g + 2 * d + ii, p = 16 * pt + c;
+                        const double v = (k < m && p < np) ? src[(int64_t)k * A.count + p0 + p] : 0.0;
+                        uint16_t lv[3];
+                        bf16_split3(v, lv);
+#pragma unroll
+                        for (int L = 0; L < 3; L++) wd[L][d] |= (uint32_t)lv[L] << (16 * ii);
+                    }
+                }
+#pragma unroll
+                for (int L = 0; L < 3; L++) Bf[pt][hh][L] = v4u32{wd[L][0], wd[L][1], wd[L][2], wd[L][3]};
+            }
     }
     for (int e = tid; e < 9 * PT; e += NT) {
         const int I = e / PT, p = e % PT;
@@ -126,6 +212,52 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
 
     for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
         const int rt0 = (q0 / 16) * 9;
+        // weights and phases of the round's ECM points: loaded here, stored to
+        // LDS after the GEMMs (their latency hidden behind the products)
+        double wnext = 0.0;
+        int phnext = 0;
+        if (tid < QC) {
+            wnext = A.w[q0 + tid];
+            phnext = A.phase[q0 + tid];
+        }
+        if constexpr (MIXED) {
+            // F (waves 0, 1) or G lambda (waves 2, 3) over row tiles of the
+            // parity of the wave; per output tile the six level pairs of every
+            // mode half, the small products first and the hi * hi ones last
+            const bool isF = wave < 2;
+            for (int rt = wave & 1; rt < 9; rt += 2) {
+                const v4u32* ga = reinterpret_cast<const v4u32*>(A.Gb3) + ((int64_t)(rt0 + rt) * NH * 3) * 64 + lane;
+                v4u32 Af[NH][3];
+#pragma unroll
+                for (int hh = 0; hh < NH; hh++)
+#pragma unroll
+                    for (int L = 0; L < 3; L++) Af[hh][L] = ga[(hh * 3 + L) * 64];
+                v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+                for (int hh = 0; hh < NH; hh++)
+#pragma unroll
+                    for (int pt = 0; pt < 2; pt++) {
+                        acc[pt] = bf16_mfma(Af[hh][0], Bf[pt][hh][2], acc[pt]);
+                        acc[pt] = bf16_mfma(Af[hh][2], Bf[pt][hh][0], acc[pt]);
+                        acc[pt] = bf16_mfma(Af[hh][1], Bf[pt][hh][1], acc[pt]);
+                        acc[pt] = bf16_mfma(Af[hh][0], Bf[pt][hh][1], acc[pt]);
+                        acc[pt] = bf16_mfma(Af[hh][1], Bf[pt][hh][0], acc[pt]);
+                    }
+#pragma unroll
+                for (int hh = 0; hh < NH; hh++)
+#pragma unroll
+                    for (int pt = 0; pt < 2; pt++) acc[pt] = bf16_mfma(Af[hh][0], Bf[pt][hh][0], acc[pt]);
+                // accumulator element e: row 4 g + e of the tile, point 16 pt + c
+#pragma unroll
+                for (int pt = 0; pt < 2; pt++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int row = 16 * rt + 4 * g + e, col = 16 * pt + c;
+                        if (isF) sF[row][col] = (LT)((double)acc[pt][e] + sU[row % 9][col]);
+                        else sV[row][col] = (LT)(sG[row % 9][col] - (double)acc[pt][e]);
+                    }
+            }
+        } else {
 #pragma unroll
         for (int hh = 0; hh < 8 / NW; hh++) {
             const int rt = wave + NW * hh;
@@ -170,76 +302,42 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
                 else sV[row][col] = (LT)(sG[row % 9][col] - acc[e]);
             }
         }
+        }
+        if (tid < QC) {
+            Ls.sWq[tid] = wnext;
+            Ls.sPh[tid] = phnext;
+        }
         __syncthreads();
 #pragma unroll 1
         for (int k2 = 0; k2 < NPAIR; k2++) {
             const int p = pp, qq = qa + LPP * k2, q = q0 + qq;
-            double F[9], v[9];
+            const double wq = Ls.sWq[qq];
+            const int ph = Ls.sPh[qq];
+            const bool live = (q < A.Q) && (p < np);
+            using CT = typename std::conditional<MIXED, float, double>::type;
+            CT F[9], v[9], Av[9], dmu, dla;
 #pragma unroll
             for (int I = 0; I < 9; I++) {
-                F[I] = (double)sF[qq * 9 + I][p];
-                v[I] = (double)sV[qq * 9 + I][p];
+                F[I] = (CT)sF[qq * 9 + I][p];
+                v[I] = (CT)sV[qq * 9 + I][p];
             }
-            const double wq = A.w[q];
-            const int ph = A.phase[q];
             const double mu = ph ? mu1 : mu0, la = ph ? la1 : la0;
-            double Fi[9];
-            const double c00 = F[4] * F[8] - F[5] * F[7];
-            const double c01 = F[5] * F[6] - F[3] * F[8];
-            const double c02 = F[3] * F[7] - F[4] * F[6];
-            const double J = F[0] * c00 + F[1] * c01 + F[2] * c02;
-            {
-                const double id = 1.0 / J;
-                Fi[0] = c00 * id;
-                Fi[3] = c01 * id;
-                Fi[6] = c02 * id;
-                Fi[1] = (F[2] * F[7] - F[1] * F[8]) * id;
-                Fi[4] = (F[0] * F[8] - F[2] * F[6]) * id;
-                Fi[7] = (F[1] * F[6] - F[0] * F[7]) * id;
-                Fi[2] = (F[1] * F[5] - F[2] * F[4]) * id;
-                Fi[5] = (F[2] * F[3] - F[0] * F[5]) * id;
-                Fi[8] = (F[0] * F[4] - F[1] * F[3]) * id;
-            }
-            const bool live = (q < A.Q) && (p < np);
-            const bool ok = live && (J > 0.0);
-            if (live && !(J > 0.0)) atomicOr(&sbits[p], HROM_PT_JNONPOS);
-            const double ell = ok ? log(J) : 0.0;
-            double Av[9];
-            if constexpr (MIXED) {
-                float Fif[9], vf[9], Avf[9];
-#pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    Fif[k] = (float)Fi[k];
-                    vf[k] = (float)v[k];
-                }
-                nh_apply<float>(Fif, (float)mu, (float)la, (float)ell, vf, Avf);
-#pragma unroll
-                for (int k = 0; k < 9; k++) Av[k] = (double)Avf[k];
-            } else {
-                nh_apply<double>(Fi, mu, la, ell, v, Av);
-            }
+            const bool ok = pair_law<CT>(F, v, (CT)mu, (CT)la, Av, dmu, dla) && live;
+            if (live && !ok) atomicOr(&sbits[p], HROM_PT_JNONPOS);
             const double wo = ok ? wq : 0.0;
             if constexpr (RHO) {
                 // the refinement pass needs only rho; h and dL/dtheta come from
                 // the pass that follows it
 #pragma unroll
-                for (int I = 0; I < 9; I++) sV[qq * 9 + I][p] = (LT)(wo * Av[I]);
+                for (int I = 0; I < 9; I++) sV[qq * 9 + I][p] = (LT)(wo * (double)Av[I]);
             } else {
-                double dmu = 0.0, dla = 0.0;
 #pragma unroll
-                for (int i = 0; i < 3; i++)
-#pragma unroll
-                    for (int j = 0; j < 3; j++) {
-                        dmu = fma(v[3 * i + j], F[3 * i + j] - Fi[3 * j + i], dmu);
-                        dla = fma(v[3 * i + j], ell * Fi[3 * j + i], dla);
-                    }
-#pragma unroll
-                for (int I = 0; I < 9; I++) h[I] = fma(wo, Av[I], h[I]);
+                for (int I = 0; I < 9; I++) h[I] = fma(wo, (double)Av[I], h[I]);
                 const double wm = ph ? 0.0 : wo, wi = ph ? wo : 0.0;
-                gt[0] = fma(wm, dmu, gt[0]);
-                gt[1] = fma(wm, dla, gt[1]);
-                gt[2] = fma(wi, dmu, gt[2]);
-                gt[3] = fma(wi, dla, gt[3]);
+                gt[0] = fma(wm, (double)dmu, gt[0]);
+                gt[1] = fma(wm, (double)dla, gt[1]);
+                gt[2] = fma(wi, (double)dmu, gt[2]);
+                gt[3] = fma(wi, (double)dla, gt[3]);
             }
         }
         __syncthreads();
@@ -324,7 +422,7 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
 // operator of a mixed plan: FP64 law, FP64 staging) with four
 template <int MA, bool MIXED, bool RHO>
 __global__ void __launch_bounds__((MIXED || RHO) ? 256 : 512, MIXED ? 2 : 1) k_backward_b(BackwardArgs A) {
-    __shared__ BwLds<16 * MA, typename std::conditional<MIXED, float, double>::type> Ls;
+    __shared__ BwLds<MIXED ? 1 : 16 * MA, typename std::conditional<MIXED, float, double>::type> Ls;
     bw_body<MA, MIXED, RHO, (MIXED || RHO) ? 4 : 8>(A, (int64_t)blockIdx.x * kBwPT, Ls);
 }
 

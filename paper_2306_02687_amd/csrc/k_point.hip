@@ -676,6 +676,34 @@ __global__ void __launch_bounds__(256) k_build_gf(LayoutArgs A) {
     A.Gf[t] = (q < A.Q && k < A.m) ? A.G[((int64_t)q * 9 + I) * A.m + k] : 0.0;
 }
 
+// A-operand fragments of the mixed adjoint GEMM (BF16 16x16x32 MFMA, FP32
+// accumulation): row tile rt, half h (modes 32 h ..), level L of the
+// three-level BF16 split, lane (g, c), dword d holds the levels L of
+// G[q][I][k] and G[q][I][k + 1] (low half first) with 9 q + I = 16 rt + c and
+// k = 32 h + 8 g + 2 d (zero beyond m and beyond Q).
+__global__ void __launch_bounds__(256) k_build_gb3(LayoutArgs A) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int NH = gb3_halves(A.m);
+    const int64_t ntile = (int64_t)A.Qpad * 9 / 16;
+    if (t >= ntile * NH * 3 * 256) return;
+    const int d = (int)(t & 3), lane = (int)((t >> 2) & 63);
+    const int L = (int)((t >> 8) % 3);
+    const int h = (int)((t >> 8) / 3 % NH);
+    const int64_t rt = (t >> 8) / 3 / NH;
+    const int64_t row = rt * 16 + (lane & 15);
+    const int q = (int)(row / 9), I = (int)(row % 9);
+    uint32_t word = 0;
+#pragma unroll
+    for (int ii = 0; ii < 2; ii++) {
+        const int k = 32 * h + 8 * (lane >> 4) + 2 * d + ii;
+        const double v = (q < A.Q && k < A.m) ? A.G[((int64_t)q * 9 + I) * A.m + k] : 0.0;
+        uint16_t lv[3];
+        bf16_split3(v, lv);
+        word |= (uint32_t)lv[L] << (16 * ii);
+    }
+    A.Gb3[t] = word;
+}
+
 // Weights of the volume averages (Sec. 2 and 3.3): w_q / V0 with V0 = sum_q
 // w_q (summed in order), so that the ECM sums are averages over the RVE
 // whatever measure the caller's weights add up to.
@@ -699,6 +727,8 @@ void launch_build_layouts(const LayoutArgs& a, hipStream_t s) {
     if (a.prec != HROM_FP64) {
         const int64_t n2 = (int64_t)a.Qpad * ((a.m + 15) / 16) * 512;
         hipLaunchKernelGGL(k_build_frags, dim3(nblocks(n2, 256)), dim3(256), 0, s, a);
+        const int64_t n4 = (int64_t)a.Qpad * 9 / 16 * gb3_halves(a.m) * 3 * 256;
+        hipLaunchKernelGGL(k_build_gb3, dim3(nblocks(n4, 256)), dim3(256), 0, s, a);
     }
 }
 
