@@ -477,6 +477,19 @@ def svd_sweep_flops(P, M):
     return pairs_per_sweep * 2 * (2.0 * 64 * 64 * M)
 
 
+def svd_flops(P, M, r, sweeps):
+    """FP64 flops of hrom_ecm_svd with the library's automatic method: for
+    M >= 2 Ppad the Householder QR (2 M P^2 - 2 P^3 / 3), the sweeps over the
+    P rows of R and Q applied to the r leading vectors (4 M P r - 2 P^2 r);
+    else the sweeps over the M rows."""
+    nb = max(2, -(-P // 32))
+    nb += nb & 1
+    if M >= 2 * 32 * nb:
+        return (2.0 * M * P * P - 2.0 * P ** 3 / 3 + sweeps * svd_sweep_flops(P, P)
+                + 4.0 * M * P * r - 2.0 * P * P * r)
+    return sweeps * svd_sweep_flops(P, M)
+
+
 def run_ecm(args, quiet=False):
     """The offline stage end to end on the GPU (Box 2 with the empirical
     cubature of Sec. 3.3 and the POD of Sec. 3.2.1), at the sizes of the
@@ -535,7 +548,7 @@ def run_ecm(args, quiet=False):
     Xi = torch.from_numpy(X_in.T.copy()).cuda()
     (Phi, _, _, _), t_pod = timed(lambda: B.pod(Xe, Xi, wt["n_el"], wt["n_inel"]))
     Prows = p * (m + 9)
-    flops = sweeps * svd_sweep_flops(Prows, M)
+    flops = svd_flops(Prows, M, mt - 1, sweeps)
     sig_h = sig.cpu().numpy()
     res = {"kmeans_ms": t_km, "kmeans_iterations": km_iters, "paths_ms": t_paths,
            "newton_snapshots_ms": t_newton, "training_ms": t_tr, "svd_ms": t_svd, "select_ms": t_sel,

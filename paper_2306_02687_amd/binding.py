@@ -89,7 +89,7 @@ def load(path: str = LIB_PATH):
     L.hrom_biot.argtypes = [P, P, P, P, P]
     L.hrom_history.argtypes = [P, i32, P, P]
     L.hrom_ecm_training.argtypes = [i32, i32, P, P, P, P, i32, P, P, P, P, C.POINTER(i32), P]
-    L.hrom_ecm_svd.argtypes = [i32, i32, P, i32, P, P, d, i32, C.POINTER(i32), P, P]
+    L.hrom_ecm_svd.argtypes = [i32, i32, P, i32, P, P, d, i32, i32, C.POINTER(i32), P, P]
     L.hrom_ecm_select.argtypes = [i32, i32, P, d, i32, P, P, C.POINTER(i32), P, i32,
                                   C.POINTER(i32), P]
     L.hrom_training_clusters.argtypes = [i64, i32, P, i32, P, i32, P, P, C.POINTER(i32), P]
@@ -192,11 +192,16 @@ def ecm_training(G, w, phase, theta, Fr, a, stream=None):
     return xf, fint, nbad.value
 
 
-def ecm_svd(xf, r, tol=0.0, max_sweeps=0, stream=None, check=True, history=None):
+SVD_AUTO, SVD_DIRECT, SVD_QR = 0, 1, 2
+
+
+def ecm_svd(xf, r, tol=0.0, max_sweeps=0, stream=None, check=True, history=None, method=SVD_AUTO):
     """hrom_ecm_svd: the r leading left singular vectors of x_f^T, lam [M, r],
     and all singular values sigma [P].  Returns (lam, sigma, sweeps, rc); a
     list passed as history receives the largest relative off-diagonal Gram
-    entry of every sweep."""
+    entry of every sweep.  method: SVD_DIRECT sweeps x_f^T itself, SVD_QR
+    sweeps the factor R of a Householder QR first, SVD_AUTO picks QR for tall
+    matrices."""
     P, M = xf.shape
     lam = torch.empty((M, max(r, 0)), dtype=torch.float64, device=xf.device)
     sigma = torch.empty(P, dtype=torch.float64, device=xf.device)
@@ -204,7 +209,7 @@ def ecm_svd(xf, r, tol=0.0, max_sweeps=0, stream=None, check=True, history=None)
     nh = max_sweeps if max_sweeps > 0 else 40
     hist = (C.c_double * nh)()
     rc = load().hrom_ecm_svd(P, M, _ptr(xf), r, _ptr(lam) if r > 0 else None, _ptr(sigma),
-                             float(tol), int(max_sweeps), C.byref(sweeps),
+                             float(tol), int(max_sweeps), int(method), C.byref(sweeps),
                              C.cast(hist, C.c_void_p), _stream(stream))
     if check:
         _check(rc, "hrom_ecm_svd")

@@ -68,6 +68,27 @@ __device__ double block_sum(double s, double* red) {
     return t;
 }
 
+// orders the LDS accesses of one wavefront's lanes (no hardware barrier)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// sum over a workgroup of 1024 threads (fixed order); every thread gets it
+__device__ double block_sum1024(double s, double* red) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    s = wave_sum(s);
+    __syncthreads();
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    double t[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) t[i] = red[2 * i] + red[2 * i + 1];
+    const double u = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+    __syncthreads();
+    return u;
+}
+
 // ------------------------------------------------------------------------
 // training matrix
 // ------------------------------------------------------------------------
@@ -308,6 +329,11 @@ __global__ void __launch_bounds__(256) k_svd_rotate(const double* __restrict__ p
         ver[pr.x]++;
         ver[pr.y]++;
     }
+    // per step each thread takes the rotations k = tid / 64 + 4 i (i < 8) for
+    // column (row) tid % 64 and issues all their loads before its first store
+    // (disjoint rotations touch disjoint rows and columns)
+    constexpr int KT = kSW / 2 / 4;
+    const int kb = tid >> 6, li = tid & 63;
     for (int sweep = 0; sweep < max_inner; sweep++) {
         for (int step = 0; step < kSW - 1; step++) {
             if (tid < kSW / 2) {
@@ -329,29 +355,50 @@ __global__ void __launch_bounds__(256) k_svd_rotate(const double* __restrict__ p
                 pq[tid][1] = q;
             }
             __syncthreads();
-            for (int e = tid; e < (kSW / 2) * kSW; e += 256) {   // rows p, q: W <- J^T W
-                const int k = e / kSW, col = e % kSW;
-                const int p = pq[k][0], q = pq[k][1];
-                const double c = cs[k][0], s = cs[k][1];
-                const double wp = W[p][col], wq = W[q][col];
-                W[p][col] = c * wp - s * wq;
-                W[q][col] = s * wp + c * wq;
+            int p[KT], q[KT];
+            double c[KT], s[KT];
+#pragma unroll
+            for (int i = 0; i < KT; i++) {
+                const int k = kb + 4 * i;
+                p[i] = pq[k][0];
+                q[i] = pq[k][1];
+                c[i] = cs[k][0];
+                s[i] = cs[k][1];
+            }
+            {   // rows p, q: W <- J^T W (li = column)
+                double wp[KT], wq[KT];
+#pragma unroll
+                for (int i = 0; i < KT; i++) {
+                    wp[i] = W[p[i]][li];
+                    wq[i] = W[q[i]][li];
+                }
+#pragma unroll
+                for (int i = 0; i < KT; i++) {
+                    W[p[i]][li] = c[i] * wp[i] - s[i] * wq[i];
+                    W[q[i]][li] = s[i] * wp[i] + c[i] * wq[i];
+                }
             }
             __syncthreads();
-            for (int e = tid; e < (kSW / 2) * kSW; e += 256) {   // columns p, q: W <- W J, V <- V J
-                const int k = e / kSW, row = e % kSW;
-                const int p = pq[k][0], q = pq[k][1];
-                const double c = cs[k][0], s = cs[k][1];
-                const double wp = W[row][p], wq = W[row][q];
-                W[row][p] = c * wp - s * wq;
-                W[row][q] = s * wp + c * wq;
-                const double vp = V[row][p], vq = V[row][q];
-                V[row][p] = c * vp - s * vq;
-                V[row][q] = s * vp + c * vq;
+            {   // columns p, q: W <- W J, V <- V J (li = row)
+                double wp[KT], wq[KT], vp[KT], vq[KT];
+#pragma unroll
+                for (int i = 0; i < KT; i++) {
+                    wp[i] = W[li][p[i]];
+                    wq[i] = W[li][q[i]];
+                    vp[i] = V[li][p[i]];
+                    vq[i] = V[li][q[i]];
+                }
+#pragma unroll
+                for (int i = 0; i < KT; i++) {
+                    W[li][p[i]] = c[i] * wp[i] - s[i] * wq[i];
+                    W[li][q[i]] = s[i] * wp[i] + c[i] * wq[i];
+                    V[li][p[i]] = c[i] * vp[i] - s[i] * vq[i];
+                    V[li][q[i]] = s[i] * vp[i] + c[i] * vq[i];
+                }
             }
             __syncthreads();
         }
-        if (!(offdiag(W, red) > 0.1 * tol)) break;
+        if (sweep + 1 < max_inner && !(offdiag(W, red) > 0.1 * tol)) break;
     }
     for (int e = tid; e < kSW * kSW; e += 256) Vout[(int64_t)blockIdx.x * kSW * kSW + e] = V[e / kSW][e % kSW];
 }
@@ -433,6 +480,224 @@ __global__ void k_svd_extract(const double* A, int M, const int* perm, const dou
     for (int jj = threadIdx.y; jj < 32; jj += 8) {
         const int j = j0 + jj, g = g0 + threadIdx.x;
         t[jj][threadIdx.x] = (j < r && g < M) ? A[(int64_t)perm[j] * M + g] / sig_sorted[j] : 0.0;
+    }
+    __syncthreads();
+    for (int gg = threadIdx.y; gg < 32; gg += 8) {
+        const int g = g0 + gg, j = j0 + threadIdx.x;
+        if (g < M && j < r) lam[(int64_t)g * ld + j] = t[threadIdx.x][gg];
+    }
+}
+
+// ------------------------------------------------------------------------
+// Householder QR of x_f^T ahead of the sweeps (tall matrices)
+// ------------------------------------------------------------------------
+// x_f^T = Q R with Q the product of Householder reflectors, in panels of kQB
+// columns applied to the rest of the matrix in the compact WY form
+// Q_k = I - V_k T_k V_k^T.  One-sided Jacobi on the P x P factor R gives the
+// same singular values (its iterates depend on the Gram matrix alone, which R
+// shares with x_f^T) with every sweep over P rows in place of M; the left
+// vectors of x_f^T are then Q times those of R.  Householder QR is backward
+// stable, so the singular values keep their absolute accuracy relative to
+// sigma_1.
+constexpr int kQB = 32;
+
+// Reflector of column j (rows j .. M-1) and its product with the panel
+// columns j + 1 .. j + gridDim.x - 1: workgroup b handles column j + b.  Every
+// workgroup forms the reflector from column j, which no workgroup of this
+// launch writes; workgroup 0 stores v (one at row j, zero above), tau and the
+// diagonal entry beta of R.  H = I - tau v v^T maps column j to beta e_j;
+// tau = 0 (H = I) when the column is zero below row j.
+__global__ void __launch_bounds__(1024) k_qr_col(double* __restrict__ A, int M, int j, double* __restrict__ V,
+                                                 double* __restrict__ tau, double* __restrict__ beta) {
+    __shared__ double red[16];
+    const int tid = threadIdx.x;
+    const double* x = A + (int64_t)j * M;
+    double* y = A + (int64_t)(j + blockIdx.x) * M;
+    const double x1 = x[j], y1 = y[j];
+    double s = 0.0;
+#pragma unroll 4
+    for (int i = j + 1 + tid; i < M; i += 1024) s += x[i] * x[i];
+    const double sg = block_sum1024(s, red);
+    double t = 0.0, b = x1, sc = 0.0;
+    if (sg > 0.0) {
+        const double nrm = sqrt(x1 * x1 + sg);
+        b = (x1 >= 0.0) ? -nrm : nrm;
+        t = (b - x1) / b;
+        sc = 1.0 / (x1 - b);
+    }
+    if (blockIdx.x == 0) {
+        double* v = V + (int64_t)j * M;
+        for (int i = tid; i < M; i += 1024) v[i] = (i < j) ? 0.0 : ((i == j) ? 1.0 : x[i] * sc);
+        if (tid == 0) {
+            tau[j] = t;
+            beta[j] = b;
+        }
+        return;
+    }
+    if (t == 0.0) return;
+    double d = 0.0;
+#pragma unroll 4
+    for (int i = j + 1 + tid; i < M; i += 1024) d += x[i] * y[i];
+    const double f = t * (y1 + sc * block_sum1024(d, red));
+#pragma unroll 4
+    for (int i = j + 1 + tid; i < M; i += 1024) y[i] -= f * (x[i] * sc);
+    if (tid == 0) y[j] = y1 - f;
+}
+
+// Partial products V_p^T X over the rows of chunk blockIdx.y (from row r0 on)
+// for a tile of 32 columns of X per blockIdx.x (V_p: the kQB columns of a
+// panel, zero above its first row): FP64 16x16x4 MFMA, wavefront w the 16 x 16
+// tile (w / 2, w % 2); lane (g, c) feeds A[c][g] = V[k0 + g][16 (w / 2) + c]
+// and B[g][c] = X[k0 + g][16 (w % 2) + c], accumulator element e = D[g + 4 e][c]
+__global__ void __launch_bounds__(256) k_qr_cross(const double* __restrict__ Vp, const double* __restrict__ X,
+                                                  int M, int r0, int ncols, int chunk_rows, int nchunks,
+                                                  double* __restrict__ part) {
+    __shared__ double Vt[kQB][kSR + 1];
+    __shared__ double Xt[kQB][kSR + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+    const int c0 = blockIdx.x * kQB, ti = wave >> 1, tj = wave & 1;
+    const int rb0 = r0 + blockIdx.y * chunk_rows, rb1 = min(M, rb0 + chunk_rows);
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int rb = rb0; rb < rb1; rb += kSR) {
+        for (int e = tid; e < kQB * kSR; e += 256) {
+            const int cc = e / kSR, rr = e % kSR, gg = rb + rr;
+            const bool in = gg < rb1;
+            Vt[cc][rr] = in ? Vp[(int64_t)cc * M + gg] : 0.0;
+            Xt[cc][rr] = (in && c0 + cc < ncols) ? X[(int64_t)(c0 + cc) * M + gg] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k0 = 0; k0 < kSR; k0 += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Vt[16 * ti + c][k0 + g], Xt[16 * tj + c][k0 + g], acc, 0, 0,
+                                                       0);
+        __syncthreads();
+    }
+    double* out = part + ((int64_t)blockIdx.x * nchunks + blockIdx.y) * (kQB * kQB);
+#pragma unroll
+    for (int e = 0; e < 4; e++) out[(16 * ti + g + 4 * e) * kQB + 16 * tj + c] = acc[e];
+}
+
+// Z[k][col] = sum over the chunks in order of the partials of k_qr_cross
+__global__ void __launch_bounds__(256) k_qr_zsum(const double* __restrict__ part, int nchunks, int ncols,
+                                                 double* __restrict__ Z) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kQB * ncols) return;
+    const int k = e / ncols, col = e % ncols;
+    const double* src = part + (int64_t)(col / kQB) * nchunks * (kQB * kQB) + k * kQB + col % kQB;
+    double s = 0.0;
+    for (int ch = 0; ch < nchunks; ch++) s += src[(int64_t)ch * (kQB * kQB)];
+    Z[(int64_t)k * ncols + col] = s;
+}
+
+// T of the panel's compact WY form (one workgroup of kQB threads) from
+// Y = V^T V (row stride ldy) and the panel's tau: T_ii = tau_i,
+// T[0:i, i] = -tau_i T[0:i, 0:i] Y[0:i, i]
+__global__ void k_qr_tbuild(const double* __restrict__ Y, int ldy, const double* __restrict__ tau,
+                            double* __restrict__ T) {
+    __shared__ double Ts[kQB][kQB + 1];
+    const int r = threadIdx.x;
+    for (int k = 0; k < kQB; k++) Ts[r][k] = 0.0;
+    __syncthreads();
+    for (int i = 0; i < kQB; i++) {
+        double s = 0.0;
+        if (r < i)
+            for (int k = r; k < i; k++) s += Ts[r][k] * Y[k * ldy + i];
+        __syncthreads();
+        if (r < i) Ts[r][i] = -tau[i] * s;
+        if (r == i) Ts[i][i] = tau[i];
+        __syncthreads();
+    }
+    for (int k = 0; k < kQB; k++) T[r * kQB + k] = Ts[r][k];
+}
+
+// Wt = T^T Z (trans: the transposed panel, Q_k^T X) or T Z (Q_k X)
+__global__ void __launch_bounds__(256) k_qr_tmul(const double* __restrict__ T, const double* __restrict__ Z,
+                                                 int ncols, int trans, double* __restrict__ Wt) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kQB * ncols) return;
+    const int i = e / ncols, col = e % ncols;
+    double s = 0.0;
+    for (int k = 0; k < kQB; k++) s += (trans ? T[k * kQB + i] : T[i * kQB + k]) * Z[(int64_t)k * ncols + col];
+    Wt[(int64_t)i * ncols + col] = s;
+}
+
+// X[:, c] -= V_p Wt[:, c] over the rows of chunk blockIdx.y (from row r0 on)
+// for a tile of 32 columns per blockIdx.x: FP64 MFMA with the accumulator
+// started at X, wavefront w the rows 16 w .. of every 64-row step against the
+// two column tiles (A[c][g] = -V[row][k0 + g], B[g][c] = Wt[k0 + g][col])
+__global__ void __launch_bounds__(256) k_qr_update(double* __restrict__ X, const double* __restrict__ Vp, int M,
+                                                   int r0, int ncols, int chunk_rows, const double* __restrict__ Wt) {
+    __shared__ double Vt[kSR][kQB + 1];
+    __shared__ double Ws[kQB][kQB + 1];
+    __shared__ double Xt[kQB][kSR + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+    const int c0 = blockIdx.x * kQB;
+    for (int e = tid; e < kQB * kQB; e += 256) {
+        const int k = e / kQB, cc = e % kQB;
+        Ws[k][cc] = (c0 + cc < ncols) ? Wt[(int64_t)k * ncols + c0 + cc] : 0.0;
+    }
+    const int rb0 = r0 + blockIdx.y * chunk_rows, rb1 = min(M, rb0 + chunk_rows);
+    for (int rb = rb0; rb < rb1; rb += kSR) {
+        for (int e = tid; e < kQB * kSR; e += 256) {
+            const int cc = e / kSR, rr = e % kSR, gg = rb + rr;
+            const bool in = gg < rb1;
+            Vt[rr][cc] = in ? Vp[(int64_t)cc * M + gg] : 0.0;
+            Xt[cc][rr] = (in && c0 + cc < ncols) ? X[(int64_t)(c0 + cc) * M + gg] : 0.0;
+        }
+        __syncthreads();
+        v4d acc[2];
+#pragma unroll
+        for (int J = 0; J < 2; J++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc[J][e] = Xt[16 * J + c][16 * wave + g + 4 * e];
+#pragma unroll
+        for (int k0 = 0; k0 < kQB; k0 += 4) {
+            const double a = -Vt[16 * wave + c][k0 + g];
+#pragma unroll
+            for (int J = 0; J < 2; J++)
+                acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ws[k0 + g][16 * J + c], acc[J], 0, 0, 0);
+        }
+        // each wavefront rewrites only the rows it read
+#pragma unroll
+        for (int J = 0; J < 2; J++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) Xt[16 * J + c][16 * wave + g + 4 * e] = acc[J][e];
+        __syncthreads();
+        for (int e = tid; e < kQB * kSR; e += 256) {
+            const int cc = e / kSR, rr = e % kSR, gg = rb + rr;
+            if (gg < rb1 && c0 + cc < ncols) X[(int64_t)(c0 + cc) * M + gg] = Xt[cc][rr];
+        }
+        __syncthreads();
+    }
+}
+
+// R as a matrix of P rows for the sweeps: column j = (A[0 .. j-1][j], beta_j,
+// 0 ...), zero for the padding columns j >= P
+__global__ void __launch_bounds__(256) k_qr_rbuild(const double* __restrict__ A, int M, const double* beta, int P,
+                                                   int Ppad, double* __restrict__ Rm) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)Ppad * P) return;
+    const int j = (int)(e / P), i = (int)(e % P);
+    Rm[e] = (j >= P || i > j) ? 0.0 : ((i == j) ? beta[j] : A[(int64_t)j * M + i]);
+}
+
+// X[j][i] = R-side left vector j: column perm[j] of the swept matrix (MJ rows)
+// over sigma_j, zero for rows i >= MJ (j < r)
+__global__ void __launch_bounds__(256) k_qr_xinit(const double* __restrict__ Jm, int MJ, const int* perm,
+                                                  const double* sig, int r, int M, double* __restrict__ X) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)r * M) return;
+    const int j = (int)(e / M), i = (int)(e % M);
+    X[e] = (i < MJ) ? Jm[(int64_t)perm[j] * MJ + i] / sig[j] : 0.0;
+}
+
+// lam[g][j] = X[j][g] (row stride ld)
+__global__ void k_qr_out(const double* __restrict__ X, int M, int r, double* __restrict__ lam, int ld) {
+    __shared__ double t[32][33];
+    const int g0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    for (int jj = threadIdx.y; jj < 32; jj += 8) {
+        const int j = j0 + jj, g = g0 + threadIdx.x;
+        t[jj][threadIdx.x] = (j < r && g < M) ? X[(int64_t)j * M + g] : 0.0;
     }
     __syncthreads();
     for (int gg = threadIdx.y; gg < 32; gg += 8) {
@@ -1165,15 +1430,23 @@ namespace hrom {
 // the r leading left singular vectors of xf^T (xf [P][M]) into lam (row
 // stride ld), all singular values into sigma; the Jacobi of hrom_ecm_svd
 int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double* sigma, double tol,
-             int max_sweeps, int* sweeps, double* off_hist, hipStream_t stream) {
-    if (P < 1 || M < 1 || r < 0 || r > P || ld < r || !xf || !sigma || (r > 0 && !lam)) return HROM_E_INVALID;
+             int max_sweeps, int* sweeps, double* off_hist, int method, hipStream_t stream) {
+    if (P < 1 || M < 1 || r < 0 || r > P || ld < r || !xf || !sigma || (r > 0 && !lam) || method < 0 ||
+        method > 2)
+        return HROM_E_INVALID;
     if (!(tol > 0.0)) tol = 1e-13;
     if (max_sweeps <= 0) max_sweeps = 40;
     int nbk = (P + kSB - 1) / kSB;
     if (nbk < 2) nbk = 2;
     if (nbk & 1) nbk++;
     const int Ppad = nbk * kSB, npairs = nbk / 2, nrounds = nbk - 1;
-    const int chunk_rows = 1024, nchunks = (M + chunk_rows - 1) / chunk_rows;
+    // QR first: on request (M >= Ppad), or for matrices with at least twice
+    // as many rows as padded columns
+    if (method == 2 && M < Ppad) return HROM_E_INVALID;
+    const bool qr = method == 2 || (method == 0 && M >= 2 * Ppad);
+    const int MJ = qr ? P : M;   // rows of the matrix the sweeps run on
+    const int chunk_rows = qr ? 256 : 1024, nchunks = (MJ + chunk_rows - 1) / chunk_rows;
+    const int qchunk = 1024, qmax = (M + qchunk - 1) / qchunk, npan = (P + kQB - 1) / kQB;
     // tournament schedule: block 0 fixed, the others rotate
     std::vector<int2> sched((size_t)nrounds * npairs);
     for (int t = 0; t < nrounds; t++) {
@@ -1184,13 +1457,17 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
         }
     }
     Arena ar;
-    const size_t bytes = round256(sizeof(double) * (size_t)Ppad * M) +
-                         round256(sizeof(int2) * sched.size()) +
-                         round256(sizeof(double) * (size_t)npairs * nchunks * kSW * kSW) +
-                         round256(sizeof(double) * (size_t)npairs * kSW * kSW) +
-                         2 * round256(sizeof(double) * Ppad) + round256(sizeof(int) * Ppad) + 256 +
-                         round256(sizeof(int) * nbk) + round256(sizeof(int2) * sched.size()) +
-                         round256(sizeof(int) * npairs) + 4096;
+    size_t bytes = round256(sizeof(double) * (size_t)Ppad * M) + round256(sizeof(int2) * sched.size()) +
+                   round256(sizeof(double) * (size_t)npairs * nchunks * kSW * kSW) +
+                   round256(sizeof(double) * (size_t)npairs * kSW * kSW) + 2 * round256(sizeof(double) * Ppad) +
+                   round256(sizeof(int) * Ppad) + 256 + round256(sizeof(int) * nbk) +
+                   round256(sizeof(int2) * sched.size()) + round256(sizeof(int) * npairs) + 4096;
+    if (qr)
+        bytes += round256(sizeof(double) * (size_t)Ppad * M) + round256(sizeof(double) * (size_t)Ppad * P) +
+                 round256(sizeof(double) * (size_t)std::max(r, 1) * M) +
+                 round256(sizeof(double) * (size_t)(Ppad / kQB) * qmax * kQB * kQB) +
+                 2 * round256(sizeof(double) * (size_t)kQB * Ppad) +
+                 round256(sizeof(double) * (size_t)npan * kQB * kQB) + 2 * round256(sizeof(double) * Ppad) + 2048;
     if (ar.alloc(bytes) != HROM_OK) return HROM_E_NOMEM;
     double* A = ar.take<double>((size_t)Ppad * M);
     int2* dsched = ar.take<int2>(sched.size());
@@ -1203,6 +1480,19 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
     int* ver = ar.take<int>(nbk);
     int2* pver = ar.take<int2>(sched.size());
     int* apply = ar.take<int>(npairs);
+    double *V = nullptr, *Rm = nullptr, *X = nullptr, *qpart = nullptr, *Z = nullptr, *Wt = nullptr,
+           *Tall = nullptr, *tau = nullptr, *beta = nullptr;
+    if (qr) {
+        V = ar.take<double>((size_t)Ppad * M);
+        Rm = ar.take<double>((size_t)Ppad * P);
+        X = ar.take<double>((size_t)std::max(r, 1) * M);
+        qpart = ar.take<double>((size_t)(Ppad / kQB) * qmax * kQB * kQB);
+        Z = ar.take<double>((size_t)kQB * Ppad);
+        Wt = ar.take<double>((size_t)kQB * Ppad);
+        Tall = ar.take<double>((size_t)npan * kQB * kQB);
+        tau = ar.take<double>(Ppad);
+        beta = ar.take<double>(Ppad);
+    }
     if (hipMemcpyAsync(A, xf, sizeof(double) * (size_t)P * M, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
         hipMemsetAsync(A + (size_t)P * M, 0, sizeof(double) * (size_t)(Ppad - P) * M, stream) != hipSuccess ||
         hipMemcpyAsync(dsched, sched.data(), sizeof(int2) * sched.size(), hipMemcpyHostToDevice, stream) !=
@@ -1210,6 +1500,43 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
         hipMemsetAsync(ver, 0, sizeof(int) * nbk, stream) != hipSuccess ||
         hipMemsetAsync(pver, 0xff, sizeof(int2) * sched.size(), stream) != hipSuccess)
         return HROM_E_HIP;
+    // products V_p^T X, then X -= V_p W with W = T^T (V_p^T X) or T (V_p^T X),
+    // over the rows j0 .. of panel pn (V_p is zero above them)
+    auto panel_apply = [&](int pn, double* Xc, int ncols, int trans) {
+        const int j0 = pn * kQB, qn = (M - j0 + qchunk - 1) / qchunk;
+        const double* Vp = V + (size_t)j0 * M;
+        const int ct = (ncols + kQB - 1) / kQB;
+        hipLaunchKernelGGL(k_qr_cross, dim3(ct, qn), dim3(256), 0, stream, Vp, Xc, M, j0, ncols, qchunk, qn, qpart);
+        hipLaunchKernelGGL(k_qr_zsum, dim3((kQB * ncols + 255) / 256), dim3(256), 0, stream, qpart, qn, ncols, Z);
+        hipLaunchKernelGGL(k_qr_tmul, dim3((kQB * ncols + 255) / 256), dim3(256), 0, stream,
+                           Tall + (size_t)pn * kQB * kQB, Z, ncols, trans, Wt);
+        hipLaunchKernelGGL(k_qr_update, dim3(ct, qn), dim3(256), 0, stream, Xc, Vp, M, j0, ncols, qchunk, Wt);
+    };
+    double* Jm = A;
+    if (qr) {
+        if (hipMemsetAsync(V, 0, sizeof(double) * (size_t)Ppad * M, stream) != hipSuccess ||
+            hipMemsetAsync(tau, 0, sizeof(double) * Ppad, stream) != hipSuccess)
+            return HROM_E_HIP;
+        for (int pn = 0; pn < npan; pn++) {
+            const int j0 = pn * kQB, j1 = std::min(P, j0 + kQB);
+            for (int j = j0; j < j1; j++)
+                hipLaunchKernelGGL(k_qr_col, dim3(j1 - j), dim3(1024), 0, stream, A, M, j, V, tau, beta);
+            // T from Y = V_p^T V_p
+            const int qn = (M - j0 + qchunk - 1) / qchunk;
+            const double* Vp = V + (size_t)j0 * M;
+            hipLaunchKernelGGL(k_qr_cross, dim3(1, qn), dim3(256), 0, stream, Vp, Vp, M, j0, kQB, qchunk, qn, qpart);
+            hipLaunchKernelGGL(k_qr_zsum, dim3((kQB * kQB + 255) / 256), dim3(256), 0, stream, qpart, qn, kQB, Z);
+            hipLaunchKernelGGL(k_qr_tbuild, dim3(1), dim3(kQB), 0, stream, Z, kQB, tau + j0,
+                               Tall + (size_t)pn * kQB * kQB);
+            // the trailing columns: A <- Q_p^T A
+            if (P > j1) panel_apply(pn, A + (size_t)j1 * M, P - j1, 1);
+        }
+        const int64_t nr = (int64_t)Ppad * P;
+        hipLaunchKernelGGL(k_qr_rbuild, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, stream, A, M, beta, P, Ppad,
+                           Rm);
+        if (launched() != HROM_OK) return HROM_E_HIP;
+        Jm = Rm;
+    }
     int sw = 0;
     bool conv = false;
     for (; sw < max_sweeps && !conv; sw++) {
@@ -1217,11 +1544,11 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
         for (int t = 0; t < nrounds; t++) {
             const int2* pr = dsched + (size_t)t * npairs;
             const int pbase = t * npairs;
-            hipLaunchKernelGGL(k_svd_gram, dim3(npairs, nchunks), dim3(256), 0, stream, A, M, pr, chunk_rows,
+            hipLaunchKernelGGL(k_svd_gram, dim3(npairs, nchunks), dim3(256), 0, stream, Jm, MJ, pr, chunk_rows,
                                nchunks, part, ver, pver, pbase);
             hipLaunchKernelGGL(k_svd_rotate, dim3(npairs), dim3(256), 0, stream, part, nchunks, tol, 1, Vb,
                                offmax, pr, ver, pver, pbase, apply);
-            hipLaunchKernelGGL(k_svd_apply, dim3(npairs, nchunks), dim3(256), 0, stream, A, M, pr, Vb, apply,
+            hipLaunchKernelGGL(k_svd_apply, dim3(npairs, nchunks), dim3(256), 0, stream, Jm, MJ, pr, Vb, apply,
                                chunk_rows);
         }
         if (launched() != HROM_OK) return HROM_E_HIP;
@@ -1235,11 +1562,22 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
         conv = !(off > tol);
     }
     if (sweeps) *sweeps = sw;
-    hipLaunchKernelGGL(k_svd_norms, dim3(P), dim3(256), 0, stream, A, M, sig);
+    hipLaunchKernelGGL(k_svd_norms, dim3(P), dim3(256), 0, stream, Jm, MJ, sig);
     hipLaunchKernelGGL(k_svd_rank, dim3((P + 255) / 256), dim3(256), 0, stream, sig, P, perm, sig_sorted);
-    if (r > 0)
-        hipLaunchKernelGGL(k_svd_extract, dim3((M + 31) / 32, (r + 31) / 32), dim3(32, 8), 0, stream, A, M,
-                           perm, sig_sorted, r, lam, ld);
+    if (r > 0) {
+        if (qr) {
+            // left vectors of x_f^T = Q [U_R; 0]: the panels in reverse order
+            const int64_t nx = (int64_t)r * M;
+            hipLaunchKernelGGL(k_qr_xinit, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, stream, Jm, MJ, perm,
+                               sig_sorted, r, M, X);
+            for (int pn = npan - 1; pn >= 0; pn--) panel_apply(pn, X, r, 0);
+            hipLaunchKernelGGL(k_qr_out, dim3((M + 31) / 32, (r + 31) / 32), dim3(32, 8), 0, stream, X, M, r, lam,
+                               ld);
+        } else {
+            hipLaunchKernelGGL(k_svd_extract, dim3((M + 31) / 32, (r + 31) / 32), dim3(32, 8), 0, stream, A, M,
+                               perm, sig_sorted, r, lam, ld);
+        }
+    }
     if (launched() != HROM_OK) return HROM_E_HIP;
     if (hipMemcpyAsync(sigma, sig_sorted, sizeof(double) * P, hipMemcpyDeviceToDevice, stream) != hipSuccess)
         return HROM_E_HIP;
@@ -1258,8 +1596,8 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
 extern "C" {
 
 int hrom_ecm_svd(int32_t P, int32_t M, const double* xf, int32_t r, double* lam, double* sigma, double tol,
-                 int32_t max_sweeps, int32_t* sweeps, double* off_hist, hipStream_t stream) {
-    return hrom::svd_left(P, M, xf, r, lam, r, sigma, tol, max_sweeps, sweeps, off_hist, stream);
+                 int32_t max_sweeps, int32_t method, int32_t* sweeps, double* off_hist, hipStream_t stream) {
+    return hrom::svd_left(P, M, xf, r, lam, r, sigma, tol, max_sweeps, sweeps, off_hist, method, stream);
 }
 
 int hrom_ecm_select(int32_t M, int32_t r, const double* lam, double V0, int32_t mt, int32_t* z, double* w,

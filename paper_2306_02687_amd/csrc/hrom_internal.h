@@ -425,8 +425,10 @@ void set_kernel_attributes();
 
 // the r leading left singular vectors of xf^T (xf [P][M] rows) into lam with
 // row stride ld, all singular values into sigma (one-sided block Jacobi of the
-// empirical cubature, shared by the POD of the clustered training)
+// empirical cubature, shared by the POD of the clustered training); method 0:
+// Householder QR first for tall matrices (M >= 2 Ppad), 1: the sweeps on xf^T
+// itself, 2: QR first (M >= Ppad)
 int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double* sigma, double tol,
-             int max_sweeps, int* sweeps, double* off_hist, hipStream_t stream);
+             int max_sweeps, int* sweeps, double* off_hist, int method, hipStream_t stream);
 
 }  // namespace hrom

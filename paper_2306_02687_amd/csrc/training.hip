@@ -257,7 +257,7 @@ int hrom_pod(int32_t nd, int32_t s_el, const double* X_el, int32_t s_in, const d
         !X_in || !Phi || !sigma_el || !sigma_in)
         return HROM_E_INVALID;
     const int ld = n_el + n_in;
-    int rc = svd_left(s_el, nd, X_el, n_el, Phi, ld, sigma_el, 0.0, 0, nullptr, nullptr, stream);
+    int rc = svd_left(s_el, nd, X_el, n_el, Phi, ld, sigma_el, 0.0, 0, nullptr, nullptr, 0, stream);
     if (rc != HROM_OK) return rc;
     double *coef = nullptr, *Xm = nullptr;
     if (hipMalloc((void**)&coef, sizeof(double) * (size_t)s_in * n_el) != hipSuccess) return HROM_E_NOMEM;
@@ -272,7 +272,7 @@ int hrom_pod(int32_t nd, int32_t s_el, const double* X_el, int32_t s_in, const d
     if (hipGetLastError() != hipSuccess) rc = HROM_E_HIP;
     if (rc == HROM_OK)
         rc = svd_left(s_in, nd, Xm, n_in, n_in > 0 ? Phi + n_el : nullptr, ld, sigma_in, 0.0, 0, nullptr, nullptr,
-                      stream);
+                      0, stream);
     (void)hipStreamSynchronize(stream);
     (void)hipFree(coef);
     (void)hipFree(Xm);

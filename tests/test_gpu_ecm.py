@@ -76,7 +76,7 @@ def test_training_matrix(dev, orc, m, M, p):
     assert err < 1e-13 and errf < 1e-13
 
 
-def _chains(dev, orc, m, M, p, mt, seed):
+def _chains(dev, orc, m, M, p, mt, seed, method=0):
     """Oracle and GPU chains from the same inputs."""
     from paper_2306_02687_amd import binding as B
     cl = make_cluster(m, M, seed)
@@ -85,14 +85,17 @@ def _chains(dev, orc, m, M, p, mt, seed):
     xf_o, _ = orc.ecm_training_matrix(f, cl.w)
     lam_o, s_o = orc.ecm_basis(xf_o, mt - 1)
     xf, _, _ = _gpu_training(cl, Fr, a)
-    lam, sig, sweeps, _ = B.ecm_svd(xf, mt - 1)
+    lam, sig, sweeps, _ = B.ecm_svd(xf, mt - 1, method=method)
     return cl, xf_o, lam_o, s_o, lam, sig, sweeps
 
 
-@pytest.mark.parametrize("m,M,p,r", [(8, 1000, 6, 40), (6, 2100, 5, 60), (12, 1024, 8, 95)])
-def test_svd_basis(dev, orc, m, M, p, r):
-    log_case("ecm svd", m, M, p, r)
-    cl, xf_o, lam_o, s_o, lam, sig, sweeps = _chains(dev, orc, m, M, p, r + 1, 9200 + m)
+# method 1: sweeps on x_f^T itself; 2: Householder QR first, sweeps on R
+@pytest.mark.parametrize("method", [1, 2])
+@pytest.mark.parametrize("m,M,p,r", [(8, 1000, 6, 40), (6, 2100, 5, 60), (12, 1024, 8, 95),
+                                     (16, 2500, 12, 250)])
+def test_svd_basis(dev, orc, m, M, p, r, method):
+    log_case("ecm svd", m, M, p, r, method)
+    cl, xf_o, lam_o, s_o, lam, sig, sweeps = _chains(dev, orc, m, M, p, r + 1, 9200 + m, method)
     sig = sig.cpu().numpy()
     lam = lam.cpu().numpy()
     es = np.abs(sig - s_o).max() / s_o[0]
@@ -100,7 +103,7 @@ def test_svd_basis(dev, orc, m, M, p, r):
     ang = _max_angle(lam_o, lam)
     gap = (s_o[r - 1] - s_o[r]) / s_o[0]
     bound = 1e-14 / gap
-    print(f"svd P {len(s_o)} M {M} r {r}: sweeps {sweeps} sigma {es:.2e} orth {orth:.2e} "
+    print(f"svd P {len(s_o)} M {M} r {r} method {method}: sweeps {sweeps} sigma {es:.2e} orth {orth:.2e} "
           f"angle {ang:.2e} (gap {gap:.2e}, bound {bound:.2e})", flush=True)
     assert es < 1e-12 and orth < 1e-12
     assert ang < bound
@@ -242,6 +245,9 @@ def test_selection_edge_cases(dev, orc):
     big = torch.zeros((4, 1024), dtype=torch.float64, device="cuda")
     assert B.ecm_select(big, 1.0, 3, check=False)[2]["rc"] == -1         # r + 1 > 1024
     assert B.ecm_svd(xf, d + 2, check=False)[3] == -1                    # r > P
+    assert B.ecm_svd(xf, d, method=3, check=False)[3] == -1              # no such method
+    wide = torch.ones((40, 50), dtype=torch.float64, device="cuda")
+    assert B.ecm_svd(wide, 4, method=2, check=False)[3] == -1            # QR needs M >= Ppad = 64
 
 
 def test_paper_example_sizes(dev, orc):
