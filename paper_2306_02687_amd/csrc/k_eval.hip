@@ -84,6 +84,8 @@ struct KinLds {
     double sF[16 * 9][kKinPT + 1];   // F of the round, then w P in place
     double sF8[4][16][kKinPT + 1];
     double sU[9][kKinPT];
+    double sWq[16];
+    int sPh[16];
     int sbits[kKinPT];
 };
 
@@ -155,6 +157,14 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
 
     for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
         const int rt0 = (q0 / 16) * 9;
+        // weights and phases of the round's ECM points, loaded ahead of the
+        // GEMM and handed to the law through LDS
+        double wnext = 0.0;
+        int phnext = 0;
+        if (tid < QC) {
+            wnext = A.w[q0 + tid];
+            phnext = A.phase[q0 + tid];
+        }
         // ---- F - Fr: row tiles wave, wave + NW, ... < 8
 #pragma unroll
         for (int h = 0; h < 8 / NW; h++) {
@@ -194,6 +204,10 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
                 sF8[wave][g + 4 * e][16 + c] = a1[e];
             }
         }
+        if (tid < QC) {
+            L.sWq[tid] = wnext;
+            L.sPh[tid] = phnext;
+        }
         __syncthreads();
         // ---- rows 128..143 of F: fixed-order sum of the four k-range partials
         for (int e = tid; e < 16 * PT; e += NT) {
@@ -209,8 +223,8 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
             double F[9];
 #pragma unroll
             for (int I = 0; I < 9; I++) F[I] = sF[qq * 9 + I][p];
-            const double wq = A.w[q];
-            const int ph = A.phase[q];
+            const double wq = L.sWq[qq];
+            const int ph = L.sPh[qq];
             if constexpr (J2) {
                 // theta = per phase (mu, lam, sy0, H); committed state in, new state out
                 const double* mp = A.theta + 4 * ph;
