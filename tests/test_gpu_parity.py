@@ -226,12 +226,15 @@ def test_backward_vs_oracle(dev, orc, precision, split, refine):
     plan.close()
 
 
-@pytest.mark.parametrize("m,Q", [(80, 160), (96, 192)])
-@pytest.mark.parametrize("precision,split,refine", [(2, True, True), (1, True, True)])
-def test_backward_refined_beyond_64_modes(dev, orc, m, Q, precision, split, refine):
-    """The refined adjoint with more modes than lanes (rows 64.. of the
-    refinement solve on a wavefront's second register set), up to the
-    largest supported m, vs the oracle's adjoint."""
+@pytest.mark.parametrize("m,Q", [(72, 150), (80, 160), (96, 192)])
+@pytest.mark.parametrize("precision,split,refine", [(2, True, True), (1, True, True), (1, True, False),
+                                                    (2, True, False)])
+def test_backward_beyond_64_modes(dev, orc, m, Q, precision, split, refine):
+    """The adjoint with more modes than lanes, up to the largest supported m,
+    vs the oracle's adjoint: refined (rows 64.. of the refinement solve on a
+    wavefront's second register set) and unrefined (the re-evaluation's
+    BF16 three-level GEMMs over three halves of 32 modes, the last one
+    partly filled at m = 72, 80)."""
     from paper_2306_02687_amd import solve
     log_case("backward_refined", m, Q, precision, split, refine)
     N = 3
@@ -252,7 +255,7 @@ def test_backward_refined_beyond_64_modes(dev, orc, m, Q, precision, split, refi
     ref = orc.backward(cl, THETA_REF, F, ref_o["a"], 2.0 * (ref_o["Pbar"] - target))
     egF = rel_err_points(gF.cpu().numpy().T, ref["gF"])
     egt = np.linalg.norm(gth.cpu().numpy() - ref["gtheta"]) / np.linalg.norm(ref["gtheta"])
-    print("refined m", m, "prec", precision, "gF", egF.max(), "gtheta", egt, flush=True)
+    print("m", m, "prec", precision, "refine", refine, "gF", egF.max(), "gtheta", egt, flush=True)
     assert egF.max() < TOLGRAD and egt < TOLGRAD
     plan.close()
 
