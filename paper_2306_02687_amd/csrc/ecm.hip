@@ -68,12 +68,6 @@ __device__ double block_sum(double s, double* red) {
     return t;
 }
 
-// orders the LDS accesses of one wavefront's lanes (no hardware barrier)
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 // sum over a workgroup of 1024 threads (fixed order); every thread gets it
 __device__ double block_sum1024(double s, double* red) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
