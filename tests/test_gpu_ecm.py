@@ -92,7 +92,7 @@ def _chains(dev, orc, m, M, p, mt, seed, method=0):
 # method 1: sweeps on x_f^T itself; 2: Householder QR first, sweeps on R
 @pytest.mark.parametrize("method", [1, 2])
 @pytest.mark.parametrize("m,M,p,r", [(8, 1000, 6, 40), (6, 2100, 5, 60), (12, 1024, 8, 95),
-                                     (16, 2500, 12, 250)])
+                                     (16, 2500, 12, 250), (8, 150, 4, 40)])
 def test_svd_basis(dev, orc, m, M, p, r, method):
     log_case("ecm svd", m, M, p, r, method)
     cl, xf_o, lam_o, s_o, lam, sig, sweeps = _chains(dev, orc, m, M, p, r + 1, 9200 + m, method)
