@@ -479,13 +479,13 @@ def svd_sweep_flops(P, M):
 
 def svd_flops(P, M, r, sweeps):
     """FP64 flops of hrom_ecm_svd with the library's automatic method: for
-    M >= 2 Ppad the Householder QR (2 M P^2 - 2 P^3 / 3), the sweeps over the
-    P rows of R and Q applied to the r leading vectors (4 M P r - 2 P^2 r);
-    else the sweeps over the M rows."""
+    M >= 2 Ppad the Householder QR (2 M P^2 - 2 P^3 / 3), the pivoted QR of
+    the P x P factor (4 P^3 / 3), the sweeps over P rows and Q applied to the
+    r leading vectors (4 M P r - 2 P^2 r); else the sweeps over the M rows."""
     nb = max(2, -(-P // 32))
     nb += nb & 1
     if M >= 2 * 32 * nb:
-        return (2.0 * M * P * P - 2.0 * P ** 3 / 3 + sweeps * svd_sweep_flops(P, P)
+        return (2.0 * M * P * P - 2.0 * P ** 3 / 3 + 4.0 * P ** 3 / 3 + sweeps * svd_sweep_flops(P, P)
                 + 4.0 * M * P * r - 2.0 * P * P * r)
     return sweeps * svd_sweep_flops(P, M)
 

@@ -319,15 +319,18 @@ int hrom_ecm_training(int32_t m, int32_t M, const double* G, const double* w, co
  * their norms (<= 0: 1e-13); max_sweeps (<= 0: 40).  method: 1 runs the
  * one-sided Jacobi sweeps on x_f^T itself; 2 first factors x_f^T = Q R by
  * Householder reflectors (needs M >= Ppad, P rounded up to an even number of
- * 32-column blocks), sweeps the P x P factor R and returns Q times its left
- * vectors (the same singular values; every sweep over P rows in place of M);
- * 0 takes 2 when M >= 2 Ppad, else 1.  *sweeps (host, may be null) the
+ * 32-column blocks), then R^T Pi = Q2 R2 with column pivoting, sweeps the
+ * P x P matrix R2^T and returns Q Pi times its left vectors (the same
+ * singular values; every sweep over P rows in place of M, and a third of the
+ * sweeps on the pivoted triangle); 0 takes 2 when M >= 2 Ppad, else 1.  *sweeps (host, may be null) the
  * sweeps used; off_hist (host, may be null, max_sweeps entries) the largest
  * relative off-diagonal Gram entry met in each sweep.  Singular vectors are
  * determined up to sign (and rotation within equal singular values), which
  * the selection does not see.  Errors: HROM_E_INVALID (r > P, method outside
  * 0..2, method 2 with M < Ppad, ...), HROM_E_NOCONV (sweeps exhausted;
- * outputs written), HROM_E_RANK (sigma_r = 0), HROM_E_NOMEM, HROM_E_HIP. */
+ * outputs written), HROM_E_RANK (sigma_r <= max(M, P) eps sigma_1: x_f has
+ * fewer than r numerically independent directions; outputs written),
+ * HROM_E_NOMEM, HROM_E_HIP. */
 int hrom_ecm_svd(int32_t P, int32_t M, const double* xf, int32_t r, double* lam, double* sigma, double tol,
                  int32_t max_sweeps, int32_t method, int32_t* sweeps, double* off_hist, hipStream_t stream);
 

@@ -7,8 +7,10 @@
 //    snapshots per thread, the mode gradients read candidate-contiguous from
 //    a transposed copy), then per row the weighted integral f^k_i and the
 //    subtraction of f^k_i / V0.
-//  * hrom_ecm_svd: blocked one-sided Jacobi on x_f^T (columns = rows of x_f,
-//    length M): per round a tournament of disjoint pairs of 32-column blocks;
+//  * hrom_ecm_svd: for tall matrices a Householder QR x_f^T = Q R and a
+//    second, column-pivoted QR R^T Pi = Q2 R2 first (the sweeps then run on
+//    the P x P matrix R2^T); blocked one-sided Jacobi on the swept matrix:
+//    per round a tournament of disjoint pairs of 32-column blocks;
 //    for each pair the 64 x 64 Gram matrix (partial sums over row chunks,
 //    summed in a fixed order), one cyclic Jacobi sweep over it in LDS (a full
 //    inner solve cost more time than the extra outer sweep it saves), and the
@@ -487,12 +489,10 @@ __global__ void k_svd_extract(const double* A, int M, const int* perm, const dou
 // ------------------------------------------------------------------------
 // x_f^T = Q R with Q the product of Householder reflectors, in panels of kQB
 // columns applied to the rest of the matrix in the compact WY form
-// Q_k = I - V_k T_k V_k^T.  One-sided Jacobi on the P x P factor R gives the
-// same singular values (its iterates depend on the Gram matrix alone, which R
-// shares with x_f^T) with every sweep over P rows in place of M; the left
-// vectors of x_f^T are then Q times those of R.  Householder QR is backward
-// stable, so the singular values keep their absolute accuracy relative to
-// sigma_1.
+// Q_k = I - V_k T_k V_k^T.  R has the singular values of x_f^T and every
+// sweep over it touches P rows in place of M; the left vectors of x_f^T are
+// Q times those of R.  Householder QR is backward stable, so the singular
+// values keep their absolute accuracy relative to sigma_1.
 constexpr int kQB = 32;
 
 // Reflector of column j (rows j .. M-1) and its product with the panel
@@ -665,24 +665,148 @@ __global__ void __launch_bounds__(256) k_qr_update(double* __restrict__ X, const
     }
 }
 
-// R as a matrix of P rows for the sweeps: column j = (A[0 .. j-1][j], beta_j,
-// 0 ...), zero for the padding columns j >= P
-__global__ void __launch_bounds__(256) k_qr_rbuild(const double* __restrict__ A, int M, const double* beta, int P,
-                                                   int Ppad, double* __restrict__ Rm) {
+// ---- second factorisation, with column pivoting, of R^T (Drmac-Veselic
+// preconditioning): R^T Pi = Q2 R2, and the sweeps run on X = R2^T, whose
+// columns are nearly orthogonal from the start (the pivoted triangle is
+// graded), so that the quadratic phase begins within a few sweeps.  With
+// R = Pi R2^T Q2^T the left vectors of R are Pi times those of X; Q2 itself
+// is never needed.  Matrices here are stored as Ppad columns of P entries.
+
+// B[i][c] = R[i][c]: column i of B is row i of R (zero for the padding)
+__global__ void __launch_bounds__(256) k_qr_rtbuild(const double* __restrict__ A, int M, const double* beta, int P,
+                                                    int Ppad, double* __restrict__ B) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (int64_t)Ppad * P) return;
-    const int j = (int)(e / P), i = (int)(e % P);
-    Rm[e] = (j >= P || i > j) ? 0.0 : ((i == j) ? beta[j] : A[(int64_t)j * M + i]);
+    const int i = (int)(e / P), c = (int)(e % P);
+    B[e] = (i >= P || c < i) ? 0.0 : ((c == i) ? beta[i] : A[(int64_t)c * M + i]);
+}
+
+// squared norms of the columns of B, the identity permutation
+__global__ void __launch_bounds__(256) k_qrcp_init(const double* __restrict__ B, int P, double* nu, int* perm) {
+    __shared__ double red[4];
+    const double* col = B + (int64_t)blockIdx.x * P;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < P; i += 256) s += col[i] * col[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        nu[blockIdx.x] = s;
+        perm[blockIdx.x] = blockIdx.x;
+    }
+}
+
+// Step j of the pivoted QR of B (P columns of P entries): the pivot is the
+// remaining column (positions j .. P-1, physical columns through perm_in)
+// with the largest squared norm of rows j .. P-1 (nu_in, by physical column;
+// lowest position on ties), found by every workgroup alike; workgroup b
+// takes position j + b after the exchange of positions j and the pivot.
+// Workgroup 0 records beta_j (R2's diagonal) and the exchanged permutation;
+// the others apply the pivot column's reflector to their column, which no
+// workgroup of this launch reads, and record its squared norm over rows
+// j + 1 .. (nu_out).  The permutation and the norms alternate between two
+// buffers from step to step.
+__global__ void __launch_bounds__(256) k_qrcp_col(double* __restrict__ B, int P, int j, const int* __restrict__ perm_in,
+                                                  const double* __restrict__ nu_in, int* __restrict__ perm_out,
+                                                  double* __restrict__ nu_out, double* __restrict__ beta2) {
+    __shared__ double red[4];
+    __shared__ double wv[4];
+    __shared__ int wi[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double bv = -1.0;
+    int bi = INT32_MAX;
+    for (int c = j + tid; c < P; c += 256) {
+        const double v = nu_in[perm_in[c]];
+        if (v > bv) {
+            bv = v;
+            bi = c;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    if (lane == 0) {
+        wv[wave] = bv;
+        wi[wave] = bi;
+    }
+    __syncthreads();
+    double pv = wv[0];
+    int cs = wi[0];
+    for (int w = 1; w < 4; w++)
+        if (wv[w] > pv || (wv[w] == pv && wi[w] < cs)) {
+            pv = wv[w];
+            cs = wi[w];
+        }
+    const int xp = perm_in[cs];
+    const int pos = j + blockIdx.x;
+    const int yp = (pos == j) ? xp : ((pos == cs) ? perm_in[j] : perm_in[pos]);
+    const double* x = B + (int64_t)xp * P;
+    double* y = B + (int64_t)yp * P;
+    const double x1 = x[j], y1 = y[j];
+    double s = 0.0;
+    for (int i = j + 1 + tid; i < P; i += 256) s += x[i] * x[i];
+    const double sg = block_sum(s, red);
+    double t = 0.0, b = x1, sc = 0.0;
+    if (sg > 0.0) {
+        const double nrm = sqrt(x1 * x1 + sg);
+        b = (x1 >= 0.0) ? -nrm : nrm;
+        t = (b - x1) / b;
+        sc = 1.0 / (x1 - b);
+    }
+    if (blockIdx.x == 0) {
+        if (tid == 0) beta2[j] = b;
+        for (int c = tid; c < P; c += 256) perm_out[c] = (c == j) ? xp : ((c == cs) ? perm_in[j] : perm_in[c]);
+        return;
+    }
+    double f = 0.0;
+    if (t != 0.0) {
+        double d = 0.0;
+        for (int i = j + 1 + tid; i < P; i += 256) d += x[i] * y[i];
+        f = t * (y1 + sc * block_sum(d, red));
+    }
+    double s2 = 0.0;
+    for (int i = j + 1 + tid; i < P; i += 256) {
+        const double yn = y[i] - f * (x[i] * sc);
+        y[i] = yn;
+        s2 += yn * yn;
+    }
+    s2 = block_sum(s2, red);
+    if (tid == 0) {
+        y[j] = y1 - f;
+        nu_out[yp] = s2;
+    }
+}
+
+// X = R2^T for the sweeps: column i = row i of R2 over the positions,
+// (0 .. 0, beta2_i, B[perm[c]][i] for c > i); zero padding columns
+__global__ void __launch_bounds__(256) k_qrcp_xbuild(const double* __restrict__ B, int P, int Ppad, const int* perm,
+                                                     const double* beta2, double* __restrict__ X) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)Ppad * P) return;
+    const int i = (int)(e / P), c = (int)(e % P);
+    X[e] = (i >= P || c < i) ? 0.0 : ((c == i) ? beta2[i] : B[(int64_t)perm[c] * P + i]);
+}
+
+// inverse of the final permutation
+__global__ void __launch_bounds__(256) k_qrcp_iperm(const int* perm, int P, int* iperm) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < P) iperm[perm[c]] = c;
 }
 
 // X[j][i] = R-side left vector j: column perm[j] of the swept matrix (MJ rows)
-// over sigma_j, zero for rows i >= MJ (j < r)
+// over sigma_j at its row iperm[i] (i itself without iperm), zero for rows
+// i >= MJ (j < r)
 __global__ void __launch_bounds__(256) k_qr_xinit(const double* __restrict__ Jm, int MJ, const int* perm,
-                                                  const double* sig, int r, int M, double* __restrict__ X) {
+                                                  const double* sig, const int* iperm, int r, int M,
+                                                  double* __restrict__ X) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (int64_t)r * M) return;
     const int j = (int)(e / M), i = (int)(e % M);
-    X[e] = (i < MJ) ? Jm[(int64_t)perm[j] * MJ + i] / sig[j] : 0.0;
+    X[e] = (i < MJ) ? Jm[(int64_t)perm[j] * MJ + (iperm ? iperm[i] : i)] / sig[j] : 0.0;
 }
 
 // lam[g][j] = X[j][g] (row stride ld)
@@ -1461,7 +1585,9 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
                  round256(sizeof(double) * (size_t)std::max(r, 1) * M) +
                  round256(sizeof(double) * (size_t)(Ppad / kQB) * qmax * kQB * kQB) +
                  2 * round256(sizeof(double) * (size_t)kQB * Ppad) +
-                 round256(sizeof(double) * (size_t)npan * kQB * kQB) + 2 * round256(sizeof(double) * Ppad) + 2048;
+                 round256(sizeof(double) * (size_t)npan * kQB * kQB) + 3 * round256(sizeof(double) * Ppad) +
+                 round256(sizeof(double) * (size_t)Ppad * P) + 2 * round256(sizeof(double) * P) +
+                 3 * round256(sizeof(int) * P) + 4096;
     if (ar.alloc(bytes) != HROM_OK) return HROM_E_NOMEM;
     double* A = ar.take<double>((size_t)Ppad * M);
     int2* dsched = ar.take<int2>(sched.size());
@@ -1475,7 +1601,9 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
     int2* pver = ar.take<int2>(sched.size());
     int* apply = ar.take<int>(npairs);
     double *V = nullptr, *Rm = nullptr, *X = nullptr, *qpart = nullptr, *Z = nullptr, *Wt = nullptr,
-           *Tall = nullptr, *tau = nullptr, *beta = nullptr;
+           *Tall = nullptr, *tau = nullptr, *beta = nullptr, *Bq = nullptr, *nu[2] = {nullptr, nullptr},
+           *beta2 = nullptr;
+    int *pm[2] = {nullptr, nullptr}, *iperm = nullptr;
     if (qr) {
         V = ar.take<double>((size_t)Ppad * M);
         Rm = ar.take<double>((size_t)Ppad * P);
@@ -1486,6 +1614,13 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
         Tall = ar.take<double>((size_t)npan * kQB * kQB);
         tau = ar.take<double>(Ppad);
         beta = ar.take<double>(Ppad);
+        Bq = ar.take<double>((size_t)Ppad * P);
+        nu[0] = ar.take<double>(P);
+        nu[1] = ar.take<double>(P);
+        beta2 = ar.take<double>(Ppad);
+        pm[0] = ar.take<int>(P);
+        pm[1] = ar.take<int>(P);
+        iperm = ar.take<int>(P);
     }
     if (hipMemcpyAsync(A, xf, sizeof(double) * (size_t)P * M, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
         hipMemsetAsync(A + (size_t)P * M, 0, sizeof(double) * (size_t)(Ppad - P) * M, stream) != hipSuccess ||
@@ -1525,9 +1660,18 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
             // the trailing columns: A <- Q_p^T A
             if (P > j1) panel_apply(pn, A + (size_t)j1 * M, P - j1, 1);
         }
+        // R^T Pi = Q2 R2 by Householder reflectors with column pivoting, one
+        // launch per column; the sweeps then run on X = R2^T
         const int64_t nr = (int64_t)Ppad * P;
-        hipLaunchKernelGGL(k_qr_rbuild, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, stream, A, M, beta, P, Ppad,
-                           Rm);
+        const unsigned gr = (unsigned)((nr + 255) / 256);
+        hipLaunchKernelGGL(k_qr_rtbuild, dim3(gr), dim3(256), 0, stream, A, M, beta, P, Ppad, Bq);
+        hipLaunchKernelGGL(k_qrcp_init, dim3(P), dim3(256), 0, stream, Bq, P, nu[0], pm[0]);
+        for (int j = 0; j < P; j++)
+            hipLaunchKernelGGL(k_qrcp_col, dim3(P - j), dim3(256), 0, stream, Bq, P, j, pm[j & 1], nu[j & 1],
+                               pm[(j + 1) & 1], nu[(j + 1) & 1], beta2);
+        const int* pfin = pm[P & 1];
+        hipLaunchKernelGGL(k_qrcp_xbuild, dim3(gr), dim3(256), 0, stream, Bq, P, Ppad, pfin, beta2, Rm);
+        hipLaunchKernelGGL(k_qrcp_iperm, dim3((P + 255) / 256), dim3(256), 0, stream, pfin, P, iperm);
         if (launched() != HROM_OK) return HROM_E_HIP;
         Jm = Rm;
     }
@@ -1560,10 +1704,11 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
     hipLaunchKernelGGL(k_svd_rank, dim3((P + 255) / 256), dim3(256), 0, stream, sig, P, perm, sig_sorted);
     if (r > 0) {
         if (qr) {
-            // left vectors of x_f^T = Q [U_R; 0]: the panels in reverse order
+            // left vectors of x_f^T = Q [Pi U_X; 0]: the rows of X's vectors
+            // put back in R's row order, then the panels in reverse order
             const int64_t nx = (int64_t)r * M;
             hipLaunchKernelGGL(k_qr_xinit, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, stream, Jm, MJ, perm,
-                               sig_sorted, r, M, X);
+                               sig_sorted, iperm, r, M, X);
             for (int pn = npan - 1; pn >= 0; pn--) panel_apply(pn, X, r, 0);
             hipLaunchKernelGGL(k_qr_out, dim3((M + 31) / 32, (r + 31) / 32), dim3(32, 8), 0, stream, X, M, r, lam,
                                ld);
@@ -1575,14 +1720,17 @@ int svd_left(int P, int M, const double* xf, int r, double* lam, int ld, double*
     if (launched() != HROM_OK) return HROM_E_HIP;
     if (hipMemcpyAsync(sigma, sig_sorted, sizeof(double) * P, hipMemcpyDeviceToDevice, stream) != hipSuccess)
         return HROM_E_HIP;
-    double sr = 1.0;
+    // numerical rank: sigma_r at or below max(M, P) eps sigma_1 carries no
+    // direction of the data
+    double sr = 1.0, s1 = 1.0;
     if (r > 0 && (hipMemcpyAsync(&sr, sig_sorted + (r - 1), sizeof(double), hipMemcpyDeviceToHost, stream) !=
                       hipSuccess ||
+                  hipMemcpyAsync(&s1, sig_sorted, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
                   hipStreamSynchronize(stream) != hipSuccess))
         return HROM_E_HIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return HROM_E_HIP;
     if (!conv) return HROM_E_NOCONV;
-    if (!(sr > 0.0)) return HROM_E_RANK;
+    if (!(sr > (double)std::max(M, P) * std::numeric_limits<double>::epsilon() * s1)) return HROM_E_RANK;
     return HROM_OK;
 }
 }  // namespace hrom
