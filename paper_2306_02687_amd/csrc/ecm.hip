@@ -1049,7 +1049,8 @@ __device__ void residual(const SelArgs& A, int n, StepLds& L) {
 
 // c = Q_n^T b = V0 Q[r][.]; z = R^{-1} c by blocks of 64 rows from the
 // bottom: the diagonal block in LDS, solved by wavefront 0 with the solution
-// in lane registers, then the rows above updated a wavefront per row; and
+// in lane registers (the pivots' reciprocals formed lane-parallel), then the
+// rows above updated a thread per row; and
 // res = b - Q_n c
 __device__ void qr_solve(const SelArgs& A, int n, StepLds& L, bool want_res) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r = A.r, r1 = r + 1, mt = A.mt;
@@ -1067,11 +1068,14 @@ __device__ void qr_solve(const SelArgs& A, int n, StepLds& L, bool want_res) {
         }
         __syncthreads();
         if (wave == 0) {
-            // lane l holds row b0 + l: its right-hand side, then its solution
+            // lane l holds row b0 + l: its right-hand side, then its solution;
+            // the pivots' reciprocals are formed first, one per lane, so that
+            // each step of the chain is a product and a broadcast
             double rhs = (lane < bs) ? L.cw[b0 + lane] : 0.0;
+            const double dinv = (lane < bs) ? 1.0 / L.D[lane][lane] : 0.0;
             double zl = 0.0;
             for (int ii = bs - 1; ii >= 0; ii--) {
-                const double zi = readlane_d(rhs / L.D[ii][ii], ii);
+                const double zi = readlane_d(rhs * dinv, ii);
                 if (lane == ii) zl = zi;
                 if (lane < ii) rhs -= L.D[lane][ii] * zi;
             }
