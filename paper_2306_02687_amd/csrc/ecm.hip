@@ -495,6 +495,21 @@ __global__ void k_svd_extract(const double* A, int M, const int* perm, const dou
 // values keep their absolute accuracy relative to sigma_1.
 constexpr int kQB = 32;
 
+// Householder reflector of a column with head x1 and squared tail norm sg:
+// H = I - t v v^T with v = (1, sc x_tail) maps the column to b e_1; t = 0
+// (H = I) when the tail is zero
+__device__ __forceinline__ void reflector(double x1, double sg, double& b, double& t, double& sc) {
+    t = 0.0;
+    b = x1;
+    sc = 0.0;
+    if (sg > 0.0) {
+        const double nrm = sqrt(x1 * x1 + sg);
+        b = (x1 >= 0.0) ? -nrm : nrm;
+        t = (b - x1) / b;
+        sc = 1.0 / (x1 - b);
+    }
+}
+
 // Reflector of column j (rows j .. M-1) and its product with the panel
 // columns j + 1 .. j + gridDim.x - 1: workgroup b handles column j + b.  Every
 // workgroup forms the reflector from column j, which no workgroup of this
@@ -512,13 +527,8 @@ __global__ void __launch_bounds__(1024) k_qr_col(double* __restrict__ A, int M, 
 #pragma unroll 4
     for (int i = j + 1 + tid; i < M; i += 1024) s += x[i] * x[i];
     const double sg = block_sum1024(s, red);
-    double t = 0.0, b = x1, sc = 0.0;
-    if (sg > 0.0) {
-        const double nrm = sqrt(x1 * x1 + sg);
-        b = (x1 >= 0.0) ? -nrm : nrm;
-        t = (b - x1) / b;
-        sc = 1.0 / (x1 - b);
-    }
+    double t, b, sc;
+    reflector(x1, sg, b, t, sc);
     if (blockIdx.x == 0) {
         double* v = V + (int64_t)j * M;
         for (int i = tid; i < M; i += 1024) v[i] = (i < j) ? 0.0 : ((i == j) ? 1.0 : x[i] * sc);
@@ -750,13 +760,8 @@ __global__ void __launch_bounds__(256) k_qrcp_col(double* __restrict__ B, int P,
     double s = 0.0;
     for (int i = j + 1 + tid; i < P; i += 256) s += x[i] * x[i];
     const double sg = block_sum(s, red);
-    double t = 0.0, b = x1, sc = 0.0;
-    if (sg > 0.0) {
-        const double nrm = sqrt(x1 * x1 + sg);
-        b = (x1 >= 0.0) ? -nrm : nrm;
-        t = (b - x1) / b;
-        sc = 1.0 / (x1 - b);
-    }
+    double t, b, sc;
+    reflector(x1, sg, b, t, sc);
     if (blockIdx.x == 0) {
         if (tid == 0) beta2[j] = b;
         for (int c = tid; c < P; c += 256) perm_out[c] = (c == j) ? xp : ((c == cs) ? perm_in[j] : perm_in[c]);
