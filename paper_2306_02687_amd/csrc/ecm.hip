@@ -1116,8 +1116,8 @@ __device__ void qr_solve(const SelArgs& A, int n, StepLds& L, bool want_res) {
 // addressed through the position -> physical column map, so no column moves;
 // the freed physical column is reused by a later append), Q's columns j ..
 // n-1 rotate alike and the last drops; the position arrays shift left
+template <int T>   // positions per lane: T >= ceil(mt / 64)
 __device__ void qr_remove(const SelArgs& A, int j, int n, StepLds& L) {
-    constexpr int T = kMaxRows / 64;   // positions per lane
     const int tid = threadIdx.x, lane = tid & 63, r1 = A.r + 1, mt = A.mt;
     // the map without position j: chunks of 256 positions from the left,
     // each read completely before it is written (the next chunk reads only
@@ -1217,7 +1217,9 @@ __device__ void finish(const SelArgs& A, int err) {
     }
 }
 
-// steps 1 (argmax of the partial maxima) to 7 of one greedy iteration
+// steps 1 (argmax of the partial maxima) to 7 of one greedy iteration; T:
+// positions per lane of the column removal (8 for mt <= 512, else 16)
+template <int T>
 __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
     if (A.st->done) return;
     __shared__ StepLds L;
@@ -1379,7 +1381,7 @@ __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
                         }
                         nz++;
                         __syncthreads();
-                        qr_remove(A, c, n, L);
+                        qr_remove<T>(A, c, n, L);
                         n--;
                     }
                 }
@@ -1797,7 +1799,8 @@ int hrom_ecm_select(int32_t M, int32_t r, const double* lam, double V0, int32_t 
     for (;;) {
         for (int b = 0; b < 32; b++) {
             hipLaunchKernelGGL(k_sel_score, dim3(nb), dim3(256), 0, stream, A);
-            hipLaunchKernelGGL(k_sel_step, dim3(1), dim3(256), 0, stream, A);
+            if (mt <= 512) hipLaunchKernelGGL(k_sel_step<8>, dim3(1), dim3(256), 0, stream, A);
+            else hipLaunchKernelGGL(k_sel_step<16>, dim3(1), dim3(256), 0, stream, A);
         }
         launched_iters += 32;
         if (launched() != HROM_OK) return HROM_E_HIP;
