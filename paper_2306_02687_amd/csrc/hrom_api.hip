@@ -157,6 +157,7 @@ size_t plan_carve(Plan& p, char* base) {
             d.Gb3 = nullptr;
         }
         take(d.gram, (int64_t)d.m * d.m);
+        take(d.gram_part, (int64_t)((d.Q + kGramChunk - 1) / kGramChunk) * d.m * d.m);
         take(d.R, (int64_t)d.m * d.m);
         take(d.Rinv, (int64_t)d.m * d.m);
         take(d.Gt, (int64_t)d.Q * 9 * d.m);
@@ -210,7 +211,7 @@ void plan_build(const Plan& p, const hrom_cluster* clusters, hipStream_t s) {
     for (int c = 0; c < p.ncl; c++) {
         const hrom_cluster& k = clusters[c];
         const ClusterDev& d = p.cl[c];
-        BasisArgs ba{d.m, d.Q, k.G, k.w, d.gram, d.R, d.Rinv, d.Gt, p.basis_flag};
+        BasisArgs ba{d.m, d.Q, k.G, k.w, d.gram, d.gram_part, d.R, d.Rinv, d.Gt, p.basis_flag};
         launch_basis_build(ba, s);
         LayoutArgs la{};
         la.m = d.m; la.Q = d.Q; la.Qpad = d.Qpad; la.MT = d.MT; la.MP = d.MP; la.prec = p.prec;

@@ -11,6 +11,7 @@
 namespace hrom {
 
 constexpr int kMaxModes = 96;   // m <= 96
+constexpr int kGramChunk = 512; // ECM points per partial sum of the basis Gram matrix
 
 // Per-point K-hat record.  FP64 path: the upper 16 x 16 accumulator tiles of
 // the augmented contraction over Ghat = [G | I_9 | 0], MT (MT + 1) / 2 tiles of
@@ -75,6 +76,7 @@ struct ClusterDev {
     // weighted gradient inner product, Gt = G R^{-1} (every layout above is
     // built from Gt), at = R a
     double* gram;          // [m][m]
+    double* gram_part;     // [ceil(Q / kGramChunk)][m][m] partial sums of the Gram matrix
     double* R;             // [m][m] upper triangular
     double* Rinv;          // [m][m] upper triangular
     double* Gt;            // [Q][9][m]
@@ -341,6 +343,7 @@ struct BasisArgs {
     const double* G;       // caller's [Q][9][m]
     const double* w;       // caller's [Q]
     double* gram;
+    double* gram_part;     // [ceil(Q / kGramChunk)][m][m] partial Gram matrices
     double* R;
     double* Rinv;
     double* Gt;

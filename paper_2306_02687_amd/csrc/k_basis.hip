@@ -18,21 +18,31 @@ namespace hrom {
 
 static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// Gram[i][j] = sum_q w_q sum_I G[q][I][i] G[q][I][j], one thread per (i, j),
-// a fixed summation order.
-__global__ void __launch_bounds__(256) k_gram(const double* G, const double* w, int m, int Q,
-                                              double* gram) {
+// Gram[i][j] = sum_q w_q sum_I G[q][I][i] G[q][I][j]: partial sums over
+// chunks of kGramChunk ECM points (blockIdx.y), one thread per (i, j), then
+// the chunks summed in order, so the summation order is fixed
+__global__ void __launch_bounds__(256) k_gram_part(const double* G, const double* w, int m, int Q,
+                                                   double* part) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m * m) return;
     const int i = t / m, j = t % m;
+    const int q0 = blockIdx.y * kGramChunk, q1 = min(Q, q0 + kGramChunk);
     double s = 0.0;
-    for (int q = 0; q < Q; q++) {
+    for (int q = q0; q < q1; q++) {
         double sq = 0.0;
 #pragma unroll
         for (int I = 0; I < 9; I++)
             sq = fma(G[((int64_t)q * 9 + I) * m + i], G[((int64_t)q * 9 + I) * m + j], sq);
         s = fma(w[q], sq, s);
     }
+    part[(int64_t)blockIdx.y * m * m + t] = s;
+}
+
+__global__ void __launch_bounds__(256) k_gram_sum(const double* part, int mm, int nchunk, double* gram) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= mm) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunk; c++) s += part[(int64_t)c * mm + t];
     gram[t] = s;
 }
 
@@ -105,8 +115,11 @@ __global__ void __launch_bounds__(256) k_basis_apply(const double* G, const doub
 }
 
 void launch_basis_build(const BasisArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_gram, dim3(nblocks((int64_t)a.m * a.m, 256)), dim3(256), 0, s, a.G, a.w,
-                       a.m, a.Q, a.gram);
+    const int nchunk = (a.Q + kGramChunk - 1) / kGramChunk;
+    hipLaunchKernelGGL(k_gram_part, dim3(nblocks((int64_t)a.m * a.m, 256), nchunk), dim3(256), 0, s, a.G, a.w,
+                       a.m, a.Q, a.gram_part);
+    hipLaunchKernelGGL(k_gram_sum, dim3(nblocks((int64_t)a.m * a.m, 256)), dim3(256), 0, s,
+                       (const double*)a.gram_part, a.m * a.m, nchunk, a.gram);
     const size_t lds = sizeof(double) * ((size_t)a.m * a.m + 1);
     hipLaunchKernelGGL(k_basis_factor, dim3(1), dim3(256), lds, s, (const double*)a.gram, a.m, a.R,
                        a.Rinv, a.flag);
