@@ -833,6 +833,22 @@ __global__ void k_qr_out(const double* __restrict__ X, int M, int r, double* __r
 // Box 1 greedy
 // ------------------------------------------------------------------------
 constexpr int kMaxRows = 1024;   // r + 1 <= 1024, mt <= r + 1
+constexpr int kStepThreads = 512; // workgroup of the one-workgroup step
+constexpr int kStepWaves = kStepThreads / 64;
+
+// sum over the step's workgroup (fixed order); every thread gets the sum
+__device__ double step_sum(double s, double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    s = wave_sum(s);
+    __syncthreads();
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kStepWaves; w++) t += red[w];
+    __syncthreads();
+    return t;
+}
 
 struct State {
     int n;        // selected points (columns of the QR)
@@ -955,14 +971,14 @@ struct StepLds {
     int zl[kMaxRows];       // NNLS: candidates outside the passive set
     int zst[kMaxRows];      //       their pick stamps
     int zbl[kMaxRows];      //       blocked flags
-    double red[4];
+    double red[kStepWaves];
     double bsc;
     int bidx;
 };
 
 // v <- j_k = [lam_k; 1]
 __device__ void load_col(const SelArgs& A, int k, StepLds& L) {
-    for (int i = threadIdx.x; i <= A.r; i += 256) L.v[i] = (i < A.r) ? A.lam[(int64_t)k * A.r + i] : 1.0;
+    for (int i = threadIdx.x; i <= A.r; i += kStepThreads) L.v[i] = (i < A.r) ? A.lam[(int64_t)k * A.r + i] : 1.0;
     __syncthreads();
 }
 
@@ -991,7 +1007,7 @@ __device__ __forceinline__ double qrow_dot(const double* Q, int r1, int i, int n
 // then v <- v - Q_n h (a thread per row)
 __device__ void project(const SelArgs& A, int n, StepLds& L, double* h) {
     const int tid = threadIdx.x, r1 = A.r + 1;
-    for (int c = tid; c < n; c += 256) {
+    for (int c = tid; c < n; c += kStepThreads) {
         const double* q = A.Q + (int64_t)c * r1;
         double s0 = 0.0, s1 = 0.0;
         int i = 0;
@@ -1009,7 +1025,7 @@ __device__ void project(const SelArgs& A, int n, StepLds& L, double* h) {
         h[c] = s0 + s1;
     }
     __syncthreads();
-    for (int i = tid; i < r1; i += 256) L.v[i] -= qrow_dot(A.Q, r1, i, n, h);
+    for (int i = tid; i < r1; i += kStepThreads) L.v[i] -= qrow_dot(A.Q, r1, i, n, h);
     __syncthreads();
 }
 
@@ -1018,23 +1034,23 @@ __device__ void project(const SelArgs& A, int n, StepLds& L, double* h) {
 __device__ double qr_append(const SelArgs& A, int n, StepLds& L) {
     const int tid = threadIdx.x, r1 = A.r + 1;
     double s = 0.0;
-    for (int i = tid; i < r1; i += 256) s += L.v[i] * L.v[i];
-    const double vn = sqrt(block_sum(s, L.red));
+    for (int i = tid; i < r1; i += kStepThreads) s += L.v[i] * L.v[i];
+    const double vn = sqrt(step_sum(s, L.red));
     project(A, n, L, L.h);
     s = 0.0;
-    for (int i = tid; i < r1; i += 256) s += L.v[i] * L.v[i];
-    double rho = sqrt(block_sum(s, L.red));
+    for (int i = tid; i < r1; i += kStepThreads) s += L.v[i] * L.v[i];
+    double rho = sqrt(step_sum(s, L.red));
     if (n > 0 && rho < 0.7071067811865476 * vn) {   // second Gram-Schmidt pass
         project(A, n, L, L.h2);
-        for (int c = tid; c < n; c += 256) L.h[c] += L.h2[c];
+        for (int c = tid; c < n; c += kStepThreads) L.h[c] += L.h2[c];
         s = 0.0;
-        for (int i = tid; i < r1; i += 256) s += L.v[i] * L.v[i];
-        rho = sqrt(block_sum(s, L.red));
+        for (int i = tid; i < r1; i += kStepThreads) s += L.v[i] * L.v[i];
+        rho = sqrt(step_sum(s, L.red));
     }
     const int slot = (L.nfree > 0) ? L.cf[L.nfree - 1] : n;
     const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
-    for (int i = tid; i < r1; i += 256) A.Q[(int64_t)n * r1 + i] = L.v[i] * inv;
-    for (int c = tid; c < n; c += 256) A.R[(int64_t)c * A.mt + slot] = L.h[c];
+    for (int i = tid; i < r1; i += kStepThreads) A.Q[(int64_t)n * r1 + i] = L.v[i] * inv;
+    for (int c = tid; c < n; c += kStepThreads) A.R[(int64_t)c * A.mt + slot] = L.h[c];
     __syncthreads();
     if (tid == 0) {
         A.R[(int64_t)n * A.mt + slot] = rho;
@@ -1048,7 +1064,7 @@ __device__ double qr_append(const SelArgs& A, int n, StepLds& L) {
 // res = b - Q_n c with c = Q_n^T b as left by the last qr_solve
 __device__ void residual(const SelArgs& A, int n, StepLds& L) {
     const int tid = threadIdx.x, r = A.r, r1 = r + 1;
-    for (int i = tid; i < r1; i += 256) L.res[i] = ((i == r) ? A.V0 : 0.0) - qrow_dot(A.Q, r1, i, n, L.c);
+    for (int i = tid; i < r1; i += kStepThreads) L.res[i] = ((i == r) ? A.V0 : 0.0) - qrow_dot(A.Q, r1, i, n, L.c);
     __syncthreads();
 }
 
@@ -1059,7 +1075,7 @@ __device__ void residual(const SelArgs& A, int n, StepLds& L) {
 // res = b - Q_n c
 __device__ void qr_solve(const SelArgs& A, int n, StepLds& L, bool want_res) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r = A.r, r1 = r + 1, mt = A.mt;
-    for (int c = tid; c < n; c += 256) {
+    for (int c = tid; c < n; c += kStepThreads) {
         const double cv = A.V0 * A.Q[(int64_t)c * r1 + r];
         L.c[c] = cv;
         L.cw[c] = cv;
@@ -1067,7 +1083,7 @@ __device__ void qr_solve(const SelArgs& A, int n, StepLds& L, bool want_res) {
     __syncthreads();
     for (int b1 = n; b1 > 0; b1 -= 64) {
         const int b0 = max(0, b1 - 64), bs = b1 - b0;
-        for (int e = tid; e < 64 * 64; e += 256) {
+        for (int e = tid; e < 64 * 64; e += kStepThreads) {
             const int ii = e >> 6, jj = e & 63;
             L.D[ii][jj] = (ii < bs && jj < bs && jj >= ii) ? A.R[(int64_t)(b0 + ii) * mt + L.cm[b0 + jj]] : 0.0;
         }
@@ -1089,7 +1105,7 @@ __device__ void qr_solve(const SelArgs& A, int n, StepLds& L, bool want_res) {
         __syncthreads();
         // rows above the block: cw_i -= sum_j R[i][j] z_j over the block's
         // columns (a thread per row, 16 loads in flight)
-        for (int i = tid; i < b0; i += 256) {
+        for (int i = tid; i < b0; i += kStepThreads) {
             const double* Ri = A.R + (int64_t)i * mt;
             double s0 = 0.0, s1 = 0.0;
             int jj = 0;
@@ -1119,11 +1135,11 @@ __device__ void qr_solve(const SelArgs& A, int n, StepLds& L, bool want_res) {
 template <int T>   // positions per lane: T >= ceil(mt / 64)
 __device__ void qr_remove(const SelArgs& A, int j, int n, StepLds& L) {
     const int tid = threadIdx.x, lane = tid & 63, r1 = A.r + 1, mt = A.mt;
-    // the map without position j: chunks of 256 positions from the left,
+    // the map without position j: chunks of kStepThreads positions from the left,
     // each read completely before it is written (the next chunk reads only
     // positions right of it)
     const int freed = L.cm[j];
-    for (int p0 = j; p0 < n - 1; p0 += 256) {
+    for (int p0 = j; p0 < n - 1; p0 += kStepThreads) {
         int cm_n = 0, zs_n = 0, st_n = 0;
         double xw_n = 0.0;
         const int p = p0 + tid;
@@ -1194,7 +1210,7 @@ __device__ void qr_remove(const SelArgs& A, int j, int n, StepLds& L) {
         }
     }
     __syncthreads();
-    for (int i = tid; i < r1; i += 256) {
+    for (int i = tid; i < r1; i += kStepThreads) {
         double q = A.Q[(int64_t)j * r1 + i];
         double q1 = (j + 1 < n) ? A.Q[(int64_t)(j + 1) * r1 + i] : 0.0;
         double q2 = (j + 2 < n) ? A.Q[(int64_t)(j + 2) * r1 + i] : 0.0;
@@ -1220,7 +1236,7 @@ __device__ void finish(const SelArgs& A, int err) {
 // steps 1 (argmax of the partial maxima) to 7 of one greedy iteration; T:
 // positions per lane of the column removal (8 for mt <= 512, else 16)
 template <int T>
-__global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
+__global__ void __launch_bounds__(kStepThreads) k_sel_step(SelArgs A) {
     if (A.st->done) return;
     __shared__ StepLds L;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r = A.r, r1 = r + 1;
@@ -1228,7 +1244,7 @@ __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
     {
         double b = -INFINITY;
         int bi = INT32_MAX;
-        for (int e = tid; e < A.nb; e += 256) {
+        for (int e = tid; e < A.nb; e += kStepThreads) {
             const double s = A.pscore[e];
             const int i = A.pidx[e];
             if (s > b || (s == b && i < bi)) {
@@ -1245,21 +1261,21 @@ __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
                 bi = oi;
             }
         }
-        __shared__ double wb[4];
-        __shared__ int wi[4];
+        __shared__ double wb[kStepWaves];
+        __shared__ int wi[kStepWaves];
         if (lane == 0) {
             wb[wave] = b;
             wi[wave] = bi;
         }
         __syncthreads();
         if (tid == 0) {
-            for (int w = 1; w < 4; w++)
+            for (int w = 1; w < kStepWaves; w++)
                 if (wb[w] > b || (wb[w] == b && wi[w] < bi)) {
                     b = wb[w];
                     bi = wi[w];
                 }
             if (!(b > -INFINITY)) {
-                for (int w = 0; w < 4; w++)
+                for (int w = 0; w < kStepWaves; w++)
                     if (wi[w] < bi) bi = wi[w];
             }
             L.bidx = bi;
@@ -1274,14 +1290,14 @@ __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
         return;
     }
     // the selection's state into LDS
-    for (int c = tid; c < n; c += 256) {
+    for (int c = tid; c < n; c += kStepThreads) {
         L.zs[c] = A.zsel[c];
         L.st[c] = A.stamp[c];
         L.cm[c] = A.cmap[c];
         L.xw[c] = A.x[c];
     }
     const int nf0 = A.st->nfree;
-    for (int c = tid; c < nf0; c += 256) L.cf[c] = A.cfree[c];
+    for (int c = tid; c < nf0; c += kStepThreads) L.cf[c] = A.cfree[c];
     if (tid == 0) L.nfree = nf0;
     __syncthreads();
     // ---- step 2
@@ -1303,11 +1319,11 @@ __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
     qr_solve(A, n, L, false);
     // ---- step 4
     int neg = 0;
-    for (int c = tid; c < n; c += 256) neg |= (L.z[c] < 0.0) ? 1 : 0;
+    for (int c = tid; c < n; c += kStepThreads) neg |= (L.z[c] < 0.0) ? 1 : 0;
     neg = __syncthreads_or(neg);
     int ndrop = 0;
     if (!neg) {
-        for (int c = tid; c < n; c += 256) L.xw[c] = L.z[c];
+        for (int c = tid; c < n; c += kStepThreads) L.xw[c] = L.z[c];
         residual(A, n, L);
     } else {
         // ---- steps 5 and 6: Lawson-Hanson NNLS, warm start at the previous
@@ -1316,11 +1332,11 @@ __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
         // dual entry j_k . res being its positive score -- and the inner loop
         // starts from the least-squares solution of step 3
         double cmax = 1.0;
-        for (int c = tid; c < n; c += 256) cmax = fmax(cmax, A.csum[L.zs[c]]);
+        for (int c = tid; c < n; c += kStepThreads) cmax = fmax(cmax, A.csum[L.zs[c]]);
         for (int o = 32; o >= 1; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
         if (lane == 0) L.red[wave] = cmax;
         __syncthreads();
-        cmax = fmax(fmax(L.red[0], L.red[1]), fmax(L.red[2], L.red[3]));
+        for (int w = 0; w < kStepWaves; w++) cmax = fmax(cmax, L.red[w]);
         __syncthreads();
         const double tol = 1e-13 * cmax * fmax(1.0, fabs(A.V0));
         int nz = 0;
@@ -1333,11 +1349,11 @@ __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
             // inner loop: z is the least-squares solution on the passive set
             while (guard-- > 0) {
                 int allpos = 1;
-                for (int c = tid; c < n; c += 256) allpos &= (L.z[c] > 0.0) ? 1 : 0;
+                for (int c = tid; c < n; c += kStepThreads) allpos &= (L.z[c] > 0.0) ? 1 : 0;
                 allpos = __syncthreads_and(allpos);
                 if (allpos) {
-                    for (int c = tid; c < n; c += 256) L.xw[c] = L.z[c];
-                    for (int e = tid; e < nz; e += 256) L.zbl[e] = 0;
+                    for (int c = tid; c < n; c += kStepThreads) L.xw[c] = L.z[c];
+                    for (int e = tid; e < nz; e += kStepThreads) L.zbl[e] = 0;
                     __syncthreads();
                     break;
                 }
@@ -1365,7 +1381,7 @@ __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
                 }
                 __syncthreads();
                 const double al = L.bsc;
-                for (int c = tid; c < n; c += 256) {
+                for (int c = tid; c < n; c += kStepThreads) {
                     const bool at = !(L.z[c] > 0.0) && (L.xw[c] / (L.xw[c] - L.z[c]) == al);
                     const double nx = L.xw[c] + al * (L.z[c] - L.xw[c]);
                     L.xw[c] = (at || !(nx > 0.0)) ? 0.0 : nx;
@@ -1385,13 +1401,13 @@ __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
                         n--;
                     }
                 }
-                for (int e = tid; e < nz; e += 256) L.zbl[e] = 0;
+                for (int e = tid; e < nz; e += kStepThreads) L.zbl[e] = 0;
                 __syncthreads();
                 qr_solve(A, n, L, false);
             }
             residual(A, n, L);     // c of the passive set is left by the last solve
             // outer: the dual entry of every non-passive, unblocked candidate
-            for (int e = wave; e < nz; e += 4) {
+            for (int e = wave; e < nz; e += kStepWaves) {
                 double sg = 0.0;
                 if (!L.zbl[e]) {
                     const double* lk = A.lam + (int64_t)L.zl[e] * r;
@@ -1455,14 +1471,14 @@ __global__ void __launch_bounds__(256) k_sel_step(SelArgs A) {
     }
     // ---- step 7
     __syncthreads();
-    for (int c = tid; c < n; c += 256) {
+    for (int c = tid; c < n; c += kStepThreads) {
         A.x[c] = L.xw[c];
         A.zsel[c] = L.zs[c];
         A.stamp[c] = L.st[c];
         A.cmap[c] = L.cm[c];
     }
-    for (int c = tid; c < L.nfree; c += 256) A.cfree[c] = L.cf[c];
-    for (int i = tid; i < r1; i += 256) A.res[i] = L.res[i];
+    for (int c = tid; c < L.nfree; c += kStepThreads) A.cfree[c] = L.cf[c];
+    for (int i = tid; i < r1; i += kStepThreads) A.res[i] = L.res[i];
     if (tid == 0) {
         A.st->nfree = L.nfree;
         if (A.trace && it < A.trace_cap) {
@@ -1799,8 +1815,8 @@ int hrom_ecm_select(int32_t M, int32_t r, const double* lam, double V0, int32_t 
     for (;;) {
         for (int b = 0; b < 32; b++) {
             hipLaunchKernelGGL(k_sel_score, dim3(nb), dim3(256), 0, stream, A);
-            if (mt <= 512) hipLaunchKernelGGL(k_sel_step<8>, dim3(1), dim3(256), 0, stream, A);
-            else hipLaunchKernelGGL(k_sel_step<16>, dim3(1), dim3(256), 0, stream, A);
+            if (mt <= 512) hipLaunchKernelGGL(k_sel_step<8>, dim3(1), dim3(kStepThreads), 0, stream, A);
+            else hipLaunchKernelGGL(k_sel_step<16>, dim3(1), dim3(kStepThreads), 0, stream, A);
         }
         launched_iters += 32;
         if (launched() != HROM_OK) return HROM_E_HIP;
