@@ -689,7 +689,7 @@ template <int MA, int PREC, bool SPLIT, bool PF, int NP = 1, bool J2 = false>
 __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ * kWR]) {
     constexpr int NA = MA * (MA + 1) / 2;
     constexpr int QR = kCQ / NP;   // ECM points per LDS round
-    constexpr int kUnrollQ = NP == 2 ? 4 : 2;   // ECM points per unrolled step (registers allow 4 with two points)
+    constexpr int kUnrollQ = 2;   // ECM points per unrolled step (4 with two points spills)
     static_assert(NP == 1 || NP == 2, "one or two points per wavefront");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, c = lane & 15;
@@ -831,8 +831,11 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
                 for (int t = 0; t < MA; t++) T[t] = Pk<PREC>::mfma(Wq[pp], Gc[t], v4f{0.f, 0.f, 0.f, 0.f});
                 accFF[pp] = Pk<PREC>::mfma(Wq[pp], Ip, accFF[pp]);
                 // KFa = sum_q T_q (W_q is symmetric): the T tiles summed in FP32
+                // (accumulator row 4g + 3 carries no component and is skipped)
 #pragma unroll
-                for (int t = 0; t < MA; t++) accF[pp][t] += T[t];
+                for (int t = 0; t < MA; t++)
+#pragma unroll
+                    for (int e = 0; e < 3; e++) accF[pp][t][e] += T[t][e];
 #pragma unroll
                 for (int tj = 0; tj < MA; tj++) {
                     const v4u32 B = t_operand<PREC, SPLIT>(T[tj], in_g1);
@@ -884,7 +887,7 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
 #pragma unroll
         for (int t = 0; t < MA; t++)
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
+            for (int e = 0; e < 3; e++) {
                 // sum of T tiles: component row 4 g + e, mode column 16 t + c
                 const int KI = pos_comp(4 * g + e), k = 16 * t + c;
                 if (KI >= 0 && k < m) put(mp + KI, k, accF[pp][t][e]);
