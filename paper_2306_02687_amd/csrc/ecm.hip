@@ -1095,10 +1095,21 @@ __device__ void qr_solve(const SelArgs& A, int n, StepLds& L, bool want_res) {
             double rhs = (lane < bs) ? L.cw[b0 + lane] : 0.0;
             const double dinv = (lane < bs) ? 1.0 / L.D[lane][lane] : 0.0;
             double zl = 0.0;
-            for (int ii = bs - 1; ii >= 0; ii--) {
-                const double zi = readlane_d(rhs * dinv, ii);
-                if (lane == ii) zl = zi;
-                if (lane < ii) rhs -= L.D[lane][ii] * zi;
+            // the lane's entries of eight columns read ahead of their steps
+            // and the updates selected rather than branched, so that no LDS
+            // read waits inside the chain
+            for (int i0 = bs - 1; i0 >= 0; i0 -= 8) {
+                double dv[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) dv[u] = L.D[lane][max(i0 - u, 0)];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int ii = i0 - u;
+                    if (ii < 0) break;
+                    const double zi = readlane_d(rhs * dinv, ii);
+                    zl = (lane == ii) ? zi : zl;
+                    rhs = (lane < ii) ? rhs - dv[u] * zi : rhs;
+                }
             }
             if (lane < bs) L.z[b0 + lane] = zl;
         }
@@ -1162,60 +1173,66 @@ __device__ void qr_remove(const SelArgs& A, int j, int n, StepLds& L) {
     __syncthreads();
     if (tid < 64) {
         // lane owns positions col = lane + 64 t of the new map; cr: the row
-        // being finished, nx: the next row, nn: the one after (prefetched)
+        // being finished, nx: the next row, nn: the one after (prefetched).
+        // Every load and store is unconditional, so that the compiler can
+        // count the memory operations in flight and wait for the prefetch
+        // only: lanes past the last position read and write the freed
+        // physical column (dead until a later append rewrites it), and lanes
+        // left of the pivot write below the diagonal of row i, which no
+        // reader of R touches.  Position i sits in slot i / 64, one copy of
+        // the step per slot, so the slots left of it drop out
         int pc[T];
 #pragma unroll
         for (int t = 0; t < T; t++) {
             const int col = lane + 64 * t;
-            pc[t] = (col < n - 1) ? L.cm[col] : 0;
+            pc[t] = (col < n - 1) ? L.cm[col] : freed;
         }
+        const int64_t rj1 = min(j + 1, n - 1);
         double cr[T], nx[T];
 #pragma unroll
-        for (int t = 0; t < T; t++) {
-            const int col = lane + 64 * t;
-            cr[t] = (col >= j && col < n - 1) ? A.R[(int64_t)j * mt + pc[t]] : 0.0;
-            nx[t] = (col >= j && col < n - 1) ? A.R[(int64_t)(j + 1) * mt + pc[t]] : 0.0;
-        }
-        for (int i = j; i < n - 1; i++) {
-            double nn[T];
+        for (int t = 0; t < T; t++) cr[t] = A.R[(int64_t)j * mt + pc[t]];
 #pragma unroll
-            for (int t = 0; t < T; t++) {
-                const int col = lane + 64 * t;
-                nn[t] = (col >= i + 1 && col < n - 1 && i + 2 < n) ? A.R[(int64_t)(i + 2) * mt + pc[t]] : 0.0;
-            }
-            double own_a = 0.0, own_b = 0.0;
+        for (int t = 0; t < T; t++) nx[t] = A.R[rj1 * mt + pc[t]];
+        // T stores into the freed column after the first rows' loads: every
+        // way into a step then has a step's stores and loads issued after the
+        // next row's loads, so each step waits for its prefetch alone
 #pragma unroll
-            for (int t = 0; t < T; t++)
-                if (t == (i >> 6)) {
-                    own_a = cr[t];
-                    own_b = nx[t];
-                }
-            const double a = readlane_d(own_a, i & 63);
-            const double b = readlane_d(own_b, i & 63);
-            const double rr = sqrt(a * a + b * b);
-            const double c = rr > 0.0 ? a / rr : 1.0, s = rr > 0.0 ? b / rr : 0.0;
+        for (int t = 0; t < T; t++) A.R[(int64_t)min(j + t, n - 1) * mt + freed] = 0.0;
 #pragma unroll
-            for (int t = 0; t < T; t++) {
-                const int col = lane + 64 * t;
-                if (col >= i && col < n - 1) {
+        for (int t0 = 0; t0 < T; t0++) {
+            const int ilo = max(j, 64 * t0), ihi = min(n - 1, 64 * t0 + 64);
+            for (int i = ilo; i < ihi; i++) {
+                const int64_t r2 = min(i + 2, n - 1);
+                double nn[T];
+#pragma unroll
+                for (int t = t0; t < T; t++) nn[t] = A.R[r2 * mt + pc[t]];
+                const double a = readlane_d(cr[t0], i & 63);
+                const double b = readlane_d(nx[t0], i & 63);
+                const double rr = sqrt(a * a + b * b);
+                const double c = rr > 0.0 ? a / rr : 1.0, s = rr > 0.0 ? b / rr : 0.0;
+#pragma unroll
+                for (int t = t0; t < T; t++) {
                     A.R[(int64_t)i * mt + pc[t]] = c * cr[t] + s * nx[t];
                     cr[t] = -s * cr[t] + c * nx[t];
+                    nx[t] = nn[t];
                 }
-                nx[t] = nn[t];
-            }
-            if (lane == 0) {
-                L.gs[i][0] = c;
-                L.gs[i][1] = s;
+                if (lane == 0) {
+                    L.gs[i][0] = c;
+                    L.gs[i][1] = s;
+                }
             }
         }
     }
     __syncthreads();
     for (int i = tid; i < r1; i += kStepThreads) {
+        // the rows ahead are loaded unconditionally (clamped to the last
+        // column, whose value is then never used), so that the waits stay on
+        // the oldest of the three loads in flight
         double q = A.Q[(int64_t)j * r1 + i];
-        double q1 = (j + 1 < n) ? A.Q[(int64_t)(j + 1) * r1 + i] : 0.0;
-        double q2 = (j + 2 < n) ? A.Q[(int64_t)(j + 2) * r1 + i] : 0.0;
+        double q1 = A.Q[(int64_t)min(j + 1, n - 1) * r1 + i];
+        double q2 = A.Q[(int64_t)min(j + 2, n - 1) * r1 + i];
         for (int t = j; t < n - 1; t++) {
-            const double q3 = (t + 3 < n) ? A.Q[(int64_t)(t + 3) * r1 + i] : 0.0;
+            const double q3 = A.Q[(int64_t)min(t + 3, n - 1) * r1 + i];
             const double c = L.gs[t][0], s = L.gs[t][1];
             A.Q[(int64_t)t * r1 + i] = c * q + s * q1;
             q = -s * q + c * q1;
