@@ -868,7 +868,7 @@ struct SelArgs {
     double* csum;        // [M] sum_i |J_ik|
     uint8_t* avail;      // [M]
     double* Q;           // [mt][r + 1], column c at Q + c (r + 1)
-    double* R;           // [mt][mt] row-major
+    double* R;           // [mt][mt] by physical column: entry (row i, column pc) at pc mt + i
     double* x;           // [mt] weights by position
     int* zsel;           // [mt] candidate of each position
     int* stamp;          // [mt] iteration that picked the candidate
@@ -1003,26 +1003,41 @@ __device__ __forceinline__ double qrow_dot(const double* Q, int r1, int i, int n
     return s;
 }
 
-// h <- Q_n^T v (a thread per column, streaming it with 16 loads in flight),
-// then v <- v - Q_n h (a thread per row)
+// h <- Q_n^T v: a wavefront per four columns, its lanes over consecutive rows
+// (every load instruction reads whole cache lines; a thread per column read
+// 64 lines per instruction), four 64-row chunks of the four columns in flight
+// per lane, then fixed-order wavefront sums; v <- v - Q_n h (a thread per row)
 __device__ void project(const SelArgs& A, int n, StepLds& L, double* h) {
-    const int tid = threadIdx.x, r1 = A.r + 1;
-    for (int c = tid; c < n; c += kStepThreads) {
-        const double* q = A.Q + (int64_t)c * r1;
-        double s0 = 0.0, s1 = 0.0;
-        int i = 0;
-        for (; i + 16 <= r1; i += 16) {
-            double t[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r1 = A.r + 1;
+    constexpr int CG = 4;
+    for (int c0 = 4 * wave; c0 < n; c0 += 4 * kStepWaves) {
+        // columns past n read column c0 and are discarded
+        int64_t off[4];
 #pragma unroll
-            for (int u = 0; u < 16; u++) t[u] = q[i + u];
+        for (int u = 0; u < 4; u++) off[u] = (int64_t)((c0 + u < n) ? c0 + u : c0) * r1;
+        double sc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i0 = 0; i0 < r1; i0 += 64 * CG) {
+            // rows past r1 read the last row with weight zero
+            double qv[CG][4], vv[CG];
 #pragma unroll
-            for (int u = 0; u < 16; u += 2) {
-                s0 += t[u] * L.v[i + u];
-                s1 += t[u + 1] * L.v[i + u + 1];
+            for (int k = 0; k < CG; k++) {
+                const int i = i0 + 64 * k + lane, ic = min(i, r1 - 1);
+                vv[k] = (i < r1) ? L.v[ic] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; u++) qv[k][u] = A.Q[off[u] + ic];
             }
+#pragma unroll
+            for (int k = 0; k < CG; k++)
+#pragma unroll
+                for (int u = 0; u < 4; u++) sc[u] += qv[k][u] * vv[k];
         }
-        for (; i < r1; i++) s0 += q[i] * L.v[i];
-        h[c] = s0 + s1;
+#pragma unroll
+        for (int u = 0; u < 4; u++) sc[u] = wave_sum(sc[u]);
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (c0 + u < n) h[c0 + u] = sc[u];
+        }
     }
     __syncthreads();
     for (int i = tid; i < r1; i += kStepThreads) L.v[i] -= qrow_dot(A.Q, r1, i, n, h);
@@ -1050,10 +1065,10 @@ __device__ double qr_append(const SelArgs& A, int n, StepLds& L) {
     const int slot = (L.nfree > 0) ? L.cf[L.nfree - 1] : n;
     const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
     for (int i = tid; i < r1; i += kStepThreads) A.Q[(int64_t)n * r1 + i] = L.v[i] * inv;
-    for (int c = tid; c < n; c += kStepThreads) A.R[(int64_t)c * A.mt + slot] = L.h[c];
+    for (int c = tid; c < n; c += kStepThreads) A.R[(int64_t)slot * A.mt + c] = L.h[c];
     __syncthreads();
     if (tid == 0) {
-        A.R[(int64_t)n * A.mt + slot] = rho;
+        A.R[(int64_t)slot * A.mt + n] = rho;
         L.cm[n] = slot;
         if (L.nfree > 0) L.nfree--;
     }
@@ -1083,9 +1098,10 @@ __device__ void qr_solve(const SelArgs& A, int n, StepLds& L, bool want_res) {
     __syncthreads();
     for (int b1 = n; b1 > 0; b1 -= 64) {
         const int b0 = max(0, b1 - 64), bs = b1 - b0;
+        // the diagonal block, lanes over the rows of a column (whole cache lines)
         for (int e = tid; e < 64 * 64; e += kStepThreads) {
-            const int ii = e >> 6, jj = e & 63;
-            L.D[ii][jj] = (ii < bs && jj < bs && jj >= ii) ? A.R[(int64_t)(b0 + ii) * mt + L.cm[b0 + jj]] : 0.0;
+            const int ii = e & 63, jj = e >> 6;
+            L.D[ii][jj] = (ii < bs && jj < bs && jj >= ii) ? A.R[L.cm[b0 + jj] * mt + b0 + ii] : 0.0;
         }
         __syncthreads();
         if (wave == 0) {
@@ -1115,22 +1131,23 @@ __device__ void qr_solve(const SelArgs& A, int n, StepLds& L, bool want_res) {
         }
         __syncthreads();
         // rows above the block: cw_i -= sum_j R[i][j] z_j over the block's
-        // columns (a thread per row, 16 loads in flight)
+        // columns (a thread per row, so that each load instruction reads
+        // consecutive rows of one column; 16 loads in flight)
         for (int i = tid; i < b0; i += kStepThreads) {
-            const double* Ri = A.R + (int64_t)i * mt;
+            const double* Ri = A.R + i;
             double s0 = 0.0, s1 = 0.0;
             int jj = 0;
             for (; jj + 16 <= bs; jj += 16) {
                 double t[16];
 #pragma unroll
-                for (int u = 0; u < 16; u++) t[u] = Ri[L.cm[b0 + jj + u]];
+                for (int u = 0; u < 16; u++) t[u] = Ri[L.cm[b0 + jj + u] * mt];
 #pragma unroll
                 for (int u = 0; u < 16; u += 2) {
                     s0 += t[u] * L.z[b0 + jj + u];
                     s1 += t[u + 1] * L.z[b0 + jj + u + 1];
                 }
             }
-            for (; jj < bs; jj++) s0 += Ri[L.cm[b0 + jj]] * L.z[b0 + jj];
+            for (; jj < bs; jj++) s0 += Ri[L.cm[b0 + jj] * mt] * L.z[b0 + jj];
             L.cw[i] -= s0 + s1;
         }
         __syncthreads();
@@ -1181,38 +1198,39 @@ __device__ void qr_remove(const SelArgs& A, int j, int n, StepLds& L) {
         // left of the pivot write below the diagonal of row i, which no
         // reader of R touches.  Position i sits in slot i / 64, one copy of
         // the step per slot, so the slots left of it drop out
+        // pc: element offset of the lane's physical column (< mt * mt, int)
         int pc[T];
 #pragma unroll
         for (int t = 0; t < T; t++) {
             const int col = lane + 64 * t;
-            pc[t] = (col < n - 1) ? L.cm[col] : freed;
+            pc[t] = ((col < n - 1) ? L.cm[col] : freed) * mt;
         }
-        const int64_t rj1 = min(j + 1, n - 1);
+        const int rj1 = min(j + 1, n - 1);
         double cr[T], nx[T];
 #pragma unroll
-        for (int t = 0; t < T; t++) cr[t] = A.R[(int64_t)j * mt + pc[t]];
+        for (int t = 0; t < T; t++) cr[t] = A.R[pc[t] + j];
 #pragma unroll
-        for (int t = 0; t < T; t++) nx[t] = A.R[rj1 * mt + pc[t]];
+        for (int t = 0; t < T; t++) nx[t] = A.R[pc[t] + rj1];
         // T stores into the freed column after the first rows' loads: every
         // way into a step then has a step's stores and loads issued after the
         // next row's loads, so each step waits for its prefetch alone
 #pragma unroll
-        for (int t = 0; t < T; t++) A.R[(int64_t)min(j + t, n - 1) * mt + freed] = 0.0;
+        for (int t = 0; t < T; t++) A.R[(int64_t)freed * mt + min(j + t, n - 1)] = 0.0;
 #pragma unroll
         for (int t0 = 0; t0 < T; t0++) {
             const int ilo = max(j, 64 * t0), ihi = min(n - 1, 64 * t0 + 64);
             for (int i = ilo; i < ihi; i++) {
-                const int64_t r2 = min(i + 2, n - 1);
+                const int r2 = min(i + 2, n - 1);
                 double nn[T];
 #pragma unroll
-                for (int t = t0; t < T; t++) nn[t] = A.R[r2 * mt + pc[t]];
+                for (int t = t0; t < T; t++) nn[t] = A.R[pc[t] + r2];
                 const double a = readlane_d(cr[t0], i & 63);
                 const double b = readlane_d(nx[t0], i & 63);
                 const double rr = sqrt(a * a + b * b);
                 const double c = rr > 0.0 ? a / rr : 1.0, s = rr > 0.0 ? b / rr : 0.0;
 #pragma unroll
                 for (int t = t0; t < T; t++) {
-                    A.R[(int64_t)i * mt + pc[t]] = c * cr[t] + s * nx[t];
+                    A.R[pc[t] + i] = c * cr[t] + s * nx[t];
                     cr[t] = -s * cr[t] + c * nx[t];
                     nx[t] = nn[t];
                 }
