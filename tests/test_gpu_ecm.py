@@ -209,6 +209,8 @@ def test_selection_maximum_size(dev, orc):
     b[-1] = V0
     print(f"maximum size: iterations {info['iters']} NNLS {int(trace[:, 1].sum())} "
           f"dropped {int(trace[:, 2].sum())} residual {np.linalg.norm(J[:, z] @ w - b):.2e}", flush=True)
+    # the removal path of the instance for more than 512 points runs here
+    assert int(trace[:, 2].sum()) > 0
     assert len(z) == mt and len(set(z.tolist())) == mt and np.all(w > 0)
     assert np.linalg.norm(J[:, z] @ w - b) < 1e-9 * V0
     assert abs(w.sum() - V0) < 1e-11 * V0
