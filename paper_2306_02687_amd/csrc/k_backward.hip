@@ -225,13 +225,24 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
             // parity of the wave; per output tile the six level pairs of every
             // mode half, the small products first and the hi * hi ones last
             const bool isF = wave < 2;
-            for (int rt = wave & 1; rt < 9; rt += 2) {
-                const v4u32* ga = reinterpret_cast<const v4u32*>(A.Gb3) + ((int64_t)(rt0 + rt) * NH * 3) * 64 + lane;
-                v4u32 Af[NH][3];
+            // the next row tile's fragments are loaded while this one's
+            // products run (the last tile reloads itself)
+            v4u32 Af[NH][3];
+            {
+                const v4u32* ga = reinterpret_cast<const v4u32*>(A.Gb3) + ((int64_t)(rt0 + (wave & 1)) * NH * 3) * 64 + lane;
 #pragma unroll
                 for (int hh = 0; hh < NH; hh++)
 #pragma unroll
                     for (int L = 0; L < 3; L++) Af[hh][L] = ga[(hh * 3 + L) * 64];
+            }
+            for (int rt = wave & 1; rt < 9; rt += 2) {
+                const int rn = (rt + 2 < 9) ? rt + 2 : rt;
+                const v4u32* gn = reinterpret_cast<const v4u32*>(A.Gb3) + ((int64_t)(rt0 + rn) * NH * 3) * 64 + lane;
+                v4u32 An[NH][3];
+#pragma unroll
+                for (int hh = 0; hh < NH; hh++)
+#pragma unroll
+                    for (int L = 0; L < 3; L++) An[hh][L] = gn[(hh * 3 + L) * 64];
                 v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
                 for (int hh = 0; hh < NH; hh++)
@@ -256,6 +267,10 @@ __device__ void bw_body(const BackwardArgs& A, int64_t p0, BwLds<AR, LT>& Ls) {
                         if (isF) sF[row][col] = (LT)((double)acc[pt][e] + sU[row % 9][col]);
                         else sV[row][col] = (LT)(sG[row % 9][col] - (double)acc[pt][e]);
                     }
+#pragma unroll
+                for (int hh = 0; hh < NH; hh++)
+#pragma unroll
+                    for (int L = 0; L < 3; L++) Af[hh][L] = An[hh][L];
             }
         } else {
 #pragma unroll
