@@ -739,7 +739,23 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
     v4u32 Gc[MA];
 #pragma unroll
     for (int t = 0; t < MA; t++) Gc[t] = fp[t * 64];
+    // the tangent scalars of the lane's ECM point, one round ahead
+    v4f xn0, xn1, xn2;
+    {
+        const v4f* src = (const v4f*)(qsp + (int64_t)qq * 12);
+        xn0 = src[0];
+        xn1 = src[1];
+        xn2 = src[2];
+    }
     for (int q0 = 0; q0 < A.Qpad; q0 += QR) {
+        const v4f x0 = xn0, x1 = xn1, x2 = xn2;
+        {
+            const int qn = (q0 + QR < A.Qpad) ? q0 + QR : q0;
+            const v4f* src = (const v4f*)(qsp + (int64_t)(qn + qq) * 12);
+            xn0 = src[0];
+            xn1 = src[1];
+            xn2 = src[2];
+        }
         // ---- W rows of this round: lane (pb, qq, u < 3) builds the rows
         // (i, j) = (u, 0..2) of W_{q0+qq} of point pb; the lanes u = 3 build none
         if constexpr (J2) {
@@ -747,8 +763,6 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
             // (w kappa, w 2 mu th, w 2 mu thb, n xx yy zz xy yz xz):
             //   W[(i,j)][(k,l)] = w kappa d_ij d_kl + w 2 mu th (sym(d_ik d_jl) - d_ij d_kl / 3)
             //                     - w 2 mu thb n_ij n_kl
-            const v4f* src = (const v4f*)(qsp + (int64_t)(q0 + qq) * 12);
-            const v4f x0 = src[0], x1 = src[1], x2 = src[2];
             const float a0 = x0[0], a1 = x0[1], a2 = x0[2];
             const float nv[6] = {x0[3], x1[0], x1[1], x1[2], x1[3], x2[0]};
 #pragma unroll
@@ -774,8 +788,6 @@ __device__ void tan_mixed_body(const EvalArgs& A, int64_t pl0, v4u32 (*s_w)[kCQ 
                 }
             }
         } else {
-            const v4f* src = (const v4f*)(qsp + (int64_t)(q0 + qq) * 12);
-            const v4f x0 = src[0], x1 = src[1], x2 = src[2];
             const float F[9] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3], x2[0]};
             const float c0 = x2[1], c1 = x2[2], c2 = x2[3];
             // W[(i,j)][(k,l)] = c1 F(l,i) F(j,k) + c2 F(j,i) F(l,k) + c0 [k = i][l = j]:
