@@ -78,14 +78,24 @@ __device__ __forceinline__ void tangent_row(const T* Fi, T c0, T c1, T c2, T* W)
 // two workgroups share a CU and the matrix phases of one overlap the material
 // law of the other.
 constexpr int kKinPT = 32;
+// weights and phases of a round's ECM points, staged through LDS up to four
+// mode tiles; with more the workgroup would outgrow half the CU's LDS
+// (80 KiB at six tiles), and the law reads them from memory itself
+template <int AR>
+constexpr bool kin_stage_w() { return AR <= 64; }
+template <int AR, bool W = kin_stage_w<AR>()>
+struct KinLdsW {};
+template <int AR>
+struct KinLdsW<AR, true> {
+    double sWq[16];
+    int sPh[16];
+};
 template <int AR>   // rows of the mode amplitudes (>= 16 ceil(m / 16))
-struct KinLds {
+struct KinLds : KinLdsW<AR> {
     double sA[AR][kKinPT];
     double sF[16 * 9][kKinPT + 1];   // F of the round, then w P in place
     double sF8[4][16][kKinPT + 1];
     double sU[9][kKinPT];
-    double sWq[16];
-    int sPh[16];
     int sbits[kKinPT];
 };
 
@@ -158,10 +168,11 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
     for (int q0 = 0; q0 < A.Qpad; q0 += QC) {
         const int rt0 = (q0 / 16) * 9;
         // weights and phases of the round's ECM points, loaded ahead of the
-        // GEMM and handed to the law through LDS
+        // GEMM and handed to the law through LDS (where it has room for them)
+        constexpr bool WS = kin_stage_w<AR>();
         double wnext = 0.0;
         int phnext = 0;
-        if (tid < QC) {
+        if (WS && tid < QC) {
             wnext = A.w[q0 + tid];
             phnext = A.phase[q0 + tid];
         }
@@ -204,9 +215,11 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
                 sF8[wave][g + 4 * e][16 + c] = a1[e];
             }
         }
-        if (tid < QC) {
-            L.sWq[tid] = wnext;
-            L.sPh[tid] = phnext;
+        if constexpr (WS) {
+            if (tid < QC) {
+                L.sWq[tid] = wnext;
+                L.sPh[tid] = phnext;
+            }
         }
         __syncthreads();
         // ---- rows 128..143 of F: fixed-order sum of the four k-range partials
@@ -223,8 +236,15 @@ __device__ void kin_body(const EvalArgs& A, int64_t p0, KinLds<AR>& L) {
             double F[9];
 #pragma unroll
             for (int I = 0; I < 9; I++) F[I] = sF[qq * 9 + I][p];
-            const double wq = L.sWq[qq];
-            const int ph = L.sPh[qq];
+            double wq;
+            int ph;
+            if constexpr (WS) {
+                wq = L.sWq[qq];
+                ph = L.sPh[qq];
+            } else {
+                wq = A.w[q];
+                ph = A.phase[q];
+            }
             if constexpr (J2) {
                 // theta = per phase (mu, lam, sy0, H); committed state in, new state out
                 const double* mp = A.theta + 4 * ph;
