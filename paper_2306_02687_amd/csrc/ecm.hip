@@ -1195,9 +1195,9 @@ __device__ void qr_remove(const SelArgs& A, int j, int n, StepLds& L) {
         // count the memory operations in flight and wait for the prefetch
         // only: lanes past the last position read and write the freed
         // physical column (dead until a later append rewrites it), and lanes
-        // left of the pivot write below the diagonal of row i, which no
-        // reader of R touches.  Position i sits in slot i / 64, one copy of
-        // the step per slot, so the slots left of it drop out
+        // left of the pivot write row i of their column, below its diagonal,
+        // where no reader of R looks.  Position i sits in slot i / 64, one
+        // copy of the step per slot, so the slots left of it drop out
         // pc: element offset of the lane's physical column (< mt * mt, int)
         int pc[T];
 #pragma unroll
